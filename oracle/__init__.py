@@ -1,0 +1,260 @@
+"""FP64 CPU oracle for the 2D3V electromagnetic PIC step.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg of
+the benchmark may import this package; the GPU library never does, and this
+package imports nothing from it.  The arithmetic lives in ``pic_oracle.c``
+(plain C, built with ``-ffp-contract=off``); this module only marshals numpy
+arrays through ``ctypes``.
+
+Every function follows a passage of the paper (Guidotti, "Accelerating
+Particle-Mesh Algorithms with FPGAs and OmpSs@OpenCL"):
+
+* ``interp``            -- linear interpolation on the staggered grid (Sec. 3.1)
+* ``boris``             -- relativistic Boris push, Eqs. (6)-(10)
+* ``deposit_move``      -- Villasenor-Buneman current, Eqs. (12)-(16), with the
+                           1/2/3-piece split of Figs. 3.4-3.5
+* ``OracleSim.push_deposit`` -- the particle loop of Listing 3.1 + Eq. (11)
+* ``yee_b`` / ``yee_e`` / ``OracleSim.field_advance`` -- Eqs. (19)-(20), the
+                           three-step Yee update of Listing 3.1
+* ``sort_canonical``    -- strict tile re-sort (Sec. 4.3, Fig. 4.5)
+* ``rho`` / energies / divergences -- diagnostics (Eq. 17, Eq. 18, Eq. 12)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "pic_oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+_d = ctypes.c_double
+_i = ctypes.c_int
+_i64 = ctypes.c_int64
+_p = ctypes.c_void_p
+
+
+def build(force: bool = True) -> str:
+    """Compile ``pic_oracle.c`` into ``liboracle.so`` with gcc (strict FP64)."""
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+             "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_SO)
+        L.ora_interp.argtypes = [_i, _i, _p, _p, _i, _i, _d, _d, _p]
+        L.ora_boris.argtypes = [_d, _d, _p, _p]
+        L.ora_deposit_move.argtypes = [_i, _i, _d, _d, _d, _d, _d, _i, _i, _d, _d, _d, _d, _p]
+        L.ora_advance.argtypes = [_i, _i, _d, _d, _d, _d, _d, _i64] + [_p] * 10
+        L.ora_advance.restype = _i
+        L.ora_yee_b.argtypes = [_i, _i, _d, _d, _d, _p, _p]
+        L.ora_yee_e.argtypes = [_i, _i, _d, _d, _d, _p, _p, _p]
+        L.ora_field_advance.argtypes = [_i, _i, _d, _d, _d, _p, _p, _p]
+        L.ora_sort_canonical.argtypes = [_i, _i, _i, _i64, _p, _p, _p, _p]
+        L.ora_sort_canonical.restype = _i
+        L.ora_deposit_rho.argtypes = [_i, _i, _d, _i64, _p, _p, _p, _p, _p]
+        L.ora_field_energy.argtypes = [_i, _i, _d, _d, _p]
+        L.ora_field_energy.restype = _d
+        L.ora_kinetic_energy.argtypes = [_d, _d, _d, _d, _i64, _p, _p, _p]
+        L.ora_kinetic_energy.restype = _d
+        L.ora_div_e.argtypes = [_i, _i, _d, _d, _p, _p]
+        L.ora_div_b.argtypes = [_i, _i, _d, _d, _p, _p]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+# --------------------------------------------------------------------------
+# single-particle / single-operator entry points (used by the pins)
+# --------------------------------------------------------------------------
+
+def interp(nx, ny, E, B, ix, iy, x, y) -> np.ndarray:
+    """{Ex,Ey,Ez,Bx,By,Bz} at one particle; E, B are (3, ny, nx) arrays."""
+    E = _f64(E)
+    B = _f64(B)
+    out = np.zeros(6)
+    lib().ora_interp(nx, ny, _ptr(E), _ptr(B), int(ix), int(iy), float(x), float(y), _ptr(out))
+    return out
+
+
+def boris(qm, dt, EB, u) -> np.ndarray:
+    """One Boris update of u(t-dt/2) -> u(t+dt/2) in the fields EB = (E, B)."""
+    EB = _f64(EB)
+    u = _f64(u).copy()
+    lib().ora_boris(float(qm), float(dt), _ptr(EB), _ptr(u))
+    return u
+
+
+def deposit_move(nx, ny, dx, dy, dt, q, vz, ix, iy, x, y, ddx, ddy, J=None) -> np.ndarray:
+    """Current (3, ny, nx) of one straight move by (ddx, ddy) cells."""
+    if J is None:
+        J = np.zeros((3, ny, nx))
+    lib().ora_deposit_move(nx, ny, dx, dy, dt, q, vz, int(ix), int(iy), float(x), float(y),
+                           float(ddx), float(ddy), _ptr(J))
+    return J
+
+
+def yee_b(nx, ny, dx, dy, h, E, B):
+    lib().ora_yee_b(nx, ny, dx, dy, h, _ptr(E), _ptr(B))
+
+
+def yee_e(nx, ny, dx, dy, h, B, J, E):
+    lib().ora_yee_e(nx, ny, dx, dy, h, _ptr(B), _ptr(J), _ptr(E))
+
+
+def sort_canonical(nx, ny, T, ix, iy):
+    """Canonical strict tile sort.  Returns (off[ntiles+1], src[n]) as int64."""
+    ix = _i32(ix)
+    iy = _i32(iy)
+    n = ix.size
+    ntiles = (nx // T) * (ny // T)
+    off = np.zeros(ntiles + 1, dtype=np.int64)
+    src = np.zeros(max(n, 1), dtype=np.int64)
+    rc = lib().ora_sort_canonical(nx, ny, T, n, _ptr(ix), _ptr(iy), _ptr(off), _ptr(src))
+    if rc != 0:
+        raise ValueError("cell index out of range")
+    return off, src[:n]
+
+
+def rho(nx, ny, q, ix, iy, x, y, out=None) -> np.ndarray:
+    """Node charge density (ny, nx) of one species (accumulates into out)."""
+    if out is None:
+        out = np.zeros((ny, nx))
+    ix = _i32(ix)
+    iy = _i32(iy)
+    x = _f64(x)
+    y = _f64(y)
+    lib().ora_deposit_rho(nx, ny, q, ix.size, _ptr(ix), _ptr(iy), _ptr(x), _ptr(y), _ptr(out))
+    return out
+
+
+def field_energy(nx, ny, dx, dy, F) -> float:
+    F = _f64(F)
+    return lib().ora_field_energy(nx, ny, dx, dy, _ptr(F))
+
+
+def kinetic_energy(dx, dy, qm, q, ux, uy, uz) -> float:
+    ux, uy, uz = _f64(ux), _f64(uy), _f64(uz)
+    return lib().ora_kinetic_energy(dx, dy, qm, q, ux.size, _ptr(ux), _ptr(uy), _ptr(uz))
+
+
+def div_e(nx, ny, dx, dy, F) -> np.ndarray:
+    F = _f64(F)
+    out = np.zeros((ny, nx))
+    lib().ora_div_e(nx, ny, dx, dy, _ptr(F), _ptr(out))
+    return out
+
+
+def div_b(nx, ny, dx, dy, B) -> np.ndarray:
+    B = _f64(B)
+    out = np.zeros((ny, nx))
+    lib().ora_div_b(nx, ny, dx, dy, _ptr(B), _ptr(out))
+    return out
+
+
+# --------------------------------------------------------------------------
+# whole-simulation driver
+# --------------------------------------------------------------------------
+
+class OracleSpecies:
+    """Particles of one species, FP64 offsets and momenta, int32 cells."""
+
+    def __init__(self, qm, q, ix, iy, x, y, ux, uy, uz):
+        self.qm = float(qm)
+        self.q = float(q)
+        self.ix = _i32(ix).copy()
+        self.iy = _i32(iy).copy()
+        self.x = _f64(x).copy()
+        self.y = _f64(y).copy()
+        self.ux = _f64(ux).copy()
+        self.uy = _f64(uy).copy()
+        self.uz = _f64(uz).copy()
+
+    @property
+    def n(self):
+        return self.ix.size
+
+    def permute(self, src):
+        for name in ("ix", "iy", "x", "y", "ux", "uy", "uz"):
+            setattr(self, name, np.ascontiguousarray(getattr(self, name)[src]))
+
+
+class OracleSim:
+    """Serial FP64 PIC on a periodic nx x ny grid (Listing 3.1 order)."""
+
+    def __init__(self, nx, ny, dx, dy, dt, species, E=None, B=None):
+        self.nx, self.ny = int(nx), int(ny)
+        self.dx, self.dy, self.dt = float(dx), float(dy), float(dt)
+        self.species = list(species)
+        shape = (3, self.ny, self.nx)
+        self.E = np.zeros(shape) if E is None else _f64(E).reshape(shape).copy()
+        self.B = np.zeros(shape) if B is None else _f64(B).reshape(shape).copy()
+        self.J = np.zeros(shape)
+
+    def push_deposit(self):
+        """Zero J, then interpolate / push / move / deposit every particle."""
+        self.J[...] = 0.0
+        for s in self.species:
+            rc = lib().ora_advance(self.nx, self.ny, self.dx, self.dy, self.dt, s.qm, s.q, s.n,
+                                   _ptr(s.ix), _ptr(s.iy), _ptr(s.x), _ptr(s.y),
+                                   _ptr(s.ux), _ptr(s.uy), _ptr(s.uz),
+                                   _ptr(self.E), _ptr(self.B), _ptr(self.J))
+            if rc != 0:
+                raise FloatingPointError("a particle moved one cell or more (Courant condition)")
+
+    def field_advance(self):
+        lib().ora_field_advance(self.nx, self.ny, self.dx, self.dy, self.dt,
+                                _ptr(self.E), _ptr(self.B), _ptr(self.J))
+
+    def sort(self, T):
+        """Canonical tile sort of every species; returns the new offsets."""
+        offs = []
+        for s in self.species:
+            off, src = sort_canonical(self.nx, self.ny, T, s.ix, s.iy)
+            s.permute(src)
+            offs.append(off)
+        return offs
+
+    def step(self, T=None):
+        self.push_deposit()
+        if T is not None:
+            self.sort(T)
+        self.field_advance()
+
+    def rho(self):
+        r = np.zeros((self.ny, self.nx))
+        for s in self.species:
+            rho(self.nx, self.ny, s.q, s.ix, s.iy, s.x, s.y, out=r)
+        return r
+
+    def energies(self):
+        ue = field_energy(self.nx, self.ny, self.dx, self.dy, self.E)
+        ub = field_energy(self.nx, self.ny, self.dx, self.dy, self.B)
+        uk = [kinetic_energy(self.dx, self.dy, s.qm, s.q, s.ux, s.uy, s.uz) for s in self.species]
+        return ue, ub, uk

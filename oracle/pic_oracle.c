@@ -1,0 +1,446 @@
+/*
+ * Plain FP64 CPU oracle for the 2D3V electromagnetic particle-in-cell step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct reference
+ * that the HIP path is checked against.  Only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no code, header or
+ * constant with the GPU library: it has no tiles, no guard cells and no LDS; it
+ * indexes the periodic grid modulo (nx, ny) and walks the particles one by one
+ * in array order, following the serial loop of the paper (Sec. 3.2, Listing 3.1).
+ *
+ * Conventions (normalised units of Eqs. 21-22, so c = 1):
+ *   - A particle lives in cell (ix, iy) with in-cell offsets x, y in [0, 1);
+ *     its position in cell units is X = ix + x, Y = iy + y.  Node (i, j) sits at
+ *     the integer point (i, j).
+ *   - Yee staggering (Fig. 3.1 is lost; standard 2D layout):
+ *       Ex (i+1/2, j)   Ey (i, j+1/2)   Ez (i, j)
+ *       Bx (i, j+1/2)   By (i+1/2, j)   Bz (i+1/2, j+1/2)
+ *     J is co-located with E, the charge density with the nodes.
+ *   - A field array holds three components, each an (ny x nx) row-major plane:
+ *     F[c*nx*ny + j*nx + i].
+ *   - q is the charge carried by one macro-particle (a charge density, e.g.
+ *     -n0/ppc), qm the species charge-to-mass ratio.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define IDX(i, j, nx) ((int64_t)(j) * (nx) + (i))
+
+static int wrap(int i, int n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Field interpolation (Sec. 3.1: linear interpolation from the cell and its  */
+/* neighbours on the staggered grid).                                         */
+/* ------------------------------------------------------------------------ */
+
+/* Bilinear interpolation of one staggered component sampled at (i+sx, j+sy). */
+static double interp_component(const double *F, int nx, int ny, double X,
+                               double Y, double sx, double sy)
+{
+    double xs = X - sx, ys = Y - sy;
+    double fi = floor(xs), fj = floor(ys);
+    double wx = xs - fi, wy = ys - fj;
+    int i0 = (int)fi, j0 = (int)fj;
+    double v = 0.0;
+    for (int b = 0; b < 2; b++)
+        for (int a = 0; a < 2; a++) {
+            double w = (a ? wx : 1.0 - wx) * (b ? wy : 1.0 - wy);
+            v += w * F[IDX(wrap(i0 + a, nx), wrap(j0 + b, ny), nx)];
+        }
+    return v;
+}
+
+/* Stagger offsets of the six field components, in the order Ex Ey Ez Bx By Bz. */
+static const double STAG_X[6] = {0.5, 0.0, 0.0, 0.0, 0.5, 0.5};
+static const double STAG_Y[6] = {0.0, 0.5, 0.0, 0.5, 0.0, 0.5};
+
+/* E and B at a particle: out = {Ex, Ey, Ez, Bx, By, Bz}. */
+void ora_interp(int nx, int ny, const double *E, const double *B, int ix,
+                int iy, double x, double y, double *out)
+{
+    const int64_t plane = (int64_t)nx * ny;
+    double X = ix + x, Y = iy + y;
+    for (int c = 0; c < 3; c++) {
+        out[c] = interp_component(E + c * plane, nx, ny, X, Y, STAG_X[c],
+                                  STAG_Y[c]);
+        out[3 + c] = interp_component(B + c * plane, nx, ny, X, Y,
+                                      STAG_X[3 + c], STAG_Y[3 + c]);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Relativistic Boris push, Eqs. (6)-(10).                                    */
+/* ------------------------------------------------------------------------ */
+
+static void cross(const double a[3], const double b[3], double out[3])
+{
+    out[0] = a[1] * b[2] - a[2] * b[1];
+    out[1] = a[2] * b[0] - a[0] * b[2];
+    out[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/*
+ * u holds u(t - dt/2) on entry and u(t + dt/2) on exit.  EB = {E, B} at the
+ * particle at time t.  The rotation vector n of Eq. (10) uses the Lorentz
+ * factor of u- (Eq. 6), which equals that of u+ since Eqs. (7)-(8) are a pure
+ * rotation.
+ */
+void ora_boris(double qm, double dt, const double *EB, double *u)
+{
+    const double h = 0.5 * qm * dt; /* q dt / 2m */
+    double um[3], up[3], upl[3], n[3], s[3], c[3];
+    for (int k = 0; k < 3; k++) um[k] = u[k] + h * EB[k]; /* Eq. (6) */
+    double g = sqrt(1.0 + um[0] * um[0] + um[1] * um[1] + um[2] * um[2]);
+    for (int k = 0; k < 3; k++) n[k] = (h / g) * EB[3 + k]; /* Eq. (10) */
+    cross(um, n, c);
+    for (int k = 0; k < 3; k++) up[k] = um[k] + c[k]; /* Eq. (7) */
+    double nn = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+    for (int k = 0; k < 3; k++) s[k] = 2.0 * n[k] / (1.0 + nn);
+    cross(up, s, c);
+    for (int k = 0; k < 3; k++) upl[k] = um[k] + c[k]; /* Eq. (8) */
+    for (int k = 0; k < 3; k++) u[k] = upl[k] + h * EB[k]; /* Eq. (9) */
+}
+
+/* ------------------------------------------------------------------------ */
+/* Villasenor-Buneman charge-conserving current deposit, Eqs. (12)-(16),      */
+/* with the split of a motion that crosses cell faces into 1, 2 or 3 pieces   */
+/* that each stay inside one cell (Sec. 3.1, Figs. 3.4-3.5).                  */
+/* ------------------------------------------------------------------------ */
+
+static double clamp01(double v) { return v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v); }
+
+/*
+ * One piece of the motion, inside cell (cx, cy), from (xa, ya) to (xb, yb) in
+ * that cell's frame ([0,1]^2), lasting the fraction frac of the time step.
+ *
+ * The particle is a unit square of charge q centred on its position.  With the
+ * cloud inside cell (cx, cy) it straddles the dual-cell face x = cx + 1/2, and
+ * the part of its height below y = cy + 1/2 is 1 - y: moving by dxk it pushes
+ * q dxk (1 - y_mid) across face (cx+1/2, cy) and q dxk y_mid across
+ * (cx+1/2, cy+1) (Eqs. 13-14 measured from the cell centre, y' = y - 1/2).
+ * Eqs. (15)-(16) give Jy the same way.  Fluxes become current densities by
+ * multiplying with dx/dt (dy/dt).
+ *
+ * The out-of-plane current has no flux form; it is deposited as q vz times
+ * the exact time average, along the piece, of the bilinear weight of each
+ * corner node.
+ */
+static void deposit_piece(int nx, int ny, double dx, double dy, double dt,
+                          double *J, double q, double vz, int cx, int cy,
+                          double xa, double ya, double xb, double yb,
+                          double frac)
+{
+    const int64_t plane = (int64_t)nx * ny;
+    double *Jx = J, *Jy = J + plane, *Jz = J + 2 * plane;
+    double dxk = xb - xa, dyk = yb - ya;
+    double xm = 0.5 * (xa + xb), ym = 0.5 * (ya + yb);
+    int i0 = wrap(cx, nx), i1 = wrap(cx + 1, nx);
+    int j0 = wrap(cy, ny), j1 = wrap(cy + 1, ny);
+
+    Jx[IDX(i0, j0, nx)] += q * dxk * (1.0 - ym) * dx / dt;
+    Jx[IDX(i0, j1, nx)] += q * dxk * ym * dx / dt;
+    Jy[IDX(i0, j0, nx)] += q * dyk * (1.0 - xm) * dy / dt;
+    Jy[IDX(i1, j0, nx)] += q * dyk * xm * dy / dt;
+
+    for (int b = 0; b < 2; b++)
+        for (int a = 0; a < 2; a++) {
+            double f0 = a ? xa : 1.0 - xa, f1 = a ? xb : 1.0 - xb;
+            double g0 = b ? ya : 1.0 - ya, g1 = b ? yb : 1.0 - yb;
+            /* integral over s in [0,1] of (f0 + s(f1-f0)) (g0 + s(g1-g0)) */
+            double w = (f0 * g0 + f1 * g1) / 3.0 + (f0 * g1 + f1 * g0) / 6.0;
+            Jz[IDX(a ? i1 : i0, b ? j1 : j0, nx)] += q * vz * frac * w;
+        }
+}
+
+/*
+ * Deposit the current of a straight motion from offset (x, y) in cell (ix, iy)
+ * by (ddx, ddy) cells, |ddx|, |ddy| < 1.  The path is cut where it meets the
+ * faces x = 0 / x = 1 and y = 0 / y = 1 of the starting cell; the cut times,
+ * in increasing order, give 1, 2 or 3 pieces.  Each piece lies inside the cell
+ * that holds its midpoint.
+ */
+void ora_deposit_move(int nx, int ny, double dx, double dy, double dt,
+                      double q, double vz, int ix, int iy, double x, double y,
+                      double ddx, double ddy, double *J)
+{
+    double tau[4];
+    int nt = 0;
+    double x1 = x + ddx, y1 = y + ddy;
+    tau[nt++] = 0.0;
+    if (x1 >= 1.0) tau[nt++] = (1.0 - x) / ddx;
+    else if (x1 < 0.0) tau[nt++] = -x / ddx;
+    if (y1 >= 1.0) tau[nt++] = (1.0 - y) / ddy;
+    else if (y1 < 0.0) tau[nt++] = -y / ddy;
+    tau[nt++] = 1.0;
+    if (nt == 4 && tau[2] < tau[1]) {
+        double t = tau[1];
+        tau[1] = tau[2];
+        tau[2] = t;
+    }
+    for (int k = 0; k + 1 < nt; k++) {
+        double ta = clamp01(tau[k]), tb = clamp01(tau[k + 1]);
+        double xa = x + ta * ddx, ya = y + ta * ddy;
+        double xb = x + tb * ddx, yb = y + tb * ddy;
+        int cx = (int)floor(0.5 * (xa + xb));
+        int cy = (int)floor(0.5 * (ya + yb));
+        deposit_piece(nx, ny, dx, dy, dt, J, q, vz, ix + cx, iy + cy,
+                      clamp01(xa - cx), clamp01(ya - cy), clamp01(xb - cx),
+                      clamp01(yb - cy), tb - ta);
+    }
+}
+
+/* Move one offset coordinate by d cells and renormalise it into [0, 1). */
+static void advance_coord(int *i, double *x, double d, int n)
+{
+    double v = *x + d;
+    if (v >= 1.0) {
+        v -= 1.0;
+        *i += 1;
+    } else if (v < 0.0) {
+        v += 1.0;
+        *i -= 1;
+        if (v >= 1.0) { /* round-off put it exactly on the face */
+            v = 0.0;
+            *i += 1;
+        }
+    }
+    *x = v;
+    *i = wrap(*i, n);
+}
+
+/*
+ * The particle half of one time step (Listing 3.1, the loop over particles):
+ * for every particle in array order, interpolate E and B, Boris-push the
+ * momentum, move the particle by Eq. (11) and deposit its current into J
+ * (which the caller zeroes; contributions of all species add up).
+ * Returns 0, or -1 if a particle would move one cell or more (Eq. 1 violated).
+ */
+int ora_advance(int nx, int ny, double dx, double dy, double dt, double qm,
+                double q, int64_t n, int32_t *ix, int32_t *iy, double *x,
+                double *y, double *ux, double *uy, double *uz, const double *E,
+                const double *B, double *J)
+{
+    for (int64_t p = 0; p < n; p++) {
+        double EB[6], u[3] = {ux[p], uy[p], uz[p]};
+        ora_interp(nx, ny, E, B, ix[p], iy[p], x[p], y[p], EB);
+        ora_boris(qm, dt, EB, u);
+        double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        double ddx = u[0] / g * dt / dx; /* Eq. (11), in cells */
+        double ddy = u[1] / g * dt / dy;
+        if (fabs(ddx) >= 1.0 || fabs(ddy) >= 1.0) return -1;
+        ora_deposit_move(nx, ny, dx, dy, dt, q, u[2] / g, ix[p], iy[p], x[p],
+                         y[p], ddx, ddy, J);
+        int i = ix[p], j = iy[p];
+        double xx = x[p], yy = y[p];
+        advance_coord(&i, &xx, ddx, nx);
+        advance_coord(&j, &yy, ddy, ny);
+        ix[p] = i;
+        iy[p] = j;
+        x[p] = xx;
+        y[p] = yy;
+        ux[p] = u[0];
+        uy[p] = u[1];
+        uz[p] = u[2];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Yee finite-difference field advance, Eqs. (19)-(20) (Sec. 3.1).            */
+/* ------------------------------------------------------------------------ */
+
+/* Faraday's law, B -= h curl E. */
+void ora_yee_b(int nx, int ny, double dx, double dy, double h, const double *E,
+               double *B)
+{
+    const int64_t plane = (int64_t)nx * ny;
+    const double *Ex = E, *Ey = E + plane, *Ez = E + 2 * plane;
+    double *Bx = B, *By = B + plane, *Bz = B + 2 * plane;
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) {
+            int ip = wrap(i + 1, nx), jp = wrap(j + 1, ny);
+            int64_t k = IDX(i, j, nx);
+            double dEz_dy = (Ez[IDX(i, jp, nx)] - Ez[k]) / dy;
+            double dEz_dx = (Ez[IDX(ip, j, nx)] - Ez[k]) / dx;
+            double dEy_dx = (Ey[IDX(ip, j, nx)] - Ey[k]) / dx;
+            double dEx_dy = (Ex[IDX(i, jp, nx)] - Ex[k]) / dy;
+            Bx[k] -= h * dEz_dy;
+            By[k] += h * dEz_dx;
+            Bz[k] -= h * (dEy_dx - dEx_dy);
+        }
+}
+
+/* Ampere's law with the particle current, E += h (curl B - J). */
+void ora_yee_e(int nx, int ny, double dx, double dy, double h, const double *B,
+               const double *J, double *E)
+{
+    const int64_t plane = (int64_t)nx * ny;
+    const double *Bx = B, *By = B + plane, *Bz = B + 2 * plane;
+    double *Ex = E, *Ey = E + plane, *Ez = E + 2 * plane;
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) {
+            int im = wrap(i - 1, nx), jm = wrap(j - 1, ny);
+            int64_t k = IDX(i, j, nx);
+            double dBz_dy = (Bz[k] - Bz[IDX(i, jm, nx)]) / dy;
+            double dBz_dx = (Bz[k] - Bz[IDX(im, j, nx)]) / dx;
+            double dBy_dx = (By[k] - By[IDX(im, j, nx)]) / dx;
+            double dBx_dy = (Bx[k] - Bx[IDX(i, jm, nx)]) / dy;
+            Ex[k] += h * (dBz_dy - J[k]);
+            Ey[k] += h * (-dBz_dx - J[plane + k]);
+            Ez[k] += h * (dBy_dx - dBx_dy - J[2 * plane + k]);
+        }
+}
+
+/* The three-step field advance of Listing 3.1: B half step, E full step, B half step. */
+void ora_field_advance(int nx, int ny, double dx, double dy, double dt,
+                       double *E, double *B, const double *J)
+{
+    ora_yee_b(nx, ny, dx, dy, 0.5 * dt, E, B);
+    ora_yee_e(nx, ny, dx, dy, dt, B, J, E);
+    ora_yee_b(nx, ny, dx, dy, 0.5 * dt, E, B);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Strict re-sort of particles by tile (Sec. 4.3, the bucket sort of Fig.   */
+/* 4.5): tile_offset is recounted from the final positions, and every        */
+/* particle whose slot is outside its tile's new section moves into a hole.  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Tiles are T x T cells, numbered row-major: t = (iy / T) * (nx / T) + ix / T.
+ * Output: off[0 .. ntiles] (new tile_offset) and src[0 .. n): the particle at
+ * slot j after the sort is the one that was at slot src[j].
+ *
+ * The pairing of holes and movers is not fixed by the paper (it registers them
+ * with atomics).  The canonical choice made here: holes are the non-staying
+ * slots in ascending order (so they come grouped by section), movers are the
+ * non-staying particles ordered by destination tile and, within one tile, by
+ * ascending slot; the k-th hole receives the k-th mover.
+ * Returns 0, or -1 if a cell index is out of range.
+ */
+int ora_sort_canonical(int nx, int ny, int T, int64_t n, const int32_t *ix,
+                       const int32_t *iy, int64_t *off, int64_t *src)
+{
+    const int ntx = nx / T, nty = ny / T;
+    const int64_t ntiles = (int64_t)ntx * nty;
+    int64_t *tile = malloc(sizeof(int64_t) * (n ? n : 1));
+    int64_t *cnt = calloc(ntiles + 1, sizeof(int64_t));
+    int64_t *mstart = calloc(ntiles + 1, sizeof(int64_t));
+    int64_t *holes = malloc(sizeof(int64_t) * (n ? n : 1));
+    int64_t *movers = malloc(sizeof(int64_t) * (n ? n : 1));
+    char *stay = malloc(n ? n : 1);
+    int rc = 0;
+
+    /* step (1): count the particles per tile at their final position */
+    for (int64_t i = 0; i < n; i++) {
+        if (ix[i] < 0 || ix[i] >= nx || iy[i] < 0 || iy[i] >= ny) {
+            rc = -1;
+            goto done;
+        }
+        tile[i] = (int64_t)(iy[i] / T) * ntx + ix[i] / T;
+        cnt[tile[i]]++;
+    }
+    off[0] = 0;
+    for (int64_t t = 0; t < ntiles; t++) off[t + 1] = off[t] + cnt[t];
+
+    /* a particle stays iff its slot is inside its tile's new section */
+    for (int64_t i = 0; i < n; i++)
+        stay[i] = (i >= off[tile[i]] && i < off[tile[i] + 1]);
+
+    /* steps (2)-(4): holes in ascending order; movers grouped by destination tile */
+    int64_t nh = 0;
+    for (int64_t i = 0; i < n; i++)
+        if (!stay[i]) holes[nh++] = i;
+    memset(cnt, 0, sizeof(int64_t) * (ntiles + 1));
+    for (int64_t i = 0; i < n; i++)
+        if (!stay[i]) cnt[tile[i]]++;
+    for (int64_t t = 0; t < ntiles; t++) mstart[t + 1] = mstart[t] + cnt[t];
+    for (int64_t i = 0; i < n; i++)
+        if (!stay[i]) movers[mstart[tile[i]]++] = i;
+
+    /* step (5): move */
+    for (int64_t j = 0; j < n; j++) src[j] = j;
+    for (int64_t k = 0; k < nh; k++) src[holes[k]] = movers[k];
+
+done:
+    free(tile);
+    free(cnt);
+    free(mstart);
+    free(holes);
+    free(movers);
+    free(stay);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Diagnostics.                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* Charge density at the nodes: area (CIC) weighting of the unit-square cloud. */
+void ora_deposit_rho(int nx, int ny, double q, int64_t n, const int32_t *ix,
+                     const int32_t *iy, const double *x, const double *y,
+                     double *rho)
+{
+    for (int64_t p = 0; p < n; p++) {
+        int i0 = ix[p], j0 = iy[p];
+        int i1 = wrap(i0 + 1, nx), j1 = wrap(j0 + 1, ny);
+        rho[IDX(i0, j0, nx)] += q * (1.0 - x[p]) * (1.0 - y[p]);
+        rho[IDX(i1, j0, nx)] += q * x[p] * (1.0 - y[p]);
+        rho[IDX(i0, j1, nx)] += q * (1.0 - x[p]) * y[p];
+        rho[IDX(i1, j1, nx)] += q * x[p] * y[p];
+    }
+}
+
+/* 1/2 dx dy sum of F^2 over the three components of a field. */
+double ora_field_energy(int nx, int ny, double dx, double dy, const double *F)
+{
+    double s = 0.0;
+    for (int64_t k = 0; k < 3 * (int64_t)nx * ny; k++) s += F[k] * F[k];
+    return 0.5 * dx * dy * s;
+}
+
+/* Kinetic energy dx dy sum m_p (gamma - 1), with particle mass m_p = q / qm. */
+double ora_kinetic_energy(double dx, double dy, double qm, double q, int64_t n,
+                          const double *ux, const double *uy, const double *uz)
+{
+    double s = 0.0;
+    for (int64_t p = 0; p < n; p++) {
+        double u2 = ux[p] * ux[p] + uy[p] * uy[p] + uz[p] * uz[p];
+        s += sqrt(1.0 + u2) - 1.0;
+    }
+    return dx * dy * (q / qm) * s;
+}
+
+/* Discrete divergence of an E-staggered field at the nodes. */
+void ora_div_e(int nx, int ny, double dx, double dy, const double *F,
+               double *out)
+{
+    const int64_t plane = (int64_t)nx * ny;
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) {
+            int im = wrap(i - 1, nx), jm = wrap(j - 1, ny);
+            out[IDX(i, j, nx)] =
+                (F[IDX(i, j, nx)] - F[IDX(im, j, nx)]) / dx +
+                (F[plane + IDX(i, j, nx)] - F[plane + IDX(i, jm, nx)]) / dy;
+        }
+}
+
+/* Discrete divergence of B at the cell centres (i+1/2, j+1/2). */
+void ora_div_b(int nx, int ny, double dx, double dy, const double *B,
+               double *out)
+{
+    const int64_t plane = (int64_t)nx * ny;
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) {
+            int ip = wrap(i + 1, nx), jp = wrap(j + 1, ny);
+            out[IDX(i, j, nx)] =
+                (B[IDX(ip, j, nx)] - B[IDX(i, j, nx)]) / dx +
+                (B[plane + IDX(i, jp, nx)] - B[plane + IDX(i, j, nx)]) / dy;
+        }
+}

@@ -1,0 +1,365 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: every expected value is a closed
+form, an invariant, a textbook special case or a brute-force computation done
+independently in numpy (area flux of the unit-square cloud, node charge of the
+cloud, discrete divergence).  A dropped term, a wrong sign or a transposed
+operand in the oracle fails at least one of these.
+"""
+import math
+
+import numpy as np
+import pytest
+
+# Staggered sample points of the six components (standard 2D Yee layout; the
+# paper's Fig. 3.1 is lost): (sx, sy) such that F[i, j] lives at (i+sx, j+sy).
+STAGGER = [(0.5, 0.0), (0.0, 0.5), (0.0, 0.0),   # Ex Ey Ez
+           (0.0, 0.5), (0.5, 0.0), (0.5, 0.5)]   # Bx By Bz
+
+
+# ---------------------------------------------------------------- helpers
+def node_charge(nx, ny, q, X, Y):
+    """Charge of unit-square clouds centred at (X, Y) (cell units) on the node
+    dual cells [i-1/2, i+1/2] x [j-1/2, j+1/2]: overlap areas, by definition."""
+    rho = np.zeros((ny, nx))
+    for Xc, Yc in zip(np.atleast_1d(X), np.atleast_1d(Y)):
+        i0, j0 = int(math.floor(Xc)), int(math.floor(Yc))
+        for i in range(i0 - 1, i0 + 3):
+            ox = max(0.0, min(Xc + 0.5, i + 0.5) - max(Xc - 0.5, i - 0.5))
+            for j in range(j0 - 1, j0 + 3):
+                oy = max(0.0, min(Yc + 0.5, j + 0.5) - max(Yc - 0.5, j - 0.5))
+                rho[j % ny, i % nx] += q * ox * oy
+    return rho
+
+
+def div_edge(J, dx, dy):
+    """Divergence at the nodes of a field living on (i+1/2, j) / (i, j+1/2)."""
+    return (J[0] - np.roll(J[0], 1, axis=1)) / dx + (J[1] - np.roll(J[1], 1, axis=0)) / dy
+
+
+def brute_current(nx, ny, dx, dy, dt, q, vz, X0, Y0, ddx, ddy, nsub=200000):
+    """Current of a unit-square cloud moving straight from (X0, Y0) by
+    (ddx, ddy) cells, by direct quadrature of the charge crossing each
+    dual-cell face and of the time-averaged overlap with each node cell."""
+    tau = (np.arange(nsub) + 0.5) / nsub
+    Xc = X0 + tau * ddx
+    Yc = Y0 + tau * ddy
+    J = np.zeros((3, ny, nx))
+    ilo, ihi = int(math.floor(min(X0, X0 + ddx))) - 2, int(math.floor(max(X0, X0 + ddx))) + 3
+    jlo, jhi = int(math.floor(min(Y0, Y0 + ddy))) - 2, int(math.floor(max(Y0, Y0 + ddy))) + 3
+
+    def overlap(c, a):  # length of [c-1/2, c+1/2] inside [a-1/2, a+1/2]
+        return np.clip(np.minimum(c + 0.5, a + 0.5) - np.maximum(c - 0.5, a - 0.5), 0.0, None)
+
+    for i in range(ilo, ihi):
+        for j in range(jlo, jhi):
+            # face x = i + 1/2, y in [j-1/2, j+1/2]  (Jx[i, j])
+            inside = np.abs(Xc - (i + 0.5)) < 0.5
+            J[0, j % ny, i % nx] += q * ddx * np.mean(inside * overlap(Yc, j)) * dx / dt
+            # face y = j + 1/2, x in [i-1/2, i+1/2]  (Jy[i, j])
+            inside = np.abs(Yc - (j + 0.5)) < 0.5
+            J[1, j % ny, i % nx] += q * ddy * np.mean(inside * overlap(Xc, i)) * dy / dt
+            # out-of-plane current at node (i, j): q vz times mean overlap area
+            J[2, j % ny, i % nx] += q * vz * np.mean(overlap(Xc, i) * overlap(Yc, j))
+    return J
+
+
+def new_position(nx, ny, ix, iy, x, y, ddx, ddy):
+    X = ix + x + ddx
+    Y = iy + y + ddy
+    return X % nx, Y % ny
+
+
+# ---------------------------------------------------------------- interpolation
+def test_interp_reproduces_bilinear_functions(ora):
+    """Bilinear interpolation is exact for span{1, X, Y, XY} sampled at each
+    component's staggered points (Sec. 3.1, linear interpolation)."""
+    nx, ny = 16, 12
+    rng = np.random.default_rng(11)
+    coef = rng.uniform(-1, 1, size=(6, 4))
+    I, Jg = np.meshgrid(np.arange(nx), np.arange(ny))
+    F = np.zeros((6, ny, nx))
+    for c, (sx, sy) in enumerate(STAGGER):
+        X, Y = I + sx, Jg + sy
+        a, b, cc, d = coef[c]
+        F[c] = a + b * X + cc * Y + d * X * Y
+    for _ in range(200):
+        ix, iy = rng.integers(2, nx - 3), rng.integers(2, ny - 3)
+        x, y = rng.random(), rng.random()
+        out = ora.interp(nx, ny, F[:3], F[3:], ix, iy, x, y)
+        X, Y = ix + x, iy + y
+        want = coef[:, 0] + coef[:, 1] * X + coef[:, 2] * Y + coef[:, 3] * X * Y
+        np.testing.assert_allclose(out, want, rtol=0, atol=1e-12)
+
+
+def test_interp_constant_field_everywhere(ora):
+    nx, ny = 8, 8
+    E = np.array([1.5, -2.0, 0.25])[:, None, None] * np.ones((3, ny, nx))
+    B = np.array([-0.5, 3.0, 7.0])[:, None, None] * np.ones((3, ny, nx))
+    for ix, iy, x, y in [(0, 0, 0.0, 0.0), (7, 7, 0.999, 0.999), (0, 7, 0.01, 0.6), (3, 4, 0.5, 0.5)]:
+        out = ora.interp(nx, ny, E, B, ix, iy, x, y)
+        np.testing.assert_allclose(out, [1.5, -2.0, 0.25, -0.5, 3.0, 7.0], atol=1e-14)
+
+
+# ---------------------------------------------------------------- Boris
+def test_boris_pure_electric_kick(ora):
+    """With B = 0, Eqs. (6)-(9) reduce to u += (q/m) E dt."""
+    rng = np.random.default_rng(1)
+    for _ in range(100):
+        qm, dt = rng.choice([-1.0, 1.0, -0.01]), 0.07
+        E = rng.normal(size=3)
+        u = rng.normal(size=3)
+        out = ora.boris(qm, dt, np.r_[E, 0, 0, 0], u)
+        np.testing.assert_allclose(out, u + qm * E * dt, rtol=0, atol=1e-14)
+
+
+def test_boris_pure_magnetic_rotation(ora):
+    """With E = 0 the update is a rotation about B: |u| and u.B are kept, the
+    angle is 2 atan(|q/m| |B| dt / (2 gamma)), and the sense is that of
+    du/dt = (q/m) u/gamma x B (Eq. 2)."""
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        qm = rng.choice([-1.0, 1.0, -3.0])
+        dt = 0.07
+        B = rng.normal(size=3) * rng.uniform(0.1, 5)
+        u = rng.normal(size=3) * rng.uniform(0.01, 3)
+        out = ora.boris(qm, dt, np.r_[0, 0, 0, B], u)
+        assert abs(np.linalg.norm(out) - np.linalg.norm(u)) <= 4e-16 * np.linalg.norm(u) * 8
+        bh = B / np.linalg.norm(B)
+        assert abs(out @ bh - u @ bh) < 1e-13 * np.linalg.norm(u)
+        up0, up1 = u - (u @ bh) * bh, out - (out @ bh) * bh
+        gamma = math.sqrt(1 + u @ u)
+        theta = 2 * math.atan(abs(qm) * np.linalg.norm(B) * dt / (2 * gamma))
+        cosang = up0 @ up1 / (np.linalg.norm(up0) * np.linalg.norm(up1))
+        sinang = np.cross(up0, up1) @ bh / (np.linalg.norm(up0) * np.linalg.norm(up1))
+        ang = math.atan2(sinang, cosang)
+        assert abs(abs(ang) - theta) < 1e-12
+        # sense: first-order step is along (q/m) (u x B)
+        force = qm * np.cross(u, B)
+        assert np.sign(ang) == np.sign(np.cross(up0, force) @ bh)
+
+
+def test_cyclotron_orbit_radius(ora):
+    """Uniform B_z, full particle advance (interp + Boris + Eq. 11): the
+    positions are the vertices of a regular polygon whose circumradius is
+    r_L sqrt(1 + eps^2), eps = |q/m| B dt / (2 gamma)."""
+    nx = ny = 64
+    dx = dy = 0.1
+    dt = 0.07
+    Bz = 2.0
+    E = np.zeros((3, ny, nx))
+    B = np.zeros((3, ny, nx))
+    B[2] = Bz
+    u0 = np.array([0.3, 0.0, 0.1])
+    sp = ora.OracleSpecies(-1.0, -1.0, [30], [30], [0.25], [0.5], [u0[0]], [u0[1]], [u0[2]])
+    sim = ora.OracleSim(nx, ny, dx, dy, dt, [sp], E, B)
+    pts = []
+    for _ in range(400):
+        sim.push_deposit()
+        pts.append(((sp.ix[0] + sp.x[0]) * dx, (sp.iy[0] + sp.y[0]) * dy))
+    P = np.array(pts)
+    # algebraic circle fit
+    A = np.c_[2 * P[:, 0], 2 * P[:, 1], np.ones(len(P))]
+    b = (P ** 2).sum(1)
+    cx, cy, c = np.linalg.lstsq(A, b, rcond=None)[0]
+    R = math.sqrt(c + cx * cx + cy * cy)
+    gamma = math.sqrt(1 + u0 @ u0)
+    rL = math.hypot(u0[0], u0[1]) / Bz
+    eps = Bz * dt / (2 * gamma)
+    assert abs(R / (rL * math.sqrt(1 + eps * eps)) - 1) < 1e-9
+    np.testing.assert_allclose(np.hypot(P[:, 0] - cx, P[:, 1] - cy), R, rtol=1e-9)
+    # momentum magnitude and u_z untouched by the rotation
+    assert abs(math.hypot(sp.ux[0], sp.uy[0]) - 0.3) < 1e-13
+    assert sp.uz[0] == 0.1
+
+
+def test_free_streaming(ora):
+    """E = B = 0: momenta stay bit-identical, X_n = X_0 + n v dt (mod L)."""
+    nx, ny = 16, 8
+    dx, dy, dt = 0.1, 0.2, 0.07
+    rng = np.random.default_rng(3)
+    n = 500
+    ix = rng.integers(0, nx, n)
+    iy = rng.integers(0, ny, n)
+    x, y = rng.random(n), rng.random(n)
+    u = rng.normal(size=(3, n)) * 0.7
+    sp = ora.OracleSpecies(-1.0, -0.1, ix, iy, x, y, *u)
+    sim = ora.OracleSim(nx, ny, dx, dy, dt, [sp])
+    steps = 50
+    for _ in range(steps):
+        sim.push_deposit()
+    assert np.array_equal(sp.ux, u[0]) and np.array_equal(sp.uy, u[1]) and np.array_equal(sp.uz, u[2])
+    g = np.sqrt(1 + (u ** 2).sum(0))
+    Xw = (ix + x + steps * u[0] / g * dt / dx) % nx
+    Yw = (iy + y + steps * u[1] / g * dt / dy) % ny
+    dXp = (sp.ix + sp.x - Xw + nx / 2) % nx - nx / 2
+    dYp = (sp.iy + sp.y - Yw + ny / 2) % ny - ny / 2
+    assert np.abs(dXp).max() < 1e-11 and np.abs(dYp).max() < 1e-11
+    assert (sp.x >= 0).all() and (sp.x < 1).all() and (sp.y >= 0).all() and (sp.y < 1).all()
+
+
+# ---------------------------------------------------------------- current deposit
+def _deposit_cases(rng, n_random=300):
+    cases = []
+    for _ in range(n_random):
+        cases.append((rng.integers(0, 6), rng.integers(0, 6), rng.random(), rng.random(),
+                      rng.uniform(-0.99, 0.99), rng.uniform(-0.99, 0.99)))
+    # forced: no crossing, x only, y only, both (x first / y first), corner hit,
+    # exact face landing, zero motion, negative directions, grid-edge wrap
+    cases += [
+        (2, 2, 0.5, 0.5, 0.2, -0.1),
+        (2, 2, 0.9, 0.5, 0.3, 0.05),
+        (2, 2, 0.5, 0.1, 0.05, -0.3),
+        (2, 2, 0.9, 0.8, 0.5, 0.25),
+        (2, 2, 0.8, 0.9, 0.25, 0.5),
+        (2, 2, 0.75, 0.75, 0.5, 0.5),     # hits the corner exactly
+        (2, 2, 0.25, 0.25, -0.5, -0.5),
+        (2, 2, 0.5, 0.5, 0.5, 0.0),       # lands exactly on x = 1
+        (2, 2, 0.5, 0.5, 0.0, 0.0),
+        (2, 2, 0.1, 0.2, -0.6, -0.7),
+        (0, 0, 0.05, 0.05, -0.5, -0.4),   # wraps at the low edges
+        (5, 5, 0.95, 0.95, 0.6, 0.7),     # wraps at the high edges
+    ]
+    return cases
+
+
+def test_deposit_continuity_single_particle(ora):
+    """Charge conservation, Eq. (12): rho(new) - rho(old) + dt div J = 0 for
+    every 1-, 2- and 3-piece motion, with rho the node charge of the cloud."""
+    nx, ny, dx, dy, dt, q = 6, 6, 0.1, 0.1, 0.07, -0.37
+    rng = np.random.default_rng(4)
+    for ix, iy, x, y, ddx, ddy in _deposit_cases(rng):
+        J = ora.deposit_move(nx, ny, dx, dy, dt, q, 0.3, ix, iy, x, y, ddx, ddy)
+        X1, Y1 = new_position(nx, ny, ix, iy, x, y, ddx, ddy)
+        r0 = node_charge(nx, ny, q, ix + x, iy + y)
+        r1 = node_charge(nx, ny, q, X1, Y1)
+        res = r1 - r0 + dt * div_edge(J, dx, dy)
+        assert np.abs(res).max() < 1e-13, (ix, iy, x, y, ddx, ddy)
+        # total fluxes: the whole charge moved by (ddx, ddy) cells
+        assert abs(J[0].sum() * dt / dx - q * ddx) < 1e-14
+        assert abs(J[1].sum() * dt / dy - q * ddy) < 1e-14
+        assert abs(J[2].sum() - q * 0.3) < 1e-14
+
+
+def test_deposit_matches_brute_force_area_flux(ora):
+    """Villasenor-Buneman fluxes (Eqs. 13-16 + splits) against a direct
+    quadrature of the charge of the unit-square cloud crossing each face, and
+    Jz against the time-averaged cloud/node-cell overlap."""
+    nx, ny, dx, dy, dt, q, vz = 8, 8, 0.1, 0.1, 0.07, 0.5, -0.4
+    rng = np.random.default_rng(5)
+    cases = _deposit_cases(rng, n_random=12)
+    for ix, iy, x, y, ddx, ddy in cases:
+        ix, iy = ix + 1, iy + 1
+        J = ora.deposit_move(nx, ny, dx, dy, dt, q, vz, ix, iy, x, y, ddx, ddy)
+        Jb = brute_current(nx, ny, dx, dy, dt, q, vz, ix + x, iy + y, ddx, ddy)
+        scale = abs(q) * dx / dt
+        np.testing.assert_allclose(J[0], Jb[0], atol=2e-5 * scale)
+        np.testing.assert_allclose(J[1], Jb[1], atol=2e-5 * scale)
+        np.testing.assert_allclose(J[2], Jb[2], atol=1e-8)
+
+
+def test_deposit_jz_reduces_to_cic_without_inplane_motion(ora):
+    nx, ny = 6, 6
+    J = ora.deposit_move(nx, ny, 0.1, 0.1, 0.07, 0.25, 0.6, 2, 3, 0.3, 0.8, 0.0, 0.0)
+    want = node_charge(nx, ny, 0.25 * 0.6, 2.3, 3.8)
+    np.testing.assert_allclose(J[2], want, atol=1e-15)
+    assert np.abs(J[:2]).max() == 0.0
+
+
+# ---------------------------------------------------------------- Yee solver
+def _yee_mode_run(ora, mode, steps=200):
+    nx, ny, dx, dy, dt = 32, 16, 0.1, 0.1, 0.07
+    kx, ky = 2 * math.pi * 2 / (nx * dx), 2 * math.pi * 1 / (ny * dy)
+    K2 = (2 * math.sin(kx * dx / 2) / dx) ** 2 + (2 * math.sin(ky * dy / 2) / dy) ** 2
+    w = 2 / dt * math.asin(dt * math.sqrt(K2) / 2)
+    I, Jg = np.meshgrid(np.arange(nx), np.arange(ny))
+    E = np.zeros((3, ny, nx))
+    B = np.zeros((3, ny, nx))
+    J = np.zeros((3, ny, nx))
+    if mode == "TM":   # Ez at the nodes
+        f0 = np.cos(kx * I * dx + ky * Jg * dy)
+        E[2] = f0
+    else:              # Bz at the cell centres
+        f0 = np.cos(kx * (I + 0.5) * dx + ky * (Jg + 0.5) * dy)
+        B[2] = f0
+    for n in range(1, steps + 1):
+        ora.yee_b(nx, ny, dx, dy, dt / 2, E, B)
+        ora.yee_e(nx, ny, dx, dy, dt, B, J, E)
+        ora.yee_b(nx, ny, dx, dy, dt / 2, E, B)
+        f = E[2] if mode == "TM" else B[2]
+        np.testing.assert_allclose(f, f0 * math.cos(n * w * dt), atol=1e-11)
+    return E, B, dx, dy
+
+
+def test_yee_tm_mode_follows_discrete_dispersion(ora):
+    """A single vacuum mode oscillates at (sin(w dt/2)/dt)^2 = sum_i (sin(k_i dx_i/2)/dx_i)^2,
+    and div B stays zero (Eqs. 18-20, three-step update of Listing 3.1)."""
+    E, B, dx, dy = _yee_mode_run(ora, "TM")
+    divB = (np.roll(B[0], -1, axis=1) - B[0]) / dx + (np.roll(B[1], -1, axis=0) - B[1]) / dy
+    assert np.abs(divB).max() < 1e-11
+
+
+def test_yee_te_mode_follows_discrete_dispersion(ora):
+    E, B, dx, dy = _yee_mode_run(ora, "TE")
+    assert np.abs(div_edge(E, dx, dy)).max() < 1e-10
+
+
+# ---------------------------------------------------------------- whole-step invariants
+def _thermal_sim(ora, nx=16, ny=16, ppc=(2, 2), u_th=0.25, seed=7, fields=False):
+    import pic_workloads as pw
+    spec = pw.SpeciesSpec(-1.0, ppc, (u_th,) * 3, (0.05, -0.03, 0.0))
+    st = pw.species_state(nx, ny, 4, spec, seed)
+    sp = ora.OracleSpecies(spec.qm, spec.q, st["ix"], st["iy"], st["x"], st["y"], st["ux"], st["uy"], st["uz"])
+    E = B = None
+    if fields:
+        E, B = pw.random_fields(nx, ny, 0.05, seed)
+    return ora.OracleSim(nx, ny, 0.1, 0.1, 0.07, [sp], E, B)
+
+
+def test_gauss_law_residual_is_preserved(ora):
+    """div E - rho is constant in time to round-off: exact continuity of the
+    deposit (Eq. 12) + Ampere's law on the Yee grid (Eqs. 17, 20)."""
+    sim = _thermal_sim(ora, fields=True)
+    s = sim.species[0]
+    g0 = div_edge(sim.E, sim.dx, sim.dy) - node_charge(sim.nx, sim.ny, s.q, s.ix + s.x, s.iy + s.y)
+    for _ in range(15):
+        sim.push_deposit()
+        sim.field_advance()
+    g = div_edge(sim.E, sim.dx, sim.dy) - node_charge(sim.nx, sim.ny, s.q, s.ix + s.x, s.iy + s.y)
+    assert np.abs(g - g0).max() < 1e-11
+
+
+def test_langmuir_frequency_leapfrog(ora):
+    """Cold plasma oscillation: w = (2/dt) asin(w_p dt / 2) (leapfrog), w_p = 1
+    for unit density electrons; kinetic and field energy trade one-to-one."""
+    import pic_workloads as pw
+    nx, ny, dx, dy, dt = 512, 2, 0.1, 0.1, 0.07
+    spec = pw.SpeciesSpec(-1.0, (4, 1), (0.0, 0.0, 0.0), (0.0, 0.0, 0.0))
+    st = pw.species_state(nx, ny, 2, spec, 1)
+    k = 2 * math.pi / (nx * dx)
+    X = (st["ix"] + st["x"].astype(np.float64)) * dx
+    v0 = 1e-4
+    ux = v0 * np.sin(k * X)
+    sp = ora.OracleSpecies(-1.0, spec.q, st["ix"], st["iy"], st["x"], st["y"], ux, 0 * ux, 0 * ux)
+    sim = ora.OracleSim(nx, ny, dx, dy, dt, [sp])
+    xs = (np.arange(nx) + 0.5) * dx
+    amp, ue, uk = [], [], []
+    for _ in range(500):
+        uk_before = sim.energies()[2][0]          # u at t - dt/2
+        sim.push_deposit()
+        uk_after = sim.energies()[2][0]           # u at t + dt/2
+        ue.append(sim.energies()[0])              # E at t (before the field update)
+        uk.append(0.5 * (uk_before + uk_after))   # time-centred kinetic energy
+        sim.field_advance()
+        amp.append(sim.E[0, 0] @ np.sin(k * xs))   # Ex ~ sin(kx) for u_x ~ sin(kx)
+    from scipy.optimize import curve_fit
+    t = np.arange(1, 501) * dt
+    a = np.array(amp)
+    p, _ = curve_fit(lambda t, A, B, w: A * np.sin(w * t) + B * np.cos(w * t), t, a,
+                     p0=[a[np.argmax(np.abs(a))], 0.0, 1.0])
+    w_theory = 2 / dt * math.asin(dt / 2)
+    assert abs(p[2] / w_theory - 1) < 5e-5, p[2] / w_theory
+    assert abs(p[2] - 1.0) > 1.5e-4     # the leapfrog shift is resolved
+    tot = np.array(ue) + np.array(uk)
+    swing = np.ptp(ue)
+    assert np.ptp(tot) < 5e-3 * swing

@@ -1,0 +1,96 @@
+"""Pins of the oracle's strict tile sort (Sec. 4.3, Fig. 4.5).
+
+The canonical result is characterised by four properties, each taken from the
+paper's description of the sort: (a) the new sections hold only their own
+tile's particles, counted from the final positions (step 1); (b) a particle
+already inside its tile's new section is not moved; (c) the holes of a section
+are filled by the particles entering that tile (steps 2-5), and -- the
+tie-break the paper leaves to atomics, fixed here -- in ascending order of
+their old slots; (d) the result is a permutation.  Brute-force enumeration over
+all permutations of tiny arrays shows these determine a unique answer, which
+the oracle must return.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _read_golden(name):
+    d = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, v = line.split(":")
+            vals = [int(t) for t in v.split()]
+            d[k.strip()] = vals if len(vals) > 1 or k.strip() in ("ix", "iy", "off", "src") else vals[0]
+    return d
+
+
+@pytest.mark.parametrize("name", ["sort_fig45.txt", "sort_shift3.txt"])
+def test_sort_golden(ora, name):
+    g = _read_golden(name)
+    off, src = ora.sort_canonical(g["nx"], g["ny"], g["T"], g["ix"], g["iy"])
+    assert off.tolist() == g["off"]
+    assert src.tolist() == g["src"]
+
+
+def _tiles(nx, T, ix, iy):
+    return (np.asarray(iy) // T) * (nx // T) + np.asarray(ix) // T
+
+
+def _valid(perm, tile, off):
+    n = len(tile)
+    for j in range(n):
+        t = tile[perm[j]]
+        if not (off[t] <= j < off[t + 1]):
+            return False
+    stay = [off[tile[i]] <= i < off[tile[i] + 1] for i in range(n)]
+    for i in range(n):
+        if stay[i] and perm[i] != i:
+            return False
+    for t in range(len(off) - 1):
+        filled = [perm[j] for j in range(off[t], off[t + 1]) if not stay[j]]
+        if filled != sorted(filled):
+            return False
+    return True
+
+
+def test_sort_brute_force_tiny(ora):
+    rng = np.random.default_rng(0)
+    for trial in range(150):
+        nx, ny, T = [(2, 2, 1), (4, 2, 2), (3, 1, 1), (2, 1, 1)][trial % 4]
+        n = int(rng.integers(0, 7))
+        ix = rng.integers(0, nx, n)
+        iy = rng.integers(0, ny, n)
+        tile = _tiles(nx, T, ix, iy)
+        ntiles = (nx // T) * (ny // T)
+        off = np.r_[0, np.cumsum(np.bincount(tile, minlength=ntiles))] if n else np.zeros(ntiles + 1, int)
+        sols = [p for p in itertools.permutations(range(n)) if _valid(p, tile, off)]
+        assert len(sols) == 1
+        o_off, o_src = ora.sort_canonical(nx, ny, T, ix, iy)
+        assert o_off.tolist() == off.tolist()
+        assert tuple(o_src.tolist()) == sols[0]
+
+
+def test_sort_properties_large(ora):
+    rng = np.random.default_rng(1)
+    nx, ny, T = 64, 32, 8
+    for n in [0, 1, 1000, 20000]:
+        ix = rng.integers(0, nx, n)
+        iy = rng.integers(0, ny, n)
+        off, src = ora.sort_canonical(nx, ny, T, ix, iy)
+        tile = _tiles(nx, T, ix, iy)
+        assert sorted(src.tolist()) == list(range(n))
+        assert off.tolist() == np.r_[0, np.cumsum(np.bincount(tile, minlength=(nx // T) * (ny // T)))].tolist()
+        assert _valid(src, tile, off)
+
+
+def test_sort_rejects_bad_cells(ora):
+    with pytest.raises(ValueError):
+        ora.sort_canonical(4, 4, 2, [0, 4], [0, 0])
