@@ -1,0 +1,200 @@
+"""Throughput of the PIC hot path on one MI355X.
+
+Workload: the warm uniform plasma, 2048 x 2048 cells, dx = dy = 0.1,
+dt = 0.07, periodic, 16 electrons per cell (67,108,864 particles), u_th = 0.05
+with drift u_x = 0.2, tile 16 x 16, strict sort every step, FP32 particles
+with an int32 packed cell index + FP32 in-cell offsets.  Synthetic, seeded.
+
+A timed step is one full PIC step through the C ABI: push + deposit
+(pic_push_deposit), strict re-sort (pic_sort) and the Yee field advance
+(pic_field_advance).  `value` counts particle pushes over the whole step.
+
+Prints ONE JSON line.  Per-kernel durations come from HIP events that libpic
+records on the launching stream during the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-pushes/sec (push+deposit+sort), 1 MI355X; % of HBM roofline"
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+BYTES_PARTICLE = 24          # cell (4) + x, y (8) + ux, uy, uz (12)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def push_bytes(n_particles, n_tiles, tile, leavers, n_species=1):
+    """Algorithmic HBM bytes of one push + deposit launch: every particle read
+    and written once, each tile's E/B halo ((T+2)^2 cells x 6 fields) read once,
+    each tile's current halo ((T+3)^2 nodes x 3) written once, the tile_offset
+    pair and the count record (16 ints) per tile and species, and one 4-byte
+    entry per leaver."""
+    return (2 * BYTES_PARTICLE * n_particles
+            + n_tiles * (tile + 2) ** 2 * 6 * 4
+            + n_tiles * (tile + 3) ** 2 * 3 * 4
+            + n_species * n_tiles * (8 + 16 * 4)
+            + 4 * leavers)
+
+
+def cpu_baseline(w, st, budget_s=10.0, max_steps=8):
+    """The oracle (serial FP64 C) on a bounded sample of the same workload:
+    the first 8,388,608 particles (the lower eighth of the grid), full-size
+    fields, push + deposit + canonical sort per step, until ~budget_s."""
+    import oracle
+    s = w.species[0]
+    M = min(8 * 1024 * 1024, st["ix"].size)
+    sp = oracle.OracleSpecies(s.qm, s.q, *(st[k][:M] for k in ("ix", "iy", "x", "y", "ux", "uy", "uz")))
+    sim = oracle.OracleSim(w.nx, w.ny, w.dx, w.dy, w.dt, [sp])
+    steps, t_hot = 0, 0.0
+    while steps < max_steps and (steps == 0 or t_hot < budget_s):
+        t0 = time.perf_counter()
+        sim.push_deposit()
+        sim.sort(w.tile)
+        t_hot += time.perf_counter() - t0
+        sim.field_advance()
+        steps += 1
+    return {"value": M * steps / t_hot, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {M} particles (tiles 0-{M // (w.tile * w.tile * s.n_ppc) - 1}) of the "
+                      f"{w.nx}x{w.ny} workload, {steps} steps of push+deposit+sort, serial FP64 C "
+                      f"(field advance untimed)",
+            "seconds": t_hot}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--replicas", type=int, default=0)
+    ap.add_argument("--workload", default="warm2048")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "push_traffic.json"),
+                    help="HBM traffic of the push kernel measured by rocprofv3 PMC runs (optional)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is "
+              f"not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import pic_workloads as pw
+    from paper_2501_14795_amd import Sim, _lib
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    w = pw.WORKLOADS[args.workload]
+    T = args.tile
+    t0 = time.perf_counter()
+    states = pw.workload_state(w, tile=T)
+    n = sum(s["ix"].size for s in states)
+    log(f"generated {n} particles in {time.perf_counter() - t0:.1f}s")
+
+    cpu = None
+    if not args.no_cpu_baseline and len(states) == 1:
+        cpu = cpu_baseline(w, states[0])
+        log(f"cpu baseline {cpu['value'] / 1e6:.2f} M push/s over {cpu['seconds']:.1f}s")
+
+    sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, T, [(s.qm, s.q, st) for s, st in zip(w.species, states)],
+              j_replicas=args.replicas)
+    del states
+    log("initialised")
+    for _ in range(args.warmup):
+        sim.step()
+    rc = sim.check()
+    if rc != 0:
+        raise SystemExit(f"device error after warmup: {_lib.strerror(rc)}")
+
+    torch.cuda.synchronize()
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sim.step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = sim.timing()
+    sim.set_timing(False)
+    rc = sim.check()
+    if rc != 0:
+        raise SystemExit(f"device error in the timed region: {_lib.strerror(rc)}")
+    d = sim.diag(_lib.PIC_DIAG_COUNTS | _lib.PIC_DIAG_ENERGY)
+    leavers = sum(d.leavers[k] for k in range(len(w.species)))
+    movers = sum(d.movers[k] for k in range(len(w.species)))
+
+    ms_step = elapsed * 1e3 / args.steps
+    value = n * args.steps / elapsed
+    push_ms = kt["push"][0] / max(kt["push"][1], 1)
+    pb = push_bytes(n, sim.n_tiles, T, leavers, len(w.species))
+    achieved = pb / (push_ms * 1e-3) / 1e9
+    hot_ms = sum(kt[k][0] for k in ("push", "j_reduce", "sort_scan", "sort_plan", "sort_scatter")) / args.steps
+
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            if tj.get("workload") == w.name and tj.get("tile") == T and tj.get("kernel_source_sha") == \
+                    _kernel_sha():
+                traffic = tj.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "particle-pushes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "dx": w.dx, "dt": w.dt,
+                   "particles": n, "ppc": sum(s.n_ppc for s in w.species), "tile": T,
+                   "j_replicas": args.replicas or (4 if T < 32 else 2), "sort_every": 1,
+                   "step": "push+deposit+sort+field_advance"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_push_deposit", "algorithmic_bytes_per_launch": pb,
+                     "avg_launch_ms": push_ms},
+        "hot_path": {
+            "ms_per_step": hot_ms,
+            "pushes_per_s": n / (hot_ms * 1e-3),
+            "kernel_ms_per_step": {k: v[0] / args.steps for k, v in kt.items()},
+            "leavers_per_step": leavers, "movers_per_step": movers,
+        },
+        "energy": {"u_e": d.u_e, "u_b": d.u_b, "u_k": d.u_k[0]},
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+    }
+    sim.close()
+    print(json.dumps(out), flush=True)
+
+
+def _kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("k_push.hip", "pic_internal.h"):
+        with open(os.path.join(ROOT, "paper_2501_14795_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

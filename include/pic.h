@@ -1,0 +1,217 @@
+/*
+ * libpic -- tiled 2D3V electromagnetic particle-in-cell step for AMD MI355X
+ * (gfx950), C ABI.
+ *
+ * The library advances a periodic 2D plasma by the PIC cycle of Guidotti,
+ * "Accelerating Particle-Mesh Algorithms with FPGAs and OmpSs@OpenCL":
+ * per-tile field interpolation (Sec. 3.1), the relativistic Boris push
+ * (Eqs. 6-10), the position advance (Eq. 11), Villasenor-Buneman
+ * charge-conserving current deposition with cell-crossing splits
+ * (Eqs. 12-16, Figs. 3.4-3.5), the strict re-sort of particles by tile
+ * (Sec. 4.3), and the three-step Yee field update (Eqs. 19-20, Listing 3.1).
+ *
+ * Units are the normalised units of Eqs. (21)-(22): c = 1, charges in units
+ * of e, masses in units of m_e, lengths in c / w_n, times in 1 / w_n.
+ *
+ * Memory model
+ *   - Every device buffer is allocated and owned by the caller; the library
+ *     keeps non-owning pointers and a small host-side record, and never frees
+ *     caller memory.  pic_query() tells the caller what to allocate.
+ *   - Every function that takes a hipStream_t enqueues its work on that stream
+ *     and returns without synchronising, except pic_init(), pic_check(),
+ *     pic_diag(), pic_get_tile_offsets() and pic_get_timing(), which
+ *     synchronise the stream they are given.
+ *   - Calls on one pic_sim must not run concurrently from several host
+ *     threads.
+ *
+ * Data layout
+ *   - Grid: nx x ny cells, node (i, j) at (i dx, j dy), periodic in x and y.
+ *     The field buffer holds nine FP32 planes of ny x nx values, row-major
+ *     (index j * nx + i), in the order Ex Ey Ez Bx By Bz Jx Jy Jz.  Yee
+ *     staggering: Ex and Jx at (i+1/2, j), Ey and Jy at (i, j+1/2), Ez and Jz
+ *     at (i, j), Bx at (i, j+1/2), By at (i+1/2, j), Bz at (i+1/2, j+1/2).
+ *   - Particles, one structure-of-arrays per species, n entries each:
+ *       cell  int32  ix | (iy << 16), 0 <= ix < nx, 0 <= iy < ny
+ *       x, y  float  offset inside the cell, in cells, in [0, 1)
+ *       ux, uy, uz  float  momentum u = gamma v (Eq. 2)
+ *     Particles must be grouped by tile: tiles are tile x tile cells numbered
+ *     row-major (t = (iy / tile) * (nx / tile) + ix / tile) and the particles
+ *     of tile t occupy one contiguous section, sections in increasing t.
+ *     pic_sort() restores this order after every push.
+ *
+ * Errors: every int-returning call returns PIC_OK (0) or a negative PIC_E*
+ * code; pic_strerror() names it.  Kernels that detect a bad state set a
+ * device-side flag that pic_check() (and pic_diag()) read back.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_MAX_SPECIES 4
+
+/* return codes */
+#define PIC_OK 0
+#define PIC_EINVAL (-1)   /* bad argument: sizes, pointers, alignment */
+#define PIC_ECFL (-2)     /* dt violates the Courant condition, Eq. (1) */
+#define PIC_ETILE (-3)    /* tile size unsupported or does not divide the grid */
+#define PIC_EHIP (-4)     /* a HIP runtime call failed */
+#define PIC_EORDER (-5)   /* particles not grouped by tile, or a cell out of range */
+#define PIC_ERANGE (-6)   /* a particle tried to move one cell or more in a step */
+#define PIC_ESORT (-7)    /* internal sort consistency check failed */
+#define PIC_ECOUNT (-8)   /* tile counts do not add up to the particle count */
+
+typedef struct pic_species {
+    double qm;    /* charge-to-mass ratio q/m (electrons: -1) */
+    double q;     /* charge density carried by one particle (e.g. -n0 / ppc) */
+    int64_t n;    /* number of particles, 0 <= n < 2^31 */
+} pic_species;
+
+typedef struct pic_config {
+    int32_t nx, ny;      /* cells; multiples of tile, 1 <= nx, ny <= 32767 */
+    double dx, dy, dt;   /* cell size and time step; dt < 1/sqrt(1/dx^2 + 1/dy^2) */
+    int32_t tile;        /* tile edge in cells: 8, 16 or 32 */
+    int32_t j_replicas;  /* LDS current replicas per tile: 1, 2 or 4 (0 = default) */
+    int32_t n_species;   /* 1 .. PIC_MAX_SPECIES */
+    uint32_t flags;      /* reserved, must be 0 */
+    pic_species species[PIC_MAX_SPECIES];
+} pic_config;
+
+typedef struct pic_particles {   /* device pointers, n entries each */
+    int32_t *cell;
+    float *x, *y, *ux, *uy, *uz;
+} pic_particles;
+
+typedef struct pic_buffers {
+    float *fields;       /* device, 9 * nx * ny floats (layout above) */
+    void *work;          /* device, pic_sizes.work_bytes, 256-byte aligned */
+    size_t work_bytes;
+    pic_particles sp[PIC_MAX_SPECIES];
+} pic_buffers;
+
+typedef struct pic_sizes {
+    int32_t n_tiles;
+    size_t field_bytes;  /* bytes of pic_buffers.fields */
+    size_t work_bytes;   /* bytes of pic_buffers.work */
+} pic_sizes;
+
+typedef struct pic_sim pic_sim;   /* opaque */
+
+/*
+ * Sizes of the caller-allocated buffers for cfg.  Allocates nothing.
+ * Returns PIC_EINVAL / PIC_ETILE / PIC_ECFL on a bad configuration.
+ */
+int pic_query(const pic_config *cfg, pic_sizes *out);
+
+/*
+ * Validate cfg (Courant condition Eq. 1, tile divisibility, sizes) and bind
+ * the caller's buffers.  The caller has filled the particle arrays (grouped
+ * by tile) and the E and B planes; J is overwritten by every push.  Builds
+ * tile_offset for every species on the device, checks the tile grouping and
+ * synchronises `stream`.  Returns PIC_EORDER if the particles are not grouped
+ * by tile or a cell is out of range.  On success *out owns a host record
+ * that pic_destroy() frees.
+ */
+int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
+             pic_sim **out);
+
+/*
+ * Particle half of the step (Listing 3.1 loop body, Sec. 4.2): for every tile,
+ * stage its E/B halo in LDS, interpolate, Boris-push (Eqs. 6-10), move
+ * (Eq. 11), deposit the Villasenor-Buneman current of each 1/2/3-piece
+ * motion into LDS (Eqs. 13-16), then write J (all species) into the J planes,
+ * folding the periodic images (update_gc_add).  Also records, per tile, the
+ * particles that left it, as input for pic_sort().  A particle that would move
+ * one cell or more sets PIC_ERANGE (reported by pic_check()).
+ */
+int pic_push_deposit(pic_sim *sim, hipStream_t stream);
+
+/*
+ * Strict re-sort by tile after a push (Sec. 4.3, Fig. 4.5): recount the
+ * tiles, rebuild tile_offset, and move every particle whose slot lies outside
+ * its tile's new section into a hole.  The result is the canonical one: holes
+ * in ascending slot order receive the movers ordered by destination tile,
+ * then by old slot.  Particles already in their section do not move.
+ */
+int pic_sort(pic_sim *sim, hipStream_t stream);
+
+/*
+ * Field half of the step (Listing 3.1): B half step, E full step with the
+ * current J, B half step (Eqs. 19-20 on the Yee grid, periodic images read
+ * directly: update_gc_copy).
+ */
+int pic_field_advance(pic_sim *sim, hipStream_t stream);
+
+/* pic_push_deposit + pic_sort + pic_field_advance. */
+int pic_step(pic_sim *sim, hipStream_t stream);
+
+/* Synchronise `stream` and report (and clear) the device error flags. */
+int pic_check(pic_sim *sim, hipStream_t stream);
+
+/* Diagnostics, FP64 reductions on the device. */
+#define PIC_DIAG_ENERGY 1u          /* u_e, u_b, u_k */
+#define PIC_DIAG_RHO_SNAPSHOT 2u    /* remember rho of the current positions */
+#define PIC_DIAG_CONTINUITY 4u      /* residual against the snapshot and current J */
+#define PIC_DIAG_COUNTS 8u          /* leavers of the last push, movers of the last sort */
+
+typedef struct pic_diag_out {
+    double u_e;                       /* 1/2 dx dy sum |E|^2 */
+    double u_b;                       /* 1/2 dx dy sum |B|^2 */
+    double u_k[PIC_MAX_SPECIES];      /* dx dy sum (q/qm) (gamma - 1) */
+    double continuity_max;            /* max |rho' - rho + dt div J| */
+    double rho_max;                   /* max |rho'| */
+    int64_t leavers[PIC_MAX_SPECIES]; /* particles whose tile changed */
+    int64_t movers[PIC_MAX_SPECIES];  /* particles moved by the last sort */
+} pic_diag_out;
+
+/*
+ * Compute the diagnostics selected by `what` (bitwise OR of PIC_DIAG_*) on
+ * `stream`, synchronise it and fill *out (fields not selected are zero).
+ * PIC_DIAG_CONTINUITY evaluates Eq. (12) in discrete form,
+ * rho(now) - rho(snapshot) + dt * div J, at the nodes; it returns PIC_EINVAL
+ * without an earlier PIC_DIAG_RHO_SNAPSHOT.  Also reports device error flags
+ * like pic_check().
+ */
+int pic_diag(pic_sim *sim, unsigned what, pic_diag_out *out, hipStream_t stream);
+
+/* Copy the current tile_offset of `species` (n_tiles + 1 int32) to host memory. */
+int pic_get_tile_offsets(pic_sim *sim, int species, int32_t *host_out, hipStream_t stream);
+
+/* Per-kernel timing with HIP events on the launching stream. */
+#define PIC_KERNEL_PUSH 0         /* push + deposit kernel */
+#define PIC_KERNEL_JREDUCE 1      /* tile current fold into the J planes */
+#define PIC_KERNEL_SORT_SCAN 2    /* tile recount + tile_offset scan */
+#define PIC_KERNEL_SORT_PLAN 3    /* hole/mover pairing + mover gather */
+#define PIC_KERNEL_SORT_SCATTER 4 /* mover scatter into holes */
+#define PIC_KERNEL_FIELD 5        /* the three Yee sub-steps */
+#define PIC_N_KERNELS 6
+
+typedef struct pic_timing_out {
+    double ms_total[PIC_N_KERNELS];   /* summed event time since the last reset */
+    int64_t launches[PIC_N_KERNELS];
+} pic_timing_out;
+
+/* enable = 1: record HIP events around every launch from now on; 0: stop. Resets the sums. */
+int pic_set_timing(pic_sim *sim, int enable);
+
+/* Synchronise on the recorded events and return the sums since the last reset. */
+int pic_get_timing(pic_sim *sim, pic_timing_out *out);
+
+/* Static string naming a return code. */
+const char *pic_strerror(int code);
+
+/* Free the host record.  Caller buffers are untouched. */
+void pic_destroy(pic_sim *sim);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIC_H */

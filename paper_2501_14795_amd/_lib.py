@@ -1,0 +1,186 @@
+"""ctypes binding of libpic's C ABI (include/pic.h): structures and the
+``pic_*`` functions under the same names.  Argument marshalling only -- every
+step of the PIC cycle runs in the HIP kernels of libpic.so.  There is no CPU
+fallback: if the library is missing this module raises on first use."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(HERE, "libpic.so")
+
+MAX_SPECIES = 4
+
+PIC_OK = 0
+PIC_EINVAL = -1
+PIC_ECFL = -2
+PIC_ETILE = -3
+PIC_EHIP = -4
+PIC_EORDER = -5
+PIC_ERANGE = -6
+PIC_ESORT = -7
+PIC_ECOUNT = -8
+
+PIC_DIAG_ENERGY = 1
+PIC_DIAG_RHO_SNAPSHOT = 2
+PIC_DIAG_CONTINUITY = 4
+PIC_DIAG_COUNTS = 8
+
+KERNELS = ["push", "j_reduce", "sort_scan", "sort_plan", "sort_scatter", "field"]
+
+# every symbol the header declares
+EXPORTS = [
+    "pic_query", "pic_init", "pic_push_deposit", "pic_sort", "pic_field_advance", "pic_step",
+    "pic_check", "pic_diag", "pic_get_tile_offsets", "pic_set_timing", "pic_get_timing",
+    "pic_strerror", "pic_destroy",
+]
+
+
+class pic_species(ctypes.Structure):
+    _fields_ = [("qm", ctypes.c_double), ("q", ctypes.c_double), ("n", ctypes.c_int64)]
+
+
+class pic_config(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dt", ctypes.c_double),
+                ("tile", ctypes.c_int32), ("j_replicas", ctypes.c_int32),
+                ("n_species", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("species", pic_species * MAX_SPECIES)]
+
+
+class pic_particles(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("cell", "x", "y", "ux", "uy", "uz")]
+
+
+class pic_buffers(ctypes.Structure):
+    _fields_ = [("fields", ctypes.c_void_p), ("work", ctypes.c_void_p),
+                ("work_bytes", ctypes.c_size_t), ("sp", pic_particles * MAX_SPECIES)]
+
+
+class pic_sizes(ctypes.Structure):
+    _fields_ = [("n_tiles", ctypes.c_int32), ("field_bytes", ctypes.c_size_t),
+                ("work_bytes", ctypes.c_size_t)]
+
+
+class pic_diag_out(ctypes.Structure):
+    _fields_ = [("u_e", ctypes.c_double), ("u_b", ctypes.c_double),
+                ("u_k", ctypes.c_double * MAX_SPECIES),
+                ("continuity_max", ctypes.c_double), ("rho_max", ctypes.c_double),
+                ("leavers", ctypes.c_int64 * MAX_SPECIES), ("movers", ctypes.c_int64 * MAX_SPECIES)]
+
+
+class pic_timing_out(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_double * 6), ("launches", ctypes.c_int64 * 6)]
+
+
+class PicError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+_L = None
+
+
+def load(path: str = SO_PATH):
+    """Load libpic.so (raises if it has not been built)."""
+    global _L
+    if _L is not None:
+        return _L
+    if not os.path.exists(path):
+        raise ImportError(f"libpic.so not built at {path}; run __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp = ctypes.c_void_p
+    L.pic_query.argtypes = [P(pic_config), P(pic_sizes)]
+    L.pic_init.argtypes = [P(pic_config), P(pic_buffers), vp, P(vp)]
+    for name in ("pic_push_deposit", "pic_sort", "pic_field_advance", "pic_step", "pic_check"):
+        getattr(L, name).argtypes = [vp, vp]
+    L.pic_diag.argtypes = [vp, ctypes.c_uint, P(pic_diag_out), vp]
+    L.pic_get_tile_offsets.argtypes = [vp, ctypes.c_int, vp, vp]
+    L.pic_set_timing.argtypes = [vp, ctypes.c_int]
+    L.pic_get_timing.argtypes = [vp, P(pic_timing_out)]
+    L.pic_strerror.argtypes = [ctypes.c_int]
+    L.pic_strerror.restype = ctypes.c_char_p
+    L.pic_destroy.argtypes = [vp]
+    L.pic_destroy.restype = None
+    for name in EXPORTS:
+        if name not in ("pic_strerror", "pic_destroy"):
+            getattr(L, name).restype = ctypes.c_int
+    _L = L
+    return L
+
+
+def strerror(code: int) -> str:
+    return load().pic_strerror(int(code)).decode()
+
+
+def _chk(rc: int, where: str) -> int:
+    if rc != PIC_OK:
+        raise PicError(rc, where)
+    return rc
+
+
+# ---- the C functions, same names, raising PicError on a negative code ----
+
+def pic_query(cfg: pic_config) -> pic_sizes:
+    out = pic_sizes()
+    _chk(load().pic_query(ctypes.byref(cfg), ctypes.byref(out)), "pic_query")
+    return out
+
+
+def pic_init(cfg: pic_config, bufs: pic_buffers, stream: int) -> int:
+    h = ctypes.c_void_p()
+    _chk(load().pic_init(ctypes.byref(cfg), ctypes.byref(bufs), ctypes.c_void_p(stream), ctypes.byref(h)),
+         "pic_init")
+    return h.value
+
+
+def pic_push_deposit(sim: int, stream: int):
+    _chk(load().pic_push_deposit(ctypes.c_void_p(sim), ctypes.c_void_p(stream)), "pic_push_deposit")
+
+
+def pic_sort(sim: int, stream: int):
+    _chk(load().pic_sort(ctypes.c_void_p(sim), ctypes.c_void_p(stream)), "pic_sort")
+
+
+def pic_field_advance(sim: int, stream: int):
+    _chk(load().pic_field_advance(ctypes.c_void_p(sim), ctypes.c_void_p(stream)), "pic_field_advance")
+
+
+def pic_step(sim: int, stream: int):
+    _chk(load().pic_step(ctypes.c_void_p(sim), ctypes.c_void_p(stream)), "pic_step")
+
+
+def pic_check(sim: int, stream: int) -> int:
+    """Returns the code (does not raise) so callers can test error paths."""
+    return load().pic_check(ctypes.c_void_p(sim), ctypes.c_void_p(stream))
+
+
+def pic_diag(sim: int, what: int, stream: int) -> pic_diag_out:
+    out = pic_diag_out()
+    _chk(load().pic_diag(ctypes.c_void_p(sim), ctypes.c_uint(what), ctypes.byref(out), ctypes.c_void_p(stream)),
+         "pic_diag")
+    return out
+
+
+def pic_get_tile_offsets(sim: int, species: int, n_tiles: int, stream: int):
+    buf = (ctypes.c_int32 * (n_tiles + 1))()
+    _chk(load().pic_get_tile_offsets(ctypes.c_void_p(sim), species, ctypes.cast(buf, ctypes.c_void_p),
+                                     ctypes.c_void_p(stream)), "pic_get_tile_offsets")
+    return list(buf)
+
+
+def pic_set_timing(sim: int, enable: bool):
+    _chk(load().pic_set_timing(ctypes.c_void_p(sim), 1 if enable else 0), "pic_set_timing")
+
+
+def pic_get_timing(sim: int) -> pic_timing_out:
+    out = pic_timing_out()
+    _chk(load().pic_get_timing(ctypes.c_void_p(sim), ctypes.byref(out)), "pic_get_timing")
+    return out
+
+
+def pic_destroy(sim: int):
+    load().pic_destroy(ctypes.c_void_p(sim))

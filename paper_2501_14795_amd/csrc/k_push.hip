@@ -1,0 +1,369 @@
+// Particle push + current deposit for one tile per workgroup, and the fold of
+// the per-tile current halos into the global J planes.
+//
+// Per tile (Sec. 4.2.2 maps one tile to one work-group; redesigned here for
+// gfx950 wave64 + LDS):
+//   1. stage the tile's E/B halo (cells -1..T on each axis) in LDS, packed so
+//      that the two x-neighbours every bilinear stencil needs come in one
+//      ds_read_b64/b128;
+//   2. each wavefront streams a contiguous quarter of the tile's particle
+//      section (coalesced SoA loads, no block barrier in the loop);
+//   3. per particle: bilinear interpolation at the staggered points
+//      (Sec. 3.1), Boris push (Eqs. 6-10), move (Eq. 11), and the
+//      Villasenor-Buneman current (Eqs. 13-16) of each of the 1, 2 or 3 pieces
+//      of the motion (Figs. 3.4-3.5) added into one of R LDS current replicas
+//      (replica = lane mod R) with ds_add_f32;
+//   4. particles whose tile changed are appended, in slot order, to the
+//      wavefront's leaver sub-list (ballot + mbcnt), and counted per
+//      direction -- the input of the strict sort (Sec. 4.3, step 1);
+//   5. the replicas are summed and the (T+3)^2 current halo of the tile is
+//      written out; k_j_reduce then adds the up-to-four overlapping tile halos
+//      of every node in a fixed order (deterministic, no global atomics).
+#include "pic_internal.h"
+
+namespace pic {
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ __forceinline__ float lerpf(float a, float b, float w) { return fmaf(w, b - a, a); }
+
+__device__ __forceinline__ float clamp01(float v) { return fminf(fmaxf(v, 0.0f), 1.0f); }
+
+__device__ __forceinline__ int lane_rank(unsigned long long m)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// Length of the section share streamed by one wavefront: ceil(n/4) rounded up
+// to whole 64-particle chunks.  The sort reads the leaver sub-lists with it.
+__host__ __device__ __forceinline__ int wave_share(int n) { return (((n + 3) >> 2) + 63) & ~63; }
+
+// Current of one piece of the motion inside cell (cx, cy) (tile-relative,
+// -1..T), from (xa, ya) to (xb, yb) in that cell's frame, lasting `frac` of
+// the step.  Jx/Jy are the Villasenor-Buneman face fluxes times dx/dt, dy/dt;
+// Jz is q vz frac times the time-averaged bilinear weight of each corner,
+// written as w_mid + or - dxk dyk / 12.
+template <int NJ>
+__device__ __forceinline__ void deposit_piece(float *sj, int cx, int cy, float xa, float ya,
+                                              float xb, float yb, float frac, float jxs,
+                                              float jys, float qvz)
+{
+    constexpr int P = NJ * NJ;
+    const float dxk = xb - xa, dyk = yb - ya;
+    const float xm = 0.5f * (xa + xb), ym = 0.5f * (ya + yb);
+    const float ax = jxs * dxk, ay = jys * dyk;
+    const float c = dxk * dyk * (1.0f / 12.0f);
+    const float jz = qvz * frac;
+    const float xm1 = 1.0f - xm, ym1 = 1.0f - ym;
+    const int b = (cy + 1) * NJ + (cx + 1);
+    atomicAdd(&sj[b], ax * ym1);
+    atomicAdd(&sj[b + NJ], ax * ym);
+    atomicAdd(&sj[P + b], ay * xm1);
+    atomicAdd(&sj[P + b + 1], ay * xm);
+    atomicAdd(&sj[2 * P + b], jz * fmaf(xm1, ym1, c));
+    atomicAdd(&sj[2 * P + b + 1], jz * fmaf(xm, ym1, -c));
+    atomicAdd(&sj[2 * P + b + NJ], jz * fmaf(xm1, ym, -c));
+    atomicAdd(&sj[2 * P + b + NJ + 1], jz * fmaf(xm, ym, c));
+}
+
+template <int T, int R>
+__global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
+{
+    constexpr int NE = T + 2;   // staged E/B cells per axis: relative -1..T
+    constexpr int NJ = T + 3;   // current halo nodes per axis: relative -1..T+1
+    constexpr int JP = NJ * NJ;
+
+    // packed E/B: entry [r][c] holds the values at relative cells c-1 and c
+    // (x-neighbours) of row r-1
+    __shared__ float4 s_exby[NE * NE];   // Ex(c-1), By(c-1), Ex(c), By(c)
+    __shared__ float4 s_eybx[NE * NE];   // Ey, Bx likewise
+    __shared__ float2 s_ez[NE * NE];
+    __shared__ float2 s_bz[NE * NE];
+    __shared__ float s_j[R][3 * JP];
+    __shared__ int s_dir[kMaxSpecies][9];
+    __shared__ int s_wl[kMaxSpecies][kWaves];
+
+    const int tile = blockIdx.x;
+    const int tx = tile % a.ntx, ty = tile / a.ntx;
+    const int gx0 = tx * T, gy0 = ty * T;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int64_t plane = (int64_t)a.nx * a.ny;
+
+    for (int e = tid; e < NE * NE; e += kBlock) {
+        const int r = e / NE, c = e - r * NE;
+        const int64_t row = (int64_t)wrapi(gy0 - 1 + r, a.ny) * a.nx;
+        const int64_t i0 = row + wrapi(gx0 - 1 + c, a.nx);
+        const int64_t i1 = row + wrapi(gx0 + c, a.nx);
+        const float *f = a.fld;
+        s_exby[e] = make_float4(f[i0], f[4 * plane + i0], f[i1], f[4 * plane + i1]);
+        s_eybx[e] = make_float4(f[plane + i0], f[3 * plane + i0], f[plane + i1], f[3 * plane + i1]);
+        s_ez[e] = make_float2(f[2 * plane + i0], f[2 * plane + i1]);
+        s_bz[e] = make_float2(f[5 * plane + i0], f[5 * plane + i1]);
+    }
+    for (int e = tid; e < R * 3 * JP; e += kBlock) (&s_j[0][0])[e] = 0.0f;
+    if (tid < kMaxSpecies * 9) (&s_dir[0][0])[tid] = 0;
+    __syncthreads();
+
+    float *sj = s_j[lane % R];
+    const bool tx_wrap = a.ntx > 1, ty_wrap = a.nty > 1;
+
+    for (int s = 0; s < a.n_species; ++s) {
+        const SpeciesDev sp = a.sp[s];
+        const int begin = sp.off[tile];
+        const int n = sp.off[tile + 1] - begin;
+        const int share = wave_share(n);
+        const int lo = wave * share;
+        const int hi = min(lo + share, n);
+        int nleav = 0;   // wavefront-uniform
+        for (int kb = lo; kb < hi; kb += 64) {
+            const int k = kb + lane;
+            bool leaver = false;
+            int dir = 4;
+            if (k < hi) {
+                const int64_t i = (int64_t)begin + k;
+                const int cell = sp.cell[i];
+                float x = sp.x[i], y = sp.y[i];
+                float ux = sp.ux[i], uy = sp.uy[i], uz = sp.uz[i];
+                int lx = (cell & 0xffff) - gx0, ly = (cell >> 16) - gy0;
+                if ((unsigned)lx >= (unsigned)T || (unsigned)ly >= (unsigned)T) {
+                    atomicOr(a.err, kErrOrder);
+                    lx = min(max(lx, 0), T - 1);
+                    ly = min(max(ly, 0), T - 1);
+                }
+
+                // ---- interpolation (bilinear at each component's staggered point)
+                const bool xh = x >= 0.5f, yh = y >= 0.5f;
+                const float wxh = xh ? x - 0.5f : x + 0.5f;   // weight for (i+1/2) points
+                const float wyh = yh ? y - 0.5f : y + 0.5f;
+                const int ch = lx + (xh ? 1 : 0);             // packed column of the half stencil
+                const int rh = ly + (yh ? 1 : 0);
+                const int c0 = lx + 1, r0 = ly + 1;
+                const float4 p0 = s_exby[r0 * NE + ch], p1 = s_exby[(r0 + 1) * NE + ch];
+                const float4 q0 = s_eybx[rh * NE + c0], q1 = s_eybx[(rh + 1) * NE + c0];
+                const float2 z0 = s_ez[r0 * NE + c0], z1 = s_ez[(r0 + 1) * NE + c0];
+                const float2 b0 = s_bz[rh * NE + ch], b1 = s_bz[(rh + 1) * NE + ch];
+                const float Ex = lerpf(lerpf(p0.x, p0.z, wxh), lerpf(p1.x, p1.z, wxh), y);
+                const float By = lerpf(lerpf(p0.y, p0.w, wxh), lerpf(p1.y, p1.w, wxh), y);
+                const float Ey = lerpf(lerpf(q0.x, q0.z, x), lerpf(q1.x, q1.z, x), wyh);
+                const float Bx = lerpf(lerpf(q0.y, q0.w, x), lerpf(q1.y, q1.w, x), wyh);
+                const float Ez = lerpf(lerpf(z0.x, z0.y, x), lerpf(z1.x, z1.y, x), y);
+                const float Bz = lerpf(lerpf(b0.x, b0.y, wxh), lerpf(b1.x, b1.y, wxh), wyh);
+
+                // ---- Boris push (Eqs. 6-10)
+                const float h = sp.h;
+                const float mx = fmaf(h, Ex, ux), my = fmaf(h, Ey, uy), mz = fmaf(h, Ez, uz);
+                const float gi = rsqrtf(fmaf(mx, mx, fmaf(my, my, fmaf(mz, mz, 1.0f))));
+                const float hg = h * gi;
+                const float tx_ = hg * Bx, ty_ = hg * By, tz_ = hg * Bz;
+                const float px = fmaf(my, tz_, fmaf(-mz, ty_, mx));
+                const float py = fmaf(mz, tx_, fmaf(-mx, tz_, my));
+                const float pz = fmaf(mx, ty_, fmaf(-my, tx_, mz));
+                const float f2 = __fdividef(2.0f, fmaf(tx_, tx_, fmaf(ty_, ty_, fmaf(tz_, tz_, 1.0f))));
+                const float sx_ = f2 * tx_, sy_ = f2 * ty_, sz_ = f2 * tz_;
+                ux = fmaf(h, Ex, fmaf(py, sz_, fmaf(-pz, sy_, mx)));
+                uy = fmaf(h, Ey, fmaf(pz, sx_, fmaf(-px, sz_, my)));
+                uz = fmaf(h, Ez, fmaf(px, sy_, fmaf(-py, sx_, mz)));
+
+                // ---- move (Eq. 11), in cells
+                const float ig = rsqrtf(fmaf(ux, ux, fmaf(uy, uy, fmaf(uz, uz, 1.0f))));
+                float dX = ux * ig * a.cx, dY = uy * ig * a.cy;
+                if (!(fabsf(dX) < 1.0f && fabsf(dY) < 1.0f)) {
+                    atomicOr(a.err, kErrRange);
+                    dX = 0.0f;
+                    dY = 0.0f;
+                }
+                const float x1 = x + dX, y1 = y + dY;
+                const int sxn = x1 >= 1.0f ? 1 : (x1 < 0.0f ? -1 : 0);
+                const int syn = y1 >= 1.0f ? 1 : (y1 < 0.0f ? -1 : 0);
+
+                // ---- Villasenor-Buneman deposit of the 1, 2 or 3 pieces
+                {
+                    const float ex = sxn > 0 ? 1.0f : 0.0f;   // x face crossed (start-cell frame)
+                    const float ey = syn > 0 ? 1.0f : 0.0f;
+                    const float tcx = sxn ? clamp01(__fdividef(ex - x, dX)) : 1.0f;
+                    const float tcy = syn ? clamp01(__fdividef(ey - y, dY)) : 1.0f;
+                    const bool xfirst = sxn != 0 && (syn == 0 || tcx <= tcy);
+                    const float t1 = xfirst ? tcx : tcy;
+                    const float t2 = xfirst ? tcy : tcx;
+                    const int nseg = 1 + (sxn != 0) + (syn != 0);
+                    const float qvz = sp.q * uz * ig;
+                    float ax_ = x, ay_ = y, ta = 0.0f;
+                    int ox = 0, oy = 0;
+#pragma unroll
+                    for (int p = 0; p < 3; ++p) {
+                        if (p < nseg) {
+                            float tb, bx, by;
+                            int nox = ox, noy = oy;
+                            if (p == nseg - 1) {
+                                tb = 1.0f;
+                                bx = x1;
+                                by = y1;
+                            } else {
+                                const bool xev = (p == 0) ? xfirst : !xfirst;
+                                tb = (p == 0) ? t1 : t2;
+                                if (xev) {
+                                    bx = ex;
+                                    by = fmaf(tb, dY, y);
+                                    nox = ox + sxn;
+                                } else {
+                                    bx = fmaf(tb, dX, x);
+                                    by = ey;
+                                    noy = oy + syn;
+                                }
+                            }
+                            deposit_piece<NJ>(sj, lx + ox, ly + oy, clamp01(ax_ - ox),
+                                              clamp01(ay_ - oy), clamp01(bx - ox),
+                                              clamp01(by - oy), tb - ta, sp.jx, sp.jy, qvz);
+                            ax_ = bx;
+                            ay_ = by;
+                            ta = tb;
+                            ox = nox;
+                            oy = noy;
+                        }
+                    }
+                }
+
+                // ---- new position: offset back into [0,1), cell index, periodic wrap
+                int nlx = lx, nly = ly;
+                float xn = x1, yn = y1;
+                if (sxn > 0) {
+                    xn = x1 - 1.0f;
+                    nlx += 1;
+                } else if (sxn < 0) {
+                    xn = x1 + 1.0f;
+                    nlx -= 1;
+                    if (xn >= 1.0f) {   // rounded onto the face: it is x = 0 of the old cell
+                        xn = 0.0f;
+                        nlx += 1;
+                    }
+                }
+                if (syn > 0) {
+                    yn = y1 - 1.0f;
+                    nly += 1;
+                } else if (syn < 0) {
+                    yn = y1 + 1.0f;
+                    nly -= 1;
+                    if (yn >= 1.0f) {
+                        yn = 0.0f;
+                        nly += 1;
+                    }
+                }
+                const int gx = wrapi(gx0 + nlx, a.nx), gy = wrapi(gy0 + nly, a.ny);
+                sp.cell[i] = gx | (gy << 16);
+                sp.x[i] = xn;
+                sp.y[i] = yn;
+                sp.ux[i] = ux;
+                sp.uy[i] = uy;
+                sp.uz[i] = uz;
+
+                const int dtx = tx_wrap ? (nlx < 0 ? -1 : (nlx >= T ? 1 : 0)) : 0;
+                const int dty = ty_wrap ? (nly < 0 ? -1 : (nly >= T ? 1 : 0)) : 0;
+                dir = (dty + 1) * 3 + (dtx + 1);
+                leaver = dir != 4;
+            }
+            const unsigned long long m = __ballot(leaver);
+            if (leaver) {
+                sp.leav[(int64_t)begin + lo + nleav + lane_rank(m)] = ((uint32_t)k << 4) | (uint32_t)dir;
+                atomicAdd(&s_dir[s][dir], 1);
+            }
+            nleav += __popcll(m);
+        }
+        if (lane == 0) s_wl[s][wave] = nleav;
+    }
+    __syncthreads();
+
+    // per-tile count records
+    if (tid < a.n_species * kCntStride) {
+        const int s = tid / kCntStride, k = tid % kCntStride;
+        const int n = a.sp[s].off[tile + 1] - a.sp[s].off[tile];
+        int leavers = 0;
+        for (int w = 0; w < kWaves; ++w) leavers += s_wl[s][w];
+        int v = 0;
+        if (k < 9) v = (k == 4) ? n - leavers : s_dir[s][k];
+        else if (k == kCntLeavers) v = leavers;
+        else if (k < kCntSub + kWaves) v = s_wl[s][k - kCntSub];
+        a.sp[s].cnt[(int64_t)tile * kCntStride + k] = v;
+    }
+
+    // sum the replicas and write the tile's current halo
+    float *out = a.jtile + (int64_t)tile * 3 * JP;
+    for (int e = tid; e < 3 * JP; e += kBlock) {
+        float v = s_j[0][e];
+#pragma unroll
+        for (int r = 1; r < R; ++r) v += s_j[r][e];
+        out[e] = v;
+    }
+}
+
+// J[c][gy][gx] = sum over the tiles whose halo (relative -1..T+1) covers the
+// node, in fixed (ty, tx) order -- the periodic fold of update_gc_add.
+template <int T>
+__global__ void __launch_bounds__(256) k_j_reduce(const float *__restrict__ jtile, float *__restrict__ J,
+                                                  int nx, int ny, int ntx, int nty)
+{
+    constexpr int NJ = T + 3;
+    constexpr int JP = NJ * NJ;
+    const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (gx >= nx || gy >= ny) return;
+    const int bx = gx / T, by = gy / T;
+    float acc[3] = {0.0f, 0.0f, 0.0f};
+    for (int ky = -1; ky <= 1; ++ky) {
+        const int ry = gy - (by + ky) * T;
+        if (ry < -1 || ry > T + 1) continue;
+        const int ty = wrapi(by + ky, nty);
+        for (int kx = -1; kx <= 1; ++kx) {
+            const int rx = gx - (bx + kx) * T;
+            if (rx < -1 || rx > T + 1) continue;
+            const int tx = wrapi(bx + kx, ntx);
+            const float *src = jtile + (int64_t)(ty * ntx + tx) * 3 * JP + (ry + 1) * NJ + (rx + 1);
+            acc[0] += src[0];
+            acc[1] += src[JP];
+            acc[2] += src[2 * JP];
+        }
+    }
+    const int64_t plane = (int64_t)nx * ny;
+    const int64_t k = (int64_t)gy * nx + gx;
+    J[k] = acc[0];
+    J[plane + k] = acc[1];
+    J[2 * plane + k] = acc[2];
+}
+
+template <int T, int R>
+static void launch_pd(const PushArgs &a, int n_tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_push_deposit<T, R>), dim3(n_tiles), dim3(kBlock), 0, s, a);
+}
+
+template <int T>
+static void launch_pd_r(int replicas, const PushArgs &a, int n_tiles, hipStream_t s)
+{
+    switch (replicas) {
+    case 1: launch_pd<T, 1>(a, n_tiles, s); break;
+    case 2: launch_pd<T, 2>(a, n_tiles, s); break;
+    default: launch_pd<T, 4>(a, n_tiles, s); break;
+    }
+}
+
+void launch_push_deposit(int tile, int replicas, const PushArgs &a, int n_tiles, hipStream_t s)
+{
+    switch (tile) {
+    case 8: launch_pd_r<8>(replicas, a, n_tiles, s); break;
+    case 16: launch_pd_r<16>(replicas, a, n_tiles, s); break;
+    default: launch_pd_r<32>(replicas, a, n_tiles, s); break;
+    }
+}
+
+void launch_j_reduce(int tile, const float *jtile, float *J, int nx, int ny, int ntx, int nty,
+                     hipStream_t s)
+{
+    dim3 grid((nx + 63) / 64, (ny + 3) / 4);
+    switch (tile) {
+    case 8: hipLaunchKernelGGL((k_j_reduce<8>), grid, dim3(256), 0, s, jtile, J, nx, ny, ntx, nty); break;
+    case 16: hipLaunchKernelGGL((k_j_reduce<16>), grid, dim3(256), 0, s, jtile, J, nx, ny, ntx, nty); break;
+    default: hipLaunchKernelGGL((k_j_reduce<32>), grid, dim3(256), 0, s, jtile, J, nx, ny, ntx, nty); break;
+    }
+}
+
+}  // namespace pic

@@ -1,0 +1,529 @@
+// C ABI of libpic: validation, workspace carve-up, launch sequencing, error
+// flags, diagnostics and per-kernel event timing.  See include/pic.h.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "pic_internal.h"
+
+using namespace pic;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+    size_t err = 0, dacc = 0, cacc = 0, jtile = 0, rho_prev = 0, rho_now = 0;
+    size_t off[kMaxSpecies][2] = {}, cnt[kMaxSpecies] = {}, leav[kMaxSpecies] = {};
+    size_t hole[kMaxSpecies] = {}, stg[kMaxSpecies][6] = {}, mcount[kMaxSpecies] = {};
+    size_t total = 0;
+};
+
+int default_replicas(int tile) { return tile >= 32 ? 2 : 4; }
+
+int validate(const pic_config *c)
+{
+    if (!c) return PIC_EINVAL;
+    if (c->flags != 0) return PIC_EINVAL;
+    if (c->tile != 8 && c->tile != 16 && c->tile != 32) return PIC_ETILE;
+    if (c->nx < c->tile || c->ny < c->tile || c->nx > 32767 || c->ny > 32767) return PIC_EINVAL;
+    if (c->nx % c->tile || c->ny % c->tile) return PIC_ETILE;
+    if (c->j_replicas != 0 && c->j_replicas != 1 && c->j_replicas != 2 && c->j_replicas != 4)
+        return PIC_EINVAL;
+    if (c->n_species < 1 || c->n_species > kMaxSpecies) return PIC_EINVAL;
+    if (!(c->dx > 0) || !(c->dy > 0) || !(c->dt > 0)) return PIC_EINVAL;
+    // Courant-Levy condition, Eq. (1), with c = 1
+    if (!(c->dt < 1.0 / sqrt(1.0 / (c->dx * c->dx) + 1.0 / (c->dy * c->dy)))) return PIC_ECFL;
+    for (int s = 0; s < c->n_species; ++s) {
+        const pic_species &sp = c->species[s];
+        if (sp.n < 0 || sp.n >= (int64_t)1 << 31) return PIC_EINVAL;
+        if (!isfinite(sp.qm) || !isfinite(sp.q)) return PIC_EINVAL;
+    }
+    return PIC_OK;
+}
+
+Layout make_layout(const pic_config *c)
+{
+    Layout L;
+    const int T = c->tile;
+    const int64_t n_tiles = (int64_t)(c->nx / T) * (c->ny / T);
+    const int64_t nodes = (int64_t)c->nx * c->ny;
+    size_t p = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = p;
+        p = align_up(p + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    L.err = take(64);
+    L.dacc = take(32 * sizeof(double));
+    L.cacc = take(8 * sizeof(unsigned long long));
+    L.jtile = take((size_t)n_tiles * 3 * (T + 3) * (T + 3) * sizeof(float));
+    L.rho_prev = take(nodes * sizeof(double));
+    L.rho_now = take(nodes * sizeof(double));
+    for (int s = 0; s < c->n_species; ++s) {
+        const size_t n = (size_t)c->species[s].n;
+        L.off[s][0] = take((n_tiles + 1) * sizeof(int32_t));
+        L.off[s][1] = take((n_tiles + 1) * sizeof(int32_t));
+        L.cnt[s] = take((size_t)n_tiles * kCntStride * sizeof(int32_t));
+        L.leav[s] = take(n * sizeof(uint32_t));
+        L.hole[s] = take(n * sizeof(int32_t));
+        for (int k = 0; k < 6; ++k) L.stg[s][k] = take(n * 4);
+        L.mcount[s] = take((size_t)n_tiles * sizeof(int32_t));
+    }
+    L.total = p;
+    return L;
+}
+
+}  // namespace
+
+struct pic_sim {
+    pic_config cfg;
+    pic_buffers buf;
+    int ntx, nty, n_tiles, tile, replicas;
+    char *work;
+    int *err;
+    double *dacc;
+    unsigned long long *cacc;
+    float *jtile;
+    double *rho_prev, *rho_now;
+    bool have_snapshot;
+    struct Sp {
+        int32_t *off[2];
+        int cur;
+        int32_t *cnt;
+        uint32_t *leav;
+        int32_t *hole;
+        int32_t *stg_cell;
+        float *stg[5];
+        int32_t *mcount;
+    } sp[kMaxSpecies];
+    // timing
+    bool timing;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[PIC_N_KERNELS];
+    double ms[PIC_N_KERNELS];
+    int64_t launches[PIC_N_KERNELS];
+};
+
+namespace {
+
+hipEvent_t take_event(pic_sim *s)
+{
+    if (!s->pool.empty()) {
+        hipEvent_t e = s->pool.back();
+        s->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records HIP events around the launches of one kernel class on `stream`.
+struct Timed {
+    pic_sim *s;
+    int k;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    Timed(pic_sim *sim, int kernel, hipStream_t stream) : s(sim), k(kernel), st(stream)
+    {
+        if (s->timing) {
+            a = take_event(s);
+            if (a) (void)hipEventRecord(a, st);
+        }
+    }
+    ~Timed()
+    {
+        if (a) {
+            hipEvent_t b = take_event(s);
+            if (b) {
+                (void)hipEventRecord(b, st);
+                s->pending[k].push_back({a, b});
+            } else {
+                s->pool.push_back(a);
+            }
+        }
+    }
+};
+
+int hip_ok(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EHIP; }
+
+int read_errors(pic_sim *s, hipStream_t stream)
+{
+    int h = 0;
+    if (hipMemcpyAsync(&h, s->err, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess) return PIC_EHIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return PIC_EHIP;
+    if (h) {
+        if (hipMemsetAsync(s->err, 0, sizeof(int), stream) != hipSuccess) return PIC_EHIP;
+        if (hipStreamSynchronize(stream) != hipSuccess) return PIC_EHIP;
+    }
+    if (h & kErrOrder) return PIC_EORDER;
+    if (h & kErrRange) return PIC_ERANGE;
+    if (h & kErrCount) return PIC_ECOUNT;
+    if (h & kErrSort) return PIC_ESORT;
+    return PIC_OK;
+}
+
+DiagSpecies diag_species(const pic_sim *s, int k)
+{
+    DiagSpecies d;
+    const pic_particles &p = s->buf.sp[k];
+    d.cell = p.cell;
+    d.x = p.x;
+    d.y = p.y;
+    d.ux = p.ux;
+    d.uy = p.uy;
+    d.uz = p.uz;
+    d.n = (int32_t)s->cfg.species[k].n;
+    d.q = s->cfg.species[k].q;
+    return d;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pic_strerror(int code)
+{
+    switch (code) {
+    case PIC_OK: return "ok";
+    case PIC_EINVAL: return "invalid argument";
+    case PIC_ECFL: return "time step violates the Courant condition";
+    case PIC_ETILE: return "tile size unsupported or does not divide the grid";
+    case PIC_EHIP: return "HIP runtime call failed";
+    case PIC_EORDER: return "particles not grouped by tile or cell index out of range";
+    case PIC_ERANGE: return "a particle moved one cell or more in one step";
+    case PIC_ESORT: return "sort consistency check failed";
+    case PIC_ECOUNT: return "tile counts do not add up to the particle count";
+    default: return "unknown error";
+    }
+}
+
+int pic_query(const pic_config *cfg, pic_sizes *out)
+{
+    if (!out) return PIC_EINVAL;
+    const int rc = validate(cfg);
+    if (rc) return rc;
+    const Layout L = make_layout(cfg);
+    out->n_tiles = (cfg->nx / cfg->tile) * (cfg->ny / cfg->tile);
+    out->field_bytes = (size_t)9 * cfg->nx * cfg->ny * sizeof(float);
+    out->work_bytes = L.total;
+    return PIC_OK;
+}
+
+int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream, pic_sim **out)
+{
+    if (!out || !bufs) return PIC_EINVAL;
+    *out = nullptr;
+    int rc = validate(cfg);
+    if (rc) return rc;
+    const Layout L = make_layout(cfg);
+    if (!bufs->fields || !bufs->work || bufs->work_bytes < L.total) return PIC_EINVAL;
+    if (((uintptr_t)bufs->work) % kAlign) return PIC_EINVAL;
+    for (int s = 0; s < cfg->n_species; ++s) {
+        const pic_particles &p = bufs->sp[s];
+        if (cfg->species[s].n > 0 && (!p.cell || !p.x || !p.y || !p.ux || !p.uy || !p.uz)) return PIC_EINVAL;
+    }
+
+    pic_sim *S = new (std::nothrow) pic_sim();
+    if (!S) return PIC_EINVAL;
+    S->cfg = *cfg;
+    S->buf = *bufs;
+    S->tile = cfg->tile;
+    S->ntx = cfg->nx / cfg->tile;
+    S->nty = cfg->ny / cfg->tile;
+    S->n_tiles = S->ntx * S->nty;
+    S->replicas = cfg->j_replicas ? cfg->j_replicas : default_replicas(cfg->tile);
+    char *w = (char *)bufs->work;
+    S->work = w;
+    S->err = (int *)(w + L.err);
+    S->dacc = (double *)(w + L.dacc);
+    S->cacc = (unsigned long long *)(w + L.cacc);
+    S->jtile = (float *)(w + L.jtile);
+    S->rho_prev = (double *)(w + L.rho_prev);
+    S->rho_now = (double *)(w + L.rho_now);
+    for (int s = 0; s < cfg->n_species; ++s) {
+        auto &P = S->sp[s];
+        P.off[0] = (int32_t *)(w + L.off[s][0]);
+        P.off[1] = (int32_t *)(w + L.off[s][1]);
+        P.cur = 0;
+        P.cnt = (int32_t *)(w + L.cnt[s]);
+        P.leav = (uint32_t *)(w + L.leav[s]);
+        P.hole = (int32_t *)(w + L.hole[s]);
+        P.stg_cell = (int32_t *)(w + L.stg[s][0]);
+        for (int k = 0; k < 5; ++k) P.stg[k] = (float *)(w + L.stg[s][k + 1]);
+        P.mcount = (int32_t *)(w + L.mcount[s]);
+    }
+
+    rc = hip_ok(hipMemsetAsync(S->err, 0, 64, stream));
+    for (int s = 0; s < cfg->n_species && rc == PIC_OK; ++s) {
+        auto &P = S->sp[s];
+        // counts go through the cnt record area, which the first push overwrites
+        rc = hip_ok(hipMemsetAsync(P.cnt, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
+        if (rc) break;
+        launch_init_tiles(bufs->sp[s].cell, (int32_t)cfg->species[s].n, cfg->nx, cfg->ny, cfg->tile, S->ntx,
+                          P.cnt, S->n_tiles, P.off[0], S->err, stream);
+        rc = hip_ok(hipMemsetAsync(P.mcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
+    }
+    if (rc == PIC_OK) rc = hip_ok(hipGetLastError());
+    if (rc == PIC_OK) rc = read_errors(S, stream);
+    if (rc != PIC_OK) {
+        delete S;
+        return rc;
+    }
+    *out = S;
+    return PIC_OK;
+}
+
+int pic_push_deposit(pic_sim *S, hipStream_t stream)
+{
+    if (!S) return PIC_EINVAL;
+    const pic_config &c = S->cfg;
+    PushArgs a;
+    memset(&a, 0, sizeof(a));
+    const int64_t plane = (int64_t)c.nx * c.ny;
+    a.fld = S->buf.fields;
+    a.jtile = S->jtile;
+    a.err = S->err;
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.ntx = S->ntx;
+    a.nty = S->nty;
+    a.cx = (float)(c.dt / c.dx);
+    a.cy = (float)(c.dt / c.dy);
+    a.n_species = c.n_species;
+    for (int s = 0; s < c.n_species; ++s) {
+        const pic_particles &p = S->buf.sp[s];
+        SpeciesDev &d = a.sp[s];
+        d.cell = p.cell;
+        d.x = p.x;
+        d.y = p.y;
+        d.ux = p.ux;
+        d.uy = p.uy;
+        d.uz = p.uz;
+        d.off = S->sp[s].off[S->sp[s].cur];
+        d.cnt = S->sp[s].cnt;
+        d.leav = S->sp[s].leav;
+        d.n = (int32_t)c.species[s].n;
+        d.h = (float)(0.5 * c.species[s].qm * c.dt);
+        d.jx = (float)(c.species[s].q * c.dx / c.dt);
+        d.jy = (float)(c.species[s].q * c.dy / c.dt);
+        d.q = (float)c.species[s].q;
+    }
+    {
+        Timed t(S, PIC_KERNEL_PUSH, stream);
+        launch_push_deposit(S->tile, S->replicas, a, S->n_tiles, stream);
+    }
+    {
+        Timed t(S, PIC_KERNEL_JREDUCE, stream);
+        launch_j_reduce(S->tile, S->jtile, S->buf.fields + 6 * plane, c.nx, c.ny, S->ntx, S->nty, stream);
+    }
+    return hip_ok(hipGetLastError());
+}
+
+int pic_sort(pic_sim *S, hipStream_t stream)
+{
+    if (!S) return PIC_EINVAL;
+    const pic_config &c = S->cfg;
+    SortArgs a;
+    memset(&a, 0, sizeof(a));
+    a.err = S->err;
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.ntx = S->ntx;
+    a.nty = S->nty;
+    a.tile = S->tile;
+    a.n_species = c.n_species;
+    for (int s = 0; s < c.n_species; ++s) {
+        const pic_particles &p = S->buf.sp[s];
+        auto &P = S->sp[s];
+        SortSpecies &d = a.sp[s];
+        d.cell = p.cell;
+        d.x = p.x;
+        d.y = p.y;
+        d.ux = p.ux;
+        d.uy = p.uy;
+        d.uz = p.uz;
+        d.off = P.off[P.cur];
+        d.offn = P.off[P.cur ^ 1];
+        d.cnt = P.cnt;
+        d.leav = P.leav;
+        d.hole = P.hole;
+        d.stg_cell = P.stg_cell;
+        d.stg_x = P.stg[0];
+        d.stg_y = P.stg[1];
+        d.stg_ux = P.stg[2];
+        d.stg_uy = P.stg[3];
+        d.stg_uz = P.stg[4];
+        d.mcount = P.mcount;
+        d.n = (int32_t)c.species[s].n;
+    }
+    {
+        Timed t(S, PIC_KERNEL_SORT_SCAN, stream);
+        launch_sort_scan(a, S->n_tiles, stream);
+    }
+    {
+        Timed t(S, PIC_KERNEL_SORT_PLAN, stream);
+        launch_sort_plan(a, S->n_tiles, stream);
+    }
+    {
+        Timed t(S, PIC_KERNEL_SORT_SCATTER, stream);
+        launch_sort_scatter(a, S->n_tiles, stream);
+    }
+    for (int s = 0; s < c.n_species; ++s) S->sp[s].cur ^= 1;
+    return hip_ok(hipGetLastError());
+}
+
+int pic_field_advance(pic_sim *S, hipStream_t stream)
+{
+    if (!S) return PIC_EINVAL;
+    const pic_config &c = S->cfg;
+    Timed t(S, PIC_KERNEL_FIELD, stream);
+    launch_yee_b(S->buf.fields, c.nx, c.ny, (float)(0.5 * c.dt / c.dx), (float)(0.5 * c.dt / c.dy), stream);
+    launch_yee_e(S->buf.fields, c.nx, c.ny, (float)c.dt, (float)(c.dt / c.dx), (float)(c.dt / c.dy), stream);
+    launch_yee_b(S->buf.fields, c.nx, c.ny, (float)(0.5 * c.dt / c.dx), (float)(0.5 * c.dt / c.dy), stream);
+    return hip_ok(hipGetLastError());
+}
+
+int pic_step(pic_sim *S, hipStream_t stream)
+{
+    int rc = pic_push_deposit(S, stream);
+    if (rc == PIC_OK) rc = pic_sort(S, stream);
+    if (rc == PIC_OK) rc = pic_field_advance(S, stream);
+    return rc;
+}
+
+int pic_check(pic_sim *S, hipStream_t stream)
+{
+    if (!S) return PIC_EINVAL;
+    return read_errors(S, stream);
+}
+
+int pic_diag(pic_sim *S, unsigned what, pic_diag_out *out, hipStream_t stream)
+{
+    if (!S || !out) return PIC_EINVAL;
+    memset(out, 0, sizeof(*out));
+    const pic_config &c = S->cfg;
+    const int64_t plane = (int64_t)c.nx * c.ny;
+    if ((what & PIC_DIAG_CONTINUITY) && !S->have_snapshot) return PIC_EINVAL;
+    int rc = hip_ok(hipMemsetAsync(S->dacc, 0, 32 * sizeof(double), stream));
+    if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(S->cacc, 0, 8 * sizeof(unsigned long long), stream));
+    if (rc) return rc;
+    if (what & PIC_DIAG_ENERGY) {
+        launch_diag_field_energy(S->buf.fields, plane, S->dacc, stream);
+        for (int s = 0; s < c.n_species; ++s) launch_diag_kinetic(diag_species(S, s), S->dacc + 2 + s, stream);
+    }
+    if (what & (PIC_DIAG_RHO_SNAPSHOT | PIC_DIAG_CONTINUITY)) {
+        rc = hip_ok(hipMemsetAsync(S->rho_now, 0, plane * sizeof(double), stream));
+        if (rc) return rc;
+        for (int s = 0; s < c.n_species; ++s) launch_diag_rho(diag_species(S, s), c.nx, c.ny, S->rho_now, stream);
+    }
+    if (what & PIC_DIAG_CONTINUITY)
+        launch_diag_continuity(S->rho_prev, S->rho_now, S->buf.fields + 6 * plane, c.nx, c.ny, c.dt, c.dx, c.dy,
+                               S->dacc + 8, stream);
+    double dh[32];
+    unsigned long long ch[8 * kMaxSpecies];
+    rc = hip_ok(hipMemcpyAsync(dh, S->dacc, sizeof(dh), hipMemcpyDeviceToHost, stream));
+    if (rc == PIC_OK && (what & PIC_DIAG_COUNTS)) {
+        for (int s = 0; s < c.n_species && rc == PIC_OK; ++s) {
+            rc = hip_ok(hipMemsetAsync(S->cacc, 0, 2 * sizeof(unsigned long long), stream));
+            if (rc) break;
+            launch_diag_counts(S->sp[s].cnt, S->sp[s].mcount, S->n_tiles, S->cacc, stream);
+            rc = hip_ok(hipMemcpyAsync(ch + 2 * s, S->cacc, 2 * sizeof(unsigned long long),
+                                       hipMemcpyDeviceToHost, stream));
+            if (rc == PIC_OK) rc = hip_ok(hipStreamSynchronize(stream));
+        }
+    }
+    if (rc == PIC_OK) rc = hip_ok(hipStreamSynchronize(stream));
+    if (rc) return rc;
+    if (what & PIC_DIAG_ENERGY) {
+        const double dA = c.dx * c.dy;
+        out->u_e = 0.5 * dA * dh[0];
+        out->u_b = 0.5 * dA * dh[1];
+        for (int s = 0; s < c.n_species; ++s)
+            out->u_k[s] = dA * (c.species[s].q / c.species[s].qm) * dh[2 + s];
+    }
+    if (what & PIC_DIAG_CONTINUITY) {
+        out->continuity_max = dh[8];
+        out->rho_max = dh[9];
+    }
+    if (what & PIC_DIAG_COUNTS)
+        for (int s = 0; s < c.n_species; ++s) {
+            out->leavers[s] = (int64_t)ch[2 * s];
+            out->movers[s] = (int64_t)ch[2 * s + 1];
+        }
+    if (what & (PIC_DIAG_RHO_SNAPSHOT | PIC_DIAG_CONTINUITY)) {
+        std::swap(S->rho_prev, S->rho_now);
+        S->have_snapshot = true;
+    }
+    return read_errors(S, stream);
+}
+
+int pic_get_tile_offsets(pic_sim *S, int species, int32_t *host_out, hipStream_t stream)
+{
+    if (!S || !host_out || species < 0 || species >= S->cfg.n_species) return PIC_EINVAL;
+    const auto &P = S->sp[species];
+    int rc = hip_ok(hipMemcpyAsync(host_out, P.off[P.cur], (size_t)(S->n_tiles + 1) * sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, stream));
+    if (rc == PIC_OK) rc = hip_ok(hipStreamSynchronize(stream));
+    return rc;
+}
+
+int pic_set_timing(pic_sim *S, int enable)
+{
+    if (!S) return PIC_EINVAL;
+    for (int k = 0; k < PIC_N_KERNELS; ++k) {
+        for (auto &pr : S->pending[k]) {
+            (void)hipEventSynchronize(pr.second);
+            S->pool.push_back(pr.first);
+            S->pool.push_back(pr.second);
+        }
+        S->pending[k].clear();
+        S->ms[k] = 0.0;
+        S->launches[k] = 0;
+    }
+    S->timing = enable != 0;
+    return PIC_OK;
+}
+
+int pic_get_timing(pic_sim *S, pic_timing_out *out)
+{
+    if (!S || !out) return PIC_EINVAL;
+    int rc = PIC_OK;
+    for (int k = 0; k < PIC_N_KERNELS; ++k) {
+        for (auto &pr : S->pending[k]) {
+            if (hipEventSynchronize(pr.second) != hipSuccess) rc = PIC_EHIP;
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess) rc = PIC_EHIP;
+            S->ms[k] += ms;
+            S->launches[k] += 1;
+            S->pool.push_back(pr.first);
+            S->pool.push_back(pr.second);
+        }
+        S->pending[k].clear();
+        out->ms_total[k] = S->ms[k];
+        out->launches[k] = S->launches[k];
+    }
+    return rc;
+}
+
+void pic_destroy(pic_sim *S)
+{
+    if (!S) return;
+    for (int k = 0; k < PIC_N_KERNELS; ++k)
+        for (auto &pr : S->pending[k]) {
+            (void)hipEventSynchronize(pr.second);
+            S->pool.push_back(pr.first);
+            S->pool.push_back(pr.second);
+        }
+    for (hipEvent_t e : S->pool) (void)hipEventDestroy(e);
+    delete S;
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+// Internal declarations shared by the libpic translation units (host launchers
+// and kernels).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pic.h"
+
+namespace pic {
+
+constexpr int kMaxSpecies = PIC_MAX_SPECIES;
+constexpr int kBlock = 256;          // threads per push / sort block (4 wavefronts)
+constexpr int kWaves = kBlock / 64;
+constexpr int kCntStride = 16;       // ints per tile in the count record
+
+// Count record of one tile, written by the push kernel:
+//   [0..8]   particles per direction of motion d = (dty+1)*3 + (dtx+1);
+//            [4] holds the particles that kept their tile
+//   [9]      leavers (sum of the eight non-centre directions)
+//   [10..13] leavers found by wavefront w (length of leaver sub-list w)
+constexpr int kCntLeavers = 9;
+constexpr int kCntSub = 10;
+
+// Device error bits (ORed into Sim::err).
+enum : int {
+    kErrOrder = 1,   // particle outside its tile section / cell out of range
+    kErrRange = 2,   // displacement of one cell or more
+    kErrSort = 4,    // hole / mover count mismatch
+    kErrCount = 8,   // tile counts do not sum to n
+};
+
+struct SpeciesDev {
+    int32_t *cell;
+    float *x, *y, *ux, *uy, *uz;
+    const int32_t *off;   // tile_offset at the start of the step (n_tiles + 1)
+    int32_t *cnt;         // [n_tiles][kCntStride]
+    uint32_t *leav;       // [n]: leaver sub-lists, (slot - off[t]) << 4 | direction
+    int32_t n;
+    float h;              // (q/m) dt / 2
+    float jx;             // q dx / dt
+    float jy;             // q dy / dt
+    float q;
+};
+
+struct PushArgs {
+    const float *fld;     // Ex Ey Ez Bx By Bz planes
+    float *jtile;         // [n_tiles][3][(T+3)^2]
+    int *err;
+    int nx, ny, ntx, nty;
+    float cx, cy;         // dt/dx, dt/dy
+    int n_species;
+    SpeciesDev sp[kMaxSpecies];
+};
+
+struct SortSpecies {
+    int32_t *cell;
+    float *x, *y, *ux, *uy, *uz;
+    const int32_t *off;   // old tile_offset
+    int32_t *offn;        // new tile_offset
+    const int32_t *cnt;
+    const uint32_t *leav;
+    int32_t *hole;        // [n]
+    int32_t *stg_cell;    // staging SoA [n] each
+    float *stg_x, *stg_y, *stg_ux, *stg_uy, *stg_uz;
+    int32_t *mcount;      // [n_tiles]
+    int32_t n;
+};
+
+struct SortArgs {
+    int *err;
+    int nx, ny, ntx, nty, tile;
+    int n_species;
+    SortSpecies sp[kMaxSpecies];
+};
+
+// ---- launchers (each defined next to its kernels) ----
+void launch_push_deposit(int tile, int replicas, const PushArgs &a, int n_tiles, hipStream_t s);
+void launch_j_reduce(int tile, const float *jtile, float *J, int nx, int ny, int ntx, int nty,
+                     hipStream_t s);
+void launch_sort_scan(const SortArgs &a, int n_tiles, hipStream_t s);
+void launch_sort_plan(const SortArgs &a, int n_tiles, hipStream_t s);
+void launch_sort_scatter(const SortArgs &a, int n_tiles, hipStream_t s);
+void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile, int ntx,
+                       int32_t *counts, int n_tiles, int32_t *off, int *err, hipStream_t s);
+void launch_yee_b(float *fld, int nx, int ny, float hdx, float hdy, hipStream_t s);
+void launch_yee_e(float *fld, int nx, int ny, float dt, float dtdx, float dtdy, hipStream_t s);
+
+struct DiagSpecies {
+    const int32_t *cell;
+    const float *x, *y, *ux, *uy, *uz;
+    int32_t n;
+    double q;
+};
+void launch_diag_field_energy(const float *fld, int64_t plane, double *acc, hipStream_t s);
+void launch_diag_kinetic(const DiagSpecies &sp, double *acc, hipStream_t s);
+void launch_diag_rho(const DiagSpecies &sp, int nx, int ny, double *rho, hipStream_t s);
+void launch_diag_continuity(const double *rho_prev, const double *rho_now, const float *J,
+                            int nx, int ny, double dt, double dx, double dy, double *acc,
+                            hipStream_t s);
+void launch_diag_counts(const int32_t *cnt, const int32_t *mcount, int n_tiles,
+                        unsigned long long *acc, hipStream_t s);
+
+}  // namespace pic

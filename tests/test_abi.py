@@ -1,0 +1,116 @@
+"""The C-ABI library loads on a machine without a GPU, exports every symbol
+include/pic.h declares, its ctypes mirror matches the C layout, and the
+allocation-free calls (pic_query, pic_strerror) validate configurations."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pic.h")
+
+
+def _lib():
+    from paper_2501_14795_amd import _lib
+    if not os.path.exists(_lib.SO_PATH):
+        pytest.skip("libpic.so not built")
+    return _lib
+
+
+def test_exports_every_declared_symbol():
+    L = _lib()
+    text = open(HEADER).read()
+    declared = set(re.findall(r"^\s*(?:int|void|const char \*)\s*(pic_\w+)\s*\(", text, re.M))
+    assert declared == set(L.EXPORTS)
+    lib = L.load()
+    for name in declared:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", L.SO_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT (pic_\w+)$", out, re.M))
+    assert declared <= exported
+
+
+def test_struct_layout_matches_header(tmp_path):
+    L = _lib()
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "pic.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(pic_config), sizeof(pic_buffers), sizeof(pic_sizes),
+         sizeof(pic_diag_out), sizeof(pic_timing_out), sizeof(pic_species), sizeof(pic_particles));
+  printf("%zu %zu %zu %zu %zu\\n", offsetof(pic_config, species), offsetof(pic_config, tile),
+         offsetof(pic_buffers, sp), offsetof(pic_diag_out, leavers), offsetof(pic_sizes, work_bytes));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                           "-I", "/opt/rocm/include", str(src), "-o", str(exe)])
+    got = subprocess.check_output([str(exe)], text=True).split()
+    c = ctypes
+    want = [c.sizeof(L.pic_config), c.sizeof(L.pic_buffers), c.sizeof(L.pic_sizes),
+            c.sizeof(L.pic_diag_out), c.sizeof(L.pic_timing_out), c.sizeof(L.pic_species),
+            c.sizeof(L.pic_particles),
+            L.pic_config.species.offset, L.pic_config.tile.offset, L.pic_buffers.sp.offset,
+            L.pic_diag_out.leavers.offset, L.pic_sizes.work_bytes.offset]
+    assert [int(v) for v in got] == want
+
+
+def _cfg(L, nx=64, ny=64, dx=0.1, dy=0.1, dt=0.07, tile=16, n=1000, ns=1, reps=0):
+    c = L.pic_config()
+    c.nx, c.ny, c.dx, c.dy, c.dt, c.tile, c.j_replicas, c.n_species, c.flags = nx, ny, dx, dy, dt, tile, reps, ns, 0
+    for k in range(ns):
+        c.species[k].qm = -1.0
+        c.species[k].q = -1.0 / 16
+        c.species[k].n = n
+    return c
+
+
+def test_query_sizes_and_validation():
+    L = _lib()
+    s = L.pic_query(_cfg(L))
+    assert s.n_tiles == 16 and s.field_bytes == 9 * 64 * 64 * 4 and s.work_bytes > 0
+    big = L.pic_query(_cfg(L, nx=2048, ny=2048, n=2048 * 2048 * 16))
+    assert big.n_tiles == 128 * 128
+    # workspace grows linearly with particles (leaver list, holes, staging: 32 B/particle)
+    s2 = L.pic_query(_cfg(L, n=2000))
+    assert 32 * 1000 <= s2.work_bytes - s.work_bytes <= 32 * 1000 + 4096
+    cases = [
+        (dict(dt=0.0708), L.PIC_ECFL),          # Eq. (1): limit 0.070711 at dx = dy = 0.1
+        (dict(dt=0.08), L.PIC_ECFL),
+        (dict(tile=12), L.PIC_ETILE),
+        (dict(nx=72), L.PIC_ETILE),
+        (dict(nx=8, tile=16), L.PIC_EINVAL),
+        (dict(nx=32768 + 16), L.PIC_EINVAL),
+        (dict(ns=0), L.PIC_EINVAL),
+        (dict(ns=5), L.PIC_EINVAL),
+        (dict(reps=3), L.PIC_EINVAL),
+        (dict(n=-1), L.PIC_EINVAL),
+        (dict(n=2 ** 31), L.PIC_EINVAL),
+    ]
+    for kw, code in cases:
+        ns = kw.pop("ns", 1)
+        c = _cfg(L, ns=min(max(ns, 0), 4), **kw)
+        if ns == 0 or ns == 5:
+            c.n_species = ns
+        with pytest.raises(L.PicError) as e:
+            L.pic_query(c)
+        assert e.value.code == code, (kw, e.value.code)
+    assert L.pic_query(_cfg(L, dt=0.0707)).n_tiles == 16
+    for code in range(0, -9, -1):
+        assert L.strerror(code) != "unknown error"
+    assert L.strerror(-99) == "unknown error"
+
+
+def test_init_rejects_bad_buffers_without_touching_the_device():
+    L = _lib()
+    c = _cfg(L)
+    b = L.pic_buffers()   # all NULL
+    with pytest.raises(L.PicError) as e:
+        L.pic_init(c, b, 0)
+    assert e.value.code == L.PIC_EINVAL
