@@ -18,7 +18,9 @@
 //      direction -- the input of the strict sort (Sec. 4.3, step 1);
 //   5. the replicas are summed and the (T+3)^2 current halo of the tile is
 //      written out; k_j_reduce then adds the up-to-four overlapping tile halos
-//      of every node in a fixed order (deterministic, no global atomics).
+//      of every node in a fixed order (no global atomics).  The LDS atomics
+//      of step 3 add in an order that varies between runs, so J is
+//      reproducible to FP32 round-off, not bit for bit.
 #include "pic_internal.h"
 
 namespace pic {

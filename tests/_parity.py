@@ -64,6 +64,17 @@ def particle_errors(g, o, nx, ny):
     return float(pos), float(du / umax)
 
 
+def as_species(g):
+    """A GPU state dict viewed like an OracleSpecies (FP64 offsets/momenta)."""
+    class _S:
+        pass
+    s = _S()
+    s.ix, s.iy = g["ix"], g["iy"]
+    for k in ("x", "y", "ux", "uy", "uz"):
+        setattr(s, k, g[k].astype(np.float64))
+    return s
+
+
 def matched_particle_errors(g, o, nx, ny):
     """Like particle_errors, but when the slot order differs (a tile crossing
     decided differently in FP32 and FP64 reorders a section) the particles are

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import pic_workloads as pw
-from _parity import (flush, make_pair, matched_particle_errors, oracle_from_gpu, particle_errors,
+from _parity import (as_species, flush, make_pair, matched_particle_errors, oracle_from_gpu, particle_errors,
                      rel_err, sort_replay, species_states)
 
 pytestmark = pytest.mark.gpu
@@ -168,21 +168,33 @@ def test_current_replicas(reps):
     _replay_steps(64, 64, 16, specs, states, E, B, steps=2, reps=reps, label=f"R={reps}")
 
 
-def test_deterministic_bitwise():
+def test_repeatability():
+    """Two identical runs.  Particle updates and the sort are deterministic, so
+    the first push and sort agree bit for bit; the LDS current is summed with
+    float atomics whose order across wavefronts is not fixed, so J -- and
+    everything downstream of it -- agrees only to FP32 round-off."""
     specs, states, E, B = _uniform(u_th=0.2, fields=0.05, seed=8)
-    runs = []
+    first, runs = [], []
     for _ in range(2):
         sim, _ = make_pair(64, 64, DX, DY, DT, 16, specs, states, E, B)
-        for _s in range(5):
+        sim.push_deposit()
+        sim.sort()
+        first.append((sim.state(0), sim.field_arrays()["J"]))
+        sim.field_advance()
+        for _s in range(4):
             sim.step()
         assert sim.check() == 0
         runs.append((sim.state(0), sim.field_arrays()))
         sim.close()
-    (a, fa), (b, fb) = runs
+    (a, ja), (b, jb) = first
     for k in a:
-        assert np.array_equal(a[k], b[k])
+        assert np.array_equal(a[k], b[k]), k
+    assert rel_err(ja, jb) < 1e-6
+    (a, fa), (b, fb) = runs
+    pos, du = particle_errors(a, as_species(b), 64, 64)
+    assert pos < 1e-5 and du < 1e-5
     for k in fa:
-        assert np.array_equal(fa[k], fb[k])
+        assert rel_err(fa[k], fb[k]) < 1e-5, k
 
 
 def test_empty_species_and_zero_particles():
