@@ -80,7 +80,11 @@ def main():
     ap.add_argument("--tile", type=int, default=16)
     ap.add_argument("--replicas", type=int, default=0)
     ap.add_argument("--workload", default="warm2048")
+    ap.add_argument("--j-float", action="store_true", help="FP32-atomic LDS current instead of fixed point")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (a known-size "
+                         "reference kernel for the HBM byte counters of a profiling run)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "push_traffic.json"),
                     help="HBM traffic of the push kernel measured by rocprofv3 PMC runs (optional)")
     args = ap.parse_args()
@@ -97,6 +101,13 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_probe_mib:
+        nb = args.copy_probe_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = pw.WORKLOADS[args.workload]
     T = args.tile
     t0 = time.perf_counter()
@@ -110,7 +121,7 @@ def main():
         log(f"cpu baseline {cpu['value'] / 1e6:.2f} M push/s over {cpu['seconds']:.1f}s")
 
     sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, T, [(s.qm, s.q, st) for s, st in zip(w.species, states)],
-              j_replicas=args.replicas)
+              j_replicas=args.replicas, j_float=args.j_float)
     del states
     log("initialised")
     for _ in range(args.warmup):
@@ -168,7 +179,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "nx": w.nx, "ny": w.ny, "dx": w.dx, "dt": w.dt,
                    "particles": n, "ppc": sum(s.n_ppc for s in w.species), "tile": T,
-                   "j_replicas": args.replicas or (4 if T < 32 else 2), "sort_every": 1,
+                   "j_accumulation": "fp32-atomic" if args.j_float else "int64-fixed-point",
+                   "j_replicas": args.replicas or ((4 if T < 32 else 2) if args.j_float else 1),
+                   "sort_every": 1,
                    "step": "push+deposit+sort+field_advance"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

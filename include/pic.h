@@ -68,6 +68,16 @@ extern "C" {
 #define PIC_ESORT (-7)    /* internal sort consistency check failed */
 #define PIC_ECOUNT (-8)   /* tile counts do not add up to the particle count */
 
+/*
+ * Current accumulation inside a tile (pic_config.flags).
+ * Default (0): exact int64 fixed point -- each deposit contribution is rounded
+ *   once to 2^-24 of the largest possible contribution (max |q| moving one
+ *   cell), sums are exact, J is bit-reproducible from run to run.
+ * PIC_FLAG_J_FLOAT: FP32 atomic adds into j_replicas LDS copies, summed with
+ *   compensation; J reproducible only to round-off (and slower on gfx950).
+ */
+#define PIC_FLAG_J_FLOAT 1u
+
 typedef struct pic_species {
     double qm;    /* charge-to-mass ratio q/m (electrons: -1) */
     double q;     /* charge density carried by one particle (e.g. -n0 / ppc) */
@@ -80,7 +90,7 @@ typedef struct pic_config {
     int32_t tile;        /* tile edge in cells: 8, 16 or 32 */
     int32_t j_replicas;  /* LDS current replicas per tile: 1, 2 or 4 (0 = default) */
     int32_t n_species;   /* 1 .. PIC_MAX_SPECIES */
-    uint32_t flags;      /* reserved, must be 0 */
+    uint32_t flags;      /* 0 or PIC_FLAG_J_FLOAT */
     pic_species species[PIC_MAX_SPECIES];
 } pic_config;
 

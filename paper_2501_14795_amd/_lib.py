@@ -22,6 +22,8 @@ PIC_ERANGE = -6
 PIC_ESORT = -7
 PIC_ECOUNT = -8
 
+PIC_FLAG_J_FLOAT = 1
+
 PIC_DIAG_ENERGY = 1
 PIC_DIAG_RHO_SNAPSHOT = 2
 PIC_DIAG_CONTINUITY = 4
@@ -90,6 +92,12 @@ def load(path: str = SO_PATH):
         return _L
     if not os.path.exists(path):
         raise ImportError(f"libpic.so not built at {path}; run __graft_entry__.build()")
+    try:
+        # torch ships its own HIP runtime; load it first so libpic binds to the
+        # same libamdhip64 instance instead of a second copy from /opt/rocm
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     P = ctypes.POINTER
     vp = ctypes.c_void_p

@@ -6,21 +6,28 @@
 //   1. stage the tile's E/B halo (cells -1..T on each axis) in LDS, packed so
 //      that the two x-neighbours every bilinear stencil needs come in one
 //      ds_read_b64/b128;
-//   2. each wavefront streams a contiguous quarter of the tile's particle
-//      section (coalesced SoA loads, no block barrier in the loop);
+//   2. the 64-aligned particle chunks covering the tile's section are split
+//      into four contiguous runs, one per wavefront; every chunk is one
+//      coalesced buffer load per SoA array (per-tile buffer base in SGPRs), and
+//      there is no block barrier in the loop;
 //   3. per particle: bilinear interpolation at the staggered points
 //      (Sec. 3.1), Boris push (Eqs. 6-10), move (Eq. 11), and the
 //      Villasenor-Buneman current (Eqs. 13-16) of each of the 1, 2 or 3 pieces
-//      of the motion (Figs. 3.4-3.5) added into one of R LDS current replicas
-//      (replica = lane mod R) with ds_add_f32;
+//      of the motion (Figs. 3.4-3.5), added into the LDS current of the tile:
+//        kJFixed  exact int64 fixed point (ds_add_u64): every contribution is
+//                 rounded once to 2^-24 of the largest possible contribution,
+//                 the sums are exact, so J does not depend on the order of
+//                 the additions -- bit-reproducible from run to run;
+//        kJFloat  FP32 ds_add_f32 into one of R replicas (lane mod R), the
+//                 replicas summed with compensation at the end.  Kept as the
+//                 reference mode: on gfx950 FP32 LDS atomics are several times
+//                 slower than integer ones;
 //   4. particles whose tile changed are appended, in slot order, to the
 //      wavefront's leaver sub-list (ballot + mbcnt), and counted per
 //      direction -- the input of the strict sort (Sec. 4.3, step 1);
-//   5. the replicas are summed and the (T+3)^2 current halo of the tile is
+//   5. the tile's (T+3)^2 current halo is converted to physical units and
 //      written out; k_j_reduce then adds the up-to-four overlapping tile halos
-//      of every node in a fixed order (no global atomics).  The LDS atomics
-//      of step 3 add in an order that varies between runs, so J is
-//      reproducible to FP32 round-off, not bit for bit.
+//      of every node in a fixed order with compensation (no global atomics).
 #include "pic_internal.h"
 
 namespace pic {
@@ -36,44 +43,100 @@ __device__ __forceinline__ int lane_rank(unsigned long long m)
     return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-// Length of the section share streamed by one wavefront: ceil(n/4) rounded up
-// to whole 64-particle chunks.  The sort reads the leaver sub-lists with it.
-__host__ __device__ __forceinline__ int wave_share(int n) { return (((n + 3) >> 2) + 63) & ~63; }
+constexpr int kRsrcWord3 = 0x00020000;   // raw 32-bit buffer access, gfx9 family
+
+struct Stream6 {
+    __amdgpu_buffer_rsrc_t cell, x, y, ux, uy, uz;
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(void *base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, bytes, kRsrcWord3);
+}
+
+__device__ __forceinline__ float ldf(__amdgpu_buffer_rsrc_t r, int off)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+__device__ __forceinline__ void stf(__amdgpu_buffer_rsrc_t r, int off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+}
+
+// LDS current accumulator of one mode.
+template <int JM>
+struct JAcc;
+
+template <>
+struct JAcc<kJFixed> {
+    using T = unsigned long long;
+    __device__ static __forceinline__ void add(T *p, float v)
+    {
+        const long long q = (long long)(int)rintf(v);
+        atomicAdd(p, (T)q);
+    }
+    __device__ static __forceinline__ float value(const T *p, int replicas, int stride, float unit)
+    {
+        long long s = 0;
+        for (int r = 0; r < replicas; ++r) s += (long long)p[r * stride];
+        return (float)((double)s * (double)unit);
+    }
+};
+
+template <>
+struct JAcc<kJFloat> {
+    using T = float;
+    __device__ static __forceinline__ void add(T *p, float v) { atomicAdd(p, v); }
+    __device__ static __forceinline__ float value(const T *p, int replicas, int stride, float unit)
+    {
+        // compensated (TwoSum) sum of the replicas
+        float s = 0.0f, c = 0.0f;
+        for (int r = 0; r < replicas; ++r) {
+            const float v = p[r * stride];
+            const float t = s + v;
+            const float bp = t - s;
+            c += (s - (t - bp)) + (v - bp);
+            s = t;
+        }
+        return (s + c) * unit;
+    }
+};
 
 // Current of one piece of the motion inside cell (cx, cy) (tile-relative,
 // -1..T), from (xa, ya) to (xb, yb) in that cell's frame, lasting `frac` of
-// the step.  Jx/Jy are the Villasenor-Buneman face fluxes times dx/dt, dy/dt;
-// Jz is q vz frac times the time-averaged bilinear weight of each corner,
-// written as w_mid + or - dxk dyk / 12.
-template <int NJ>
-__device__ __forceinline__ void deposit_piece(float *sj, int cx, int cy, float xa, float ya,
-                                              float xb, float yb, float frac, float jxs,
-                                              float jys, float qvz)
+// the step, in accumulator units (fq = particle charge in those units).
+// Jx/Jy: the Villasenor-Buneman face fluxes; Jz: fq vz frac times the exact
+// time average of each corner's bilinear weight, w_mid +- dxk dyk / 12.
+template <int NJ, int JM>
+__device__ __forceinline__ void deposit_piece(typename JAcc<JM>::T *sj, int cx, int cy, float xa, float ya,
+                                              float xb, float yb, float frac, float fq, float fqvz)
 {
     constexpr int P = NJ * NJ;
+    using A = JAcc<JM>;
     const float dxk = xb - xa, dyk = yb - ya;
     const float xm = 0.5f * (xa + xb), ym = 0.5f * (ya + yb);
-    const float ax = jxs * dxk, ay = jys * dyk;
+    const float ax = fq * dxk, ay = fq * dyk, az = fqvz * frac;
     const float c = dxk * dyk * (1.0f / 12.0f);
-    const float jz = qvz * frac;
     const float xm1 = 1.0f - xm, ym1 = 1.0f - ym;
     const int b = (cy + 1) * NJ + (cx + 1);
-    atomicAdd(&sj[b], ax * ym1);
-    atomicAdd(&sj[b + NJ], ax * ym);
-    atomicAdd(&sj[P + b], ay * xm1);
-    atomicAdd(&sj[P + b + 1], ay * xm);
-    atomicAdd(&sj[2 * P + b], jz * fmaf(xm1, ym1, c));
-    atomicAdd(&sj[2 * P + b + 1], jz * fmaf(xm, ym1, -c));
-    atomicAdd(&sj[2 * P + b + NJ], jz * fmaf(xm1, ym, -c));
-    atomicAdd(&sj[2 * P + b + NJ + 1], jz * fmaf(xm, ym, c));
+    A::add(&sj[b], ax * ym1);
+    A::add(&sj[b + NJ], ax * ym);
+    A::add(&sj[P + b], ay * xm1);
+    A::add(&sj[P + b + 1], ay * xm);
+    A::add(&sj[2 * P + b], az * fmaf(xm1, ym1, c));
+    A::add(&sj[2 * P + b + 1], az * fmaf(xm, ym1, -c));
+    A::add(&sj[2 * P + b + NJ], az * fmaf(xm1, ym, -c));
+    A::add(&sj[2 * P + b + NJ + 1], az * fmaf(xm, ym, c));
 }
 
-template <int T, int R>
+template <int T, int R, int JM>
 __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
 {
     constexpr int NE = T + 2;   // staged E/B cells per axis: relative -1..T
     constexpr int NJ = T + 3;   // current halo nodes per axis: relative -1..T+1
     constexpr int JP = NJ * NJ;
+    using Acc = typename JAcc<JM>::T;
 
     // packed E/B: entry [r][c] holds the values at relative cells c-1 and c
     // (x-neighbours) of row r-1
@@ -81,7 +144,7 @@ __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
     __shared__ float4 s_eybx[NE * NE];   // Ey, Bx likewise
     __shared__ float2 s_ez[NE * NE];
     __shared__ float2 s_bz[NE * NE];
-    __shared__ float s_j[R][3 * JP];
+    __shared__ Acc s_j[R][3 * JP];
     __shared__ int s_dir[kMaxSpecies][9];
     __shared__ int s_wl[kMaxSpecies][kWaves];
 
@@ -103,173 +166,186 @@ __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
         s_ez[e] = make_float2(f[2 * plane + i0], f[2 * plane + i1]);
         s_bz[e] = make_float2(f[5 * plane + i0], f[5 * plane + i1]);
     }
-    for (int e = tid; e < R * 3 * JP; e += kBlock) (&s_j[0][0])[e] = 0.0f;
+    for (int e = tid; e < R * 3 * JP; e += kBlock) (&s_j[0][0])[e] = Acc(0);
     if (tid < kMaxSpecies * 9) (&s_dir[0][0])[tid] = 0;
     __syncthreads();
 
-    float *sj = s_j[lane % R];
+    Acc *sj = s_j[R > 1 ? lane % R : 0];
     const bool tx_wrap = a.ntx > 1, ty_wrap = a.nty > 1;
 
     for (int s = 0; s < a.n_species; ++s) {
         const SpeciesDev sp = a.sp[s];
-        const int begin = sp.off[tile];
-        const int n = sp.off[tile + 1] - begin;
-        const int share = wave_share(n);
-        const int lo = wave * share;
-        const int hi = min(lo + share, n);
+        const int begin = sp.off[tile], end = sp.off[tile + 1];
+        int lo, hi;
+        wave_range(begin, end, wave, lo, hi);
         int nleav = 0;   // wavefront-uniform
-        for (int kb = lo; kb < hi; kb += 64) {
-            const int k = kb + lane;
-            bool leaver = false;
-            int dir = 4;
-            if (k < hi) {
-                const int64_t i = (int64_t)begin + k;
-                const int cell = sp.cell[i];
-                float x = sp.x[i], y = sp.y[i];
-                float ux = sp.ux[i], uy = sp.uy[i], uz = sp.uz[i];
-                int lx = (cell & 0xffff) - gx0, ly = (cell >> 16) - gy0;
-                if ((unsigned)lx >= (unsigned)T || (unsigned)ly >= (unsigned)T) {
-                    atomicOr(a.err, kErrOrder);
-                    lx = min(max(lx, 0), T - 1);
-                    ly = min(max(ly, 0), T - 1);
-                }
+        if (lo < hi) {
+            // buffer views starting at the first 64-aligned slot of the section
+            const int base = (begin >> 6) << 6;
+            const int bytes = (end - base) * 4;
+            Stream6 st;
+            st.cell = rsrc(sp.cell + base, bytes);
+            st.x = rsrc(sp.x + base, bytes);
+            st.y = rsrc(sp.y + base, bytes);
+            st.ux = rsrc(sp.ux + base, bytes);
+            st.uy = rsrc(sp.uy + base, bytes);
+            st.uz = rsrc(sp.uz + base, bytes);
+            const float h = sp.h, fq = sp.fq;
+            for (int cb = (lo >> 6) << 6; cb < hi; cb += 64) {
+                const int i = cb + lane;
+                const int off = (i - base) * 4;
+                // loads past the section end return 0; lanes before it read the
+                // previous tile's particles and discard them
+                const int cell = (int)__builtin_amdgcn_raw_buffer_load_b32(st.cell, off, 0, 0);
+                const float x = ldf(st.x, off), y = ldf(st.y, off);
+                float ux = ldf(st.ux, off), uy = ldf(st.uy, off), uz = ldf(st.uz, off);
+                bool leaver = false;
+                int dir = 4;
+                if (i >= lo && i < hi) {
+                    int lx = (cell & 0xffff) - gx0, ly = (cell >> 16) - gy0;
+                    if ((unsigned)lx >= (unsigned)T || (unsigned)ly >= (unsigned)T) {
+                        atomicOr(a.err, kErrOrder);
+                        lx = min(max(lx, 0), T - 1);
+                        ly = min(max(ly, 0), T - 1);
+                    }
 
-                // ---- interpolation (bilinear at each component's staggered point)
-                const bool xh = x >= 0.5f, yh = y >= 0.5f;
-                const float wxh = xh ? x - 0.5f : x + 0.5f;   // weight for (i+1/2) points
-                const float wyh = yh ? y - 0.5f : y + 0.5f;
-                const int ch = lx + (xh ? 1 : 0);             // packed column of the half stencil
-                const int rh = ly + (yh ? 1 : 0);
-                const int c0 = lx + 1, r0 = ly + 1;
-                const float4 p0 = s_exby[r0 * NE + ch], p1 = s_exby[(r0 + 1) * NE + ch];
-                const float4 q0 = s_eybx[rh * NE + c0], q1 = s_eybx[(rh + 1) * NE + c0];
-                const float2 z0 = s_ez[r0 * NE + c0], z1 = s_ez[(r0 + 1) * NE + c0];
-                const float2 b0 = s_bz[rh * NE + ch], b1 = s_bz[(rh + 1) * NE + ch];
-                const float Ex = lerpf(lerpf(p0.x, p0.z, wxh), lerpf(p1.x, p1.z, wxh), y);
-                const float By = lerpf(lerpf(p0.y, p0.w, wxh), lerpf(p1.y, p1.w, wxh), y);
-                const float Ey = lerpf(lerpf(q0.x, q0.z, x), lerpf(q1.x, q1.z, x), wyh);
-                const float Bx = lerpf(lerpf(q0.y, q0.w, x), lerpf(q1.y, q1.w, x), wyh);
-                const float Ez = lerpf(lerpf(z0.x, z0.y, x), lerpf(z1.x, z1.y, x), y);
-                const float Bz = lerpf(lerpf(b0.x, b0.y, wxh), lerpf(b1.x, b1.y, wxh), wyh);
+                    // ---- interpolation (bilinear at each component's staggered point)
+                    const bool xh = x >= 0.5f, yh = y >= 0.5f;
+                    const float wxh = xh ? x - 0.5f : x + 0.5f;   // weight for (i+1/2) points
+                    const float wyh = yh ? y - 0.5f : y + 0.5f;
+                    const int ch = lx + (xh ? 1 : 0);             // packed column of the half stencil
+                    const int rh = ly + (yh ? 1 : 0);
+                    const int c0 = lx + 1, r0 = ly + 1;
+                    const float4 p0 = s_exby[r0 * NE + ch], p1 = s_exby[(r0 + 1) * NE + ch];
+                    const float4 q0 = s_eybx[rh * NE + c0], q1 = s_eybx[(rh + 1) * NE + c0];
+                    const float2 z0 = s_ez[r0 * NE + c0], z1 = s_ez[(r0 + 1) * NE + c0];
+                    const float2 b0 = s_bz[rh * NE + ch], b1 = s_bz[(rh + 1) * NE + ch];
+                    const float Ex = lerpf(lerpf(p0.x, p0.z, wxh), lerpf(p1.x, p1.z, wxh), y);
+                    const float By = lerpf(lerpf(p0.y, p0.w, wxh), lerpf(p1.y, p1.w, wxh), y);
+                    const float Ey = lerpf(lerpf(q0.x, q0.z, x), lerpf(q1.x, q1.z, x), wyh);
+                    const float Bx = lerpf(lerpf(q0.y, q0.w, x), lerpf(q1.y, q1.w, x), wyh);
+                    const float Ez = lerpf(lerpf(z0.x, z0.y, x), lerpf(z1.x, z1.y, x), y);
+                    const float Bz = lerpf(lerpf(b0.x, b0.y, wxh), lerpf(b1.x, b1.y, wxh), wyh);
 
-                // ---- Boris push (Eqs. 6-10)
-                const float h = sp.h;
-                const float mx = fmaf(h, Ex, ux), my = fmaf(h, Ey, uy), mz = fmaf(h, Ez, uz);
-                const float gi = rsqrtf(fmaf(mx, mx, fmaf(my, my, fmaf(mz, mz, 1.0f))));
-                const float hg = h * gi;
-                const float tx_ = hg * Bx, ty_ = hg * By, tz_ = hg * Bz;
-                const float px = fmaf(my, tz_, fmaf(-mz, ty_, mx));
-                const float py = fmaf(mz, tx_, fmaf(-mx, tz_, my));
-                const float pz = fmaf(mx, ty_, fmaf(-my, tx_, mz));
-                const float f2 = __fdividef(2.0f, fmaf(tx_, tx_, fmaf(ty_, ty_, fmaf(tz_, tz_, 1.0f))));
-                const float sx_ = f2 * tx_, sy_ = f2 * ty_, sz_ = f2 * tz_;
-                ux = fmaf(h, Ex, fmaf(py, sz_, fmaf(-pz, sy_, mx)));
-                uy = fmaf(h, Ey, fmaf(pz, sx_, fmaf(-px, sz_, my)));
-                uz = fmaf(h, Ez, fmaf(px, sy_, fmaf(-py, sx_, mz)));
+                    // ---- Boris push (Eqs. 6-10); 1 + |u|^2 >= 1, so the hardware
+                    // reciprocal square root needs no denormal care
+                    const float mx = fmaf(h, Ex, ux), my = fmaf(h, Ey, uy), mz = fmaf(h, Ez, uz);
+                    const float gi = __builtin_amdgcn_rsqf(fmaf(mx, mx, fmaf(my, my, fmaf(mz, mz, 1.0f))));
+                    const float hg = h * gi;
+                    const float tx_ = hg * Bx, ty_ = hg * By, tz_ = hg * Bz;
+                    const float px = fmaf(my, tz_, fmaf(-mz, ty_, mx));
+                    const float py = fmaf(mz, tx_, fmaf(-mx, tz_, my));
+                    const float pz = fmaf(mx, ty_, fmaf(-my, tx_, mz));
+                    const float f2 =
+                        2.0f * __builtin_amdgcn_rcpf(fmaf(tx_, tx_, fmaf(ty_, ty_, fmaf(tz_, tz_, 1.0f))));
+                    const float sx_ = f2 * tx_, sy_ = f2 * ty_, sz_ = f2 * tz_;
+                    ux = fmaf(h, Ex, fmaf(py, sz_, fmaf(-pz, sy_, mx)));
+                    uy = fmaf(h, Ey, fmaf(pz, sx_, fmaf(-px, sz_, my)));
+                    uz = fmaf(h, Ez, fmaf(px, sy_, fmaf(-py, sx_, mz)));
 
-                // ---- move (Eq. 11), in cells
-                const float ig = rsqrtf(fmaf(ux, ux, fmaf(uy, uy, fmaf(uz, uz, 1.0f))));
-                float dX = ux * ig * a.cx, dY = uy * ig * a.cy;
-                if (!(fabsf(dX) < 1.0f && fabsf(dY) < 1.0f)) {
-                    atomicOr(a.err, kErrRange);
-                    dX = 0.0f;
-                    dY = 0.0f;
-                }
-                const float x1 = x + dX, y1 = y + dY;
-                const int sxn = x1 >= 1.0f ? 1 : (x1 < 0.0f ? -1 : 0);
-                const int syn = y1 >= 1.0f ? 1 : (y1 < 0.0f ? -1 : 0);
+                    // ---- move (Eq. 11), in cells
+                    const float ig = __builtin_amdgcn_rsqf(fmaf(ux, ux, fmaf(uy, uy, fmaf(uz, uz, 1.0f))));
+                    float dX = ux * ig * a.cx, dY = uy * ig * a.cy;
+                    if (!(fabsf(dX) < 1.0f && fabsf(dY) < 1.0f)) {
+                        atomicOr(a.err, kErrRange);
+                        dX = 0.0f;
+                        dY = 0.0f;
+                    }
+                    const float x1 = x + dX, y1 = y + dY;
+                    const int sxn = x1 >= 1.0f ? 1 : (x1 < 0.0f ? -1 : 0);
+                    const int syn = y1 >= 1.0f ? 1 : (y1 < 0.0f ? -1 : 0);
 
-                // ---- Villasenor-Buneman deposit of the 1, 2 or 3 pieces
-                {
-                    const float ex = sxn > 0 ? 1.0f : 0.0f;   // x face crossed (start-cell frame)
-                    const float ey = syn > 0 ? 1.0f : 0.0f;
-                    const float tcx = sxn ? clamp01(__fdividef(ex - x, dX)) : 1.0f;
-                    const float tcy = syn ? clamp01(__fdividef(ey - y, dY)) : 1.0f;
-                    const bool xfirst = sxn != 0 && (syn == 0 || tcx <= tcy);
-                    const float t1 = xfirst ? tcx : tcy;
-                    const float t2 = xfirst ? tcy : tcx;
-                    const int nseg = 1 + (sxn != 0) + (syn != 0);
-                    const float qvz = sp.q * uz * ig;
-                    float ax_ = x, ay_ = y, ta = 0.0f;
-                    int ox = 0, oy = 0;
+                    // ---- Villasenor-Buneman deposit of the 1, 2 or 3 pieces
+                    {
+                        const float ex = sxn > 0 ? 1.0f : 0.0f;   // x face crossed (start-cell frame)
+                        const float ey = syn > 0 ? 1.0f : 0.0f;
+                        const float tcx = sxn ? clamp01((ex - x) * __builtin_amdgcn_rcpf(dX)) : 1.0f;
+                        const float tcy = syn ? clamp01((ey - y) * __builtin_amdgcn_rcpf(dY)) : 1.0f;
+                        const bool xfirst = sxn != 0 && (syn == 0 || tcx <= tcy);
+                        const float t1 = xfirst ? tcx : tcy;
+                        const float t2 = xfirst ? tcy : tcx;
+                        const int nseg = 1 + (sxn != 0) + (syn != 0);
+                        const float fqvz = fq * uz * ig;
+                        float ax_ = x, ay_ = y, ta = 0.0f;
+                        int ox = 0, oy = 0;
 #pragma unroll
-                    for (int p = 0; p < 3; ++p) {
-                        if (p < nseg) {
-                            float tb, bx, by;
-                            int nox = ox, noy = oy;
-                            if (p == nseg - 1) {
-                                tb = 1.0f;
-                                bx = x1;
-                                by = y1;
-                            } else {
-                                const bool xev = (p == 0) ? xfirst : !xfirst;
-                                tb = (p == 0) ? t1 : t2;
-                                if (xev) {
-                                    bx = ex;
-                                    by = fmaf(tb, dY, y);
-                                    nox = ox + sxn;
+                        for (int p = 0; p < 3; ++p) {
+                            if (p < nseg) {
+                                float tb, bx, by;
+                                int nox = ox, noy = oy;
+                                if (p == nseg - 1) {
+                                    tb = 1.0f;
+                                    bx = x1;
+                                    by = y1;
                                 } else {
-                                    bx = fmaf(tb, dX, x);
-                                    by = ey;
-                                    noy = oy + syn;
+                                    const bool xev = (p == 0) ? xfirst : !xfirst;
+                                    tb = (p == 0) ? t1 : t2;
+                                    if (xev) {
+                                        bx = ex;
+                                        by = fmaf(tb, dY, y);
+                                        nox = ox + sxn;
+                                    } else {
+                                        bx = fmaf(tb, dX, x);
+                                        by = ey;
+                                        noy = oy + syn;
+                                    }
                                 }
+                                deposit_piece<NJ, JM>(sj, lx + ox, ly + oy, clamp01(ax_ - ox), clamp01(ay_ - oy),
+                                                      clamp01(bx - ox), clamp01(by - oy), tb - ta, fq, fqvz);
+                                ax_ = bx;
+                                ay_ = by;
+                                ta = tb;
+                                ox = nox;
+                                oy = noy;
                             }
-                            deposit_piece<NJ>(sj, lx + ox, ly + oy, clamp01(ax_ - ox),
-                                              clamp01(ay_ - oy), clamp01(bx - ox),
-                                              clamp01(by - oy), tb - ta, sp.jx, sp.jy, qvz);
-                            ax_ = bx;
-                            ay_ = by;
-                            ta = tb;
-                            ox = nox;
-                            oy = noy;
                         }
                     }
-                }
 
-                // ---- new position: offset back into [0,1), cell index, periodic wrap
-                int nlx = lx, nly = ly;
-                float xn = x1, yn = y1;
-                if (sxn > 0) {
-                    xn = x1 - 1.0f;
-                    nlx += 1;
-                } else if (sxn < 0) {
-                    xn = x1 + 1.0f;
-                    nlx -= 1;
-                    if (xn >= 1.0f) {   // rounded onto the face: it is x = 0 of the old cell
-                        xn = 0.0f;
+                    // ---- new position: offset back into [0,1), cell index, periodic wrap
+                    int nlx = lx, nly = ly;
+                    float xn = x1, yn = y1;
+                    if (sxn > 0) {
+                        xn = x1 - 1.0f;
                         nlx += 1;
+                    } else if (sxn < 0) {
+                        xn = x1 + 1.0f;
+                        nlx -= 1;
+                        if (xn >= 1.0f) {   // rounded onto the face: it is x = 0 of the old cell
+                            xn = 0.0f;
+                            nlx += 1;
+                        }
                     }
-                }
-                if (syn > 0) {
-                    yn = y1 - 1.0f;
-                    nly += 1;
-                } else if (syn < 0) {
-                    yn = y1 + 1.0f;
-                    nly -= 1;
-                    if (yn >= 1.0f) {
-                        yn = 0.0f;
+                    if (syn > 0) {
+                        yn = y1 - 1.0f;
                         nly += 1;
+                    } else if (syn < 0) {
+                        yn = y1 + 1.0f;
+                        nly -= 1;
+                        if (yn >= 1.0f) {
+                            yn = 0.0f;
+                            nly += 1;
+                        }
                     }
-                }
-                const int gx = wrapi(gx0 + nlx, a.nx), gy = wrapi(gy0 + nly, a.ny);
-                sp.cell[i] = gx | (gy << 16);
-                sp.x[i] = xn;
-                sp.y[i] = yn;
-                sp.ux[i] = ux;
-                sp.uy[i] = uy;
-                sp.uz[i] = uz;
+                    const int gx = wrapi(gx0 + nlx, a.nx), gy = wrapi(gy0 + nly, a.ny);
+                    __builtin_amdgcn_raw_buffer_store_b32((unsigned)(gx | (gy << 16)), st.cell, off, 0, 0);
+                    stf(st.x, off, xn);
+                    stf(st.y, off, yn);
+                    stf(st.ux, off, ux);
+                    stf(st.uy, off, uy);
+                    stf(st.uz, off, uz);
 
-                const int dtx = tx_wrap ? (nlx < 0 ? -1 : (nlx >= T ? 1 : 0)) : 0;
-                const int dty = ty_wrap ? (nly < 0 ? -1 : (nly >= T ? 1 : 0)) : 0;
-                dir = (dty + 1) * 3 + (dtx + 1);
-                leaver = dir != 4;
+                    const int dtx = tx_wrap ? (nlx < 0 ? -1 : (nlx >= T ? 1 : 0)) : 0;
+                    const int dty = ty_wrap ? (nly < 0 ? -1 : (nly >= T ? 1 : 0)) : 0;
+                    dir = (dty + 1) * 3 + (dtx + 1);
+                    leaver = dir != 4;
+                }
+                const unsigned long long m = __ballot(leaver);
+                if (leaver) {
+                    sp.leav[(int64_t)lo + nleav + lane_rank(m)] = ((uint32_t)(i - begin) << 4) | (uint32_t)dir;
+                    atomicAdd(&s_dir[s][dir], 1);
+                }
+                nleav += __popcll(m);
             }
-            const unsigned long long m = __ballot(leaver);
-            if (leaver) {
-                sp.leav[(int64_t)begin + lo + nleav + lane_rank(m)] = ((uint32_t)k << 4) | (uint32_t)dir;
-                atomicAdd(&s_dir[s][dir], 1);
-            }
-            nleav += __popcll(m);
         }
         if (lane == 0) s_wl[s][wave] = nleav;
     }
@@ -288,18 +364,17 @@ __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
         a.sp[s].cnt[(int64_t)tile * kCntStride + k] = v;
     }
 
-    // sum the replicas and write the tile's current halo
+    // the tile's current halo in physical units
     float *out = a.jtile + (int64_t)tile * 3 * JP;
     for (int e = tid; e < 3 * JP; e += kBlock) {
-        float v = s_j[0][e];
-#pragma unroll
-        for (int r = 1; r < R; ++r) v += s_j[r][e];
-        out[e] = v;
+        const int comp = e / JP;
+        out[e] = JAcc<JM>::value(&s_j[0][e], R, 3 * JP, a.ju[comp]);
     }
 }
 
 // J[c][gy][gx] = sum over the tiles whose halo (relative -1..T+1) covers the
-// node, in fixed (ty, tx) order -- the periodic fold of update_gc_add.
+// node, in fixed (ty, tx) order with compensation -- the periodic fold of
+// update_gc_add.
 template <int T>
 __global__ void __launch_bounds__(256) k_j_reduce(const float *__restrict__ jtile, float *__restrict__ J,
                                                   int nx, int ny, int ntx, int nty)
@@ -310,7 +385,7 @@ __global__ void __launch_bounds__(256) k_j_reduce(const float *__restrict__ jtil
     const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
     if (gx >= nx || gy >= ny) return;
     const int bx = gx / T, by = gy / T;
-    float acc[3] = {0.0f, 0.0f, 0.0f};
+    float sum[3] = {0.0f, 0.0f, 0.0f}, cmp[3] = {0.0f, 0.0f, 0.0f};
     for (int ky = -1; ky <= 1; ++ky) {
         const int ry = gy - (by + ky) * T;
         if (ry < -1 || ry > T + 1) continue;
@@ -320,40 +395,55 @@ __global__ void __launch_bounds__(256) k_j_reduce(const float *__restrict__ jtil
             if (rx < -1 || rx > T + 1) continue;
             const int tx = wrapi(bx + kx, ntx);
             const float *src = jtile + (int64_t)(ty * ntx + tx) * 3 * JP + (ry + 1) * NJ + (rx + 1);
-            acc[0] += src[0];
-            acc[1] += src[JP];
-            acc[2] += src[2 * JP];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float v = src[c * JP];
+                const float t = sum[c] + v;
+                const float bp = t - sum[c];
+                cmp[c] += (sum[c] - (t - bp)) + (v - bp);
+                sum[c] = t;
+            }
         }
     }
     const int64_t plane = (int64_t)nx * ny;
     const int64_t k = (int64_t)gy * nx + gx;
-    J[k] = acc[0];
-    J[plane + k] = acc[1];
-    J[2 * plane + k] = acc[2];
+    J[k] = sum[0] + cmp[0];
+    J[plane + k] = sum[1] + cmp[1];
+    J[2 * plane + k] = sum[2] + cmp[2];
 }
 
-template <int T, int R>
+template <int T, int R, int JM>
 static void launch_pd(const PushArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_push_deposit<T, R>), dim3(n_tiles), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_push_deposit<T, R, JM>), dim3(n_tiles), dim3(kBlock), 0, s, a);
 }
 
-template <int T>
+template <int T, int JM>
 static void launch_pd_r(int replicas, const PushArgs &a, int n_tiles, hipStream_t s)
 {
     switch (replicas) {
-    case 1: launch_pd<T, 1>(a, n_tiles, s); break;
-    case 2: launch_pd<T, 2>(a, n_tiles, s); break;
-    default: launch_pd<T, 4>(a, n_tiles, s); break;
+    case 1: launch_pd<T, 1, JM>(a, n_tiles, s); break;
+    case 2: launch_pd<T, 2, JM>(a, n_tiles, s); break;
+    default:
+        // configurations over the LDS budget are rejected by pic_query/pic_init
+        if constexpr (push_lds_bytes(T, 4, JM) <= kLdsBytes) launch_pd<T, 4, JM>(a, n_tiles, s);
+        break;
     }
 }
 
-void launch_push_deposit(int tile, int replicas, const PushArgs &a, int n_tiles, hipStream_t s)
+template <int T>
+static void launch_pd_j(int replicas, int jmode, const PushArgs &a, int n_tiles, hipStream_t s)
+{
+    if (jmode == kJFloat) launch_pd_r<T, kJFloat>(replicas, a, n_tiles, s);
+    else launch_pd_r<T, kJFixed>(replicas, a, n_tiles, s);
+}
+
+void launch_push_deposit(int tile, int replicas, int jmode, const PushArgs &a, int n_tiles, hipStream_t s)
 {
     switch (tile) {
-    case 8: launch_pd_r<8>(replicas, a, n_tiles, s); break;
-    case 16: launch_pd_r<16>(replicas, a, n_tiles, s); break;
-    default: launch_pd_r<32>(replicas, a, n_tiles, s); break;
+    case 8: launch_pd_j<8>(replicas, jmode, a, n_tiles, s); break;
+    case 16: launch_pd_j<16>(replicas, jmode, a, n_tiles, s); break;
+    default: launch_pd_j<32>(replicas, jmode, a, n_tiles, s); break;
     }
 }
 

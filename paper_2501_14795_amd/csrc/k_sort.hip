@@ -29,8 +29,6 @@ __device__ __forceinline__ int lane_rank_s(unsigned long long m)
     return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
-__host__ __device__ __forceinline__ int wave_share_s(int n) { return (((n + 3) >> 2) + 63) & ~63; }
-
 // Exclusive scan of one int per thread over a 1024-thread block; returns the
 // thread's prefix and writes the block total to *total.
 __device__ int block_exclusive_scan_1024(int v, int *total)
@@ -123,15 +121,16 @@ __global__ void __launch_bounds__(kBlock) k_sort_plan(SortArgs a, int n_tiles)
     {
         const int lA = max(A, oA), lB = min(B, oB);
         if (lA < lB) {
-            const int share = wave_share_s(oB - oA);
             for (int w = 0; w < kWaves; ++w) {
                 const int cw = sp.cnt[(int64_t)t * kCntStride + kCntSub + w];
-                const int64_t base = (int64_t)oA + w * share;
+                int wlo, whi;
+                wave_range(oA, oB, w, wlo, whi);
+                const int64_t base = wlo;
                 for (int b = 0; b < cw; b += 64) {
                     const int k = b + lane;
                     bool p = false;
                     int slot = 0;
-                    if (k < cw && w * share + k < oB - oA) {
+                    if (k < cw && k < whi - wlo) {
                         slot = oA + (int)(sp.leav[base + k] >> 4);
                         p = slot >= lA && slot < lB;
                     }
@@ -196,16 +195,17 @@ __global__ void __launch_bounds__(kBlock) k_sort_plan(SortArgs a, int n_tiles)
             }
         } else {
             const int so = sp.off[s], ns = sp.off[s + 1] - so;
-            const int share = wave_share_s(ns);
             const int sx = s % ntx, sy = s / ntx;
             for (int w = 0; w < kWaves; ++w) {
                 const int cw = sp.cnt[(int64_t)s * kCntStride + kCntSub + w];
-                const int64_t base = (int64_t)so + w * share;
+                int wlo, whi;
+                wave_range(so, so + ns, w, wlo, whi);
+                const int64_t base = wlo;
                 for (int b = 0; b < cw; b += 64) {
                     const int k = b + lane;
                     bool p = false;
                     int slot = 0;
-                    if (k < cw && w * share + k < ns) {
+                    if (k < cw && k < whi - wlo) {
                         const uint32_t e = sp.leav[base + k];
                         const int d = (int)(e & 15u), loc = (int)(e >> 4);
                         const int dest = wrap_s(sy + d / 3 - 1, nty) * ntx + wrap_s(sx + d % 3 - 1, ntx);

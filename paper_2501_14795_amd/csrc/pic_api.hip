@@ -25,18 +25,28 @@ struct Layout {
     size_t total = 0;
 };
 
-int default_replicas(int tile) { return tile >= 32 ? 2 : 4; }
+int j_mode(const pic_config *c) { return (c->flags & PIC_FLAG_J_FLOAT) ? kJFloat : kJFixed; }
+
+int default_replicas(const pic_config *c)
+{
+    if (j_mode(c) == kJFixed) return 1;   // integer LDS atomics need no replicas
+    return c->tile >= 32 ? 2 : 4;
+}
 
 int validate(const pic_config *c)
 {
     if (!c) return PIC_EINVAL;
-    if (c->flags != 0) return PIC_EINVAL;
+    if (c->flags & ~(uint32_t)PIC_FLAG_J_FLOAT) return PIC_EINVAL;
     if (c->tile != 8 && c->tile != 16 && c->tile != 32) return PIC_ETILE;
     if (c->nx < c->tile || c->ny < c->tile || c->nx > 32767 || c->ny > 32767) return PIC_EINVAL;
     if (c->nx % c->tile || c->ny % c->tile) return PIC_ETILE;
     if (c->j_replicas != 0 && c->j_replicas != 1 && c->j_replicas != 2 && c->j_replicas != 4)
         return PIC_EINVAL;
     if (c->n_species < 1 || c->n_species > kMaxSpecies) return PIC_EINVAL;
+    {
+        const int r = c->j_replicas ? c->j_replicas : default_replicas(c);
+        if (push_lds_bytes(c->tile, r, j_mode(c)) > kLdsBytes) return PIC_EINVAL;
+    }
     if (!(c->dx > 0) || !(c->dy > 0) || !(c->dt > 0)) return PIC_EINVAL;
     // Courant-Levy condition, Eq. (1), with c = 1
     if (!(c->dt < 1.0 / sqrt(1.0 / (c->dx * c->dx) + 1.0 / (c->dy * c->dy)))) return PIC_ECFL;
@@ -239,7 +249,7 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
     S->ntx = cfg->nx / cfg->tile;
     S->nty = cfg->ny / cfg->tile;
     S->n_tiles = S->ntx * S->nty;
-    S->replicas = cfg->j_replicas ? cfg->j_replicas : default_replicas(cfg->tile);
+    S->replicas = cfg->j_replicas ? cfg->j_replicas : default_replicas(cfg);
     char *w = (char *)bufs->work;
     S->work = w;
     S->err = (int *)(w + L.err);
@@ -297,6 +307,16 @@ int pic_push_deposit(pic_sim *S, hipStream_t stream)
     a.nty = S->nty;
     a.cx = (float)(c.dt / c.dx);
     a.cy = (float)(c.dt / c.dy);
+    // accumulator units: the largest particle charge moving one cell (Jx, Jy)
+    // or at the speed of light (Jz) is 1 (x 2^24 in fixed point)
+    double qmax = 0.0;
+    for (int s = 0; s < c.n_species; ++s) qmax = std::max(qmax, fabs(c.species[s].q));
+    if (qmax == 0.0) qmax = 1.0;
+    const int jm = j_mode(&c);
+    const double scale = jm == kJFixed ? (double)kFixedScale : 1.0;
+    a.ju[0] = (float)(qmax * c.dx / c.dt / scale);
+    a.ju[1] = (float)(qmax * c.dy / c.dt / scale);
+    a.ju[2] = (float)(qmax / scale);
     a.n_species = c.n_species;
     for (int s = 0; s < c.n_species; ++s) {
         const pic_particles &p = S->buf.sp[s];
@@ -312,13 +332,11 @@ int pic_push_deposit(pic_sim *S, hipStream_t stream)
         d.leav = S->sp[s].leav;
         d.n = (int32_t)c.species[s].n;
         d.h = (float)(0.5 * c.species[s].qm * c.dt);
-        d.jx = (float)(c.species[s].q * c.dx / c.dt);
-        d.jy = (float)(c.species[s].q * c.dy / c.dt);
-        d.q = (float)c.species[s].q;
+        d.fq = (float)(scale * c.species[s].q / qmax);
     }
     {
         Timed t(S, PIC_KERNEL_PUSH, stream);
-        launch_push_deposit(S->tile, S->replicas, a, S->n_tiles, stream);
+        launch_push_deposit(S->tile, S->replicas, jm, a, S->n_tiles, stream);
     }
     {
         Timed t(S, PIC_KERNEL_JREDUCE, stream);

@@ -30,6 +30,27 @@ enum : int {
     kErrCount = 8,   // tile counts do not sum to n
 };
 
+// Current accumulation modes of the push kernel.
+enum : int {
+    kJFixed = 0,   // exact int64 fixed point in LDS (default)
+    kJFloat = 1,   // FP32 LDS atomics, compensated replica sum
+};
+
+// Fixed-point resolution: one current contribution of the largest possible
+// magnitude (the particle charge of the largest species times a full cell of
+// motion) is 2^24 units, so a contribution converts to int32 exactly enough
+// (2^-25 relative rounding) and int64 sums cannot overflow.
+constexpr float kFixedScale = 16777216.0f;
+
+constexpr int kLdsBytes = 160 * 1024;   // LDS of one gfx950 compute unit
+
+// Static LDS of the push kernel for tile T, R current replicas, mode JM.
+constexpr int push_lds_bytes(int T, int R, int JM)
+{
+    return (T + 2) * (T + 2) * 48 + R * 3 * (T + 3) * (T + 3) * (JM == kJFixed ? 8 : 4) +
+           kMaxSpecies * (9 + kWaves) * 4;
+}
+
 struct SpeciesDev {
     int32_t *cell;
     float *x, *y, *ux, *uy, *uz;
@@ -38,20 +59,37 @@ struct SpeciesDev {
     uint32_t *leav;       // [n]: leaver sub-lists, (slot - off[t]) << 4 | direction
     int32_t n;
     float h;              // (q/m) dt / 2
-    float jx;             // q dx / dt
-    float jy;             // q dy / dt
-    float q;
+    float fq;             // charge in accumulator units: q / max|q| (x kFixedScale in fixed mode)
 };
 
 struct PushArgs {
     const float *fld;     // Ex Ey Ez Bx By Bz planes
-    float *jtile;         // [n_tiles][3][(T+3)^2]
+    float *jtile;         // [n_tiles][3][(T+3)^2], physical current of each tile halo
     int *err;
     int nx, ny, ntx, nty;
     float cx, cy;         // dt/dx, dt/dy
+    float ju[3];          // accumulator unit -> physical Jx, Jy, Jz
     int n_species;
     SpeciesDev sp[kMaxSpecies];
 };
+
+// The part of a tile section [begin, end) streamed by wavefront w of the
+// push kernel: the 64-aligned chunks covering the section are split into
+// kWaves contiguous runs.  Returns the slot range [lo, hi) (lo >= hi: none).
+// The leavers found by wavefront w are stored from slot lo of the leaver list.
+__host__ __device__ __forceinline__ void wave_range(int begin, int end, int w, int &lo, int &hi)
+{
+    if (end <= begin) {
+        lo = hi = begin;
+        return;
+    }
+    const int c0 = begin >> 6, c1 = (end + 63) >> 6;
+    const int q = (c1 - c0 + kWaves - 1) / kWaves;
+    const int a = (c0 + w * q) << 6, b = (c0 + (w + 1) * q) << 6;
+    lo = a > begin ? a : begin;
+    hi = b < end ? b : end;
+    if (hi < lo) hi = lo;
+}
 
 struct SortSpecies {
     int32_t *cell;
@@ -75,7 +113,7 @@ struct SortArgs {
 };
 
 // ---- launchers (each defined next to its kernels) ----
-void launch_push_deposit(int tile, int replicas, const PushArgs &a, int n_tiles, hipStream_t s);
+void launch_push_deposit(int tile, int replicas, int jmode, const PushArgs &a, int n_tiles, hipStream_t s);
 void launch_j_reduce(int tile, const float *jtile, float *J, int nx, int ny, int ntx, int nty,
                      hipStream_t s);
 void launch_sort_scan(const SortArgs &a, int n_tiles, hipStream_t s);

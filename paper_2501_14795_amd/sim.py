@@ -31,7 +31,7 @@ class Sim:
 
     def __init__(self, nx: int, ny: int, dx: float, dy: float, dt: float, tile: int,
                  species: Sequence, E: Optional[np.ndarray] = None, B: Optional[np.ndarray] = None,
-                 j_replicas: int = 0, device: str = "cuda:0", stream=None):
+                 j_replicas: int = 0, j_float: bool = False, device: str = "cuda:0", stream=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libpic needs a GPU (torch.cuda.is_available() is False)")
@@ -45,7 +45,7 @@ class Sim:
         cfg.tile = self.tile
         cfg.j_replicas = int(j_replicas)
         cfg.n_species = len(species)
-        cfg.flags = 0
+        cfg.flags = _lib.PIC_FLAG_J_FLOAT if j_float else 0
         if not 1 <= len(species) <= _lib.MAX_SPECIES:
             raise ValueError("1..4 species")
         for k, (qm, q, st) in enumerate(species):

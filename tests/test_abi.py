@@ -61,9 +61,9 @@ int main(void) {
     assert [int(v) for v in got] == want
 
 
-def _cfg(L, nx=64, ny=64, dx=0.1, dy=0.1, dt=0.07, tile=16, n=1000, ns=1, reps=0):
+def _cfg(L, nx=64, ny=64, dx=0.1, dy=0.1, dt=0.07, tile=16, n=1000, ns=1, reps=0, flags=0):
     c = L.pic_config()
-    c.nx, c.ny, c.dx, c.dy, c.dt, c.tile, c.j_replicas, c.n_species, c.flags = nx, ny, dx, dy, dt, tile, reps, ns, 0
+    c.nx, c.ny, c.dx, c.dy, c.dt, c.tile, c.j_replicas, c.n_species, c.flags = nx, ny, dx, dy, dt, tile, reps, ns, flags
     for k in range(ns):
         c.species[k].qm = -1.0
         c.species[k].q = -1.0 / 16
@@ -90,6 +90,8 @@ def test_query_sizes_and_validation():
         (dict(ns=0), L.PIC_EINVAL),
         (dict(ns=5), L.PIC_EINVAL),
         (dict(reps=3), L.PIC_EINVAL),
+        (dict(flags=2), L.PIC_EINVAL),
+        (dict(nx=64, tile=32, reps=4), L.PIC_EINVAL),   # int64 current x 4 replicas > LDS
         (dict(n=-1), L.PIC_EINVAL),
         (dict(n=2 ** 31), L.PIC_EINVAL),
     ]
@@ -102,6 +104,7 @@ def test_query_sizes_and_validation():
             L.pic_query(c)
         assert e.value.code == code, (kw, e.value.code)
     assert L.pic_query(_cfg(L, dt=0.0707)).n_tiles == 16
+    assert L.pic_query(_cfg(L, nx=64, tile=32, reps=4, flags=L.PIC_FLAG_J_FLOAT)).n_tiles == 4
     for code in range(0, -9, -1):
         assert L.strerror(code) != "unknown error"
     assert L.strerror(-99) == "unknown error"

@@ -42,10 +42,10 @@ def _uniform(nx=64, ny=64, tile=16, ppc=(4, 4), u_th=0.1, u_fl=(0, 0, 0), seed=1
     return specs, states, E, B
 
 
-def _replay_steps(nx, ny, tile, specs, states, E, B, steps, reps=0, label=""):
+def _replay_steps(nx, ny, tile, specs, states, E, B, steps, reps=0, label="", j_float=False):
     """Every step: push on the GPU vs the oracle push of the GPU's own state,
     then the bit-exact sort replay, then the field advance vs the oracle."""
-    sim, _ = make_pair(nx, ny, DX, DY, DT, tile, specs, states, E, B, j_replicas=reps)
+    sim, _ = make_pair(nx, ny, DX, DY, DT, tile, specs, states, E, B, j_replicas=reps, j_float=j_float)
     worst = [0.0, 0.0, 0.0, 0.0]
     for step in range(steps):
         flush(f"[{label}] step {step}")
@@ -162,21 +162,48 @@ def test_empty_and_ragged_tiles():
     _replay_steps(64, 64, 8, specs, states, E, B, steps=6, label="sub-box")
 
 
-@pytest.mark.parametrize("reps", [1, 2, 4])
-def test_current_replicas(reps):
+@pytest.mark.parametrize("j_float,reps", [(False, 1), (False, 2), (True, 1), (True, 2), (True, 4)])
+def test_current_modes_and_replicas(j_float, reps):
+    """Exact fixed-point (default) and FP32-atomic LDS current, with 1, 2, 4
+    LDS replicas: same parity bar."""
     specs, states, E, B = _uniform(u_th=0.2, fields=0.05, seed=7)
-    _replay_steps(64, 64, 16, specs, states, E, B, steps=2, reps=reps, label=f"R={reps}")
+    _replay_steps(64, 64, 16, specs, states, E, B, steps=2, reps=reps, j_float=j_float,
+                  label=f"{'float' if j_float else 'fixed'} R={reps}")
 
 
-def test_repeatability():
-    """Two identical runs.  Particle updates and the sort are deterministic, so
-    the first push and sort agree bit for bit; the LDS current is summed with
-    float atomics whose order across wavefronts is not fixed, so J -- and
-    everything downstream of it -- agrees only to FP32 round-off."""
+@pytest.mark.parametrize("tile", [8, 32])
+def test_float_current_mode_other_tiles(tile):
+    specs, states, E, B = _uniform(nx=64, ny=64, tile=tile, ppc=(2, 2), u_th=0.3, seed=13, fields=0.05)
+    _replay_steps(64, 64, tile, specs, states, E, B, steps=2, j_float=True, label=f"float T={tile}")
+
+
+def test_repeatability_fixed_point_is_bitwise():
+    """Two identical runs with the default exact fixed-point current: particle
+    updates, the sort and the integer current sums are all order-independent,
+    so five full steps agree bit for bit."""
+    specs, states, E, B = _uniform(u_th=0.2, fields=0.05, seed=8)
+    runs = []
+    for _ in range(2):
+        sim, _ = make_pair(64, 64, DX, DY, DT, 16, specs, states, E, B)
+        for _s in range(5):
+            sim.step()
+        assert sim.check() == 0
+        runs.append((sim.state(0), sim.field_arrays()))
+        sim.close()
+    (a, fa), (b, fb) = runs
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+
+
+def test_repeatability_float_mode_to_roundoff():
+    """FP32 LDS atomics add in an order that varies between runs: the first
+    push and sort agree bit for bit (they do not read J), J only to round-off."""
     specs, states, E, B = _uniform(u_th=0.2, fields=0.05, seed=8)
     first, runs = [], []
     for _ in range(2):
-        sim, _ = make_pair(64, 64, DX, DY, DT, 16, specs, states, E, B)
+        sim, _ = make_pair(64, 64, DX, DY, DT, 16, specs, states, E, B, j_float=True)
         sim.push_deposit()
         sim.sort()
         first.append((sim.state(0), sim.field_arrays()["J"]))
