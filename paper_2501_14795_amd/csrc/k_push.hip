@@ -200,7 +200,8 @@ __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
                 const float x = ldf(st.x, off), y = ldf(st.y, off);
                 float ux = ldf(st.ux, off), uy = ldf(st.uy, off), uz = ldf(st.uz, off);
                 bool leaver = false;
-                int dir = 4;
+                int dir = 4, ncell = 0;
+                float xn = 0.0f, yn = 0.0f;
                 if (i >= lo && i < hi) {
                     int lx = (cell & 0xffff) - gx0, ly = (cell >> 16) - gy0;
                     if ((unsigned)lx >= (unsigned)T || (unsigned)ly >= (unsigned)T) {
@@ -303,7 +304,8 @@ __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
 
                     // ---- new position: offset back into [0,1), cell index, periodic wrap
                     int nlx = lx, nly = ly;
-                    float xn = x1, yn = y1;
+                    xn = x1;
+                    yn = y1;
                     if (sxn > 0) {
                         xn = x1 - 1.0f;
                         nlx += 1;
@@ -327,7 +329,8 @@ __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
                         }
                     }
                     const int gx = wrapi(gx0 + nlx, a.nx), gy = wrapi(gy0 + nly, a.ny);
-                    __builtin_amdgcn_raw_buffer_store_b32((unsigned)(gx | (gy << 16)), st.cell, off, 0, 0);
+                    ncell = gx | (gy << 16);
+                    __builtin_amdgcn_raw_buffer_store_b32((unsigned)ncell, st.cell, off, 0, 0);
                     stf(st.x, off, xn);
                     stf(st.y, off, yn);
                     stf(st.ux, off, ux);
@@ -341,7 +344,14 @@ __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
                 }
                 const unsigned long long m = __ballot(leaver);
                 if (leaver) {
-                    sp.leav[(int64_t)lo + nleav + lane_rank(m)] = ((uint32_t)(i - begin) << 4) | (uint32_t)dir;
+                    const int64_t pos = (int64_t)lo + nleav + lane_rank(m);
+                    sp.leav[pos] = ((uint32_t)(i - begin) << 4) | (uint32_t)dir;
+                    sp.lp.cell[pos] = ncell;
+                    sp.lp.x[pos] = xn;
+                    sp.lp.y[pos] = yn;
+                    sp.lp.ux[pos] = ux;
+                    sp.lp.uy[pos] = uy;
+                    sp.lp.uz[pos] = uz;
                     atomicAdd(&s_dir[s][dir], 1);
                 }
                 nleav += __popcll(m);

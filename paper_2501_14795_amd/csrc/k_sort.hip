@@ -71,25 +71,112 @@ __device__ __forceinline__ int tile_count_in(const int32_t *cnt, int t, int ntx,
     return v;
 }
 
-__global__ void __launch_bounds__(1024) k_sort_scan(SortArgs a, int n_tiles)
+// Step (1), first pass: new count of every tile and its exclusive prefix
+// within its block of kScanBlock tiles; block totals to bsum.
+__global__ void __launch_bounds__(kScanBlock) k_sort_count(SortArgs a, int n_tiles)
+{
+    const SortSpecies &sp = a.sp[blockIdx.y];
+    const int t = blockIdx.x * kScanBlock + threadIdx.x;
+    const int c = t < n_tiles ? tile_count_in(sp.cnt, t, a.ntx, a.nty) : 0;
+    // block exclusive scan (kScanBlock = 256: four wavefronts)
+    __shared__ int s_w[kScanBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) s_w[w] = x;
+    __syncthreads();
+    int base = 0;
+    for (int k = 0; k < w; ++k) base += s_w[k];
+    if (t < n_tiles) sp.offn[t] = base + x - c;
+    if (threadIdx.x == kScanBlock - 1) sp.bsum[blockIdx.x] = base + x;
+}
+
+// Step (1), second pass (one block per species): exclusive scan of the block
+// totals in place; tile_offset'[n_tiles] = total, checked against n.
+__global__ void __launch_bounds__(1024) k_sort_scan_blocks(SortArgs a, int n_tiles)
 {
     const SortSpecies &sp = a.sp[blockIdx.x];
-    const int per = (n_tiles + 1023) / 1024;
-    const int t0 = min((int)threadIdx.x * per, n_tiles), t1 = min(t0 + per, n_tiles);
-    int sum = 0;
-    for (int t = t0; t < t1; ++t) sum += tile_count_in(sp.cnt, t, a.ntx, a.nty);
-    int total;
-    int base = block_exclusive_scan_1024(sum, &total);
-    for (int t = t0; t < t1; ++t) {
-        sp.offn[t] = base;
-        base += tile_count_in(sp.cnt, t, a.ntx, a.nty);
+    const int nb = (n_tiles + kScanBlock - 1) / kScanBlock;
+    int carry = 0;
+    for (int b0 = 0; b0 < nb; b0 += 1024) {
+        const int b = b0 + threadIdx.x;
+        const int v = b < nb ? sp.bsum[b] : 0;
+        int total;
+        const int ex = block_exclusive_scan_1024(v, &total);
+        if (b < nb) sp.bsum[b] = carry + ex;
+        carry += total;
+        __syncthreads();
     }
     if (threadIdx.x == 0) {
-        sp.offn[n_tiles] = total;
-        if (total != sp.n) atomicOr(a.err, kErrCount);
+        sp.offn[n_tiles] = carry;
+        if (carry != sp.n) atomicOr(a.err, kErrCount);
     }
 }
 
+// Step (1), third pass: add each block's base.
+__global__ void __launch_bounds__(kScanBlock) k_sort_add_base(SortArgs a, int n_tiles)
+{
+    const SortSpecies &sp = a.sp[blockIdx.y];
+    const int t = blockIdx.x * kScanBlock + threadIdx.x;
+    if (t < n_tiles) sp.offn[t] += sp.bsum[blockIdx.x];
+}
+
+// Slot of the list holding flat index k, over the lists described by lanes
+// 0..63 (exclusive prefix `ex` of their lengths, INT_MAX past the last list):
+// the largest L with ex_L <= k.  Fixed-step binary search, all lanes active.
+__device__ __forceinline__ int find_list(int k, int ex)
+{
+    int lo = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        const int e = __shfl(ex, lo + step < 64 ? lo + step : 63, 64);
+        if (lo + step < 64 && e <= k) lo += step;
+    }
+    return lo;
+}
+
+// Wave-wide exclusive prefix of v (and the total).
+__device__ __forceinline__ int wave_exclusive(int v, int &total)
+{
+    const int lane = threadIdx.x & 63;
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+__device__ __forceinline__ void copy_particle(const Parts &src, int64_t i, const Parts &dst, int64_t j)
+{
+    dst.cell[j] = src.cell[i];
+    dst.x[j] = src.x[i];
+    dst.y[j] = src.y[i];
+    dst.ux[j] = src.ux[i];
+    dst.uy[j] = src.uy[i];
+    dst.uz[j] = src.uz[i];
+}
+
+// Steps (2)-(4) of the sort for one destination tile t per wavefront, new
+// section [A, B), old section [oA, oB).  Every candidate list of holes and
+// of movers is described by one lane; the lists are then streamed as one
+// flat index space, 64 candidates per iteration, and compacted with ballots,
+// which keeps both outputs in ascending slot order.
+//   hole lists  : [A, min(B, oA))  slots of lower old sections (hole unless
+//                                  the particle there moved into t)
+//                 t's leaver sub-lists, restricted to [max(A,oA), min(B,oB))
+//                 [max(A, oB), B)  slots of higher old sections
+//   mover lists : for each source tile s of t (the nine tiles a particle of t
+//                 can come from, ascending, duplicates dropped):
+//                 s != t: s's four leaver sub-lists, entries heading to t whose
+//                         slot is outside [A, B); data from the leaver copy
+//                 s == t: t's slots outside [A, B) whose particle kept tile t
 __global__ void __launch_bounds__(kBlock) k_sort_plan(SortArgs a, int n_tiles)
 {
     const int lane = threadIdx.x & 63;
@@ -100,135 +187,143 @@ __global__ void __launch_bounds__(kBlock) k_sort_plan(SortArgs a, int n_tiles)
     const int tsh = __builtin_ctz(a.tile);
     const int A = sp.offn[t], B = sp.offn[t + 1];
     const int oA = sp.off[t], oB = sp.off[t + 1];
-
     auto tile_of = [&](int cell) { return ((cell >> 16) >> tsh) * ntx + ((cell & 0xffff) >> tsh); };
+    bool bad = false;
 
     // ---------------- holes, ascending
     int nh = 0;
-    auto hole_scan = [&](int lo, int hi, bool want_foreign) {
-        for (int b = lo; b < hi; b += 64) {
-            const int i = b + lane;
-            bool p = false;
-            if (i < hi) p = (tile_of(sp.cell[i]) != t) == want_foreign;
-            const unsigned long long m = __ballot(p);
-            if (p && nh + lane_rank_s(m) < B - A) sp.hole[(int64_t)A + nh + lane_rank_s(m)] = i;
-            nh += __popcll(m);
-        }
-    };
-    // part of [A, B) below t's old section: holes unless the particle moved into t
-    hole_scan(A, min(B, oA), true);
-    // part of [A, B) inside t's old section: holes are t's leavers there
     {
         const int lA = max(A, oA), lB = min(B, oB);
-        if (lA < lB) {
-            for (int w = 0; w < kWaves; ++w) {
-                const int cw = sp.cnt[(int64_t)t * kCntStride + kCntSub + w];
-                int wlo, whi;
-                wave_range(oA, oB, w, wlo, whi);
-                const int64_t base = wlo;
-                for (int b = 0; b < cw; b += 64) {
-                    const int k = b + lane;
-                    bool p = false;
-                    int slot = 0;
-                    if (k < cw && k < whi - wlo) {
-                        slot = oA + (int)(sp.leav[base + k] >> 4);
-                        p = slot >= lA && slot < lB;
-                    }
-                    const unsigned long long m = __ballot(p);
-                    if (p && nh + lane_rank_s(m) < B - A) sp.hole[(int64_t)A + nh + lane_rank_s(m)] = slot;
-                    nh += __popcll(m);
+        int kind = 0, base = 0, len = 0;   // kind 0: slot range, 1: leaver sub-list of t
+        if (lane == 0) {
+            base = A;
+            len = max(0, min(B, oA) - A);
+        } else if (lane <= kWaves) {
+            int wlo, whi;
+            wave_range(oA, oB, lane - 1, wlo, whi);
+            kind = 1;
+            base = wlo;
+            len = lA < lB ? min(sp.cnt[(int64_t)t * kCntStride + kCntSub + lane - 1], whi - wlo) : 0;
+        } else if (lane == kWaves + 1) {
+            base = max(A, oB);
+            len = max(0, B - base);
+        }
+        int total;
+        int ex = wave_exclusive(len, total);
+        if (lane > kWaves + 1) ex = INT_MAX;
+        for (int k0 = 0; k0 < total; k0 += 64) {
+            const int k = k0 + lane;
+            const int L = find_list(k, ex);
+            const int kL = __shfl(kind, L, 64), bL = __shfl(base, L, 64), eL = __shfl(ex, L, 64);
+            bool p = false;
+            int slot = 0;
+            if (k < total) {
+                if (kL == 0) {
+                    slot = bL + (k - eL);
+                    p = tile_of(sp.p.cell[slot]) != t;
+                } else {
+                    slot = oA + (int)(sp.leav[(int64_t)bL + (k - eL)] >> 4);
+                    p = slot >= lA && slot < lB;
                 }
             }
+            const unsigned long long m = __ballot(p);
+            const int r = nh + lane_rank_s(m);
+            if (p && r < B - A) sp.hole[(int64_t)A + r] = slot;
+            nh += __popcll(m);
         }
     }
-    // part of [A, B) above t's old section
-    hole_scan(max(A, oB), B, true);
 
     // ---------------- movers, ascending old slot, gathered into staging
     int nm = 0;
-    bool bad = false;
-    auto gather = [&](bool p, int slot) {
-        const unsigned long long m = __ballot(p);
-        if (p) {
-            const int r = A + nm + lane_rank_s(m);
-            if (r < B) {
-                sp.stg_cell[r] = sp.cell[slot];
-                sp.stg_x[r] = sp.x[slot];
-                sp.stg_y[r] = sp.y[slot];
-                sp.stg_ux[r] = sp.ux[slot];
-                sp.stg_uy[r] = sp.uy[slot];
-                sp.stg_uz[r] = sp.uz[slot];
+    {
+        // source tiles: lane o < 9 holds one, then its rank among the distinct ones
+        const int tx = t % ntx, ty = t / ntx;
+        int so = -1;
+        if (lane < 9) so = wrap_s(ty - (lane / 3 - 1), nty) * ntx + wrap_s(tx - (lane % 3 - 1), ntx);
+        int rank = 0, first = 1, nuniq = 0;
+#pragma unroll
+        for (int o = 0; o < 9; ++o) {
+            const int v = __shfl(so, o, 64);
+            bool vfirst = true;
+            for (int o2 = 0; o2 < o; ++o2)
+                if (__shfl(so, o2, 64) == v) vfirst = false;
+            if (vfirst) ++nuniq;
+            if (vfirst && v < so) ++rank;
+            if (o < lane && v == so) first = 0;
+        }
+        // list L = 4 * (rank of its source) + w
+        const int L = lane, pr = L >> 2, w = L & 3;
+        int src = -1;
+#pragma unroll
+        for (int o = 0; o < 9; ++o) {
+            const int v = __shfl(so, o, 64), vr = __shfl(rank, o, 64), vf = __shfl(first, o, 64);
+            if (vf && vr == pr) src = v;
+        }
+        int kind = 0, base = 0, len = 0;   // kind 0: slot range of t, 1: leaver sub-list of src
+        if (pr < nuniq) {
+            if (src == t) {
+                if (w == 0) {
+                    base = oA;
+                    len = max(0, min(oB, A) - oA);
+                } else if (w == 1) {
+                    base = max(oA, B);
+                    len = max(0, oB - base);
+                }
+            } else {
+                const int s0 = sp.off[src], s1 = sp.off[src + 1];
+                int wlo, whi;
+                wave_range(s0, s1, w, wlo, whi);
+                kind = 1;
+                base = wlo;
+                len = min(sp.cnt[(int64_t)src * kCntStride + kCntSub + w], whi - wlo);
             }
         }
-        nm += __popcll(m);
-    };
-
-    // the nine tiles a particle of t can come from, ascending, duplicates dropped
-    const int tx = t % ntx, ty = t / ntx;
-    int src[9];
-#pragma unroll
-    for (int o = 0; o < 9; ++o) src[o] = wrap_s(ty - (o / 3 - 1), nty) * ntx + wrap_s(tx - (o % 3 - 1), ntx);
-#pragma unroll
-    for (int i = 1; i < 9; ++i)
-#pragma unroll
-        for (int j = i; j > 0; --j)
-            if (src[j] < src[j - 1]) {
-                const int tmp = src[j];
-                src[j] = src[j - 1];
-                src[j - 1] = tmp;
-            }
-
-#pragma unroll
-    for (int o = 0; o < 9; ++o) {
-        const int s = src[o];
-        if (o > 0 && s == src[o - 1]) continue;
-        if (s == t) {
-            // t's own particles outside [A, B) that kept tile t
-            const int lo1 = oA, hi1 = min(oB, A), lo2 = max(oA, B), hi2 = oB;
-            for (int r = 0; r < 2; ++r) {
-                const int lo = r ? lo2 : lo1, hi = r ? hi2 : hi1;
-                for (int b = lo; b < hi; b += 64) {
-                    const int i = b + lane;
-                    const bool p = i < hi && tile_of(sp.cell[i]) == t;
-                    gather(p, i);
-                }
-            }
-        } else {
-            const int so = sp.off[s], ns = sp.off[s + 1] - so;
-            const int sx = s % ntx, sy = s / ntx;
-            for (int w = 0; w < kWaves; ++w) {
-                const int cw = sp.cnt[(int64_t)s * kCntStride + kCntSub + w];
-                int wlo, whi;
-                wave_range(so, so + ns, w, wlo, whi);
-                const int64_t base = wlo;
-                for (int b = 0; b < cw; b += 64) {
-                    const int k = b + lane;
-                    bool p = false;
-                    int slot = 0;
-                    if (k < cw && k < whi - wlo) {
-                        const uint32_t e = sp.leav[base + k];
-                        const int d = (int)(e & 15u), loc = (int)(e >> 4);
+        int total;
+        int ex = wave_exclusive(len, total);
+        if (pr >= nuniq) ex = INT_MAX;
+        for (int k0 = 0; k0 < total; k0 += 64) {
+            const int k = k0 + lane;
+            const int Lk = find_list(k, ex);
+            const int kL = __shfl(kind, Lk, 64), bL = __shfl(base, Lk, 64), eL = __shfl(ex, Lk, 64);
+            const int sL = __shfl(src, Lk, 64);
+            bool p = false;
+            bool from_leavers = false;
+            int64_t at = 0;
+            if (k < total) {
+                if (kL == 0) {
+                    at = bL + (k - eL);
+                    p = tile_of(sp.p.cell[at]) == t;
+                } else {
+                    at = (int64_t)bL + (k - eL);
+                    const uint32_t e = sp.leav[at];
+                    const int d = (int)(e & 15u), loc = (int)(e >> 4);
+                    const int s0 = sp.off[sL], ns = sp.off[sL + 1] - s0;
+                    if (loc >= ns || d > 8) {
+                        bad = true;
+                    } else {
+                        const int sx = sL % ntx, sy = sL / ntx;
                         const int dest = wrap_s(sy + d / 3 - 1, nty) * ntx + wrap_s(sx + d % 3 - 1, ntx);
-                        if (loc >= ns || d > 8) {
-                            bad = true;
-                        } else {
-                            slot = so + loc;
-                            p = dest == t && !(slot >= A && slot < B);
-                        }
+                        const int slot = s0 + loc;
+                        p = dest == t && !(slot >= A && slot < B);
+                        from_leavers = true;
                     }
-                    gather(p, slot);
                 }
             }
+            const unsigned long long m = __ballot(p);
+            const int r = nm + lane_rank_s(m);
+            if (p && r < B - A) copy_particle(from_leavers ? sp.lp : sp.p, at, sp.stg, (int64_t)A + r);
+            nm += __popcll(m);
         }
     }
 
+    const bool anybad = __ballot(bad) != 0ull;
     if (lane == 0) {
-        if (nh != nm || bad) atomicOr(a.err, kErrSort);
+        if (nh != nm || anybad) atomicOr(a.err, kErrSort);
         sp.mcount[t] = min(nh, nm);
     }
-    if (__ballot(bad) != 0ull && lane == 0) atomicOr(a.err, kErrSort);
 }
 
+// Step (5): the k-th hole of each tile receives the k-th mover.
 __global__ void __launch_bounds__(kBlock) k_sort_scatter(SortArgs a, int n_tiles)
 {
     const int lane = threadIdx.x & 63;
@@ -238,13 +333,7 @@ __global__ void __launch_bounds__(kBlock) k_sort_scatter(SortArgs a, int n_tiles
     const int A = sp.offn[t], m = sp.mcount[t];
     for (int k = lane; k < m; k += 64) {
         const int64_t r = (int64_t)A + k;
-        const int dst = sp.hole[r];
-        sp.cell[dst] = sp.stg_cell[r];
-        sp.x[dst] = sp.stg_x[r];
-        sp.y[dst] = sp.stg_y[r];
-        sp.ux[dst] = sp.stg_ux[r];
-        sp.uy[dst] = sp.stg_uy[r];
-        sp.uz[dst] = sp.stg_uz[r];
+        copy_particle(sp.stg, r, sp.p, sp.hole[r]);
     }
 }
 
@@ -290,7 +379,11 @@ __global__ void __launch_bounds__(1024) k_init_scan(const int32_t *counts, int n
 
 void launch_sort_scan(const SortArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sort_scan, dim3(a.n_species), dim3(1024), 0, s, a, n_tiles);
+    hipLaunchKernelGGL(k_sort_count, dim3((n_tiles + kScanBlock - 1) / kScanBlock, a.n_species), dim3(kScanBlock),
+                       0, s, a, n_tiles);
+    hipLaunchKernelGGL(k_sort_scan_blocks, dim3(a.n_species), dim3(1024), 0, s, a, n_tiles);
+    hipLaunchKernelGGL(k_sort_add_base, dim3((n_tiles + kScanBlock - 1) / kScanBlock, a.n_species),
+                       dim3(kScanBlock), 0, s, a, n_tiles);
 }
 
 void launch_sort_plan(const SortArgs &a, int n_tiles, hipStream_t s)

@@ -21,7 +21,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 struct Layout {
     size_t err = 0, dacc = 0, cacc = 0, jtile = 0, rho_prev = 0, rho_now = 0;
     size_t off[kMaxSpecies][2] = {}, cnt[kMaxSpecies] = {}, leav[kMaxSpecies] = {};
-    size_t hole[kMaxSpecies] = {}, stg[kMaxSpecies][6] = {}, mcount[kMaxSpecies] = {};
+    size_t hole[kMaxSpecies] = {}, stg[kMaxSpecies][6] = {}, mcount[kMaxSpecies] = {}, bsum[kMaxSpecies] = {};
+    size_t lpart[kMaxSpecies][6] = {};
     size_t total = 0;
 };
 
@@ -82,9 +83,11 @@ Layout make_layout(const pic_config *c)
         L.off[s][1] = take((n_tiles + 1) * sizeof(int32_t));
         L.cnt[s] = take((size_t)n_tiles * kCntStride * sizeof(int32_t));
         L.leav[s] = take(n * sizeof(uint32_t));
+        for (int k = 0; k < 6; ++k) L.lpart[s][k] = take(n * 4);
         L.hole[s] = take(n * sizeof(int32_t));
         for (int k = 0; k < 6; ++k) L.stg[s][k] = take(n * 4);
         L.mcount[s] = take((size_t)n_tiles * sizeof(int32_t));
+        L.bsum[s] = take((size_t)(n_tiles / kScanBlock + 1) * sizeof(int32_t));
     }
     L.total = p;
     return L;
@@ -109,9 +112,10 @@ struct pic_sim {
         int32_t *cnt;
         uint32_t *leav;
         int32_t *hole;
-        int32_t *stg_cell;
-        float *stg[5];
+        Parts stg;
+        Parts lp;
         int32_t *mcount;
+        int32_t *bsum;
     } sp[kMaxSpecies];
     // timing
     bool timing;
@@ -266,9 +270,20 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
         P.cnt = (int32_t *)(w + L.cnt[s]);
         P.leav = (uint32_t *)(w + L.leav[s]);
         P.hole = (int32_t *)(w + L.hole[s]);
-        P.stg_cell = (int32_t *)(w + L.stg[s][0]);
-        for (int k = 0; k < 5; ++k) P.stg[k] = (float *)(w + L.stg[s][k + 1]);
+        auto parts_at = [&](const size_t *o) {
+            Parts q;
+            q.cell = (int32_t *)(w + o[0]);
+            q.x = (float *)(w + o[1]);
+            q.y = (float *)(w + o[2]);
+            q.ux = (float *)(w + o[3]);
+            q.uy = (float *)(w + o[4]);
+            q.uz = (float *)(w + o[5]);
+            return q;
+        };
+        P.stg = parts_at(L.stg[s]);
+        P.lp = parts_at(L.lpart[s]);
         P.mcount = (int32_t *)(w + L.mcount[s]);
+        P.bsum = (int32_t *)(w + L.bsum[s]);
     }
 
     rc = hip_ok(hipMemsetAsync(S->err, 0, 64, stream));
@@ -330,6 +345,7 @@ int pic_push_deposit(pic_sim *S, hipStream_t stream)
         d.off = S->sp[s].off[S->sp[s].cur];
         d.cnt = S->sp[s].cnt;
         d.leav = S->sp[s].leav;
+        d.lp = S->sp[s].lp;
         d.n = (int32_t)c.species[s].n;
         d.h = (float)(0.5 * c.species[s].qm * c.dt);
         d.fq = (float)(scale * c.species[s].q / qmax);
@@ -362,24 +378,21 @@ int pic_sort(pic_sim *S, hipStream_t stream)
         const pic_particles &p = S->buf.sp[s];
         auto &P = S->sp[s];
         SortSpecies &d = a.sp[s];
-        d.cell = p.cell;
-        d.x = p.x;
-        d.y = p.y;
-        d.ux = p.ux;
-        d.uy = p.uy;
-        d.uz = p.uz;
+        d.p.cell = p.cell;
+        d.p.x = p.x;
+        d.p.y = p.y;
+        d.p.ux = p.ux;
+        d.p.uy = p.uy;
+        d.p.uz = p.uz;
+        d.lp = P.lp;
+        d.stg = P.stg;
         d.off = P.off[P.cur];
         d.offn = P.off[P.cur ^ 1];
         d.cnt = P.cnt;
         d.leav = P.leav;
         d.hole = P.hole;
-        d.stg_cell = P.stg_cell;
-        d.stg_x = P.stg[0];
-        d.stg_y = P.stg[1];
-        d.stg_ux = P.stg[2];
-        d.stg_uy = P.stg[3];
-        d.stg_uz = P.stg[4];
         d.mcount = P.mcount;
+        d.bsum = P.bsum;
         d.n = (int32_t)c.species[s].n;
     }
     {

@@ -13,6 +13,7 @@ constexpr int kMaxSpecies = PIC_MAX_SPECIES;
 constexpr int kBlock = 256;          // threads per push / sort block (4 wavefronts)
 constexpr int kWaves = kBlock / 64;
 constexpr int kCntStride = 16;       // ints per tile in the count record
+constexpr int kScanBlock = 256;      // tiles per block of the tile-count scan
 
 // Count record of one tile, written by the push kernel:
 //   [0..8]   particles per direction of motion d = (dty+1)*3 + (dtx+1);
@@ -51,12 +52,19 @@ constexpr int push_lds_bytes(int T, int R, int JM)
            kMaxSpecies * (9 + kWaves) * 4;
 }
 
+// One species' particles as a structure of arrays (n entries each).
+struct Parts {
+    int32_t *cell;
+    float *x, *y, *ux, *uy, *uz;
+};
+
 struct SpeciesDev {
     int32_t *cell;
     float *x, *y, *ux, *uy, *uz;
     const int32_t *off;   // tile_offset at the start of the step (n_tiles + 1)
     int32_t *cnt;         // [n_tiles][kCntStride]
     uint32_t *leav;       // [n]: leaver sub-lists, (slot - off[t]) << 4 | direction
+    Parts lp;             // [n]: the leavers' new particle data, same positions as leav
     int32_t n;
     float h;              // (q/m) dt / 2
     float fq;             // charge in accumulator units: q / max|q| (x kFixedScale in fixed mode)
@@ -92,16 +100,16 @@ __host__ __device__ __forceinline__ void wave_range(int begin, int end, int w, i
 }
 
 struct SortSpecies {
-    int32_t *cell;
-    float *x, *y, *ux, *uy, *uz;
+    Parts p;              // the particle arrays
+    Parts lp;             // leaver particle data written by the push kernel
+    Parts stg;            // mover staging, [n]: tile t's movers at offn[t] + k
     const int32_t *off;   // old tile_offset
     int32_t *offn;        // new tile_offset
     const int32_t *cnt;
     const uint32_t *leav;
-    int32_t *hole;        // [n]
-    int32_t *stg_cell;    // staging SoA [n] each
-    float *stg_x, *stg_y, *stg_ux, *stg_uy, *stg_uz;
+    int32_t *hole;        // [n]: tile t's holes, ascending, at offn[t] + k
     int32_t *mcount;      // [n_tiles]
+    int32_t *bsum;        // [n_tiles / kScanBlock + 1] block totals of the tile scan
     int32_t n;
 };
 
