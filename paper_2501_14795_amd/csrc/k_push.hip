@@ -130,6 +130,25 @@ __device__ __forceinline__ void deposit_piece(typename JAcc<JM>::T *sj, int cx, 
     A::add(&sj[2 * P + b + NJ + 1], az * fmaf(xm, ym, c));
 }
 
+// Write the n leavers buffered in LDS by one wavefront to the leaver list
+// and the leaver copies, from position pos on (contiguous: whole lines).
+__device__ __forceinline__ void flush_leavers(const SpeciesDev &sp, uint32_t (*lb)[kLeaverBuf], int n,
+                                              int64_t pos, int lane)
+{
+    __builtin_amdgcn_wave_barrier();
+    if (lane < n) {
+        const int64_t q = pos + lane;
+        sp.leav[q] = lb[0][lane];
+        sp.lp.cell[q] = (int32_t)lb[1][lane];
+        sp.lp.x[q] = __uint_as_float(lb[2][lane]);
+        sp.lp.y[q] = __uint_as_float(lb[3][lane]);
+        sp.lp.ux[q] = __uint_as_float(lb[4][lane]);
+        sp.lp.uy[q] = __uint_as_float(lb[5][lane]);
+        sp.lp.uz[q] = __uint_as_float(lb[6][lane]);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <int T, int R, int JM>
 __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
 {
@@ -147,6 +166,7 @@ __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
     __shared__ Acc s_j[R][3 * JP];
     __shared__ int s_dir[kMaxSpecies][9];
     __shared__ int s_wl[kMaxSpecies][kWaves];
+    __shared__ uint32_t s_lb[kWaves][7][kLeaverBuf];   // leaver entry + new particle data
 
     const int tile = blockIdx.x;
     const int tx = tile % a.ntx, ty = tile / a.ntx;
@@ -191,14 +211,26 @@ __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
             st.uy = rsrc(sp.uy + base, bytes);
             st.uz = rsrc(sp.uz + base, bytes);
             const float h = sp.h, fq = sp.fq;
-            for (int cb = (lo >> 6) << 6; cb < hi; cb += 64) {
+            int nbuf = 0;   // leavers waiting in the wavefront's LDS buffer (uniform)
+            // Loads past the section end return 0; lanes before it read the
+            // previous tile's particles and discard them.  The next chunk is
+            // always prefetched before the current one is processed.
+            int cb = (lo >> 6) << 6;
+            int off = (cb + lane - base) * 4;
+            int n_cell = (int)__builtin_amdgcn_raw_buffer_load_b32(st.cell, off, 0, 0);
+            float n_x = ldf(st.x, off), n_y = ldf(st.y, off);
+            float n_ux = ldf(st.ux, off), n_uy = ldf(st.uy, off), n_uz = ldf(st.uz, off);
+            for (; cb < hi; cb += 64, off += 256) {
                 const int i = cb + lane;
-                const int off = (i - base) * 4;
-                // loads past the section end return 0; lanes before it read the
-                // previous tile's particles and discard them
-                const int cell = (int)__builtin_amdgcn_raw_buffer_load_b32(st.cell, off, 0, 0);
-                const float x = ldf(st.x, off), y = ldf(st.y, off);
-                float ux = ldf(st.ux, off), uy = ldf(st.uy, off), uz = ldf(st.uz, off);
+                const int cell = n_cell;
+                const float x = n_x, y = n_y;
+                float ux = n_ux, uy = n_uy, uz = n_uz;
+                n_cell = (int)__builtin_amdgcn_raw_buffer_load_b32(st.cell, off + 256, 0, 0);
+                n_x = ldf(st.x, off + 256);
+                n_y = ldf(st.y, off + 256);
+                n_ux = ldf(st.ux, off + 256);
+                n_uy = ldf(st.uy, off + 256);
+                n_uz = ldf(st.uz, off + 256);
                 bool leaver = false;
                 int dir = 4, ncell = 0;
                 float xn = 0.0f, yn = 0.0f;
@@ -342,20 +374,32 @@ __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
                     dir = (dty + 1) * 3 + (dtx + 1);
                     leaver = dir != 4;
                 }
+                // leavers go to the wavefront's LDS buffer in slot order; a full
+                // buffer is written out as whole cache lines
                 const unsigned long long m = __ballot(leaver);
-                if (leaver) {
-                    const int64_t pos = (int64_t)lo + nleav + lane_rank(m);
-                    sp.leav[pos] = ((uint32_t)(i - begin) << 4) | (uint32_t)dir;
-                    sp.lp.cell[pos] = ncell;
-                    sp.lp.x[pos] = xn;
-                    sp.lp.y[pos] = yn;
-                    sp.lp.ux[pos] = ux;
-                    sp.lp.uy[pos] = uy;
-                    sp.lp.uz[pos] = uz;
-                    atomicAdd(&s_dir[s][dir], 1);
+                const int c = __popcll(m);
+                if (c != 0) {
+                    if (nbuf + c > kLeaverBuf) {
+                        flush_leavers(sp, s_lb[wave], nbuf, (int64_t)lo + nleav, lane);
+                        nleav += nbuf;
+                        nbuf = 0;
+                    }
+                    if (leaver) {
+                        const int r = nbuf + lane_rank(m);
+                        s_lb[wave][0][r] = ((uint32_t)(i - begin) << 4) | (uint32_t)dir;
+                        s_lb[wave][1][r] = (uint32_t)ncell;
+                        s_lb[wave][2][r] = __float_as_uint(xn);
+                        s_lb[wave][3][r] = __float_as_uint(yn);
+                        s_lb[wave][4][r] = __float_as_uint(ux);
+                        s_lb[wave][5][r] = __float_as_uint(uy);
+                        s_lb[wave][6][r] = __float_as_uint(uz);
+                        atomicAdd(&s_dir[s][dir], 1);
+                    }
+                    nbuf += c;
                 }
-                nleav += __popcll(m);
             }
+            flush_leavers(sp, s_lb[wave], nbuf, (int64_t)lo + nleav, lane);
+            nleav += nbuf;
         }
         if (lane == 0) s_wl[s][wave] = nleav;
     }

@@ -44,12 +44,13 @@ enum : int {
 constexpr float kFixedScale = 16777216.0f;
 
 constexpr int kLdsBytes = 160 * 1024;   // LDS of one gfx950 compute unit
+constexpr int kLeaverBuf = 64;           // leavers buffered per wavefront before a write-out
 
 // Static LDS of the push kernel for tile T, R current replicas, mode JM.
 constexpr int push_lds_bytes(int T, int R, int JM)
 {
     return (T + 2) * (T + 2) * 48 + R * 3 * (T + 3) * (T + 3) * (JM == kJFixed ? 8 : 4) +
-           kMaxSpecies * (9 + kWaves) * 4;
+           kMaxSpecies * (9 + kWaves) * 4 + kWaves * 7 * kLeaverBuf * 4;
 }
 
 // One species' particles as a structure of arrays (n entries each).
