@@ -81,6 +81,7 @@ def main():
     ap.add_argument("--replicas", type=int, default=0)
     ap.add_argument("--workload", default="warm2048")
     ap.add_argument("--j-float", action="store_true", help="FP32-atomic LDS current instead of fixed point")
+
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "

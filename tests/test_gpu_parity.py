@@ -271,3 +271,30 @@ def test_energy_diagnostic_matches_oracle():
     assert abs(d.u_e - ue) <= 1e-12 * ue and abs(d.u_b - ub) <= 1e-12 * ub
     assert abs(d.u_k[0] - uk[0]) <= 1e-12 * uk[0]
     sim.close()
+
+
+@pytest.mark.parametrize("nx,ny,tile,nspecies,box", [(64, 64, 16, 1, None), (32, 32, 16, 2, None),
+                                                    (64, 32, 8, 1, (3, 40, 5, 21)), (64, 64, 32, 1, None)])
+def test_step_equals_explicit_calls(nx, ny, tile, nspecies, box):
+    """Six pic_step calls give bit for bit the state of six rounds of
+    pic_push_deposit / pic_sort / pic_field_advance (fixed-point current)."""
+    specs, states, E, B = _uniform(nx=nx, ny=ny, tile=tile, ppc=(2, 2), u_th=0.3, u_fl=(0.2, 0.1, 0.3),
+                                   seed=21, fields=0.05, box=box, nspecies=nspecies)
+    a, _ = make_pair(nx, ny, DX, DY, DT, tile, specs, states, E, B)
+    b, _ = make_pair(nx, ny, DX, DY, DT, tile, specs, states, E, B)
+    for _ in range(6):
+        a.step()
+        b.push_deposit()
+        b.sort()
+        b.field_advance()
+    assert a.check() == 0 and b.check() == 0
+    for k in range(nspecies):
+        assert np.array_equal(a.tile_offsets(k), b.tile_offsets(k))
+        sa, sb = a.state(k), b.state(k)
+        for name in sa:
+            assert np.array_equal(sa[name], sb[name]), name
+    fa, fb = a.field_arrays(), b.field_arrays()
+    for name in fa:
+        assert np.array_equal(fa[name], fb[name]), name
+    a.close()
+    b.close()
