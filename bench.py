@@ -72,6 +72,65 @@ def cpu_baseline(w, st, budget_s=10.0, max_steps=8):
             "seconds": t_hot}
 
 
+def batched_comparison(n_sims=256, steps=5, tune_sims=32):
+    """The batched workload (256 independent simulations, grids 32..256
+    cells, 8..64 ppc): the autotuner picks tile size x replicas on the first
+    tune_sims members, then the full batch runs as captured-graph replays, as
+    direct batched launches, and one simulation per launch sequence (pic_step
+    on each member in turn), all on the same members and data."""
+    import torch
+
+    import pic_workloads as pw
+    from paper_2501_14795_amd import Batch, _lib
+    from paper_2501_14795_amd.tune import autotune_batch, time_batch
+
+    specs = pw.batched_members(n_sims, 4)
+
+    def build(tile, subset=None):
+        out = []
+        for m in (specs if subset is None else specs[:subset]):
+            st = pw.species_state(m["nx"], m["ny"], tile, m["spec"], m["seed"])
+            out.append({"nx": m["nx"], "ny": m["ny"], "dx": m["dx"], "dy": m["dy"], "dt": m["dt"],
+                        "species": [(m["spec"].qm, m["spec"].q, st)]})
+        return out
+
+    t0 = time.perf_counter()
+    (tile, reps), tuning = autotune_batch(lambda T: build(T, tune_sims))
+    log(f"autotuned tile {tile} replicas {reps} in {time.perf_counter() - t0:.1f}s: {tuning}")
+    members = build(tile)
+    n = sum(m["species"][0][2]["ix"].size for m in members)
+    b = Batch(members, tile=tile, j_replicas=reps)
+    del members
+    direct = time_batch(b, steps)
+    # one simulation per launch sequence, on the same members
+    s = b.stream.cuda_stream
+    for m in b.members:
+        _lib.pic_step(m.handle, s)
+    b.stream.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for m in b.members:
+            _lib.pic_step(m.handle, s)
+    b.stream.synchronize()
+    per_sim = (time.perf_counter() - t0) / steps
+    b.capture()
+    graph = time_batch(b, steps)
+    rc = b.check()
+    b.close()
+    if rc != 0:
+        raise SystemExit(f"device error in the batched run: {_lib.strerror(rc)}")
+    return {
+        "workload": f"{n_sims} simulations, grids 32..256 cells, 8..64 ppc (seed 4)",
+        "particles": n, "steps": steps, "tile": tile, "j_replicas": reps,
+        "autotune_ms_per_step": {f"T{k[0]}_R{k[1]}": v * 1e3 for k, v in tuning.items()},
+        "graph_pushes_per_s": n / graph, "direct_pushes_per_s": n / direct,
+        "per_sim_launch_pushes_per_s": n / per_sim,
+        "graph_ms_per_step": graph * 1e3, "direct_ms_per_step": direct * 1e3,
+        "per_sim_launch_ms_per_step": per_sim * 1e3,
+        "speedup_vs_per_sim_launch": per_sim / graph,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +142,7 @@ def main():
     ap.add_argument("--j-float", action="store_true", help="FP32-atomic LDS current instead of fixed point")
 
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-mode comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (a known-size "
                          "reference kernel for the HBM byte counters of a profiling run)")
@@ -198,6 +258,12 @@ def main():
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
     }
     sim.close()
+    del sim
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched"] = batched_comparison()
+        log(f"batched: {out['batched']}")
     print(json.dumps(out), flush=True)
 
 

@@ -214,6 +214,51 @@ int pic_set_timing(pic_sim *sim, int enable);
 /* Synchronise on the recorded events and return the sums since the last reset. */
 int pic_get_timing(pic_sim *sim, pic_timing_out *out);
 
+/*
+ * ---- Many independent simulations advanced together (batched mode) ----
+ *
+ * Hundreds of small simulations (each its own grid, species and particle
+ * count) share every kernel launch: one launch per phase of the step for the
+ * whole batch, the push as a persistent grid that takes (simulation, tile)
+ * work items largest-simulation-first, and optionally one captured HIP graph
+ * per step.  All members must share tile, j_replicas and flags.  Results are
+ * bit-identical to advancing each member alone with pic_step.
+ */
+typedef struct pic_batch pic_batch;
+
+/* Device bytes the batch itself needs (descriptors, work tables, counter). */
+int pic_batch_query(int n, const pic_config *cfgs, size_t *bytes);
+
+/*
+ * n >= 1 members: cfgs[i] / bufs[i] exactly as for pic_init (each member's
+ * own caller-owned fields, workspace and particles).  batch_work: device
+ * memory of pic_batch_query() bytes, 256-byte aligned, caller-owned.
+ * Synchronises `stream`.  Errors as pic_init, or PIC_EINVAL if the members do
+ * not share tile / j_replicas / flags.
+ */
+int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void *batch_work,
+                   size_t batch_bytes, hipStream_t stream, pic_batch **out);
+
+/* nsteps full steps of every member (push + deposit, sort, field advance):
+ * replays of the captured graph if pic_batch_capture() was called, else
+ * direct launches. */
+int pic_batch_step(pic_batch *b, int nsteps, hipStream_t stream);
+
+/* Capture one batched step into a HIP graph on `stream` (a non-null stream);
+ * later pic_batch_step() calls on any stream replay it.  Nothing runs here. */
+int pic_batch_capture(pic_batch *b, hipStream_t stream);
+
+/* Member i as a pic_sim for pic_diag / pic_get_tile_offsets / pic_check and
+ * the single-member calls; owned by the batch (do not pic_destroy it).
+ * NULL if i is out of range. */
+pic_sim *pic_batch_sim(pic_batch *b, int i);
+
+/* pic_check of every member; the first error found. */
+int pic_batch_check(pic_batch *b, hipStream_t stream);
+
+/* Free the batch's host record, its graph and its members' host records. */
+void pic_batch_destroy(pic_batch *b);
+
 /* Static string naming a return code. */
 const char *pic_strerror(int code);
 

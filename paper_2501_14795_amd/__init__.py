@@ -7,6 +7,6 @@ declared in ``include/pic.h``); this package is a thin ctypes binding
 """
 from . import _lib
 from ._lib import PicError
-from .sim import Sim, pack_cells, unpack_cells
+from .sim import Batch, BatchMember, Sim, pack_cells, unpack_cells
 
-__all__ = ["Sim", "PicError", "pack_cells", "unpack_cells", "_lib"]
+__all__ = ["Sim", "Batch", "BatchMember", "PicError", "pack_cells", "unpack_cells", "_lib"]

@@ -35,6 +35,8 @@ KERNELS = ["push", "j_reduce", "sort_scan", "sort_plan", "sort_scatter", "field"
 EXPORTS = [
     "pic_query", "pic_init", "pic_push_deposit", "pic_sort", "pic_field_advance", "pic_step",
     "pic_check", "pic_diag", "pic_get_tile_offsets", "pic_set_timing", "pic_get_timing",
+    "pic_batch_query", "pic_batch_init", "pic_batch_step", "pic_batch_capture", "pic_batch_sim",
+    "pic_batch_check", "pic_batch_destroy",
     "pic_strerror", "pic_destroy",
 ]
 
@@ -113,8 +115,17 @@ def load(path: str = SO_PATH):
     L.pic_strerror.restype = ctypes.c_char_p
     L.pic_destroy.argtypes = [vp]
     L.pic_destroy.restype = None
+    L.pic_batch_query.argtypes = [ctypes.c_int, P(pic_config), P(ctypes.c_size_t)]
+    L.pic_batch_init.argtypes = [ctypes.c_int, P(pic_config), P(pic_buffers), vp, ctypes.c_size_t, vp, P(vp)]
+    L.pic_batch_step.argtypes = [vp, ctypes.c_int, vp]
+    L.pic_batch_capture.argtypes = [vp, vp]
+    L.pic_batch_sim.argtypes = [vp, ctypes.c_int]
+    L.pic_batch_sim.restype = vp
+    L.pic_batch_check.argtypes = [vp, vp]
+    L.pic_batch_destroy.argtypes = [vp]
+    L.pic_batch_destroy.restype = None
     for name in EXPORTS:
-        if name not in ("pic_strerror", "pic_destroy"):
+        if name not in ("pic_strerror", "pic_destroy", "pic_batch_sim", "pic_batch_destroy"):
             getattr(L, name).restype = ctypes.c_int
     _L = L
     return L
@@ -192,3 +203,42 @@ def pic_get_timing(sim: int) -> pic_timing_out:
 
 def pic_destroy(sim: int):
     load().pic_destroy(ctypes.c_void_p(sim))
+
+
+def pic_batch_query(cfgs) -> int:
+    arr = (pic_config * len(cfgs))(*cfgs)
+    out = ctypes.c_size_t()
+    _chk(load().pic_batch_query(len(cfgs), arr, ctypes.byref(out)), "pic_batch_query")
+    return out.value
+
+
+def pic_batch_init(cfgs, bufs, work: int, work_bytes: int, stream: int) -> int:
+    ca = (pic_config * len(cfgs))(*cfgs)
+    ba = (pic_buffers * len(bufs))(*bufs)
+    h = ctypes.c_void_p()
+    _chk(load().pic_batch_init(len(cfgs), ca, ba, ctypes.c_void_p(work), work_bytes, ctypes.c_void_p(stream),
+                               ctypes.byref(h)), "pic_batch_init")
+    return h.value
+
+
+def pic_batch_step(batch: int, nsteps: int, stream: int):
+    _chk(load().pic_batch_step(ctypes.c_void_p(batch), nsteps, ctypes.c_void_p(stream)), "pic_batch_step")
+
+
+def pic_batch_capture(batch: int, stream: int):
+    _chk(load().pic_batch_capture(ctypes.c_void_p(batch), ctypes.c_void_p(stream)), "pic_batch_capture")
+
+
+def pic_batch_sim(batch: int, i: int) -> int:
+    h = load().pic_batch_sim(ctypes.c_void_p(batch), i)
+    if not h:
+        raise PicError(PIC_EINVAL, "pic_batch_sim")
+    return h
+
+
+def pic_batch_check(batch: int, stream: int) -> int:
+    return load().pic_batch_check(ctypes.c_void_p(batch), ctypes.c_void_p(stream))
+
+
+def pic_batch_destroy(batch: int):
+    load().pic_batch_destroy(ctypes.c_void_p(batch))

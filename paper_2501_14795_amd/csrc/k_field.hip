@@ -6,12 +6,14 @@
 
 namespace pic {
 
-// Faraday: B -= h curl E, with hdx = h/dx, hdy = h/dy.
-__global__ void __launch_bounds__(256) k_yee_b(float *__restrict__ f, int nx, int ny, float hdx, float hdy)
+// Faraday: B -= h curl E for one 64 x 4 block of cells (hdx = h/dx, hdy = h/dy).
+__device__ __forceinline__ void yee_b_block(const FieldArgs &a, int bx, int by)
 {
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int i = bx * 64 + (threadIdx.x & 63);
+    const int j = by * 4 + (threadIdx.x >> 6);
+    const int nx = a.nx, ny = a.ny;
     if (i >= nx || j >= ny) return;
+    float *__restrict__ f = a.fld;
     const int64_t P = (int64_t)nx * ny;
     const int64_t k = (int64_t)j * nx + i;
     const int64_t kx = (int64_t)j * nx + (i + 1 == nx ? 0 : i + 1);
@@ -19,18 +21,19 @@ __global__ void __launch_bounds__(256) k_yee_b(float *__restrict__ f, int nx, in
     const float *Ex = f, *Ey = f + P, *Ez = f + 2 * P;
     float *Bx = f + 3 * P, *By = f + 4 * P, *Bz = f + 5 * P;
     const float ez = Ez[k];
-    Bx[k] -= hdy * (Ez[ky] - ez);
-    By[k] += hdx * (Ez[kx] - ez);
-    Bz[k] -= hdx * (Ey[kx] - Ey[k]) - hdy * (Ex[ky] - Ex[k]);
+    Bx[k] -= a.hdy * (Ez[ky] - ez);
+    By[k] += a.hdx * (Ez[kx] - ez);
+    Bz[k] -= a.hdx * (Ey[kx] - Ey[k]) - a.hdy * (Ex[ky] - Ex[k]);
 }
 
-// Ampere: E += dt (curl B - J), with dtdx = dt/dx, dtdy = dt/dy.
-__global__ void __launch_bounds__(256) k_yee_e(float *__restrict__ f, int nx, int ny, float dt, float dtdx,
-                                               float dtdy)
+// Ampere: E += dt (curl B - J) for one 64 x 4 block of cells.
+__device__ __forceinline__ void yee_e_block(const FieldArgs &a, int bx, int by)
 {
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int i = bx * 64 + (threadIdx.x & 63);
+    const int j = by * 4 + (threadIdx.x >> 6);
+    const int nx = a.nx, ny = a.ny;
     if (i >= nx || j >= ny) return;
+    float *__restrict__ f = a.fld;
     const int64_t P = (int64_t)nx * ny;
     const int64_t k = (int64_t)j * nx + i;
     const int64_t kx = (int64_t)j * nx + (i == 0 ? nx - 1 : i - 1);
@@ -39,20 +42,40 @@ __global__ void __launch_bounds__(256) k_yee_e(float *__restrict__ f, int nx, in
     const float *Bx = f + 3 * P, *By = f + 4 * P, *Bz = f + 5 * P;
     const float *Jx = f + 6 * P, *Jy = f + 7 * P, *Jz = f + 8 * P;
     const float bz = Bz[k];
-    Ex[k] += dtdy * (bz - Bz[ky]) - dt * Jx[k];
-    Ey[k] += -dtdx * (bz - Bz[kx]) - dt * Jy[k];
-    Ez[k] += dtdx * (By[k] - By[kx]) - dtdy * (Bx[k] - Bx[ky]) - dt * Jz[k];
+    Ex[k] += a.dtdy * (bz - Bz[ky]) - a.dt * Jx[k];
+    Ey[k] += -a.dtdx * (bz - Bz[kx]) - a.dt * Jy[k];
+    Ez[k] += a.dtdx * (By[k] - By[kx]) - a.dtdy * (Bx[k] - Bx[ky]) - a.dt * Jz[k];
 }
 
-void launch_yee_b(float *fld, int nx, int ny, float hdx, float hdy, hipStream_t s)
+__global__ void __launch_bounds__(256) k_yee_b(FieldArgs a) { yee_b_block(a, blockIdx.x, blockIdx.y); }
+__global__ void __launch_bounds__(256) k_yee_e(FieldArgs a) { yee_e_block(a, blockIdx.x, blockIdx.y); }
+
+// many simulations: items = (simulation, bx, by)
+__global__ void __launch_bounds__(256) k_yee_b_b(const FieldArgs *d, const int4 *it)
 {
-    hipLaunchKernelGGL(k_yee_b, dim3((nx + 63) / 64, (ny + 3) / 4), dim3(256), 0, s, fld, nx, ny, hdx, hdy);
+    const int4 w = it[blockIdx.x];
+    yee_b_block(d[w.x], w.y, w.z);
+}
+__global__ void __launch_bounds__(256) k_yee_e_b(const FieldArgs *d, const int4 *it)
+{
+    const int4 w = it[blockIdx.x];
+    yee_e_block(d[w.x], w.y, w.z);
 }
 
-void launch_yee_e(float *fld, int nx, int ny, float dt, float dtdx, float dtdy, hipStream_t s)
+void launch_field_advance(const FieldArgs &f, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_yee_e, dim3((nx + 63) / 64, (ny + 3) / 4), dim3(256), 0, s, fld, nx, ny, dt, dtdx,
-                       dtdy);
+    const dim3 grid((f.nx + 63) / 64, (f.ny + 3) / 4);
+    hipLaunchKernelGGL(k_yee_b, grid, dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_yee_e, grid, dim3(256), 0, s, f);
+    hipLaunchKernelGGL(k_yee_b, grid, dim3(256), 0, s, f);
+}
+
+void launch_field_advance_batch(const FieldArgs *descs, const int4 *items, int n_items, hipStream_t s)
+{
+    if (n_items == 0) return;
+    hipLaunchKernelGGL(k_yee_b_b, dim3(n_items), dim3(256), 0, s, descs, items);
+    hipLaunchKernelGGL(k_yee_e_b, dim3(n_items), dim3(256), 0, s, descs, items);
+    hipLaunchKernelGGL(k_yee_b_b, dim3(n_items), dim3(256), 0, s, descs, items);
 }
 
 }  // namespace pic

@@ -149,8 +149,9 @@ __device__ __forceinline__ void flush_leavers(const SpeciesDev &sp, uint32_t (*l
     __builtin_amdgcn_wave_barrier();
 }
 
+// One tile of one simulation, by the whole 256-thread workgroup.
 template <int T, int R, int JM>
-__global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
+__device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
 {
     constexpr int NE = T + 2;   // staged E/B cells per axis: relative -1..T
     constexpr int NJ = T + 3;   // current halo nodes per axis: relative -1..T+1
@@ -168,7 +169,6 @@ __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
     __shared__ int s_wl[kMaxSpecies][kWaves];
     __shared__ uint32_t s_lb[kWaves][7][kLeaverBuf];   // leaver entry + new particle data
 
-    const int tile = blockIdx.x;
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int gx0 = tx * T, gy0 = ty * T;
     const int tid = threadIdx.x;
@@ -426,17 +426,45 @@ __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
     }
 }
 
+template <int T, int R, int JM>
+__global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
+{
+    push_tile<T, R, JM>(a, blockIdx.x);
+}
+
+// Many simulations in one launch: a persistent grid takes (simulation, tile)
+// items from a shared counter (the items come largest simulations first, so
+// the expensive tiles start early and the cheap ones fill the tail).
+template <int T, int R, int JM>
+__global__ void __launch_bounds__(kBlock) k_push_batch(const PushArgs *__restrict__ descs,
+                                                       const int4 *__restrict__ items, int n_items, int *counter)
+{
+    __shared__ int s_item;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (it >= n_items) break;
+        const int4 w = items[it];
+        push_tile<T, R, JM>(descs[w.x], w.y);
+        __syncthreads();
+    }
+}
+
 // J[c][gy][gx] = sum over the tiles whose halo (relative -1..T+1) covers the
 // node, in fixed (ty, tx) order with compensation -- the periodic fold of
-// update_gc_add.
+// update_gc_add.  One 64 x 4 block of nodes.
 template <int T>
-__global__ void __launch_bounds__(256) k_j_reduce(const float *__restrict__ jtile, float *__restrict__ J,
-                                                  int nx, int ny, int ntx, int nty)
+__device__ __forceinline__ void j_reduce_block(const JReduceArgs &r, int bxb, int byb)
 {
     constexpr int NJ = T + 3;
     constexpr int JP = NJ * NJ;
-    const int gx = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int gy = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const float *__restrict__ jtile = r.jtile;
+    float *__restrict__ J = r.J;
+    const int nx = r.nx, ny = r.ny, ntx = r.ntx, nty = r.nty;
+    const int gx = bxb * 64 + (threadIdx.x & 63);
+    const int gy = byb * 4 + (threadIdx.x >> 6);
     if (gx >= nx || gy >= ny) return;
     const int bx = gx / T, by = gy / T;
     float sum[3] = {0.0f, 0.0f, 0.0f}, cmp[3] = {0.0f, 0.0f, 0.0f};
@@ -464,6 +492,21 @@ __global__ void __launch_bounds__(256) k_j_reduce(const float *__restrict__ jtil
     J[k] = sum[0] + cmp[0];
     J[plane + k] = sum[1] + cmp[1];
     J[2 * plane + k] = sum[2] + cmp[2];
+}
+
+template <int T>
+__global__ void __launch_bounds__(256) k_j_reduce(JReduceArgs r)
+{
+    j_reduce_block<T>(r, blockIdx.x, blockIdx.y);
+}
+
+// node blocks of many simulations: items = (simulation, bx, by)
+template <int T>
+__global__ void __launch_bounds__(256) k_j_reduce_batch(const JReduceArgs *__restrict__ descs,
+                                                        const int4 *__restrict__ items)
+{
+    const int4 w = items[blockIdx.x];
+    j_reduce_block<T>(descs[w.x], w.y, w.z);
 }
 
 template <int T, int R, int JM>
@@ -501,15 +544,68 @@ void launch_push_deposit(int tile, int replicas, int jmode, const PushArgs &a, i
     }
 }
 
-void launch_j_reduce(int tile, const float *jtile, float *J, int nx, int ny, int ntx, int nty,
-                     hipStream_t s)
+void launch_j_reduce(int tile, const JReduceArgs &r, hipStream_t s)
 {
-    dim3 grid((nx + 63) / 64, (ny + 3) / 4);
+    dim3 grid((r.nx + 63) / 64, (r.ny + 3) / 4);
     switch (tile) {
-    case 8: hipLaunchKernelGGL((k_j_reduce<8>), grid, dim3(256), 0, s, jtile, J, nx, ny, ntx, nty); break;
-    case 16: hipLaunchKernelGGL((k_j_reduce<16>), grid, dim3(256), 0, s, jtile, J, nx, ny, ntx, nty); break;
-    default: hipLaunchKernelGGL((k_j_reduce<32>), grid, dim3(256), 0, s, jtile, J, nx, ny, ntx, nty); break;
+    case 8: hipLaunchKernelGGL((k_j_reduce<8>), grid, dim3(256), 0, s, r); break;
+    case 16: hipLaunchKernelGGL((k_j_reduce<16>), grid, dim3(256), 0, s, r); break;
+    default: hipLaunchKernelGGL((k_j_reduce<32>), grid, dim3(256), 0, s, r); break;
     }
+}
+
+template <int T, int R, int JM>
+static void launch_pb(const PushArgs *descs, const int4 *items, int n_items, int *counter, int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_push_batch<T, R, JM>), dim3(grid), dim3(kBlock), 0, s, descs, items, n_items, counter);
+}
+
+template <int T, int JM>
+static void launch_pb_r(int replicas, const PushArgs *descs, const int4 *items, int n_items, int *counter,
+                        int grid, hipStream_t s)
+{
+    switch (replicas) {
+    case 1: launch_pb<T, 1, JM>(descs, items, n_items, counter, grid, s); break;
+    case 2: launch_pb<T, 2, JM>(descs, items, n_items, counter, grid, s); break;
+    default:
+        if constexpr (push_lds_bytes(T, 4, JM) <= kLdsBytes) launch_pb<T, 4, JM>(descs, items, n_items, counter, grid, s);
+        break;
+    }
+}
+
+template <int T>
+static void launch_pb_j(int replicas, int jmode, const PushArgs *descs, const int4 *items, int n_items,
+                        int *counter, int grid, hipStream_t s)
+{
+    if (jmode == kJFloat) launch_pb_r<T, kJFloat>(replicas, descs, items, n_items, counter, grid, s);
+    else launch_pb_r<T, kJFixed>(replicas, descs, items, n_items, counter, grid, s);
+}
+
+void launch_push_batch(int tile, int replicas, int jmode, const PushArgs *descs, const int4 *items, int n_items,
+                       int *counter, int grid, hipStream_t s)
+{
+    switch (tile) {
+    case 8: launch_pb_j<8>(replicas, jmode, descs, items, n_items, counter, grid, s); break;
+    case 16: launch_pb_j<16>(replicas, jmode, descs, items, n_items, counter, grid, s); break;
+    default: launch_pb_j<32>(replicas, jmode, descs, items, n_items, counter, grid, s); break;
+    }
+}
+
+void launch_j_reduce_batch(int tile, const JReduceArgs *descs, const int4 *items, int n_items, hipStream_t s)
+{
+    if (n_items == 0) return;
+    switch (tile) {
+    case 8: hipLaunchKernelGGL((k_j_reduce_batch<8>), dim3(n_items), dim3(256), 0, s, descs, items); break;
+    case 16: hipLaunchKernelGGL((k_j_reduce_batch<16>), dim3(n_items), dim3(256), 0, s, descs, items); break;
+    default: hipLaunchKernelGGL((k_j_reduce_batch<32>), dim3(n_items), dim3(256), 0, s, descs, items); break;
+    }
+}
+
+__global__ void k_set_int(int *p, int v) { *p = v; }
+
+void launch_set_int(int *p, int v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, p, v);
 }
 
 }  // namespace pic

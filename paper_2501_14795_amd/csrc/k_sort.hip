@@ -73,10 +73,11 @@ __device__ __forceinline__ int tile_count_in(const int32_t *cnt, int t, int ntx,
 
 // Step (1), first pass: new count of every tile and its exclusive prefix
 // within its block of kScanBlock tiles; block totals to bsum.
-__global__ void __launch_bounds__(kScanBlock) k_sort_count(SortArgs a, int n_tiles)
+__device__ __forceinline__ void sort_count_unit(const SortArgs &a, int spi, int blk)
 {
-    const SortSpecies &sp = a.sp[blockIdx.y];
-    const int t = blockIdx.x * kScanBlock + threadIdx.x;
+    const SortSpecies &sp = a.sp[spi];
+    const int n_tiles = a.n_tiles;
+    const int t = blk * kScanBlock + threadIdx.x;
     const int c = t < n_tiles ? tile_count_in(sp.cnt, t, a.ntx, a.nty) : 0;
     // block exclusive scan (kScanBlock = 256: four wavefronts)
     __shared__ int s_w[kScanBlock / 64];
@@ -92,14 +93,15 @@ __global__ void __launch_bounds__(kScanBlock) k_sort_count(SortArgs a, int n_til
     int base = 0;
     for (int k = 0; k < w; ++k) base += s_w[k];
     if (t < n_tiles) sp.offn[t] = base + x - c;
-    if (threadIdx.x == kScanBlock - 1) sp.bsum[blockIdx.x] = base + x;
+    if (threadIdx.x == kScanBlock - 1) sp.bsum[blk] = base + x;
 }
 
 // Step (1), second pass (one block per species): exclusive scan of the block
 // totals in place; tile_offset'[n_tiles] = total, checked against n.
-__global__ void __launch_bounds__(1024) k_sort_scan_blocks(SortArgs a, int n_tiles)
+__device__ __forceinline__ void sort_scan_unit(const SortArgs &a, int spi)
 {
-    const SortSpecies &sp = a.sp[blockIdx.x];
+    const SortSpecies &sp = a.sp[spi];
+    const int n_tiles = a.n_tiles;
     const int nb = (n_tiles + kScanBlock - 1) / kScanBlock;
     int carry = 0;
     for (int b0 = 0; b0 < nb; b0 += 1024) {
@@ -118,11 +120,11 @@ __global__ void __launch_bounds__(1024) k_sort_scan_blocks(SortArgs a, int n_til
 }
 
 // Step (1), third pass: add each block's base.
-__global__ void __launch_bounds__(kScanBlock) k_sort_add_base(SortArgs a, int n_tiles)
+__device__ __forceinline__ void sort_add_unit(const SortArgs &a, int spi, int blk)
 {
-    const SortSpecies &sp = a.sp[blockIdx.y];
-    const int t = blockIdx.x * kScanBlock + threadIdx.x;
-    if (t < n_tiles) sp.offn[t] += sp.bsum[blockIdx.x];
+    const SortSpecies &sp = a.sp[spi];
+    const int t = blk * kScanBlock + threadIdx.x;
+    if (t < a.n_tiles) sp.offn[t] += sp.bsum[blk];
 }
 
 // Slot of the list holding flat index k, over the lists described by lanes
@@ -177,12 +179,12 @@ __device__ __forceinline__ void copy_particle(const Parts &src, int64_t i, const
 //                 s != t: s's four leaver sub-lists, entries heading to t whose
 //                         slot is outside [A, B); data from the leaver copy
 //                 s == t: t's slots outside [A, B) whose particle kept tile t
-__global__ void __launch_bounds__(kBlock) k_sort_plan(SortArgs a, int n_tiles)
+__device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int grp)
 {
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (t >= n_tiles) return;   // whole wavefront
-    const SortSpecies &sp = a.sp[blockIdx.y];
+    const int t = grp * kWaves + (threadIdx.x >> 6);
+    if (t >= a.n_tiles) return;   // whole wavefront
+    const SortSpecies &sp = a.sp[spi];
     const int ntx = a.ntx, nty = a.nty;
     const int tsh = __builtin_ctz(a.tile);
     const int A = sp.offn[t], B = sp.offn[t + 1];
@@ -323,18 +325,57 @@ __global__ void __launch_bounds__(kBlock) k_sort_plan(SortArgs a, int n_tiles)
     }
 }
 
-// Step (5): the k-th hole of each tile receives the k-th mover.
-__global__ void __launch_bounds__(kBlock) k_sort_scatter(SortArgs a, int n_tiles)
+// Step (5): the k-th hole of each tile receives the k-th mover; the new
+// tile_offset replaces the old one (all plans have read the old one).
+__device__ __forceinline__ void sort_scatter_unit(const SortArgs &a, int spi, int grp)
 {
     const int lane = threadIdx.x & 63;
-    const int t = blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (t >= n_tiles) return;
-    const SortSpecies &sp = a.sp[blockIdx.y];
+    const int t = grp * kWaves + (threadIdx.x >> 6);
+    if (t >= a.n_tiles) return;
+    const SortSpecies &sp = a.sp[spi];
     const int A = sp.offn[t], m = sp.mcount[t];
     for (int k = lane; k < m; k += 64) {
         const int64_t r = (int64_t)A + k;
         copy_particle(sp.stg, r, sp.p, sp.hole[r]);
     }
+    if (lane == 0) {
+        sp.off[t] = A;
+        if (t == a.n_tiles - 1) sp.off[t + 1] = sp.offn[t + 1];
+    }
+}
+
+// ---- single-simulation kernels: blockIdx.y = species
+__global__ void __launch_bounds__(kScanBlock) k_sort_count(SortArgs a) { sort_count_unit(a, blockIdx.y, blockIdx.x); }
+__global__ void __launch_bounds__(1024) k_sort_scan_blocks(SortArgs a) { sort_scan_unit(a, blockIdx.x); }
+__global__ void __launch_bounds__(kScanBlock) k_sort_add_base(SortArgs a) { sort_add_unit(a, blockIdx.y, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_sort_plan(SortArgs a) { sort_plan_unit(a, blockIdx.y, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_sort_scatter(SortArgs a) { sort_scatter_unit(a, blockIdx.y, blockIdx.x); }
+
+// ---- many simulations: one block per work item (sim, species, unit)
+__global__ void __launch_bounds__(kScanBlock) k_sort_count_b(const SortArgs *d, const int4 *it)
+{
+    const int4 w = it[blockIdx.x];
+    sort_count_unit(d[w.x], w.y, w.z);
+}
+__global__ void __launch_bounds__(1024) k_sort_scan_blocks_b(const SortArgs *d, const int4 *it)
+{
+    const int4 w = it[blockIdx.x];
+    sort_scan_unit(d[w.x], w.y);
+}
+__global__ void __launch_bounds__(kScanBlock) k_sort_add_base_b(const SortArgs *d, const int4 *it)
+{
+    const int4 w = it[blockIdx.x];
+    sort_add_unit(d[w.x], w.y, w.z);
+}
+__global__ void __launch_bounds__(kBlock) k_sort_plan_b(const SortArgs *d, const int4 *it)
+{
+    const int4 w = it[blockIdx.x];
+    sort_plan_unit(d[w.x], w.y, w.z);
+}
+__global__ void __launch_bounds__(kBlock) k_sort_scatter_b(const SortArgs *d, const int4 *it)
+{
+    const int4 w = it[blockIdx.x];
+    sort_scatter_unit(d[w.x], w.y, w.z);
 }
 
 // ---- initial tile_offset from caller particles that are grouped by tile
@@ -379,23 +420,30 @@ __global__ void __launch_bounds__(1024) k_init_scan(const int32_t *counts, int n
 
 void launch_sort_scan(const SortArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sort_count, dim3((n_tiles + kScanBlock - 1) / kScanBlock, a.n_species), dim3(kScanBlock),
-                       0, s, a, n_tiles);
-    hipLaunchKernelGGL(k_sort_scan_blocks, dim3(a.n_species), dim3(1024), 0, s, a, n_tiles);
-    hipLaunchKernelGGL(k_sort_add_base, dim3((n_tiles + kScanBlock - 1) / kScanBlock, a.n_species),
-                       dim3(kScanBlock), 0, s, a, n_tiles);
+    const int nb = (n_tiles + kScanBlock - 1) / kScanBlock;
+    hipLaunchKernelGGL(k_sort_count, dim3(nb, a.n_species), dim3(kScanBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sort_scan_blocks, dim3(a.n_species), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_sort_add_base, dim3(nb, a.n_species), dim3(kScanBlock), 0, s, a);
 }
 
 void launch_sort_plan(const SortArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sort_plan, dim3((n_tiles + kWaves - 1) / kWaves, a.n_species), dim3(kBlock), 0, s,
-                       a, n_tiles);
+    hipLaunchKernelGGL(k_sort_plan, dim3((n_tiles + kWaves - 1) / kWaves, a.n_species), dim3(kBlock), 0, s, a);
 }
 
 void launch_sort_scatter(const SortArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sort_scatter, dim3((n_tiles + kWaves - 1) / kWaves, a.n_species), dim3(kBlock), 0,
-                       s, a, n_tiles);
+    hipLaunchKernelGGL(k_sort_scatter, dim3((n_tiles + kWaves - 1) / kWaves, a.n_species), dim3(kBlock), 0, s, a);
+}
+
+void launch_sort_batch(const SortBatch &b, hipStream_t s)
+{
+    if (b.n_count == 0) return;
+    hipLaunchKernelGGL(k_sort_count_b, dim3(b.n_count), dim3(kScanBlock), 0, s, b.descs, b.count_items);
+    hipLaunchKernelGGL(k_sort_scan_blocks_b, dim3(b.n_scan), dim3(1024), 0, s, b.descs, b.scan_items);
+    hipLaunchKernelGGL(k_sort_add_base_b, dim3(b.n_count), dim3(kScanBlock), 0, s, b.descs, b.count_items);
+    hipLaunchKernelGGL(k_sort_plan_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
+    hipLaunchKernelGGL(k_sort_scatter_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
 }
 
 void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile, int ntx, int32_t *counts,

@@ -107,8 +107,8 @@ struct pic_sim {
     double *rho_prev, *rho_now;
     bool have_snapshot;
     struct Sp {
-        int32_t *off[2];
-        int cur;
+        int32_t *off;    // current tile_offset
+        int32_t *offn;   // the sort's new tile_offset (scratch, copied into off)
         int32_t *cnt;
         uint32_t *leav;
         int32_t *hole;
@@ -199,6 +199,116 @@ DiagSpecies diag_species(const pic_sim *s, int k)
     return d;
 }
 
+// Kernel arguments of one simulation (identical every step: the sort writes
+// the new tile_offset in place).
+PushArgs push_args(const pic_sim *S)
+{
+    const pic_config &c = S->cfg;
+    PushArgs a;
+    memset(&a, 0, sizeof(a));
+    a.fld = S->buf.fields;
+    a.jtile = S->jtile;
+    a.err = S->err;
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.ntx = S->ntx;
+    a.nty = S->nty;
+    a.cx = (float)(c.dt / c.dx);
+    a.cy = (float)(c.dt / c.dy);
+    // accumulator units: the largest particle charge moving one cell (Jx, Jy)
+    // or at the speed of light (Jz) is 1 (x 2^24 in fixed point)
+    double qmax = 0.0;
+    for (int s = 0; s < c.n_species; ++s) qmax = std::max(qmax, fabs(c.species[s].q));
+    if (qmax == 0.0) qmax = 1.0;
+    const double scale = j_mode(&c) == kJFixed ? (double)kFixedScale : 1.0;
+    a.ju[0] = (float)(qmax * c.dx / c.dt / scale);
+    a.ju[1] = (float)(qmax * c.dy / c.dt / scale);
+    a.ju[2] = (float)(qmax / scale);
+    a.n_species = c.n_species;
+    for (int s = 0; s < c.n_species; ++s) {
+        const pic_particles &p = S->buf.sp[s];
+        SpeciesDev &d = a.sp[s];
+        d.cell = p.cell;
+        d.x = p.x;
+        d.y = p.y;
+        d.ux = p.ux;
+        d.uy = p.uy;
+        d.uz = p.uz;
+        d.off = S->sp[s].off;
+        d.cnt = S->sp[s].cnt;
+        d.leav = S->sp[s].leav;
+        d.lp = S->sp[s].lp;
+        d.n = (int32_t)c.species[s].n;
+        d.h = (float)(0.5 * c.species[s].qm * c.dt);
+        d.fq = (float)(scale * c.species[s].q / qmax);
+    }
+    return a;
+}
+
+JReduceArgs jreduce_args(const pic_sim *S)
+{
+    JReduceArgs r;
+    r.jtile = S->jtile;
+    r.J = S->buf.fields + (int64_t)6 * S->cfg.nx * S->cfg.ny;
+    r.nx = S->cfg.nx;
+    r.ny = S->cfg.ny;
+    r.ntx = S->ntx;
+    r.nty = S->nty;
+    return r;
+}
+
+SortArgs sort_args(const pic_sim *S)
+{
+    const pic_config &c = S->cfg;
+    SortArgs a;
+    memset(&a, 0, sizeof(a));
+    a.err = S->err;
+    a.nx = c.nx;
+    a.ny = c.ny;
+    a.ntx = S->ntx;
+    a.nty = S->nty;
+    a.tile = S->tile;
+    a.n_tiles = S->n_tiles;
+    a.n_species = c.n_species;
+    for (int s = 0; s < c.n_species; ++s) {
+        const pic_particles &p = S->buf.sp[s];
+        const auto &P = S->sp[s];
+        SortSpecies &d = a.sp[s];
+        d.p.cell = p.cell;
+        d.p.x = p.x;
+        d.p.y = p.y;
+        d.p.ux = p.ux;
+        d.p.uy = p.uy;
+        d.p.uz = p.uz;
+        d.lp = P.lp;
+        d.stg = P.stg;
+        d.off = P.off;
+        d.offn = P.offn;
+        d.cnt = P.cnt;
+        d.leav = P.leav;
+        d.hole = P.hole;
+        d.mcount = P.mcount;
+        d.bsum = P.bsum;
+        d.n = (int32_t)c.species[s].n;
+    }
+    return a;
+}
+
+FieldArgs field_args(const pic_sim *S)
+{
+    const pic_config &c = S->cfg;
+    FieldArgs f;
+    f.fld = S->buf.fields;
+    f.nx = c.nx;
+    f.ny = c.ny;
+    f.hdx = (float)(0.5 * c.dt / c.dx);
+    f.hdy = (float)(0.5 * c.dt / c.dy);
+    f.dt = (float)c.dt;
+    f.dtdx = (float)(c.dt / c.dx);
+    f.dtdy = (float)(c.dt / c.dy);
+    return f;
+}
+
 }  // namespace
 
 extern "C" {
@@ -264,9 +374,8 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
     S->rho_now = (double *)(w + L.rho_now);
     for (int s = 0; s < cfg->n_species; ++s) {
         auto &P = S->sp[s];
-        P.off[0] = (int32_t *)(w + L.off[s][0]);
-        P.off[1] = (int32_t *)(w + L.off[s][1]);
-        P.cur = 0;
+        P.off = (int32_t *)(w + L.off[s][0]);
+        P.offn = (int32_t *)(w + L.off[s][1]);
         P.cnt = (int32_t *)(w + L.cnt[s]);
         P.leav = (uint32_t *)(w + L.leav[s]);
         P.hole = (int32_t *)(w + L.hole[s]);
@@ -293,7 +402,7 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
         rc = hip_ok(hipMemsetAsync(P.cnt, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
         if (rc) break;
         launch_init_tiles(bufs->sp[s].cell, (int32_t)cfg->species[s].n, cfg->nx, cfg->ny, cfg->tile, S->ntx,
-                          P.cnt, S->n_tiles, P.off[0], S->err, stream);
+                          P.cnt, S->n_tiles, P.off, S->err, stream);
         rc = hip_ok(hipMemsetAsync(P.mcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
     }
     if (rc == PIC_OK) rc = hip_ok(hipGetLastError());
@@ -309,54 +418,14 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
 int pic_push_deposit(pic_sim *S, hipStream_t stream)
 {
     if (!S) return PIC_EINVAL;
-    const pic_config &c = S->cfg;
-    PushArgs a;
-    memset(&a, 0, sizeof(a));
-    const int64_t plane = (int64_t)c.nx * c.ny;
-    a.fld = S->buf.fields;
-    a.jtile = S->jtile;
-    a.err = S->err;
-    a.nx = c.nx;
-    a.ny = c.ny;
-    a.ntx = S->ntx;
-    a.nty = S->nty;
-    a.cx = (float)(c.dt / c.dx);
-    a.cy = (float)(c.dt / c.dy);
-    // accumulator units: the largest particle charge moving one cell (Jx, Jy)
-    // or at the speed of light (Jz) is 1 (x 2^24 in fixed point)
-    double qmax = 0.0;
-    for (int s = 0; s < c.n_species; ++s) qmax = std::max(qmax, fabs(c.species[s].q));
-    if (qmax == 0.0) qmax = 1.0;
-    const int jm = j_mode(&c);
-    const double scale = jm == kJFixed ? (double)kFixedScale : 1.0;
-    a.ju[0] = (float)(qmax * c.dx / c.dt / scale);
-    a.ju[1] = (float)(qmax * c.dy / c.dt / scale);
-    a.ju[2] = (float)(qmax / scale);
-    a.n_species = c.n_species;
-    for (int s = 0; s < c.n_species; ++s) {
-        const pic_particles &p = S->buf.sp[s];
-        SpeciesDev &d = a.sp[s];
-        d.cell = p.cell;
-        d.x = p.x;
-        d.y = p.y;
-        d.ux = p.ux;
-        d.uy = p.uy;
-        d.uz = p.uz;
-        d.off = S->sp[s].off[S->sp[s].cur];
-        d.cnt = S->sp[s].cnt;
-        d.leav = S->sp[s].leav;
-        d.lp = S->sp[s].lp;
-        d.n = (int32_t)c.species[s].n;
-        d.h = (float)(0.5 * c.species[s].qm * c.dt);
-        d.fq = (float)(scale * c.species[s].q / qmax);
-    }
+    const PushArgs a = push_args(S);
     {
         Timed t(S, PIC_KERNEL_PUSH, stream);
-        launch_push_deposit(S->tile, S->replicas, jm, a, S->n_tiles, stream);
+        launch_push_deposit(S->tile, S->replicas, j_mode(&S->cfg), a, S->n_tiles, stream);
     }
     {
         Timed t(S, PIC_KERNEL_JREDUCE, stream);
-        launch_j_reduce(S->tile, S->jtile, S->buf.fields + 6 * plane, c.nx, c.ny, S->ntx, S->nty, stream);
+        launch_j_reduce(S->tile, jreduce_args(S), stream);
     }
     return hip_ok(hipGetLastError());
 }
@@ -364,37 +433,7 @@ int pic_push_deposit(pic_sim *S, hipStream_t stream)
 int pic_sort(pic_sim *S, hipStream_t stream)
 {
     if (!S) return PIC_EINVAL;
-    const pic_config &c = S->cfg;
-    SortArgs a;
-    memset(&a, 0, sizeof(a));
-    a.err = S->err;
-    a.nx = c.nx;
-    a.ny = c.ny;
-    a.ntx = S->ntx;
-    a.nty = S->nty;
-    a.tile = S->tile;
-    a.n_species = c.n_species;
-    for (int s = 0; s < c.n_species; ++s) {
-        const pic_particles &p = S->buf.sp[s];
-        auto &P = S->sp[s];
-        SortSpecies &d = a.sp[s];
-        d.p.cell = p.cell;
-        d.p.x = p.x;
-        d.p.y = p.y;
-        d.p.ux = p.ux;
-        d.p.uy = p.uy;
-        d.p.uz = p.uz;
-        d.lp = P.lp;
-        d.stg = P.stg;
-        d.off = P.off[P.cur];
-        d.offn = P.off[P.cur ^ 1];
-        d.cnt = P.cnt;
-        d.leav = P.leav;
-        d.hole = P.hole;
-        d.mcount = P.mcount;
-        d.bsum = P.bsum;
-        d.n = (int32_t)c.species[s].n;
-    }
+    const SortArgs a = sort_args(S);
     {
         Timed t(S, PIC_KERNEL_SORT_SCAN, stream);
         launch_sort_scan(a, S->n_tiles, stream);
@@ -407,18 +446,14 @@ int pic_sort(pic_sim *S, hipStream_t stream)
         Timed t(S, PIC_KERNEL_SORT_SCATTER, stream);
         launch_sort_scatter(a, S->n_tiles, stream);
     }
-    for (int s = 0; s < c.n_species; ++s) S->sp[s].cur ^= 1;
     return hip_ok(hipGetLastError());
 }
 
 int pic_field_advance(pic_sim *S, hipStream_t stream)
 {
     if (!S) return PIC_EINVAL;
-    const pic_config &c = S->cfg;
     Timed t(S, PIC_KERNEL_FIELD, stream);
-    launch_yee_b(S->buf.fields, c.nx, c.ny, (float)(0.5 * c.dt / c.dx), (float)(0.5 * c.dt / c.dy), stream);
-    launch_yee_e(S->buf.fields, c.nx, c.ny, (float)c.dt, (float)(c.dt / c.dx), (float)(c.dt / c.dy), stream);
-    launch_yee_b(S->buf.fields, c.nx, c.ny, (float)(0.5 * c.dt / c.dx), (float)(0.5 * c.dt / c.dy), stream);
+    launch_field_advance(field_args(S), stream);
     return hip_ok(hipGetLastError());
 }
 
@@ -500,7 +535,7 @@ int pic_get_tile_offsets(pic_sim *S, int species, int32_t *host_out, hipStream_t
 {
     if (!S || !host_out || species < 0 || species >= S->cfg.n_species) return PIC_EINVAL;
     const auto &P = S->sp[species];
-    int rc = hip_ok(hipMemcpyAsync(host_out, P.off[P.cur], (size_t)(S->n_tiles + 1) * sizeof(int32_t),
+    int rc = hip_ok(hipMemcpyAsync(host_out, P.off, (size_t)(S->n_tiles + 1) * sizeof(int32_t),
                                    hipMemcpyDeviceToHost, stream));
     if (rc == PIC_OK) rc = hip_ok(hipStreamSynchronize(stream));
     return rc;
@@ -555,6 +590,275 @@ void pic_destroy(pic_sim *S)
         }
     for (hipEvent_t e : S->pool) (void)hipEventDestroy(e);
     delete S;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// batched mode
+// ---------------------------------------------------------------------------
+
+struct pic_batch {
+    std::vector<pic_sim *> sims;
+    int tile, replicas, jm;
+    int cus;
+    char *dev;
+    // device tables
+    PushArgs *d_push;
+    JReduceArgs *d_jr;
+    SortArgs *d_sort;
+    FieldArgs *d_field;
+    int4 *push_items, *node_items, *count_items, *scan_items, *plan_items;
+    int n_push, n_node, n_count, n_scan, n_plan;
+    int *counter;
+    int push_grid;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t d_push, d_jr, d_sort, d_field, push_items, node_items, count_items, scan_items, plan_items, counter, total;
+    int n_push, n_node, n_count, n_scan, n_plan;
+};
+
+int batch_validate(int n, const pic_config *cfgs)
+{
+    if (n < 1 || !cfgs) return PIC_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        const int rc = validate(&cfgs[i]);
+        if (rc) return rc;
+        if (cfgs[i].tile != cfgs[0].tile || cfgs[i].flags != cfgs[0].flags ||
+            cfgs[i].j_replicas != cfgs[0].j_replicas)
+            return PIC_EINVAL;
+    }
+    return PIC_OK;
+}
+
+BatchLayout batch_layout(int n, const pic_config *cfgs)
+{
+    BatchLayout L;
+    L.n_push = L.n_node = L.n_count = L.n_scan = L.n_plan = 0;
+    for (int i = 0; i < n; ++i) {
+        const pic_config &c = cfgs[i];
+        const int nt = (c.nx / c.tile) * (c.ny / c.tile);
+        L.n_push += nt;
+        L.n_node += ((c.nx + 63) / 64) * ((c.ny + 3) / 4);
+        L.n_count += c.n_species * ((nt + kScanBlock - 1) / kScanBlock);
+        L.n_scan += c.n_species;
+        L.n_plan += c.n_species * ((nt + kWaves - 1) / kWaves);
+    }
+    size_t p = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = p;
+        p = align_up(p + std::max<size_t>(bytes, 1));
+        return at;
+    };
+    L.d_push = take(n * sizeof(PushArgs));
+    L.d_jr = take(n * sizeof(JReduceArgs));
+    L.d_sort = take(n * sizeof(SortArgs));
+    L.d_field = take(n * sizeof(FieldArgs));
+    L.push_items = take(L.n_push * sizeof(int4));
+    L.node_items = take(L.n_node * sizeof(int4));
+    L.count_items = take(L.n_count * sizeof(int4));
+    L.scan_items = take(L.n_scan * sizeof(int4));
+    L.plan_items = take(L.n_plan * sizeof(int4));
+    L.counter = take(64);
+    L.total = p;
+    return L;
+}
+
+void batch_enqueue_step(pic_batch *b, hipStream_t stream)
+{
+    launch_set_int(b->counter, 0, stream);
+    launch_push_batch(b->tile, b->replicas, b->jm, b->d_push, b->push_items, b->n_push, b->counter, b->push_grid,
+                      stream);
+    launch_j_reduce_batch(b->tile, b->d_jr, b->node_items, b->n_node, stream);
+    SortBatch sb;
+    sb.descs = b->d_sort;
+    sb.count_items = b->count_items;
+    sb.n_count = b->n_count;
+    sb.scan_items = b->scan_items;
+    sb.n_scan = b->n_scan;
+    sb.plan_items = b->plan_items;
+    sb.n_plan = b->n_plan;
+    launch_sort_batch(sb, stream);
+    launch_field_advance_batch(b->d_field, b->node_items, b->n_node, stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_batch_query(int n, const pic_config *cfgs, size_t *bytes)
+{
+    if (!bytes) return PIC_EINVAL;
+    const int rc = batch_validate(n, cfgs);
+    if (rc) return rc;
+    *bytes = batch_layout(n, cfgs).total;
+    return PIC_OK;
+}
+
+int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void *batch_work, size_t batch_bytes,
+                   hipStream_t stream, pic_batch **out)
+{
+    if (!out || !bufs) return PIC_EINVAL;
+    *out = nullptr;
+    int rc = batch_validate(n, cfgs);
+    if (rc) return rc;
+    const BatchLayout L = batch_layout(n, cfgs);
+    if (!batch_work || batch_bytes < L.total || ((uintptr_t)batch_work) % kAlign) return PIC_EINVAL;
+
+    pic_batch *B = new (std::nothrow) pic_batch();
+    if (!B) return PIC_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        pic_sim *S = nullptr;
+        rc = pic_init(&cfgs[i], &bufs[i], stream, &S);
+        if (rc) {
+            pic_batch_destroy(B);
+            return rc;
+        }
+        B->sims.push_back(S);
+    }
+    B->tile = cfgs[0].tile;
+    B->jm = j_mode(&cfgs[0]);
+    B->replicas = cfgs[0].j_replicas ? cfgs[0].j_replicas : default_replicas(&cfgs[0]);
+    char *d = (char *)batch_work;
+    B->dev = d;
+    B->d_push = (PushArgs *)(d + L.d_push);
+    B->d_jr = (JReduceArgs *)(d + L.d_jr);
+    B->d_sort = (SortArgs *)(d + L.d_sort);
+    B->d_field = (FieldArgs *)(d + L.d_field);
+    B->push_items = (int4 *)(d + L.push_items);
+    B->node_items = (int4 *)(d + L.node_items);
+    B->count_items = (int4 *)(d + L.count_items);
+    B->scan_items = (int4 *)(d + L.scan_items);
+    B->plan_items = (int4 *)(d + L.plan_items);
+    B->counter = (int *)(d + L.counter);
+    B->n_push = L.n_push;
+    B->n_node = L.n_node;
+    B->n_count = L.n_count;
+    B->n_scan = L.n_scan;
+    B->n_plan = L.n_plan;
+
+    // host images of the descriptors and work tables
+    std::vector<PushArgs> hp(n);
+    std::vector<JReduceArgs> hj(n);
+    std::vector<SortArgs> hs(n);
+    std::vector<FieldArgs> hf(n);
+    std::vector<int4> push_items, node_items, count_items, scan_items, plan_items;
+    std::vector<std::pair<double, int>> cost(n);
+    for (int i = 0; i < n; ++i) {
+        const pic_sim *S = B->sims[i];
+        hp[i] = push_args(S);
+        hj[i] = jreduce_args(S);
+        hs[i] = sort_args(S);
+        hf[i] = field_args(S);
+        int64_t np = 0;
+        for (int s = 0; s < S->cfg.n_species; ++s) np += S->cfg.species[s].n;
+        cost[i] = {-(double)np / S->n_tiles, i};   // particles per tile, largest first
+        for (int by = 0; by < (S->cfg.ny + 3) / 4; ++by)
+            for (int bx = 0; bx < (S->cfg.nx + 63) / 64; ++bx) node_items.push_back(make_int4(i, bx, by, 0));
+        for (int s = 0; s < S->cfg.n_species; ++s) {
+            for (int k = 0; k < (S->n_tiles + kScanBlock - 1) / kScanBlock; ++k)
+                count_items.push_back(make_int4(i, s, k, 0));
+            scan_items.push_back(make_int4(i, s, 0, 0));
+            for (int k = 0; k < (S->n_tiles + kWaves - 1) / kWaves; ++k) plan_items.push_back(make_int4(i, s, k, 0));
+        }
+    }
+    std::sort(cost.begin(), cost.end());
+    for (const auto &c : cost)
+        for (int t = 0; t < B->sims[c.second]->n_tiles; ++t) push_items.push_back(make_int4(c.second, t, 0, 0));
+
+    auto up = [&](void *dst, const void *src, size_t bytes) {
+        if (rc == PIC_OK && bytes) rc = hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream));
+    };
+    up(B->d_push, hp.data(), n * sizeof(PushArgs));
+    up(B->d_jr, hj.data(), n * sizeof(JReduceArgs));
+    up(B->d_sort, hs.data(), n * sizeof(SortArgs));
+    up(B->d_field, hf.data(), n * sizeof(FieldArgs));
+    up(B->push_items, push_items.data(), push_items.size() * sizeof(int4));
+    up(B->node_items, node_items.data(), node_items.size() * sizeof(int4));
+    up(B->count_items, count_items.data(), count_items.size() * sizeof(int4));
+    up(B->scan_items, scan_items.data(), scan_items.size() * sizeof(int4));
+    up(B->plan_items, plan_items.data(), plan_items.size() * sizeof(int4));
+    if (rc == PIC_OK) rc = hip_ok(hipStreamSynchronize(stream));
+
+    // persistent push grid: as many workgroups as fit on the device at once
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int per_cu = std::max(1, std::min(8, kLdsBytes / push_lds_bytes(B->tile, B->replicas, B->jm)));
+    B->cus = cus;
+    B->push_grid = std::max(1, std::min(B->n_push, cus * per_cu));
+    if (rc) {
+        pic_batch_destroy(B);
+        return rc;
+    }
+    *out = B;
+    return PIC_OK;
+}
+
+int pic_batch_step(pic_batch *B, int nsteps, hipStream_t stream)
+{
+    if (!B || nsteps < 0) return PIC_EINVAL;
+    for (int k = 0; k < nsteps; ++k) {
+        if (B->exec) {
+            if (hipGraphLaunch(B->exec, stream) != hipSuccess) return PIC_EHIP;
+        } else {
+            batch_enqueue_step(B, stream);
+        }
+    }
+    return hip_ok(hipGetLastError());
+}
+
+int pic_batch_capture(pic_batch *B, hipStream_t stream)
+{
+    if (!B || !stream) return PIC_EINVAL;
+    if (B->exec) {
+        (void)hipGraphExecDestroy(B->exec);
+        B->exec = nullptr;
+    }
+    if (B->graph) {
+        (void)hipGraphDestroy(B->graph);
+        B->graph = nullptr;
+    }
+    if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PIC_EHIP;
+    batch_enqueue_step(B, stream);
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(stream, &g) != hipSuccess || !g) return PIC_EHIP;
+    B->graph = g;
+    if (hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        B->exec = nullptr;
+        return PIC_EHIP;
+    }
+    return PIC_OK;
+}
+
+pic_sim *pic_batch_sim(pic_batch *B, int i)
+{
+    if (!B || i < 0 || i >= (int)B->sims.size()) return nullptr;
+    return B->sims[i];
+}
+
+int pic_batch_check(pic_batch *B, hipStream_t stream)
+{
+    if (!B) return PIC_EINVAL;
+    int first = PIC_OK;
+    for (pic_sim *S : B->sims) {
+        const int rc = read_errors(S, stream);
+        if (rc && first == PIC_OK) first = rc;
+    }
+    return first;
+}
+
+void pic_batch_destroy(pic_batch *B)
+{
+    if (!B) return;
+    if (B->exec) (void)hipGraphExecDestroy(B->exec);
+    if (B->graph) (void)hipGraphDestroy(B->graph);
+    for (pic_sim *S : B->sims) pic_destroy(S);
+    delete B;
 }
 
 }  // extern "C"

@@ -104,8 +104,8 @@ struct SortSpecies {
     Parts p;              // the particle arrays
     Parts lp;             // leaver particle data written by the push kernel
     Parts stg;            // mover staging, [n]: tile t's movers at offn[t] + k
-    const int32_t *off;   // old tile_offset
-    int32_t *offn;        // new tile_offset
+    int32_t *off;         // tile_offset: read by the plan, replaced by the new one in the scatter
+    int32_t *offn;        // new tile_offset (scratch)
     const int32_t *cnt;
     const uint32_t *leav;
     int32_t *hole;        // [n]: tile t's holes, ascending, at offn[t] + k
@@ -117,21 +117,49 @@ struct SortSpecies {
 struct SortArgs {
     int *err;
     int nx, ny, ntx, nty, tile;
+    int n_tiles;
     int n_species;
     SortSpecies sp[kMaxSpecies];
 };
 
+struct JReduceArgs {
+    const float *jtile;
+    float *J;             // the Jx plane; Jy, Jz follow
+    int nx, ny, ntx, nty;
+};
+
+struct FieldArgs {
+    float *fld;
+    int nx, ny;
+    float hdx, hdy;       // (dt/2)/dx, (dt/2)/dy  (B half steps)
+    float dt, dtdx, dtdy; // E full step
+};
+
 // ---- launchers (each defined next to its kernels) ----
 void launch_push_deposit(int tile, int replicas, int jmode, const PushArgs &a, int n_tiles, hipStream_t s);
-void launch_j_reduce(int tile, const float *jtile, float *J, int nx, int ny, int ntx, int nty,
-                     hipStream_t s);
+void launch_j_reduce(int tile, const JReduceArgs &r, hipStream_t s);
+void launch_push_batch(int tile, int replicas, int jmode, const PushArgs *descs, const int4 *items, int n_items,
+                       int *counter, int grid, hipStream_t s);
+void launch_j_reduce_batch(int tile, const JReduceArgs *descs, const int4 *items, int n_items, hipStream_t s);
+void launch_set_int(int *p, int v, hipStream_t s);
 void launch_sort_scan(const SortArgs &a, int n_tiles, hipStream_t s);
 void launch_sort_plan(const SortArgs &a, int n_tiles, hipStream_t s);
 void launch_sort_scatter(const SortArgs &a, int n_tiles, hipStream_t s);
+
+// Batched sort phases.  Work tables (int4 per block):
+//   count/add: (sim, species, block of kScanBlock tiles)   scan: (sim, species)
+//   plan/scatter: (sim, species, group of kWaves tiles)
+struct SortBatch {
+    const SortArgs *descs;
+    const int4 *count_items; int n_count;
+    const int4 *scan_items; int n_scan;
+    const int4 *plan_items; int n_plan;
+};
+void launch_sort_batch(const SortBatch &b, hipStream_t s);
 void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile, int ntx,
                        int32_t *counts, int n_tiles, int32_t *off, int *err, hipStream_t s);
-void launch_yee_b(float *fld, int nx, int ny, float hdx, float hdy, hipStream_t s);
-void launch_yee_e(float *fld, int nx, int ny, float dt, float dtdx, float dtdy, hipStream_t s);
+void launch_field_advance(const FieldArgs &f, hipStream_t s);
+void launch_field_advance_batch(const FieldArgs *descs, const int4 *items, int n_items, hipStream_t s);
 
 struct DiagSpecies {
     const int32_t *cell;

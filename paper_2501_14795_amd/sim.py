@@ -1,8 +1,8 @@
-"""A periodic 2D PIC simulation on one MI355X, driven through libpic's C ABI.
+"""Periodic 2D PIC simulations on one MI355X, driven through libpic's C ABI.
 
 PyTorch provides the device memory (caller-owned buffers of the C ABI) and the
-stream; every step of the cycle runs in libpic's HIP kernels.  This class only
-allocates, uploads, packs cell indices (ix | iy << 16) and downloads."""
+streams; every step of the cycle runs in libpic's HIP kernels.  These classes
+only allocate, upload, pack cell indices (ix | iy << 16) and download."""
 from __future__ import annotations
 
 from typing import Dict, List, Optional, Sequence
@@ -23,22 +23,23 @@ def unpack_cells(cell: np.ndarray):
     return (cell & 0xFFFF).astype(np.int32), (cell >> 16).astype(np.int32)
 
 
-class Sim:
-    """Owns the device buffers of one simulation.
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libpic needs a GPU (torch.cuda.is_available() is False)")
+    _lib.load()
+    return torch
 
-    species: list of (qm, q, state) where state is a dict of numpy arrays
-    ix, iy (int32), x, y, ux, uy, uz (float32), grouped by tile."""
 
-    def __init__(self, nx: int, ny: int, dx: float, dy: float, dt: float, tile: int,
-                 species: Sequence, E: Optional[np.ndarray] = None, B: Optional[np.ndarray] = None,
-                 j_replicas: int = 0, j_float: bool = False, device: str = "cuda:0", stream=None):
-        import torch
-        if not torch.cuda.is_available():
-            raise RuntimeError("libpic needs a GPU (torch.cuda.is_available() is False)")
-        _lib.load()
-        self.torch = torch
-        self.device = torch.device(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+class _Buffers:
+    """The caller-owned device buffers of one simulation (torch tensors) and
+    the pic_config / pic_buffers structures that describe them."""
+
+    def __init__(self, nx, ny, dx, dy, dt, tile, species, E=None, B=None, j_replicas=0, j_float=False,
+                 device="cuda:0"):
+        torch = _torch()
+        if not 1 <= len(species) <= _lib.MAX_SPECIES:
+            raise ValueError("1..4 species")
         self.nx, self.ny, self.tile = int(nx), int(ny), int(tile)
         cfg = _lib.pic_config()
         cfg.nx, cfg.ny, cfg.dx, cfg.dy, cfg.dt = self.nx, self.ny, float(dx), float(dy), float(dt)
@@ -46,8 +47,6 @@ class Sim:
         cfg.j_replicas = int(j_replicas)
         cfg.n_species = len(species)
         cfg.flags = _lib.PIC_FLAG_J_FLOAT if j_float else 0
-        if not 1 <= len(species) <= _lib.MAX_SPECIES:
-            raise ValueError("1..4 species")
         for k, (qm, q, st) in enumerate(species):
             cfg.species[k].qm = float(qm)
             cfg.species[k].q = float(q)
@@ -55,35 +54,58 @@ class Sim:
         self.cfg = cfg
         sizes = _lib.pic_query(cfg)
         self.n_tiles = sizes.n_tiles
-        dev = self.device
+        dev = torch.device(device)
         self.fields = torch.zeros((9, self.ny, self.nx), dtype=torch.float32, device=dev)
         if E is not None:
             self.fields[0:3] = torch.from_numpy(np.ascontiguousarray(E, np.float32)).to(dev)
         if B is not None:
             self.fields[3:6] = torch.from_numpy(np.ascontiguousarray(B, np.float32)).to(dev)
         self.work = torch.empty(sizes.work_bytes + 256, dtype=torch.uint8, device=dev)
-        work_ptr = (self.work.data_ptr() + 255) & ~255
-        self.particles: List[Dict[str, "torch.Tensor"]] = []
         bufs = _lib.pic_buffers()
         bufs.fields = self.fields.data_ptr()
-        bufs.work = work_ptr
+        bufs.work = (self.work.data_ptr() + 255) & ~255
         bufs.work_bytes = sizes.work_bytes
+        self.particles: List[Dict[str, "torch.Tensor"]] = []
         for k, (qm, q, st) in enumerate(species):
-            cell = pack_cells(st["ix"], st["iy"])
-            p = {"cell": torch.from_numpy(cell).to(dev)}
+            p = {"cell": torch.from_numpy(pack_cells(st["ix"], st["iy"])).to(dev)}
             for name in PARTICLE_FIELDS[1:]:
                 p[name] = torch.from_numpy(np.ascontiguousarray(st[name], np.float32)).to(dev)
             self.particles.append(p)
             for name in PARTICLE_FIELDS:
                 setattr(bufs.sp[k], name, p[name].data_ptr() if p[name].numel() else None)
         self.bufs = bufs
-        torch.cuda.synchronize(dev)
-        self.handle = _lib.pic_init(cfg, bufs, self.stream.cuda_stream)
 
-    # ---- the C functions
+
+class _SimView:
+    """The pic_* calls and host copies of one simulation (a pic_sim handle)."""
+
+    handle: int
+    stream: object
+    buf: _Buffers
+
     @property
     def s(self) -> int:
         return self.stream.cuda_stream
+
+    @property
+    def nx(self):
+        return self.buf.nx
+
+    @property
+    def ny(self):
+        return self.buf.ny
+
+    @property
+    def n_tiles(self):
+        return self.buf.n_tiles
+
+    @property
+    def fields(self):
+        return self.buf.fields
+
+    @property
+    def particles(self):
+        return self.buf.particles
 
     def push_deposit(self):
         _lib.pic_push_deposit(self.handle, self.s)
@@ -113,7 +135,6 @@ class Sim:
         t = _lib.pic_get_timing(self.handle)
         return {name: (t.ms_total[k], t.launches[k]) for k, name in enumerate(_lib.KERNELS)}
 
-    # ---- host copies
     def state(self, species: int = 0) -> Dict[str, np.ndarray]:
         self.stream.synchronize()
         p = self.particles[species]
@@ -126,9 +147,88 @@ class Sim:
         f = self.fields.cpu().numpy()
         return {"E": f[0:3].copy(), "B": f[3:6].copy(), "J": f[6:9].copy()}
 
+
+class Sim(_SimView):
+    """One simulation that owns its device buffers.
+
+    species: list of (qm, q, state) where state is a dict of numpy arrays
+    ix, iy (int32), x, y, ux, uy, uz (float32), grouped by tile."""
+
+    def __init__(self, nx: int, ny: int, dx: float, dy: float, dt: float, tile: int,
+                 species: Sequence, E: Optional[np.ndarray] = None, B: Optional[np.ndarray] = None,
+                 j_replicas: int = 0, j_float: bool = False, device: str = "cuda:0", stream=None):
+        torch = _torch()
+        self.handle = None
+        self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+        self.buf = _Buffers(nx, ny, dx, dy, dt, tile, species, E, B, j_replicas, j_float, device)
+        self.cfg = self.buf.cfg
+        torch.cuda.synchronize(torch.device(device))
+        self.handle = _lib.pic_init(self.cfg, self.buf.bufs, self.s)
+
     def close(self):
         if getattr(self, "handle", None):
             _lib.pic_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchMember(_SimView):
+    """A member of a Batch (its pic_sim is owned by the batch)."""
+
+    def __init__(self, batch, i, buf):
+        self.batch = batch
+        self.buf = buf
+        self.stream = batch.stream
+        self.handle = _lib.pic_batch_sim(batch.handle, i)
+
+
+class Batch:
+    """Many independent simulations advanced together: one launch per phase
+    for all of them, optionally replayed from a captured HIP graph.
+
+    members: list of dicts with keys nx, ny, dx, dy, dt, species (as for Sim)
+    and optionally E, B.  All share tile, j_replicas, j_float."""
+
+    def __init__(self, members: Sequence[dict], tile: int, j_replicas: int = 0, j_float: bool = False,
+                 device: str = "cuda:0", stream=None):
+        torch = _torch()
+        self.handle = None
+        self.stream = stream if stream is not None else torch.cuda.Stream(torch.device(device))
+        self.bufs = [_Buffers(m["nx"], m["ny"], m["dx"], m["dy"], m["dt"], tile, m["species"], m.get("E"),
+                              m.get("B"), j_replicas, j_float, device) for m in members]
+        cfgs = [b.cfg for b in self.bufs]
+        nbytes = _lib.pic_batch_query(cfgs)
+        self.work = torch.empty(nbytes + 256, dtype=torch.uint8, device=torch.device(device))
+        torch.cuda.synchronize(torch.device(device))
+        self.handle = _lib.pic_batch_init(cfgs, [b.bufs for b in self.bufs], (self.work.data_ptr() + 255) & ~255,
+                                          nbytes, self.stream.cuda_stream)
+        self.members = [BatchMember(self, i, b) for i, b in enumerate(self.bufs)]
+        self.captured = False
+
+    def __len__(self):
+        return len(self.members)
+
+    def __getitem__(self, i) -> BatchMember:
+        return self.members[i]
+
+    def step(self, nsteps: int = 1):
+        _lib.pic_batch_step(self.handle, nsteps, self.stream.cuda_stream)
+
+    def capture(self):
+        _lib.pic_batch_capture(self.handle, self.stream.cuda_stream)
+        self.captured = True
+
+    def check(self) -> int:
+        return _lib.pic_batch_check(self.handle, self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.pic_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -155,3 +155,26 @@ def random_fields(nx: int, ny: int, amp: float, seed: int):
             comps.append(amp * f / 3.0)
         out.append(np.stack(comps).astype(np.float32))
     return out[0], out[1]
+
+
+PPC_LATTICE = {8: (4, 2), 16: (4, 4), 32: (8, 4), 64: (8, 8)}
+
+
+def batched_members(n_sims: int = 256, seed: int = 4, sizes=(32, 64, 96, 128, 160, 192, 224, 256),
+                    ppcs=(8, 16, 32, 64), dx: float = 0.1, dt: float = 0.07):
+    """Specifications of many independent small simulations (the batched
+    workload): nx and ny independently uniform on `sizes`, particles per cell
+    uniform on `ppcs`, u_th ~ U[0.01, 0.2] isotropic, drift zero with
+    probability 1/2 else each component ~ U[-0.3, 0.3].  One electron species
+    each.  Returns a list of dicts (nx, ny, dx, dy, dt, spec, seed)."""
+    rng = np.random.Generator(np.random.Philox(np.random.SeedSequence([seed, 7777])))
+    out = []
+    for k in range(n_sims):
+        nx = int(rng.choice(sizes))
+        ny = int(rng.choice(sizes))
+        ppc = int(rng.choice(ppcs))
+        u_th = float(rng.uniform(0.01, 0.2))
+        drift = (0.0, 0.0, 0.0) if rng.random() < 0.5 else tuple(float(v) for v in rng.uniform(-0.3, 0.3, 3))
+        spec = SpeciesSpec(-1.0, PPC_LATTICE[ppc], (u_th,) * 3, drift)
+        out.append({"nx": nx, "ny": ny, "dx": dx, "dy": dx, "dt": dt, "spec": spec, "seed": seed * 100000 + k})
+    return out

@@ -23,7 +23,7 @@ def _lib():
 def test_exports_every_declared_symbol():
     L = _lib()
     text = open(HEADER).read()
-    declared = set(re.findall(r"^\s*(?:int|void|const char \*)\s*(pic_\w+)\s*\(", text, re.M))
+    declared = set(re.findall(r"^\s*(?:int|void|const char \*|pic_sim \*)\s*(pic_\w+)\s*\(", text, re.M))
     assert declared == set(L.EXPORTS)
     lib = L.load()
     for name in declared:
@@ -117,3 +117,20 @@ def test_init_rejects_bad_buffers_without_touching_the_device():
     with pytest.raises(L.PicError) as e:
         L.pic_init(c, b, 0)
     assert e.value.code == L.PIC_EINVAL
+
+
+def test_batch_query_validation():
+    L = _lib()
+    cfgs = [_cfg(L, nx=32, ny=64), _cfg(L, nx=64, ny=32, n=500)]
+    nb = L.pic_batch_query(cfgs)
+    assert nb > 0
+    for bad in ([_cfg(L), _cfg(L, tile=8)], [_cfg(L), _cfg(L, flags=L.PIC_FLAG_J_FLOAT)],
+                [_cfg(L), _cfg(L, reps=2)]):
+        with pytest.raises(L.PicError) as e:
+            L.pic_batch_query(bad)
+        assert e.value.code == L.PIC_EINVAL
+    with pytest.raises(L.PicError):
+        L.pic_batch_query([])
+    with pytest.raises(L.PicError) as e:
+        L.pic_batch_query([_cfg(L), _cfg(L, dt=0.08)])
+    assert e.value.code == L.PIC_ECFL
