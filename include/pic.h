@@ -67,12 +67,16 @@ extern "C" {
 #define PIC_ERANGE (-6)   /* a particle tried to move one cell or more in a step */
 #define PIC_ESORT (-7)    /* internal sort consistency check failed */
 #define PIC_ECOUNT (-8)   /* tile counts do not add up to the particle count */
+#define PIC_EOVERFLOW (-9) /* fixed-point current: 2^16+ contributions to one node of one tile */
 
 /*
  * Current accumulation inside a tile (pic_config.flags).
- * Default (0): exact int64 fixed point -- each deposit contribution is rounded
- *   once to 2^-24 of the largest possible contribution (max |q| moving one
- *   cell), sums are exact, J is bit-reproducible from run to run.
+ * Default (0): exact 64-bit fixed point -- each deposit contribution is
+ *   rounded once, to within 2^-23 of the largest possible contribution (max
+ *   |q| moving one cell), sums are exact, J is bit-reproducible from run to
+ *   run.
+ *   Limit: fewer than 2^16 contributions to one node within one tile per step
+ *   (else PIC_EOVERFLOW), i.e. a few thousand particles per cell.
  * PIC_FLAG_J_FLOAT: FP32 atomic adds into j_replicas LDS copies, summed with
  *   compensation; J reproducible only to round-off (and slower on gfx950).
  */

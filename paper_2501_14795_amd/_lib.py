@@ -21,6 +21,7 @@ PIC_EORDER = -5
 PIC_ERANGE = -6
 PIC_ESORT = -7
 PIC_ECOUNT = -8
+PIC_EOVERFLOW = -9
 
 PIC_FLAG_J_FLOAT = 1
 

@@ -68,18 +68,32 @@ __device__ __forceinline__ void stf(__amdgpu_buffer_rsrc_t r, int off, float v)
 template <int JM>
 struct JAcc;
 
+// Exact fixed point.  A contribution a*w (|a*w| <= 2^22 units) is stored as
+// u = a*w + 3*2^22, an integer in [2^23, 2^24): a single fma rounds it to the
+// nearest integer, because floats in [2^23, 2^24) are spaced by exactly one.
+// Each 64-bit add also carries 2^40, so the high bits count the
+// contributions and the bias is removed exactly at the end; the low 40 bits
+// cannot carry into the count while a node takes fewer than 2^16
+// contributions per tile (checked).
 template <>
 struct JAcc<kJFixed> {
     using T = unsigned long long;
-    __device__ static __forceinline__ void add(T *p, float v)
+    static constexpr unsigned long long kCount = 1ull << 40;
+    static constexpr float kBias = 12582912.0f;   // 3 * 2^22
+    __device__ static __forceinline__ void add(T *p, float a, float w)
     {
-        const long long q = (long long)(int)rintf(v);
-        atomicAdd(p, (T)q);
+        const unsigned u = (unsigned)fmaf(a, w, kBias);
+        atomicAdd(p, kCount | (T)u);
     }
-    __device__ static __forceinline__ float value(const T *p, int replicas, int stride, float unit)
+    __device__ static __forceinline__ float value(const T *p, int replicas, int stride, float unit, int *err)
     {
         long long s = 0;
-        for (int r = 0; r < replicas; ++r) s += (long long)p[r * stride];
+        for (int r = 0; r < replicas; ++r) {
+            const T t = p[r * stride];
+            const long long count = (long long)(t >> 40);
+            if (count >= 65536) atomicOr(err, kErrOverflow);
+            s += (long long)(t & (kCount - 1)) - count * 12582912ll;
+        }
         return (float)((double)s * (double)unit);
     }
 };
@@ -87,8 +101,8 @@ struct JAcc<kJFixed> {
 template <>
 struct JAcc<kJFloat> {
     using T = float;
-    __device__ static __forceinline__ void add(T *p, float v) { atomicAdd(p, v); }
-    __device__ static __forceinline__ float value(const T *p, int replicas, int stride, float unit)
+    __device__ static __forceinline__ void add(T *p, float a, float w) { atomicAdd(p, a * w); }
+    __device__ static __forceinline__ float value(const T *p, int replicas, int stride, float unit, int *)
     {
         // compensated (TwoSum) sum of the replicas
         float s = 0.0f, c = 0.0f;
@@ -119,15 +133,15 @@ __device__ __forceinline__ void deposit_piece(typename JAcc<JM>::T *sj, int cx, 
     const float ax = fq * dxk, ay = fq * dyk, az = fqvz * frac;
     const float c = dxk * dyk * (1.0f / 12.0f);
     const float xm1 = 1.0f - xm, ym1 = 1.0f - ym;
-    const int b = (cy + 1) * NJ + (cx + 1);
-    A::add(&sj[b], ax * ym1);
-    A::add(&sj[b + NJ], ax * ym);
-    A::add(&sj[P + b], ay * xm1);
-    A::add(&sj[P + b + 1], ay * xm);
-    A::add(&sj[2 * P + b], az * fmaf(xm1, ym1, c));
-    A::add(&sj[2 * P + b + 1], az * fmaf(xm, ym1, -c));
-    A::add(&sj[2 * P + b + NJ], az * fmaf(xm1, ym, -c));
-    A::add(&sj[2 * P + b + NJ + 1], az * fmaf(xm, ym, c));
+    const int b = __mul24(cy + 1, NJ) + (cx + 1);   // 24-bit multiply: full rate
+    A::add(&sj[b], ax, ym1);
+    A::add(&sj[b + NJ], ax, ym);
+    A::add(&sj[P + b], ay, xm1);
+    A::add(&sj[P + b + 1], ay, xm);
+    A::add(&sj[2 * P + b], az, fmaf(xm1, ym1, c));
+    A::add(&sj[2 * P + b + 1], az, fmaf(xm, ym1, -c));
+    A::add(&sj[2 * P + b + NJ], az, fmaf(xm1, ym, -c));
+    A::add(&sj[2 * P + b + NJ + 1], az, fmaf(xm, ym, c));
 }
 
 // Write the n leavers buffered in LDS by one wavefront to the leaver list
@@ -249,10 +263,11 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                     const int ch = lx + (xh ? 1 : 0);             // packed column of the half stencil
                     const int rh = ly + (yh ? 1 : 0);
                     const int c0 = lx + 1, r0 = ly + 1;
-                    const float4 p0 = s_exby[r0 * NE + ch], p1 = s_exby[(r0 + 1) * NE + ch];
-                    const float4 q0 = s_eybx[rh * NE + c0], q1 = s_eybx[(rh + 1) * NE + c0];
-                    const float2 z0 = s_ez[r0 * NE + c0], z1 = s_ez[(r0 + 1) * NE + c0];
-                    const float2 b0 = s_bz[rh * NE + ch], b1 = s_bz[(rh + 1) * NE + ch];
+                    const int e0 = __mul24(r0, NE), eh = __mul24(rh, NE);
+                    const float4 p0 = s_exby[e0 + ch], p1 = s_exby[e0 + NE + ch];
+                    const float4 q0 = s_eybx[eh + c0], q1 = s_eybx[eh + NE + c0];
+                    const float2 z0 = s_ez[e0 + c0], z1 = s_ez[e0 + NE + c0];
+                    const float2 b0 = s_bz[eh + ch], b1 = s_bz[eh + NE + ch];
                     const float Ex = lerpf(lerpf(p0.x, p0.z, wxh), lerpf(p1.x, p1.z, wxh), y);
                     const float By = lerpf(lerpf(p0.y, p0.w, wxh), lerpf(p1.y, p1.w, wxh), y);
                     const float Ey = lerpf(lerpf(q0.x, q0.z, x), lerpf(q1.x, q1.z, x), wyh);
@@ -422,7 +437,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
     float *out = a.jtile + (int64_t)tile * 3 * JP;
     for (int e = tid; e < 3 * JP; e += kBlock) {
         const int comp = e / JP;
-        out[e] = JAcc<JM>::value(&s_j[0][e], R, 3 * JP, a.ju[comp]);
+        out[e] = JAcc<JM>::value(&s_j[0][e], R, 3 * JP, a.ju[comp], a.err);
     }
 }
 

@@ -181,6 +181,7 @@ int read_errors(pic_sim *s, hipStream_t stream)
     if (h & kErrRange) return PIC_ERANGE;
     if (h & kErrCount) return PIC_ECOUNT;
     if (h & kErrSort) return PIC_ESORT;
+    if (h & kErrOverflow) return PIC_EOVERFLOW;
     return PIC_OK;
 }
 
@@ -325,6 +326,7 @@ const char *pic_strerror(int code)
     case PIC_ERANGE: return "a particle moved one cell or more in one step";
     case PIC_ESORT: return "sort consistency check failed";
     case PIC_ECOUNT: return "tile counts do not add up to the particle count";
+    case PIC_EOVERFLOW: return "a tile current accumulator took 2^16 or more contributions to one node";
     default: return "unknown error";
     }
 }

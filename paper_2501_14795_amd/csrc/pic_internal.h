@@ -29,6 +29,7 @@ enum : int {
     kErrRange = 2,   // displacement of one cell or more
     kErrSort = 4,    // hole / mover count mismatch
     kErrCount = 8,   // tile counts do not sum to n
+    kErrOverflow = 16, // a fixed-point current accumulator took 2^16 contributions or more
 };
 
 // Current accumulation modes of the push kernel.
@@ -39,9 +40,9 @@ enum : int {
 
 // Fixed-point resolution: one current contribution of the largest possible
 // magnitude (the particle charge of the largest species times a full cell of
-// motion) is 2^24 units, so a contribution converts to int32 exactly enough
-// (2^-25 relative rounding) and int64 sums cannot overflow.
-constexpr float kFixedScale = 16777216.0f;
+// motion) is 2^22 units; each contribution is rounded once to a unit
+// (error at most 2^-23 of the largest one) and the sums are exact.
+constexpr float kFixedScale = 4194304.0f;
 
 constexpr int kLdsBytes = 160 * 1024;   // LDS of one gfx950 compute unit
 constexpr int kLeaverBuf = 64;           // leavers buffered per wavefront before a write-out

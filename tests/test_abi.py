@@ -105,7 +105,7 @@ def test_query_sizes_and_validation():
         assert e.value.code == code, (kw, e.value.code)
     assert L.pic_query(_cfg(L, dt=0.0707)).n_tiles == 16
     assert L.pic_query(_cfg(L, nx=64, tile=32, reps=4, flags=L.PIC_FLAG_J_FLOAT)).n_tiles == 4
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         assert L.strerror(code) != "unknown error"
     assert L.strerror(-99) == "unknown error"
 
