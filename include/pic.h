@@ -19,8 +19,8 @@
  *     caller memory.  pic_query() tells the caller what to allocate.
  *   - Every function that takes a hipStream_t enqueues its work on that stream
  *     and returns without synchronising, except pic_init(), pic_check(),
- *     pic_diag(), pic_get_tile_offsets() and pic_get_timing(), which
- *     synchronise the stream they are given.
+ *     pic_diag(), pic_get_state(), pic_set_state(), pic_get_tile_offsets()
+ *     and pic_get_timing(), which synchronise the stream they are given.
  *   - Calls on one pic_sim must not run concurrently from several host
  *     threads.
  *
@@ -174,6 +174,7 @@ int pic_check(pic_sim *sim, hipStream_t stream);
 #define PIC_DIAG_RHO_SNAPSHOT 2u    /* remember rho of the current positions */
 #define PIC_DIAG_CONTINUITY 4u      /* residual against the snapshot and current J */
 #define PIC_DIAG_COUNTS 8u          /* leavers of the last push, movers of the last sort */
+#define PIC_DIAG_GAUSS 16u          /* residuals of Gauss's law and of div B = 0 */
 
 typedef struct pic_diag_out {
     double u_e;                       /* 1/2 dx dy sum |E|^2 */
@@ -183,6 +184,8 @@ typedef struct pic_diag_out {
     double rho_max;                   /* max |rho'| */
     int64_t leavers[PIC_MAX_SPECIES]; /* particles whose tile changed */
     int64_t movers[PIC_MAX_SPECIES];  /* particles moved by the last sort */
+    double gauss_max;                 /* max |div E - (rho - rho_bar)| over the nodes */
+    double divb_max;                  /* max |div B| over the cell centres */
 } pic_diag_out;
 
 /*
@@ -190,10 +193,38 @@ typedef struct pic_diag_out {
  * `stream`, synchronise it and fill *out (fields not selected are zero).
  * PIC_DIAG_CONTINUITY evaluates Eq. (12) in discrete form,
  * rho(now) - rho(snapshot) + dt * div J, at the nodes; it returns PIC_EINVAL
- * without an earlier PIC_DIAG_RHO_SNAPSHOT.  Also reports device error flags
- * like pic_check().
+ * without an earlier PIC_DIAG_RHO_SNAPSHOT.  PIC_DIAG_GAUSS evaluates
+ * Gauss's law on the Yee grid, div E = rho - rho_bar at the nodes, with the
+ * ions a uniform neutralising background rho_bar (the mean of rho, from the
+ * particle charges and counts), and div B at the cell centres; a
+ * charge-conserving step keeps both at their initial values.  Also reports
+ * device error flags like pic_check().
  */
 int pic_diag(pic_sim *sim, unsigned what, pic_diag_out *out, hipStream_t stream);
+
+/*
+ * State I/O: host copies of everything that carries over from one step to
+ * the next -- the field planes and every species' particles -- for
+ * checkpoint / resume and for replaying a step on another implementation.
+ * tile_offset is derived from the particles and rebuilt on load.
+ */
+typedef struct pic_host_state {
+    float *fields;                      /* host, 9 * nx * ny floats (layout above) */
+    pic_particles sp[PIC_MAX_SPECIES];  /* host arrays, species[s].n entries each */
+} pic_host_state;
+
+/* Copy the field planes and the particles of every species to the caller's
+ * host arrays (a NULL array is skipped) and synchronise `stream`. */
+int pic_get_state(pic_sim *sim, const pic_host_state *out, hipStream_t stream);
+
+/*
+ * Load the field planes and the particles (the counts of the config, grouped
+ * by tile as for pic_init) from host arrays, rebuild tile_offset, forget the
+ * rho snapshot of pic_diag and synchronise `stream`.  Every array must be
+ * given.  Returns PIC_EORDER if the particles are not grouped by tile (the
+ * simulation then needs a valid state before its next step).
+ */
+int pic_set_state(pic_sim *sim, const pic_host_state *in, hipStream_t stream);
 
 /* Copy the current tile_offset of `species` (n_tiles + 1 int32) to host memory. */
 int pic_get_tile_offsets(pic_sim *sim, int species, int32_t *host_out, hipStream_t stream);

@@ -29,13 +29,15 @@ PIC_DIAG_ENERGY = 1
 PIC_DIAG_RHO_SNAPSHOT = 2
 PIC_DIAG_CONTINUITY = 4
 PIC_DIAG_COUNTS = 8
+PIC_DIAG_GAUSS = 16
 
 KERNELS = ["push", "j_reduce", "sort_scan", "sort_plan", "sort_scatter", "field"]
 
 # every symbol the header declares
 EXPORTS = [
     "pic_query", "pic_init", "pic_push_deposit", "pic_sort", "pic_field_advance", "pic_step",
-    "pic_check", "pic_diag", "pic_get_tile_offsets", "pic_set_timing", "pic_get_timing",
+    "pic_check", "pic_diag", "pic_get_state", "pic_set_state", "pic_get_tile_offsets",
+    "pic_set_timing", "pic_get_timing",
     "pic_batch_query", "pic_batch_init", "pic_batch_step", "pic_batch_capture", "pic_batch_sim",
     "pic_batch_check", "pic_batch_destroy",
     "pic_strerror", "pic_destroy",
@@ -72,7 +74,12 @@ class pic_diag_out(ctypes.Structure):
     _fields_ = [("u_e", ctypes.c_double), ("u_b", ctypes.c_double),
                 ("u_k", ctypes.c_double * MAX_SPECIES),
                 ("continuity_max", ctypes.c_double), ("rho_max", ctypes.c_double),
-                ("leavers", ctypes.c_int64 * MAX_SPECIES), ("movers", ctypes.c_int64 * MAX_SPECIES)]
+                ("leavers", ctypes.c_int64 * MAX_SPECIES), ("movers", ctypes.c_int64 * MAX_SPECIES),
+                ("gauss_max", ctypes.c_double), ("divb_max", ctypes.c_double)]
+
+
+class pic_host_state(ctypes.Structure):
+    _fields_ = [("fields", ctypes.c_void_p), ("sp", pic_particles * MAX_SPECIES)]
 
 
 class pic_timing_out(ctypes.Structure):
@@ -110,6 +117,8 @@ def load(path: str = SO_PATH):
         getattr(L, name).argtypes = [vp, vp]
     L.pic_diag.argtypes = [vp, ctypes.c_uint, P(pic_diag_out), vp]
     L.pic_get_tile_offsets.argtypes = [vp, ctypes.c_int, vp, vp]
+    L.pic_get_state.argtypes = [vp, P(pic_host_state), vp]
+    L.pic_set_state.argtypes = [vp, P(pic_host_state), vp]
     L.pic_set_timing.argtypes = [vp, ctypes.c_int]
     L.pic_get_timing.argtypes = [vp, P(pic_timing_out)]
     L.pic_strerror.argtypes = [ctypes.c_int]
@@ -183,6 +192,16 @@ def pic_diag(sim: int, what: int, stream: int) -> pic_diag_out:
     _chk(load().pic_diag(ctypes.c_void_p(sim), ctypes.c_uint(what), ctypes.byref(out), ctypes.c_void_p(stream)),
          "pic_diag")
     return out
+
+
+def pic_get_state(sim: int, state: pic_host_state, stream: int):
+    _chk(load().pic_get_state(ctypes.c_void_p(sim), ctypes.byref(state), ctypes.c_void_p(stream)),
+         "pic_get_state")
+
+
+def pic_set_state(sim: int, state: pic_host_state, stream: int):
+    _chk(load().pic_set_state(ctypes.c_void_p(sim), ctypes.byref(state), ctypes.c_void_p(stream)),
+         "pic_set_state")
 
 
 def pic_get_tile_offsets(sim: int, species: int, n_tiles: int, stream: int):

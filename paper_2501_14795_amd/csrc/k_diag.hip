@@ -1,5 +1,6 @@
 // Diagnostics with FP64 accumulation (energies, node charge density, the
-// discrete continuity residual of Eq. 12).  Not on the hot path.
+// discrete continuity residual of Eq. 12, the residuals of Gauss's law and of
+// div B = 0).  Not on the hot path.
 #include "pic_internal.h"
 
 namespace pic {
@@ -87,6 +88,28 @@ __global__ void __launch_bounds__(256) k_continuity(const double *rho_prev, cons
     atomic_max_nonneg(&acc[1], fabs(rho_now[k]));
 }
 
+// Gauss's law residual at the nodes, div E - (rho - rho_bar) with the ions a
+// uniform neutralising background rho_bar, and div B at the cell centres
+// (i+1/2, j+1/2); maxima of their magnitudes into acc[0], acc[1].
+__global__ void __launch_bounds__(256) k_gauss(const float *__restrict__ f, const double *rho, double rho_bar,
+                                               int nx, int ny, double dx, double dy, double *acc)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= nx || j >= ny) return;
+    const int64_t P = (int64_t)nx * ny;
+    const int64_t k = (int64_t)j * nx + i;
+    const int64_t kxm = (int64_t)j * nx + (i == 0 ? nx - 1 : i - 1);
+    const int64_t kym = (int64_t)(j == 0 ? ny - 1 : j - 1) * nx + i;
+    const int64_t kxp = (int64_t)j * nx + (i + 1 == nx ? 0 : i + 1);
+    const int64_t kyp = (int64_t)(j + 1 == ny ? 0 : j + 1) * nx + i;
+    const double dive = ((double)f[k] - (double)f[kxm]) / dx + ((double)f[P + k] - (double)f[P + kym]) / dy;
+    const double divb = ((double)f[3 * P + kxp] - (double)f[3 * P + k]) / dx +
+                        ((double)f[4 * P + kyp] - (double)f[4 * P + k]) / dy;
+    atomic_max_nonneg(&acc[0], fabs(dive - (rho[k] - rho_bar)));
+    atomic_max_nonneg(&acc[1], fabs(divb));
+}
+
 __global__ void __launch_bounds__(256) k_counts(const int32_t *cnt, const int32_t *mcount, int n_tiles,
                                                 unsigned long long *acc)
 {
@@ -118,6 +141,13 @@ void launch_diag_continuity(const double *rho_prev, const double *rho_now, const
 {
     hipLaunchKernelGGL(k_continuity, dim3((nx + 63) / 64, (ny + 3) / 4), dim3(256), 0, s, rho_prev, rho_now,
                        J, nx, ny, dt, dx, dy, acc);
+}
+
+void launch_diag_gauss(const float *fld, const double *rho, double rho_bar, int nx, int ny, double dx, double dy,
+                       double *acc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gauss, dim3((nx + 63) / 64, (ny + 3) / 4), dim3(256), 0, s, fld, rho, rho_bar, nx, ny,
+                       dx, dy, acc);
 }
 
 void launch_diag_counts(const int32_t *cnt, const int32_t *mcount, int n_tiles, unsigned long long *acc,

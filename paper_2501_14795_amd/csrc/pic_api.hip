@@ -343,6 +343,30 @@ int pic_query(const pic_config *cfg, pic_sizes *out)
     return PIC_OK;
 }
 
+namespace {
+
+// tile_offset of every species from its particle cells (which must be grouped
+// by tile); synchronises and reports PIC_EORDER / PIC_ECOUNT.
+int build_tiles(pic_sim *S, hipStream_t stream)
+{
+    const pic_config &c = S->cfg;
+    int rc = PIC_OK;
+    for (int s = 0; s < c.n_species && rc == PIC_OK; ++s) {
+        auto &P = S->sp[s];
+        // counts go through the cnt record area, which the next push overwrites
+        rc = hip_ok(hipMemsetAsync(P.cnt, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
+        if (rc) break;
+        launch_init_tiles(S->buf.sp[s].cell, (int32_t)c.species[s].n, c.nx, c.ny, c.tile, S->ntx, P.cnt,
+                          S->n_tiles, P.off, S->err, stream);
+        rc = hip_ok(hipMemsetAsync(P.mcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
+    }
+    if (rc == PIC_OK) rc = hip_ok(hipGetLastError());
+    if (rc == PIC_OK) rc = read_errors(S, stream);
+    return rc;
+}
+
+}  // namespace
+
 int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream, pic_sim **out)
 {
     if (!out || !bufs) return PIC_EINVAL;
@@ -398,17 +422,7 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
     }
 
     rc = hip_ok(hipMemsetAsync(S->err, 0, 64, stream));
-    for (int s = 0; s < cfg->n_species && rc == PIC_OK; ++s) {
-        auto &P = S->sp[s];
-        // counts go through the cnt record area, which the first push overwrites
-        rc = hip_ok(hipMemsetAsync(P.cnt, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
-        if (rc) break;
-        launch_init_tiles(bufs->sp[s].cell, (int32_t)cfg->species[s].n, cfg->nx, cfg->ny, cfg->tile, S->ntx,
-                          P.cnt, S->n_tiles, P.off, S->err, stream);
-        rc = hip_ok(hipMemsetAsync(P.mcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
-    }
-    if (rc == PIC_OK) rc = hip_ok(hipGetLastError());
-    if (rc == PIC_OK) rc = read_errors(S, stream);
+    if (rc == PIC_OK) rc = build_tiles(S, stream);
     if (rc != PIC_OK) {
         delete S;
         return rc;
@@ -487,7 +501,7 @@ int pic_diag(pic_sim *S, unsigned what, pic_diag_out *out, hipStream_t stream)
         launch_diag_field_energy(S->buf.fields, plane, S->dacc, stream);
         for (int s = 0; s < c.n_species; ++s) launch_diag_kinetic(diag_species(S, s), S->dacc + 2 + s, stream);
     }
-    if (what & (PIC_DIAG_RHO_SNAPSHOT | PIC_DIAG_CONTINUITY)) {
+    if (what & (PIC_DIAG_RHO_SNAPSHOT | PIC_DIAG_CONTINUITY | PIC_DIAG_GAUSS)) {
         rc = hip_ok(hipMemsetAsync(S->rho_now, 0, plane * sizeof(double), stream));
         if (rc) return rc;
         for (int s = 0; s < c.n_species; ++s) launch_diag_rho(diag_species(S, s), c.nx, c.ny, S->rho_now, stream);
@@ -495,6 +509,12 @@ int pic_diag(pic_sim *S, unsigned what, pic_diag_out *out, hipStream_t stream)
     if (what & PIC_DIAG_CONTINUITY)
         launch_diag_continuity(S->rho_prev, S->rho_now, S->buf.fields + 6 * plane, c.nx, c.ny, c.dt, c.dx, c.dy,
                                S->dacc + 8, stream);
+    if (what & PIC_DIAG_GAUSS) {
+        double total = 0.0;
+        for (int s = 0; s < c.n_species; ++s) total += c.species[s].q * (double)c.species[s].n;
+        launch_diag_gauss(S->buf.fields, S->rho_now, total / (double)plane, c.nx, c.ny, c.dx, c.dy, S->dacc + 10,
+                          stream);
+    }
     double dh[32];
     unsigned long long ch[8 * kMaxSpecies];
     rc = hip_ok(hipMemcpyAsync(dh, S->dacc, sizeof(dh), hipMemcpyDeviceToHost, stream));
@@ -521,6 +541,10 @@ int pic_diag(pic_sim *S, unsigned what, pic_diag_out *out, hipStream_t stream)
         out->continuity_max = dh[8];
         out->rho_max = dh[9];
     }
+    if (what & PIC_DIAG_GAUSS) {
+        out->gauss_max = dh[10];
+        out->divb_max = dh[11];
+    }
     if (what & PIC_DIAG_COUNTS)
         for (int s = 0; s < c.n_species; ++s) {
             out->leavers[s] = (int64_t)ch[2 * s];
@@ -531,6 +555,55 @@ int pic_diag(pic_sim *S, unsigned what, pic_diag_out *out, hipStream_t stream)
         S->have_snapshot = true;
     }
     return read_errors(S, stream);
+}
+
+namespace {
+
+// one host <-> device copy of each particle array of species s
+int copy_particles(pic_sim *S, int s, const pic_particles &host, bool to_host, hipStream_t stream)
+{
+    const pic_particles &dev = S->buf.sp[s];
+    const size_t n = (size_t)S->cfg.species[s].n;
+    void *const hp[6] = {host.cell, host.x, host.y, host.ux, host.uy, host.uz};
+    void *const dp[6] = {dev.cell, dev.x, dev.y, dev.ux, dev.uy, dev.uz};
+    int rc = PIC_OK;
+    for (int k = 0; k < 6 && rc == PIC_OK && n > 0; ++k) {
+        if (!hp[k]) {
+            if (to_host) continue;
+            return PIC_EINVAL;
+        }
+        rc = to_host ? hip_ok(hipMemcpyAsync(hp[k], dp[k], 4 * n, hipMemcpyDeviceToHost, stream))
+                     : hip_ok(hipMemcpyAsync(dp[k], hp[k], 4 * n, hipMemcpyHostToDevice, stream));
+    }
+    return rc;
+}
+
+}  // namespace
+
+int pic_get_state(pic_sim *S, const pic_host_state *out, hipStream_t stream)
+{
+    if (!S || !out) return PIC_EINVAL;
+    const size_t fbytes = 9 * sizeof(float) * (size_t)S->cfg.nx * S->cfg.ny;
+    int rc = PIC_OK;
+    if (out->fields) rc = hip_ok(hipMemcpyAsync(out->fields, S->buf.fields, fbytes, hipMemcpyDeviceToHost, stream));
+    for (int s = 0; s < S->cfg.n_species && rc == PIC_OK; ++s) rc = copy_particles(S, s, out->sp[s], true, stream);
+    if (rc == PIC_OK) rc = hip_ok(hipStreamSynchronize(stream));
+    return rc;
+}
+
+int pic_set_state(pic_sim *S, const pic_host_state *in, hipStream_t stream)
+{
+    if (!S || !in || !in->fields) return PIC_EINVAL;
+    for (int s = 0; s < S->cfg.n_species; ++s) {
+        const pic_particles &p = in->sp[s];
+        if (S->cfg.species[s].n > 0 && (!p.cell || !p.x || !p.y || !p.ux || !p.uy || !p.uz)) return PIC_EINVAL;
+    }
+    const size_t fbytes = 9 * sizeof(float) * (size_t)S->cfg.nx * S->cfg.ny;
+    int rc = hip_ok(hipMemcpyAsync(S->buf.fields, in->fields, fbytes, hipMemcpyHostToDevice, stream));
+    for (int s = 0; s < S->cfg.n_species && rc == PIC_OK; ++s) rc = copy_particles(S, s, in->sp[s], false, stream);
+    S->have_snapshot = false;
+    if (rc == PIC_OK) rc = build_tiles(S, stream);
+    return rc;
 }
 
 int pic_get_tile_offsets(pic_sim *S, int species, int32_t *host_out, hipStream_t stream)

@@ -174,6 +174,8 @@ void launch_diag_rho(const DiagSpecies &sp, int nx, int ny, double *rho, hipStre
 void launch_diag_continuity(const double *rho_prev, const double *rho_now, const float *J,
                             int nx, int ny, double dt, double dx, double dy, double *acc,
                             hipStream_t s);
+void launch_diag_gauss(const float *fld, const double *rho, double rho_bar, int nx, int ny, double dx, double dy,
+                       double *acc, hipStream_t s);
 void launch_diag_counts(const int32_t *cnt, const int32_t *mcount, int n_tiles,
                         unsigned long long *acc, hipStream_t s);
 

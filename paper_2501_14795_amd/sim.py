@@ -142,6 +142,41 @@ class _SimView:
         out["ix"], out["iy"] = unpack_cells(out["cell"])
         return out
 
+    def get_state(self) -> Dict[str, object]:
+        """Host copy of the step-to-step state through pic_get_state:
+        {"fields": (9, ny, nx) float32, "species": [{cell, x, y, ux, uy, uz}]}."""
+        cfg = self.buf.cfg
+        hs = _lib.pic_host_state()
+        out = {"fields": np.empty((9, self.ny, self.nx), np.float32), "species": []}
+        hs.fields = out["fields"].ctypes.data
+        for k in range(cfg.n_species):
+            n = int(cfg.species[k].n)
+            arrs = {name: np.empty(n, np.int32 if name == "cell" else np.float32) for name in PARTICLE_FIELDS}
+            for name in PARTICLE_FIELDS:
+                setattr(hs.sp[k], name, arrs[name].ctypes.data if n else None)
+            out["species"].append(arrs)
+        _lib.pic_get_state(self.handle, hs, self.s)
+        return out
+
+    def set_state(self, state: Dict[str, object]):
+        """Load a state of the form get_state() returns (pic_set_state)."""
+        cfg = self.buf.cfg
+        hs = _lib.pic_host_state()
+        keep = [np.ascontiguousarray(state["fields"], np.float32)]
+        if keep[0].shape != (9, self.ny, self.nx):
+            raise ValueError("fields must be (9, ny, nx)")
+        hs.fields = keep[0].ctypes.data
+        for k in range(cfg.n_species):
+            sp = state["species"][k]
+            for name in PARTICLE_FIELDS:
+                a = np.ascontiguousarray(sp[name], np.int32 if name == "cell" else np.float32)
+                if a.size != int(cfg.species[k].n):
+                    raise ValueError(f"species {k}: {name} has {a.size} entries, the config {cfg.species[k].n}")
+                keep.append(a)
+                setattr(hs.sp[k], name, a.ctypes.data if a.size else None)
+        self.stream.synchronize()
+        _lib.pic_set_state(self.handle, hs, self.s)
+
     def field_arrays(self) -> Dict[str, np.ndarray]:
         self.stream.synchronize()
         f = self.fields.cpu().numpy()

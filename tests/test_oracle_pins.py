@@ -363,3 +363,54 @@ def test_langmuir_frequency_leapfrog(ora):
     tot = np.array(ue) + np.array(uk)
     swing = np.ptp(ue)
     assert np.ptp(tot) < 5e-3 * swing
+
+
+# ---------------------------------------------------------------- divergence diagnostics
+def test_divergences_closed_form(ora):
+    """The oracle's div E (at the nodes) and div B (at the cell centres) of
+    single Fourier modes sampled at their staggered points equal the exact
+    centred difference 2 sin(k d/2)/d times the mode at the divergence point."""
+    nx, ny, dx, dy = 32, 24, 0.1, 0.2
+    kx, ky = 2 * math.pi * 3 / (nx * dx), 2 * math.pi * 2 / (ny * dy)
+    ii, jj = np.meshgrid(np.arange(nx), np.arange(ny))
+
+    def sample(comp, f):
+        sx, sy = STAGGER[comp]
+        return f((ii + sx) * dx, (jj + sy) * dy)
+
+    E = np.zeros((3, ny, nx))
+    E[0] = sample(0, lambda X, Y: np.sin(kx * X))
+    E[1] = sample(1, lambda X, Y: np.cos(ky * Y + 0.3))
+    E[2] = 7.0                                     # Ez does not enter div E in 2D
+    want = (2 * math.sin(kx * dx / 2) / dx * np.cos(kx * ii * dx)
+            - 2 * math.sin(ky * dy / 2) / dy * np.sin(ky * jj * dy + 0.3))
+    np.testing.assert_allclose(ora.div_e(nx, ny, dx, dy, E), want, atol=1e-11)
+
+    B = np.zeros((3, ny, nx))
+    B[0] = sample(3, lambda X, Y: np.cos(kx * X - 0.7))
+    B[1] = sample(4, lambda X, Y: np.sin(ky * Y))
+    B[2] = -5.0
+    Xc, Yc = (ii + 0.5) * dx, (jj + 0.5) * dy
+    want = (-2 * math.sin(kx * dx / 2) / dx * np.sin(kx * Xc - 0.7)
+            + 2 * math.sin(ky * dy / 2) / dy * np.cos(ky * Yc))
+    np.testing.assert_allclose(ora.div_b(nx, ny, dx, dy, B), want, atol=1e-11)
+
+
+def test_divergence_of_yee_curl_vanishes(ora):
+    """div B is unchanged by a Faraday half step from any E (div curl = 0 on the
+    Yee grid), and div E is unchanged by an Ampere step with J = 0."""
+    import pic_workloads as pw
+    nx, ny, dx, dy = 24, 16, 0.1, 0.15
+    E, B = pw.random_fields(nx, ny, 1.0, 11)
+    E = E.astype(np.float64) + np.random.default_rng(3).standard_normal((3, ny, nx))
+    B = B.astype(np.float64) + np.random.default_rng(4).standard_normal((3, ny, nx))
+    d0 = ora.div_b(nx, ny, dx, dy, B)
+    B2 = B.copy()
+    ora.yee_b(nx, ny, dx, dy, 0.05, E, B2)
+    assert np.abs(B2 - B).max() > 0.1
+    np.testing.assert_allclose(ora.div_b(nx, ny, dx, dy, B2), d0, atol=1e-11)
+    e0 = ora.div_e(nx, ny, dx, dy, E)
+    E2 = E.copy()
+    ora.yee_e(nx, ny, dx, dy, 0.05, B, np.zeros_like(B), E2)
+    assert np.abs(E2 - E).max() > 0.1
+    np.testing.assert_allclose(ora.div_e(nx, ny, dx, dy, E2), e0, atol=1e-11)
