@@ -82,6 +82,17 @@ extern "C" {
  */
 #define PIC_FLAG_J_FLOAT 1u
 
+/*
+ * Binomial current filter (pic_config.j_filter; Listing 3.1's optional
+ * smoothing of J after update_gc_add).  Each pass smooths every J component
+ * with the three-point kernel (1/4, 1/2, 1/4) along x, then along y, on the
+ * periodic grid (FP32, the two directions in one stencil).  The filter
+ * commutes with the discrete divergence, so the filtered current conserves the
+ * equally filtered charge density; pic_diag's continuity and Gauss residuals
+ * then use that filtered density.
+ */
+#define PIC_MAX_FILTER 16
+
 typedef struct pic_species {
     double qm;    /* charge-to-mass ratio q/m (electrons: -1) */
     double q;     /* charge density carried by one particle (e.g. -n0 / ppc) */
@@ -95,6 +106,7 @@ typedef struct pic_config {
     int32_t j_replicas;  /* LDS current replicas per tile: 1, 2 or 4 (0 = default) */
     int32_t n_species;   /* 1 .. PIC_MAX_SPECIES */
     uint32_t flags;      /* 0 or PIC_FLAG_J_FLOAT */
+    int32_t j_filter;    /* binomial current filter passes, 0 (off) .. PIC_MAX_FILTER */
     pic_species species[PIC_MAX_SPECIES];
 } pic_config;
 
@@ -141,7 +153,8 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
  * stage its E/B halo in LDS, interpolate, Boris-push (Eqs. 6-10), move
  * (Eq. 11), deposit the Villasenor-Buneman current of each 1/2/3-piece
  * motion into LDS (Eqs. 13-16), then write J (all species) into the J planes,
- * folding the periodic images (update_gc_add).  Also records, per tile, the
+ * folding the periodic images (update_gc_add), and apply the binomial filter
+ * if pic_config.j_filter > 0.  Also records, per tile, the
  * particles that left it, as input for pic_sort().  A particle that would move
  * one cell or more sets PIC_ERANGE (reported by pic_check()).
  */
@@ -236,7 +249,8 @@ int pic_get_tile_offsets(pic_sim *sim, int species, int32_t *host_out, hipStream
 #define PIC_KERNEL_SORT_PLAN 3    /* hole/mover pairing + mover gather */
 #define PIC_KERNEL_SORT_SCATTER 4 /* mover scatter into holes */
 #define PIC_KERNEL_FIELD 5        /* the three Yee sub-steps */
-#define PIC_N_KERNELS 6
+#define PIC_KERNEL_FILTER 6       /* binomial current filter passes */
+#define PIC_N_KERNELS 7
 
 typedef struct pic_timing_out {
     double ms_total[PIC_N_KERNELS];   /* summed event time since the last reset */
@@ -256,8 +270,8 @@ int pic_get_timing(pic_sim *sim, pic_timing_out *out);
  * count) share every kernel launch: one launch per phase of the step for the
  * whole batch, the push as a persistent grid that takes (simulation, tile)
  * work items largest-simulation-first, and optionally one captured HIP graph
- * per step.  All members must share tile, j_replicas and flags.  Results are
- * bit-identical to advancing each member alone with pic_step.
+ * per step.  All members must share tile, j_replicas, flags and j_filter.
+ * Results are bit-identical to advancing each member alone with pic_step.
  */
 typedef struct pic_batch pic_batch;
 
@@ -269,7 +283,7 @@ int pic_batch_query(int n, const pic_config *cfgs, size_t *bytes);
  * own caller-owned fields, workspace and particles).  batch_work: device
  * memory of pic_batch_query() bytes, 256-byte aligned, caller-owned.
  * Synchronises `stream`.  Errors as pic_init, or PIC_EINVAL if the members do
- * not share tile / j_replicas / flags.
+ * not share tile / j_replicas / flags / j_filter.
  */
 int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void *batch_work,
                    size_t batch_bytes, hipStream_t stream, pic_batch **out);

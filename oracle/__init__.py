@@ -17,6 +17,7 @@ Particle-Mesh Algorithms with FPGAs and OmpSs@OpenCL"):
 * ``yee_b`` / ``yee_e`` / ``OracleSim.field_advance`` -- Eqs. (19)-(20), the
                            three-step Yee update of Listing 3.1
 * ``sort_canonical``    -- strict tile re-sort (Sec. 4.3, Fig. 4.5)
+* ``binomial_filter``   -- the optional current smoothing of Listing 3.1
 * ``rho`` / energies / divergences -- diagnostics (Eq. 17, Eq. 18, Eq. 12)
 """
 from __future__ import annotations
@@ -73,6 +74,7 @@ def lib():
         L.ora_kinetic_energy.restype = _d
         L.ora_div_e.argtypes = [_i, _i, _d, _d, _p, _p]
         L.ora_div_b.argtypes = [_i, _i, _d, _d, _p, _p]
+        L.ora_binomial_filter.argtypes = [_i, _i, _i, _i64, _p]
         _lib = L
     return _lib
 
@@ -178,6 +180,15 @@ def div_b(nx, ny, dx, dy, B) -> np.ndarray:
     return out
 
 
+def binomial_filter(nx, ny, passes, F):
+    """In place: `passes` binomial (1/4, 1/2, 1/4) passes, x then y, on each
+    (ny, nx) plane of the FP64 array F (shape (ny, nx) or (k, ny, nx))."""
+    if F.dtype != np.float64 or not F.flags.c_contiguous or F.shape[-2:] != (ny, nx):
+        raise ValueError("F must be a C-contiguous float64 array of (..., ny, nx) planes")
+    lib().ora_binomial_filter(nx, ny, int(passes), F.size // (nx * ny), _ptr(F))
+    return F
+
+
 # --------------------------------------------------------------------------
 # whole-simulation driver
 # --------------------------------------------------------------------------
@@ -208,8 +219,9 @@ class OracleSpecies:
 class OracleSim:
     """Serial FP64 PIC on a periodic nx x ny grid (Listing 3.1 order)."""
 
-    def __init__(self, nx, ny, dx, dy, dt, species, E=None, B=None):
+    def __init__(self, nx, ny, dx, dy, dt, species, E=None, B=None, j_filter=0):
         self.nx, self.ny = int(nx), int(ny)
+        self.j_filter = int(j_filter)
         self.dx, self.dy, self.dt = float(dx), float(dy), float(dt)
         self.species = list(species)
         shape = (3, self.ny, self.nx)
@@ -227,6 +239,8 @@ class OracleSim:
                                    _ptr(self.E), _ptr(self.B), _ptr(self.J))
             if rc != 0:
                 raise FloatingPointError("a particle moved one cell or more (Courant condition)")
+        if self.j_filter:
+            binomial_filter(self.nx, self.ny, self.j_filter, self.J)
 
     def field_advance(self):
         lib().ora_field_advance(self.nx, self.ny, self.dx, self.dy, self.dt,
@@ -247,10 +261,14 @@ class OracleSim:
             self.sort(T)
         self.field_advance()
 
-    def rho(self):
+    def rho(self, filtered=False):
+        """Node charge density; with filtered=True smoothed by the current filter
+        (the density whose continuity the filtered current satisfies)."""
         r = np.zeros((self.ny, self.nx))
         for s in self.species:
             rho(self.nx, self.ny, s.q, s.ix, s.iy, s.x, s.y, out=r)
+        if filtered and self.j_filter:
+            binomial_filter(self.nx, self.ny, self.j_filter, r)
         return r
 
     def energies(self):

@@ -31,7 +31,8 @@ PIC_DIAG_CONTINUITY = 4
 PIC_DIAG_COUNTS = 8
 PIC_DIAG_GAUSS = 16
 
-KERNELS = ["push", "j_reduce", "sort_scan", "sort_plan", "sort_scatter", "field"]
+KERNELS = ["push", "j_reduce", "sort_scan", "sort_plan", "sort_scatter", "field", "filter"]
+PIC_MAX_FILTER = 16
 
 # every symbol the header declares
 EXPORTS = [
@@ -52,7 +53,7 @@ class pic_config(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dt", ctypes.c_double),
                 ("tile", ctypes.c_int32), ("j_replicas", ctypes.c_int32),
-                ("n_species", ctypes.c_int32), ("flags", ctypes.c_uint32),
+                ("n_species", ctypes.c_int32), ("flags", ctypes.c_uint32), ("j_filter", ctypes.c_int32),
                 ("species", pic_species * MAX_SPECIES)]
 
 
@@ -83,7 +84,7 @@ class pic_host_state(ctypes.Structure):
 
 
 class pic_timing_out(ctypes.Structure):
-    _fields_ = [("ms_total", ctypes.c_double * 6), ("launches", ctypes.c_int64 * 6)]
+    _fields_ = [("ms_total", ctypes.c_double * 7), ("launches", ctypes.c_int64 * 7)]
 
 
 class PicError(RuntimeError):

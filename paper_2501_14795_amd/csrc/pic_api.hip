@@ -19,7 +19,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t err = 0, dacc = 0, cacc = 0, jtile = 0, rho_prev = 0, rho_now = 0;
+    size_t err = 0, dacc = 0, cacc = 0, jtile = 0, rho_prev = 0, rho_now = 0, jf = 0, rho_tmp = 0;
     size_t off[kMaxSpecies][2] = {}, cnt[kMaxSpecies] = {}, leav[kMaxSpecies] = {};
     size_t hole[kMaxSpecies] = {}, stg[kMaxSpecies][6] = {}, mcount[kMaxSpecies] = {}, bsum[kMaxSpecies] = {};
     size_t lpart[kMaxSpecies][6] = {};
@@ -44,6 +44,7 @@ int validate(const pic_config *c)
     if (c->j_replicas != 0 && c->j_replicas != 1 && c->j_replicas != 2 && c->j_replicas != 4)
         return PIC_EINVAL;
     if (c->n_species < 1 || c->n_species > kMaxSpecies) return PIC_EINVAL;
+    if (c->j_filter < 0 || c->j_filter > PIC_MAX_FILTER) return PIC_EINVAL;
     {
         const int r = c->j_replicas ? c->j_replicas : default_replicas(c);
         if (push_lds_bytes(c->tile, r, j_mode(c)) > kLdsBytes) return PIC_EINVAL;
@@ -77,6 +78,10 @@ Layout make_layout(const pic_config *c)
     L.jtile = take((size_t)n_tiles * 3 * (T + 3) * (T + 3) * sizeof(float));
     L.rho_prev = take(nodes * sizeof(double));
     L.rho_now = take(nodes * sizeof(double));
+    if (c->j_filter > 0) {
+        L.jf = take(nodes * 3 * sizeof(float));      // filter ping-pong partner of the J planes
+        L.rho_tmp = take(nodes * sizeof(double));    // the same for the diagnostic density
+    }
     for (int s = 0; s < c->n_species; ++s) {
         const size_t n = (size_t)c->species[s].n;
         L.off[s][0] = take((n_tiles + 1) * sizeof(int32_t));
@@ -105,6 +110,8 @@ struct pic_sim {
     unsigned long long *cacc;
     float *jtile;
     double *rho_prev, *rho_now;
+    float *jf;          // filter partner of the J planes (j_filter > 0)
+    double *rho_tmp;    // filter partner of rho_now (j_filter > 0)
     bool have_snapshot;
     struct Sp {
         int32_t *off;    // current tile_offset
@@ -246,11 +253,29 @@ PushArgs push_args(const pic_sim *S)
     return a;
 }
 
+float *j_planes(const pic_sim *S) { return S->buf.fields + (int64_t)6 * S->cfg.nx * S->cfg.ny; }
+
+// The filter passes alternate between the J planes and jf; the tile fold
+// writes to whichever of the two makes the last pass land in the J planes.
+float *j_fold_target(const pic_sim *S) { return (S->cfg.j_filter & 1) ? S->jf : j_planes(S); }
+
+FilterArgs filter_args(const pic_sim *S, int pass)
+{
+    float *first = j_fold_target(S), *second = first == S->jf ? j_planes(S) : S->jf;
+    FilterArgs f;
+    f.src = (pass & 1) ? second : first;
+    f.dst = (pass & 1) ? first : second;
+    f.nx = S->cfg.nx;
+    f.ny = S->cfg.ny;
+    f.planes = 3;
+    return f;
+}
+
 JReduceArgs jreduce_args(const pic_sim *S)
 {
     JReduceArgs r;
     r.jtile = S->jtile;
-    r.J = S->buf.fields + (int64_t)6 * S->cfg.nx * S->cfg.ny;
+    r.J = j_fold_target(S);
     r.nx = S->cfg.nx;
     r.ny = S->cfg.ny;
     r.ntx = S->ntx;
@@ -398,6 +423,8 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
     S->jtile = (float *)(w + L.jtile);
     S->rho_prev = (double *)(w + L.rho_prev);
     S->rho_now = (double *)(w + L.rho_now);
+    S->jf = cfg->j_filter > 0 ? (float *)(w + L.jf) : nullptr;
+    S->rho_tmp = cfg->j_filter > 0 ? (double *)(w + L.rho_tmp) : nullptr;
     for (int s = 0; s < cfg->n_species; ++s) {
         auto &P = S->sp[s];
         P.off = (int32_t *)(w + L.off[s][0]);
@@ -442,6 +469,10 @@ int pic_push_deposit(pic_sim *S, hipStream_t stream)
     {
         Timed t(S, PIC_KERNEL_JREDUCE, stream);
         launch_j_reduce(S->tile, jreduce_args(S), stream);
+    }
+    for (int p = 0; p < S->cfg.j_filter; ++p) {
+        Timed t(S, PIC_KERNEL_FILTER, stream);
+        launch_filter(filter_args(S, p), false, stream);
     }
     return hip_ok(hipGetLastError());
 }
@@ -505,6 +536,21 @@ int pic_diag(pic_sim *S, unsigned what, pic_diag_out *out, hipStream_t stream)
         rc = hip_ok(hipMemsetAsync(S->rho_now, 0, plane * sizeof(double), stream));
         if (rc) return rc;
         for (int s = 0; s < c.n_species; ++s) launch_diag_rho(diag_species(S, s), c.nx, c.ny, S->rho_now, stream);
+        // the density whose continuity the filtered current satisfies
+        for (int p = 0; p < c.j_filter; ++p) {
+            FilterArgs f;
+            f.src = (p & 1) ? S->rho_tmp : S->rho_now;
+            f.dst = (p & 1) ? S->rho_now : S->rho_tmp;
+            f.nx = c.nx;
+            f.ny = c.ny;
+            f.planes = 1;
+            launch_filter(f, true, stream);
+        }
+        if (c.j_filter & 1) {
+            rc = hip_ok(hipMemcpyAsync(S->rho_now, S->rho_tmp, plane * sizeof(double), hipMemcpyDeviceToDevice,
+                                       stream));
+            if (rc) return rc;
+        }
     }
     if (what & PIC_DIAG_CONTINUITY)
         launch_diag_continuity(S->rho_prev, S->rho_now, S->buf.fields + 6 * plane, c.nx, c.ny, c.dt, c.dx, c.dy,
@@ -683,6 +729,8 @@ struct pic_batch {
     JReduceArgs *d_jr;
     SortArgs *d_sort;
     FieldArgs *d_field;
+    FilterArgs *d_filter;   // 2 n: the even passes, then the odd passes
+    int j_filter;
     int4 *push_items, *node_items, *count_items, *scan_items, *plan_items;
     int n_push, n_node, n_count, n_scan, n_plan;
     int *counter;
@@ -694,7 +742,7 @@ struct pic_batch {
 namespace {
 
 struct BatchLayout {
-    size_t d_push, d_jr, d_sort, d_field, push_items, node_items, count_items, scan_items, plan_items, counter, total;
+    size_t d_push, d_jr, d_sort, d_field, d_filter, push_items, node_items, count_items, scan_items, plan_items, counter, total;
     int n_push, n_node, n_count, n_scan, n_plan;
 };
 
@@ -705,7 +753,7 @@ int batch_validate(int n, const pic_config *cfgs)
         const int rc = validate(&cfgs[i]);
         if (rc) return rc;
         if (cfgs[i].tile != cfgs[0].tile || cfgs[i].flags != cfgs[0].flags ||
-            cfgs[i].j_replicas != cfgs[0].j_replicas)
+            cfgs[i].j_replicas != cfgs[0].j_replicas || cfgs[i].j_filter != cfgs[0].j_filter)
             return PIC_EINVAL;
     }
     return PIC_OK;
@@ -734,6 +782,7 @@ BatchLayout batch_layout(int n, const pic_config *cfgs)
     L.d_jr = take(n * sizeof(JReduceArgs));
     L.d_sort = take(n * sizeof(SortArgs));
     L.d_field = take(n * sizeof(FieldArgs));
+    L.d_filter = take(2 * n * sizeof(FilterArgs));
     L.push_items = take(L.n_push * sizeof(int4));
     L.node_items = take(L.n_node * sizeof(int4));
     L.count_items = take(L.n_count * sizeof(int4));
@@ -750,6 +799,8 @@ void batch_enqueue_step(pic_batch *b, hipStream_t stream)
     launch_push_batch(b->tile, b->replicas, b->jm, b->d_push, b->push_items, b->n_push, b->counter, b->push_grid,
                       stream);
     launch_j_reduce_batch(b->tile, b->d_jr, b->node_items, b->n_node, stream);
+    for (int p = 0; p < b->j_filter; ++p)
+        launch_filter_batch(b->d_filter + (p & 1) * b->sims.size(), b->node_items, b->n_node, stream);
     SortBatch sb;
     sb.descs = b->d_sort;
     sb.count_items = b->count_items;
@@ -797,6 +848,7 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
         B->sims.push_back(S);
     }
     B->tile = cfgs[0].tile;
+    B->j_filter = cfgs[0].j_filter;
     B->jm = j_mode(&cfgs[0]);
     B->replicas = cfgs[0].j_replicas ? cfgs[0].j_replicas : default_replicas(&cfgs[0]);
     char *d = (char *)batch_work;
@@ -805,6 +857,7 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
     B->d_jr = (JReduceArgs *)(d + L.d_jr);
     B->d_sort = (SortArgs *)(d + L.d_sort);
     B->d_field = (FieldArgs *)(d + L.d_field);
+    B->d_filter = (FilterArgs *)(d + L.d_filter);
     B->push_items = (int4 *)(d + L.push_items);
     B->node_items = (int4 *)(d + L.node_items);
     B->count_items = (int4 *)(d + L.count_items);
@@ -822,6 +875,7 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
     std::vector<JReduceArgs> hj(n);
     std::vector<SortArgs> hs(n);
     std::vector<FieldArgs> hf(n);
+    std::vector<FilterArgs> hfl(2 * n);
     std::vector<int4> push_items, node_items, count_items, scan_items, plan_items;
     std::vector<std::pair<double, int>> cost(n);
     for (int i = 0; i < n; ++i) {
@@ -830,6 +884,8 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
         hj[i] = jreduce_args(S);
         hs[i] = sort_args(S);
         hf[i] = field_args(S);
+        hfl[i] = filter_args(S, 0);
+        hfl[n + i] = filter_args(S, 1);
         int64_t np = 0;
         for (int s = 0; s < S->cfg.n_species; ++s) np += S->cfg.species[s].n;
         cost[i] = {-(double)np / S->n_tiles, i};   // particles per tile, largest first
@@ -853,6 +909,7 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
     up(B->d_jr, hj.data(), n * sizeof(JReduceArgs));
     up(B->d_sort, hs.data(), n * sizeof(SortArgs));
     up(B->d_field, hf.data(), n * sizeof(FieldArgs));
+    up(B->d_filter, hfl.data(), 2 * n * sizeof(FilterArgs));
     up(B->push_items, push_items.data(), push_items.size() * sizeof(int4));
     up(B->node_items, node_items.data(), node_items.size() * sizeof(int4));
     up(B->count_items, count_items.data(), count_items.size() * sizeof(int4));

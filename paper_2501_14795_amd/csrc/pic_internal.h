@@ -129,6 +129,13 @@ struct JReduceArgs {
     int nx, ny, ntx, nty;
 };
 
+// one binomial filter pass: `planes` planes of nx x ny values (float or double)
+struct FilterArgs {
+    const void *src;
+    void *dst;
+    int nx, ny, planes;
+};
+
 struct FieldArgs {
     float *fld;
     int nx, ny;
@@ -159,6 +166,8 @@ struct SortBatch {
 void launch_sort_batch(const SortBatch &b, hipStream_t s);
 void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile, int ntx,
                        int32_t *counts, int n_tiles, int32_t *off, int *err, hipStream_t s);
+void launch_filter(const FilterArgs &a, bool fp64, hipStream_t s);
+void launch_filter_batch(const FilterArgs *descs, const int4 *items, int n_items, hipStream_t s);
 void launch_field_advance(const FieldArgs &f, hipStream_t s);
 void launch_field_advance_batch(const FieldArgs *descs, const int4 *items, int n_items, hipStream_t s);
 

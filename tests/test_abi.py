@@ -61,9 +61,10 @@ int main(void) {
     assert [int(v) for v in got] == want
 
 
-def _cfg(L, nx=64, ny=64, dx=0.1, dy=0.1, dt=0.07, tile=16, n=1000, ns=1, reps=0, flags=0):
+def _cfg(L, nx=64, ny=64, dx=0.1, dy=0.1, dt=0.07, tile=16, n=1000, ns=1, reps=0, flags=0, filt=0):
     c = L.pic_config()
     c.nx, c.ny, c.dx, c.dy, c.dt, c.tile, c.j_replicas, c.n_species, c.flags = nx, ny, dx, dy, dt, tile, reps, ns, flags
+    c.j_filter = filt
     for k in range(ns):
         c.species[k].qm = -1.0
         c.species[k].q = -1.0 / 16
@@ -94,6 +95,8 @@ def test_query_sizes_and_validation():
         (dict(nx=64, tile=32, reps=4), L.PIC_EINVAL),   # int64 current x 4 replicas > LDS
         (dict(n=-1), L.PIC_EINVAL),
         (dict(n=2 ** 31), L.PIC_EINVAL),
+        (dict(filt=-1), L.PIC_EINVAL),
+        (dict(filt=L.PIC_MAX_FILTER + 1), L.PIC_EINVAL),
     ]
     for kw, code in cases:
         ns = kw.pop("ns", 1)
@@ -105,6 +108,9 @@ def test_query_sizes_and_validation():
         assert e.value.code == code, (kw, e.value.code)
     assert L.pic_query(_cfg(L, dt=0.0707)).n_tiles == 16
     assert L.pic_query(_cfg(L, nx=64, tile=32, reps=4, flags=L.PIC_FLAG_J_FLOAT)).n_tiles == 4
+    # the filter's ping-pong planes: three FP32 current planes + one FP64 density plane
+    sf = L.pic_query(_cfg(L, filt=L.PIC_MAX_FILTER))
+    assert 20 * 64 * 64 <= sf.work_bytes - s.work_bytes <= 20 * 64 * 64 + 2 * 256
     for code in range(0, -10, -1):
         assert L.strerror(code) != "unknown error"
     assert L.strerror(-99) == "unknown error"
@@ -125,7 +131,7 @@ def test_batch_query_validation():
     nb = L.pic_batch_query(cfgs)
     assert nb > 0
     for bad in ([_cfg(L), _cfg(L, tile=8)], [_cfg(L), _cfg(L, flags=L.PIC_FLAG_J_FLOAT)],
-                [_cfg(L), _cfg(L, reps=2)]):
+                [_cfg(L), _cfg(L, reps=2)], [_cfg(L), _cfg(L, filt=1)]):
         with pytest.raises(L.PicError) as e:
             L.pic_batch_query(bad)
         assert e.value.code == L.PIC_EINVAL

@@ -414,3 +414,47 @@ def test_divergence_of_yee_curl_vanishes(ora):
     ora.yee_e(nx, ny, dx, dy, 0.05, B, np.zeros_like(B), E2)
     assert np.abs(E2 - E).max() > 0.1
     np.testing.assert_allclose(ora.div_e(nx, ny, dx, dy, E2), e0, atol=1e-11)
+
+
+# ---------------------------------------------------------------- binomial current filter
+def test_binomial_filter_fourier_response(ora):
+    """Every periodic Fourier mode is an eigenvector of the binomial (1/4, 1/2,
+    1/4) pass along x then y, with eigenvalue cos^2(pi m/nx) cos^2(pi l/ny);
+    `passes` passes raise it to that power.  The Nyquist mode is removed, the
+    mean is kept."""
+    nx, ny = 24, 16
+    ii, jj = np.meshgrid(np.arange(nx), np.arange(ny))
+    for passes in (1, 2, 3):
+        modes = [(1, 0, 0.3), (3, 5, -1.1), (nx // 2, 2, 0.0)]
+        F = np.stack([np.cos(2 * math.pi * (m * ii / nx + l * jj / ny) + ph) for m, l, ph in modes])
+        want = np.stack([(math.cos(math.pi * m / nx) ** 2 * math.cos(math.pi * l / ny) ** 2) ** passes * F[k]
+                         for k, (m, l, _) in enumerate(modes)])
+        ora.binomial_filter(nx, ny, passes, F)
+        np.testing.assert_allclose(F, want, atol=1e-14)
+    G = np.random.default_rng(5).standard_normal((ny, nx)) + 3.0
+    s0 = G.sum()
+    ora.binomial_filter(nx, ny, 4, G)
+    assert abs(G.sum() - s0) < 1e-11
+
+
+def test_filtered_current_keeps_continuity(ora):
+    """The filter commutes with the discrete divergence, so the filtered current
+    satisfies Eq. (12) exactly with the equally filtered charge density, and
+    Gauss's law with it stays at its initial residual."""
+    sim = _thermal_sim(ora, fields=True)
+    sim.j_filter = 2
+    s = sim.species[0]
+    g0 = div_edge(sim.E, sim.dx, sim.dy) - sim.rho(filtered=True)
+    for _ in range(3):
+        r0 = sim.rho(filtered=True)
+        raw0 = node_charge(sim.nx, sim.ny, s.q, s.ix + s.x, s.iy + s.y)
+        sim.push_deposit()
+        r1 = sim.rho(filtered=True)
+        res = r1 - r0 + sim.dt * div_edge(sim.J, sim.dx, sim.dy)
+        assert np.abs(res).max() < 1e-13 * np.abs(r1).max()
+        # the plain node charge does not satisfy it with the filtered current
+        raw1 = node_charge(sim.nx, sim.ny, s.q, s.ix + s.x, s.iy + s.y)
+        assert np.abs(raw1 - raw0 + sim.dt * div_edge(sim.J, sim.dx, sim.dy)).max() > 1e-4 * np.abs(r1).max()
+        sim.field_advance()
+    g = div_edge(sim.E, sim.dx, sim.dy) - sim.rho(filtered=True)
+    assert np.abs(g - g0).max() < 1e-11
