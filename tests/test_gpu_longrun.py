@@ -1,0 +1,132 @@
+"""Long-run precision: the cold Langmuir oscillation (initial state and oracle
+reference history: tests/golden/langmuir_fixture.py).
+
+* 1024 x 1024 cells, 33.5 M particles, 10,000 steps on the GPU:
+  - the Ex mode amplitude follows the FP64 oracle's history of the same
+    x-structure (1024 x 16 cells) step by step up to step 1,500;
+  - its frequency, fitted over the first 1,000 steps, equals the oracle's and
+    the leapfrog closed form w = (2/dt) asin(w_p dt/2) up to the O((k dx)^2)
+    grid correction, and resolves the leapfrog shift from w_p;
+  - the discrete continuity residual (Eq. 12, FP64 device reduction) stays at
+    round-off every 1,000 steps;
+  - the run stays exactly one-dimensional (B, u_y and the y-variation of E are
+    exactly zero) -- the fixed-point current sums make every row identical;
+  - the total energy follows the oracle's (scaled by the area) to 2e-5 up to
+    step 1,250; later the cold plasma heats (the FP64 oracle heats the same
+    way, from round-off) and the two histories agree statistically.
+* The same x-structure on 1024 x 16 cells for 200 steps, GPU FP32 against the
+  FP64 oracle from the same initial state: the error table for E, B, J and the
+  total energy.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from _parity import flush, rel_err
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+from langmuir_fixture import DT, DX, langmuir_state, mode_weights, read_fixture  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def test_langmuir_long_run_full_size():
+    import torch
+    from paper_2501_14795_amd import Sim, _lib
+    nx = ny = 1024
+    spec, st, E = langmuir_state(nx, ny, 16)
+    sim = Sim(nx, ny, DX, DX, DT, 16, [(spec.qm, spec.q, st)], E=E.astype(np.float32))
+    del st
+    w = torch.tensor(mode_weights(nx), dtype=torch.float64, device="cuda")
+    ref = read_fixture()
+    area = ny / 16.0                       # the fixture is 1024 x 16 cells
+    steps, every = 10000, 5
+    amps, times, energy, cont = [], [], {}, []
+    for n in range(1, steps + 1):
+        if n % 1000 == 1:
+            sim.diag(_lib.PIC_DIAG_RHO_SNAPSHOT)
+            sim.push_deposit()
+            d = sim.diag(_lib.PIC_DIAG_CONTINUITY)
+            cont.append(d.continuity_max / d.rho_max)
+            sim.sort()
+            sim.field_advance()
+        else:
+            sim.step()
+        if n % every == 0 and n <= 1500:
+            amps.append((sim.fields[0, 0].double() * w).sum())
+            times.append(n * DT)
+        if n % 250 == 0:
+            d = sim.diag(_lib.PIC_DIAG_ENERGY)
+            energy[n] = d.u_e + d.u_b + d.u_k[0]
+            if n in ref:
+                flush(f"step {n}: U = {energy[n]:.6e}, oracle (x{area:.0f}) {ref[n][0] * area:.6e}, "
+                      f"ratio {energy[n] / (ref[n][0] * area):.6f}")
+    assert sim.check() == 0
+    assert sim.fields[3:6].abs().max().item() == 0.0
+    assert sim.particles[0]["uy"].abs().max().item() == 0.0
+    assert sim.fields[0].std(dim=0).max().item() == 0.0
+    a = torch.stack(amps).cpu().numpy()
+    t = np.array(times)
+    a_ref = np.array([ref[int(round(x / DT))][3] for x in t])
+    scale = np.abs(a_ref).max()
+    for upto in (500, 1000, 1500):
+        m = t <= upto * DT + 1e-9
+        flush(f"Ex mode up to step {upto}: max |gpu - oracle| / max|oracle| = "
+              f"{np.abs(a[m] - a_ref[m]).max() / scale:.2e}")
+    assert np.abs(a - a_ref).max() <= 2e-3 * scale
+    from scipy.optimize import curve_fit
+
+    def fit(y):
+        m = t <= 1000 * DT + 1e-9
+        p, _ = curve_fit(lambda t, A, B, om: A * np.cos(om * t) + B * np.sin(om * t), t[m], y[m],
+                         p0=[y[0], 0.0, 1.0])
+        return p[2]
+
+    w_gpu, w_ora = fit(a), fit(a_ref)
+    w_theory = 2 / DT * math.asin(DT / 2)
+    kdx2 = (2 * math.pi / nx) ** 2
+    flush(f"omega gpu {w_gpu:.8f} oracle {w_ora:.8f} theory {w_theory:.8f} (gpu/theory - 1 = "
+          f"{w_gpu / w_theory - 1:.2e}, (k dx)^2 = {kdx2:.1e}); continuity max {max(cont):.2e}; "
+          f"energy {energy[250]:.4e} -> {energy[steps]:.4e}")
+    assert abs(w_gpu - w_ora) < 2e-6
+    assert abs(w_gpu / w_theory - 1) < 2 * kdx2
+    assert abs(w_gpu - 1.0) > 1e-4          # the leapfrog shift (2e-4) is resolved
+    assert max(cont) < 1e-6
+    for n, r in ref.items():
+        if n % 250:
+            continue
+        ratio = energy[n] / (r[0] * area)
+        assert abs(ratio - 1) < (2e-5 if n <= 1250 else 0.25), (n, ratio)
+    sim.close()
+
+
+def test_langmuir_error_table_against_oracle():
+    """Same initial state on both sides; errors relative to the oracle's max."""
+    from paper_2501_14795_amd import Sim, _lib
+    nx, ny = 1024, 16
+    spec, st, E = langmuir_state(nx, ny, 16)
+    sim = Sim(nx, ny, DX, DX, DT, 16, [(spec.qm, spec.q, st)], E=E.astype(np.float32))
+    osp = oracle.OracleSpecies(spec.qm, spec.q, st["ix"], st["iy"], st["x"], st["y"], st["ux"], st["uy"], st["uz"])
+    ora = oracle.OracleSim(nx, ny, DX, DX, DT, [osp], E.astype(np.float32).astype(np.float64))
+    rows = []
+    for n in range(1, 201):
+        sim.step()
+        ora.step(T=16)
+        if n % 50 == 0:
+            f = sim.field_arrays()
+            d = sim.diag(_lib.PIC_DIAG_ENERGY)
+            ue, ub, uk = ora.energies()
+            tot_g, tot_o = d.u_e + d.u_b + d.u_k[0], ue + ub + uk[0]
+            rows.append((n, rel_err(f["E"], ora.E), np.abs(f["B"]).max(), rel_err(f["J"], ora.J),
+                         abs(tot_g - tot_o) / tot_o))
+    flush("step  E rel err   max|B| (oracle: 0)   J rel err   total energy rel err")
+    for r in rows:
+        flush(f"{r[0]:4d}  {r[1]:.2e}    {r[2]:.2e}            {r[3]:.2e}    {r[4]:.2e}")
+    assert sim.check() == 0
+    assert all(r[1] < 1e-4 and r[3] < 1e-4 and r[4] < 1e-5 for r in rows)
+    assert np.abs(ora.B).max() < 1e-12 and rows[-1][2] == 0.0
+    sim.close()
