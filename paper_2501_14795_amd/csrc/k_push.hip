@@ -13,11 +13,15 @@
 //   3. per particle: bilinear interpolation at the staggered points
 //      (Sec. 3.1), Boris push (Eqs. 6-10), move (Eq. 11), and the
 //      Villasenor-Buneman current (Eqs. 13-16) of each of the 1, 2 or 3 pieces
-//      of the motion (Figs. 3.4-3.5), added into the LDS current of the tile:
+//      of the motion (Figs. 3.4-3.5), added into the LDS current of the tile
+//      (the first piece at once; the second and third -- present for the ~15%
+//      of particles that cross a cell face -- through a per-wavefront LDS
+//      queue drained 64 pieces at a time, so a wavefront does not run the
+//      deposit three times when a few of its lanes cross):
 //        kJFixed  exact int64 fixed point (ds_add_u64): every contribution is
-//                 rounded once to 2^-24 of the largest possible contribution,
-//                 the sums are exact, so J does not depend on the order of
-//                 the additions -- bit-reproducible from run to run;
+//                 rounded once, to within 2^-23 of the largest possible
+//                 contribution, the sums are exact, so J does not depend on
+//                 the order of the additions -- bit-reproducible;
 //        kJFloat  FP32 ds_add_f32 into one of R replicas (lane mod R), the
 //                 replicas summed with compensation at the end.  Kept as the
 //                 reference mode: on gfx950 FP32 LDS atomics are several times
@@ -117,23 +121,29 @@ struct JAcc<kJFloat> {
     }
 };
 
-// Current of one piece of the motion inside cell (cx, cy) (tile-relative,
-// -1..T), from (xa, ya) to (xb, yb) in that cell's frame, lasting `frac` of
-// the step, in accumulator units (fq = particle charge in those units).
-// Jx/Jy: the Villasenor-Buneman face fluxes; Jz: fq vz frac times the exact
+// LDS index of tile-relative cell (cx, cy) in the (T+3)^2 current halo.
+template <int NJ>
+__device__ __forceinline__ int jcell(int cx, int cy)
+{
+    return __mul24(cy + 1, NJ) + (cx + 1);   // 24-bit multiply: full rate
+}
+
+// Current of one piece of the motion inside the cell at halo index b, from
+// (xa, ya) to (xb, yb) in that cell's frame, in accumulator units (fq =
+// particle charge in those units; az = fq vz times the piece's share of the
+// step).  Jx/Jy: the Villasenor-Buneman face fluxes; Jz: az times the exact
 // time average of each corner's bilinear weight, w_mid +- dxk dyk / 12.
 template <int NJ, int JM>
-__device__ __forceinline__ void deposit_piece(typename JAcc<JM>::T *sj, int cx, int cy, float xa, float ya,
-                                              float xb, float yb, float frac, float fq, float fqvz)
+__device__ __forceinline__ void deposit_piece(typename JAcc<JM>::T *sj, int b, float xa, float ya, float xb,
+                                              float yb, float az, float fq)
 {
     constexpr int P = NJ * NJ;
     using A = JAcc<JM>;
     const float dxk = xb - xa, dyk = yb - ya;
     const float xm = 0.5f * (xa + xb), ym = 0.5f * (ya + yb);
-    const float ax = fq * dxk, ay = fq * dyk, az = fqvz * frac;
+    const float ax = fq * dxk, ay = fq * dyk;
     const float c = dxk * dyk * (1.0f / 12.0f);
     const float xm1 = 1.0f - xm, ym1 = 1.0f - ym;
-    const int b = __mul24(cy + 1, NJ) + (cx + 1);   // 24-bit multiply: full rate
     A::add(&sj[b], ax, ym1);
     A::add(&sj[b + NJ], ax, ym);
     A::add(&sj[P + b], ay, xm1);
@@ -142,6 +152,47 @@ __device__ __forceinline__ void deposit_piece(typename JAcc<JM>::T *sj, int cx, 
     A::add(&sj[2 * P + b + 1], az, fmaf(xm, ym1, -c));
     A::add(&sj[2 * P + b + NJ], az, fmaf(xm1, ym, -c));
     A::add(&sj[2 * P + b + NJ + 1], az, fmaf(xm, ym, c));
+}
+
+// The wavefront's queue of second and third pieces: kPieceBuf entries of
+// (halo index, xa, ya, xb, yb, az).
+
+template <int NJ, int JM>
+__device__ __forceinline__ void drain_pieces(typename JAcc<JM>::T *sj, uint32_t (*pq)[kPieceBuf], int n,
+                                             float fq, int lane)
+{
+    __builtin_amdgcn_wave_barrier();
+    if (lane < n)
+        deposit_piece<NJ, JM>(sj, (int)pq[0][lane], __uint_as_float(pq[1][lane]), __uint_as_float(pq[2][lane]),
+                              __uint_as_float(pq[3][lane]), __uint_as_float(pq[4][lane]),
+                              __uint_as_float(pq[5][lane]), fq);
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Append the pieces of the lanes with `has` set to the queue (slot order by
+// lane), draining it first if they do not fit.  n: queue fill, uniform.
+template <int NJ, int JM>
+__device__ __forceinline__ void queue_piece(typename JAcc<JM>::T *sj, uint32_t (*pq)[kPieceBuf], int &n, bool has,
+                                            int b, float xa, float ya, float xb, float yb, float az, float fq,
+                                            int lane)
+{
+    const unsigned long long m = __ballot(has);
+    const int c = __popcll(m);
+    if (c == 0) return;
+    if (n + c > kPieceBuf) {
+        drain_pieces<NJ, JM>(sj, pq, n, fq, lane);
+        n = 0;
+    }
+    if (has) {
+        const int r = n + lane_rank(m);
+        pq[0][r] = (uint32_t)b;
+        pq[1][r] = __float_as_uint(xa);
+        pq[2][r] = __float_as_uint(ya);
+        pq[3][r] = __float_as_uint(xb);
+        pq[4][r] = __float_as_uint(yb);
+        pq[5][r] = __float_as_uint(az);
+    }
+    n += c;
 }
 
 // Write the n leavers buffered in LDS by one wavefront to the leaver list
@@ -182,6 +233,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
     __shared__ int s_dir[kMaxSpecies][9];
     __shared__ int s_wl[kMaxSpecies][kWaves];
     __shared__ uint32_t s_lb[kWaves][7][kLeaverBuf];   // leaver entry + new particle data
+    __shared__ uint32_t s_pq[kWaves][6][kPieceBuf];    // queued second / third pieces
 
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int gx0 = tx * T, gy0 = ty * T;
@@ -226,6 +278,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             st.uz = rsrc(sp.uz + base, bytes);
             const float h = sp.h, fq = sp.fq;
             int nbuf = 0;   // leavers waiting in the wavefront's LDS buffer (uniform)
+            int npq = 0;    // pieces waiting in the wavefront's queue (uniform)
             // Loads past the section end return 0; lanes before it read the
             // previous tile's particles and discard them.  The next chunk is
             // always prefetched before the current one is processed.
@@ -248,6 +301,11 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                 bool leaver = false;
                 int dir = 4, ncell = 0;
                 float xn = 0.0f, yn = 0.0f;
+                // second and third pieces of the motion, queued below
+                bool has1 = false, has2 = false;
+                int qb1 = 0, qb2 = 0;
+                float xa1 = 0.0f, ya1 = 0.0f, xb1 = 0.0f, yb1 = 0.0f, az1 = 0.0f;
+                float xa2 = 0.0f, ya2 = 0.0f, xb2 = 0.0f, yb2 = 0.0f, az2 = 0.0f;
                 if (i >= lo && i < hi) {
                     int lx = (cell & 0xffff) - gx0, ly = (cell >> 16) - gy0;
                     if ((unsigned)lx >= (unsigned)T || (unsigned)ly >= (unsigned)T) {
@@ -303,7 +361,10 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                     const int sxn = x1 >= 1.0f ? 1 : (x1 < 0.0f ? -1 : 0);
                     const int syn = y1 >= 1.0f ? 1 : (y1 < 0.0f ? -1 : 0);
 
-                    // ---- Villasenor-Buneman deposit of the 1, 2 or 3 pieces
+                    // ---- Villasenor-Buneman deposit of the 1, 2 or 3 pieces: the
+                    // motion is cut at the face crossings in time order; piece k
+                    // lies in the cell reached after k crossings, in whose frame
+                    // its endpoints are taken
                     {
                         const float ex = sxn > 0 ? 1.0f : 0.0f;   // x face crossed (start-cell frame)
                         const float ey = syn > 0 ? 1.0f : 0.0f;
@@ -314,38 +375,38 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                         const float t2 = xfirst ? tcy : tcx;
                         const int nseg = 1 + (sxn != 0) + (syn != 0);
                         const float fqvz = fq * uz * ig;
-                        float ax_ = x, ay_ = y, ta = 0.0f;
-                        int ox = 0, oy = 0;
-#pragma unroll
-                        for (int p = 0; p < 3; ++p) {
-                            if (p < nseg) {
-                                float tb, bx, by;
-                                int nox = ox, noy = oy;
-                                if (p == nseg - 1) {
-                                    tb = 1.0f;
-                                    bx = x1;
-                                    by = y1;
-                                } else {
-                                    const bool xev = (p == 0) ? xfirst : !xfirst;
-                                    tb = (p == 0) ? t1 : t2;
-                                    if (xev) {
-                                        bx = ex;
-                                        by = fmaf(tb, dY, y);
-                                        nox = ox + sxn;
-                                    } else {
-                                        bx = fmaf(tb, dX, x);
-                                        by = ey;
-                                        noy = oy + syn;
-                                    }
-                                }
-                                deposit_piece<NJ, JM>(sj, lx + ox, ly + oy, clamp01(ax_ - ox), clamp01(ay_ - oy),
-                                                      clamp01(bx - ox), clamp01(by - oy), tb - ta, fq, fqvz);
-                                ax_ = bx;
-                                ay_ = by;
-                                ta = tb;
-                                ox = nox;
-                                oy = noy;
-                            }
+                        // crossing points (start-cell frame)
+                        const float p1x = xfirst ? ex : fmaf(t1, dX, x);
+                        const float p1y = xfirst ? fmaf(t1, dY, y) : ey;
+                        const float p2x = xfirst ? fmaf(t2, dX, x) : ex;
+                        const float p2y = xfirst ? ey : fmaf(t2, dY, y);
+                        // piece 0, in the start cell
+                        const float e0x = nseg == 1 ? x1 : p1x, e0y = nseg == 1 ? y1 : p1y;
+                        const float f0 = nseg == 1 ? 1.0f : t1;
+                        deposit_piece<NJ, JM>(sj, jcell<NJ>(lx, ly), clamp01(x), clamp01(y), clamp01(e0x),
+                                              clamp01(e0y), fqvz * (f0 - 0.0f), fq);
+                        // piece 1, after the first crossing
+                        if (nseg >= 2) {
+                            const int ox = xfirst ? sxn : 0, oy = xfirst ? 0 : syn;
+                            const float e1x = nseg == 2 ? x1 : p2x, e1y = nseg == 2 ? y1 : p2y;
+                            const float f1 = nseg == 2 ? 1.0f : t2;
+                            has1 = true;
+                            qb1 = jcell<NJ>(lx + ox, ly + oy);
+                            xa1 = clamp01(p1x - ox);
+                            ya1 = clamp01(p1y - oy);
+                            xb1 = clamp01(e1x - ox);
+                            yb1 = clamp01(e1y - oy);
+                            az1 = fqvz * (f1 - t1);
+                        }
+                        // piece 2, after both crossings
+                        if (nseg == 3) {
+                            has2 = true;
+                            qb2 = jcell<NJ>(lx + sxn, ly + syn);
+                            xa2 = clamp01(p2x - sxn);
+                            ya2 = clamp01(p2y - syn);
+                            xb2 = clamp01(x1 - sxn);
+                            yb2 = clamp01(y1 - syn);
+                            az2 = fqvz * (1.0f - t2);
                         }
                     }
 
@@ -389,6 +450,8 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                     dir = (dty + 1) * 3 + (dtx + 1);
                     leaver = dir != 4;
                 }
+                queue_piece<NJ, JM>(sj, s_pq[wave], npq, has1, qb1, xa1, ya1, xb1, yb1, az1, fq, lane);
+                queue_piece<NJ, JM>(sj, s_pq[wave], npq, has2, qb2, xa2, ya2, xb2, yb2, az2, fq, lane);
                 // leavers go to the wavefront's LDS buffer in slot order; a full
                 // buffer is written out as whole cache lines
                 const unsigned long long m = __ballot(leaver);
@@ -413,6 +476,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                     nbuf += c;
                 }
             }
+            drain_pieces<NJ, JM>(sj, s_pq[wave], npq, fq, lane);
             flush_leavers(sp, s_lb[wave], nbuf, (int64_t)lo + nleav, lane);
             nleav += nbuf;
         }

@@ -46,12 +46,15 @@ constexpr float kFixedScale = 4194304.0f;
 
 constexpr int kLdsBytes = 160 * 1024;   // LDS of one gfx950 compute unit
 constexpr int kLeaverBuf = 64;           // leavers buffered per wavefront before a write-out
+constexpr int kPieceBuf = 64;            // queued second / third motion pieces per wavefront
+// one ballot can add a whole wavefront to either buffer
+static_assert(kLeaverBuf >= 64 && kPieceBuf >= 64, "per-wavefront LDS buffers must hold 64 entries");
 
 // Static LDS of the push kernel for tile T, R current replicas, mode JM.
 constexpr int push_lds_bytes(int T, int R, int JM)
 {
     return (T + 2) * (T + 2) * 48 + R * 3 * (T + 3) * (T + 3) * (JM == kJFixed ? 8 : 4) +
-           kMaxSpecies * (9 + kWaves) * 4 + kWaves * 7 * kLeaverBuf * 4;
+           kMaxSpecies * (9 + kWaves) * 4 + kWaves * 7 * kLeaverBuf * 4 + kWaves * 6 * kPieceBuf * 4;
 }
 
 // One species' particles as a structure of arrays (n entries each).
