@@ -238,7 +238,9 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int gx0 = tx * T, gy0 = ty * T;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    // the wavefront index is uniform across the wavefront: keep it (and the
+    // buffer descriptors derived from it) in scalar registers
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t plane = (int64_t)a.nx * a.ny;
 
     for (int e = tid; e < NE * NE; e += kBlock) {
@@ -266,9 +268,12 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
         wave_range(begin, end, wave, lo, hi);
         int nleav = 0;   // wavefront-uniform
         if (lo < hi) {
-            // buffer views starting at the first 64-aligned slot of the section
+            // buffer views from the first 64-aligned slot of the section to the
+            // end of this wavefront's run: loads beyond it (the prefetch past
+            // the last chunk, the tail lanes of that chunk) return 0 without
+            // touching memory
             const int base = (begin >> 6) << 6;
-            const int bytes = (end - base) * 4;
+            const int bytes = (hi - base) * 4;
             Stream6 st;
             st.cell = rsrc(sp.cell + base, bytes);
             st.x = rsrc(sp.x + base, bytes);
@@ -279,9 +284,10 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             const float h = sp.h, fq = sp.fq;
             int nbuf = 0;   // leavers waiting in the wavefront's LDS buffer (uniform)
             int npq = 0;    // pieces waiting in the wavefront's queue (uniform)
-            // Loads past the section end return 0; lanes before it read the
-            // previous tile's particles and discard them.  The next chunk is
-            // always prefetched before the current one is processed.
+            // Loads past the run's end return 0; lanes before its start (first
+            // chunk of the section only) read the previous tile's particles
+            // and discard them.  The next chunk is always prefetched before
+            // the current one is processed.
             int cb = (lo >> 6) << 6;
             int off = (cb + lane - base) * 4;
             int n_cell = (int)__builtin_amdgcn_raw_buffer_load_b32(st.cell, off, 0, 0);

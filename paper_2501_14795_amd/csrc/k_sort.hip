@@ -182,7 +182,8 @@ __device__ __forceinline__ void copy_particle(const Parts &src, int64_t i, const
 __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int grp)
 {
     const int lane = threadIdx.x & 63;
-    const int t = grp * kWaves + (threadIdx.x >> 6);
+    // one tile per wavefront: the index is wavefront-uniform (scalar registers)
+    const int t = grp * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (t >= a.n_tiles) return;   // whole wavefront
     const SortSpecies &sp = a.sp[spi];
     const int ntx = a.ntx, nty = a.nty;
@@ -330,7 +331,7 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
 __device__ __forceinline__ void sort_scatter_unit(const SortArgs &a, int spi, int grp)
 {
     const int lane = threadIdx.x & 63;
-    const int t = grp * kWaves + (threadIdx.x >> 6);
+    const int t = grp * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (t >= a.n_tiles) return;
     const SortSpecies &sp = a.sp[spi];
     const int A = sp.offn[t], m = sp.mcount[t];
