@@ -131,6 +131,62 @@ def batched_comparison(n_sims=256, steps=5, tune_sims=32):
     }
 
 
+def filter_measurement(w, launches=20):
+    """One binomial current-filter pass over the workload's grid (three FP32
+    planes in, three out: 24 B per node), event-timed on a particle-free
+    simulation of the same grid with one filter pass per step."""
+    import numpy as np
+
+    from paper_2501_14795_amd import Sim
+    empty = {k: np.zeros(0, np.int32 if k in ("ix", "iy") else np.float32)
+             for k in ("ix", "iy", "x", "y", "ux", "uy", "uz")}
+    sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, w.tile, [(-1.0, -1.0, empty)], j_filter=1)
+    for _ in range(3):
+        sim.push_deposit()
+    sim.set_timing(True)
+    for _ in range(launches):
+        sim.push_deposit()
+    kt = sim.timing()
+    sim.set_timing(False)
+    sim.close()
+    ms = kt["filter"][0] / max(kt["filter"][1], 1)
+    nbytes = 24 * w.nx * w.ny
+    return {"kernel": "k_binomial_f", "grid": f"{w.nx}x{w.ny}", "pass_ms": ms, "bytes_per_pass": nbytes,
+            "achieved": nbytes / (ms * 1e-3) / 1e9, "unit": "GB/s", "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def esirkepov_measurement(w, T, steps=20, warmup=3):
+    """The same workload and step with the Esirkepov deposit (the variant
+    deposit): whole-step rate and the push kernel's event-timed duration."""
+    import torch
+
+    import pic_workloads as pw
+    from paper_2501_14795_amd import Sim
+    states = pw.workload_state(w, tile=T)
+    n = sum(s["ix"].size for s in states)
+    sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, T, [(s.qm, s.q, st) for s, st in zip(w.species, states)],
+              esirkepov=True)
+    del states
+    for _ in range(warmup):
+        sim.step()
+    torch.cuda.synchronize()
+    sim.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kt = sim.timing()
+    sim.set_timing(False)
+    rc = sim.check()
+    sim.close()
+    if rc != 0:
+        raise SystemExit("device error in the Esirkepov measurement")
+    push_ms = kt["push"][0] / max(kt["push"][1], 1)
+    return {"workload": w.name, "steps": steps, "pushes_per_s": n * steps / elapsed,
+            "ms_per_step": elapsed * 1e3 / steps, "push_kernel_ms": push_ms}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +196,10 @@ def main():
     ap.add_argument("--replicas", type=int, default=0)
     ap.add_argument("--workload", default="warm2048")
     ap.add_argument("--j-float", action="store_true", help="FP32-atomic LDS current instead of fixed point")
+    ap.add_argument("--j-filter", type=int, default=0, help="binomial current filter passes in the timed step")
+    ap.add_argument("--esirkepov", action="store_true", help="Esirkepov deposit instead of split Villasenor-Buneman")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the short measurements of the filter pass and of the Esirkepov deposit")
 
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-mode comparison")
@@ -182,7 +242,7 @@ def main():
         log(f"cpu baseline {cpu['value'] / 1e6:.2f} M push/s over {cpu['seconds']:.1f}s")
 
     sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, T, [(s.qm, s.q, st) for s, st in zip(w.species, states)],
-              j_replicas=args.replicas, j_float=args.j_float)
+              j_replicas=args.replicas, j_float=args.j_float, j_filter=args.j_filter, esirkepov=args.esirkepov)
     del states
     log("initialised")
     for _ in range(args.warmup):
@@ -242,7 +302,8 @@ def main():
                    "particles": n, "ppc": sum(s.n_ppc for s in w.species), "tile": T,
                    "j_accumulation": "fp32-atomic" if args.j_float else "int64-fixed-point",
                    "j_replicas": args.replicas or ((4 if T < 32 else 2) if args.j_float else 1),
-                   "sort_every": 1,
+                   "sort_every": 1, "j_filter": args.j_filter,
+                   "deposit": "esirkepov" if args.esirkepov else "villasenor-buneman-split",
                    "step": "push+deposit+sort+field_advance"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -261,6 +322,12 @@ def main():
     del sim
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    if not args.no_variants:
+        out["filter_pass"] = filter_measurement(w)
+        log(f"filter pass: {out['filter_pass']}")
+        if not args.esirkepov:
+            out["esirkepov"] = esirkepov_measurement(w, T)
+            log(f"esirkepov: {out['esirkepov']}")
     if not args.no_batched:
         out["batched"] = batched_comparison()
         log(f"batched: {out['batched']}")

@@ -83,6 +83,17 @@ extern "C" {
 #define PIC_FLAG_J_FLOAT 1u
 
 /*
+ * Deposit scheme (pic_config.flags).  Default: Villasenor-Buneman fluxes
+ * (Eqs. 13-16) of the 1, 2 or 3 pieces a motion is split into at cell faces
+ * (Figs. 3.4-3.5).  PIC_FLAG_ESIRKEPOV: Esirkepov's density decomposition
+ * (Comput. Phys. Commun. 135 (2001) 144) with the linear shape -- equal to the
+ * default for motions inside one cell, a different charge-conserving current
+ * on a 4 x 4 node stencil for motions that cross a face.  Fixed-point current
+ * only (PIC_EINVAL together with PIC_FLAG_J_FLOAT).
+ */
+#define PIC_FLAG_ESIRKEPOV 2u
+
+/*
  * Binomial current filter (pic_config.j_filter; Listing 3.1's optional
  * smoothing of J after update_gc_add).  Each pass smooths every J component
  * with the three-point kernel (1/4, 1/2, 1/4) along x, then along y, on the
@@ -105,7 +116,7 @@ typedef struct pic_config {
     int32_t tile;        /* tile edge in cells: 8, 16 or 32 */
     int32_t j_replicas;  /* LDS current replicas per tile: 1, 2 or 4 (0 = default) */
     int32_t n_species;   /* 1 .. PIC_MAX_SPECIES */
-    uint32_t flags;      /* 0 or PIC_FLAG_J_FLOAT */
+    uint32_t flags;      /* 0, PIC_FLAG_J_FLOAT or PIC_FLAG_ESIRKEPOV */
     int32_t j_filter;    /* binomial current filter passes, 0 (off) .. PIC_MAX_FILTER */
     pic_species species[PIC_MAX_SPECIES];
 } pic_config;

@@ -13,6 +13,8 @@ Particle-Mesh Algorithms with FPGAs and OmpSs@OpenCL"):
 * ``boris``             -- relativistic Boris push, Eqs. (6)-(10)
 * ``deposit_move``      -- Villasenor-Buneman current, Eqs. (12)-(16), with the
                            1/2/3-piece split of Figs. 3.4-3.5
+* ``deposit_esirkepov`` -- Esirkepov's charge-conserving current, the variant
+                           deposit (density decomposition, linear shape)
 * ``OracleSim.push_deposit`` -- the particle loop of Listing 3.1 + Eq. (11)
 * ``yee_b`` / ``yee_e`` / ``OracleSim.field_advance`` -- Eqs. (19)-(20), the
                            three-step Yee update of Listing 3.1
@@ -60,7 +62,8 @@ def lib():
         L.ora_interp.argtypes = [_i, _i, _p, _p, _i, _i, _d, _d, _p]
         L.ora_boris.argtypes = [_d, _d, _p, _p]
         L.ora_deposit_move.argtypes = [_i, _i, _d, _d, _d, _d, _d, _i, _i, _d, _d, _d, _d, _p]
-        L.ora_advance.argtypes = [_i, _i, _d, _d, _d, _d, _d, _i64] + [_p] * 10
+        L.ora_advance.argtypes = [_i, _i, _d, _d, _d, _d, _d, _i64] + [_p] * 10 + [_i]
+        L.ora_deposit_esirkepov.argtypes = [_i, _i, _d, _d, _d, _d, _d, _i, _i, _d, _d, _d, _d, _p]
         L.ora_advance.restype = _i
         L.ora_yee_b.argtypes = [_i, _i, _d, _d, _d, _p, _p]
         L.ora_yee_e.argtypes = [_i, _i, _d, _d, _d, _p, _p, _p]
@@ -119,6 +122,15 @@ def deposit_move(nx, ny, dx, dy, dt, q, vz, ix, iy, x, y, ddx, ddy, J=None) -> n
         J = np.zeros((3, ny, nx))
     lib().ora_deposit_move(nx, ny, dx, dy, dt, q, vz, int(ix), int(iy), float(x), float(y),
                            float(ddx), float(ddy), _ptr(J))
+    return J
+
+
+def deposit_esirkepov(nx, ny, dx, dy, dt, q, vz, ix, iy, x, y, ddx, ddy, J=None) -> np.ndarray:
+    """Esirkepov current (3, ny, nx) of one straight move by (ddx, ddy) cells."""
+    if J is None:
+        J = np.zeros((3, ny, nx))
+    lib().ora_deposit_esirkepov(nx, ny, dx, dy, dt, q, vz, int(ix), int(iy), float(x), float(y),
+                                float(ddx), float(ddy), _ptr(J))
     return J
 
 
@@ -219,9 +231,10 @@ class OracleSpecies:
 class OracleSim:
     """Serial FP64 PIC on a periodic nx x ny grid (Listing 3.1 order)."""
 
-    def __init__(self, nx, ny, dx, dy, dt, species, E=None, B=None, j_filter=0):
+    def __init__(self, nx, ny, dx, dy, dt, species, E=None, B=None, j_filter=0, esirkepov=False):
         self.nx, self.ny = int(nx), int(ny)
         self.j_filter = int(j_filter)
+        self.esirkepov = bool(esirkepov)
         self.dx, self.dy, self.dt = float(dx), float(dy), float(dt)
         self.species = list(species)
         shape = (3, self.ny, self.nx)
@@ -236,7 +249,7 @@ class OracleSim:
             rc = lib().ora_advance(self.nx, self.ny, self.dx, self.dy, self.dt, s.qm, s.q, s.n,
                                    _ptr(s.ix), _ptr(s.iy), _ptr(s.x), _ptr(s.y),
                                    _ptr(s.ux), _ptr(s.uy), _ptr(s.uz),
-                                   _ptr(self.E), _ptr(self.B), _ptr(self.J))
+                                   _ptr(self.E), _ptr(self.B), _ptr(self.J), int(self.esirkepov))
             if rc != 0:
                 raise FloatingPointError("a particle moved one cell or more (Courant condition)")
         if self.j_filter:

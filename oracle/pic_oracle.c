@@ -195,6 +195,71 @@ void ora_deposit_move(int nx, int ny, double dx, double dy, double dt,
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Esirkepov's charge-conserving current (Esirkepov, Comput. Phys. Commun.   */
+/* 135 (2001) 144), the alternative deposit to Eqs. (13)-(16) with splits:    */
+/* the change of the particle's shape-function product over the step is      */
+/* decomposed into an x part W^x and a y part W^y, and the current is their  */
+/* running sum across the stencil.  Linear (cloud-in-cell) shape.            */
+/* ------------------------------------------------------------------------ */
+
+/* Cloud-in-cell weight of a node at distance d (cells). */
+static double shape_cic(double d)
+{
+    double a = fabs(d);
+    return a < 1.0 ? 1.0 - a : 0.0;
+}
+
+/*
+ * Current of a straight motion from offset (x, y) in cell (ix, iy) by
+ * (ddx, ddy) cells, |ddx|, |ddy| < 1, on the 4 x 4 nodes ix-1 .. ix+2 (and
+ * likewise in y).  With S0, S1 the node weights before and after and
+ * DS = S1 - S0:
+ *   W^x_kl = DSx_k (S0y_l + DSy_l / 2),   W^y_kl = DSy_l (S0x_k + DSx_k / 2),
+ *   W^z_kl = S0x_k S0y_l + (DSx_k S0y_l + S0x_k DSy_l) / 2 + DSx_k DSy_l / 3,
+ * and Jx at (k + 1/2, l) = -q dx/dt sum_{k' <= k} W^x_k'l (likewise Jy),
+ * Jz at (k, l) = q vz W^z_kl.
+ */
+void ora_deposit_esirkepov(int nx, int ny, double dx, double dy, double dt,
+                           double q, double vz, int ix, int iy, double x,
+                           double y, double ddx, double ddy, double *J)
+{
+    const int64_t plane = (int64_t)nx * ny;
+    double *Jx = J, *Jy = J + plane, *Jz = J + 2 * plane;
+    double s0x[4], s1x[4], dsx[4], s0y[4], s1y[4], dsy[4];
+    for (int k = 0; k < 4; k++) {
+        double p = k - 1; /* node position relative to the starting cell */
+        s0x[k] = shape_cic(x - p);
+        s1x[k] = shape_cic(x + ddx - p);
+        dsx[k] = s1x[k] - s0x[k];
+        s0y[k] = shape_cic(y - p);
+        s1y[k] = shape_cic(y + ddy - p);
+        dsy[k] = s1y[k] - s0y[k];
+    }
+    for (int l = 0; l < 4; l++) {
+        int j = wrap(iy - 1 + l, ny);
+        double run = 0.0;
+        for (int k = 0; k < 3; k++) {
+            run -= dsx[k] * (s0y[l] + 0.5 * dsy[l]);
+            Jx[IDX(wrap(ix - 1 + k, nx), j, nx)] += q * run * dx / dt;
+        }
+    }
+    for (int k = 0; k < 4; k++) {
+        int i = wrap(ix - 1 + k, nx);
+        double run = 0.0;
+        for (int l = 0; l < 3; l++) {
+            run -= dsy[l] * (s0x[k] + 0.5 * dsx[k]);
+            Jy[IDX(i, wrap(iy - 1 + l, ny), nx)] += q * run * dy / dt;
+        }
+    }
+    for (int l = 0; l < 4; l++)
+        for (int k = 0; k < 4; k++) {
+            double w = s0x[k] * s0y[l] + 0.5 * (dsx[k] * s0y[l] + s0x[k] * dsy[l]) +
+                       dsx[k] * dsy[l] / 3.0;
+            Jz[IDX(wrap(ix - 1 + k, nx), wrap(iy - 1 + l, ny), nx)] += q * vz * w;
+        }
+}
+
 /* Move one offset coordinate by d cells and renormalise it into [0, 1). */
 static void advance_coord(int *i, double *x, double d, int n)
 {
@@ -218,13 +283,14 @@ static void advance_coord(int *i, double *x, double d, int n)
  * The particle half of one time step (Listing 3.1, the loop over particles):
  * for every particle in array order, interpolate E and B, Boris-push the
  * momentum, move the particle by Eq. (11) and deposit its current into J
- * (which the caller zeroes; contributions of all species add up).
+ * (which the caller zeroes; contributions of all species add up) --
+ * esirkepov = 0: Villasenor-Buneman with splits, 1: Esirkepov.
  * Returns 0, or -1 if a particle would move one cell or more (Eq. 1 violated).
  */
 int ora_advance(int nx, int ny, double dx, double dy, double dt, double qm,
                 double q, int64_t n, int32_t *ix, int32_t *iy, double *x,
                 double *y, double *ux, double *uy, double *uz, const double *E,
-                const double *B, double *J)
+                const double *B, double *J, int esirkepov)
 {
     for (int64_t p = 0; p < n; p++) {
         double EB[6], u[3] = {ux[p], uy[p], uz[p]};
@@ -234,8 +300,12 @@ int ora_advance(int nx, int ny, double dx, double dy, double dt, double qm,
         double ddx = u[0] / g * dt / dx; /* Eq. (11), in cells */
         double ddy = u[1] / g * dt / dy;
         if (fabs(ddx) >= 1.0 || fabs(ddy) >= 1.0) return -1;
-        ora_deposit_move(nx, ny, dx, dy, dt, q, u[2] / g, ix[p], iy[p], x[p],
-                         y[p], ddx, ddy, J);
+        if (esirkepov)
+            ora_deposit_esirkepov(nx, ny, dx, dy, dt, q, u[2] / g, ix[p], iy[p],
+                                  x[p], y[p], ddx, ddy, J);
+        else
+            ora_deposit_move(nx, ny, dx, dy, dt, q, u[2] / g, ix[p], iy[p],
+                             x[p], y[p], ddx, ddy, J);
         int i = ix[p], j = iy[p];
         double xx = x[p], yy = y[p];
         advance_coord(&i, &xx, ddx, nx);

@@ -24,6 +24,7 @@ PIC_ECOUNT = -8
 PIC_EOVERFLOW = -9
 
 PIC_FLAG_J_FLOAT = 1
+PIC_FLAG_ESIRKEPOV = 2
 
 PIC_DIAG_ENERGY = 1
 PIC_DIAG_RHO_SNAPSHOT = 2

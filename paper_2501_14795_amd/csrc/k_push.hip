@@ -154,24 +154,84 @@ __device__ __forceinline__ void deposit_piece(typename JAcc<JM>::T *sj, int b, f
     A::add(&sj[2 * P + b + NJ + 1], az, fmaf(xm, ym, c));
 }
 
-// The wavefront's queue of second and third pieces: kPieceBuf entries of
-// (halo index, xa, ya, xb, yb, az).
-
+// Esirkepov's current of a whole straight motion (the variant deposit) from
+// (x, y) in the cell at halo index b to (x1, y1) in that cell's frame
+// (x1, y1 in (-1, 2)), on the 4 x 4 nodes around it.  Node weights of the
+// linear shape before (S0) and after (S1), DS = S1 - S0:
+//   W^x_kl = DSx_k (S0y_l + DSy_l / 2)   -> Jx at (k+1/2, l) = -sum_{k'<=k} W^x
+//   W^y_kl = DSy_l (S0x_k + DSx_k / 2)   -> Jy likewise
+//   W^z_kl = S0x S0y + (DSx S0y + S0x DSy) / 2 + DSx DSy / 3
+// in accumulator units (fq: particle charge; az: fq vz for the whole step).
+// Within one cell it equals the Villasenor-Buneman piece.
 template <int NJ, int JM>
+__device__ __forceinline__ void deposit_esirkepov(typename JAcc<JM>::T *sj, int b, float x, float y, float x1,
+                                                  float y1, float az, float fq)
+{
+    constexpr int P = NJ * NJ;
+    using A = JAcc<JM>;
+    const float s0x[4] = {0.0f, 1.0f - x, x, 0.0f}, s0y[4] = {0.0f, 1.0f - y, y, 0.0f};
+    float dsx[4], dsy[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        dsx[k] = fmaxf(0.0f, 1.0f - fabsf(x1 - (float)(k - 1))) - s0x[k];
+        dsy[k] = fmaxf(0.0f, 1.0f - fabsf(y1 - (float)(k - 1))) - s0y[k];
+    }
+    const int o = b - NJ - 1;   // node (-1, -1) relative to the cell
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const float gy = fmaf(0.5f, dsy[l], s0y[l]);
+        float run = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            run = fmaf(-dsx[k], gy, run);
+            A::add(&sj[o + l * NJ + k], fq, run);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float gx = fmaf(0.5f, dsx[k], s0x[k]);
+        float run = 0.0f;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            run = fmaf(-dsy[l], gx, run);
+            A::add(&sj[P + o + l * NJ + k], fq, run);
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float w = s0x[k] * s0y[l] + 0.5f * (dsx[k] * s0y[l] + s0x[k] * dsy[l]) +
+                            dsx[k] * dsy[l] * (1.0f / 3.0f);
+            A::add(&sj[2 * P + o + l * NJ + k], az, w);
+        }
+}
+
+// The wavefront's queue of deposit jobs: kPieceBuf entries of
+// (halo index, xa, ya, xb, yb, az) -- second and third pieces of split
+// motions (Villasenor-Buneman) or whole face-crossing motions (Esirkepov).
+
+template <int NJ, int JM, int DM>
 __device__ __forceinline__ void drain_pieces(typename JAcc<JM>::T *sj, uint32_t (*pq)[kPieceBuf], int n,
                                              float fq, int lane)
 {
     __builtin_amdgcn_wave_barrier();
-    if (lane < n)
-        deposit_piece<NJ, JM>(sj, (int)pq[0][lane], __uint_as_float(pq[1][lane]), __uint_as_float(pq[2][lane]),
-                              __uint_as_float(pq[3][lane]), __uint_as_float(pq[4][lane]),
-                              __uint_as_float(pq[5][lane]), fq);
+    if (lane < n) {
+        const int b = (int)pq[0][lane];
+        const float xa = __uint_as_float(pq[1][lane]), ya = __uint_as_float(pq[2][lane]);
+        const float xb = __uint_as_float(pq[3][lane]), yb = __uint_as_float(pq[4][lane]);
+        const float az = __uint_as_float(pq[5][lane]);
+        if constexpr (DM == kDepEsirkepov)
+            deposit_esirkepov<NJ, JM>(sj, b, xa, ya, xb, yb, az, fq);
+        else
+            deposit_piece<NJ, JM>(sj, b, xa, ya, xb, yb, az, fq);
+    }
     __builtin_amdgcn_wave_barrier();
 }
 
 // Append the pieces of the lanes with `has` set to the queue (slot order by
 // lane), draining it first if they do not fit.  n: queue fill, uniform.
-template <int NJ, int JM>
+template <int NJ, int JM, int DM>
 __device__ __forceinline__ void queue_piece(typename JAcc<JM>::T *sj, uint32_t (*pq)[kPieceBuf], int &n, bool has,
                                             int b, float xa, float ya, float xb, float yb, float az, float fq,
                                             int lane)
@@ -180,7 +240,7 @@ __device__ __forceinline__ void queue_piece(typename JAcc<JM>::T *sj, uint32_t (
     const int c = __popcll(m);
     if (c == 0) return;
     if (n + c > kPieceBuf) {
-        drain_pieces<NJ, JM>(sj, pq, n, fq, lane);
+        drain_pieces<NJ, JM, DM>(sj, pq, n, fq, lane);
         n = 0;
     }
     if (has) {
@@ -215,7 +275,7 @@ __device__ __forceinline__ void flush_leavers(const SpeciesDev &sp, uint32_t (*l
 }
 
 // One tile of one simulation, by the whole 256-thread workgroup.
-template <int T, int R, int JM>
+template <int T, int R, int JM, int DM>
 __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
 {
     constexpr int NE = T + 2;   // staged E/B cells per axis: relative -1..T
@@ -386,13 +446,30 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                         const float p1y = xfirst ? fmaf(t1, dY, y) : ey;
                         const float p2x = xfirst ? fmaf(t2, dX, x) : ex;
                         const float p2y = xfirst ? ey : fmaf(t2, dY, y);
+                        if constexpr (DM == kDepEsirkepov) {
+                            // inside the cell both schemes coincide; a crossing
+                            // motion is queued whole for the 4 x 4 stencil
+                            if (nseg == 1) {
+                                deposit_piece<NJ, JM>(sj, jcell<NJ>(lx, ly), clamp01(x), clamp01(y), clamp01(x1),
+                                                      clamp01(y1), fqvz * (1.0f - 0.0f), fq);
+                            } else {
+                                has1 = true;
+                                qb1 = jcell<NJ>(lx, ly);
+                                xa1 = x;
+                                ya1 = y;
+                                xb1 = x1;
+                                yb1 = y1;
+                                az1 = fqvz;
+                            }
+                        }
                         // piece 0, in the start cell
                         const float e0x = nseg == 1 ? x1 : p1x, e0y = nseg == 1 ? y1 : p1y;
                         const float f0 = nseg == 1 ? 1.0f : t1;
-                        deposit_piece<NJ, JM>(sj, jcell<NJ>(lx, ly), clamp01(x), clamp01(y), clamp01(e0x),
-                                              clamp01(e0y), fqvz * (f0 - 0.0f), fq);
+                        if constexpr (DM == kDepVB)
+                            deposit_piece<NJ, JM>(sj, jcell<NJ>(lx, ly), clamp01(x), clamp01(y), clamp01(e0x),
+                                                  clamp01(e0y), fqvz * (f0 - 0.0f), fq);
                         // piece 1, after the first crossing
-                        if (nseg >= 2) {
+                        if (DM == kDepVB && nseg >= 2) {
                             const int ox = xfirst ? sxn : 0, oy = xfirst ? 0 : syn;
                             const float e1x = nseg == 2 ? x1 : p2x, e1y = nseg == 2 ? y1 : p2y;
                             const float f1 = nseg == 2 ? 1.0f : t2;
@@ -405,7 +482,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                             az1 = fqvz * (f1 - t1);
                         }
                         // piece 2, after both crossings
-                        if (nseg == 3) {
+                        if (DM == kDepVB && nseg == 3) {
                             has2 = true;
                             qb2 = jcell<NJ>(lx + sxn, ly + syn);
                             xa2 = clamp01(p2x - sxn);
@@ -456,8 +533,9 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                     dir = (dty + 1) * 3 + (dtx + 1);
                     leaver = dir != 4;
                 }
-                queue_piece<NJ, JM>(sj, s_pq[wave], npq, has1, qb1, xa1, ya1, xb1, yb1, az1, fq, lane);
-                queue_piece<NJ, JM>(sj, s_pq[wave], npq, has2, qb2, xa2, ya2, xb2, yb2, az2, fq, lane);
+                queue_piece<NJ, JM, DM>(sj, s_pq[wave], npq, has1, qb1, xa1, ya1, xb1, yb1, az1, fq, lane);
+                if constexpr (DM == kDepVB)
+                    queue_piece<NJ, JM, DM>(sj, s_pq[wave], npq, has2, qb2, xa2, ya2, xb2, yb2, az2, fq, lane);
                 // leavers go to the wavefront's LDS buffer in slot order; a full
                 // buffer is written out as whole cache lines
                 const unsigned long long m = __ballot(leaver);
@@ -482,7 +560,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                     nbuf += c;
                 }
             }
-            drain_pieces<NJ, JM>(sj, s_pq[wave], npq, fq, lane);
+            drain_pieces<NJ, JM, DM>(sj, s_pq[wave], npq, fq, lane);
             flush_leavers(sp, s_lb[wave], nbuf, (int64_t)lo + nleav, lane);
             nleav += nbuf;
         }
@@ -511,16 +589,16 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
     }
 }
 
-template <int T, int R, int JM>
+template <int T, int R, int JM, int DM>
 __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
 {
-    push_tile<T, R, JM>(a, blockIdx.x);
+    push_tile<T, R, JM, DM>(a, blockIdx.x);
 }
 
 // Many simulations in one launch: a persistent grid takes (simulation, tile)
 // items from a shared counter (the items come largest simulations first, so
 // the expensive tiles start early and the cheap ones fill the tail).
-template <int T, int R, int JM>
+template <int T, int R, int JM, int DM>
 __global__ void __launch_bounds__(kBlock) k_push_batch(const PushArgs *__restrict__ descs,
                                                        const int4 *__restrict__ items, int n_items, int *counter)
 {
@@ -532,7 +610,7 @@ __global__ void __launch_bounds__(kBlock) k_push_batch(const PushArgs *__restric
         __syncthreads();
         if (it >= n_items) break;
         const int4 w = items[it];
-        push_tile<T, R, JM>(descs[w.x], w.y);
+        push_tile<T, R, JM, DM>(descs[w.x], w.y);
         __syncthreads();
     }
 }
@@ -594,38 +672,41 @@ __global__ void __launch_bounds__(256) k_j_reduce_batch(const JReduceArgs *__res
     j_reduce_block<T>(descs[w.x], w.y, w.z);
 }
 
-template <int T, int R, int JM>
+template <int T, int R, int JM, int DM>
 static void launch_pd(const PushArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_push_deposit<T, R, JM>), dim3(n_tiles), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_push_deposit<T, R, JM, DM>), dim3(n_tiles), dim3(kBlock), 0, s, a);
 }
 
-template <int T, int JM>
+template <int T, int JM, int DM>
 static void launch_pd_r(int replicas, const PushArgs &a, int n_tiles, hipStream_t s)
 {
     switch (replicas) {
-    case 1: launch_pd<T, 1, JM>(a, n_tiles, s); break;
-    case 2: launch_pd<T, 2, JM>(a, n_tiles, s); break;
+    case 1: launch_pd<T, 1, JM, DM>(a, n_tiles, s); break;
+    case 2: launch_pd<T, 2, JM, DM>(a, n_tiles, s); break;
     default:
         // configurations over the LDS budget are rejected by pic_query/pic_init
-        if constexpr (push_lds_bytes(T, 4, JM) <= kLdsBytes) launch_pd<T, 4, JM>(a, n_tiles, s);
+        if constexpr (push_lds_bytes(T, 4, JM) <= kLdsBytes) launch_pd<T, 4, JM, DM>(a, n_tiles, s);
         break;
     }
 }
 
+// the Esirkepov deposit is built for the fixed-point current only
 template <int T>
-static void launch_pd_j(int replicas, int jmode, const PushArgs &a, int n_tiles, hipStream_t s)
+static void launch_pd_j(int replicas, int jmode, int dmode, const PushArgs &a, int n_tiles, hipStream_t s)
 {
-    if (jmode == kJFloat) launch_pd_r<T, kJFloat>(replicas, a, n_tiles, s);
-    else launch_pd_r<T, kJFixed>(replicas, a, n_tiles, s);
+    if (jmode == kJFloat) launch_pd_r<T, kJFloat, kDepVB>(replicas, a, n_tiles, s);
+    else if (dmode == kDepEsirkepov) launch_pd_r<T, kJFixed, kDepEsirkepov>(replicas, a, n_tiles, s);
+    else launch_pd_r<T, kJFixed, kDepVB>(replicas, a, n_tiles, s);
 }
 
-void launch_push_deposit(int tile, int replicas, int jmode, const PushArgs &a, int n_tiles, hipStream_t s)
+void launch_push_deposit(int tile, int replicas, int jmode, int dmode, const PushArgs &a, int n_tiles,
+                         hipStream_t s)
 {
     switch (tile) {
-    case 8: launch_pd_j<8>(replicas, jmode, a, n_tiles, s); break;
-    case 16: launch_pd_j<16>(replicas, jmode, a, n_tiles, s); break;
-    default: launch_pd_j<32>(replicas, jmode, a, n_tiles, s); break;
+    case 8: launch_pd_j<8>(replicas, jmode, dmode, a, n_tiles, s); break;
+    case 16: launch_pd_j<16>(replicas, jmode, dmode, a, n_tiles, s); break;
+    default: launch_pd_j<32>(replicas, jmode, dmode, a, n_tiles, s); break;
     }
 }
 
@@ -639,40 +720,44 @@ void launch_j_reduce(int tile, const JReduceArgs &r, hipStream_t s)
     }
 }
 
-template <int T, int R, int JM>
+template <int T, int R, int JM, int DM>
 static void launch_pb(const PushArgs *descs, const int4 *items, int n_items, int *counter, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_push_batch<T, R, JM>), dim3(grid), dim3(kBlock), 0, s, descs, items, n_items, counter);
+    hipLaunchKernelGGL((k_push_batch<T, R, JM, DM>), dim3(grid), dim3(kBlock), 0, s, descs, items, n_items,
+                       counter);
 }
 
-template <int T, int JM>
+template <int T, int JM, int DM>
 static void launch_pb_r(int replicas, const PushArgs *descs, const int4 *items, int n_items, int *counter,
                         int grid, hipStream_t s)
 {
     switch (replicas) {
-    case 1: launch_pb<T, 1, JM>(descs, items, n_items, counter, grid, s); break;
-    case 2: launch_pb<T, 2, JM>(descs, items, n_items, counter, grid, s); break;
+    case 1: launch_pb<T, 1, JM, DM>(descs, items, n_items, counter, grid, s); break;
+    case 2: launch_pb<T, 2, JM, DM>(descs, items, n_items, counter, grid, s); break;
     default:
-        if constexpr (push_lds_bytes(T, 4, JM) <= kLdsBytes) launch_pb<T, 4, JM>(descs, items, n_items, counter, grid, s);
+        if constexpr (push_lds_bytes(T, 4, JM) <= kLdsBytes)
+            launch_pb<T, 4, JM, DM>(descs, items, n_items, counter, grid, s);
         break;
     }
 }
 
 template <int T>
-static void launch_pb_j(int replicas, int jmode, const PushArgs *descs, const int4 *items, int n_items,
+static void launch_pb_j(int replicas, int jmode, int dmode, const PushArgs *descs, const int4 *items, int n_items,
                         int *counter, int grid, hipStream_t s)
 {
-    if (jmode == kJFloat) launch_pb_r<T, kJFloat>(replicas, descs, items, n_items, counter, grid, s);
-    else launch_pb_r<T, kJFixed>(replicas, descs, items, n_items, counter, grid, s);
+    if (jmode == kJFloat) launch_pb_r<T, kJFloat, kDepVB>(replicas, descs, items, n_items, counter, grid, s);
+    else if (dmode == kDepEsirkepov)
+        launch_pb_r<T, kJFixed, kDepEsirkepov>(replicas, descs, items, n_items, counter, grid, s);
+    else launch_pb_r<T, kJFixed, kDepVB>(replicas, descs, items, n_items, counter, grid, s);
 }
 
-void launch_push_batch(int tile, int replicas, int jmode, const PushArgs *descs, const int4 *items, int n_items,
-                       int *counter, int grid, hipStream_t s)
+void launch_push_batch(int tile, int replicas, int jmode, int dmode, const PushArgs *descs, const int4 *items,
+                       int n_items, int *counter, int grid, hipStream_t s)
 {
     switch (tile) {
-    case 8: launch_pb_j<8>(replicas, jmode, descs, items, n_items, counter, grid, s); break;
-    case 16: launch_pb_j<16>(replicas, jmode, descs, items, n_items, counter, grid, s); break;
-    default: launch_pb_j<32>(replicas, jmode, descs, items, n_items, counter, grid, s); break;
+    case 8: launch_pb_j<8>(replicas, jmode, dmode, descs, items, n_items, counter, grid, s); break;
+    case 16: launch_pb_j<16>(replicas, jmode, dmode, descs, items, n_items, counter, grid, s); break;
+    default: launch_pb_j<32>(replicas, jmode, dmode, descs, items, n_items, counter, grid, s); break;
     }
 }
 

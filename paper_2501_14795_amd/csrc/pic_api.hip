@@ -27,6 +27,7 @@ struct Layout {
 };
 
 int j_mode(const pic_config *c) { return (c->flags & PIC_FLAG_J_FLOAT) ? kJFloat : kJFixed; }
+int d_mode(const pic_config *c) { return (c->flags & PIC_FLAG_ESIRKEPOV) ? kDepEsirkepov : kDepVB; }
 
 int default_replicas(const pic_config *c)
 {
@@ -37,7 +38,9 @@ int default_replicas(const pic_config *c)
 int validate(const pic_config *c)
 {
     if (!c) return PIC_EINVAL;
-    if (c->flags & ~(uint32_t)PIC_FLAG_J_FLOAT) return PIC_EINVAL;
+    if (c->flags & ~(uint32_t)(PIC_FLAG_J_FLOAT | PIC_FLAG_ESIRKEPOV)) return PIC_EINVAL;
+    // the Esirkepov deposit is built for the fixed-point current only
+    if ((c->flags & PIC_FLAG_ESIRKEPOV) && (c->flags & PIC_FLAG_J_FLOAT)) return PIC_EINVAL;
     if (c->tile != 8 && c->tile != 16 && c->tile != 32) return PIC_ETILE;
     if (c->nx < c->tile || c->ny < c->tile || c->nx > 32767 || c->ny > 32767) return PIC_EINVAL;
     if (c->nx % c->tile || c->ny % c->tile) return PIC_ETILE;
@@ -464,7 +467,7 @@ int pic_push_deposit(pic_sim *S, hipStream_t stream)
     const PushArgs a = push_args(S);
     {
         Timed t(S, PIC_KERNEL_PUSH, stream);
-        launch_push_deposit(S->tile, S->replicas, j_mode(&S->cfg), a, S->n_tiles, stream);
+        launch_push_deposit(S->tile, S->replicas, j_mode(&S->cfg), d_mode(&S->cfg), a, S->n_tiles, stream);
     }
     {
         Timed t(S, PIC_KERNEL_JREDUCE, stream);
@@ -721,7 +724,7 @@ void pic_destroy(pic_sim *S)
 
 struct pic_batch {
     std::vector<pic_sim *> sims;
-    int tile, replicas, jm;
+    int tile, replicas, jm, dm;
     int cus;
     char *dev;
     // device tables
@@ -796,8 +799,8 @@ BatchLayout batch_layout(int n, const pic_config *cfgs)
 void batch_enqueue_step(pic_batch *b, hipStream_t stream)
 {
     launch_set_int(b->counter, 0, stream);
-    launch_push_batch(b->tile, b->replicas, b->jm, b->d_push, b->push_items, b->n_push, b->counter, b->push_grid,
-                      stream);
+    launch_push_batch(b->tile, b->replicas, b->jm, b->dm, b->d_push, b->push_items, b->n_push, b->counter,
+                      b->push_grid, stream);
     launch_j_reduce_batch(b->tile, b->d_jr, b->node_items, b->n_node, stream);
     for (int p = 0; p < b->j_filter; ++p)
         launch_filter_batch(b->d_filter + (p & 1) * b->sims.size(), b->node_items, b->n_node, stream);
@@ -850,6 +853,7 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
     B->tile = cfgs[0].tile;
     B->j_filter = cfgs[0].j_filter;
     B->jm = j_mode(&cfgs[0]);
+    B->dm = d_mode(&cfgs[0]);
     B->replicas = cfgs[0].j_replicas ? cfgs[0].j_replicas : default_replicas(&cfgs[0]);
     char *d = (char *)batch_work;
     B->dev = d;

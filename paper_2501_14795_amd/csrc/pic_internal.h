@@ -44,6 +44,10 @@ enum : int {
 // (error at most 2^-23 of the largest one) and the sums are exact.
 constexpr float kFixedScale = 4194304.0f;
 
+// deposit scheme of the push kernel
+constexpr int kDepVB = 0;          // Villasenor-Buneman with the 1/2/3-piece split (Eqs. 13-16)
+constexpr int kDepEsirkepov = 1;   // Esirkepov's density decomposition (variant)
+
 constexpr int kLdsBytes = 160 * 1024;   // LDS of one gfx950 compute unit
 constexpr int kLeaverBuf = 64;           // leavers buffered per wavefront before a write-out
 constexpr int kPieceBuf = 64;            // queued second / third motion pieces per wavefront
@@ -147,10 +151,11 @@ struct FieldArgs {
 };
 
 // ---- launchers (each defined next to its kernels) ----
-void launch_push_deposit(int tile, int replicas, int jmode, const PushArgs &a, int n_tiles, hipStream_t s);
+void launch_push_deposit(int tile, int replicas, int jmode, int dmode, const PushArgs &a, int n_tiles,
+                         hipStream_t s);
 void launch_j_reduce(int tile, const JReduceArgs &r, hipStream_t s);
-void launch_push_batch(int tile, int replicas, int jmode, const PushArgs *descs, const int4 *items, int n_items,
-                       int *counter, int grid, hipStream_t s);
+void launch_push_batch(int tile, int replicas, int jmode, int dmode, const PushArgs *descs, const int4 *items,
+                       int n_items, int *counter, int grid, hipStream_t s);
 void launch_j_reduce_batch(int tile, const JReduceArgs *descs, const int4 *items, int n_items, hipStream_t s);
 void launch_set_int(int *p, int v, hipStream_t s);
 void launch_sort_scan(const SortArgs &a, int n_tiles, hipStream_t s);

@@ -36,7 +36,7 @@ class _Buffers:
     the pic_config / pic_buffers structures that describe them."""
 
     def __init__(self, nx, ny, dx, dy, dt, tile, species, E=None, B=None, j_replicas=0, j_float=False,
-                 device="cuda:0", j_filter=0):
+                 device="cuda:0", j_filter=0, esirkepov=False):
         torch = _torch()
         if not 1 <= len(species) <= _lib.MAX_SPECIES:
             raise ValueError("1..4 species")
@@ -46,7 +46,7 @@ class _Buffers:
         cfg.tile = self.tile
         cfg.j_replicas = int(j_replicas)
         cfg.n_species = len(species)
-        cfg.flags = _lib.PIC_FLAG_J_FLOAT if j_float else 0
+        cfg.flags = (_lib.PIC_FLAG_J_FLOAT if j_float else 0) | (_lib.PIC_FLAG_ESIRKEPOV if esirkepov else 0)
         cfg.j_filter = int(j_filter)
         for k, (qm, q, st) in enumerate(species):
             cfg.species[k].qm = float(qm)
@@ -193,11 +193,12 @@ class Sim(_SimView):
     def __init__(self, nx: int, ny: int, dx: float, dy: float, dt: float, tile: int,
                  species: Sequence, E: Optional[np.ndarray] = None, B: Optional[np.ndarray] = None,
                  j_replicas: int = 0, j_float: bool = False, device: str = "cuda:0", stream=None,
-                 j_filter: int = 0):
+                 j_filter: int = 0, esirkepov: bool = False):
         torch = _torch()
         self.handle = None
         self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
-        self.buf = _Buffers(nx, ny, dx, dy, dt, tile, species, E, B, j_replicas, j_float, device, j_filter)
+        self.buf = _Buffers(nx, ny, dx, dy, dt, tile, species, E, B, j_replicas, j_float, device, j_filter,
+                            esirkepov)
         self.cfg = self.buf.cfg
         torch.cuda.synchronize(torch.device(device))
         self.handle = _lib.pic_init(self.cfg, self.buf.bufs, self.s)
@@ -229,15 +230,16 @@ class Batch:
     for all of them, optionally replayed from a captured HIP graph.
 
     members: list of dicts with keys nx, ny, dx, dy, dt, species (as for Sim)
-    and optionally E, B.  All share tile, j_replicas, j_float, j_filter."""
+    and optionally E, B.  All share tile, j_replicas, j_float, j_filter and
+    the deposit scheme."""
 
     def __init__(self, members: Sequence[dict], tile: int, j_replicas: int = 0, j_float: bool = False,
-                 device: str = "cuda:0", stream=None, j_filter: int = 0):
+                 device: str = "cuda:0", stream=None, j_filter: int = 0, esirkepov: bool = False):
         torch = _torch()
         self.handle = None
         self.stream = stream if stream is not None else torch.cuda.Stream(torch.device(device))
         self.bufs = [_Buffers(m["nx"], m["ny"], m["dx"], m["dy"], m["dt"], tile, m["species"], m.get("E"),
-                              m.get("B"), j_replicas, j_float, device, j_filter) for m in members]
+                              m.get("B"), j_replicas, j_float, device, j_filter, esirkepov) for m in members]
         cfgs = [b.cfg for b in self.bufs]
         nbytes = _lib.pic_batch_query(cfgs)
         self.work = torch.empty(nbytes + 256, dtype=torch.uint8, device=torch.device(device))

@@ -91,7 +91,8 @@ def test_query_sizes_and_validation():
         (dict(ns=0), L.PIC_EINVAL),
         (dict(ns=5), L.PIC_EINVAL),
         (dict(reps=3), L.PIC_EINVAL),
-        (dict(flags=2), L.PIC_EINVAL),
+        (dict(flags=4), L.PIC_EINVAL),
+        (dict(flags=3), L.PIC_EINVAL),          # Esirkepov needs the fixed-point current
         (dict(nx=64, tile=32, reps=4), L.PIC_EINVAL),   # int64 current x 4 replicas > LDS
         (dict(n=-1), L.PIC_EINVAL),
         (dict(n=2 ** 31), L.PIC_EINVAL),
@@ -108,6 +109,7 @@ def test_query_sizes_and_validation():
         assert e.value.code == code, (kw, e.value.code)
     assert L.pic_query(_cfg(L, dt=0.0707)).n_tiles == 16
     assert L.pic_query(_cfg(L, nx=64, tile=32, reps=4, flags=L.PIC_FLAG_J_FLOAT)).n_tiles == 4
+    assert L.pic_query(_cfg(L, flags=L.PIC_FLAG_ESIRKEPOV)).work_bytes == s.work_bytes
     # the filter's ping-pong planes: three FP32 current planes + one FP64 density plane
     sf = L.pic_query(_cfg(L, filt=L.PIC_MAX_FILTER))
     assert 20 * 64 * 64 <= sf.work_bytes - s.work_bytes <= 20 * 64 * 64 + 2 * 256
@@ -131,7 +133,8 @@ def test_batch_query_validation():
     nb = L.pic_batch_query(cfgs)
     assert nb > 0
     for bad in ([_cfg(L), _cfg(L, tile=8)], [_cfg(L), _cfg(L, flags=L.PIC_FLAG_J_FLOAT)],
-                [_cfg(L), _cfg(L, reps=2)], [_cfg(L), _cfg(L, filt=1)]):
+                [_cfg(L), _cfg(L, reps=2)], [_cfg(L), _cfg(L, filt=1)],
+                [_cfg(L), _cfg(L, flags=L.PIC_FLAG_ESIRKEPOV)]):
         with pytest.raises(L.PicError) as e:
             L.pic_batch_query(bad)
         assert e.value.code == L.PIC_EINVAL

@@ -458,3 +458,70 @@ def test_filtered_current_keeps_continuity(ora):
         sim.field_advance()
     g = div_edge(sim.E, sim.dx, sim.dy) - sim.rho(filtered=True)
     assert np.abs(g - g0).max() < 1e-11
+
+
+# ---------------------------------------------------------------- Esirkepov deposit (variant)
+def test_esirkepov_continuity_and_totals(ora):
+    """Esirkepov's decomposition conserves charge exactly, Eq. (12), for every
+    motion (the node charge of the cloud before and after, by overlap areas),
+    and moves the whole charge: sum Jx dt/dx = q ddx, sum Jz = q vz."""
+    nx, ny, dx, dy, dt, q, vz = 6, 6, 0.1, 0.1, 0.07, -0.37, 0.3
+    rng = np.random.default_rng(14)
+    for ix, iy, x, y, ddx, ddy in _deposit_cases(rng):
+        J = ora.deposit_esirkepov(nx, ny, dx, dy, dt, q, vz, ix, iy, x, y, ddx, ddy)
+        X1, Y1 = new_position(nx, ny, ix, iy, x, y, ddx, ddy)
+        res = node_charge(nx, ny, q, X1, Y1) - node_charge(nx, ny, q, ix + x, iy + y) + dt * div_edge(J, dx, dy)
+        assert np.abs(res).max() < 1e-13, (ix, iy, x, y, ddx, ddy)
+        assert abs(J[0].sum() * dt / dx - q * ddx) < 1e-14
+        assert abs(J[1].sum() * dt / dy - q * ddy) < 1e-14
+        assert abs(J[2].sum() - q * vz) < 1e-14
+
+
+def test_esirkepov_special_cases(ora):
+    """(1) A motion that stays inside its cell: identical to the
+    Villasenor-Buneman current (both reduce to the same linear-shape fluxes and
+    the same time average for Jz).  (2) Motion along x only, crossing a face:
+    the exact charge flux, checked by quadrature of the cloud.  (3) Motion
+    along y only: no Jx.  (4) Exchanging x and y exchanges Jx and Jy and
+    transposes the grid.  (5) An oblique crossing: a different current from
+    the split Villasenor-Buneman one (the two schemes are not the same)."""
+    nx, ny, dx, dy, dt, q, vz = 8, 8, 0.1, 0.1, 0.07, 0.5, -0.4
+    rng = np.random.default_rng(15)
+    for _ in range(200):
+        x, y = rng.uniform(0.05, 0.95, 2)
+        ddx = rng.uniform(-x, 1 - x) * 0.999
+        ddy = rng.uniform(-y, 1 - y) * 0.999
+        Je = ora.deposit_esirkepov(nx, ny, dx, dy, dt, q, vz, 3, 4, x, y, ddx, ddy)
+        Jv = ora.deposit_move(nx, ny, dx, dy, dt, q, vz, 3, 4, x, y, ddx, ddy)
+        np.testing.assert_allclose(Je, Jv, atol=1e-13)
+    scale = abs(q) * dx / dt
+    for x, y, ddx in ((0.8, 0.3, 0.45), (0.2, 0.7, -0.6), (0.5, 0.5, 0.5)):
+        Je = ora.deposit_esirkepov(nx, ny, dx, dy, dt, q, vz, 3, 4, x, y, ddx, 0.0)
+        Jb = brute_current(nx, ny, dx, dy, dt, q, vz, 3 + x, 4 + y, ddx, 0.0)
+        np.testing.assert_allclose(Je[0], Jb[0], atol=2e-5 * scale)
+        np.testing.assert_allclose(Je[1], 0.0, atol=1e-15)
+    Je = ora.deposit_esirkepov(nx, ny, dx, dy, dt, q, vz, 3, 4, 0.4, 0.8, 0.0, 0.7)
+    assert np.abs(Je[0]).max() == 0.0 and np.abs(Je[1]).max() > 0.1 * scale
+    for x, y, ddx, ddy in ((0.9, 0.2, 0.3, 0.5), (0.1, 0.95, -0.4, 0.2), (0.7, 0.8, 0.6, 0.45)):
+        A = ora.deposit_esirkepov(8, 6, dx, dx, dt, q, vz, 3, 2, x, y, ddx, ddy)
+        Bt = ora.deposit_esirkepov(6, 8, dx, dx, dt, q, vz, 2, 3, y, x, ddy, ddx)
+        np.testing.assert_allclose(A[0], Bt[1].T, atol=1e-14)
+        np.testing.assert_allclose(A[1], Bt[0].T, atol=1e-14)
+        np.testing.assert_allclose(A[2], Bt[2].T, atol=1e-14)
+    Je = ora.deposit_esirkepov(nx, ny, dx, dy, dt, q, vz, 3, 4, 0.9, 0.8, 0.4, 0.5)
+    Jv = ora.deposit_move(nx, ny, dx, dy, dt, q, vz, 3, 4, 0.9, 0.8, 0.4, 0.5)
+    assert np.abs(Je[0] - Jv[0]).max() > 1e-3 * scale
+
+
+def test_esirkepov_whole_step_gauss(ora):
+    """Full steps with the Esirkepov deposit keep Gauss's law at its initial
+    residual, like the split Villasenor-Buneman deposit."""
+    sim = _thermal_sim(ora, fields=True)
+    sim.esirkepov = True
+    s = sim.species[0]
+    g0 = div_edge(sim.E, sim.dx, sim.dy) - node_charge(sim.nx, sim.ny, s.q, s.ix + s.x, s.iy + s.y)
+    for _ in range(10):
+        sim.push_deposit()
+        sim.field_advance()
+    g = div_edge(sim.E, sim.dx, sim.dy) - node_charge(sim.nx, sim.ny, s.q, s.ix + s.x, s.iy + s.y)
+    assert np.abs(g - g0).max() < 1e-11
