@@ -39,16 +39,16 @@ def push_bytes(n_particles, n_tiles, tile, leavers, n_species=1):
     """Algorithmic HBM bytes of one push + deposit launch: every particle read
     and written once, each tile's E/B halo ((T+2)^2 cells x 6 fields) read once,
     each tile's current halo ((T+3)^2 nodes x 3) written once, the tile_offset
-    pair and the count record (16 ints) per tile and species, and one 4-byte
+    pair and the count record (32 ints) per tile and species, and one 4-byte
     entry per leaver."""
     return (2 * BYTES_PARTICLE * n_particles
             + n_tiles * (tile + 2) ** 2 * 6 * 4
             + n_tiles * (tile + 3) ** 2 * 3 * 4
-            + n_species * n_tiles * (8 + 16 * 4)
+            + n_species * n_tiles * (8 + 32 * 4)
             + 4 * leavers)
 
 
-def cpu_baseline(w, st, budget_s=10.0, max_steps=8):
+def cpu_baseline(w, st, T, budget_s=10.0, max_steps=8):
     """The oracle (serial FP64 C) on a bounded sample of the same workload:
     the first 8,388,608 particles (the lower eighth of the grid), full-size
     fields, push + deposit + canonical sort per step, until ~budget_s."""
@@ -61,12 +61,12 @@ def cpu_baseline(w, st, budget_s=10.0, max_steps=8):
     while steps < max_steps and (steps == 0 or t_hot < budget_s):
         t0 = time.perf_counter()
         sim.push_deposit()
-        sim.sort(w.tile)
+        sim.sort(T)
         t_hot += time.perf_counter() - t0
         sim.field_advance()
         steps += 1
     return {"value": M * steps / t_hot, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {M} particles (tiles 0-{M // (w.tile * w.tile * s.n_ppc) - 1}) of the "
+            "sample": f"first {M} particles (tiles 0-{M // (T * T * s.n_ppc) - 1}, tile {T}) of the "
                       f"{w.nx}x{w.ny} workload, {steps} steps of push+deposit+sort, serial FP64 C "
                       f"(field advance untimed)",
             "seconds": t_hot}
@@ -192,7 +192,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--tile", type=int, default=0, help="tile edge (default: the workload's)")
     ap.add_argument("--replicas", type=int, default=0)
     ap.add_argument("--workload", default="warm2048")
     ap.add_argument("--j-float", action="store_true", help="FP32-atomic LDS current instead of fixed point")
@@ -230,7 +230,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = pw.WORKLOADS[args.workload]
-    T = args.tile
+    T = args.tile or w.tile
     t0 = time.perf_counter()
     states = pw.workload_state(w, tile=T)
     n = sum(s["ix"].size for s in states)
@@ -238,7 +238,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline and len(states) == 1:
-        cpu = cpu_baseline(w, states[0])
+        cpu = cpu_baseline(w, states[0], T)
         log(f"cpu baseline {cpu['value'] / 1e6:.2f} M push/s over {cpu['seconds']:.1f}s")
 
     sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, T, [(s.qm, s.q, st) for s, st in zip(w.species, states)],

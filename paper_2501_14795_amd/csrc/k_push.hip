@@ -7,7 +7,8 @@
 //      that the two x-neighbours every bilinear stencil needs come in one
 //      ds_read_b64/b128;
 //   2. the 64-aligned particle chunks covering the tile's section are split
-//      into four contiguous runs, one per wavefront; every chunk is one
+//      into contiguous runs, one per wavefront (4 wavefronts per tile up to
+//      16 x 16 tiles, 16 for 32 x 32 tiles); every chunk is one
 //      coalesced buffer load per SoA array (per-tile buffer base in SGPRs), and
 //      there is no block barrier in the loop;
 //   3. per particle: bilinear interpolation at the staggered points
@@ -274,13 +275,15 @@ __device__ __forceinline__ void flush_leavers(const SpeciesDev &sp, uint32_t (*l
     __builtin_amdgcn_wave_barrier();
 }
 
-// One tile of one simulation, by the whole 256-thread workgroup.
+// One tile of one simulation, by the whole workgroup (push_waves(T) wavefronts).
 template <int T, int R, int JM, int DM>
 __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
 {
     constexpr int NE = T + 2;   // staged E/B cells per axis: relative -1..T
     constexpr int NJ = T + 3;   // current halo nodes per axis: relative -1..T+1
     constexpr int JP = NJ * NJ;
+    constexpr int W = push_waves(T);   // wavefronts of the workgroup
+    constexpr int NT = 64 * W;         // its threads
     using Acc = typename JAcc<JM>::T;
 
     // packed E/B: entry [r][c] holds the values at relative cells c-1 and c
@@ -291,9 +294,9 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
     __shared__ float2 s_bz[NE * NE];
     __shared__ Acc s_j[R][3 * JP];
     __shared__ int s_dir[kMaxSpecies][9];
-    __shared__ int s_wl[kMaxSpecies][kWaves];
-    __shared__ uint32_t s_lb[kWaves][7][kLeaverBuf];   // leaver entry + new particle data
-    __shared__ uint32_t s_pq[kWaves][6][kPieceBuf];    // queued second / third pieces
+    __shared__ int s_wl[kMaxSpecies][W];
+    __shared__ uint32_t s_lb[W][7][kLeaverBuf];   // leaver entry + new particle data
+    __shared__ uint32_t s_pq[W][6][kPieceBuf];    // queued deposit jobs
 
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int gx0 = tx * T, gy0 = ty * T;
@@ -303,7 +306,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
     const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t plane = (int64_t)a.nx * a.ny;
 
-    for (int e = tid; e < NE * NE; e += kBlock) {
+    for (int e = tid; e < NE * NE; e += NT) {
         const int r = e / NE, c = e - r * NE;
         const int64_t row = (int64_t)wrapi(gy0 - 1 + r, a.ny) * a.nx;
         const int64_t i0 = row + wrapi(gx0 - 1 + c, a.nx);
@@ -314,7 +317,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
         s_ez[e] = make_float2(f[2 * plane + i0], f[2 * plane + i1]);
         s_bz[e] = make_float2(f[5 * plane + i0], f[5 * plane + i1]);
     }
-    for (int e = tid; e < R * 3 * JP; e += kBlock) (&s_j[0][0])[e] = Acc(0);
+    for (int e = tid; e < R * 3 * JP; e += NT) (&s_j[0][0])[e] = Acc(0);
     if (tid < kMaxSpecies * 9) (&s_dir[0][0])[tid] = 0;
     __syncthreads();
 
@@ -325,7 +328,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
         const SpeciesDev sp = a.sp[s];
         const int begin = sp.off[tile], end = sp.off[tile + 1];
         int lo, hi;
-        wave_range(begin, end, wave, lo, hi);
+        wave_range(begin, end, wave, W, lo, hi);
         int nleav = 0;   // wavefront-uniform
         if (lo < hi) {
             // buffer views from the first 64-aligned slot of the section to the
@@ -573,24 +576,24 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
         const int s = tid / kCntStride, k = tid % kCntStride;
         const int n = a.sp[s].off[tile + 1] - a.sp[s].off[tile];
         int leavers = 0;
-        for (int w = 0; w < kWaves; ++w) leavers += s_wl[s][w];
+        for (int w = 0; w < W; ++w) leavers += s_wl[s][w];
         int v = 0;
         if (k < 9) v = (k == 4) ? n - leavers : s_dir[s][k];
         else if (k == kCntLeavers) v = leavers;
-        else if (k < kCntSub + kWaves) v = s_wl[s][k - kCntSub];
+        else if (k < kCntSub + W) v = s_wl[s][k - kCntSub];
         a.sp[s].cnt[(int64_t)tile * kCntStride + k] = v;
     }
 
     // the tile's current halo in physical units
     float *out = a.jtile + (int64_t)tile * 3 * JP;
-    for (int e = tid; e < 3 * JP; e += kBlock) {
+    for (int e = tid; e < 3 * JP; e += NT) {
         const int comp = e / JP;
         out[e] = JAcc<JM>::value(&s_j[0][e], R, 3 * JP, a.ju[comp], a.err);
     }
 }
 
 template <int T, int R, int JM, int DM>
-__global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
+__global__ void __launch_bounds__(64 * push_waves(T)) k_push_deposit(PushArgs a)
 {
     push_tile<T, R, JM, DM>(a, blockIdx.x);
 }
@@ -599,7 +602,7 @@ __global__ void __launch_bounds__(kBlock) k_push_deposit(PushArgs a)
 // items from a shared counter (the items come largest simulations first, so
 // the expensive tiles start early and the cheap ones fill the tail).
 template <int T, int R, int JM, int DM>
-__global__ void __launch_bounds__(kBlock) k_push_batch(const PushArgs *__restrict__ descs,
+__global__ void __launch_bounds__(64 * push_waves(T)) k_push_batch(const PushArgs *__restrict__ descs,
                                                        const int4 *__restrict__ items, int n_items, int *counter)
 {
     __shared__ int s_item;
@@ -675,7 +678,7 @@ __global__ void __launch_bounds__(256) k_j_reduce_batch(const JReduceArgs *__res
 template <int T, int R, int JM, int DM>
 static void launch_pd(const PushArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_push_deposit<T, R, JM, DM>), dim3(n_tiles), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_push_deposit<T, R, JM, DM>), dim3(n_tiles), dim3(64 * push_waves(T)), 0, s, a);
 }
 
 template <int T, int JM, int DM>
@@ -683,7 +686,9 @@ static void launch_pd_r(int replicas, const PushArgs &a, int n_tiles, hipStream_
 {
     switch (replicas) {
     case 1: launch_pd<T, 1, JM, DM>(a, n_tiles, s); break;
-    case 2: launch_pd<T, 2, JM, DM>(a, n_tiles, s); break;
+    case 2:
+        if constexpr (push_lds_bytes(T, 2, JM) <= kLdsBytes) launch_pd<T, 2, JM, DM>(a, n_tiles, s);
+        break;
     default:
         // configurations over the LDS budget are rejected by pic_query/pic_init
         if constexpr (push_lds_bytes(T, 4, JM) <= kLdsBytes) launch_pd<T, 4, JM, DM>(a, n_tiles, s);
@@ -723,8 +728,8 @@ void launch_j_reduce(int tile, const JReduceArgs &r, hipStream_t s)
 template <int T, int R, int JM, int DM>
 static void launch_pb(const PushArgs *descs, const int4 *items, int n_items, int *counter, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_push_batch<T, R, JM, DM>), dim3(grid), dim3(kBlock), 0, s, descs, items, n_items,
-                       counter);
+    hipLaunchKernelGGL((k_push_batch<T, R, JM, DM>), dim3(grid), dim3(64 * push_waves(T)), 0, s, descs, items,
+                       n_items, counter);
 }
 
 template <int T, int JM, int DM>
@@ -733,7 +738,10 @@ static void launch_pb_r(int replicas, const PushArgs *descs, const int4 *items, 
 {
     switch (replicas) {
     case 1: launch_pb<T, 1, JM, DM>(descs, items, n_items, counter, grid, s); break;
-    case 2: launch_pb<T, 2, JM, DM>(descs, items, n_items, counter, grid, s); break;
+    case 2:
+        if constexpr (push_lds_bytes(T, 2, JM) <= kLdsBytes)
+            launch_pb<T, 2, JM, DM>(descs, items, n_items, counter, grid, s);
+        break;
     default:
         if constexpr (push_lds_bytes(T, 4, JM) <= kLdsBytes)
             launch_pb<T, 4, JM, DM>(descs, items, n_items, counter, grid, s);

@@ -169,25 +169,28 @@ __device__ __forceinline__ void copy_particle(const Parts &src, int64_t i, const
 // section [A, B), old section [oA, oB).  Every candidate list of holes and
 // of movers is described by one lane; the lists are then streamed as one
 // flat index space, 64 candidates per iteration, and compacted with ballots,
-// which keeps both outputs in ascending slot order.
+// which keeps both outputs in ascending slot order.  W = leaver sub-lists per
+// tile (the push kernel's wavefronts per tile).
 //   hole lists  : [A, min(B, oA))  slots of lower old sections (hole unless
 //                                  the particle there moved into t)
-//                 t's leaver sub-lists, restricted to [max(A,oA), min(B,oB))
+//                 t's W leaver sub-lists, restricted to [max(A,oA), min(B,oB))
 //                 [max(A, oB), B)  slots of higher old sections
 //   mover lists : for each source tile s of t (the nine tiles a particle of t
 //                 can come from, ascending, duplicates dropped):
-//                 s != t: s's four leaver sub-lists, entries heading to t whose
+//                 s != t: s's W leaver sub-lists, entries heading to t whose
 //                         slot is outside [A, B); data from the leaver copy
 //                 s == t: t's slots outside [A, B) whose particle kept tile t
+//                 streamed 64 / W sources at a time, in ascending order
 __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int grp)
 {
     const int lane = threadIdx.x & 63;
     // one tile per wavefront: the index is wavefront-uniform (scalar registers)
-    const int t = grp * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = grp * kSortWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (t >= a.n_tiles) return;   // whole wavefront
     const SortSpecies &sp = a.sp[spi];
     const int ntx = a.ntx, nty = a.nty;
     const int tsh = __builtin_ctz(a.tile);
+    const int W = push_waves(a.tile);   // leaver sub-lists per tile
     const int A = sp.offn[t], B = sp.offn[t + 1];
     const int oA = sp.off[t], oB = sp.off[t + 1];
     auto tile_of = [&](int cell) { return ((cell >> 16) >> tsh) * ntx + ((cell & 0xffff) >> tsh); };
@@ -201,19 +204,19 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
         if (lane == 0) {
             base = A;
             len = max(0, min(B, oA) - A);
-        } else if (lane <= kWaves) {
+        } else if (lane <= W) {
             int wlo, whi;
-            wave_range(oA, oB, lane - 1, wlo, whi);
+            wave_range(oA, oB, lane - 1, W, wlo, whi);
             kind = 1;
             base = wlo;
             len = lA < lB ? min(sp.cnt[(int64_t)t * kCntStride + kCntSub + lane - 1], whi - wlo) : 0;
-        } else if (lane == kWaves + 1) {
+        } else if (lane == W + 1) {
             base = max(A, oB);
             len = max(0, B - base);
         }
         int total;
         int ex = wave_exclusive(len, total);
-        if (lane > kWaves + 1) ex = INT_MAX;
+        if (lane > W + 1) ex = INT_MAX;
         for (int k0 = 0; k0 < total; k0 += 64) {
             const int k = k0 + lane;
             const int L = find_list(k, ex);
@@ -254,16 +257,13 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
             if (vfirst && v < so) ++rank;
             if (o < lane && v == so) first = 0;
         }
-        // list L = 4 * (rank of its source) + w
-        const int L = lane, pr = L >> 2, w = L & 3;
-        int src = -1;
-#pragma unroll
-        for (int o = 0; o < 9; ++o) {
-            const int v = __shfl(so, o, 64), vr = __shfl(rank, o, 64), vf = __shfl(first, o, 64);
-            if (vf && vr == pr) src = v;
-        }
-        int kind = 0, base = 0, len = 0;   // kind 0: slot range of t, 1: leaver sub-list of src
-        if (pr < nuniq) {
+        // The lists of one source tile: kind 0 -- t's own slot ranges outside
+        // [A, B) (lists 0 and 1), kind 1 -- the source's W leaver sub-lists.
+        auto source_list = [&](int src, int w, int &kind, int &base, int &len) {
+            kind = 0;
+            base = 0;
+            len = 0;
+            if (src < 0) return;   // no source of that rank
             if (src == t) {
                 if (w == 0) {
                     base = oA;
@@ -272,50 +272,76 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
                     base = max(oA, B);
                     len = max(0, oB - base);
                 }
-            } else {
+            } else if (w < W) {
                 const int s0 = sp.off[src], s1 = sp.off[src + 1];
                 int wlo, whi;
-                wave_range(s0, s1, w, wlo, whi);
+                wave_range(s0, s1, w, W, wlo, whi);
                 kind = 1;
                 base = wlo;
                 len = min(sp.cnt[(int64_t)src * kCntStride + kCntSub + w], whi - wlo);
             }
-        }
-        int total;
-        int ex = wave_exclusive(len, total);
-        if (pr >= nuniq) ex = INT_MAX;
-        for (int k0 = 0; k0 < total; k0 += 64) {
-            const int k = k0 + lane;
-            const int Lk = find_list(k, ex);
-            const int kL = __shfl(kind, Lk, 64), bL = __shfl(base, Lk, 64), eL = __shfl(ex, Lk, 64);
-            const int sL = __shfl(src, Lk, 64);
-            bool p = false;
-            bool from_leavers = false;
-            int64_t at = 0;
-            if (k < total) {
-                if (kL == 0) {
-                    at = bL + (k - eL);
-                    p = tile_of(sp.p.cell[at]) == t;
-                } else {
-                    at = (int64_t)bL + (k - eL);
-                    const uint32_t e = sp.leav[at];
-                    const int d = (int)(e & 15u), loc = (int)(e >> 4);
-                    const int s0 = sp.off[sL], ns = sp.off[sL + 1] - s0;
-                    if (loc >= ns || d > 8) {
-                        bad = true;
+        };
+        // Stream the lists held by the lanes (one each; `valid` false: none) as
+        // one index space, 64 candidates per iteration, appending t's movers.
+        auto stream_lists = [&](int kind, int base, int len, int src, bool valid) {
+            int total;
+            int ex = wave_exclusive(len, total);
+            if (!valid) ex = INT_MAX;
+            for (int k0 = 0; k0 < total; k0 += 64) {
+                const int k = k0 + lane;
+                const int Lk = find_list(k, ex);
+                const int kL = __shfl(kind, Lk, 64), bL = __shfl(base, Lk, 64), eL = __shfl(ex, Lk, 64);
+                const int sL = __shfl(src, Lk, 64);
+                bool p = false;
+                bool from_leavers = false;
+                int64_t at = 0;
+                if (k < total) {
+                    if (kL == 0) {
+                        at = bL + (k - eL);
+                        p = tile_of(sp.p.cell[at]) == t;
                     } else {
-                        const int sx = sL % ntx, sy = sL / ntx;
-                        const int dest = wrap_s(sy + d / 3 - 1, nty) * ntx + wrap_s(sx + d % 3 - 1, ntx);
-                        const int slot = s0 + loc;
-                        p = dest == t && !(slot >= A && slot < B);
-                        from_leavers = true;
+                        at = (int64_t)bL + (k - eL);
+                        const uint32_t e = sp.leav[at];
+                        const int d = (int)(e & 15u), loc = (int)(e >> 4);
+                        const int s0 = sp.off[sL], ns = sp.off[sL + 1] - s0;
+                        if (loc >= ns || d > 8) {
+                            bad = true;
+                        } else {
+                            const int sx = sL % ntx, sy = sL / ntx;
+                            const int dest = wrap_s(sy + d / 3 - 1, nty) * ntx + wrap_s(sx + d % 3 - 1, ntx);
+                            const int slot = s0 + loc;
+                            p = dest == t && !(slot >= A && slot < B);
+                            from_leavers = true;
+                        }
                     }
                 }
+                const unsigned long long m = __ballot(p);
+                const int r = nm + lane_rank_s(m);
+                if (p && r < B - A) copy_particle(from_leavers ? sp.lp : sp.p, at, sp.stg, (int64_t)A + r);
+                nm += __popcll(m);
             }
-            const unsigned long long m = __ballot(p);
-            const int r = nm + lane_rank_s(m);
-            if (p && r < B - A) copy_particle(from_leavers ? sp.lp : sp.p, at, sp.stg, (int64_t)A + r);
-            nm += __popcll(m);
+        };
+        // the source tile of rank q (ascending tile id = ascending old slot),
+        // -1 if there is none; executed by all lanes (it reads lanes 0..8)
+        auto source_of_rank = [&](int q) {
+            int v = -1;
+#pragma unroll
+            for (int o = 0; o < 9; ++o) {
+                // every lane takes part in every shuffle; the selection follows
+                const int so_o = __shfl(so, o, 64), rank_o = __shfl(rank, o, 64), first_o = __shfl(first, o, 64);
+                if (first_o && rank_o == q) v = so_o;
+            }
+            return v;
+        };
+        // 64 / W sources per round, in ascending order: lane L holds list
+        // L % W of the source of rank q0 + L / W (one round when W = 4)
+        const int G = 64 / W;
+        for (int q0 = 0; q0 < nuniq; q0 += G) {
+            const int pr = q0 + lane / W, w = lane % W;
+            const int src = source_of_rank(pr);
+            int kind, base, len;
+            source_list(src, w, kind, base, len);
+            stream_lists(kind, base, len, src, pr < nuniq);
         }
     }
 
@@ -331,7 +357,7 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
 __device__ __forceinline__ void sort_scatter_unit(const SortArgs &a, int spi, int grp)
 {
     const int lane = threadIdx.x & 63;
-    const int t = grp * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = grp * kSortWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (t >= a.n_tiles) return;
     const SortSpecies &sp = a.sp[spi];
     const int A = sp.offn[t], m = sp.mcount[t];
@@ -429,12 +455,14 @@ void launch_sort_scan(const SortArgs &a, int n_tiles, hipStream_t s)
 
 void launch_sort_plan(const SortArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sort_plan, dim3((n_tiles + kWaves - 1) / kWaves, a.n_species), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sort_plan, dim3((n_tiles + kSortWaves - 1) / kSortWaves, a.n_species), dim3(kBlock), 0, s,
+                       a);
 }
 
 void launch_sort_scatter(const SortArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sort_scatter, dim3((n_tiles + kWaves - 1) / kWaves, a.n_species), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_sort_scatter, dim3((n_tiles + kSortWaves - 1) / kSortWaves, a.n_species), dim3(kBlock), 0,
+                       s, a);
 }
 
 void launch_sort_batch(const SortBatch &b, hipStream_t s)

@@ -773,7 +773,7 @@ BatchLayout batch_layout(int n, const pic_config *cfgs)
         L.n_node += ((c.nx + 63) / 64) * ((c.ny + 3) / 4);
         L.n_count += c.n_species * ((nt + kScanBlock - 1) / kScanBlock);
         L.n_scan += c.n_species;
-        L.n_plan += c.n_species * ((nt + kWaves - 1) / kWaves);
+        L.n_plan += c.n_species * ((nt + kSortWaves - 1) / kSortWaves);
     }
     size_t p = 0;
     auto take = [&](size_t bytes) {
@@ -899,7 +899,8 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
             for (int k = 0; k < (S->n_tiles + kScanBlock - 1) / kScanBlock; ++k)
                 count_items.push_back(make_int4(i, s, k, 0));
             scan_items.push_back(make_int4(i, s, 0, 0));
-            for (int k = 0; k < (S->n_tiles + kWaves - 1) / kWaves; ++k) plan_items.push_back(make_int4(i, s, k, 0));
+            for (int k = 0; k < (S->n_tiles + kSortWaves - 1) / kSortWaves; ++k)
+                plan_items.push_back(make_int4(i, s, k, 0));
         }
     }
     std::sort(cost.begin(), cost.end());

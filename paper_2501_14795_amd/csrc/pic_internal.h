@@ -10,18 +10,25 @@
 namespace pic {
 
 constexpr int kMaxSpecies = PIC_MAX_SPECIES;
-constexpr int kBlock = 256;          // threads per push / sort block (4 wavefronts)
-constexpr int kWaves = kBlock / 64;
-constexpr int kCntStride = 16;       // ints per tile in the count record
+constexpr int kBlock = 256;          // threads per sort / stencil block (4 wavefronts)
+constexpr int kSortWaves = kBlock / 64;   // tiles per sort plan / scatter block (one per wavefront)
+constexpr int kCntStride = 32;       // ints per tile in the count record
 constexpr int kScanBlock = 256;      // tiles per block of the tile-count scan
 
+// Wavefronts that push one tile (one workgroup of 64 * W threads): 4 up to
+// 16 x 16 tiles; 16 for 32 x 32 tiles, whose LDS (E/B halo and current) fills
+// most of a compute unit, so a single workgroup must bring the occupancy.
+__host__ __device__ constexpr int push_waves(int T) { return T >= 32 ? 16 : 4; }
+constexpr int kMaxWaves = 16;
+
 // Count record of one tile, written by the push kernel:
-//   [0..8]   particles per direction of motion d = (dty+1)*3 + (dtx+1);
-//            [4] holds the particles that kept their tile
-//   [9]      leavers (sum of the eight non-centre directions)
-//   [10..13] leavers found by wavefront w (length of leaver sub-list w)
+//   [0..8]        particles per direction of motion d = (dty+1)*3 + (dtx+1);
+//                 [4] holds the particles that kept their tile
+//   [9]           leavers (sum of the eight non-centre directions)
+//   [10..10+W-1]  leavers found by wavefront w (length of leaver sub-list w)
 constexpr int kCntLeavers = 9;
 constexpr int kCntSub = 10;
+static_assert(kCntSub + kMaxWaves <= kCntStride, "count record too short");
 
 // Device error bits (ORed into Sim::err).
 enum : int {
@@ -58,7 +65,8 @@ static_assert(kLeaverBuf >= 64 && kPieceBuf >= 64, "per-wavefront LDS buffers mu
 constexpr int push_lds_bytes(int T, int R, int JM)
 {
     return (T + 2) * (T + 2) * 48 + R * 3 * (T + 3) * (T + 3) * (JM == kJFixed ? 8 : 4) +
-           kMaxSpecies * (9 + kWaves) * 4 + kWaves * 7 * kLeaverBuf * 4 + kWaves * 6 * kPieceBuf * 4;
+           kMaxSpecies * (9 + push_waves(T)) * 4 + push_waves(T) * 7 * kLeaverBuf * 4 +
+           push_waves(T) * 6 * kPieceBuf * 4;
 }
 
 // One species' particles as a structure of arrays (n entries each).
@@ -92,16 +100,16 @@ struct PushArgs {
 
 // The part of a tile section [begin, end) streamed by wavefront w of the
 // push kernel: the 64-aligned chunks covering the section are split into
-// kWaves contiguous runs.  Returns the slot range [lo, hi) (lo >= hi: none).
+// W contiguous runs.  Returns the slot range [lo, hi) (lo >= hi: none).
 // The leavers found by wavefront w are stored from slot lo of the leaver list.
-__host__ __device__ __forceinline__ void wave_range(int begin, int end, int w, int &lo, int &hi)
+__host__ __device__ __forceinline__ void wave_range(int begin, int end, int w, int W, int &lo, int &hi)
 {
     if (end <= begin) {
         lo = hi = begin;
         return;
     }
     const int c0 = begin >> 6, c1 = (end + 63) >> 6;
-    const int q = (c1 - c0 + kWaves - 1) / kWaves;
+    const int q = (c1 - c0 + W - 1) / W;
     const int a = (c0 + w * q) << 6, b = (c0 + (w + 1) * q) << 6;
     lo = a > begin ? a : begin;
     hi = b < end ? b : end;
@@ -164,7 +172,7 @@ void launch_sort_scatter(const SortArgs &a, int n_tiles, hipStream_t s);
 
 // Batched sort phases.  Work tables (int4 per block):
 //   count/add: (sim, species, block of kScanBlock tiles)   scan: (sim, species)
-//   plan/scatter: (sim, species, group of kWaves tiles)
+//   plan/scatter: (sim, species, group of kSortWaves tiles)
 struct SortBatch {
     const SortArgs *descs;
     const int4 *count_items; int n_count;

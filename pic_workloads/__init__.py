@@ -71,9 +71,9 @@ WORKLOADS = {
          SpeciesSpec(-1.0, (8, 8), (0.1, 0.1, 0.1), (0.0, 0.0, -0.6))],
         "512x512 cells, two electron beams u_fl=+-0.6 along z, 64 ppc each"),
     "warm2048": Workload(
-        "warm2048", 2048, 2048, 0.1, 0.1, 0.07, 16, 200, 3,
+        "warm2048", 2048, 2048, 0.1, 0.1, 0.07, 32, 200, 3,
         [SpeciesSpec(-1.0, (4, 4), (0.05, 0.05, 0.05), (0.2, 0.0, 0.0))],
-        "2048x2048 cells, 16 ppc warm electrons u_th=0.05 drifting u_x=0.2"),
+        "2048x2048 cells, 16 ppc warm electrons u_th=0.05 drifting u_x=0.2, tile 32"),
     "langmuir1024": Workload(
         "langmuir1024", 1024, 1024, 0.1, 0.1, 0.07, 16, 10000, 5,
         [SpeciesSpec(-1.0, (8, 4), (0.0, 0.0, 0.0), (0.0, 0.0, 0.0))],

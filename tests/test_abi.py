@@ -108,7 +108,9 @@ def test_query_sizes_and_validation():
             L.pic_query(c)
         assert e.value.code == code, (kw, e.value.code)
     assert L.pic_query(_cfg(L, dt=0.0707)).n_tiles == 16
-    assert L.pic_query(_cfg(L, nx=64, tile=32, reps=4, flags=L.PIC_FLAG_J_FLOAT)).n_tiles == 4
+    assert L.pic_query(_cfg(L, nx=64, tile=32, reps=2, flags=L.PIC_FLAG_J_FLOAT)).n_tiles == 4
+    with pytest.raises(L.PicError):   # 16 wavefronts per 32 x 32 tile leave no room for 4 FP32 replicas
+        L.pic_query(_cfg(L, nx=64, tile=32, reps=4, flags=L.PIC_FLAG_J_FLOAT))
     assert L.pic_query(_cfg(L, flags=L.PIC_FLAG_ESIRKEPOV)).work_bytes == s.work_bytes
     # the filter's ping-pong planes: three FP32 current planes + one FP64 density plane
     sf = L.pic_query(_cfg(L, filt=L.PIC_MAX_FILTER))

@@ -33,10 +33,10 @@ def _assert_same(a, b):
     assert np.array_equal(a.tile_offsets(0), b.tile_offsets(0))
 
 
-@pytest.mark.parametrize("tile", [16, 8])
+@pytest.mark.parametrize("tile", [16, 8, 32])
 def test_batch_equals_members_run_alone(tile):
     from paper_2501_14795_amd import Batch, Sim
-    members = _members(7, 11, tile)
+    members = _members(7, 11, tile, sizes=(32, 64, 96) if tile == 32 else (32, 48, 64, 96))
     batch = Batch(members, tile=tile)
     alone = [Sim(m["nx"], m["ny"], m["dx"], m["dy"], m["dt"], tile, m["species"]) for m in members]
     for _ in range(4):
