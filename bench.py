@@ -65,7 +65,14 @@ def cpu_baseline(w, st, T, budget_s=10.0, max_steps=8):
         t_hot += time.perf_counter() - t0
         sim.field_advance()
         steps += 1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": M * steps / t_hot, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
+            "host_cores": os.cpu_count(), "cpu_model": model,
             "sample": f"first {M} particles (tiles 0-{M // (T * T * s.n_ppc) - 1}, tile {T}) of the "
                       f"{w.nx}x{w.ny} workload, {steps} steps of push+deposit+sort, serial FP64 C "
                       f"(field advance untimed)",
@@ -316,7 +323,8 @@ def main():
             "leavers_per_step": leavers, "movers_per_step": movers,
         },
         "energy": {"u_e": d.u_e, "u_b": d.u_b, "u_k": d.u_k[0]},
-        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample",
+                                                                     "host_cores", "cpu_model")},
     }
     sim.close()
     del sim
