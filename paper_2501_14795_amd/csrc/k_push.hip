@@ -620,7 +620,11 @@ __global__ void __launch_bounds__(64 * push_waves(T)) k_push_batch(const PushArg
 
 // J[c][gy][gx] = sum over the tiles whose halo (relative -1..T+1) covers the
 // node, in fixed (ty, tx) order with compensation -- the periodic fold of
-// update_gc_add.  One 64 x 4 block of nodes.
+// update_gc_add.  One 64 x 4 block of nodes.  A node at tile-relative
+// (rx, ry) is covered by its own tile and, along x, by the left neighbour
+// when rx <= 1 or the right one when rx >= T-1 (likewise along y): at most
+// 2 x 2 halos, whose values are all loaded before the sums (absent ones as
+// zero, which leaves a compensated sum unchanged).
 template <int T>
 __device__ __forceinline__ void j_reduce_block(const JReduceArgs &r, int bxb, int byb)
 {
@@ -633,26 +637,34 @@ __device__ __forceinline__ void j_reduce_block(const JReduceArgs &r, int bxb, in
     const int gy = byb * 4 + (threadIdx.x >> 6);
     if (gx >= nx || gy >= ny) return;
     const int bx = gx / T, by = gy / T;
-    float sum[3] = {0.0f, 0.0f, 0.0f}, cmp[3] = {0.0f, 0.0f, 0.0f};
-    for (int ky = -1; ky <= 1; ++ky) {
-        const int ry = gy - (by + ky) * T;
-        if (ry < -1 || ry > T + 1) continue;
-        const int ty = wrapi(by + ky, nty);
-        for (int kx = -1; kx <= 1; ++kx) {
-            const int rx = gx - (bx + kx) * T;
-            if (rx < -1 || rx > T + 1) continue;
-            const int tx = wrapi(bx + kx, ntx);
-            const float *src = jtile + (int64_t)(ty * ntx + tx) * 3 * JP + (ry + 1) * NJ + (rx + 1);
+    const int rx = gx - bx * T, ry = gy - by * T;
+    // the two candidate offsets per axis, ascending: (-1, 0), (0, +1) or (0, none)
+    const int kx0 = rx <= 1 ? -1 : 0, kx1 = rx <= 1 ? 0 : (rx >= T - 1 ? 1 : 0);
+    const bool hx = rx <= 1 || rx >= T - 1;
+    const int ky0 = ry <= 1 ? -1 : 0, ky1 = ry <= 1 ? 0 : (ry >= T - 1 ? 1 : 0);
+    const bool hy = ry <= 1 || ry >= T - 1;
+    float v[4][3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float v = src[c * JP];
-                const float t = sum[c] + v;
-                const float bp = t - sum[c];
-                cmp[c] += (sum[c] - (t - bp)) + (v - bp);
-                sum[c] = t;
-            }
-        }
+    for (int q = 0; q < 4; ++q) {
+        const int ky = (q >> 1) ? ky1 : ky0, kx = (q & 1) ? kx1 : kx0;
+        const bool valid = ((q >> 1) == 0 || hy) && ((q & 1) == 0 || hx);
+        const int ty = wrapi(by + ky, nty), tx = wrapi(bx + kx, ntx);
+        const int ly = ry - ky * T, lx = rx - kx * T;   // in -1..T+1
+        const float *src = jtile + (int64_t)(ty * ntx + tx) * 3 * JP + (ly + 1) * NJ + (lx + 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) v[q][c] = valid ? src[c * JP] : 0.0f;
     }
+    float sum[3] = {0.0f, 0.0f, 0.0f}, cmp[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float x = v[q][c];
+            const float t = sum[c] + x;
+            const float bp = t - sum[c];
+            cmp[c] += (sum[c] - (t - bp)) + (x - bp);
+            sum[c] = t;
+        }
     const int64_t plane = (int64_t)nx * ny;
     const int64_t k = (int64_t)gy * nx + gx;
     J[k] = sum[0] + cmp[0];
