@@ -18,7 +18,9 @@ Particle-Mesh Algorithms with FPGAs and OmpSs@OpenCL"):
 * ``OracleSim.push_deposit`` -- the particle loop of Listing 3.1 + Eq. (11)
 * ``yee_b`` / ``yee_e`` / ``OracleSim.field_advance`` -- Eqs. (19)-(20), the
                            three-step Yee update of Listing 3.1
-* ``sort_canonical``    -- strict tile re-sort (Sec. 4.3, Fig. 4.5)
+* ``sort_canonical``    -- strict tile re-sort (Sec. 4.3, Fig. 4.5), with the
+                           removed / appended particles of the moving window
+* ``OracleSim.move_window`` -- the moving-window step of Listing 3.1
 * ``binomial_filter``   -- the optional current smoothing of Listing 3.1
 * ``rho`` / energies / divergences -- diagnostics (Eq. 17, Eq. 18, Eq. 12)
 """
@@ -68,7 +70,7 @@ def lib():
         L.ora_yee_b.argtypes = [_i, _i, _d, _d, _d, _p, _p]
         L.ora_yee_e.argtypes = [_i, _i, _d, _d, _d, _p, _p, _p]
         L.ora_field_advance.argtypes = [_i, _i, _d, _d, _d, _p, _p, _p]
-        L.ora_sort_canonical.argtypes = [_i, _i, _i, _i64, _p, _p, _p, _p]
+        L.ora_sort_canonical.argtypes = [_i, _i, _i, _i64, _p, _p, _p, _p, _p, _p]
         L.ora_sort_canonical.restype = _i
         L.ora_deposit_rho.argtypes = [_i, _i, _d, _i64, _p, _p, _p, _p, _p]
         L.ora_field_energy.argtypes = [_i, _i, _d, _d, _p]
@@ -142,18 +144,22 @@ def yee_e(nx, ny, dx, dy, h, B, J, E):
     lib().ora_yee_e(nx, ny, dx, dy, h, _ptr(B), _ptr(J), _ptr(E))
 
 
-def sort_canonical(nx, ny, T, ix, iy):
-    """Canonical strict tile sort.  Returns (off[ntiles+1], src[n]) as int64."""
+def sort_canonical(nx, ny, T, ix, iy, removed=None):
+    """Canonical strict tile sort.  Returns (off[ntiles+1], src[n']) as int64;
+    `removed` (bool array or None) marks particles that belong to no tile."""
     ix = _i32(ix)
     iy = _i32(iy)
     n = ix.size
     ntiles = (nx // T) * (ny // T)
     off = np.zeros(ntiles + 1, dtype=np.int64)
     src = np.zeros(max(n, 1), dtype=np.int64)
-    rc = lib().ora_sort_canonical(nx, ny, T, n, _ptr(ix), _ptr(iy), _ptr(off), _ptr(src))
+    n_out = np.zeros(1, dtype=np.int64)
+    rm = None if removed is None else np.ascontiguousarray(removed, dtype=np.uint8)
+    rc = lib().ora_sort_canonical(nx, ny, T, n, _ptr(ix), _ptr(iy), None if rm is None else _ptr(rm), _ptr(off),
+                                  _ptr(src), _ptr(n_out))
     if rc != 0:
         raise ValueError("cell index out of range")
-    return off, src[:n]
+    return off, src[:int(n_out[0])]
 
 
 def rho(nx, ny, q, ix, iy, x, y, out=None) -> np.ndarray:
@@ -273,6 +279,29 @@ class OracleSim:
         if T is not None:
             self.sort(T)
         self.field_advance()
+
+    def move_window(self, inject, T):
+        """The moving-window step at the end of Listing 3.1: E and B move one
+        cell towards -x (the new last column is zero), every particle moves one
+        cell towards -x (ix - 1, offsets kept), the particles that were in
+        column 0 leave, and the new particles `inject` (one dict of ix, iy, x,
+        y, ux, uy, uz arrays per species, all in column nx - 1) come in.  The
+        particles are then re-sorted canonically by tile, the new ones counted
+        as appended after the existing ones, the leaving ones as removed."""
+        for F in (self.E, self.B):
+            F[:, :, :-1] = F[:, :, 1:].copy()
+            F[:, :, -1] = 0.0
+        for s, inj in zip(self.species, inject):
+            ix = s.ix - 1
+            removed = ix < 0
+            ix = np.where(removed, 0, ix)
+            cat = {"ix": np.r_[ix, _i32(inj["ix"])], "iy": np.r_[s.iy, _i32(inj["iy"])]}
+            for name in ("x", "y", "ux", "uy", "uz"):
+                cat[name] = np.r_[getattr(s, name), _f64(inj[name])]
+            rm = np.r_[removed, np.zeros(len(inj["ix"]), bool)]
+            _, src = sort_canonical(self.nx, self.ny, T, cat["ix"], cat["iy"], removed=rm)
+            for name, v in cat.items():
+                setattr(s, name, np.ascontiguousarray(v[src], dtype=np.int32 if name in ("ix", "iy") else np.float64))
 
     def rho(self, filtered=False):
         """Node charge density; with filtered=True smoothed by the current filter

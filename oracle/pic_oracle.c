@@ -384,7 +384,7 @@ void ora_field_advance(int nx, int ny, double dx, double dy, double dt,
 
 /*
  * Tiles are T x T cells, numbered row-major: t = (iy / T) * (nx / T) + ix / T.
- * Output: off[0 .. ntiles] (new tile_offset) and src[0 .. n): the particle at
+ * Output: off[0 .. ntiles] (new tile_offset) and src[0 .. n'): the particle at
  * slot j after the sort is the one that was at slot src[j].
  *
  * The pairing of holes and movers is not fixed by the paper (it registers them
@@ -392,10 +392,16 @@ void ora_field_advance(int nx, int ny, double dx, double dy, double dt,
  * slots in ascending order (so they come grouped by section), movers are the
  * non-staying particles ordered by destination tile and, within one tile, by
  * ascending slot; the k-th hole receives the k-th mover.
- * Returns 0, or -1 if a cell index is out of range.
+ *
+ * removed (NULL: none): particles with removed[i] != 0 belong to no tile (the
+ * moving window drops them); they are not counted, their slots are holes, and
+ * the array shrinks to n' = n - (removed particles) slots.  Particles appended
+ * to the array (the window's new particles) are movers like any other.
+ * *n_out = n'.  Returns 0, or -1 if a cell index is out of range.
  */
 int ora_sort_canonical(int nx, int ny, int T, int64_t n, const int32_t *ix,
-                       const int32_t *iy, int64_t *off, int64_t *src)
+                       const int32_t *iy, const unsigned char *removed,
+                       int64_t *off, int64_t *src, int64_t *n_out)
 {
     const int ntx = nx / T, nty = ny / T;
     const int64_t ntiles = (int64_t)ntx * nty;
@@ -409,6 +415,10 @@ int ora_sort_canonical(int nx, int ny, int T, int64_t n, const int32_t *ix,
 
     /* step (1): count the particles per tile at their final position */
     for (int64_t i = 0; i < n; i++) {
+        if (removed && removed[i]) {
+            tile[i] = -1;
+            continue;
+        }
         if (ix[i] < 0 || ix[i] >= nx || iy[i] < 0 || iy[i] >= ny) {
             rc = -1;
             goto done;
@@ -418,25 +428,29 @@ int ora_sort_canonical(int nx, int ny, int T, int64_t n, const int32_t *ix,
     }
     off[0] = 0;
     for (int64_t t = 0; t < ntiles; t++) off[t + 1] = off[t] + cnt[t];
+    const int64_t n_new = off[ntiles];
 
     /* a particle stays iff its slot is inside its tile's new section */
     for (int64_t i = 0; i < n; i++)
-        stay[i] = (i >= off[tile[i]] && i < off[tile[i] + 1]);
+        stay[i] = tile[i] >= 0 && i >= off[tile[i]] && i < off[tile[i] + 1];
 
-    /* steps (2)-(4): holes in ascending order; movers grouped by destination tile */
+    /* steps (2)-(4): holes (non-staying slots of the new array) in ascending
+       order; movers (non-staying particles that still exist) grouped by
+       destination tile */
     int64_t nh = 0;
-    for (int64_t i = 0; i < n; i++)
+    for (int64_t i = 0; i < n_new; i++)
         if (!stay[i]) holes[nh++] = i;
     memset(cnt, 0, sizeof(int64_t) * (ntiles + 1));
     for (int64_t i = 0; i < n; i++)
-        if (!stay[i]) cnt[tile[i]]++;
+        if (tile[i] >= 0 && !stay[i]) cnt[tile[i]]++;
     for (int64_t t = 0; t < ntiles; t++) mstart[t + 1] = mstart[t] + cnt[t];
     for (int64_t i = 0; i < n; i++)
-        if (!stay[i]) movers[mstart[tile[i]]++] = i;
+        if (tile[i] >= 0 && !stay[i]) movers[mstart[tile[i]]++] = i;
 
     /* step (5): move */
-    for (int64_t j = 0; j < n; j++) src[j] = j;
+    for (int64_t j = 0; j < n_new; j++) src[j] = j;
     for (int64_t k = 0; k < nh; k++) src[holes[k]] = movers[k];
+    *n_out = n_new;
 
 done:
     free(tile);

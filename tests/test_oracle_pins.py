@@ -525,3 +525,68 @@ def test_esirkepov_whole_step_gauss(ora):
         sim.field_advance()
     g = div_edge(sim.E, sim.dx, sim.dy) - node_charge(sim.nx, sim.ny, s.q, s.ix + s.x, s.iy + s.y)
     assert np.abs(g - g0).max() < 1e-11
+
+
+# ---------------------------------------------------------------- moving window
+def _lattice_column(nx, ny, ppc, column):
+    px, py = ppc
+    a, b, j = np.meshgrid(np.arange(px), np.arange(py), np.arange(ny), indexing="ij")
+    n = a.size
+    return {"ix": np.full(n, column, np.int32), "iy": j.reshape(-1).astype(np.int32),
+            "x": ((a.reshape(-1) + 0.5) / px), "y": ((b.reshape(-1) + 0.5) / py),
+            "ux": np.zeros(n), "uy": np.zeros(n), "uz": np.zeros(n)}
+
+
+def test_moving_window_keeps_a_uniform_plasma(ora):
+    """A window shift over a uniform cold lattice plasma, with a fresh lattice
+    column injected at the new right edge, gives back the same plasma: the
+    same number of particles, the same positions and exactly the same node
+    charge."""
+    import pic_workloads as pw
+    nx, ny, T = 16, 8, 4
+    spec = pw.SpeciesSpec(-1.0, (2, 2), (0.0, 0.0, 0.0), (0.0, 0.0, 0.0))
+    st = pw.species_state(nx, ny, T, spec, 1)
+    sp = ora.OracleSpecies(spec.qm, spec.q, st["ix"], st["iy"], st["x"], st["y"], st["ux"], st["uy"], st["uz"])
+    sim = ora.OracleSim(nx, ny, 0.1, 0.1, 0.07, [sp])
+    r0 = sim.rho()
+    pos0 = sorted(zip(sp.ix.tolist(), sp.iy.tolist(), sp.x.tolist(), sp.y.tolist()))
+    sim.move_window([_lattice_column(nx, ny, (2, 2), nx - 1)], T)
+    s = sim.species[0]
+    assert s.ix.size == st["ix"].size
+    assert sorted(zip(s.ix.tolist(), s.iy.tolist(), s.x.tolist(), s.y.tolist())) == pos0
+    np.testing.assert_array_equal(sim.rho(), r0)
+    tiles = (s.iy // T) * (nx // T) + s.ix // T
+    assert (np.diff(tiles) >= 0).all()          # re-sorted by tile
+
+
+def test_moving_window_holds_a_light_pulse(ora):
+    """A vacuum light pulse travelling in +x, with the window shifted by one
+    cell whenever light has crossed one cell (every 2 steps at c dt = dx/2),
+    stays where it is in window coordinates; without the shifts it moves
+    about one cell per two steps."""
+    nx, ny, dx, dt = 256, 4, 0.1, 0.05
+    X = np.arange(nx)
+    def pulse():
+        E = np.zeros((3, ny, nx))
+        B = np.zeros((3, ny, nx))
+        E[2] = np.exp(-((X - 60.0) / 8.0) ** 2)[None, :]
+        # By at (i + 1/2), a quarter cell behind: half a time step at c dt = dx / 2
+        B[1] = -np.exp(-((X + 0.5 - 60.0 - 0.25) / 8.0) ** 2)[None, :]
+        return E, B
+    def centroid(E):
+        w = E[2, 0] ** 2
+        return (w * X).sum() / w.sum()
+    for shift in (True, False):
+        E, B = pulse()
+        sim = ora.OracleSim(nx, ny, dx, dx, dt, [], E, B)
+        c0 = centroid(sim.E)
+        for n in range(1, 81):
+            sim.push_deposit()
+            sim.field_advance()
+            if shift and n % 2 == 0:
+                sim.move_window([], 4)
+        moved = centroid(sim.E) - c0
+        if shift:
+            assert abs(moved) < 1.0, moved
+        else:
+            assert abs(moved - 40.0) < 1.0, moved

@@ -28,14 +28,15 @@ def _read_golden(name):
                 continue
             k, v = line.split(":")
             vals = [int(t) for t in v.split()]
-            d[k.strip()] = vals if len(vals) > 1 or k.strip() in ("ix", "iy", "off", "src") else vals[0]
+            d[k.strip()] = vals if len(vals) > 1 or k.strip() in ("ix", "iy", "off", "src", "removed") else vals[0]
     return d
 
 
-@pytest.mark.parametrize("name", ["sort_fig45.txt", "sort_shift3.txt"])
+@pytest.mark.parametrize("name", ["sort_fig45.txt", "sort_shift3.txt", "sort_window.txt"])
 def test_sort_golden(ora, name):
     g = _read_golden(name)
-    off, src = ora.sort_canonical(g["nx"], g["ny"], g["T"], g["ix"], g["iy"])
+    removed = None if "removed" not in g else np.array(g["removed"], bool)
+    off, src = ora.sort_canonical(g["nx"], g["ny"], g["T"], g["ix"], g["iy"], removed=removed)
     assert off.tolist() == g["off"]
     assert src.tolist() == g["src"]
 
@@ -94,3 +95,49 @@ def test_sort_properties_large(ora):
 def test_sort_rejects_bad_cells(ora):
     with pytest.raises(ValueError):
         ora.sort_canonical(4, 4, 2, [0, 4], [0, 0])
+
+
+def _valid_removal(perm, tile, removed, off):
+    """(a) sections hold their own tile, (b) a kept particle already inside
+    its new section stays, (c) holes take movers in ascending old slot,
+    (d) every kept particle appears exactly once and no removed one does."""
+    n_new = off[-1]
+    kept = [i for i in range(len(tile)) if not removed[i]]
+    if sorted(perm) != kept:
+        return False
+    for j in range(n_new):
+        t = tile[perm[j]]
+        if not (off[t] <= j < off[t + 1]):
+            return False
+    stay = [not removed[i] and off[tile[i]] <= i < off[tile[i] + 1] for i in range(len(tile))]
+    for i in range(n_new):
+        if stay[i] and perm[i] != i:
+            return False
+    for t in range(len(off) - 1):
+        filled = [perm[j] for j in range(off[t], off[t + 1]) if not stay[j]]
+        if filled != sorted(filled):
+            return False
+    return True
+
+
+def test_sort_with_removal_brute_force_tiny(ora):
+    """The moving window's sort: some particles removed, new ones appended;
+    enumerating every arrangement of the kept particles shows the properties
+    fix one answer, which the oracle returns."""
+    rng = np.random.default_rng(7)
+    for trial in range(150):
+        nx, ny, T = [(2, 2, 1), (4, 2, 2), (3, 1, 1), (2, 1, 1)][trial % 4]
+        n = int(rng.integers(1, 7))
+        ix = rng.integers(0, nx, n)
+        iy = rng.integers(0, ny, n)
+        removed = rng.random(n) < 0.3
+        tile = _tiles(nx, T, ix, iy)
+        ntiles = (nx // T) * (ny // T)
+        kept_tiles = tile[~removed]
+        off = np.r_[0, np.cumsum(np.bincount(kept_tiles, minlength=ntiles))]
+        n_new = int(off[-1])
+        sols = [p for p in itertools.permutations(range(n), n_new) if _valid_removal(list(p), tile, removed, off)]
+        assert len(sols) == 1, (trial, len(sols))
+        o_off, o_src = ora.sort_canonical(nx, ny, T, ix, iy, removed=removed)
+        assert o_off.tolist() == off.tolist()
+        assert tuple(o_src.tolist()) == sols[0]
