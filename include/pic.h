@@ -94,6 +94,13 @@ extern "C" {
 #define PIC_FLAG_ESIRKEPOV 2u
 
 /*
+ * Moving window (pic_config.flags; the last step of Listing 3.1): enables
+ * pic_move_window() and sizes the workspace for it.  Not available in
+ * batched mode.
+ */
+#define PIC_FLAG_MOVING_WINDOW 4u
+
+/*
  * Binomial current filter (pic_config.j_filter; Listing 3.1's optional
  * smoothing of J after update_gc_add).  Each pass smooths every J component
  * with the three-point kernel (1/4, 1/2, 1/4) along x, then along y, on the
@@ -108,6 +115,8 @@ typedef struct pic_species {
     double qm;    /* charge-to-mass ratio q/m (electrons: -1) */
     double q;     /* charge density carried by one particle (e.g. -n0 / ppc) */
     int64_t n;    /* number of particles, 0 <= n < 2^31 */
+    int64_t cap;  /* entries of the particle arrays, n <= cap < 2^31 (0: n); the
+                     moving window adds and removes particles within it */
 } pic_species;
 
 typedef struct pic_config {
@@ -116,7 +125,7 @@ typedef struct pic_config {
     int32_t tile;        /* tile edge in cells: 8, 16 or 32 */
     int32_t j_replicas;  /* LDS current replicas per tile: 1, 2 or 4 (0 = default) */
     int32_t n_species;   /* 1 .. PIC_MAX_SPECIES */
-    uint32_t flags;      /* 0, PIC_FLAG_J_FLOAT or PIC_FLAG_ESIRKEPOV */
+    uint32_t flags;      /* PIC_FLAG_J_FLOAT, PIC_FLAG_ESIRKEPOV, PIC_FLAG_MOVING_WINDOW or 0 */
     int32_t j_filter;    /* binomial current filter passes, 0 (off) .. PIC_MAX_FILTER */
     pic_species species[PIC_MAX_SPECIES];
 } pic_config;
@@ -128,6 +137,7 @@ typedef struct pic_particles {   /* device pointers, n entries each */
 
 typedef struct pic_buffers {
     float *fields;       /* device, 9 * nx * ny floats (layout above) */
+    /* particle arrays: device, species[s].cap entries each (n of them valid) */
     void *work;          /* device, pic_sizes.work_bytes, 256-byte aligned */
     size_t work_bytes;
     pic_particles sp[PIC_MAX_SPECIES];
@@ -186,6 +196,26 @@ int pic_sort(pic_sim *sim, hipStream_t stream);
  * directly: update_gc_copy).
  */
 int pic_field_advance(pic_sim *sim, hipStream_t stream);
+
+/*
+ * Move the window one cell towards +x (the moving-window step at the end of
+ * Listing 3.1; requires PIC_FLAG_MOVING_WINDOW): E and B move one cell towards
+ * -x and the last column becomes zero; every particle moves one cell towards
+ * -x (ix - 1, offsets kept); the particles that were in column 0 leave; the
+ * n_inject[s] new particles of species s (device arrays inject[s], all in
+ * column nx - 1 and grouped by tile, e.g. fresh plasma drawn by the caller)
+ * come in.  The particles are re-sorted by tile canonically, as pic_sort does,
+ * with the new particles taken as appended after the existing ones.  The
+ * particle counts change (pic_get_counts); the call synchronises `stream`.
+ * Returns PIC_EINVAL if a count would exceed its species' capacity and
+ * PIC_EORDER if a new particle is outside column nx - 1 or the new particles
+ * are not grouped by tile.
+ */
+int pic_move_window(pic_sim *sim, const pic_particles *inject, const int64_t *n_inject, hipStream_t stream);
+
+/* Current particle count of every species (n_species values; host record, no
+ * device access). */
+int pic_get_counts(pic_sim *sim, int64_t *counts);
 
 /* pic_push_deposit + pic_sort + pic_field_advance. */
 int pic_step(pic_sim *sim, hipStream_t stream);

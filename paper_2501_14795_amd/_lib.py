@@ -25,6 +25,7 @@ PIC_EOVERFLOW = -9
 
 PIC_FLAG_J_FLOAT = 1
 PIC_FLAG_ESIRKEPOV = 2
+PIC_FLAG_MOVING_WINDOW = 4
 
 PIC_DIAG_ENERGY = 1
 PIC_DIAG_RHO_SNAPSHOT = 2
@@ -37,7 +38,8 @@ PIC_MAX_FILTER = 16
 
 # every symbol the header declares
 EXPORTS = [
-    "pic_query", "pic_init", "pic_push_deposit", "pic_sort", "pic_field_advance", "pic_step",
+    "pic_query", "pic_init", "pic_push_deposit", "pic_sort", "pic_field_advance", "pic_move_window",
+    "pic_get_counts", "pic_step",
     "pic_check", "pic_diag", "pic_get_state", "pic_set_state", "pic_get_tile_offsets",
     "pic_set_timing", "pic_get_timing",
     "pic_batch_query", "pic_batch_init", "pic_batch_step", "pic_batch_capture", "pic_batch_sim",
@@ -47,7 +49,7 @@ EXPORTS = [
 
 
 class pic_species(ctypes.Structure):
-    _fields_ = [("qm", ctypes.c_double), ("q", ctypes.c_double), ("n", ctypes.c_int64)]
+    _fields_ = [("qm", ctypes.c_double), ("q", ctypes.c_double), ("n", ctypes.c_int64), ("cap", ctypes.c_int64)]
 
 
 class pic_config(ctypes.Structure):
@@ -120,6 +122,8 @@ def load(path: str = SO_PATH):
     L.pic_diag.argtypes = [vp, ctypes.c_uint, P(pic_diag_out), vp]
     L.pic_get_tile_offsets.argtypes = [vp, ctypes.c_int, vp, vp]
     L.pic_get_state.argtypes = [vp, P(pic_host_state), vp]
+    L.pic_move_window.argtypes = [vp, P(pic_particles), P(ctypes.c_int64), vp]
+    L.pic_get_counts.argtypes = [vp, P(ctypes.c_int64)]
     L.pic_set_state.argtypes = [vp, P(pic_host_state), vp]
     L.pic_set_timing.argtypes = [vp, ctypes.c_int]
     L.pic_get_timing.argtypes = [vp, P(pic_timing_out)]
@@ -194,6 +198,19 @@ def pic_diag(sim: int, what: int, stream: int) -> pic_diag_out:
     _chk(load().pic_diag(ctypes.c_void_p(sim), ctypes.c_uint(what), ctypes.byref(out), ctypes.c_void_p(stream)),
          "pic_diag")
     return out
+
+
+def pic_move_window(sim: int, inject, n_inject, stream: int):
+    """inject: sequence of pic_particles (device pointers), n_inject: counts."""
+    arr = (pic_particles * MAX_SPECIES)(*inject)
+    cnt = (ctypes.c_int64 * MAX_SPECIES)(*n_inject)
+    _chk(load().pic_move_window(ctypes.c_void_p(sim), arr, cnt, ctypes.c_void_p(stream)), "pic_move_window")
+
+
+def pic_get_counts(sim: int, n_species: int):
+    out = (ctypes.c_int64 * MAX_SPECIES)()
+    _chk(load().pic_get_counts(ctypes.c_void_p(sim), out), "pic_get_counts")
+    return [int(out[k]) for k in range(n_species)]
 
 
 def pic_get_state(sim: int, state: pic_host_state, stream: int):

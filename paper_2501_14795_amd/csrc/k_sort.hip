@@ -78,7 +78,8 @@ __device__ __forceinline__ void sort_count_unit(const SortArgs &a, int spi, int 
     const SortSpecies &sp = a.sp[spi];
     const int n_tiles = a.n_tiles;
     const int t = blk * kScanBlock + threadIdx.x;
-    const int c = t < n_tiles ? tile_count_in(sp.cnt, t, a.ntx, a.nty) : 0;
+    int c = t < n_tiles ? tile_count_in(sp.cnt, t, a.ntx, a.nty) : 0;
+    if (t < n_tiles && sp.inj_off) c += sp.inj_off[t + 1] - sp.inj_off[t];   // the window's new particles
     // block exclusive scan (kScanBlock = 256: four wavefronts)
     __shared__ int s_w[kScanBlock / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -115,7 +116,8 @@ __device__ __forceinline__ void sort_scan_unit(const SortArgs &a, int spi)
     }
     if (threadIdx.x == 0) {
         sp.offn[n_tiles] = carry;
-        if (carry != sp.n) atomicOr(a.err, kErrCount);
+        const int expect = sp.removed ? sp.n - *sp.removed + sp.inj_n : sp.n;
+        if (carry != expect) atomicOr(a.err, kErrCount);
     }
 }
 
@@ -193,7 +195,8 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
     const int W = push_waves(a.tile);   // leaver sub-lists per tile
     const int A = sp.offn[t], B = sp.offn[t + 1];
     const int oA = sp.off[t], oB = sp.off[t + 1];
-    auto tile_of = [&](int cell) { return ((cell >> 16) >> tsh) * ntx + ((cell & 0xffff) >> tsh); };
+    // a negative cell marks a particle that left the moving window: no tile
+    auto tile_of = [&](int cell) { return cell < 0 ? -1 : ((cell >> 16) >> tsh) * ntx + ((cell & 0xffff) >> tsh); };
     bool bad = false;
 
     // ---------------- holes, ascending
@@ -304,9 +307,9 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
                         const uint32_t e = sp.leav[at];
                         const int d = (int)(e & 15u), loc = (int)(e >> 4);
                         const int s0 = sp.off[sL], ns = sp.off[sL + 1] - s0;
-                        if (loc >= ns || d > 8) {
+                        if (loc >= ns || d > kDirRemoved) {
                             bad = true;
-                        } else {
+                        } else if (d != kDirRemoved) {   // a removed particle is nobody's mover
                             const int sx = sL % ntx, sy = sL / ntx;
                             const int dest = wrap_s(sy + d / 3 - 1, nty) * ntx + wrap_s(sx + d % 3 - 1, ntx);
                             const int slot = s0 + loc;
@@ -342,6 +345,20 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
             int kind, base, len;
             source_list(src, w, kind, base, len);
             stream_lists(kind, base, len, src, pr < nuniq);
+        }
+        if (sp.inj_off) {
+            // the window's new particles for t, appended after every old
+            // section: the parts of their slot range outside [A, B)
+            const int i0 = sp.n + sp.inj_off[t], i1 = sp.n + sp.inj_off[t + 1];
+            int base = 0, len = 0;
+            if (lane == 0) {
+                base = i0;
+                len = max(0, min(i1, A) - i0);
+            } else if (lane == 1) {
+                base = max(i0, B);
+                len = max(0, i1 - base);
+            }
+            stream_lists(0, base, len, t, lane < 2);
         }
     }
 

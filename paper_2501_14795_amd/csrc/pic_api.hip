@@ -20,6 +20,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t err = 0, dacc = 0, cacc = 0, jtile = 0, rho_prev = 0, rho_now = 0, jf = 0, rho_tmp = 0;
+    size_t ftmp = 0, wrem = 0, inj_off[kMaxSpecies] = {};
     size_t off[kMaxSpecies][2] = {}, cnt[kMaxSpecies] = {}, leav[kMaxSpecies] = {};
     size_t hole[kMaxSpecies] = {}, stg[kMaxSpecies][6] = {}, mcount[kMaxSpecies] = {}, bsum[kMaxSpecies] = {};
     size_t lpart[kMaxSpecies][6] = {};
@@ -38,7 +39,7 @@ int default_replicas(const pic_config *c)
 int validate(const pic_config *c)
 {
     if (!c) return PIC_EINVAL;
-    if (c->flags & ~(uint32_t)(PIC_FLAG_J_FLOAT | PIC_FLAG_ESIRKEPOV)) return PIC_EINVAL;
+    if (c->flags & ~(uint32_t)(PIC_FLAG_J_FLOAT | PIC_FLAG_ESIRKEPOV | PIC_FLAG_MOVING_WINDOW)) return PIC_EINVAL;
     // the Esirkepov deposit is built for the fixed-point current only
     if ((c->flags & PIC_FLAG_ESIRKEPOV) && (c->flags & PIC_FLAG_J_FLOAT)) return PIC_EINVAL;
     if (c->tile != 8 && c->tile != 16 && c->tile != 32) return PIC_ETILE;
@@ -58,6 +59,7 @@ int validate(const pic_config *c)
     for (int s = 0; s < c->n_species; ++s) {
         const pic_species &sp = c->species[s];
         if (sp.n < 0 || sp.n >= (int64_t)1 << 31) return PIC_EINVAL;
+        if (sp.cap != 0 && (sp.cap < sp.n || sp.cap >= (int64_t)1 << 31)) return PIC_EINVAL;
         if (!isfinite(sp.qm) || !isfinite(sp.q)) return PIC_EINVAL;
     }
     return PIC_OK;
@@ -85,8 +87,14 @@ Layout make_layout(const pic_config *c)
         L.jf = take(nodes * 3 * sizeof(float));      // filter ping-pong partner of the J planes
         L.rho_tmp = take(nodes * sizeof(double));    // the same for the diagnostic density
     }
+    if (c->flags & PIC_FLAG_MOVING_WINDOW) {
+        L.ftmp = take(nodes * 6 * sizeof(float));    // E and B shifted by one cell
+        L.wrem = take(kMaxSpecies * sizeof(int32_t));
+        for (int s = 0; s < c->n_species; ++s) L.inj_off[s] = take((n_tiles + 1) * sizeof(int32_t));
+    }
     for (int s = 0; s < c->n_species; ++s) {
-        const size_t n = (size_t)c->species[s].n;
+        // per-particle scratch sized for the capacity (the window changes n)
+        const size_t n = (size_t)(c->species[s].cap ? c->species[s].cap : c->species[s].n);
         L.off[s][0] = take((n_tiles + 1) * sizeof(int32_t));
         L.off[s][1] = take((n_tiles + 1) * sizeof(int32_t));
         L.cnt[s] = take((size_t)n_tiles * kCntStride * sizeof(int32_t));
@@ -115,6 +123,9 @@ struct pic_sim {
     double *rho_prev, *rho_now;
     float *jf;          // filter partner of the J planes (j_filter > 0)
     double *rho_tmp;    // filter partner of rho_now (j_filter > 0)
+    float *ftmp;        // moving window: shifted E and B
+    int32_t *wrem;      // moving window: particles that left, per species
+    int64_t cap[kMaxSpecies];
     bool have_snapshot;
     struct Sp {
         int32_t *off;    // current tile_offset
@@ -126,6 +137,7 @@ struct pic_sim {
         Parts lp;
         int32_t *mcount;
         int32_t *bsum;
+        int32_t *inj_off;   // moving window: tile offsets of the new particles
     } sp[kMaxSpecies];
     // timing
     bool timing;
@@ -319,6 +331,9 @@ SortArgs sort_args(const pic_sim *S)
         d.mcount = P.mcount;
         d.bsum = P.bsum;
         d.n = (int32_t)c.species[s].n;
+        d.inj_off = nullptr;
+        d.inj_n = 0;
+        d.removed = nullptr;
     }
     return a;
 }
@@ -428,6 +443,9 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
     S->rho_now = (double *)(w + L.rho_now);
     S->jf = cfg->j_filter > 0 ? (float *)(w + L.jf) : nullptr;
     S->rho_tmp = cfg->j_filter > 0 ? (double *)(w + L.rho_tmp) : nullptr;
+    const bool window = (cfg->flags & PIC_FLAG_MOVING_WINDOW) != 0;
+    S->ftmp = window ? (float *)(w + L.ftmp) : nullptr;
+    S->wrem = window ? (int32_t *)(w + L.wrem) : nullptr;
     for (int s = 0; s < cfg->n_species; ++s) {
         auto &P = S->sp[s];
         P.off = (int32_t *)(w + L.off[s][0]);
@@ -449,6 +467,8 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
         P.lp = parts_at(L.lpart[s]);
         P.mcount = (int32_t *)(w + L.mcount[s]);
         P.bsum = (int32_t *)(w + L.bsum[s]);
+        P.inj_off = window ? (int32_t *)(w + L.inj_off[s]) : nullptr;
+        S->cap[s] = cfg->species[s].cap ? cfg->species[s].cap : cfg->species[s].n;
     }
 
     rc = hip_ok(hipMemsetAsync(S->err, 0, 64, stream));
@@ -505,6 +525,91 @@ int pic_field_advance(pic_sim *S, hipStream_t stream)
     Timed t(S, PIC_KERNEL_FIELD, stream);
     launch_field_advance(field_args(S), stream);
     return hip_ok(hipGetLastError());
+}
+
+int pic_move_window(pic_sim *S, const pic_particles *inject, const int64_t *n_inject, hipStream_t stream)
+{
+    if (!S || !(S->cfg.flags & PIC_FLAG_MOVING_WINDOW)) return PIC_EINVAL;
+    pic_config &c = S->cfg;
+    int64_t k[kMaxSpecies] = {};
+    for (int s = 0; s < c.n_species; ++s) {
+        k[s] = n_inject ? n_inject[s] : 0;
+        if (k[s] < 0 || c.species[s].n + k[s] > S->cap[s]) return PIC_EINVAL;
+        if (k[s] > 0) {
+            if (!inject) return PIC_EINVAL;
+            const pic_particles &q = inject[s];
+            if (!q.cell || !q.x || !q.y || !q.ux || !q.uy || !q.uz) return PIC_EINVAL;
+        }
+    }
+    const int64_t plane = (int64_t)c.nx * c.ny;
+    SortArgs a = sort_args(S);
+    int rc = PIC_OK;
+    // 1. the new particles into the unused slots after the existing ones, and
+    //    checked (column nx - 1, grouped by tile) before anything changes
+    for (int s = 0; s < c.n_species && rc == PIC_OK; ++s) {
+        if (k[s] == 0) continue;
+        const pic_particles &p = S->buf.sp[s];
+        auto &P = S->sp[s];
+        const size_t n0 = (size_t)c.species[s].n, bytes = (size_t)k[s] * 4;
+        const pic_particles &q = inject[s];
+        void *const dst[6] = {p.cell + n0, p.x + n0, p.y + n0, p.ux + n0, p.uy + n0, p.uz + n0};
+        const void *const src[6] = {q.cell, q.x, q.y, q.ux, q.uy, q.uz};
+        for (int f = 0; f < 6 && rc == PIC_OK; ++f)
+            rc = hip_ok(hipMemcpyAsync(dst[f], src[f], bytes, hipMemcpyDeviceToDevice, stream));
+        if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(P.mcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
+        if (rc) break;
+        launch_check_column(p.cell + n0, (int)k[s], c.nx, S->err, stream);
+        launch_init_tiles(p.cell + n0, (int32_t)k[s], c.nx, c.ny, c.tile, S->ntx, P.mcount, S->n_tiles, P.inj_off,
+                          S->err, stream);
+        a.sp[s].inj_off = P.inj_off;
+        a.sp[s].inj_n = (int32_t)k[s];
+    }
+    if (rc == PIC_OK) rc = hip_ok(hipGetLastError());
+    if (rc == PIC_OK) rc = read_errors(S, stream);
+    if (rc) return rc;
+    // 2. the fields, one cell towards -x
+    launch_shift_fields(S->buf.fields, S->ftmp, c.nx, c.ny, stream);
+    rc = hip_ok(hipMemcpyAsync(S->buf.fields, S->ftmp, 6 * plane * sizeof(float), hipMemcpyDeviceToDevice, stream));
+    if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(S->wrem, 0, kMaxSpecies * sizeof(int32_t), stream));
+    // 3. the particles, one cell towards -x: leaver lists and counts for the sort
+    for (int s = 0; s < c.n_species && rc == PIC_OK; ++s) {
+        auto &P = S->sp[s];
+        WindowSpecies ws;
+        ws.p = a.sp[s].p;
+        ws.lp = P.lp;
+        ws.off = P.off;
+        ws.cnt = P.cnt;
+        ws.leav = P.leav;
+        ws.removed = S->wrem + s;
+        launch_window_shift(S->tile, ws, c.nx, S->ntx, S->n_tiles, S->err, stream);
+        a.sp[s].removed = S->wrem + s;
+    }
+    if (rc == PIC_OK) rc = hip_ok(hipGetLastError());
+    if (rc) return rc;
+    // 4. the canonical re-sort, the new particles taken as appended
+    launch_sort_scan(a, S->n_tiles, stream);
+    launch_sort_plan(a, S->n_tiles, stream);
+    launch_sort_scatter(a, S->n_tiles, stream);
+    rc = hip_ok(hipGetLastError());
+    // the new counts
+    int32_t nn[kMaxSpecies] = {};
+    for (int s = 0; s < c.n_species && rc == PIC_OK; ++s)
+        rc = hip_ok(hipMemcpyAsync(&nn[s], S->sp[s].off + S->n_tiles, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                   stream));
+    if (rc == PIC_OK) rc = hip_ok(hipStreamSynchronize(stream));
+    if (rc) return rc;
+    rc = read_errors(S, stream);
+    if (rc) return rc;
+    for (int s = 0; s < c.n_species; ++s) c.species[s].n = nn[s];
+    S->have_snapshot = false;
+    return PIC_OK;
+}
+
+int pic_get_counts(pic_sim *S, int64_t *counts)
+{
+    if (!S || !counts) return PIC_EINVAL;
+    for (int s = 0; s < S->cfg.n_species; ++s) counts[s] = S->cfg.species[s].n;
+    return PIC_OK;
 }
 
 int pic_step(pic_sim *S, hipStream_t stream)
@@ -758,6 +863,7 @@ int batch_validate(int n, const pic_config *cfgs)
         if (cfgs[i].tile != cfgs[0].tile || cfgs[i].flags != cfgs[0].flags ||
             cfgs[i].j_replicas != cfgs[0].j_replicas || cfgs[i].j_filter != cfgs[0].j_filter)
             return PIC_EINVAL;
+        if (cfgs[i].flags & PIC_FLAG_MOVING_WINDOW) return PIC_EINVAL;   // member counts are fixed
     }
     return PIC_OK;
 }

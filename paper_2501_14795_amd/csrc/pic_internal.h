@@ -28,6 +28,8 @@ constexpr int kMaxWaves = 16;
 //   [10..10+W-1]  leavers found by wavefront w (length of leaver sub-list w)
 constexpr int kCntLeavers = 9;
 constexpr int kCntSub = 10;
+// leaver-entry direction of a particle that left the moving window (no tile)
+constexpr int kDirRemoved = 9;
 static_assert(kCntSub + kMaxWaves <= kCntStride, "count record too short");
 
 // Device error bits (ORed into Sim::err).
@@ -127,7 +129,13 @@ struct SortSpecies {
     int32_t *hole;        // [n]: tile t's holes, ascending, at offn[t] + k
     int32_t *mcount;      // [n_tiles]
     int32_t *bsum;        // [n_tiles / kScanBlock + 1] block totals of the tile scan
-    int32_t n;
+    int32_t n;            // particles before the sort
+    // moving window (else null / 0): new particles appended at slots
+    // [n, n + inj_n), grouped by tile (tile t's at n + inj_off[t] ..), and a
+    // device count of the particles that left
+    const int32_t *inj_off;
+    int32_t inj_n;
+    const int32_t *removed;
 };
 
 struct SortArgs {
@@ -182,6 +190,20 @@ struct SortBatch {
 void launch_sort_batch(const SortBatch &b, hipStream_t s);
 void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile, int ntx,
                        int32_t *counts, int n_tiles, int32_t *off, int *err, hipStream_t s);
+// moving window: E and B one cell towards -x into tmp (6 planes), last column zero
+void launch_shift_fields(const float *fld, float *tmp, int nx, int ny, hipStream_t s);
+// moving window: every particle of every tile one cell towards -x; leaver
+// sub-lists, copies and count records in the push kernel's format
+struct WindowSpecies {
+    Parts p;
+    Parts lp;
+    const int32_t *off;
+    int32_t *cnt;
+    uint32_t *leav;
+    int32_t *removed;   // device count of the particles that left
+};
+void launch_window_shift(int tile, const WindowSpecies &w, int nx, int ntx, int n_tiles, int *err, hipStream_t s);
+void launch_check_column(const int32_t *cell, int n, int nx, int *err, hipStream_t s);
 void launch_filter(const FilterArgs &a, bool fp64, hipStream_t s);
 void launch_filter_batch(const FilterArgs *descs, const int4 *items, int n_items, hipStream_t s);
 void launch_field_advance(const FieldArgs &f, hipStream_t s);

@@ -36,7 +36,7 @@ class _Buffers:
     the pic_config / pic_buffers structures that describe them."""
 
     def __init__(self, nx, ny, dx, dy, dt, tile, species, E=None, B=None, j_replicas=0, j_float=False,
-                 device="cuda:0", j_filter=0, esirkepov=False):
+                 device="cuda:0", j_filter=0, esirkepov=False, moving_window=False, capacity=None):
         torch = _torch()
         if not 1 <= len(species) <= _lib.MAX_SPECIES:
             raise ValueError("1..4 species")
@@ -46,12 +46,14 @@ class _Buffers:
         cfg.tile = self.tile
         cfg.j_replicas = int(j_replicas)
         cfg.n_species = len(species)
-        cfg.flags = (_lib.PIC_FLAG_J_FLOAT if j_float else 0) | (_lib.PIC_FLAG_ESIRKEPOV if esirkepov else 0)
+        cfg.flags = ((_lib.PIC_FLAG_J_FLOAT if j_float else 0) | (_lib.PIC_FLAG_ESIRKEPOV if esirkepov else 0) |
+                     (_lib.PIC_FLAG_MOVING_WINDOW if moving_window else 0))
         cfg.j_filter = int(j_filter)
         for k, (qm, q, st) in enumerate(species):
             cfg.species[k].qm = float(qm)
             cfg.species[k].q = float(q)
             cfg.species[k].n = int(np.asarray(st["ix"]).size)
+            cfg.species[k].cap = int(capacity[k]) if capacity is not None else 0
         self.cfg = cfg
         sizes = _lib.pic_query(cfg)
         self.n_tiles = sizes.n_tiles
@@ -68,9 +70,15 @@ class _Buffers:
         bufs.work_bytes = sizes.work_bytes
         self.particles: List[Dict[str, "torch.Tensor"]] = []
         for k, (qm, q, st) in enumerate(species):
-            p = {"cell": torch.from_numpy(pack_cells(st["ix"], st["iy"])).to(dev)}
-            for name in PARTICLE_FIELDS[1:]:
-                p[name] = torch.from_numpy(np.ascontiguousarray(st[name], np.float32)).to(dev)
+            n = int(cfg.species[k].n)
+            cap = max(n, int(cfg.species[k].cap))
+            p = {}
+            for name in PARTICLE_FIELDS:
+                a = pack_cells(st["ix"], st["iy"]) if name == "cell" else np.ascontiguousarray(st[name], np.float32)
+                t = torch.zeros(cap, dtype=torch.int32 if name == "cell" else torch.float32, device=dev)
+                if n:
+                    t[:n] = torch.from_numpy(a).to(dev)
+                p[name] = t
             self.particles.append(p)
             for name in PARTICLE_FIELDS:
                 setattr(bufs.sp[k], name, p[name].data_ptr() if p[name].numel() else None)
@@ -136,10 +144,37 @@ class _SimView:
         t = _lib.pic_get_timing(self.handle)
         return {name: (t.ms_total[k], t.launches[k]) for k, name in enumerate(_lib.KERNELS)}
 
+    def counts(self):
+        """Current particle count of every species (the moving window changes them)."""
+        return _lib.pic_get_counts(self.handle, self.buf.cfg.n_species)
+
+    def move_window(self, inject: Sequence[Dict[str, np.ndarray]]):
+        """One moving-window step (pic_move_window); inject[k]: the new
+        particles of species k (ix, iy, x, y, ux, uy, uz arrays, all in column
+        nx - 1, grouped by tile)."""
+        torch = _torch()
+        dev = self.fields.device
+        keep, arr, cnt = [], [], []
+        for k in range(self.buf.cfg.n_species):
+            st = inject[k]
+            pp = _lib.pic_particles()
+            n = int(np.asarray(st["ix"]).size)
+            if n:
+                for name in PARTICLE_FIELDS:
+                    a = pack_cells(st["ix"], st["iy"]) if name == "cell" else np.ascontiguousarray(st[name], np.float32)
+                    t = torch.from_numpy(a).to(dev)
+                    keep.append(t)
+                    setattr(pp, name, t.data_ptr())
+            arr.append(pp)
+            cnt.append(n)
+        torch.cuda.synchronize(dev)
+        _lib.pic_move_window(self.handle, arr, cnt, self.s)
+
     def state(self, species: int = 0) -> Dict[str, np.ndarray]:
         self.stream.synchronize()
         p = self.particles[species]
-        out = {name: p[name].cpu().numpy() for name in PARTICLE_FIELDS}
+        n = self.counts()[species]
+        out = {name: p[name][:n].cpu().numpy() for name in PARTICLE_FIELDS}
         out["ix"], out["iy"] = unpack_cells(out["cell"])
         return out
 
@@ -150,8 +185,9 @@ class _SimView:
         hs = _lib.pic_host_state()
         out = {"fields": np.empty((9, self.ny, self.nx), np.float32), "species": []}
         hs.fields = out["fields"].ctypes.data
+        counts = self.counts()
         for k in range(cfg.n_species):
-            n = int(cfg.species[k].n)
+            n = counts[k]
             arrs = {name: np.empty(n, np.int32 if name == "cell" else np.float32) for name in PARTICLE_FIELDS}
             for name in PARTICLE_FIELDS:
                 setattr(hs.sp[k], name, arrs[name].ctypes.data if n else None)
@@ -167,12 +203,13 @@ class _SimView:
         if keep[0].shape != (9, self.ny, self.nx):
             raise ValueError("fields must be (9, ny, nx)")
         hs.fields = keep[0].ctypes.data
+        counts = self.counts()
         for k in range(cfg.n_species):
             sp = state["species"][k]
             for name in PARTICLE_FIELDS:
                 a = np.ascontiguousarray(sp[name], np.int32 if name == "cell" else np.float32)
-                if a.size != int(cfg.species[k].n):
-                    raise ValueError(f"species {k}: {name} has {a.size} entries, the config {cfg.species[k].n}")
+                if a.size != counts[k]:
+                    raise ValueError(f"species {k}: {name} has {a.size} entries, the simulation {counts[k]}")
                 keep.append(a)
                 setattr(hs.sp[k], name, a.ctypes.data if a.size else None)
         self.stream.synchronize()
@@ -193,12 +230,12 @@ class Sim(_SimView):
     def __init__(self, nx: int, ny: int, dx: float, dy: float, dt: float, tile: int,
                  species: Sequence, E: Optional[np.ndarray] = None, B: Optional[np.ndarray] = None,
                  j_replicas: int = 0, j_float: bool = False, device: str = "cuda:0", stream=None,
-                 j_filter: int = 0, esirkepov: bool = False):
+                 j_filter: int = 0, esirkepov: bool = False, moving_window: bool = False, capacity=None):
         torch = _torch()
         self.handle = None
         self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
         self.buf = _Buffers(nx, ny, dx, dy, dt, tile, species, E, B, j_replicas, j_float, device, j_filter,
-                            esirkepov)
+                            esirkepov, moving_window, capacity)
         self.cfg = self.buf.cfg
         torch.cuda.synchronize(torch.device(device))
         self.handle = _lib.pic_init(self.cfg, self.buf.bufs, self.s)

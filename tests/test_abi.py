@@ -91,7 +91,7 @@ def test_query_sizes_and_validation():
         (dict(ns=0), L.PIC_EINVAL),
         (dict(ns=5), L.PIC_EINVAL),
         (dict(reps=3), L.PIC_EINVAL),
-        (dict(flags=4), L.PIC_EINVAL),
+        (dict(flags=8), L.PIC_EINVAL),
         (dict(flags=3), L.PIC_EINVAL),          # Esirkepov needs the fixed-point current
         (dict(nx=64, tile=32, reps=4), L.PIC_EINVAL),   # int64 current x 4 replicas > LDS
         (dict(n=-1), L.PIC_EINVAL),
@@ -112,6 +112,16 @@ def test_query_sizes_and_validation():
     with pytest.raises(L.PicError):   # 16 wavefronts per 32 x 32 tile leave no room for 4 FP32 replicas
         L.pic_query(_cfg(L, nx=64, tile=32, reps=4, flags=L.PIC_FLAG_J_FLOAT))
     assert L.pic_query(_cfg(L, flags=L.PIC_FLAG_ESIRKEPOV)).work_bytes == s.work_bytes
+    # capacity: per-particle scratch sized for it; below n is invalid
+    c = _cfg(L)
+    c.species[0].cap = 2000
+    assert L.pic_query(c).work_bytes == s2.work_bytes
+    c.species[0].cap = 999
+    with pytest.raises(L.PicError):
+        L.pic_query(c)
+    # the moving window adds the shifted-field planes and the new particles' tile offsets
+    sw = L.pic_query(_cfg(L, flags=L.PIC_FLAG_MOVING_WINDOW))
+    assert 24 * 64 * 64 <= sw.work_bytes - s.work_bytes <= 24 * 64 * 64 + 4 * 256
     # the filter's ping-pong planes: three FP32 current planes + one FP64 density plane
     sf = L.pic_query(_cfg(L, filt=L.PIC_MAX_FILTER))
     assert 20 * 64 * 64 <= sf.work_bytes - s.work_bytes <= 20 * 64 * 64 + 2 * 256
@@ -136,7 +146,8 @@ def test_batch_query_validation():
     assert nb > 0
     for bad in ([_cfg(L), _cfg(L, tile=8)], [_cfg(L), _cfg(L, flags=L.PIC_FLAG_J_FLOAT)],
                 [_cfg(L), _cfg(L, reps=2)], [_cfg(L), _cfg(L, filt=1)],
-                [_cfg(L), _cfg(L, flags=L.PIC_FLAG_ESIRKEPOV)]):
+                [_cfg(L), _cfg(L, flags=L.PIC_FLAG_ESIRKEPOV)],
+                [_cfg(L, flags=L.PIC_FLAG_MOVING_WINDOW)]):
         with pytest.raises(L.PicError) as e:
             L.pic_batch_query(bad)
         assert e.value.code == L.PIC_EINVAL
