@@ -194,6 +194,51 @@ def esirkepov_measurement(w, T, steps=20, warmup=3):
             "ms_per_step": elapsed * 1e3 / steps, "push_kernel_ms": push_ms}
 
 
+def window_measurement(w, T, moves=20, warmup=3, n_columns=4):
+    """The moving-window step on the same workload: after each full step the
+    window moves one cell (pic_move_window) and a new column of plasma of the
+    workload's species, ppc and temperature comes in (pre-drawn, resident in
+    HBM, cycled over n_columns draws).  pic_move_window synchronises, so the
+    window call is wall-timed on its own; the steps between are not counted."""
+    import torch
+
+    import pic_workloads as pw
+    from paper_2501_14795_amd import Sim, _lib
+    states = pw.workload_state(w, tile=T)
+    n = [st["ix"].size for st in states]
+    col_n = [int(np.ceil(k / w.nx)) * 2 for k in n]
+    sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, T, [(s.qm, s.q, st) for s, st in zip(w.species, states)],
+              moving_window=True, capacity=[k + c for k, c in zip(n, col_n)])
+    del states
+    cols = []
+    for c in range(n_columns):
+        per = []
+        for k, spec in enumerate(w.species):
+            st = pw.species_state(T, w.ny, T, spec, w.seed + 1000 + c, k, cell_box=(T - 1, T, 0, w.ny))
+            st["ix"] = st["ix"] + (w.nx - T)
+            per.append(sim.upload_particles(st))
+        cols.append(per)
+    times = []
+    for i in range(warmup + moves):
+        sim.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.move_window(cols[i % n_columns])
+        if i >= warmup:
+            times.append(time.perf_counter() - t0)
+    counts = sim.counts()
+    d = sim.diag(_lib.PIC_DIAG_COUNTS)   # of the last move
+    removed, movers = list(d.leavers)[:len(w.species)], list(d.movers)[:len(w.species)]
+    rc = sim.check()
+    sim.close()
+    if rc != 0:
+        raise SystemExit("device error in the moving-window measurement")
+    ms = 1e3 * sum(times) / len(times)
+    return {"workload": w.name, "moves": moves, "window_ms": ms, "window_ms_min": 1e3 * min(times),
+            "new_per_move": [int(t["cell"].numel()) for t in cols[0]],
+            "last_move": {"removed": removed, "moved_by_sort": movers}, "particles_after": counts}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,6 +381,8 @@ def main():
         if not args.esirkepov:
             out["esirkepov"] = esirkepov_measurement(w, T)
             log(f"esirkepov: {out['esirkepov']}")
+        out["moving_window"] = window_measurement(w, T)
+        log(f"moving window: {out['moving_window']}")
     if not args.no_batched:
         out["batched"] = batched_comparison()
         log(f"batched: {out['batched']}")

@@ -199,19 +199,31 @@ int pic_field_advance(pic_sim *sim, hipStream_t stream);
 
 /*
  * Move the window one cell towards +x (the moving-window step at the end of
- * Listing 3.1; requires PIC_FLAG_MOVING_WINDOW): E and B move one cell towards
- * -x and the last column becomes zero; every particle moves one cell towards
- * -x (ix - 1, offsets kept); the particles that were in column 0 leave; the
- * n_inject[s] new particles of species s (device arrays inject[s], all in
- * column nx - 1 and grouped by tile, e.g. fresh plasma drawn by the caller)
- * come in.  The particles are re-sorted by tile canonically, as pic_sort does,
- * with the new particles taken as appended after the existing ones.  The
+ * Listing 3.1; requires PIC_FLAG_MOVING_WINDOW).  In window coordinates: E and
+ * B move one cell towards -x and the last column becomes zero; every particle
+ * moves one cell towards -x (offsets kept); the particles that were in window
+ * column 0 leave; the n_inject[s] new particles of species s (device arrays
+ * inject[s], cells given in window column nx - 1 and grouped by tile, e.g.
+ * fresh plasma drawn by the caller) come in.
+ * In the arrays: the grid is periodic between moves, so the shift is kept as
+ * a relabelling -- window column i is array column (i + origin) mod nx, and
+ * the move advances origin (pic_get_window_origin) by one.  Only the array
+ * column that held window column 0 changes: its E and B become zero, its
+ * particles leave and the new particles are placed in it.  The particles are
+ * then re-sorted by tile canonically, as pic_sort does, the leaving ones
+ * removed and the new ones taken as appended after the existing ones.  The
  * particle counts change (pic_get_counts); the call synchronises `stream`.
- * Returns PIC_EINVAL if a count would exceed its species' capacity and
- * PIC_EORDER if a new particle is outside column nx - 1 or the new particles
- * are not grouped by tile.
+ * Returns PIC_EINVAL if a count would exceed its species' capacity, and
+ * PIC_EORDER if a new particle is outside window column nx - 1 or the new
+ * particles are not grouped by tile (nothing has changed then).
  */
 int pic_move_window(pic_sim *sim, const pic_particles *inject, const int64_t *n_inject, hipStream_t stream);
+
+/* Array column that holds window column 0 (0 until the first pic_move_window
+ * and always 0 without PIC_FLAG_MOVING_WINDOW; host record, no device access).
+ * The field planes, the particles' cells and tile_offset are in array
+ * columns; diagnostics do not depend on the origin. */
+int pic_get_window_origin(pic_sim *sim, int32_t *origin);
 
 /* Current particle count of every species (n_species values; host record, no
  * device access). */
@@ -264,19 +276,27 @@ int pic_diag(pic_sim *sim, unsigned what, pic_diag_out *out, hipStream_t stream)
  */
 typedef struct pic_host_state {
     float *fields;                      /* host, 9 * nx * ny floats (layout above) */
-    pic_particles sp[PIC_MAX_SPECIES];  /* host arrays, species[s].n entries each */
+    pic_particles sp[PIC_MAX_SPECIES];  /* host arrays, n[s] entries each */
+    int64_t n[PIC_MAX_SPECIES];         /* particle counts (pic_get_counts) */
+    int32_t window_origin;              /* see pic_get_window_origin */
 } pic_host_state;
 
-/* Copy the field planes and the particles of every species to the caller's
- * host arrays (a NULL array is skipped) and synchronise `stream`. */
-int pic_get_state(pic_sim *sim, const pic_host_state *out, hipStream_t stream);
+/* Copy the field planes and the particles of every species (array columns)
+ * to the caller's host arrays (a NULL array is skipped; the arrays hold the
+ * current counts, pic_get_counts), set out->n and out->window_origin and
+ * synchronise `stream`. */
+int pic_get_state(pic_sim *sim, pic_host_state *out, hipStream_t stream);
 
 /*
- * Load the field planes and the particles (the counts of the config, grouped
- * by tile as for pic_init) from host arrays, rebuild tile_offset, forget the
- * rho snapshot of pic_diag and synchronise `stream`.  Every array must be
- * given.  Returns PIC_EORDER if the particles are not grouped by tile (the
- * simulation then needs a valid state before its next step).
+ * Load the field planes, the particles (in->n[s] of species s, grouped by
+ * tile as for pic_init; array columns) and the window origin from host
+ * arrays, rebuild tile_offset, forget the rho snapshot of pic_diag and
+ * synchronise `stream`.  Every array must be given.  With
+ * PIC_FLAG_MOVING_WINDOW a count may be anything up to the species' capacity
+ * and 0 <= origin < nx; without it the counts must be the current ones and
+ * the origin 0 (else PIC_EINVAL, nothing loaded).  Returns PIC_EORDER if the
+ * particles are not grouped by tile (the simulation then needs a valid state
+ * before its next step).
  */
 int pic_set_state(pic_sim *sim, const pic_host_state *in, hipStream_t stream);
 

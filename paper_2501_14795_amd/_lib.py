@@ -39,7 +39,7 @@ PIC_MAX_FILTER = 16
 # every symbol the header declares
 EXPORTS = [
     "pic_query", "pic_init", "pic_push_deposit", "pic_sort", "pic_field_advance", "pic_move_window",
-    "pic_get_counts", "pic_step",
+    "pic_get_window_origin", "pic_get_counts", "pic_step",
     "pic_check", "pic_diag", "pic_get_state", "pic_set_state", "pic_get_tile_offsets",
     "pic_set_timing", "pic_get_timing",
     "pic_batch_query", "pic_batch_init", "pic_batch_step", "pic_batch_capture", "pic_batch_sim",
@@ -83,7 +83,8 @@ class pic_diag_out(ctypes.Structure):
 
 
 class pic_host_state(ctypes.Structure):
-    _fields_ = [("fields", ctypes.c_void_p), ("sp", pic_particles * MAX_SPECIES)]
+    _fields_ = [("fields", ctypes.c_void_p), ("sp", pic_particles * MAX_SPECIES),
+                ("n", ctypes.c_int64 * MAX_SPECIES), ("window_origin", ctypes.c_int32)]
 
 
 class pic_timing_out(ctypes.Structure):
@@ -124,6 +125,7 @@ def load(path: str = SO_PATH):
     L.pic_get_state.argtypes = [vp, P(pic_host_state), vp]
     L.pic_move_window.argtypes = [vp, P(pic_particles), P(ctypes.c_int64), vp]
     L.pic_get_counts.argtypes = [vp, P(ctypes.c_int64)]
+    L.pic_get_window_origin.argtypes = [vp, P(ctypes.c_int32)]
     L.pic_set_state.argtypes = [vp, P(pic_host_state), vp]
     L.pic_set_timing.argtypes = [vp, ctypes.c_int]
     L.pic_get_timing.argtypes = [vp, P(pic_timing_out)]
@@ -205,6 +207,12 @@ def pic_move_window(sim: int, inject, n_inject, stream: int):
     arr = (pic_particles * MAX_SPECIES)(*inject)
     cnt = (ctypes.c_int64 * MAX_SPECIES)(*n_inject)
     _chk(load().pic_move_window(ctypes.c_void_p(sim), arr, cnt, ctypes.c_void_p(stream)), "pic_move_window")
+
+
+def pic_get_window_origin(sim: int) -> int:
+    out = ctypes.c_int32()
+    _chk(load().pic_get_window_origin(ctypes.c_void_p(sim), ctypes.byref(out)), "pic_get_window_origin")
+    return int(out.value)
 
 
 def pic_get_counts(sim: int, n_species: int):

@@ -20,7 +20,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
     size_t err = 0, dacc = 0, cacc = 0, jtile = 0, rho_prev = 0, rho_now = 0, jf = 0, rho_tmp = 0;
-    size_t ftmp = 0, wrem = 0, inj_off[kMaxSpecies] = {};
+    size_t wrem = 0, inj_off[kMaxSpecies] = {};
     size_t off[kMaxSpecies][2] = {}, cnt[kMaxSpecies] = {}, leav[kMaxSpecies] = {};
     size_t hole[kMaxSpecies] = {}, stg[kMaxSpecies][6] = {}, mcount[kMaxSpecies] = {}, bsum[kMaxSpecies] = {};
     size_t lpart[kMaxSpecies][6] = {};
@@ -88,7 +88,6 @@ Layout make_layout(const pic_config *c)
         L.rho_tmp = take(nodes * sizeof(double));    // the same for the diagnostic density
     }
     if (c->flags & PIC_FLAG_MOVING_WINDOW) {
-        L.ftmp = take(nodes * 6 * sizeof(float));    // E and B shifted by one cell
         L.wrem = take(kMaxSpecies * sizeof(int32_t));
         for (int s = 0; s < c->n_species; ++s) L.inj_off[s] = take((n_tiles + 1) * sizeof(int32_t));
     }
@@ -123,7 +122,7 @@ struct pic_sim {
     double *rho_prev, *rho_now;
     float *jf;          // filter partner of the J planes (j_filter > 0)
     double *rho_tmp;    // filter partner of rho_now (j_filter > 0)
-    float *ftmp;        // moving window: shifted E and B
+    int32_t origin;     // moving window: array column of window column 0
     int32_t *wrem;      // moving window: particles that left, per species
     int64_t cap[kMaxSpecies];
     bool have_snapshot;
@@ -444,8 +443,8 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
     S->jf = cfg->j_filter > 0 ? (float *)(w + L.jf) : nullptr;
     S->rho_tmp = cfg->j_filter > 0 ? (double *)(w + L.rho_tmp) : nullptr;
     const bool window = (cfg->flags & PIC_FLAG_MOVING_WINDOW) != 0;
-    S->ftmp = window ? (float *)(w + L.ftmp) : nullptr;
     S->wrem = window ? (int32_t *)(w + L.wrem) : nullptr;
+    S->origin = 0;
     for (int s = 0; s < cfg->n_species; ++s) {
         auto &P = S->sp[s];
         P.off = (int32_t *)(w + L.off[s][0]);
@@ -541,24 +540,26 @@ int pic_move_window(pic_sim *S, const pic_particles *inject, const int64_t *n_in
             if (!q.cell || !q.x || !q.y || !q.ux || !q.uy || !q.uz) return PIC_EINVAL;
         }
     }
-    const int64_t plane = (int64_t)c.nx * c.ny;
+    // array column of window column 0 now, and of window column nx - 1 after the move
+    const int col = S->origin;
     SortArgs a = sort_args(S);
     int rc = PIC_OK;
-    // 1. the new particles into the unused slots after the existing ones, and
-    //    checked (column nx - 1, grouped by tile) before anything changes
+    // 1. the new particles into the unused slots after the existing ones, their
+    //    cells moved to array column col, and checked (window column nx - 1,
+    //    grouped by tile) before anything changes
     for (int s = 0; s < c.n_species && rc == PIC_OK; ++s) {
         if (k[s] == 0) continue;
         const pic_particles &p = S->buf.sp[s];
         auto &P = S->sp[s];
         const size_t n0 = (size_t)c.species[s].n, bytes = (size_t)k[s] * 4;
         const pic_particles &q = inject[s];
-        void *const dst[6] = {p.cell + n0, p.x + n0, p.y + n0, p.ux + n0, p.uy + n0, p.uz + n0};
-        const void *const src[6] = {q.cell, q.x, q.y, q.ux, q.uy, q.uz};
-        for (int f = 0; f < 6 && rc == PIC_OK; ++f)
+        void *const dst[5] = {p.x + n0, p.y + n0, p.ux + n0, p.uy + n0, p.uz + n0};
+        const void *const src[5] = {q.x, q.y, q.ux, q.uy, q.uz};
+        for (int f = 0; f < 5 && rc == PIC_OK; ++f)
             rc = hip_ok(hipMemcpyAsync(dst[f], src[f], bytes, hipMemcpyDeviceToDevice, stream));
-        if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(P.mcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
         if (rc) break;
-        launch_check_column(p.cell + n0, (int)k[s], c.nx, S->err, stream);
+        launch_zero_i32(P.mcount, S->n_tiles, stream);
+        launch_place_new(q.cell, p.cell + n0, (int)k[s], c.nx, c.ny, col, S->err, stream);
         launch_init_tiles(p.cell + n0, (int32_t)k[s], c.nx, c.ny, c.tile, S->ntx, P.mcount, S->n_tiles, P.inj_off,
                           S->err, stream);
         a.sp[s].inj_off = P.inj_off;
@@ -567,21 +568,19 @@ int pic_move_window(pic_sim *S, const pic_particles *inject, const int64_t *n_in
     if (rc == PIC_OK) rc = hip_ok(hipGetLastError());
     if (rc == PIC_OK) rc = read_errors(S, stream);
     if (rc) return rc;
-    // 2. the fields, one cell towards -x
-    launch_shift_fields(S->buf.fields, S->ftmp, c.nx, c.ny, stream);
-    rc = hip_ok(hipMemcpyAsync(S->buf.fields, S->ftmp, 6 * plane * sizeof(float), hipMemcpyDeviceToDevice, stream));
-    if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(S->wrem, 0, kMaxSpecies * sizeof(int32_t), stream));
-    // 3. the particles, one cell towards -x: leaver lists and counts for the sort
+    // 2. E and B of the column that becomes window column nx - 1
+    launch_zero_column(S->buf.fields, c.nx, c.ny, col, stream);
+    launch_zero_i32(S->wrem, kMaxSpecies, stream);
+    // 3. its particles leave: leaver lists and count records for the sort
     for (int s = 0; s < c.n_species && rc == PIC_OK; ++s) {
         auto &P = S->sp[s];
         WindowSpecies ws;
         ws.p = a.sp[s].p;
-        ws.lp = P.lp;
         ws.off = P.off;
         ws.cnt = P.cnt;
         ws.leav = P.leav;
         ws.removed = S->wrem + s;
-        launch_window_shift(S->tile, ws, c.nx, S->ntx, S->n_tiles, S->err, stream);
+        launch_window_remove(S->tile, ws, S->ntx, S->nty, S->n_tiles, col, stream);
         a.sp[s].removed = S->wrem + s;
     }
     if (rc == PIC_OK) rc = hip_ok(hipGetLastError());
@@ -601,7 +600,15 @@ int pic_move_window(pic_sim *S, const pic_particles *inject, const int64_t *n_in
     rc = read_errors(S, stream);
     if (rc) return rc;
     for (int s = 0; s < c.n_species; ++s) c.species[s].n = nn[s];
+    S->origin = col + 1 == c.nx ? 0 : col + 1;
     S->have_snapshot = false;
+    return PIC_OK;
+}
+
+int pic_get_window_origin(pic_sim *S, int32_t *origin)
+{
+    if (!S || !origin) return PIC_EINVAL;
+    *origin = S->origin;
     return PIC_OK;
 }
 
@@ -734,7 +741,7 @@ int copy_particles(pic_sim *S, int s, const pic_particles &host, bool to_host, h
 
 }  // namespace
 
-int pic_get_state(pic_sim *S, const pic_host_state *out, hipStream_t stream)
+int pic_get_state(pic_sim *S, pic_host_state *out, hipStream_t stream)
 {
     if (!S || !out) return PIC_EINVAL;
     const size_t fbytes = 9 * sizeof(float) * (size_t)S->cfg.nx * S->cfg.ny;
@@ -742,21 +749,32 @@ int pic_get_state(pic_sim *S, const pic_host_state *out, hipStream_t stream)
     if (out->fields) rc = hip_ok(hipMemcpyAsync(out->fields, S->buf.fields, fbytes, hipMemcpyDeviceToHost, stream));
     for (int s = 0; s < S->cfg.n_species && rc == PIC_OK; ++s) rc = copy_particles(S, s, out->sp[s], true, stream);
     if (rc == PIC_OK) rc = hip_ok(hipStreamSynchronize(stream));
+    if (rc == PIC_OK) {
+        out->window_origin = S->origin;
+        for (int s = 0; s < PIC_MAX_SPECIES; ++s) out->n[s] = s < S->cfg.n_species ? S->cfg.species[s].n : 0;
+    }
     return rc;
 }
 
 int pic_set_state(pic_sim *S, const pic_host_state *in, hipStream_t stream)
 {
     if (!S || !in || !in->fields) return PIC_EINVAL;
+    const bool window = (S->cfg.flags & PIC_FLAG_MOVING_WINDOW) != 0;
+    if (in->window_origin < 0 || in->window_origin >= S->cfg.nx || (!window && in->window_origin != 0))
+        return PIC_EINVAL;
     for (int s = 0; s < S->cfg.n_species; ++s) {
         const pic_particles &p = in->sp[s];
-        if (S->cfg.species[s].n > 0 && (!p.cell || !p.x || !p.y || !p.ux || !p.uy || !p.uz)) return PIC_EINVAL;
+        const int64_t n = in->n[s];
+        if (n < 0 || n > S->cap[s] || (!window && n != S->cfg.species[s].n)) return PIC_EINVAL;
+        if (n > 0 && (!p.cell || !p.x || !p.y || !p.ux || !p.uy || !p.uz)) return PIC_EINVAL;
     }
+    for (int s = 0; s < S->cfg.n_species; ++s) S->cfg.species[s].n = in->n[s];
     const size_t fbytes = 9 * sizeof(float) * (size_t)S->cfg.nx * S->cfg.ny;
     int rc = hip_ok(hipMemcpyAsync(S->buf.fields, in->fields, fbytes, hipMemcpyHostToDevice, stream));
     for (int s = 0; s < S->cfg.n_species && rc == PIC_OK; ++s) rc = copy_particles(S, s, in->sp[s], false, stream);
     S->have_snapshot = false;
     if (rc == PIC_OK) rc = build_tiles(S, stream);
+    if (rc == PIC_OK) S->origin = in->window_origin;
     return rc;
 }
 

@@ -190,20 +190,24 @@ struct SortBatch {
 void launch_sort_batch(const SortBatch &b, hipStream_t s);
 void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile, int ntx,
                        int32_t *counts, int n_tiles, int32_t *off, int *err, hipStream_t s);
-// moving window: E and B one cell towards -x into tmp (6 planes), last column zero
-void launch_shift_fields(const float *fld, float *tmp, int nx, int ny, hipStream_t s);
-// moving window: every particle of every tile one cell towards -x; leaver
-// sub-lists, copies and count records in the push kernel's format
+// moving window (window column i lives in array column (i + origin) mod nx):
+// E and B of array column col become zero
+void launch_zero_column(float *fld, int nx, int ny, int col, hipStream_t s);
+// p[0 .. n) = 0 (a kernel, not a memset node)
+void launch_zero_i32(int32_t *p, int n, hipStream_t s);
+// the particles of array column col leave; leaver sub-lists and count records
+// of every tile in the push kernel's format (no leaver copies: a removed
+// particle is nobody's mover)
 struct WindowSpecies {
     Parts p;
-    Parts lp;
     const int32_t *off;
     int32_t *cnt;
     uint32_t *leav;
     int32_t *removed;   // device count of the particles that left
 };
-void launch_window_shift(int tile, const WindowSpecies &w, int nx, int ntx, int n_tiles, int *err, hipStream_t s);
-void launch_check_column(const int32_t *cell, int n, int nx, int *err, hipStream_t s);
+void launch_window_remove(int tile, const WindowSpecies &w, int ntx, int nty, int n_tiles, int col, hipStream_t s);
+// new particles given in window column nx - 1 into array column col (checked)
+void launch_place_new(const int32_t *src, int32_t *dst, int n, int nx, int ny, int col, int *err, hipStream_t s);
 void launch_filter(const FilterArgs &a, bool fp64, hipStream_t s);
 void launch_filter_batch(const FilterArgs *descs, const int4 *items, int n_items, hipStream_t s);
 void launch_field_advance(const FieldArgs &f, hipStream_t s);

@@ -148,26 +148,43 @@ class _SimView:
         """Current particle count of every species (the moving window changes them)."""
         return _lib.pic_get_counts(self.handle, self.buf.cfg.n_species)
 
-    def move_window(self, inject: Sequence[Dict[str, np.ndarray]]):
-        """One moving-window step (pic_move_window); inject[k]: the new
-        particles of species k (ix, iy, x, y, ux, uy, uz arrays, all in column
-        nx - 1, grouped by tile)."""
+    def upload_particles(self, st: Dict[str, np.ndarray]) -> Dict[str, object]:
+        """Device copies (cell, x, y, ux, uy, uz) of host particle arrays
+        (ix, iy, x, y, ux, uy, uz), e.g. to keep new particles resident for
+        move_window."""
         torch = _torch()
         dev = self.fields.device
+        out = {}
+        for name in PARTICLE_FIELDS:
+            a = pack_cells(st["ix"], st["iy"]) if name == "cell" else np.ascontiguousarray(st[name], np.float32)
+            out[name] = torch.from_numpy(a).to(dev)
+        return out
+
+    def move_window(self, inject: Sequence[Dict[str, object]]):
+        """One moving-window step (pic_move_window); inject[k]: the new
+        particles of species k, all in column nx - 1 and grouped by tile --
+        host arrays (ix, iy, x, y, ux, uy, uz) or device tensors from
+        upload_particles (cell, x, y, ux, uy, uz)."""
+        torch = _torch()
         keep, arr, cnt = [], [], []
         for k in range(self.buf.cfg.n_species):
             st = inject[k]
+            if "cell" not in st:
+                st = self.upload_particles(st)
+            keep.append(st)
             pp = _lib.pic_particles()
-            n = int(np.asarray(st["ix"]).size)
+            n = int(st["cell"].numel())
             if n:
                 for name in PARTICLE_FIELDS:
-                    a = pack_cells(st["ix"], st["iy"]) if name == "cell" else np.ascontiguousarray(st[name], np.float32)
-                    t = torch.from_numpy(a).to(dev)
-                    keep.append(t)
+                    t = st[name]
+                    want = torch.int32 if name == "cell" else torch.float32
+                    if t.device != self.fields.device or t.dtype != want or not t.is_contiguous() or t.numel() != n:
+                        raise ValueError(f"inject[{k}][{name!r}]: expected {n} contiguous {want} values on "
+                                         f"{self.fields.device}")
                     setattr(pp, name, t.data_ptr())
             arr.append(pp)
             cnt.append(n)
-        torch.cuda.synchronize(dev)
+        torch.cuda.synchronize(self.fields.device)
         _lib.pic_move_window(self.handle, arr, cnt, self.s)
 
     def state(self, species: int = 0) -> Dict[str, np.ndarray]:
@@ -180,7 +197,8 @@ class _SimView:
 
     def get_state(self) -> Dict[str, object]:
         """Host copy of the step-to-step state through pic_get_state:
-        {"fields": (9, ny, nx) float32, "species": [{cell, x, y, ux, uy, uz}]}."""
+        {"fields": (9, ny, nx) float32, "species": [{cell, x, y, ux, uy, uz}],
+        "window_origin": int}, in array columns."""
         cfg = self.buf.cfg
         hs = _lib.pic_host_state()
         out = {"fields": np.empty((9, self.ny, self.nx), np.float32), "species": []}
@@ -193,27 +211,49 @@ class _SimView:
                 setattr(hs.sp[k], name, arrs[name].ctypes.data if n else None)
             out["species"].append(arrs)
         _lib.pic_get_state(self.handle, hs, self.s)
+        out["window_origin"] = int(hs.window_origin)
         return out
 
     def set_state(self, state: Dict[str, object]):
-        """Load a state of the form get_state() returns (pic_set_state)."""
+        """Load a state of the form get_state() returns (pic_set_state); the
+        counts are the arrays' lengths."""
         cfg = self.buf.cfg
         hs = _lib.pic_host_state()
         keep = [np.ascontiguousarray(state["fields"], np.float32)]
         if keep[0].shape != (9, self.ny, self.nx):
             raise ValueError("fields must be (9, ny, nx)")
         hs.fields = keep[0].ctypes.data
-        counts = self.counts()
         for k in range(cfg.n_species):
             sp = state["species"][k]
+            n = int(np.asarray(sp["cell"]).size)
+            hs.n[k] = n
             for name in PARTICLE_FIELDS:
                 a = np.ascontiguousarray(sp[name], np.int32 if name == "cell" else np.float32)
-                if a.size != counts[k]:
-                    raise ValueError(f"species {k}: {name} has {a.size} entries, the simulation {counts[k]}")
+                if a.size != n:
+                    raise ValueError(f"species {k}: {name} has {a.size} entries, cell {n}")
                 keep.append(a)
                 setattr(hs.sp[k], name, a.ctypes.data if a.size else None)
+        hs.window_origin = int(state.get("window_origin", 0))
         self.stream.synchronize()
         _lib.pic_set_state(self.handle, hs, self.s)
+
+    def window_origin(self) -> int:
+        """Array column of window column 0 (pic_get_window_origin)."""
+        return _lib.pic_get_window_origin(self.handle)
+
+    def window_fields(self) -> Dict[str, np.ndarray]:
+        """field_arrays() in window columns: window column i is array column
+        (i + origin) mod nx."""
+        o = self.window_origin()
+        return {k: np.roll(v, -o, axis=-1) for k, v in self.field_arrays().items()}
+
+    def window_state(self, species: int = 0) -> Dict[str, np.ndarray]:
+        """state() with ix in window columns (array order kept)."""
+        o = self.window_origin()
+        st = self.state(species)
+        st["ix"] = ((st["ix"] - o) % self.nx).astype(np.int32)
+        st["cell"] = pack_cells(st["ix"], st["iy"])
+        return st
 
     def field_arrays(self) -> Dict[str, np.ndarray]:
         self.stream.synchronize()
