@@ -37,7 +37,9 @@
  *     Particles must be grouped by tile: tiles are tile x tile cells numbered
  *     row-major (t = (iy / tile) * (nx / tile) + ix / tile) and the particles
  *     of tile t occupy one contiguous section, sections in increasing t.
- *     pic_sort() restores this order after every push.
+ *     pic_sort() restores this order after every push (with sort_every = k
+ *     > 1, after every k-th push: in between, a particle may be up to k - 1
+ *     cells outside the tile whose section holds it).
  *
  * Errors: every int-returning call returns PIC_OK (0) or a negative PIC_E*
  * code; pic_strerror() names it.  Kernels that detect a bad state set a
@@ -127,6 +129,12 @@ typedef struct pic_config {
     int32_t n_species;   /* 1 .. PIC_MAX_SPECIES */
     uint32_t flags;      /* PIC_FLAG_J_FLOAT, PIC_FLAG_ESIRKEPOV, PIC_FLAG_MOVING_WINDOW or 0 */
     int32_t j_filter;    /* binomial current filter passes, 0 (off) .. PIC_MAX_FILTER */
+    int32_t sort_every;  /* sort cadence k = 1, 2 or 4 (0: 1): pic_step sorts every
+                            k-th step and the push stages a halo k cells wide.  k > 1
+                            needs the fixed-point current with j_replicas <= 1, no
+                            moving window, and 2k + 1 <= tile within the LDS budget
+                            (tile 8: k <= 2; 16: k <= 4; 32: k <= 2), else PIC_EINVAL /
+                            PIC_ETILE */
     pic_species species[PIC_MAX_SPECIES];
 } pic_config;
 
@@ -176,8 +184,11 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
  * motion into LDS (Eqs. 13-16), then write J (all species) into the J planes,
  * folding the periodic images (update_gc_add), and apply the binomial filter
  * if pic_config.j_filter > 0.  Also records, per tile, the
- * particles that left it, as input for pic_sort().  A particle that would move
- * one cell or more sets PIC_ERANGE (reported by pic_check()).
+ * particles that are now outside it, as input for pic_sort().  A particle that
+ * would move one cell or more sets PIC_ERANGE (reported by pic_check()).
+ * Returns PIC_EORDER without launching anything once sort_every pushes have
+ * run since the last pic_sort() (the particles could have left the staged
+ * halo).
  */
 int pic_push_deposit(pic_sim *sim, hipStream_t stream);
 
@@ -186,7 +197,9 @@ int pic_push_deposit(pic_sim *sim, hipStream_t stream);
  * tiles, rebuild tile_offset, and move every particle whose slot lies outside
  * its tile's new section into a hole.  The result is the canonical one: holes
  * in ascending slot order receive the movers ordered by destination tile,
- * then by old slot.  Particles already in their section do not move.
+ * then by old slot.  Particles already in their section do not move.  Uses
+ * the record of the last push, so it may run after any push; with no push
+ * since the last sort it does nothing.
  */
 int pic_sort(pic_sim *sim, hipStream_t stream);
 
@@ -229,7 +242,7 @@ int pic_get_window_origin(pic_sim *sim, int32_t *origin);
  * device access). */
 int pic_get_counts(pic_sim *sim, int64_t *counts);
 
-/* pic_push_deposit + pic_sort + pic_field_advance. */
+/* pic_push_deposit + pic_sort (every sort_every-th step) + pic_field_advance. */
 int pic_step(pic_sim *sim, hipStream_t stream);
 
 /* Synchronise `stream` and report (and clear) the device error flags. */
@@ -284,7 +297,9 @@ typedef struct pic_host_state {
 /* Copy the field planes and the particles of every species (array columns)
  * to the caller's host arrays (a NULL array is skipped; the arrays hold the
  * current counts, pic_get_counts), set out->n and out->window_origin and
- * synchronise `stream`. */
+ * synchronise `stream`.  With sort_every > 1, call pic_sort() first if the
+ * state is to be loaded again: pic_set_state() needs particles grouped by
+ * tile. */
 int pic_get_state(pic_sim *sim, pic_host_state *out, hipStream_t stream);
 
 /*
@@ -331,7 +346,8 @@ int pic_get_timing(pic_sim *sim, pic_timing_out *out);
  * count) share every kernel launch: one launch per phase of the step for the
  * whole batch, the push as a persistent grid that takes (simulation, tile)
  * work items largest-simulation-first, and optionally one captured HIP graph
- * per step.  All members must share tile, j_replicas, flags and j_filter.
+ * per step.  All members must share tile, j_replicas, flags, j_filter and
+ * sort_every.
  * Results are bit-identical to advancing each member alone with pic_step.
  */
 typedef struct pic_batch pic_batch;
@@ -344,18 +360,20 @@ int pic_batch_query(int n, const pic_config *cfgs, size_t *bytes);
  * own caller-owned fields, workspace and particles).  batch_work: device
  * memory of pic_batch_query() bytes, 256-byte aligned, caller-owned.
  * Synchronises `stream`.  Errors as pic_init, or PIC_EINVAL if the members do
- * not share tile / j_replicas / flags / j_filter.
+ * not share tile / j_replicas / flags / j_filter / sort_every.
  */
 int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void *batch_work,
                    size_t batch_bytes, hipStream_t stream, pic_batch **out);
 
-/* nsteps full steps of every member (push + deposit, sort, field advance):
- * replays of the captured graph if pic_batch_capture() was called, else
- * direct launches. */
+/* nsteps full steps of every member (push + deposit, sort every sort_every-th
+ * step, field advance): replays of the captured cycle of sort_every steps if
+ * pic_batch_capture() was called and a whole cycle remains, else direct
+ * launches. */
 int pic_batch_step(pic_batch *b, int nsteps, hipStream_t stream);
 
-/* Capture one batched step into a HIP graph on `stream` (a non-null stream);
- * later pic_batch_step() calls on any stream replay it.  Nothing runs here. */
+/* Capture one batched cadence cycle (sort_every steps, the last with the
+ * sort) into a HIP graph on `stream` (a non-null stream); later
+ * pic_batch_step() calls on any stream replay it.  Nothing runs here. */
 int pic_batch_capture(pic_batch *b, hipStream_t stream);
 
 /* Member i as a pic_sim for pic_diag / pic_get_tile_offsets / pic_check and

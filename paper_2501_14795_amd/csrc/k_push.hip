@@ -3,9 +3,11 @@
 //
 // Per tile (Sec. 4.2.2 maps one tile to one work-group; redesigned here for
 // gfx950 wave64 + LDS):
-//   1. stage the tile's E/B halo (cells -1..T on each axis) in LDS, packed so
-//      that the two x-neighbours every bilinear stencil needs come in one
-//      ds_read_b64/b128;
+//   1. stage the tile's E/B halo (cells -H..T+H-1 on each axis; H = 1 when
+//      particles are sorted every step, H = k when every k steps, as a
+//      particle then strays up to k - 1 cells outside its tile) in LDS,
+//      packed so that the two x-neighbours every bilinear stencil needs come
+//      in one ds_read_b64/b128;
 //   2. the 64-aligned particle chunks covering the tile's section are split
 //      into contiguous runs, one per wavefront (4 wavefronts per tile up to
 //      16 x 16 tiles, 16 for 32 x 32 tiles); every chunk is one
@@ -30,9 +32,11 @@
 //   4. particles whose tile changed are appended, in slot order, to the
 //      wavefront's leaver sub-list (ballot + mbcnt), and counted per
 //      direction -- the input of the strict sort (Sec. 4.3, step 1);
-//   5. the tile's (T+3)^2 current halo is converted to physical units and
+//   5. the tile's (T+2H+1)^2 current halo is converted to physical units and
 //      written out; k_j_reduce then adds the up-to-four overlapping tile halos
 //      of every node in a fixed order with compensation (no global atomics).
+#include <type_traits>
+
 #include "pic_internal.h"
 
 namespace pic {
@@ -122,11 +126,12 @@ struct JAcc<kJFloat> {
     }
 };
 
-// LDS index of tile-relative cell (cx, cy) in the (T+3)^2 current halo.
-template <int NJ>
+// LDS index of tile-relative node (cx, cy) in the (T+2H+1)^2 current halo
+// (nodes -H..T+H per axis).
+template <int NJ, int H>
 __device__ __forceinline__ int jcell(int cx, int cy)
 {
-    return __mul24(cy + 1, NJ) + (cx + 1);   // 24-bit multiply: full rate
+    return __mul24(cy + H, NJ) + (cx + H);   // 24-bit multiply: full rate
 }
 
 // Current of one piece of the motion inside the cell at halo index b, from
@@ -276,18 +281,19 @@ __device__ __forceinline__ void flush_leavers(const SpeciesDev &sp, uint32_t (*l
 }
 
 // One tile of one simulation, by the whole workgroup (push_waves(T) wavefronts).
-template <int T, int R, int JM, int DM>
+template <int T, int R, int JM, int DM, int H>
 __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
 {
-    constexpr int NE = T + 2;   // staged E/B cells per axis: relative -1..T
-    constexpr int NJ = T + 3;   // current halo nodes per axis: relative -1..T+1
+    static_assert(cadence_ok(T, H), "halo pad not supported for this tile");
+    constexpr int NE = T + 2 * H;       // staged E/B cells per axis: relative -H..T+H-1
+    constexpr int NJ = T + 2 * H + 1;   // current halo nodes per axis: relative -H..T+H
     constexpr int JP = NJ * NJ;
     constexpr int W = push_waves(T);   // wavefronts of the workgroup
     constexpr int NT = 64 * W;         // its threads
     using Acc = typename JAcc<JM>::T;
 
-    // packed E/B: entry [r][c] holds the values at relative cells c-1 and c
-    // (x-neighbours) of row r-1
+    // packed E/B: entry [r][c] holds the values at relative cells c-H and
+    // c-H+1 (x-neighbours) of row r-H
     __shared__ float4 s_exby[NE * NE];   // Ex(c-1), By(c-1), Ex(c), By(c)
     __shared__ float4 s_eybx[NE * NE];   // Ey, Bx likewise
     __shared__ float2 s_ez[NE * NE];
@@ -308,9 +314,9 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
 
     for (int e = tid; e < NE * NE; e += NT) {
         const int r = e / NE, c = e - r * NE;
-        const int64_t row = (int64_t)wrapi(gy0 - 1 + r, a.ny) * a.nx;
-        const int64_t i0 = row + wrapi(gx0 - 1 + c, a.nx);
-        const int64_t i1 = row + wrapi(gx0 + c, a.nx);
+        const int64_t row = (int64_t)wrapi(gy0 - H + r, a.ny) * a.nx;
+        const int64_t i0 = row + wrapi(gx0 - H + c, a.nx);
+        const int64_t i1 = row + wrapi(gx0 - H + 1 + c, a.nx);
         const float *f = a.fld;
         s_exby[e] = make_float4(f[i0], f[4 * plane + i0], f[i1], f[4 * plane + i1]);
         s_eybx[e] = make_float4(f[plane + i0], f[3 * plane + i0], f[plane + i1], f[3 * plane + i1]);
@@ -377,19 +383,31 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                 float xa2 = 0.0f, ya2 = 0.0f, xb2 = 0.0f, yb2 = 0.0f, az2 = 0.0f;
                 if (i >= lo && i < hi) {
                     int lx = (cell & 0xffff) - gx0, ly = (cell >> 16) - gy0;
-                    if ((unsigned)lx >= (unsigned)T || (unsigned)ly >= (unsigned)T) {
+                    if constexpr (H > 1) {
+                        // since the last sort the particle may have left the
+                        // tile by up to H - 1 cells, also across the periodic
+                        // seam (one image lies in that band: 2H - 2 < T)
+                        if (cell < 0 || (cell & 0xffff) >= a.nx || (cell >> 16) >= a.ny) {
+                            lx = T + H;   // not a cell of the grid: flagged below
+                        } else {
+                            if (tx_wrap) lx += lx >= T + H - 1 ? -a.nx : (lx < 1 - H ? a.nx : 0);
+                            if (ty_wrap) ly += ly >= T + H - 1 ? -a.ny : (ly < 1 - H ? a.ny : 0);
+                        }
+                    }
+                    if ((unsigned)(lx + H - 1) >= (unsigned)(T + 2 * H - 2) ||
+                        (unsigned)(ly + H - 1) >= (unsigned)(T + 2 * H - 2)) {
                         atomicOr(a.err, kErrOrder);
-                        lx = min(max(lx, 0), T - 1);
-                        ly = min(max(ly, 0), T - 1);
+                        lx = min(max(lx, 1 - H), T + H - 2);
+                        ly = min(max(ly, 1 - H), T + H - 2);
                     }
 
                     // ---- interpolation (bilinear at each component's staggered point)
                     const bool xh = x >= 0.5f, yh = y >= 0.5f;
                     const float wxh = xh ? x - 0.5f : x + 0.5f;   // weight for (i+1/2) points
                     const float wyh = yh ? y - 0.5f : y + 0.5f;
-                    const int ch = lx + (xh ? 1 : 0);             // packed column of the half stencil
-                    const int rh = ly + (yh ? 1 : 0);
-                    const int c0 = lx + 1, r0 = ly + 1;
+                    const int ch = lx + (H - 1) + (xh ? 1 : 0);   // packed column of the half stencil
+                    const int rh = ly + (H - 1) + (yh ? 1 : 0);
+                    const int c0 = lx + H, r0 = ly + H;
                     const int e0 = __mul24(r0, NE), eh = __mul24(rh, NE);
                     const float4 p0 = s_exby[e0 + ch], p1 = s_exby[e0 + NE + ch];
                     const float4 q0 = s_eybx[eh + c0], q1 = s_eybx[eh + NE + c0];
@@ -453,11 +471,11 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                             // inside the cell both schemes coincide; a crossing
                             // motion is queued whole for the 4 x 4 stencil
                             if (nseg == 1) {
-                                deposit_piece<NJ, JM>(sj, jcell<NJ>(lx, ly), clamp01(x), clamp01(y), clamp01(x1),
+                                deposit_piece<NJ, JM>(sj, jcell<NJ, H>(lx, ly), clamp01(x), clamp01(y), clamp01(x1),
                                                       clamp01(y1), fqvz * (1.0f - 0.0f), fq);
                             } else {
                                 has1 = true;
-                                qb1 = jcell<NJ>(lx, ly);
+                                qb1 = jcell<NJ, H>(lx, ly);
                                 xa1 = x;
                                 ya1 = y;
                                 xb1 = x1;
@@ -469,7 +487,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                         const float e0x = nseg == 1 ? x1 : p1x, e0y = nseg == 1 ? y1 : p1y;
                         const float f0 = nseg == 1 ? 1.0f : t1;
                         if constexpr (DM == kDepVB)
-                            deposit_piece<NJ, JM>(sj, jcell<NJ>(lx, ly), clamp01(x), clamp01(y), clamp01(e0x),
+                            deposit_piece<NJ, JM>(sj, jcell<NJ, H>(lx, ly), clamp01(x), clamp01(y), clamp01(e0x),
                                                   clamp01(e0y), fqvz * (f0 - 0.0f), fq);
                         // piece 1, after the first crossing
                         if (DM == kDepVB && nseg >= 2) {
@@ -477,7 +495,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                             const float e1x = nseg == 2 ? x1 : p2x, e1y = nseg == 2 ? y1 : p2y;
                             const float f1 = nseg == 2 ? 1.0f : t2;
                             has1 = true;
-                            qb1 = jcell<NJ>(lx + ox, ly + oy);
+                            qb1 = jcell<NJ, H>(lx + ox, ly + oy);
                             xa1 = clamp01(p1x - ox);
                             ya1 = clamp01(p1y - oy);
                             xb1 = clamp01(e1x - ox);
@@ -487,7 +505,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                         // piece 2, after both crossings
                         if (DM == kDepVB && nseg == 3) {
                             has2 = true;
-                            qb2 = jcell<NJ>(lx + sxn, ly + syn);
+                            qb2 = jcell<NJ, H>(lx + sxn, ly + syn);
                             xa2 = clamp01(p2x - sxn);
                             ya2 = clamp01(p2y - syn);
                             xb2 = clamp01(x1 - sxn);
@@ -592,16 +610,16 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
     }
 }
 
-template <int T, int R, int JM, int DM>
+template <int T, int R, int JM, int DM, int H>
 __global__ void __launch_bounds__(64 * push_waves(T)) k_push_deposit(PushArgs a)
 {
-    push_tile<T, R, JM, DM>(a, blockIdx.x);
+    push_tile<T, R, JM, DM, H>(a, blockIdx.x);
 }
 
 // Many simulations in one launch: a persistent grid takes (simulation, tile)
 // items from a shared counter (the items come largest simulations first, so
 // the expensive tiles start early and the cheap ones fill the tail).
-template <int T, int R, int JM, int DM>
+template <int T, int R, int JM, int DM, int H>
 __global__ void __launch_bounds__(64 * push_waves(T)) k_push_batch(const PushArgs *__restrict__ descs,
                                                        const int4 *__restrict__ items, int n_items, int *counter)
 {
@@ -613,22 +631,23 @@ __global__ void __launch_bounds__(64 * push_waves(T)) k_push_batch(const PushArg
         __syncthreads();
         if (it >= n_items) break;
         const int4 w = items[it];
-        push_tile<T, R, JM, DM>(descs[w.x], w.y);
+        push_tile<T, R, JM, DM, H>(descs[w.x], w.y);
         __syncthreads();
     }
 }
 
-// J[c][gy][gx] = sum over the tiles whose halo (relative -1..T+1) covers the
-// node, in fixed (ty, tx) order with compensation -- the periodic fold of
-// update_gc_add.  One 64 x 4 block of nodes.  A node at tile-relative
-// (rx, ry) is covered by its own tile and, along x, by the left neighbour
-// when rx <= 1 or the right one when rx >= T-1 (likewise along y): at most
-// 2 x 2 halos, whose values are all loaded before the sums (absent ones as
-// zero, which leaves a compensated sum unchanged).
-template <int T>
+// J[c][gy][gx] = sum over the tiles whose halo (relative nodes -H..T+H)
+// covers the node, in fixed (ty, tx) order with compensation -- the periodic
+// fold of update_gc_add.  One 64 x 4 block of nodes.  A node at
+// tile-relative (rx, ry) is covered by its own tile and, along x, by the left
+// neighbour when rx <= H or the right one when rx >= T-H (never both: 2H + 1
+// <= T), likewise along y: at most 2 x 2 halos, whose values are all loaded
+// before the sums (absent ones as zero, which leaves a compensated sum
+// unchanged).
+template <int T, int H>
 __device__ __forceinline__ void j_reduce_block(const JReduceArgs &r, int bxb, int byb)
 {
-    constexpr int NJ = T + 3;
+    constexpr int NJ = T + 2 * H + 1;
     constexpr int JP = NJ * NJ;
     const float *__restrict__ jtile = r.jtile;
     float *__restrict__ J = r.J;
@@ -639,18 +658,18 @@ __device__ __forceinline__ void j_reduce_block(const JReduceArgs &r, int bxb, in
     const int bx = gx / T, by = gy / T;
     const int rx = gx - bx * T, ry = gy - by * T;
     // the two candidate offsets per axis, ascending: (-1, 0), (0, +1) or (0, none)
-    const int kx0 = rx <= 1 ? -1 : 0, kx1 = rx <= 1 ? 0 : (rx >= T - 1 ? 1 : 0);
-    const bool hx = rx <= 1 || rx >= T - 1;
-    const int ky0 = ry <= 1 ? -1 : 0, ky1 = ry <= 1 ? 0 : (ry >= T - 1 ? 1 : 0);
-    const bool hy = ry <= 1 || ry >= T - 1;
+    const int kx0 = rx <= H ? -1 : 0, kx1 = rx <= H ? 0 : (rx >= T - H ? 1 : 0);
+    const bool hx = rx <= H || rx >= T - H;
+    const int ky0 = ry <= H ? -1 : 0, ky1 = ry <= H ? 0 : (ry >= T - H ? 1 : 0);
+    const bool hy = ry <= H || ry >= T - H;
     float v[4][3];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int ky = (q >> 1) ? ky1 : ky0, kx = (q & 1) ? kx1 : kx0;
         const bool valid = ((q >> 1) == 0 || hy) && ((q & 1) == 0 || hx);
         const int ty = wrapi(by + ky, nty), tx = wrapi(bx + kx, ntx);
-        const int ly = ry - ky * T, lx = rx - kx * T;   // in -1..T+1
-        const float *src = jtile + (int64_t)(ty * ntx + tx) * 3 * JP + (ly + 1) * NJ + (lx + 1);
+        const int ly = ry - ky * T, lx = rx - kx * T;   // in -H..T+H
+        const float *src = jtile + (int64_t)(ty * ntx + tx) * 3 * JP + (ly + H) * NJ + (lx + H);
 #pragma unroll
         for (int c = 0; c < 3; ++c) v[q][c] = valid ? src[c * JP] : 0.0f;
     }
@@ -672,123 +691,146 @@ __device__ __forceinline__ void j_reduce_block(const JReduceArgs &r, int bxb, in
     J[2 * plane + k] = sum[2] + cmp[2];
 }
 
-template <int T>
+template <int T, int H>
 __global__ void __launch_bounds__(256) k_j_reduce(JReduceArgs r)
 {
-    j_reduce_block<T>(r, blockIdx.x, blockIdx.y);
+    j_reduce_block<T, H>(r, blockIdx.x, blockIdx.y);
 }
 
 // node blocks of many simulations: items = (simulation, bx, by)
-template <int T>
+template <int T, int H>
 __global__ void __launch_bounds__(256) k_j_reduce_batch(const JReduceArgs *__restrict__ descs,
                                                         const int4 *__restrict__ items)
 {
     const int4 w = items[blockIdx.x];
-    j_reduce_block<T>(descs[w.x], w.y, w.z);
+    j_reduce_block<T, H>(descs[w.x], w.y, w.z);
 }
 
-template <int T, int R, int JM, int DM>
+template <int T, int R, int JM, int DM, int H>
 static void launch_pd(const PushArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_push_deposit<T, R, JM, DM>), dim3(n_tiles), dim3(64 * push_waves(T)), 0, s, a);
+    hipLaunchKernelGGL((k_push_deposit<T, R, JM, DM, H>), dim3(n_tiles), dim3(64 * push_waves(T)), 0, s, a);
 }
 
-template <int T, int JM, int DM>
-static void launch_pd_r(int replicas, const PushArgs &a, int n_tiles, hipStream_t s)
+template <int T, int R, int JM, int DM, int H>
+static void launch_pb(const PushArgs *descs, const int4 *items, int n_items, int *counter, int grid, hipStream_t s)
 {
+    hipLaunchKernelGGL((k_push_batch<T, R, JM, DM, H>), dim3(grid), dim3(64 * push_waves(T)), 0, s, descs, items,
+                       n_items, counter);
+}
+
+// One push launch, single or batched, with every template parameter chosen.
+// Configurations over the LDS budget or outside cadence_ok are rejected by
+// pic_query / pic_init / pic_batch_init; they launch nothing here.
+struct PushLaunch {
+    const PushArgs *single;   // single simulation (n_tiles workgroups), or null
+    int n_tiles;
+    const PushArgs *descs;    // batched: persistent grid over the items
+    const int4 *items;
+    int n_items;
+    int *counter;
+    int grid;
+    hipStream_t s;
+    template <int T, int R, int JM, int DM, int H>
+    void go() const
+    {
+        if constexpr (push_lds_bytes(T, R, JM, H) <= kLdsBytes && cadence_ok(T, H)) {
+            if (single) launch_pd<T, R, JM, DM, H>(*single, n_tiles, s);
+            else launch_pb<T, R, JM, DM, H>(descs, items, n_items, counter, grid, s);
+        }
+    }
+};
+
+template <int T, int JM, int DM>
+static void push_r(const PushLaunch &L, int replicas, int halo)
+{
+    if (halo > 1) {
+        // sort cadences above 1: fixed-point current, one LDS copy
+        if constexpr (JM == kJFixed) {
+            if (halo == 2) L.go<T, 1, JM, DM, 2>();
+            else L.go<T, 1, JM, DM, 4>();
+        }
+        return;
+    }
     switch (replicas) {
-    case 1: launch_pd<T, 1, JM, DM>(a, n_tiles, s); break;
-    case 2:
-        if constexpr (push_lds_bytes(T, 2, JM) <= kLdsBytes) launch_pd<T, 2, JM, DM>(a, n_tiles, s);
-        break;
-    default:
-        // configurations over the LDS budget are rejected by pic_query/pic_init
-        if constexpr (push_lds_bytes(T, 4, JM) <= kLdsBytes) launch_pd<T, 4, JM, DM>(a, n_tiles, s);
-        break;
+    case 1: L.go<T, 1, JM, DM, 1>(); break;
+    case 2: L.go<T, 2, JM, DM, 1>(); break;
+    default: L.go<T, 4, JM, DM, 1>(); break;
     }
 }
 
 // the Esirkepov deposit is built for the fixed-point current only
 template <int T>
-static void launch_pd_j(int replicas, int jmode, int dmode, const PushArgs &a, int n_tiles, hipStream_t s)
+static void push_j(const PushLaunch &L, int replicas, int jmode, int dmode, int halo)
 {
-    if (jmode == kJFloat) launch_pd_r<T, kJFloat, kDepVB>(replicas, a, n_tiles, s);
-    else if (dmode == kDepEsirkepov) launch_pd_r<T, kJFixed, kDepEsirkepov>(replicas, a, n_tiles, s);
-    else launch_pd_r<T, kJFixed, kDepVB>(replicas, a, n_tiles, s);
+    if (jmode == kJFloat) push_r<T, kJFloat, kDepVB>(L, replicas, halo);
+    else if (dmode == kDepEsirkepov) push_r<T, kJFixed, kDepEsirkepov>(L, replicas, halo);
+    else push_r<T, kJFixed, kDepVB>(L, replicas, halo);
 }
 
-void launch_push_deposit(int tile, int replicas, int jmode, int dmode, const PushArgs &a, int n_tiles,
+static void push_t(const PushLaunch &L, int tile, int replicas, int jmode, int dmode, int halo)
+{
+    switch (tile) {
+    case 8: push_j<8>(L, replicas, jmode, dmode, halo); break;
+    case 16: push_j<16>(L, replicas, jmode, dmode, halo); break;
+    default: push_j<32>(L, replicas, jmode, dmode, halo); break;
+    }
+}
+
+void launch_push_deposit(int tile, int replicas, int jmode, int dmode, int halo, const PushArgs &a, int n_tiles,
                          hipStream_t s)
 {
-    switch (tile) {
-    case 8: launch_pd_j<8>(replicas, jmode, dmode, a, n_tiles, s); break;
-    case 16: launch_pd_j<16>(replicas, jmode, dmode, a, n_tiles, s); break;
-    default: launch_pd_j<32>(replicas, jmode, dmode, a, n_tiles, s); break;
-    }
+    PushLaunch L{&a, n_tiles, nullptr, nullptr, 0, nullptr, 0, s};
+    push_t(L, tile, replicas, jmode, dmode, halo);
 }
 
-void launch_j_reduce(int tile, const JReduceArgs &r, hipStream_t s)
+void launch_push_batch(int tile, int replicas, int jmode, int dmode, int halo, const PushArgs *descs,
+                       const int4 *items, int n_items, int *counter, int grid, hipStream_t s)
 {
-    dim3 grid((r.nx + 63) / 64, (r.ny + 3) / 4);
-    switch (tile) {
-    case 8: hipLaunchKernelGGL((k_j_reduce<8>), grid, dim3(256), 0, s, r); break;
-    case 16: hipLaunchKernelGGL((k_j_reduce<16>), grid, dim3(256), 0, s, r); break;
-    default: hipLaunchKernelGGL((k_j_reduce<32>), grid, dim3(256), 0, s, r); break;
-    }
-}
-
-template <int T, int R, int JM, int DM>
-static void launch_pb(const PushArgs *descs, const int4 *items, int n_items, int *counter, int grid, hipStream_t s)
-{
-    hipLaunchKernelGGL((k_push_batch<T, R, JM, DM>), dim3(grid), dim3(64 * push_waves(T)), 0, s, descs, items,
-                       n_items, counter);
-}
-
-template <int T, int JM, int DM>
-static void launch_pb_r(int replicas, const PushArgs *descs, const int4 *items, int n_items, int *counter,
-                        int grid, hipStream_t s)
-{
-    switch (replicas) {
-    case 1: launch_pb<T, 1, JM, DM>(descs, items, n_items, counter, grid, s); break;
-    case 2:
-        if constexpr (push_lds_bytes(T, 2, JM) <= kLdsBytes)
-            launch_pb<T, 2, JM, DM>(descs, items, n_items, counter, grid, s);
-        break;
-    default:
-        if constexpr (push_lds_bytes(T, 4, JM) <= kLdsBytes)
-            launch_pb<T, 4, JM, DM>(descs, items, n_items, counter, grid, s);
-        break;
-    }
+    PushLaunch L{nullptr, 0, descs, items, n_items, counter, grid, s};
+    push_t(L, tile, replicas, jmode, dmode, halo);
 }
 
 template <int T>
-static void launch_pb_j(int replicas, int jmode, int dmode, const PushArgs *descs, const int4 *items, int n_items,
-                        int *counter, int grid, hipStream_t s)
+static void jr_h(int halo, const JReduceArgs *single, const JReduceArgs *descs, const int4 *items, int n_items,
+                 hipStream_t s)
 {
-    if (jmode == kJFloat) launch_pb_r<T, kJFloat, kDepVB>(replicas, descs, items, n_items, counter, grid, s);
-    else if (dmode == kDepEsirkepov)
-        launch_pb_r<T, kJFixed, kDepEsirkepov>(replicas, descs, items, n_items, counter, grid, s);
-    else launch_pb_r<T, kJFixed, kDepVB>(replicas, descs, items, n_items, counter, grid, s);
+    auto go = [&](auto hc) {
+        constexpr int H = decltype(hc)::value;
+        if constexpr (cadence_ok(T, H)) {
+            if (single) {
+                dim3 grid((single->nx + 63) / 64, (single->ny + 3) / 4);
+                hipLaunchKernelGGL((k_j_reduce<T, H>), grid, dim3(256), 0, s, *single);
+            } else {
+                hipLaunchKernelGGL((k_j_reduce_batch<T, H>), dim3(n_items), dim3(256), 0, s, descs, items);
+            }
+        }
+    };
+    if (halo == 2) go(std::integral_constant<int, 2>());
+    else if (halo == 4) go(std::integral_constant<int, 4>());
+    else go(std::integral_constant<int, 1>());
 }
 
-void launch_push_batch(int tile, int replicas, int jmode, int dmode, const PushArgs *descs, const int4 *items,
-                       int n_items, int *counter, int grid, hipStream_t s)
+static void jr_t(int tile, int halo, const JReduceArgs *single, const JReduceArgs *descs, const int4 *items,
+                 int n_items, hipStream_t s)
 {
     switch (tile) {
-    case 8: launch_pb_j<8>(replicas, jmode, dmode, descs, items, n_items, counter, grid, s); break;
-    case 16: launch_pb_j<16>(replicas, jmode, dmode, descs, items, n_items, counter, grid, s); break;
-    default: launch_pb_j<32>(replicas, jmode, dmode, descs, items, n_items, counter, grid, s); break;
+    case 8: jr_h<8>(halo, single, descs, items, n_items, s); break;
+    case 16: jr_h<16>(halo, single, descs, items, n_items, s); break;
+    default: jr_h<32>(halo, single, descs, items, n_items, s); break;
     }
 }
 
-void launch_j_reduce_batch(int tile, const JReduceArgs *descs, const int4 *items, int n_items, hipStream_t s)
+void launch_j_reduce(int tile, int halo, const JReduceArgs &r, hipStream_t s)
+{
+    jr_t(tile, halo, &r, nullptr, nullptr, 0, s);
+}
+
+void launch_j_reduce_batch(int tile, int halo, const JReduceArgs *descs, const int4 *items, int n_items,
+                           hipStream_t s)
 {
     if (n_items == 0) return;
-    switch (tile) {
-    case 8: hipLaunchKernelGGL((k_j_reduce_batch<8>), dim3(n_items), dim3(256), 0, s, descs, items); break;
-    case 16: hipLaunchKernelGGL((k_j_reduce_batch<16>), dim3(n_items), dim3(256), 0, s, descs, items); break;
-    default: hipLaunchKernelGGL((k_j_reduce_batch<32>), dim3(n_items), dim3(256), 0, s, descs, items); break;
-    }
+    jr_t(tile, halo, nullptr, descs, items, n_items, s);
 }
 
 __global__ void k_set_int(int *p, int v) { *p = v; }

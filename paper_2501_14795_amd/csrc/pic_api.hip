@@ -30,6 +30,8 @@ struct Layout {
 int j_mode(const pic_config *c) { return (c->flags & PIC_FLAG_J_FLOAT) ? kJFloat : kJFixed; }
 int d_mode(const pic_config *c) { return (c->flags & PIC_FLAG_ESIRKEPOV) ? kDepEsirkepov : kDepVB; }
 
+int halo_of(const pic_config *c) { return c->sort_every ? c->sort_every : 1; }
+
 int default_replicas(const pic_config *c)
 {
     if (j_mode(c) == kJFixed) return 1;   // integer LDS atomics need no replicas
@@ -52,6 +54,16 @@ int validate(const pic_config *c)
     {
         const int r = c->j_replicas ? c->j_replicas : default_replicas(c);
         if (push_lds_bytes(c->tile, r, j_mode(c)) > kLdsBytes) return PIC_EINVAL;
+    }
+    {
+        // sort cadence: the push kernel's halo pad is the number of steps between sorts
+        const int k = halo_of(c);
+        if (k != 1 && k != 2 && k != 4) return PIC_EINVAL;
+        if (k > 1) {
+            if (j_mode(c) != kJFixed || c->j_replicas > 1) return PIC_EINVAL;
+            if (c->flags & PIC_FLAG_MOVING_WINDOW) return PIC_EINVAL;
+            if (!cadence_ok(c->tile, k)) return PIC_ETILE;
+        }
     }
     if (!(c->dx > 0) || !(c->dy > 0) || !(c->dt > 0)) return PIC_EINVAL;
     // Courant-Levy condition, Eq. (1), with c = 1
@@ -80,7 +92,8 @@ Layout make_layout(const pic_config *c)
     L.err = take(64);
     L.dacc = take(32 * sizeof(double));
     L.cacc = take(8 * sizeof(unsigned long long));
-    L.jtile = take((size_t)n_tiles * 3 * (T + 3) * (T + 3) * sizeof(float));
+    const int NJ = T + 2 * halo_of(c) + 1;   // current halo nodes per axis
+    L.jtile = take((size_t)n_tiles * 3 * NJ * NJ * sizeof(float));
     L.rho_prev = take(nodes * sizeof(double));
     L.rho_now = take(nodes * sizeof(double));
     if (c->j_filter > 0) {
@@ -123,6 +136,8 @@ struct pic_sim {
     float *jf;          // filter partner of the J planes (j_filter > 0)
     double *rho_tmp;    // filter partner of rho_now (j_filter > 0)
     int32_t origin;     // moving window: array column of window column 0
+    int halo;           // sort cadence: pushes between sorts (the push kernel's halo pad)
+    int since_sort;     // pushes since the last sort
     int32_t *wrem;      // moving window: particles that left, per species
     int64_t cap[kMaxSpecies];
     bool have_snapshot;
@@ -445,6 +460,8 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
     const bool window = (cfg->flags & PIC_FLAG_MOVING_WINDOW) != 0;
     S->wrem = window ? (int32_t *)(w + L.wrem) : nullptr;
     S->origin = 0;
+    S->halo = halo_of(cfg);
+    S->since_sort = 0;
     for (int s = 0; s < cfg->n_species; ++s) {
         auto &P = S->sp[s];
         P.off = (int32_t *)(w + L.off[s][0]);
@@ -483,14 +500,18 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
 int pic_push_deposit(pic_sim *S, hipStream_t stream)
 {
     if (!S) return PIC_EINVAL;
+    // a particle may stray at most sort_every - 1 cells from its tile before a push
+    if (S->since_sort >= S->halo) return PIC_EORDER;
     const PushArgs a = push_args(S);
     {
         Timed t(S, PIC_KERNEL_PUSH, stream);
-        launch_push_deposit(S->tile, S->replicas, j_mode(&S->cfg), d_mode(&S->cfg), a, S->n_tiles, stream);
+        launch_push_deposit(S->tile, S->replicas, j_mode(&S->cfg), d_mode(&S->cfg), S->halo, a, S->n_tiles,
+                            stream);
     }
+    S->since_sort += 1;
     {
         Timed t(S, PIC_KERNEL_JREDUCE, stream);
-        launch_j_reduce(S->tile, jreduce_args(S), stream);
+        launch_j_reduce(S->tile, S->halo, jreduce_args(S), stream);
     }
     for (int p = 0; p < S->cfg.j_filter; ++p) {
         Timed t(S, PIC_KERNEL_FILTER, stream);
@@ -502,6 +523,8 @@ int pic_push_deposit(pic_sim *S, hipStream_t stream)
 int pic_sort(pic_sim *S, hipStream_t stream)
 {
     if (!S) return PIC_EINVAL;
+    if (S->since_sort == 0) return PIC_OK;   // already sorted: the count records are spent
+    S->since_sort = 0;
     const SortArgs a = sort_args(S);
     {
         Timed t(S, PIC_KERNEL_SORT_SCAN, stream);
@@ -529,6 +552,7 @@ int pic_field_advance(pic_sim *S, hipStream_t stream)
 int pic_move_window(pic_sim *S, const pic_particles *inject, const int64_t *n_inject, hipStream_t stream)
 {
     if (!S || !(S->cfg.flags & PIC_FLAG_MOVING_WINDOW)) return PIC_EINVAL;
+    if (S->since_sort != 0) return PIC_EORDER;   // the last push is not sorted yet
     pic_config &c = S->cfg;
     int64_t k[kMaxSpecies] = {};
     for (int s = 0; s < c.n_species; ++s) {
@@ -622,7 +646,7 @@ int pic_get_counts(pic_sim *S, int64_t *counts)
 int pic_step(pic_sim *S, hipStream_t stream)
 {
     int rc = pic_push_deposit(S, stream);
-    if (rc == PIC_OK) rc = pic_sort(S, stream);
+    if (rc == PIC_OK && S->since_sort >= S->halo) rc = pic_sort(S, stream);
     if (rc == PIC_OK) rc = pic_field_advance(S, stream);
     return rc;
 }
@@ -773,6 +797,7 @@ int pic_set_state(pic_sim *S, const pic_host_state *in, hipStream_t stream)
     int rc = hip_ok(hipMemcpyAsync(S->buf.fields, in->fields, fbytes, hipMemcpyHostToDevice, stream));
     for (int s = 0; s < S->cfg.n_species && rc == PIC_OK; ++s) rc = copy_particles(S, s, in->sp[s], false, stream);
     S->have_snapshot = false;
+    S->since_sort = 0;
     if (rc == PIC_OK) rc = build_tiles(S, stream);
     if (rc == PIC_OK) S->origin = in->window_origin;
     return rc;
@@ -848,6 +873,8 @@ void pic_destroy(pic_sim *S)
 struct pic_batch {
     std::vector<pic_sim *> sims;
     int tile, replicas, jm, dm;
+    int halo;    // sort cadence shared by the members
+    int phase;   // steps since the members were last sorted
     int cus;
     char *dev;
     // device tables
@@ -879,7 +906,8 @@ int batch_validate(int n, const pic_config *cfgs)
         const int rc = validate(&cfgs[i]);
         if (rc) return rc;
         if (cfgs[i].tile != cfgs[0].tile || cfgs[i].flags != cfgs[0].flags ||
-            cfgs[i].j_replicas != cfgs[0].j_replicas || cfgs[i].j_filter != cfgs[0].j_filter)
+            cfgs[i].j_replicas != cfgs[0].j_replicas || cfgs[i].j_filter != cfgs[0].j_filter ||
+            halo_of(&cfgs[i]) != halo_of(&cfgs[0]))
             return PIC_EINVAL;
         if (cfgs[i].flags & PIC_FLAG_MOVING_WINDOW) return PIC_EINVAL;   // member counts are fixed
     }
@@ -920,12 +948,14 @@ BatchLayout batch_layout(int n, const pic_config *cfgs)
     return L;
 }
 
-void batch_enqueue_step(pic_batch *b, hipStream_t stream)
+// One step of every member; the sort only when `sort` is set (the last step
+// of a cadence cycle).
+void batch_enqueue_step(pic_batch *b, bool sort, hipStream_t stream)
 {
     launch_set_int(b->counter, 0, stream);
-    launch_push_batch(b->tile, b->replicas, b->jm, b->dm, b->d_push, b->push_items, b->n_push, b->counter,
+    launch_push_batch(b->tile, b->replicas, b->jm, b->dm, b->halo, b->d_push, b->push_items, b->n_push, b->counter,
                       b->push_grid, stream);
-    launch_j_reduce_batch(b->tile, b->d_jr, b->node_items, b->n_node, stream);
+    launch_j_reduce_batch(b->tile, b->halo, b->d_jr, b->node_items, b->n_node, stream);
     for (int p = 0; p < b->j_filter; ++p)
         launch_filter_batch(b->d_filter + (p & 1) * b->sims.size(), b->node_items, b->n_node, stream);
     SortBatch sb;
@@ -936,7 +966,7 @@ void batch_enqueue_step(pic_batch *b, hipStream_t stream)
     sb.n_scan = b->n_scan;
     sb.plan_items = b->plan_items;
     sb.n_plan = b->n_plan;
-    launch_sort_batch(sb, stream);
+    if (sort) launch_sort_batch(sb, stream);
     launch_field_advance_batch(b->d_field, b->node_items, b->n_node, stream);
 }
 
@@ -979,6 +1009,8 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
     B->jm = j_mode(&cfgs[0]);
     B->dm = d_mode(&cfgs[0]);
     B->replicas = cfgs[0].j_replicas ? cfgs[0].j_replicas : default_replicas(&cfgs[0]);
+    B->halo = halo_of(&cfgs[0]);
+    B->phase = 0;
     char *d = (char *)batch_work;
     B->dev = d;
     B->d_push = (PushArgs *)(d + L.d_push);
@@ -1049,7 +1081,7 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
     // persistent push grid: as many workgroups as fit on the device at once
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int per_cu = std::max(1, std::min(8, kLdsBytes / push_lds_bytes(B->tile, B->replicas, B->jm)));
+    const int per_cu = std::max(1, std::min(8, kLdsBytes / push_lds_bytes(B->tile, B->replicas, B->jm, B->halo)));
     B->cus = cus;
     B->push_grid = std::max(1, std::min(B->n_push, cus * per_cu));
     if (rc) {
@@ -1063,13 +1095,21 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
 int pic_batch_step(pic_batch *B, int nsteps, hipStream_t stream)
 {
     if (!B || nsteps < 0) return PIC_EINVAL;
-    for (int k = 0; k < nsteps; ++k) {
-        if (B->exec) {
+    int k = 0;
+    while (k < nsteps) {
+        if (B->exec && B->phase == 0 && nsteps - k >= B->halo) {
+            // one captured cadence cycle: halo steps, the last with the sort
             if (hipGraphLaunch(B->exec, stream) != hipSuccess) return PIC_EHIP;
+            k += B->halo;
         } else {
-            batch_enqueue_step(B, stream);
+            const bool sort = B->phase + 1 == B->halo;
+            batch_enqueue_step(B, sort, stream);
+            B->phase = sort ? 0 : B->phase + 1;
+            k += 1;
         }
     }
+    // the members' own record of unsorted pushes (pic_batch_sim handles)
+    for (pic_sim *S : B->sims) S->since_sort = B->phase;
     return hip_ok(hipGetLastError());
 }
 
@@ -1085,7 +1125,7 @@ int pic_batch_capture(pic_batch *B, hipStream_t stream)
         B->graph = nullptr;
     }
     if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PIC_EHIP;
-    batch_enqueue_step(B, stream);
+    for (int k = 0; k < B->halo; ++k) batch_enqueue_step(B, k + 1 == B->halo, stream);
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(stream, &g) != hipSuccess || !g) return PIC_EHIP;
     B->graph = g;

@@ -63,12 +63,25 @@ constexpr int kPieceBuf = 64;            // queued second / third motion pieces 
 // one ballot can add a whole wavefront to either buffer
 static_assert(kLeaverBuf >= 64 && kPieceBuf >= 64, "per-wavefront LDS buffers must hold 64 entries");
 
-// Static LDS of the push kernel for tile T, R current replicas, mode JM.
-constexpr int push_lds_bytes(int T, int R, int JM)
+// Static LDS of the push kernel for tile T, R current replicas, mode JM and
+// halo pad H (the sort cadence: between two sorts a particle may stray up to
+// H - 1 cells outside its tile, so the E/B halo holds cells -H..T+H-1 and
+// the current halo nodes -H..T+H).
+constexpr int push_lds_bytes(int T, int R, int JM, int H = 1)
 {
-    return (T + 2) * (T + 2) * 48 + R * 3 * (T + 3) * (T + 3) * (JM == kJFixed ? 8 : 4) +
+    return (T + 2 * H) * (T + 2 * H) * 48 + R * 3 * (T + 2 * H + 1) * (T + 2 * H + 1) * (JM == kJFixed ? 8 : 4) +
            kMaxSpecies * (9 + push_waves(T)) * 4 + push_waves(T) * 7 * kLeaverBuf * 4 +
            push_waves(T) * 6 * kPieceBuf * 4;
+}
+
+// Sort cadences the push kernel is built for: every 1, 2 or 4 steps, with
+// the fixed-point current and one LDS copy of it when above 1.  A node's
+// current halo then still overlaps at most one neighbour per axis (2H + 1 <=
+// T), a position outside the tile has one periodic image within the pad
+// (2H - 2 < T), and the LDS fits.
+constexpr bool cadence_ok(int T, int H)
+{
+    return (H == 1 || H == 2 || H == 4) && 2 * H + 1 <= T && push_lds_bytes(T, 1, kJFixed, H) <= kLdsBytes;
 }
 
 // One species' particles as a structure of arrays (n entries each).
@@ -91,7 +104,7 @@ struct SpeciesDev {
 
 struct PushArgs {
     const float *fld;     // Ex Ey Ez Bx By Bz planes
-    float *jtile;         // [n_tiles][3][(T+3)^2], physical current of each tile halo
+    float *jtile;         // [n_tiles][3][(T+2H+1)^2], physical current of each tile halo
     int *err;
     int nx, ny, ntx, nty;
     float cx, cy;         // dt/dx, dt/dy
@@ -167,12 +180,14 @@ struct FieldArgs {
 };
 
 // ---- launchers (each defined next to its kernels) ----
-void launch_push_deposit(int tile, int replicas, int jmode, int dmode, const PushArgs &a, int n_tiles,
+// halo: the pad H of cadence_ok (1 unless particles are sorted less often than every step)
+void launch_push_deposit(int tile, int replicas, int jmode, int dmode, int halo, const PushArgs &a, int n_tiles,
                          hipStream_t s);
-void launch_j_reduce(int tile, const JReduceArgs &r, hipStream_t s);
-void launch_push_batch(int tile, int replicas, int jmode, int dmode, const PushArgs *descs, const int4 *items,
-                       int n_items, int *counter, int grid, hipStream_t s);
-void launch_j_reduce_batch(int tile, const JReduceArgs *descs, const int4 *items, int n_items, hipStream_t s);
+void launch_j_reduce(int tile, int halo, const JReduceArgs &r, hipStream_t s);
+void launch_push_batch(int tile, int replicas, int jmode, int dmode, int halo, const PushArgs *descs,
+                       const int4 *items, int n_items, int *counter, int grid, hipStream_t s);
+void launch_j_reduce_batch(int tile, int halo, const JReduceArgs *descs, const int4 *items, int n_items,
+                           hipStream_t s);
 void launch_set_int(int *p, int v, hipStream_t s);
 void launch_sort_scan(const SortArgs &a, int n_tiles, hipStream_t s);
 void launch_sort_plan(const SortArgs &a, int n_tiles, hipStream_t s);

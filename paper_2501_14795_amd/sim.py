@@ -36,7 +36,8 @@ class _Buffers:
     the pic_config / pic_buffers structures that describe them."""
 
     def __init__(self, nx, ny, dx, dy, dt, tile, species, E=None, B=None, j_replicas=0, j_float=False,
-                 device="cuda:0", j_filter=0, esirkepov=False, moving_window=False, capacity=None):
+                 device="cuda:0", j_filter=0, esirkepov=False, moving_window=False, capacity=None,
+                 sort_every=1):
         torch = _torch()
         if not 1 <= len(species) <= _lib.MAX_SPECIES:
             raise ValueError("1..4 species")
@@ -49,6 +50,7 @@ class _Buffers:
         cfg.flags = ((_lib.PIC_FLAG_J_FLOAT if j_float else 0) | (_lib.PIC_FLAG_ESIRKEPOV if esirkepov else 0) |
                      (_lib.PIC_FLAG_MOVING_WINDOW if moving_window else 0))
         cfg.j_filter = int(j_filter)
+        cfg.sort_every = int(sort_every)
         for k, (qm, q, st) in enumerate(species):
             cfg.species[k].qm = float(qm)
             cfg.species[k].q = float(q)
@@ -270,12 +272,13 @@ class Sim(_SimView):
     def __init__(self, nx: int, ny: int, dx: float, dy: float, dt: float, tile: int,
                  species: Sequence, E: Optional[np.ndarray] = None, B: Optional[np.ndarray] = None,
                  j_replicas: int = 0, j_float: bool = False, device: str = "cuda:0", stream=None,
-                 j_filter: int = 0, esirkepov: bool = False, moving_window: bool = False, capacity=None):
+                 j_filter: int = 0, esirkepov: bool = False, moving_window: bool = False, capacity=None,
+                 sort_every: int = 1):
         torch = _torch()
         self.handle = None
         self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
         self.buf = _Buffers(nx, ny, dx, dy, dt, tile, species, E, B, j_replicas, j_float, device, j_filter,
-                            esirkepov, moving_window, capacity)
+                            esirkepov, moving_window, capacity, sort_every)
         self.cfg = self.buf.cfg
         torch.cuda.synchronize(torch.device(device))
         self.handle = _lib.pic_init(self.cfg, self.buf.bufs, self.s)
@@ -307,16 +310,18 @@ class Batch:
     for all of them, optionally replayed from a captured HIP graph.
 
     members: list of dicts with keys nx, ny, dx, dy, dt, species (as for Sim)
-    and optionally E, B.  All share tile, j_replicas, j_float, j_filter and
-    the deposit scheme."""
+    and optionally E, B.  All share tile, j_replicas, j_float, j_filter, the
+    deposit scheme and the sort cadence."""
 
     def __init__(self, members: Sequence[dict], tile: int, j_replicas: int = 0, j_float: bool = False,
-                 device: str = "cuda:0", stream=None, j_filter: int = 0, esirkepov: bool = False):
+                 device: str = "cuda:0", stream=None, j_filter: int = 0, esirkepov: bool = False,
+                 sort_every: int = 1):
         torch = _torch()
         self.handle = None
         self.stream = stream if stream is not None else torch.cuda.Stream(torch.device(device))
         self.bufs = [_Buffers(m["nx"], m["ny"], m["dx"], m["dy"], m["dt"], tile, m["species"], m.get("E"),
-                              m.get("B"), j_replicas, j_float, device, j_filter, esirkepov) for m in members]
+                              m.get("B"), j_replicas, j_float, device, j_filter, esirkepov,
+                              sort_every=sort_every) for m in members]
         cfgs = [b.cfg for b in self.bufs]
         nbytes = _lib.pic_batch_query(cfgs)
         self.work = torch.empty(nbytes + 256, dtype=torch.uint8, device=torch.device(device))

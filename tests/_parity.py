@@ -18,11 +18,11 @@ def species_states(nx, ny, tile, specs, seed, cell_box=None):
 
 
 def make_pair(nx, ny, dx, dy, dt, tile, specs, states, E=None, B=None, j_replicas=0, j_float=False, j_filter=0,
-              esirkepov=False):
+              esirkepov=False, sort_every=1):
     """GPU Sim and OracleSim from the same FP32 initial state."""
     from paper_2501_14795_amd import Sim
     sim = Sim(nx, ny, dx, dy, dt, tile, [(s.qm, s.q, st) for s, st in zip(specs, states)], E=E, B=B,
-              j_replicas=j_replicas, j_float=j_float, j_filter=j_filter, esirkepov=esirkepov)
+              j_replicas=j_replicas, j_float=j_float, j_filter=j_filter, esirkepov=esirkepov, sort_every=sort_every)
     osp = [oracle.OracleSpecies(s.qm, s.q, st["ix"], st["iy"], st["x"], st["y"], st["ux"], st["uy"], st["uz"])
            for s, st in zip(specs, states)]
     ora = oracle.OracleSim(nx, ny, dx, dy, dt, osp,
@@ -86,8 +86,15 @@ def matched_particle_errors(g, o, nx, ny):
     from scipy.spatial import cKDTree
     Xg = np.c_[(g["ix"] + g["x"].astype(np.float64)) % nx, (g["iy"] + g["y"].astype(np.float64)) % ny]
     Xo = np.c_[(o.ix + o.x) % nx, (o.iy + o.y) % ny]
-    tree = cKDTree(np.c_[Xo, o.ux, o.uy, o.uz], boxsize=[nx, ny, np.inf, np.inf, np.inf])
-    _, idx = tree.query(np.c_[Xg, g["ux"], g["uy"], g["uz"]])
+    # periodic in X, Y only: the tree needs non-negative coordinates and a
+    # finite box, so u is shifted by a common offset into a box far larger
+    # than its range
+    Uo = np.c_[o.ux, o.uy, o.uz]
+    Ug = np.c_[g["ux"], g["uy"], g["uz"]].astype(np.float64)
+    lo = np.minimum(Uo.min(axis=0, initial=0.0), Ug.min(axis=0, initial=0.0))
+    big = 1e9
+    tree = cKDTree(np.c_[Xo, Uo - lo], boxsize=[nx, ny, big, big, big])
+    _, idx = tree.query(np.c_[Xg, Ug - lo])
     assert len(np.unique(idx)) == len(idx), "nearest-neighbour pairing is not one-to-one"
 
     class _O:

@@ -61,10 +61,11 @@ int main(void) {
     assert [int(v) for v in got] == want
 
 
-def _cfg(L, nx=64, ny=64, dx=0.1, dy=0.1, dt=0.07, tile=16, n=1000, ns=1, reps=0, flags=0, filt=0):
+def _cfg(L, nx=64, ny=64, dx=0.1, dy=0.1, dt=0.07, tile=16, n=1000, ns=1, reps=0, flags=0, filt=0, every=0):
     c = L.pic_config()
     c.nx, c.ny, c.dx, c.dy, c.dt, c.tile, c.j_replicas, c.n_species, c.flags = nx, ny, dx, dy, dt, tile, reps, ns, flags
     c.j_filter = filt
+    c.sort_every = every
     for k in range(ns):
         c.species[k].qm = -1.0
         c.species[k].q = -1.0 / 16
@@ -98,6 +99,15 @@ def test_query_sizes_and_validation():
         (dict(n=2 ** 31), L.PIC_EINVAL),
         (dict(filt=-1), L.PIC_EINVAL),
         (dict(filt=L.PIC_MAX_FILTER + 1), L.PIC_EINVAL),
+        # sort cadence: 1, 2 or 4; above 1 only with the fixed-point current and
+        # one LDS copy, without the moving window, where the halo fits the tile
+        (dict(every=3), L.PIC_EINVAL),
+        (dict(every=-1), L.PIC_EINVAL),
+        (dict(every=2, flags=1), L.PIC_EINVAL),             # PIC_FLAG_J_FLOAT
+        (dict(every=2, reps=2), L.PIC_EINVAL),
+        (dict(every=2, flags=4), L.PIC_EINVAL),             # PIC_FLAG_MOVING_WINDOW
+        (dict(tile=8, every=4), L.PIC_ETILE),               # 2k + 1 > tile
+        (dict(nx=64, tile=32, every=4), L.PIC_ETILE),       # over the LDS budget
     ]
     for kw, code in cases:
         ns = kw.pop("ns", 1)
@@ -123,6 +133,13 @@ def test_query_sizes_and_validation():
     # tile offsets (17 int32), each rounded up to 256 bytes: no field copy
     sw = L.pic_query(_cfg(L, flags=L.PIC_FLAG_MOVING_WINDOW))
     assert sw.work_bytes - s.work_bytes == 2 * 256
+    # a sort cadence k widens every tile's current halo to (T + 2k + 1)^2 nodes
+    for every, T in ((2, 16), (4, 16), (2, 8), (2, 32)):
+        base = L.pic_query(_cfg(L, tile=T))
+        wide = L.pic_query(_cfg(L, tile=T, every=every))
+        grow = base.n_tiles * 3 * 4 * ((T + 2 * every + 1) ** 2 - (T + 3) ** 2)
+        assert grow <= wide.work_bytes - base.work_bytes <= grow + 256, (every, T)
+    assert L.pic_query(_cfg(L, every=1)).work_bytes == s.work_bytes
     # the filter's ping-pong planes: three FP32 current planes + one FP64 density plane
     sf = L.pic_query(_cfg(L, filt=L.PIC_MAX_FILTER))
     assert 20 * 64 * 64 <= sf.work_bytes - s.work_bytes <= 20 * 64 * 64 + 2 * 256
