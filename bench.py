@@ -81,10 +81,11 @@ def cpu_baseline(w, st, T, budget_s=10.0, max_steps=8):
 
 def batched_comparison(n_sims=256, steps=5, tune_sims=32):
     """The batched workload (256 independent simulations, grids 32..256
-    cells, 8..64 ppc): the autotuner picks tile size x replicas on the first
-    tune_sims members, then the full batch runs as captured-graph replays, as
-    direct batched launches, and one simulation per launch sequence (pic_step
-    on each member in turn), all on the same members and data."""
+    cells, 8..64 ppc): the autotuner picks tile size x replicas x sort
+    cadence on the first tune_sims members, then the full batch runs as
+    captured-graph replays, as direct batched launches, and one simulation per
+    launch sequence (pic_step on each member in turn, the same cadence), all
+    on the same members and data."""
     import torch
 
     import pic_workloads as pw
@@ -102,17 +103,19 @@ def batched_comparison(n_sims=256, steps=5, tune_sims=32):
         return out
 
     t0 = time.perf_counter()
-    (tile, reps), tuning = autotune_batch(lambda T: build(T, tune_sims))
-    log(f"autotuned tile {tile} replicas {reps} in {time.perf_counter() - t0:.1f}s: {tuning}")
+    (tile, reps, every), tuning = autotune_batch(lambda T: build(T, tune_sims))
+    log(f"autotuned tile {tile} replicas {reps} sort_every {every} in {time.perf_counter() - t0:.1f}s: {tuning}")
     members = build(tile)
     n = sum(m["species"][0][2]["ix"].size for m in members)
-    b = Batch(members, tile=tile, j_replicas=reps)
+    b = Batch(members, tile=tile, j_replicas=reps, sort_every=every)
     del members
     direct = time_batch(b, steps)
     # one simulation per launch sequence, on the same members
     s = b.stream.cuda_stream
-    for m in b.members:
-        _lib.pic_step(m.handle, s)
+    steps = -(-steps // every) * every   # whole cadence cycles
+    for _ in range(every):
+        for m in b.members:
+            _lib.pic_step(m.handle, s)
     b.stream.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -128,8 +131,8 @@ def batched_comparison(n_sims=256, steps=5, tune_sims=32):
         raise SystemExit(f"device error in the batched run: {_lib.strerror(rc)}")
     return {
         "workload": f"{n_sims} simulations, grids 32..256 cells, 8..64 ppc (seed 4)",
-        "particles": n, "steps": steps, "tile": tile, "j_replicas": reps,
-        "autotune_ms_per_step": {f"T{k[0]}_R{k[1]}": v * 1e3 for k, v in tuning.items()},
+        "particles": n, "steps": steps, "tile": tile, "j_replicas": reps, "sort_every": every,
+        "autotune_ms_per_step": {f"T{k[0]}_R{k[1]}_S{k[2]}": v * 1e3 for k, v in tuning.items()},
         "graph_pushes_per_s": n / graph, "direct_pushes_per_s": n / direct,
         "per_sim_launch_pushes_per_s": n / per_sim,
         "graph_ms_per_step": graph * 1e3, "direct_ms_per_step": direct * 1e3,

@@ -330,6 +330,7 @@ class Batch:
                                           nbytes, self.stream.cuda_stream)
         self.members = [BatchMember(self, i, b) for i, b in enumerate(self.bufs)]
         self.captured = False
+        self.sort_every = max(1, int(sort_every))
 
     def __len__(self):
         return len(self.members)

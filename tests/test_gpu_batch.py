@@ -104,3 +104,30 @@ def test_graph_replays_equal_direct_launches():
         _assert_same(graphed[i], direct[i])
     direct.close()
     graphed.close()
+
+
+def test_autotuner_picks_the_fastest_valid_candidate():
+    """The autotuner times every candidate the library accepts for the
+    members (tile x replicas x sort cadence), skips the ones it rejects (tile
+    8 with cadence 4; tile 32 on grids that are not multiples of 32), and
+    returns the fastest."""
+    from paper_2501_14795_amd.tune import autotune_batch
+    members = pw.batched_members(n_sims=4, seed=23)
+
+    def build(tile):
+        out = []
+        for m in members:
+            if m["nx"] % tile or m["ny"] % tile:
+                raise ValueError("not a whole number of tiles")
+            st = pw.species_state(m["nx"], m["ny"], tile, m["spec"], m["seed"])
+            out.append(dict(nx=m["nx"], ny=m["ny"], dx=m["dx"], dy=m["dy"], dt=m["dt"],
+                            species=[(m["spec"].qm, m["spec"].q, st)]))
+        return out
+
+    cands = ((8, 1, 1), (8, 1, 4), (16, 1, 1), (16, 1, 2), (16, 1, 4))
+    best, timings = autotune_batch(build, candidates=cands, steps=4)
+    flush(f"autotuner: best {best}; " + ", ".join(f"{k}: {v * 1e3:.3f} ms" for k, v in timings.items()))
+    assert (8, 1, 4) not in timings            # 2k + 1 > tile: rejected by the library
+    assert set(timings) == {(8, 1, 1), (16, 1, 1), (16, 1, 2), (16, 1, 4)}
+    assert best == min(timings, key=timings.get)
+    assert all(v > 0 for v in timings.values())
