@@ -23,6 +23,9 @@ Particle-Mesh Algorithms with FPGAs and OmpSs@OpenCL"):
 * ``OracleSim.move_window`` -- the moving-window step of Listing 3.1
 * ``binomial_filter``   -- the optional current smoothing of Listing 3.1
 * ``rho`` / energies / divergences -- diagnostics (Eq. 17, Eq. 18, Eq. 12)
+* ``solve_gauss``       -- valid initial fields (Sec. 3.2: Eqs. 17 and 18 hold
+                           before the first step), by projection with an exact
+                           periodic Poisson solve (numpy FFT, Python)
 """
 from __future__ import annotations
 
@@ -207,6 +210,46 @@ def binomial_filter(nx, ny, passes, F):
     return F
 
 
+def poisson_periodic(nx, ny, dx, dy, r) -> np.ndarray:
+    """The zero-mean psi (ny, nx) whose five-point Laplacian
+    (psi[i+1] - 2 psi[i] + psi[i-1]) / dx^2 + (same along y) / dy^2 equals r
+    on the periodic grid (r must have zero mean).  Exact: the discrete
+    Fourier modes diagonalise the operator, with eigenvalues
+    -(2 - 2 cos(2 pi m / nx)) / dx^2 - (2 - 2 cos(2 pi l / ny)) / dy^2."""
+    r = np.asarray(r, np.float64)
+    m = np.arange(nx)
+    l = np.arange(ny)
+    lam = (-(2.0 - 2.0 * np.cos(2.0 * np.pi * m / nx)) / (dx * dx))[None, :] + \
+          (-(2.0 - 2.0 * np.cos(2.0 * np.pi * l / ny)) / (dy * dy))[:, None]
+    lam[0, 0] = 1.0
+    h = np.fft.fft2(r) / lam
+    h[0, 0] = 0.0
+    return np.real(np.fft.ifft2(h))
+
+
+def solve_gauss(nx, ny, dx, dy, E, B, rho_nodes):
+    """Valid initial fields (Sec. 3.2: the fields start satisfying Eq. 17,
+    div E = rho, and Eq. 18, div B = 0), in place on FP64 E, B (3, ny, nx).
+    With the ions as a uniform background the charge is rho - mean(rho).
+    E <- E - grad psi with Lap psi = div E - (rho - mean(rho)) (psi at the
+    nodes; Ex at (i+1/2, j) takes (psi[i+1] - psi[i]) / dx, Ey likewise);
+    B <- B - grad chi with Lap chi = div B (chi at the cell centres; Bx at
+    (i, j+1/2) takes (chi[i] - chi[i-1]) / dx, By likewise).  A gradient has
+    no discrete curl on the Yee grid, so the curls of E and B -- what drives
+    Eqs. 19 and 20 -- are unchanged; with E = 0 on entry this is the
+    electrostatic field of the charge."""
+    rho_nodes = np.asarray(rho_nodes, np.float64)
+    r = div_e(nx, ny, dx, dy, E) - (rho_nodes - rho_nodes.mean())
+    psi = poisson_periodic(nx, ny, dx, dy, r - r.mean())
+    E[0] -= (np.roll(psi, -1, axis=1) - psi) / dx
+    E[1] -= (np.roll(psi, -1, axis=0) - psi) / dy
+    s = div_b(nx, ny, dx, dy, B)
+    chi = poisson_periodic(nx, ny, dx, dy, s - s.mean())
+    B[0] -= (chi - np.roll(chi, 1, axis=1)) / dx
+    B[1] -= (chi - np.roll(chi, 1, axis=0)) / dy
+    return E, B
+
+
 # --------------------------------------------------------------------------
 # whole-simulation driver
 # --------------------------------------------------------------------------
@@ -302,6 +345,11 @@ class OracleSim:
             _, src = sort_canonical(self.nx, self.ny, T, cat["ix"], cat["iy"], removed=rm)
             for name, v in cat.items():
                 setattr(s, name, np.ascontiguousarray(v[src], dtype=np.int32 if name in ("ix", "iy") else np.float64))
+
+    def solve_gauss(self):
+        """Make E and B valid initial fields for the current particles
+        (``solve_gauss``)."""
+        solve_gauss(self.nx, self.ny, self.dx, self.dy, self.E, self.B, self.rho())
 
     def rho(self, filtered=False):
         """Node charge density; with filtered=True smoothed by the current filter

@@ -590,3 +590,82 @@ def test_moving_window_holds_a_light_pulse(ora):
             assert abs(moved) < 1.0, moved
         else:
             assert abs(moved - 40.0) < 1.0, moved
+
+
+# ------------------------------------------------ valid initial fields (Eqs. 17-18)
+def _curl_e(E, dx, dy):
+    """z-curl of (Ex, Ey) at the cell centres, the Bz stencil of Eq. 19."""
+    return (np.roll(E[1], -1, axis=1) - E[1]) / dx - (np.roll(E[0], -1, axis=0) - E[0]) / dy
+
+
+def _curl_b(B, dx, dy):
+    """z-curl of (Bx, By) at the nodes, the Ez stencil of Eq. 20."""
+    return (B[1] - np.roll(B[1], 1, axis=1)) / dx - (B[0] - np.roll(B[0], 1, axis=0)) / dy
+
+
+def _div_centre(B, dx, dy):
+    """Divergence of (Bx, By) at the cell centres."""
+    return (np.roll(B[0], -1, axis=1) - B[0]) / dx + (np.roll(B[1], -1, axis=0) - B[1]) / dy
+
+
+@pytest.mark.parametrize("axis", [0, 1])
+def test_solve_gauss_single_mode_closed_form(ora, axis):
+    """A charge density cos(theta i) along one axis, E = 0 before: the discrete
+    Gauss law gives E = A d / (2 sin(theta / 2)) sin(theta (i + 1/2)) along
+    that axis and nothing along the other."""
+    nx, ny, dx, dy, m, A = 48, 40, 0.1, 0.07, 3, 0.37
+    n, d = (nx, dx) if axis == 0 else (ny, dy)
+    th = 2 * np.pi * m / n
+    prof = A * np.cos(th * np.arange(n))
+    rho = np.tile(prof, (ny, 1)) if axis == 0 else np.tile(prof[:, None], (1, nx))
+    E, B = np.zeros((3, ny, nx)), np.zeros((3, ny, nx))
+    ora.solve_gauss(nx, ny, dx, dy, E, B, rho + 5.0)      # a uniform part changes nothing
+    want = A * d / (2 * np.sin(th / 2)) * np.sin(th * (np.arange(n) + 0.5))
+    got = E[0, 0, :] if axis == 0 else E[1, :, 0]
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-13 * abs(want).max())
+    assert np.abs(E[1 - axis]).max() < 1e-13 and np.abs(E[2]).max() == 0 and np.abs(B).max() == 0
+
+
+def test_solve_gauss_random_fields(ora):
+    """Random E, B and a random particle charge: afterwards div E = rho -
+    <rho> at every node and div B = 0 at every cell centre (to round-off),
+    while the discrete curls of E and B and the z components are unchanged."""
+    import pic_workloads as pw
+    nx, ny, dx, dy = 40, 56, 0.1, 0.12
+    E, B = pw.random_fields(nx, ny, 0.3, 4)
+    E, B = E.astype(np.float64), B.astype(np.float64)
+    B[0] += np.random.default_rng(1).normal(0, 0.1, (ny, nx))   # give B a divergence
+    rng = np.random.default_rng(2)
+    n = 3000
+    X, Y = rng.random(n) * nx, rng.random(n) * ny
+    ix, iy = np.floor(X).astype(np.int32), np.floor(Y).astype(np.int32)
+    rho = node_charge(nx, ny, -0.05, X, Y)
+    assert np.allclose(rho, ora.rho(nx, ny, -0.05, ix, iy, X - ix, Y - iy))
+    E0, B0 = E.copy(), B.copy()
+    ora.solve_gauss(nx, ny, dx, dy, E, B, rho)
+    res = div_edge(E, dx, dy) - (rho - rho.mean())
+    assert np.abs(res).max() < 1e-11 * np.abs(rho).max()
+    assert np.abs(_div_centre(B, dx, dy)).max() < 1e-11 * np.abs(B).max() / dx
+    assert np.abs(_div_centre(B0, dx, dy)).max() > 0.1           # it had one
+    np.testing.assert_allclose(_curl_e(E, dx, dy), _curl_e(E0, dx, dy), rtol=0, atol=1e-11)
+    np.testing.assert_allclose(_curl_b(B, dx, dy), _curl_b(B0, dx, dy), rtol=0, atol=1e-11)
+    assert np.array_equal(E[2], E0[2]) and np.array_equal(B[2], B0[2])
+    # fields that already satisfy both laws are left as they are
+    E1, B1 = E.copy(), B.copy()
+    ora.solve_gauss(nx, ny, dx, dy, E1, B1, rho)
+    assert np.abs(E1 - E).max() < 1e-12 and np.abs(B1 - B).max() < 1e-12
+
+
+def test_solve_gauss_equals_the_one_dimensional_prefix_sum(ora):
+    """The displaced Langmuir lattice: the projection from E = 0 reproduces
+    the one-dimensional construction (running sum of rho - <rho> along x,
+    zero mean)."""
+    import sys, os
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from langmuir_fixture import DX, langmuir_state
+    nx, ny = 128, 16
+    spec, st, E_ref = langmuir_state(nx, ny, 16)
+    rho = ora.rho(nx, ny, spec.q, st["ix"], st["iy"], st["x"], st["y"])
+    E, B = np.zeros((3, ny, nx)), np.zeros((3, ny, nx))
+    ora.solve_gauss(nx, ny, DX, DX, E, B, rho)
+    np.testing.assert_allclose(E, E_ref, rtol=0, atol=1e-12 * np.abs(E_ref).max())
