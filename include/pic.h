@@ -70,6 +70,7 @@ extern "C" {
 #define PIC_ESORT (-7)    /* internal sort consistency check failed */
 #define PIC_ECOUNT (-8)   /* tile counts do not add up to the particle count */
 #define PIC_EOVERFLOW (-9) /* fixed-point current: 2^16+ contributions to one node of one tile */
+#define PIC_ENOCONV (-10)  /* pic_solve_gauss: the iteration did not reach its tolerance */
 
 /*
  * Current accumulation inside a tile (pic_config.flags).
@@ -280,6 +281,34 @@ typedef struct pic_diag_out {
  * device error flags like pic_check().
  */
 int pic_diag(pic_sim *sim, unsigned what, pic_diag_out *out, hipStream_t stream);
+
+/*
+ * Valid initial fields (Sec. 3.2: the fields start out satisfying Eq. 17,
+ * div E = rho, and Eq. 18, div B = 0).  With the ions a uniform neutralising
+ * background (rho_bar as in PIC_DIAG_GAUSS) and on the periodic Yee grid:
+ *   E <- E - grad psi,  Lap psi = div E - (rho - rho_bar)   (psi at the nodes)
+ *   B <- B - grad chi,  Lap chi = div B                     (chi at the cell centres)
+ * Lap is the five-point Laplacian, the divergence of the grid gradient; a
+ * gradient has no discrete curl, so the curls of E and B are unchanged and
+ * Ez, Bz are not touched.  From E = B = 0 this is the electrostatic field of
+ * the particles (e.g. a perturbed plasma).  rho is that of the Gauss
+ * diagnostic (binomially filtered when pic_config.j_filter > 0).  Each
+ * Poisson problem is solved by conjugate gradients in FP64 until ||r|| <= tol
+ * ||r0|| (tol <= 0: 1e-12) or max_iter iterations (<= 0: 20 max(nx, ny) +
+ * 100); the result is stored in FP32.
+ * scratch: device memory of at least PIC_GAUSS_SCRATCH_BYTES(nx, ny) bytes,
+ * 256-byte aligned, caller-owned.  Synchronises `stream`.  out (may be NULL)
+ * receives the iterations and final relative residual of both solves.
+ * Returns PIC_EINVAL for bad arguments and PIC_ENOCONV if a solve stopped
+ * short of tol (the fields then hold the last iterate's correction).
+ */
+#define PIC_GAUSS_SCRATCH_BYTES(nx, ny) (32 * (size_t)(nx) * (size_t)(ny) + 16384)
+typedef struct pic_gauss_out {
+    int32_t iterations[2];   /* [0]: E (Eq. 17), [1]: B (Eq. 18) */
+    double residual[2];      /* ||r|| / ||r0|| at the end (0 when r0 = 0) */
+} pic_gauss_out;
+int pic_solve_gauss(pic_sim *sim, void *scratch, size_t scratch_bytes, double tol, int max_iter,
+                    pic_gauss_out *out, hipStream_t stream);
 
 /*
  * State I/O: host copies of everything that carries over from one step to

@@ -22,6 +22,7 @@ PIC_ERANGE = -6
 PIC_ESORT = -7
 PIC_ECOUNT = -8
 PIC_EOVERFLOW = -9
+PIC_ENOCONV = -10
 
 PIC_FLAG_J_FLOAT = 1
 PIC_FLAG_ESIRKEPOV = 2
@@ -39,7 +40,7 @@ PIC_MAX_FILTER = 16
 # every symbol the header declares
 EXPORTS = [
     "pic_query", "pic_init", "pic_push_deposit", "pic_sort", "pic_field_advance", "pic_move_window",
-    "pic_get_window_origin", "pic_get_counts", "pic_step",
+    "pic_get_window_origin", "pic_get_counts", "pic_solve_gauss", "pic_step",
     "pic_check", "pic_diag", "pic_get_state", "pic_set_state", "pic_get_tile_offsets",
     "pic_set_timing", "pic_get_timing",
     "pic_batch_query", "pic_batch_init", "pic_batch_step", "pic_batch_capture", "pic_batch_sim",
@@ -87,6 +88,10 @@ class pic_host_state(ctypes.Structure):
                 ("n", ctypes.c_int64 * MAX_SPECIES), ("window_origin", ctypes.c_int32)]
 
 
+class pic_gauss_out(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32 * 2), ("residual", ctypes.c_double * 2)]
+
+
 class pic_timing_out(ctypes.Structure):
     _fields_ = [("ms_total", ctypes.c_double * 7), ("launches", ctypes.c_int64 * 7)]
 
@@ -126,6 +131,7 @@ def load(path: str = SO_PATH):
     L.pic_move_window.argtypes = [vp, P(pic_particles), P(ctypes.c_int64), vp]
     L.pic_get_counts.argtypes = [vp, P(ctypes.c_int64)]
     L.pic_get_window_origin.argtypes = [vp, P(ctypes.c_int32)]
+    L.pic_solve_gauss.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int, P(pic_gauss_out), vp]
     L.pic_set_state.argtypes = [vp, P(pic_host_state), vp]
     L.pic_set_timing.argtypes = [vp, ctypes.c_int]
     L.pic_get_timing.argtypes = [vp, P(pic_timing_out)]
@@ -213,6 +219,19 @@ def pic_get_window_origin(sim: int) -> int:
     out = ctypes.c_int32()
     _chk(load().pic_get_window_origin(ctypes.c_void_p(sim), ctypes.byref(out)), "pic_get_window_origin")
     return int(out.value)
+
+
+def gauss_scratch_bytes(nx: int, ny: int) -> int:
+    """PIC_GAUSS_SCRATCH_BYTES(nx, ny)."""
+    return 32 * nx * ny + 16384
+
+
+def pic_solve_gauss(sim: int, scratch: int, scratch_bytes: int, tol: float, max_iter: int, stream: int):
+    """Returns the pic_gauss_out record; raises PicError (PIC_ENOCONV included)."""
+    out = pic_gauss_out()
+    _chk(load().pic_solve_gauss(ctypes.c_void_p(sim), ctypes.c_void_p(scratch), scratch_bytes, float(tol),
+                                int(max_iter), ctypes.byref(out), ctypes.c_void_p(stream)), "pic_solve_gauss")
+    return out
 
 
 def pic_get_counts(sim: int, n_species: int):

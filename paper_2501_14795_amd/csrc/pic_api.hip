@@ -236,6 +236,40 @@ DiagSpecies diag_species(const pic_sim *s, int k)
     return d;
 }
 
+// The node charge density of the Gauss diagnostic into rho_now: every
+// species' charge at the nodes, binomially filtered like the current when the
+// filter is on (the density whose continuity the filtered current satisfies).
+int node_density(pic_sim *S, hipStream_t stream)
+{
+    const pic_config &c = S->cfg;
+    const int64_t plane = (int64_t)c.nx * c.ny;
+    int rc = hip_ok(hipMemsetAsync(S->rho_now, 0, plane * sizeof(double), stream));
+    if (rc) return rc;
+    for (int s = 0; s < c.n_species; ++s) launch_diag_rho(diag_species(S, s), c.nx, c.ny, S->rho_now, stream);
+    for (int p = 0; p < c.j_filter; ++p) {
+        FilterArgs f;
+        f.src = (p & 1) ? S->rho_tmp : S->rho_now;
+        f.dst = (p & 1) ? S->rho_now : S->rho_tmp;
+        f.nx = c.nx;
+        f.ny = c.ny;
+        f.planes = 1;
+        launch_filter(f, true, stream);
+    }
+    if (c.j_filter & 1)
+        rc = hip_ok(hipMemcpyAsync(S->rho_now, S->rho_tmp, plane * sizeof(double), hipMemcpyDeviceToDevice, stream));
+    return rc;
+}
+
+// The uniform neutralising background: the mean charge density.
+double mean_density(const pic_sim *S)
+{
+    const pic_config &c = S->cfg;
+    double total = 0.0;
+    for (int s = 0; s < c.n_species; ++s) total += c.species[s].q * (double)c.species[s].n;
+    return total / ((double)c.nx * c.ny);
+}
+
+
 // Kernel arguments of one simulation (identical every step: the sort writes
 // the new tile_offset in place).
 PushArgs push_args(const pic_sim *S)
@@ -384,6 +418,7 @@ const char *pic_strerror(int code)
     case PIC_ESORT: return "sort consistency check failed";
     case PIC_ECOUNT: return "tile counts do not add up to the particle count";
     case PIC_EOVERFLOW: return "a tile current accumulator took 2^16 or more contributions to one node";
+    case PIC_ENOCONV: return "the Poisson iteration did not reach its tolerance";
     default: return "unknown error";
     }
 }
@@ -636,6 +671,43 @@ int pic_get_window_origin(pic_sim *S, int32_t *origin)
     return PIC_OK;
 }
 
+int pic_solve_gauss(pic_sim *S, void *scratch, size_t scratch_bytes, double tol, int max_iter,
+                    pic_gauss_out *out, hipStream_t stream)
+{
+    if (!S || !scratch || ((uintptr_t)scratch) % kAlign) return PIC_EINVAL;
+    const pic_config &c = S->cfg;
+    const int64_t P = (int64_t)c.nx * c.ny;
+    if (scratch_bytes < PIC_GAUSS_SCRATCH_BYTES(c.nx, c.ny)) return PIC_EINVAL;
+    if (!(tol > 0.0)) tol = 1e-12;
+    if (max_iter <= 0) max_iter = 20 * (c.nx > c.ny ? c.nx : c.ny) + 100;
+    double *d = (double *)scratch;
+    CgScratch w;
+    w.x = d;
+    w.r = d + P;
+    w.p = d + 2 * P;
+    w.q = d + 3 * P;
+    w.partial = d + 4 * P;
+    w.scal = w.partial + kCgPartials;
+    int rc = node_density(S, stream);
+    if (rc) return rc;
+    const CgResult e = cg_project(S->buf.fields, S->rho_now, mean_density(S), 0, c.nx, c.ny, c.dx, c.dy, tol,
+                                  max_iter, w, stream);
+    if (e.iterations < 0) return PIC_EHIP;
+    const CgResult b = cg_project(S->buf.fields, nullptr, 0.0, 1, c.nx, c.ny, c.dx, c.dy, tol, max_iter, w, stream);
+    if (b.iterations < 0) return PIC_EHIP;
+    rc = hip_ok(hipGetLastError());
+    if (rc == PIC_OK) rc = hip_ok(hipStreamSynchronize(stream));
+    if (rc) return rc;
+    if (out) {
+        out->iterations[0] = e.iterations;
+        out->iterations[1] = b.iterations;
+        out->residual[0] = e.residual;
+        out->residual[1] = b.residual;
+    }
+    S->have_snapshot = false;
+    return e.converged && b.converged ? PIC_OK : PIC_ENOCONV;
+}
+
 int pic_get_counts(pic_sim *S, int64_t *counts)
 {
     if (!S || !counts) return PIC_EINVAL;
@@ -672,34 +744,14 @@ int pic_diag(pic_sim *S, unsigned what, pic_diag_out *out, hipStream_t stream)
         for (int s = 0; s < c.n_species; ++s) launch_diag_kinetic(diag_species(S, s), S->dacc + 2 + s, stream);
     }
     if (what & (PIC_DIAG_RHO_SNAPSHOT | PIC_DIAG_CONTINUITY | PIC_DIAG_GAUSS)) {
-        rc = hip_ok(hipMemsetAsync(S->rho_now, 0, plane * sizeof(double), stream));
+        rc = node_density(S, stream);
         if (rc) return rc;
-        for (int s = 0; s < c.n_species; ++s) launch_diag_rho(diag_species(S, s), c.nx, c.ny, S->rho_now, stream);
-        // the density whose continuity the filtered current satisfies
-        for (int p = 0; p < c.j_filter; ++p) {
-            FilterArgs f;
-            f.src = (p & 1) ? S->rho_tmp : S->rho_now;
-            f.dst = (p & 1) ? S->rho_now : S->rho_tmp;
-            f.nx = c.nx;
-            f.ny = c.ny;
-            f.planes = 1;
-            launch_filter(f, true, stream);
-        }
-        if (c.j_filter & 1) {
-            rc = hip_ok(hipMemcpyAsync(S->rho_now, S->rho_tmp, plane * sizeof(double), hipMemcpyDeviceToDevice,
-                                       stream));
-            if (rc) return rc;
-        }
     }
     if (what & PIC_DIAG_CONTINUITY)
         launch_diag_continuity(S->rho_prev, S->rho_now, S->buf.fields + 6 * plane, c.nx, c.ny, c.dt, c.dx, c.dy,
                                S->dacc + 8, stream);
-    if (what & PIC_DIAG_GAUSS) {
-        double total = 0.0;
-        for (int s = 0; s < c.n_species; ++s) total += c.species[s].q * (double)c.species[s].n;
-        launch_diag_gauss(S->buf.fields, S->rho_now, total / (double)plane, c.nx, c.ny, c.dx, c.dy, S->dacc + 10,
-                          stream);
-    }
+    if (what & PIC_DIAG_GAUSS)
+        launch_diag_gauss(S->buf.fields, S->rho_now, mean_density(S), c.nx, c.ny, c.dx, c.dy, S->dacc + 10, stream);
     double dh[32];
     unsigned long long ch[8 * kMaxSpecies];
     rc = hip_ok(hipMemcpyAsync(dh, S->dacc, sizeof(dh), hipMemcpyDeviceToHost, stream));

@@ -228,6 +228,21 @@ void launch_filter_batch(const FilterArgs *descs, const int4 *items, int n_items
 void launch_field_advance(const FieldArgs &f, hipStream_t s);
 void launch_field_advance_batch(const FieldArgs *descs, const int4 *items, int n_items, hipStream_t s);
 
+// Conjugate-gradient projection of E (Eq. 17) or B (Eq. 18), k_poisson.hip.
+constexpr int kCgPartials = 1024;   // per-block partial sums of one dot product, at most
+struct CgScratch {
+    double *x, *r, *p, *q;   // nx * ny each
+    double *partial;         // kCgPartials
+    double *scal;            // r.r (two parity slots), p.q, sum of the right-hand side
+};
+struct CgResult {
+    int iterations;   // -1: a HIP call failed
+    double residual;  // ||r|| / ||r0|| at the end
+    bool converged;
+};
+CgResult cg_project(float *fld, const double *rho, double rho_bar, int magnetic, int nx, int ny, double dx, double dy,
+                    double tol, int max_iter, const CgScratch &w, hipStream_t s);
+
 struct DiagSpecies {
     const int32_t *cell;
     const float *x, *y, *ux, *uy, *uz;

@@ -239,6 +239,16 @@ class _SimView:
         self.stream.synchronize()
         _lib.pic_set_state(self.handle, hs, self.s)
 
+    def solve_gauss(self, tol: float = 0.0, max_iter: int = 0):
+        """Make E and B valid initial fields for the current particles
+        (pic_solve_gauss: E satisfies Gauss's law, div B = 0, curls kept).
+        Returns the pic_gauss_out record (iterations, final residuals)."""
+        torch = _torch()
+        nbytes = _lib.gauss_scratch_bytes(self.nx, self.ny)
+        scratch = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.fields.device)
+        self.stream.synchronize()
+        return _lib.pic_solve_gauss(self.handle, (scratch.data_ptr() + 255) & ~255, nbytes, tol, max_iter, self.s)
+
     def window_origin(self) -> int:
         """Array column of window column 0 (pic_get_window_origin)."""
         return _lib.pic_get_window_origin(self.handle)

@@ -143,7 +143,7 @@ def test_query_sizes_and_validation():
     # the filter's ping-pong planes: three FP32 current planes + one FP64 density plane
     sf = L.pic_query(_cfg(L, filt=L.PIC_MAX_FILTER))
     assert 20 * 64 * 64 <= sf.work_bytes - s.work_bytes <= 20 * 64 * 64 + 2 * 256
-    for code in range(0, -10, -1):
+    for code in range(0, -11, -1):
         assert L.strerror(code) != "unknown error"
     assert L.strerror(-99) == "unknown error"
 
