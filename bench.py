@@ -393,11 +393,16 @@ def main():
 
 
 def _kernel_sha():
+    """Hash of what the push kernel is compiled from: k_push.hip and the
+    constants and structures of pic_internal.h (the part before its launcher
+    declarations, which other kernels extend)."""
     import hashlib
     h = hashlib.sha256()
-    for name in ("k_push.hip", "pic_internal.h"):
-        with open(os.path.join(ROOT, "paper_2501_14795_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+    csrc = os.path.join(ROOT, "paper_2501_14795_amd", "csrc")
+    with open(os.path.join(csrc, "k_push.hip"), "rb") as f:
+        h.update(f.read())
+    with open(os.path.join(csrc, "pic_internal.h"), "rb") as f:
+        h.update(f.read().split(b"// ---- launchers")[0])
     return h.hexdigest()[:16]
 
 
