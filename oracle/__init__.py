@@ -20,6 +20,9 @@ Particle-Mesh Algorithms with FPGAs and OmpSs@OpenCL"):
                            three-step Yee update of Listing 3.1
 * ``sort_canonical``    -- strict tile re-sort (Sec. 4.3, Fig. 4.5), with the
                            removed / appended particles of the moving window
+* ``sort_stable_by_tile`` -- particles in any order grouped into the tile
+                           sections of Sec. 4.1 (Fig. 4.3), keeping their order
+                           within a tile (numpy's stable sort, Python)
 * ``OracleSim.move_window`` -- the moving-window step of Listing 3.1
 * ``binomial_filter``   -- the optional current smoothing of Listing 3.1
 * ``rho`` / energies / divergences -- diagnostics (Eq. 17, Eq. 18, Eq. 12)
@@ -163,6 +166,22 @@ def sort_canonical(nx, ny, T, ix, iy, removed=None):
     if rc != 0:
         raise ValueError("cell index out of range")
     return off, src[:int(n_out[0])]
+
+
+def sort_stable_by_tile(nx, ny, T, ix, iy):
+    """Particles in any order grouped by tile (Sec. 4.1: the particles of a
+    tile occupy one section, sections in tile order, Fig. 4.3), the given
+    order kept inside each tile.  Tiles are numbered row-major.  Returns
+    (off[ntiles+1], src) with the grouped arrays = arrays[src]."""
+    ix = _i32(ix)
+    iy = _i32(iy)
+    if ix.size and (ix.min() < 0 or ix.max() >= nx or iy.min() < 0 or iy.max() >= ny):
+        raise ValueError("cell index out of range")
+    ntx = nx // T
+    tile = (iy // T).astype(np.int64) * ntx + ix // T
+    src = np.argsort(tile, kind="stable")
+    off = np.r_[0, np.cumsum(np.bincount(tile, minlength=ntx * (ny // T)))].astype(np.int64)
+    return off, src
 
 
 def rho(nx, ny, q, ix, iy, x, y, out=None) -> np.ndarray:

@@ -141,3 +141,34 @@ def test_sort_with_removal_brute_force_tiny(ora):
         o_off, o_src = ora.sort_canonical(nx, ny, T, ix, iy, removed=removed)
         assert o_off.tolist() == off.tolist()
         assert tuple(o_src.tolist()) == sols[0]
+
+
+def test_stable_grouping_by_tile(ora):
+    """sort_stable_by_tile is pinned by the properties that define it
+    uniquely: a permutation, tiles non-decreasing along the result, and
+    inside each tile the original indices increasing; offsets equal to the
+    tile histogram's prefix sums.  Brute force over every permutation of a
+    tiny input agrees."""
+    rng = np.random.default_rng(3)
+    for nx, ny, T, n in ((32, 16, 8, 500), (64, 64, 16, 3000), (16, 16, 16, 40)):
+        ix = rng.integers(0, nx, n).astype(np.int32)
+        iy = rng.integers(0, ny, n).astype(np.int32)
+        off, src = ora.sort_stable_by_tile(nx, ny, T, ix, iy)
+        assert sorted(src.tolist()) == list(range(n))
+        tile = (iy[src] // T) * (nx // T) + ix[src] // T
+        assert (np.diff(tile) >= 0).all()
+        same = np.diff(tile) == 0
+        assert (np.diff(src)[same] > 0).all()
+        counts = np.bincount((iy // T) * (nx // T) + ix // T, minlength=(nx // T) * (ny // T))
+        assert np.array_equal(off, np.r_[0, np.cumsum(counts)])
+    # brute force: the unique permutation with the defining properties
+    ix = np.array([9, 1, 12, 3, 9, 0], np.int32)
+    iy = np.array([2, 7, 0, 1, 6, 5], np.int32)
+    tile = (iy // 8) * 2 + ix // 8
+    ok = [p for p in itertools.permutations(range(6))
+          if all(tile[p[k]] < tile[p[k + 1]] or (tile[p[k]] == tile[p[k + 1]] and p[k] < p[k + 1])
+                 for k in range(5))]
+    assert len(ok) == 1
+    assert ora.sort_stable_by_tile(16, 8, 8, ix, iy)[1].tolist() == list(ok[0])
+    with pytest.raises(ValueError):
+        ora.sort_stable_by_tile(16, 8, 8, np.array([16], np.int32), np.array([0], np.int32))
