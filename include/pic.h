@@ -34,9 +34,10 @@
  *       cell  int32  ix | (iy << 16), 0 <= ix < nx, 0 <= iy < ny
  *       x, y  float  offset inside the cell, in cells, in [0, 1)
  *       ux, uy, uz  float  momentum u = gamma v (Eq. 2)
- *     Particles must be grouped by tile: tiles are tile x tile cells numbered
+ *     Particles are kept grouped by tile: tiles are tile x tile cells numbered
  *     row-major (t = (iy / tile) * (nx / tile) + ix / tile) and the particles
- *     of tile t occupy one contiguous section, sections in increasing t.
+ *     of tile t occupy one contiguous section, sections in increasing t
+ *     (pic_init and pic_set_state group particles given in any order).
  *     pic_sort() restores this order after every push (with sort_every = k
  *     > 1, after every k-th push: in between, a particle may be up to k - 1
  *     cells outside the tile whose section holds it).
@@ -168,12 +169,13 @@ int pic_query(const pic_config *cfg, pic_sizes *out);
 
 /*
  * Validate cfg (Courant condition Eq. 1, tile divisibility, sizes) and bind
- * the caller's buffers.  The caller has filled the particle arrays (grouped
- * by tile) and the E and B planes; J is overwritten by every push.  Builds
- * tile_offset for every species on the device, checks the tile grouping and
- * synchronises `stream`.  Returns PIC_EORDER if the particles are not grouped
- * by tile or a cell is out of range.  On success *out owns a host record
- * that pic_destroy() frees.
+ * the caller's buffers.  The caller has filled the particle arrays (in any
+ * order) and the E and B planes; J is overwritten by every push.  Groups the
+ * particles of every species by tile in place on the device if they are not
+ * yet (a stable sort on the tile id: inside a tile the given order is kept,
+ * so grouped input is left as it is), builds tile_offset and synchronises
+ * `stream`.  Returns PIC_EORDER if a cell is out of range.  On success *out
+ * owns a host record that pic_destroy() frees.
  */
 int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
              pic_sim **out);
@@ -326,21 +328,22 @@ typedef struct pic_host_state {
 /* Copy the field planes and the particles of every species (array columns)
  * to the caller's host arrays (a NULL array is skipped; the arrays hold the
  * current counts, pic_get_counts), set out->n and out->window_origin and
- * synchronise `stream`.  With sort_every > 1, call pic_sort() first if the
- * state is to be loaded again: pic_set_state() needs particles grouped by
- * tile. */
+ * synchronise `stream`.  With sort_every > 1 a state taken between two sorts
+ * holds particles outside their tile's section; pic_set_state() regroups
+ * them, so it resumes in a different (valid) slot order than a run that
+ * never stopped. */
 int pic_get_state(pic_sim *sim, pic_host_state *out, hipStream_t stream);
 
 /*
- * Load the field planes, the particles (in->n[s] of species s, grouped by
- * tile as for pic_init; array columns) and the window origin from host
- * arrays, rebuild tile_offset, forget the rho snapshot of pic_diag and
- * synchronise `stream`.  Every array must be given.  With
+ * Load the field planes, the particles (in->n[s] of species s, in any order,
+ * grouped by tile on the device as in pic_init; array columns) and the window
+ * origin from host arrays, rebuild tile_offset, forget the rho snapshot of
+ * pic_diag and synchronise `stream`.  Every array must be given.  With
  * PIC_FLAG_MOVING_WINDOW a count may be anything up to the species' capacity
  * and 0 <= origin < nx; without it the counts must be the current ones and
- * the origin 0 (else PIC_EINVAL, nothing loaded).  Returns PIC_EORDER if the
- * particles are not grouped by tile (the simulation then needs a valid state
- * before its next step).
+ * the origin 0 (else PIC_EINVAL, nothing loaded).  Returns PIC_EORDER if a
+ * cell is out of range (the simulation then needs a valid state before its
+ * next step).
  */
 int pic_set_state(pic_sim *sim, const pic_host_state *in, hipStream_t stream);
 

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 SO = os.path.join(HERE, "libpic.so")
 SOURCES = ["pic_api.hip", "k_push.hip", "k_sort.hip", "k_field.hip", "k_filter.hip", "k_window.hip", "k_diag.hip",
-           "k_poisson.hip"]
+           "k_poisson.hip", "k_tilesort.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

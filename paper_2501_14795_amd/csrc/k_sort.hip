@@ -422,7 +422,8 @@ __global__ void __launch_bounds__(kBlock) k_sort_scatter_b(const SortArgs *d, co
     sort_scatter_unit(d[w.x], w.y, w.z);
 }
 
-// ---- initial tile_offset from caller particles that are grouped by tile
+// ---- initial tile_offset from caller particles: counts, and whether they
+// are grouped by tile (kErrGroup) with every cell in the grid (kErrOrder)
 __global__ void k_init_count(const int32_t *__restrict__ cell, int32_t n, int nx, int ny, int tsh,
                              int ntx, int32_t *counts, int *err)
 {
@@ -439,7 +440,7 @@ __global__ void k_init_count(const int32_t *__restrict__ cell, int32_t n, int nx
     if (i + 1 < n) {
         const int c2 = cell[i + 1];
         const int t2 = ((c2 >> 16) >> tsh) * ntx + ((c2 & 0xffff) >> tsh);
-        if (c2 >= 0 && t2 < t) atomicOr(err, kErrOrder);
+        if (c2 >= 0 && t2 < t) atomicOr(err, kErrGroup);
     }
 }
 

@@ -204,16 +204,25 @@ struct Timed {
 
 int hip_ok(hipError_t e) { return e == hipSuccess ? PIC_OK : PIC_EHIP; }
 
-int read_errors(pic_sim *s, hipStream_t stream)
+// Synchronise `stream`, read and clear the device error bits into *h.
+int read_flags(pic_sim *s, hipStream_t stream, int *h)
 {
-    int h = 0;
-    if (hipMemcpyAsync(&h, s->err, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess) return PIC_EHIP;
+    *h = 0;
+    if (hipMemcpyAsync(h, s->err, sizeof(int), hipMemcpyDeviceToHost, stream) != hipSuccess) return PIC_EHIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return PIC_EHIP;
-    if (h) {
+    if (*h) {
         if (hipMemsetAsync(s->err, 0, sizeof(int), stream) != hipSuccess) return PIC_EHIP;
         if (hipStreamSynchronize(stream) != hipSuccess) return PIC_EHIP;
     }
-    if (h & kErrOrder) return PIC_EORDER;
+    return PIC_OK;
+}
+
+int read_errors(pic_sim *s, hipStream_t stream)
+{
+    int h = 0;
+    const int rc = read_flags(s, stream, &h);
+    if (rc) return rc;
+    if (h & (kErrOrder | kErrGroup)) return PIC_EORDER;
     if (h & kErrRange) return PIC_ERANGE;
     if (h & kErrCount) return PIC_ECOUNT;
     if (h & kErrSort) return PIC_ESORT;
@@ -439,20 +448,51 @@ namespace {
 
 // tile_offset of every species from its particle cells (which must be grouped
 // by tile); synchronises and reports PIC_EORDER / PIC_ECOUNT.
+// tile_offset of every species from its particles, grouping them by tile
+// first (stable radix sort on the device) if they arrive in another order.
+// PIC_EORDER if a cell is outside the grid.  The sort's scratch is the
+// per-particle workspace of the sort and the leaver copies, free before the
+// first push.
 int build_tiles(pic_sim *S, hipStream_t stream)
 {
     const pic_config &c = S->cfg;
     int rc = PIC_OK;
     for (int s = 0; s < c.n_species && rc == PIC_OK; ++s) {
         auto &P = S->sp[s];
-        // counts go through the cnt record area, which the next push overwrites
-        rc = hip_ok(hipMemsetAsync(P.cnt, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
-        if (rc) break;
-        launch_init_tiles(S->buf.sp[s].cell, (int32_t)c.species[s].n, c.nx, c.ny, c.tile, S->ntx, P.cnt,
-                          S->n_tiles, P.off, S->err, stream);
-        rc = hip_ok(hipMemsetAsync(P.mcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
+        const int n = (int)c.species[s].n;
+        for (int attempt = 0; attempt < 2 && rc == PIC_OK; ++attempt) {
+            // counts go through the cnt record area, which the next push overwrites
+            rc = hip_ok(hipMemsetAsync(P.cnt, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
+            if (rc) break;
+            launch_init_tiles(S->buf.sp[s].cell, n, c.nx, c.ny, c.tile, S->ntx, P.cnt, S->n_tiles, P.off, S->err,
+                              stream);
+            rc = hip_ok(hipGetLastError());
+            int h = 0;
+            if (rc == PIC_OK) rc = read_flags(S, stream, &h);
+            if (rc) break;
+            if (h & kErrOrder) return PIC_EORDER;
+            if (!(h & kErrGroup)) break;
+            if (attempt == 1) return PIC_ESORT;   // still not grouped after the sort
+            TileSortArgs t;
+            t.p = Parts{S->buf.sp[s].cell, S->buf.sp[s].x, S->buf.sp[s].y, S->buf.sp[s].ux, S->buf.sp[s].uy,
+                        S->buf.sp[s].uz};
+            t.tmp = P.lp;
+            t.key[0] = (uint32_t *)P.hole;
+            t.key[1] = P.leav;
+            t.val[0] = (uint32_t *)P.stg.cell;
+            t.val[1] = (uint32_t *)P.stg.x;
+            // the histogram: in the leaver copies' cell array when it is large
+            // enough (n >= 16384), else in the tile current halos
+            t.hist = tile_sort_hist_entries(n) <= n ? P.lp.cell : (int32_t *)S->jtile;
+            t.n = n;
+            t.tile = c.tile;
+            t.ntx = S->ntx;
+            t.n_tiles = S->n_tiles;
+            launch_tile_sort(t, stream);
+            rc = hip_ok(hipGetLastError());
+        }
+        if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(P.mcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
     }
-    if (rc == PIC_OK) rc = hip_ok(hipGetLastError());
     if (rc == PIC_OK) rc = read_errors(S, stream);
     return rc;
 }

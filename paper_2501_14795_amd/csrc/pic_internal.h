@@ -39,6 +39,7 @@ enum : int {
     kErrSort = 4,    // hole / mover count mismatch
     kErrCount = 8,   // tile counts do not sum to n
     kErrOverflow = 16, // a fixed-point current accumulator took 2^16 contributions or more
+    kErrGroup = 32,  // caller particles not grouped by tile (cells in range)
 };
 
 // Current accumulation modes of the push kernel.
@@ -205,6 +206,17 @@ struct SortBatch {
 void launch_sort_batch(const SortBatch &b, hipStream_t s);
 void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile, int ntx,
                        int32_t *counts, int n_tiles, int32_t *off, int *err, hipStream_t s);
+// grouping caller particles by tile: stable radix sort on the tile id
+// (k_tilesort.hip), in place on p
+struct TileSortArgs {
+    Parts p;                     // n each: the particle arrays
+    Parts tmp;                   // n each: a copy of them is made here
+    uint32_t *key[2], *val[2];   // n each: double buffers
+    int32_t *hist;               // tile_sort_hist_entries(n)
+    int n, tile, ntx, n_tiles;
+};
+int64_t tile_sort_hist_entries(int n);
+void launch_tile_sort(const TileSortArgs &a, hipStream_t s);
 // moving window (window column i lives in array column (i + origin) mod nx):
 // E and B of array column col become zero
 void launch_zero_column(float *fld, int nx, int ny, int col, hipStream_t s);

@@ -157,10 +157,19 @@ def test_state_round_trip_and_resume():
     for a in ref["species"][0]:
         assert np.array_equal(out2["species"][0][a], ref["species"][0][a]), a
     assert sim.check() == 0 and sim2.check() == 0
-    # particles not grouped by tile: rejected
-    bad = {"fields": ck["fields"], "species": [{k: v[::-1].copy() for k, v in ck["species"][0].items()}]}
+    # particles not grouped by tile: grouped on load (stable), as the oracle does
+    rev = {k: v[::-1].copy() for k, v in ck["species"][0].items()}
+    sim2.set_state({"fields": ck["fields"], "species": [rev]})
+    ix, iy = rev["cell"] & 0xFFFF, rev["cell"] >> 16
+    _, src = oracle.sort_stable_by_tile(sim2.nx, sim2.ny, 16, ix, iy)
+    got = sim2.get_state()["species"][0]
+    for a in rev:
+        assert np.array_equal(got[a], rev[a][src]), a
+    # a cell outside the grid: rejected
+    bad = {k: v.copy() for k, v in ck["species"][0].items()}
+    bad["cell"][7] = sim2.nx + 3
     with pytest.raises(_lib.PicError) as e:
-        sim2.set_state(bad)
+        sim2.set_state({"fields": ck["fields"], "species": [bad]})
     assert e.value.code == _lib.PIC_EORDER
     sim2.set_state(ck)
     sim2.step()

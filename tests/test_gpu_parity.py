@@ -236,13 +236,9 @@ def test_empty_species_and_zero_particles():
     sim.close()
 
 
-def test_init_rejects_particles_not_grouped_by_tile():
+def test_init_rejects_cells_outside_the_grid():
     from paper_2501_14795_amd import PicError, Sim, _lib
     specs, states, _, _ = _uniform(nx=32, ny=32, ppc=(1, 1), seed=10)
-    st = {k: v[::-1].copy() for k, v in states[0].items()}
-    with pytest.raises(PicError) as e:
-        Sim(32, 32, DX, DY, DT, 16, [(-1.0, -1.0, st)])
-    assert e.value.code == _lib.PIC_EORDER
     st = {k: v.copy() for k, v in states[0].items()}
     st["ix"][3] = 40   # out of the grid
     with pytest.raises(PicError) as e:
