@@ -277,7 +277,8 @@ class Sim(_SimView):
     """One simulation that owns its device buffers.
 
     species: list of (qm, q, state) where state is a dict of numpy arrays
-    ix, iy (int32), x, y, ux, uy, uz (float32), grouped by tile."""
+    ix, iy (int32), x, y, ux, uy, uz (float32), in any order (pic_init groups
+    them by tile)."""
 
     def __init__(self, nx: int, ny: int, dx: float, dy: float, dt: float, tile: int,
                  species: Sequence, E: Optional[np.ndarray] = None, B: Optional[np.ndarray] = None,
