@@ -165,17 +165,17 @@ def filter_measurement(w, launches=20):
             "achieved": nbytes / (ms * 1e-3) / 1e9, "unit": "GB/s", "frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
 
-def esirkepov_measurement(w, T, steps=20, warmup=3):
-    """The same workload and step with the Esirkepov deposit (the variant
-    deposit): whole-step rate and the push kernel's event-timed duration."""
+def variant_measurement(w, T, steps=20, warmup=3, **options):
+    """The same workload and step with a library option (the Esirkepov
+    deposit, the full re-sort, ...): whole-step rate and the event-timed
+    kernel durations per step."""
     import torch
 
     import pic_workloads as pw
     from paper_2501_14795_amd import Sim
     states = pw.workload_state(w, tile=T)
     n = sum(s["ix"].size for s in states)
-    sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, T, [(s.qm, s.q, st) for s, st in zip(w.species, states)],
-              esirkepov=True)
+    sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, T, [(s.qm, s.q, st) for s, st in zip(w.species, states)], **options)
     del states
     for _ in range(warmup):
         sim.step()
@@ -191,10 +191,10 @@ def esirkepov_measurement(w, T, steps=20, warmup=3):
     rc = sim.check()
     sim.close()
     if rc != 0:
-        raise SystemExit("device error in the Esirkepov measurement")
-    push_ms = kt["push"][0] / max(kt["push"][1], 1)
-    return {"workload": w.name, "steps": steps, "pushes_per_s": n * steps / elapsed,
-            "ms_per_step": elapsed * 1e3 / steps, "push_kernel_ms": push_ms}
+        raise SystemExit(f"device error in the {options} measurement")
+    return {"workload": w.name, "tile": T, "options": options, "steps": steps,
+            "pushes_per_s": n * steps / elapsed, "ms_per_step": elapsed * 1e3 / steps,
+            "kernel_ms_per_step": {k: v[0] / steps for k, v in kt.items()}}
 
 
 def window_measurement(w, T, moves=20, warmup=3, n_columns=4):
@@ -382,8 +382,10 @@ def main():
         out["filter_pass"] = filter_measurement(w)
         log(f"filter pass: {out['filter_pass']}")
         if not args.esirkepov:
-            out["esirkepov"] = esirkepov_measurement(w, T)
+            out["esirkepov"] = variant_measurement(w, T, esirkepov=True)
             log(f"esirkepov: {out['esirkepov']}")
+        out["full_sort"] = variant_measurement(w, T, full_sort=True)
+        log(f"full re-sort: {out['full_sort']}")
         out["moving_window"] = window_measurement(w, T)
         log(f"moving window: {out['moving_window']}")
     if not args.no_batched:

@@ -105,6 +105,17 @@ extern "C" {
 #define PIC_FLAG_MOVING_WINDOW 4u
 
 /*
+ * Alternative sort (pic_config.flags; the full re-sort the paper cites as the
+ * other way to keep particles grouped, Sec. 4.3): pic_sort() regroups every
+ * species out of place by a stable radix sort on the tile id (the order
+ * inside a tile kept) instead of moving only the particles that left their
+ * section.  It reads and writes every particle, so it pays only when most
+ * particles move; the autotuner and the bench compare the two.  Not in
+ * batched mode.  pic_diag's mover count is 0 with it.
+ */
+#define PIC_FLAG_FULL_SORT 8u
+
+/*
  * Binomial current filter (pic_config.j_filter; Listing 3.1's optional
  * smoothing of J after update_gc_add).  Each pass smooths every J component
  * with the three-point kernel (1/4, 1/2, 1/4) along x, then along y, on the
@@ -129,7 +140,8 @@ typedef struct pic_config {
     int32_t tile;        /* tile edge in cells: 8, 16 or 32 */
     int32_t j_replicas;  /* LDS current replicas per tile: 1, 2 or 4 (0 = default) */
     int32_t n_species;   /* 1 .. PIC_MAX_SPECIES */
-    uint32_t flags;      /* PIC_FLAG_J_FLOAT, PIC_FLAG_ESIRKEPOV, PIC_FLAG_MOVING_WINDOW or 0 */
+    uint32_t flags;      /* OR of PIC_FLAG_J_FLOAT, PIC_FLAG_ESIRKEPOV, PIC_FLAG_MOVING_WINDOW,
+                            PIC_FLAG_FULL_SORT, or 0 */
     int32_t j_filter;    /* binomial current filter passes, 0 (off) .. PIC_MAX_FILTER */
     int32_t sort_every;  /* sort cadence k = 1, 2 or 4 (0: 1): pic_step sorts every
                             k-th step and the push stages a halo k cells wide.  k > 1

@@ -422,10 +422,12 @@ __global__ void __launch_bounds__(kBlock) k_sort_scatter_b(const SortArgs *d, co
     sort_scatter_unit(d[w.x], w.y, w.z);
 }
 
-// ---- initial tile_offset from caller particles: counts, and whether they
-// are grouped by tile (kErrGroup) with every cell in the grid (kErrOrder)
-__global__ void k_init_count(const int32_t *__restrict__ cell, int32_t n, int nx, int ny, int tsh,
-                             int ntx, int32_t *counts, int *err)
+// ---- tile_offset from caller particles: whether every cell is in the grid
+// (kErrOrder) and the cells are grouped by tile (kErrGroup), then, for
+// grouped cells, off[t] = the first slot whose tile is >= t (a binary search
+// per tile: no atomics, so many particles per tile cost nothing extra)
+__global__ void k_init_check(const int32_t *__restrict__ cell, int32_t n, int nx, int ny, int tsh, int ntx,
+                             int *err)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -435,32 +437,28 @@ __global__ void k_init_count(const int32_t *__restrict__ cell, int32_t n, int nx
         atomicOr(err, kErrOrder);
         return;
     }
-    const int t = (iy >> tsh) * ntx + (ix >> tsh);
-    atomicAdd(&counts[t], 1);
     if (i + 1 < n) {
         const int c2 = cell[i + 1];
+        const int t = (iy >> tsh) * ntx + (ix >> tsh);
         const int t2 = ((c2 >> 16) >> tsh) * ntx + ((c2 & 0xffff) >> tsh);
         if (c2 >= 0 && t2 < t) atomicOr(err, kErrGroup);
     }
 }
 
-__global__ void __launch_bounds__(1024) k_init_scan(const int32_t *counts, int n_tiles, int32_t *off,
-                                                     int32_t n, int *err)
+__global__ void k_init_offsets(const int32_t *__restrict__ cell, int32_t n, int tsh, int ntx, int n_tiles,
+                               int32_t *__restrict__ off)
 {
-    const int per = (n_tiles + 1023) / 1024;
-    const int t0 = min((int)threadIdx.x * per, n_tiles), t1 = min(t0 + per, n_tiles);
-    int sum = 0;
-    for (int t = t0; t < t1; ++t) sum += counts[t];
-    int total;
-    int base = block_exclusive_scan_1024(sum, &total);
-    for (int t = t0; t < t1; ++t) {
-        off[t] = base;
-        base += counts[t];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > n_tiles) return;
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = lo + ((hi - lo) >> 1);
+        const int c = cell[mid];
+        const int tm = c < 0 ? -1 : ((c >> 16) >> tsh) * ntx + ((c & 0xffff) >> tsh);
+        if (tm < t) lo = mid + 1;
+        else hi = mid;
     }
-    if (threadIdx.x == 0) {
-        off[n_tiles] = total;
-        if (total != n) atomicOr(err, kErrOrder);
-    }
+    off[t] = lo;
 }
 
 void launch_sort_scan(const SortArgs &a, int n_tiles, hipStream_t s)
@@ -493,14 +491,14 @@ void launch_sort_batch(const SortBatch &b, hipStream_t s)
     hipLaunchKernelGGL(k_sort_scatter_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
 }
 
-void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile, int ntx, int32_t *counts,
-                       int n_tiles, int32_t *off, int *err, hipStream_t s)
+void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile, int ntx, int n_tiles, int32_t *off,
+                       int *err, hipStream_t s)
 {
     const int tsh = __builtin_ctz(tile);
     if (n > 0)
-        hipLaunchKernelGGL(k_init_count, dim3((n + 255) / 256), dim3(256), 0, s, cell, n, nx, ny, tsh, ntx,
-                           counts, err);
-    hipLaunchKernelGGL(k_init_scan, dim3(1), dim3(1024), 0, s, counts, n_tiles, off, n, err);
+        hipLaunchKernelGGL(k_init_check, dim3((n + 255) / 256), dim3(256), 0, s, cell, n, nx, ny, tsh, ntx, err);
+    hipLaunchKernelGGL(k_init_offsets, dim3((n_tiles + 1 + 255) / 256), dim3(256), 0, s, cell, n, tsh, ntx, n_tiles,
+                       off);
 }
 
 }  // namespace pic

@@ -3,7 +3,9 @@
 // arrive in any order: a stable least-significant-digit radix sort on the
 // tile id, 8 bits per pass, then a gather of the six particle arrays.
 // Stability keeps the given order inside a tile, so already grouped input is
-// left as it is.  Runs at initialisation and state loads only.
+// left as it is.  Runs at initialisation and state loads, and after every
+// push as the full re-sort of PIC_FLAG_FULL_SORT (the alternative to the
+// in-place sort, which moves only the particles that left their section).
 //
 // One pass over n keys, in chunks of kTsChunk consecutive keys per
 // workgroup:
@@ -177,10 +179,10 @@ int64_t tile_sort_hist_entries(int n)
     return len + (len + 1023) / 1024;
 }
 
-void launch_tile_sort(const TileSortArgs &a, hipStream_t s)
+const uint32_t *launch_tile_sort_perm(const TileSortArgs &a, hipStream_t s)
 {
     const int n = a.n;
-    if (n <= 1 || a.n_tiles <= 1) return;
+    if (n <= 1 || a.n_tiles <= 1) return nullptr;
     const int tsh = __builtin_ctz(a.tile);
     int bits = 0;
     while ((1 << bits) < a.n_tiles) ++bits;
@@ -204,7 +206,14 @@ void launch_tile_sort(const TileSortArgs &a, hipStream_t s)
         vin = vout;
         vout = t;
     }
-    // vin: the permutation; copy the particles aside and gather them back
+    return vin;
+}
+
+void launch_tile_sort_gather(const TileSortArgs &a, const uint32_t *perm, hipStream_t s)
+{
+    const int n = a.n;
+    if (!perm || n <= 1) return;
+    // copy the particles aside and gather them back in the new order
     const size_t bytes = (size_t)n * 4;
     (void)hipMemcpyAsync(a.tmp.cell, a.p.cell, bytes, hipMemcpyDeviceToDevice, s);
     (void)hipMemcpyAsync(a.tmp.x, a.p.x, bytes, hipMemcpyDeviceToDevice, s);
@@ -212,7 +221,12 @@ void launch_tile_sort(const TileSortArgs &a, hipStream_t s)
     (void)hipMemcpyAsync(a.tmp.ux, a.p.ux, bytes, hipMemcpyDeviceToDevice, s);
     (void)hipMemcpyAsync(a.tmp.uy, a.p.uy, bytes, hipMemcpyDeviceToDevice, s);
     (void)hipMemcpyAsync(a.tmp.uz, a.p.uz, bytes, hipMemcpyDeviceToDevice, s);
-    hipLaunchKernelGGL(k_ts_gather, dim3((n + 255) / 256), dim3(256), 0, s, a.p, a.tmp, vin, n);
+    hipLaunchKernelGGL(k_ts_gather, dim3((n + 255) / 256), dim3(256), 0, s, a.p, a.tmp, perm, n);
+}
+
+void launch_tile_sort(const TileSortArgs &a, hipStream_t s)
+{
+    launch_tile_sort_gather(a, launch_tile_sort_perm(a, s), s);
 }
 
 }  // namespace pic

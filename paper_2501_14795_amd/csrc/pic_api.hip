@@ -41,7 +41,8 @@ int default_replicas(const pic_config *c)
 int validate(const pic_config *c)
 {
     if (!c) return PIC_EINVAL;
-    if (c->flags & ~(uint32_t)(PIC_FLAG_J_FLOAT | PIC_FLAG_ESIRKEPOV | PIC_FLAG_MOVING_WINDOW)) return PIC_EINVAL;
+    if (c->flags & ~(uint32_t)(PIC_FLAG_J_FLOAT | PIC_FLAG_ESIRKEPOV | PIC_FLAG_MOVING_WINDOW | PIC_FLAG_FULL_SORT))
+        return PIC_EINVAL;
     // the Esirkepov deposit is built for the fixed-point current only
     if ((c->flags & PIC_FLAG_ESIRKEPOV) && (c->flags & PIC_FLAG_J_FLOAT)) return PIC_EINVAL;
     if (c->tile != 8 && c->tile != 16 && c->tile != 32) return PIC_ETILE;
@@ -448,6 +449,31 @@ namespace {
 
 // tile_offset of every species from its particle cells (which must be grouped
 // by tile); synchronises and reports PIC_EORDER / PIC_ECOUNT.
+// The stable radix regrouping of species s, on the per-particle scratch of
+// the in-place sort and the leaver copies (free at initialisation, and after a
+// push when the full re-sort replaces the in-place one) and, for the
+// histogram, the leaver copies' cell array (n >= its size) or the tile
+// current halos (consumed by then).
+TileSortArgs tile_sort_args(pic_sim *S, int s)
+{
+    auto &P = S->sp[s];
+    const pic_particles &b = S->buf.sp[s];
+    const int n = (int)S->cfg.species[s].n;
+    TileSortArgs t;
+    t.p = Parts{b.cell, b.x, b.y, b.ux, b.uy, b.uz};
+    t.tmp = P.lp;
+    t.key[0] = (uint32_t *)P.hole;
+    t.key[1] = P.leav;
+    t.val[0] = (uint32_t *)P.stg.cell;
+    t.val[1] = (uint32_t *)P.stg.x;
+    t.hist = tile_sort_hist_entries(n) <= n ? P.lp.cell : (int32_t *)S->jtile;
+    t.n = n;
+    t.tile = S->cfg.tile;
+    t.ntx = S->ntx;
+    t.n_tiles = S->n_tiles;
+    return t;
+}
+
 // tile_offset of every species from its particles, grouping them by tile
 // first (stable radix sort on the device) if they arrive in another order.
 // PIC_EORDER if a cell is outside the grid.  The sort's scratch is the
@@ -461,11 +487,7 @@ int build_tiles(pic_sim *S, hipStream_t stream)
         auto &P = S->sp[s];
         const int n = (int)c.species[s].n;
         for (int attempt = 0; attempt < 2 && rc == PIC_OK; ++attempt) {
-            // counts go through the cnt record area, which the next push overwrites
-            rc = hip_ok(hipMemsetAsync(P.cnt, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
-            if (rc) break;
-            launch_init_tiles(S->buf.sp[s].cell, n, c.nx, c.ny, c.tile, S->ntx, P.cnt, S->n_tiles, P.off, S->err,
-                              stream);
+            launch_init_tiles(S->buf.sp[s].cell, n, c.nx, c.ny, c.tile, S->ntx, S->n_tiles, P.off, S->err, stream);
             rc = hip_ok(hipGetLastError());
             int h = 0;
             if (rc == PIC_OK) rc = read_flags(S, stream, &h);
@@ -473,22 +495,7 @@ int build_tiles(pic_sim *S, hipStream_t stream)
             if (h & kErrOrder) return PIC_EORDER;
             if (!(h & kErrGroup)) break;
             if (attempt == 1) return PIC_ESORT;   // still not grouped after the sort
-            TileSortArgs t;
-            t.p = Parts{S->buf.sp[s].cell, S->buf.sp[s].x, S->buf.sp[s].y, S->buf.sp[s].ux, S->buf.sp[s].uy,
-                        S->buf.sp[s].uz};
-            t.tmp = P.lp;
-            t.key[0] = (uint32_t *)P.hole;
-            t.key[1] = P.leav;
-            t.val[0] = (uint32_t *)P.stg.cell;
-            t.val[1] = (uint32_t *)P.stg.x;
-            // the histogram: in the leaver copies' cell array when it is large
-            // enough (n >= 16384), else in the tile current halos
-            t.hist = tile_sort_hist_entries(n) <= n ? P.lp.cell : (int32_t *)S->jtile;
-            t.n = n;
-            t.tile = c.tile;
-            t.ntx = S->ntx;
-            t.n_tiles = S->n_tiles;
-            launch_tile_sort(t, stream);
+            launch_tile_sort(tile_sort_args(S, s), stream);
             rc = hip_ok(hipGetLastError());
         }
         if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(P.mcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
@@ -595,11 +602,43 @@ int pic_push_deposit(pic_sim *S, hipStream_t stream)
     return hip_ok(hipGetLastError());
 }
 
+// The alternative sort (PIC_FLAG_FULL_SORT): every species regrouped by the
+// stable radix sort on the tile id, then tile_offset rebuilt from the
+// grouped cells (which also re-checks the grouping: PIC_EORDER through
+// pic_check if it failed).  Timed as plan (radix passes), scatter (gather)
+// and scan (offsets).
+static int full_sort(pic_sim *S, hipStream_t stream)
+{
+    const pic_config &c = S->cfg;
+    int rc = PIC_OK;
+    for (int s = 0; s < c.n_species && rc == PIC_OK; ++s) {
+        auto &P = S->sp[s];
+        const TileSortArgs t = tile_sort_args(S, s);
+        const uint32_t *perm;
+        {
+            Timed tm(S, PIC_KERNEL_SORT_PLAN, stream);
+            perm = launch_tile_sort_perm(t, stream);
+        }
+        {
+            Timed tm(S, PIC_KERNEL_SORT_SCATTER, stream);
+            launch_tile_sort_gather(t, perm, stream);
+        }
+        {
+            Timed tm(S, PIC_KERNEL_SORT_SCAN, stream);
+            launch_init_tiles(t.p.cell, t.n, c.nx, c.ny, c.tile, S->ntx, S->n_tiles, P.off, S->err, stream);
+        }
+        if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(P.mcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
+    }
+    if (rc == PIC_OK) rc = hip_ok(hipGetLastError());
+    return rc;
+}
+
 int pic_sort(pic_sim *S, hipStream_t stream)
 {
     if (!S) return PIC_EINVAL;
     if (S->since_sort == 0) return PIC_OK;   // already sorted: the count records are spent
     S->since_sort = 0;
+    if (S->cfg.flags & PIC_FLAG_FULL_SORT) return full_sort(S, stream);
     const SortArgs a = sort_args(S);
     {
         Timed t(S, PIC_KERNEL_SORT_SCAN, stream);
@@ -657,10 +696,9 @@ int pic_move_window(pic_sim *S, const pic_particles *inject, const int64_t *n_in
         for (int f = 0; f < 5 && rc == PIC_OK; ++f)
             rc = hip_ok(hipMemcpyAsync(dst[f], src[f], bytes, hipMemcpyDeviceToDevice, stream));
         if (rc) break;
-        launch_zero_i32(P.mcount, S->n_tiles, stream);
         launch_place_new(q.cell, p.cell + n0, (int)k[s], c.nx, c.ny, col, S->err, stream);
-        launch_init_tiles(p.cell + n0, (int32_t)k[s], c.nx, c.ny, c.tile, S->ntx, P.mcount, S->n_tiles, P.inj_off,
-                          S->err, stream);
+        launch_init_tiles(p.cell + n0, (int32_t)k[s], c.nx, c.ny, c.tile, S->ntx, S->n_tiles, P.inj_off, S->err,
+                          stream);
         a.sp[s].inj_off = P.inj_off;
         a.sp[s].inj_n = (int32_t)k[s];
     }
@@ -1002,6 +1040,7 @@ int batch_validate(int n, const pic_config *cfgs)
             halo_of(&cfgs[i]) != halo_of(&cfgs[0]))
             return PIC_EINVAL;
         if (cfgs[i].flags & PIC_FLAG_MOVING_WINDOW) return PIC_EINVAL;   // member counts are fixed
+        if (cfgs[i].flags & PIC_FLAG_FULL_SORT) return PIC_EINVAL;       // the graph holds the in-place sort
     }
     return PIC_OK;
 }

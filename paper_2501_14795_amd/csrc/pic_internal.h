@@ -204,8 +204,11 @@ struct SortBatch {
     const int4 *plan_items; int n_plan;
 };
 void launch_sort_batch(const SortBatch &b, hipStream_t s);
-void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile, int ntx,
-                       int32_t *counts, int n_tiles, int32_t *off, int *err, hipStream_t s);
+// tile_offset (off, n_tiles + 1) of n cells grouped by tile; sets kErrOrder
+// for a cell outside the grid and kErrGroup if they are not grouped (off is
+// then meaningless but every write stays inside it)
+void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile, int ntx, int n_tiles, int32_t *off,
+                       int *err, hipStream_t s);
 // grouping caller particles by tile: stable radix sort on the tile id
 // (k_tilesort.hip), in place on p
 struct TileSortArgs {
@@ -217,6 +220,10 @@ struct TileSortArgs {
 };
 int64_t tile_sort_hist_entries(int n);
 void launch_tile_sort(const TileSortArgs &a, hipStream_t s);
+// the two phases: the permutation (radix passes; null if nothing to sort),
+// then the gather of the particle arrays through tmp
+const uint32_t *launch_tile_sort_perm(const TileSortArgs &a, hipStream_t s);
+void launch_tile_sort_gather(const TileSortArgs &a, const uint32_t *perm, hipStream_t s);
 // moving window (window column i lives in array column (i + origin) mod nx):
 // E and B of array column col become zero
 void launch_zero_column(float *fld, int nx, int ny, int col, hipStream_t s);

@@ -37,7 +37,7 @@ class _Buffers:
 
     def __init__(self, nx, ny, dx, dy, dt, tile, species, E=None, B=None, j_replicas=0, j_float=False,
                  device="cuda:0", j_filter=0, esirkepov=False, moving_window=False, capacity=None,
-                 sort_every=1):
+                 sort_every=1, full_sort=False):
         torch = _torch()
         if not 1 <= len(species) <= _lib.MAX_SPECIES:
             raise ValueError("1..4 species")
@@ -48,7 +48,7 @@ class _Buffers:
         cfg.j_replicas = int(j_replicas)
         cfg.n_species = len(species)
         cfg.flags = ((_lib.PIC_FLAG_J_FLOAT if j_float else 0) | (_lib.PIC_FLAG_ESIRKEPOV if esirkepov else 0) |
-                     (_lib.PIC_FLAG_MOVING_WINDOW if moving_window else 0))
+                     (_lib.PIC_FLAG_MOVING_WINDOW if moving_window else 0) | (_lib.PIC_FLAG_FULL_SORT if full_sort else 0))
         cfg.j_filter = int(j_filter)
         cfg.sort_every = int(sort_every)
         for k, (qm, q, st) in enumerate(species):
@@ -284,12 +284,12 @@ class Sim(_SimView):
                  species: Sequence, E: Optional[np.ndarray] = None, B: Optional[np.ndarray] = None,
                  j_replicas: int = 0, j_float: bool = False, device: str = "cuda:0", stream=None,
                  j_filter: int = 0, esirkepov: bool = False, moving_window: bool = False, capacity=None,
-                 sort_every: int = 1):
+                 sort_every: int = 1, full_sort: bool = False):
         torch = _torch()
         self.handle = None
         self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
         self.buf = _Buffers(nx, ny, dx, dy, dt, tile, species, E, B, j_replicas, j_float, device, j_filter,
-                            esirkepov, moving_window, capacity, sort_every)
+                            esirkepov, moving_window, capacity, sort_every, full_sort)
         self.cfg = self.buf.cfg
         torch.cuda.synchronize(torch.device(device))
         self.handle = _lib.pic_init(self.cfg, self.buf.bufs, self.s)

@@ -92,7 +92,7 @@ def test_query_sizes_and_validation():
         (dict(ns=0), L.PIC_EINVAL),
         (dict(ns=5), L.PIC_EINVAL),
         (dict(reps=3), L.PIC_EINVAL),
-        (dict(flags=8), L.PIC_EINVAL),
+        (dict(flags=16), L.PIC_EINVAL),
         (dict(flags=3), L.PIC_EINVAL),          # Esirkepov needs the fixed-point current
         (dict(nx=64, tile=32, reps=4), L.PIC_EINVAL),   # int64 current x 4 replicas > LDS
         (dict(n=-1), L.PIC_EINVAL),
@@ -122,6 +122,8 @@ def test_query_sizes_and_validation():
     with pytest.raises(L.PicError):   # 16 wavefronts per 32 x 32 tile leave no room for 4 FP32 replicas
         L.pic_query(_cfg(L, nx=64, tile=32, reps=4, flags=L.PIC_FLAG_J_FLOAT))
     assert L.pic_query(_cfg(L, flags=L.PIC_FLAG_ESIRKEPOV)).work_bytes == s.work_bytes
+    # the full re-sort works in the in-place sort's scratch: no extra workspace
+    assert L.pic_query(_cfg(L, flags=L.PIC_FLAG_FULL_SORT)).work_bytes == s.work_bytes
     # capacity: per-particle scratch sized for it; below n is invalid
     c = _cfg(L)
     c.species[0].cap = 2000
@@ -165,7 +167,8 @@ def test_batch_query_validation():
     for bad in ([_cfg(L), _cfg(L, tile=8)], [_cfg(L), _cfg(L, flags=L.PIC_FLAG_J_FLOAT)],
                 [_cfg(L), _cfg(L, reps=2)], [_cfg(L), _cfg(L, filt=1)],
                 [_cfg(L), _cfg(L, flags=L.PIC_FLAG_ESIRKEPOV)],
-                [_cfg(L, flags=L.PIC_FLAG_MOVING_WINDOW)]):
+                [_cfg(L, flags=L.PIC_FLAG_MOVING_WINDOW)], [_cfg(L, flags=L.PIC_FLAG_FULL_SORT)],
+                [_cfg(L), _cfg(L, every=2)]):
         with pytest.raises(L.PicError) as e:
             L.pic_batch_query(bad)
         assert e.value.code == L.PIC_EINVAL
