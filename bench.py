@@ -396,15 +396,14 @@ def main():
 
 def _kernel_sha():
     """Hash of what the push kernel is compiled from: k_push.hip and the
-    constants and structures of pic_internal.h (the part before its launcher
-    declarations, which other kernels extend)."""
+    definitions it shares, pic_push.h (pic_internal.h adds only launcher
+    declarations and other kernels' structures to them)."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2501_14795_amd", "csrc")
-    with open(os.path.join(csrc, "k_push.hip"), "rb") as f:
-        h.update(f.read())
-    with open(os.path.join(csrc, "pic_internal.h"), "rb") as f:
-        h.update(f.read().split(b"// ---- launchers")[0])
+    for name in ("k_push.hip", "pic_push.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
