@@ -380,6 +380,11 @@ typedef struct pic_timing_out {
 /* enable = 1: record HIP events around every launch from now on; 0: stop. Resets the sums. */
 int pic_set_timing(pic_sim *sim, int enable);
 
+/* Like pic_set_timing, for the kernels whose bit (1 << PIC_KERNEL_*) is set
+ * in mask only (0: stop): every event pair adds a little time to the step,
+ * so a throughput run times just the kernel it reports. */
+int pic_set_timing_mask(pic_sim *sim, unsigned mask);
+
 /* Synchronise on the recorded events and return the sums since the last reset. */
 int pic_get_timing(pic_sim *sim, pic_timing_out *out);
 

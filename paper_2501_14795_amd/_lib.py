@@ -43,7 +43,7 @@ EXPORTS = [
     "pic_query", "pic_init", "pic_push_deposit", "pic_sort", "pic_field_advance", "pic_move_window",
     "pic_get_window_origin", "pic_get_counts", "pic_solve_gauss", "pic_step",
     "pic_check", "pic_diag", "pic_get_state", "pic_set_state", "pic_get_tile_offsets",
-    "pic_set_timing", "pic_get_timing",
+    "pic_set_timing", "pic_set_timing_mask", "pic_get_timing",
     "pic_batch_query", "pic_batch_init", "pic_batch_step", "pic_batch_capture", "pic_batch_sim",
     "pic_batch_check", "pic_batch_destroy",
     "pic_strerror", "pic_destroy",
@@ -135,6 +135,7 @@ def load(path: str = SO_PATH):
     L.pic_solve_gauss.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int, P(pic_gauss_out), vp]
     L.pic_set_state.argtypes = [vp, P(pic_host_state), vp]
     L.pic_set_timing.argtypes = [vp, ctypes.c_int]
+    L.pic_set_timing_mask.argtypes = [vp, ctypes.c_uint]
     L.pic_get_timing.argtypes = [vp, P(pic_timing_out)]
     L.pic_strerror.argtypes = [ctypes.c_int]
     L.pic_strerror.restype = ctypes.c_char_p
@@ -260,6 +261,14 @@ def pic_get_tile_offsets(sim: int, species: int, n_tiles: int, stream: int):
 
 def pic_set_timing(sim: int, enable: bool):
     _chk(load().pic_set_timing(ctypes.c_void_p(sim), 1 if enable else 0), "pic_set_timing")
+
+
+def pic_set_timing_mask(sim: int, kernels):
+    """Time only the named kernels (names from KERNELS); an empty list stops."""
+    mask = 0
+    for name in kernels:
+        mask |= 1 << KERNELS.index(name)
+    _chk(load().pic_set_timing_mask(ctypes.c_void_p(sim), mask), "pic_set_timing_mask")
 
 
 def pic_get_timing(sim: int) -> pic_timing_out:

@@ -156,6 +156,7 @@ struct pic_sim {
     } sp[kMaxSpecies];
     // timing
     bool timing;
+    unsigned timing_mask;   // kernels timed while timing is on (bit PIC_KERNEL_*)
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[PIC_N_KERNELS];
     double ms[PIC_N_KERNELS];
@@ -184,7 +185,7 @@ struct Timed {
     hipEvent_t a = nullptr;
     Timed(pic_sim *sim, int kernel, hipStream_t stream) : s(sim), k(kernel), st(stream)
     {
-        if (s->timing) {
+        if (s->timing && ((s->timing_mask >> k) & 1u)) {
             a = take_event(s);
             if (a) (void)hipEventRecord(a, st);
         }
@@ -943,7 +944,7 @@ int pic_get_tile_offsets(pic_sim *S, int species, int32_t *host_out, hipStream_t
     return rc;
 }
 
-int pic_set_timing(pic_sim *S, int enable)
+int pic_set_timing_mask(pic_sim *S, unsigned mask)
 {
     if (!S) return PIC_EINVAL;
     for (int k = 0; k < PIC_N_KERNELS; ++k) {
@@ -956,8 +957,14 @@ int pic_set_timing(pic_sim *S, int enable)
         S->ms[k] = 0.0;
         S->launches[k] = 0;
     }
-    S->timing = enable != 0;
+    S->timing_mask = mask & ((1u << PIC_N_KERNELS) - 1u);
+    S->timing = S->timing_mask != 0;
     return PIC_OK;
+}
+
+int pic_set_timing(pic_sim *S, int enable)
+{
+    return pic_set_timing_mask(S, enable ? (1u << PIC_N_KERNELS) - 1u : 0u);
 }
 
 int pic_get_timing(pic_sim *S, pic_timing_out *out)

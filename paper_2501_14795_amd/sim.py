@@ -139,8 +139,13 @@ class _SimView:
     def tile_offsets(self, species: int = 0) -> np.ndarray:
         return np.array(_lib.pic_get_tile_offsets(self.handle, species, self.n_tiles, self.s), dtype=np.int64)
 
-    def set_timing(self, enable: bool = True):
-        _lib.pic_set_timing(self.handle, enable)
+    def set_timing(self, enable=True):
+        """True / False: time every kernel or none; a list of kernel names
+        (_lib.KERNELS): time only those."""
+        if isinstance(enable, (list, tuple)):
+            _lib.pic_set_timing_mask(self.handle, enable)
+        else:
+            _lib.pic_set_timing(self.handle, enable)
 
     def timing(self) -> Dict[str, tuple]:
         t = _lib.pic_get_timing(self.handle)

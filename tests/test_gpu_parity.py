@@ -294,3 +294,24 @@ def test_step_equals_explicit_calls(nx, ny, tile, nspecies, box):
         assert np.array_equal(fa[name], fb[name]), name
     a.close()
     b.close()
+
+
+def test_timing_mask_times_only_the_chosen_kernels():
+    """pic_set_timing_mask: events around the selected kernels only; the
+    per-kernel sums reset whenever the selection changes."""
+    from paper_2501_14795_amd import _lib
+    specs, states, E, B = _uniform(seed=31, fields=0.05)
+    sim, _ = make_pair(64, 64, DX, DY, DT, 16, specs, states, E, B)
+    sim.set_timing(["push", "field"])
+    for _ in range(3):
+        sim.step()
+    t = sim.timing()
+    assert t["push"][1] == 3 and t["field"][1] == 3 and t["push"][0] > 0
+    assert all(t[k][1] == 0 for k in _lib.KERNELS if k not in ("push", "field"))
+    sim.set_timing(True)
+    sim.step()
+    t = sim.timing()
+    assert all(t[k][1] == 1 for k in ("push", "j_reduce", "sort_scan", "sort_plan", "sort_scatter", "field"))
+    sim.set_timing(False)
+    assert sim.check() == 0
+    sim.close()
