@@ -31,6 +31,18 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 BYTES_PARTICLE = 24          # cell (4) + x, y (8) + ux, uy, uz (12)
 
 
+# The thesis's whole-run figures (500 steps, field solve and overheads
+# included, 500^2 decks of 25 M particles, FP32), as pushes/s = particles x
+# steps / time (Table 5.4): other hardware and a different workload, context only.
+PAPER_CONTEXT = {
+    "source": "thesis Table 5.4, warm deck, whole run",
+    "serial_cpu_xeon_gold_5218_1core_pushes_per_s": 10.8e6,
+    "openmp_2x_xeon_gold_5218_32t_pushes_per_s": 292e6,
+    "opencl_radeon_instinct_mi25_pushes_per_s": 2372e6,
+    "fpga_arria10_4lane_pushes_per_s": 60.8e6,
+}
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -382,6 +394,7 @@ def main():
             "leavers_per_step": leavers, "movers_per_step": movers,
         },
         "energy": {"u_e": d.u_e, "u_b": d.u_b, "u_k": d.u_k[0]},
+        "paper_context": PAPER_CONTEXT,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample",
                                                                      "host_cores", "cpu_model")},
     }
