@@ -1,5 +1,5 @@
 """Parity at the full benchmark sizes, in the launch configuration bench.py
-times (tile 16, default current mode).
+times (the workload's tile, default current mode), and with a sort cadence of 2.
 
 The oracle cannot run every particle of a 67M-particle step in a test, so:
   * push + move: a seeded random sample of particles is advanced one by one by
@@ -60,14 +60,17 @@ def _total_current_check(pre_list, post_list, specs, J, w):
         assert abs(got - want) <= 1e-6 * scale, (comp, got, want)
 
 
-@pytest.mark.parametrize("name,steps", [("warm2048", 2), ("weibel512", 2)])
-def test_full_size_step(name, steps):
+@pytest.mark.parametrize("name,steps,every", [("warm2048", 2, 1), ("weibel512", 2, 1), ("warm2048", 4, 2)])
+def test_full_size_step(name, steps, every):
+    """every > 1: the sort cadence -- the sort (checked bit-exact over all
+    particles) after every second push only."""
     from paper_2501_14795_amd import Sim
     L = _lib()
     w = pw.WORKLOADS[name]
     t0 = time.time()
     states = pw.workload_state(w)
-    sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, w.tile, [(s.qm, s.q, st) for s, st in zip(w.species, states)])
+    sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, w.tile, [(s.qm, s.q, st) for s, st in zip(w.species, states)],
+              sort_every=every)
     del states
     flush(f"[{name}] initialised {sim.n_tiles} tiles in {time.time() - t0:.1f}s")
     rng = np.random.default_rng(123)
@@ -89,6 +92,10 @@ def test_full_size_step(name, steps):
                   f"continuity {d.continuity_max:.2e}; leavers {d.leavers[k]}")
             assert pos < 1e-5 and du < 1e-5
         del pre
+        if step % every != every - 1:
+            del post
+            sim.field_advance()
+            continue
         # the sort, bit-exact over all particles
         sim.sort()
         assert sim.check() == 0

@@ -216,3 +216,43 @@ def test_window_errors():
         plain.set_state(s0)
     assert e.value.code == L.PIC_EINVAL
     plain.close()
+
+
+def test_window_full_size():
+    """The 2048^2 benchmark workload (67 M particles, 32 x 32 tiles) with the
+    moving window: after two steps, one move with a fresh column of plasma.
+    In array columns every particle array and tile_offset equal the oracle's
+    canonical sort with the origin column removed and the new particles
+    appended; E and B change in the origin column only (to zero)."""
+    from paper_2501_14795_amd import Sim
+    w = pw.WORKLOADS["warm2048"]
+    T = w.tile
+    spec = w.species[0]
+    st = pw.workload_state(w)[0]
+    n0 = st["ix"].size
+    sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, T, [(spec.qm, spec.q, st)], moving_window=True,
+              capacity=[n0 + 4 * w.ny * 16])
+    del st
+    for _ in range(2):
+        sim.step()
+    pre = sim.state(0)
+    f0 = sim.field_arrays()
+    col = pw.species_state(T, w.ny, T, spec, 77, 0, cell_box=(T - 1, T, 0, w.ny))
+    col["ix"] = col["ix"] + (w.nx - T)
+    sim.move_window([col])
+    assert sim.check() == 0 and sim.window_origin() == 1
+    lay, off = _expected_layout(pre, col, 0, w.nx, w.ny, T)
+    del pre
+    g = sim.state(0)
+    assert sim.counts()[0] == lay["ix"].size
+    for a in ARRAYS:
+        assert np.array_equal(g[a], lay[a]), a
+    assert np.array_equal(sim.tile_offsets(0), off)
+    f = sim.field_arrays()
+    for c in ("E", "B"):
+        assert not f[c][:, :, 0].any()
+        assert np.array_equal(f[c][:, :, 1:], f0[c][:, :, 1:]), c
+    flush(f"2048^2 window move: {n0} -> {lay['ix'].size} particles, layout bit-exact")
+    sim.step()
+    assert sim.check() == 0
+    sim.close()
