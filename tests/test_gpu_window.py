@@ -41,14 +41,14 @@ def _lib():
     return _lib
 
 
-def _setup(nx, ny, tile, nspecies=1, seed=3):
+def _setup(nx, ny, tile, nspecies=1, seed=3, **options):
     from paper_2501_14795_amd import Sim
     specs = [pw.SpeciesSpec(-1.0, (2, 2), (0.15,) * 3, (0.1, 0.05 * k, 0.0)) for k in range(nspecies)]
     states = [pw.species_state(nx, ny, tile, s, seed, k) for k, s in enumerate(specs)]
     E, B = pw.random_fields(nx, ny, 0.05, seed)
     cap = [st["ix"].size + 8 * ny * 4 for st in states]
     sim = Sim(nx, ny, DX, DY, DT, tile, [(s.qm, s.q, st) for s, st in zip(specs, states)], E=E, B=B,
-              moving_window=True, capacity=cap)
+              moving_window=True, capacity=cap, **options)
     return sim, specs, states, E, B, cap
 
 
@@ -57,14 +57,15 @@ def _column(nx, ny, tile, spec, seed, k):
     return pw.species_state(nx, ny, tile, spec, seed, k, cell_box=(nx - 1, nx, 0, ny))
 
 
-def _window_oracle(sim, specs):
+def _window_oracle(sim, specs, j_filter=0, esirkepov=False):
     """OracleSim holding the GPU's state in window columns (GPU slot order)."""
     f = sim.window_fields()
     osp = []
     for k, s in enumerate(specs):
         g = sim.window_state(k)
         osp.append(oracle.OracleSpecies(s.qm, s.q, g["ix"], g["iy"], g["x"], g["y"], g["ux"], g["uy"], g["uz"]))
-    return oracle.OracleSim(sim.nx, sim.ny, DX, DY, DT, osp, f["E"].astype(np.float64), f["B"].astype(np.float64))
+    return oracle.OracleSim(sim.nx, sim.ny, DX, DY, DT, osp, f["E"].astype(np.float64), f["B"].astype(np.float64),
+                            j_filter=j_filter, esirkepov=esirkepov)
 
 
 def _sorted_rows(d):
@@ -85,10 +86,15 @@ def _expected_layout(pre, inject, origin, nx, ny, tile):
     return {a: v[src] for a, v in cat.items()}, np.asarray(off, np.int64)
 
 
-@pytest.mark.parametrize("nx,ny,tile,nspecies", [(64, 32, 16, 1), (48, 40, 8, 2), (96, 64, 32, 1)])
-def test_window_step_matches_oracle(nx, ny, tile, nspecies):
+@pytest.mark.parametrize("nx,ny,tile,nspecies,options", [
+    (64, 32, 16, 1, {}), (48, 40, 8, 2, {}), (96, 64, 32, 1, {}),
+    # with the current filter, the Esirkepov deposit and the full re-sort between moves
+    (64, 48, 16, 2, {"j_filter": 1, "esirkepov": True, "full_sort": True}),
+])
+def test_window_step_matches_oracle(nx, ny, tile, nspecies, options):
     L = _lib()
-    sim, specs, *_ = _setup(nx, ny, tile, nspecies)
+    sim, specs, *_ = _setup(nx, ny, tile, nspecies, **options)
+    oopt = {"j_filter": options.get("j_filter", 0), "esirkepov": options.get("esirkepov", False)}
     n0 = sim.counts()
     cycles = 5
     for cycle in range(cycles):
@@ -121,7 +127,7 @@ def test_window_step_matches_oracle(nx, ny, tile, nspecies):
         flush(f"T{tile} cycle {cycle}: origin {origin} -> {sim.window_origin()}, counts {counts} (start {n0}), "
               f"window step bit-exact")
     # one step after the moves against the oracle's step in window columns
-    ref = _window_oracle(sim, specs)
+    ref = _window_oracle(sim, specs, **oopt)
     ref.push_deposit()
     sim.push_deposit()
     assert sim.check() == 0
