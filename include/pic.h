@@ -257,7 +257,10 @@ int pic_get_window_origin(pic_sim *sim, int32_t *origin);
  * device access). */
 int pic_get_counts(pic_sim *sim, int64_t *counts);
 
-/* pic_push_deposit + pic_sort (every sort_every-th step) + pic_field_advance. */
+/* pic_push_deposit + pic_sort (every sort_every-th step) + pic_field_advance.
+ * Issues kernels only (no memset, no synchronisation), so a caller may
+ * capture it into a HIP graph; with sort_every > 1 the captured step keeps the
+ * sort decision taken at capture time. */
 int pic_step(pic_sim *sim, hipStream_t stream);
 
 /* Synchronise `stream` and report (and clear) the device error flags. */

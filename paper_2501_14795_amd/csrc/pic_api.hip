@@ -628,7 +628,8 @@ static int full_sort(pic_sim *S, hipStream_t stream)
             Timed tm(S, PIC_KERNEL_SORT_SCAN, stream);
             launch_init_tiles(t.p.cell, t.n, c.nx, c.ny, c.tile, S->ntx, S->n_tiles, P.off, S->err, stream);
         }
-        if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(P.mcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
+        // a fill kernel, not a memset: pic_step may be captured into a graph
+        launch_zero_i32(P.mcount, S->n_tiles, stream);
     }
     if (rc == PIC_OK) rc = hip_ok(hipGetLastError());
     return rc;
