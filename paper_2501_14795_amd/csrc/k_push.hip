@@ -16,11 +16,12 @@
 //   3. per particle: bilinear interpolation at the staggered points
 //      (Sec. 3.1), Boris push (Eqs. 6-10), move (Eq. 11), and the
 //      Villasenor-Buneman current (Eqs. 13-16) of each of the 1, 2 or 3 pieces
-//      of the motion (Figs. 3.4-3.5), added into the LDS current of the tile
-//      (the first piece at once; the second and third -- present for the ~15%
-//      of particles that cross a cell face -- through a per-wavefront LDS
-//      queue drained 64 pieces at a time, so a wavefront does not run the
-//      deposit three times when a few of its lanes cross):
+//      of the motion (Figs. 3.4-3.5), added into the LDS current of the tile.
+//      A motion that stays in its cell (~85% of them) is one piece, deposited
+//      at once; one that crosses a cell face goes whole to a per-wavefront LDS
+//      queue, drained 64 motions at a time, where it is cut into its pieces --
+//      so the cutting and the extra deposits run on full wavefronts instead of
+//      on the few lanes of each wavefront that cross:
 //        kJFixed  exact int64 fixed point (ds_add_u64): every contribution is
 //                 rounded once, to within 2^-23 of the largest possible
 //                 contribution, the sums are exact, so J does not depend on
@@ -170,6 +171,45 @@ __device__ __forceinline__ void deposit_piece(typename JAcc<JM>::T *sj, int b, f
     A::add(&sj[2 * P + b + NJ + 1], az, fmaf(xm, ym, c));
 }
 
+// Villasenor-Buneman current of a motion that crosses one or two cell faces,
+// from (x, y) in the cell at halo index b by (dX, dY) cells (|dX|, |dY| < 1):
+// the motion is cut at the face crossings in time order, and piece k lies in
+// the cell reached after k crossings, in whose frame its endpoints are taken
+// (az: fq vz for the whole step, shared among the pieces by duration).
+template <int NJ, int JM>
+__device__ __forceinline__ void deposit_split(typename JAcc<JM>::T *sj, int b, float x, float y, float dX,
+                                              float dY, float az, float fq)
+{
+    const float x1 = x + dX, y1 = y + dY;
+    const int sxn = x1 >= 1.0f ? 1 : (x1 < 0.0f ? -1 : 0);
+    const int syn = y1 >= 1.0f ? 1 : (y1 < 0.0f ? -1 : 0);
+    const float ex = sxn > 0 ? 1.0f : 0.0f;   // x face crossed (start-cell frame)
+    const float ey = syn > 0 ? 1.0f : 0.0f;
+    const float tcx = sxn ? clamp01((ex - x) * __builtin_amdgcn_rcpf(dX)) : 1.0f;
+    const float tcy = syn ? clamp01((ey - y) * __builtin_amdgcn_rcpf(dY)) : 1.0f;
+    const bool xfirst = sxn != 0 && (syn == 0 || tcx <= tcy);
+    const bool three = sxn != 0 && syn != 0;
+    const float t1 = xfirst ? tcx : tcy;
+    const float t2 = xfirst ? tcy : tcx;
+    // crossing points (start-cell frame)
+    const float p1x = xfirst ? ex : fmaf(t1, dX, x);
+    const float p1y = xfirst ? fmaf(t1, dY, y) : ey;
+    const float p2x = xfirst ? fmaf(t2, dX, x) : ex;
+    const float p2y = xfirst ? ey : fmaf(t2, dY, y);
+    // piece 0, in the start cell
+    deposit_piece<NJ, JM>(sj, b, clamp01(x), clamp01(y), clamp01(p1x), clamp01(p1y), az * t1, fq);
+    // piece 1, after the first crossing
+    const int ox = xfirst ? sxn : 0, oy = xfirst ? 0 : syn;
+    const float e1x = three ? p2x : x1, e1y = three ? p2y : y1;
+    const float f1 = three ? t2 : 1.0f;
+    deposit_piece<NJ, JM>(sj, b + oy * NJ + ox, clamp01(p1x - ox), clamp01(p1y - oy), clamp01(e1x - ox),
+                          clamp01(e1y - oy), az * (f1 - t1), fq);
+    // piece 2, after both crossings
+    if (three)
+        deposit_piece<NJ, JM>(sj, b + syn * NJ + sxn, clamp01(p2x - sxn), clamp01(p2y - syn), clamp01(x1 - sxn),
+                              clamp01(y1 - syn), az * (1.0f - t2), fq);
+}
+
 // Esirkepov's current of a whole straight motion (the variant deposit) from
 // (x, y) in the cell at halo index b to (x1, y1) in that cell's frame
 // (x1, y1 in (-1, 2)), on the 4 x 4 nodes around it.  Node weights of the
@@ -223,49 +263,48 @@ __device__ __forceinline__ void deposit_esirkepov(typename JAcc<JM>::T *sj, int 
         }
 }
 
-// The wavefront's queue of deposit jobs: kPieceBuf entries of
-// (halo index, xa, ya, xb, yb, az) -- second and third pieces of split
-// motions (Villasenor-Buneman) or whole face-crossing motions (Esirkepov).
+// The wavefront's queue of face-crossing motions: kPieceBuf entries of
+// (halo index of the start cell, x, y, dX, dY, fq vz).
 
 template <int NJ, int JM, int DM>
-__device__ __forceinline__ void drain_pieces(typename JAcc<JM>::T *sj, uint32_t (*pq)[kPieceBuf], int n,
-                                             float fq, int lane)
+__device__ __forceinline__ void drain_motions(typename JAcc<JM>::T *sj, uint32_t (*pq)[kPieceBuf], int n,
+                                              float fq, int lane)
 {
     __builtin_amdgcn_wave_barrier();
     if (lane < n) {
         const int b = (int)pq[0][lane];
-        const float xa = __uint_as_float(pq[1][lane]), ya = __uint_as_float(pq[2][lane]);
-        const float xb = __uint_as_float(pq[3][lane]), yb = __uint_as_float(pq[4][lane]);
+        const float x = __uint_as_float(pq[1][lane]), y = __uint_as_float(pq[2][lane]);
+        const float dX = __uint_as_float(pq[3][lane]), dY = __uint_as_float(pq[4][lane]);
         const float az = __uint_as_float(pq[5][lane]);
         if constexpr (DM == kDepEsirkepov)
-            deposit_esirkepov<NJ, JM>(sj, b, xa, ya, xb, yb, az, fq);
+            deposit_esirkepov<NJ, JM>(sj, b, x, y, x + dX, y + dY, az, fq);
         else
-            deposit_piece<NJ, JM>(sj, b, xa, ya, xb, yb, az, fq);
+            deposit_split<NJ, JM>(sj, b, x, y, dX, dY, az, fq);
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-// Append the pieces of the lanes with `has` set to the queue (slot order by
+// Append the motions of the lanes with `has` set to the queue (slot order by
 // lane), draining it first if they do not fit.  n: queue fill, uniform.
 template <int NJ, int JM, int DM>
-__device__ __forceinline__ void queue_piece(typename JAcc<JM>::T *sj, uint32_t (*pq)[kPieceBuf], int &n, bool has,
-                                            int b, float xa, float ya, float xb, float yb, float az, float fq,
-                                            int lane)
+__device__ __forceinline__ void queue_motion(typename JAcc<JM>::T *sj, uint32_t (*pq)[kPieceBuf], int &n, bool has,
+                                             int b, float x, float y, float dX, float dY, float az, float fq,
+                                             int lane)
 {
     const unsigned long long m = __ballot(has);
     const int c = __popcll(m);
     if (c == 0) return;
     if (n + c > kPieceBuf) {
-        drain_pieces<NJ, JM, DM>(sj, pq, n, fq, lane);
+        drain_motions<NJ, JM, DM>(sj, pq, n, fq, lane);
         n = 0;
     }
     if (has) {
         const int r = n + lane_rank(m);
         pq[0][r] = (uint32_t)b;
-        pq[1][r] = __float_as_uint(xa);
-        pq[2][r] = __float_as_uint(ya);
-        pq[3][r] = __float_as_uint(xb);
-        pq[4][r] = __float_as_uint(yb);
+        pq[1][r] = __float_as_uint(x);
+        pq[2][r] = __float_as_uint(y);
+        pq[3][r] = __float_as_uint(dX);
+        pq[4][r] = __float_as_uint(dY);
         pq[5][r] = __float_as_uint(az);
     }
     n += c;
@@ -383,190 +422,130 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                 n_ux = ldf(st.ux, off + 256);
                 n_uy = ldf(st.uy, off + 256);
                 n_uz = ldf(st.uz, off + 256);
-                bool leaver = false;
-                int dir = 4, ncell = 0;
-                float xn = 0.0f, yn = 0.0f;
-                // second and third pieces of the motion, queued below
-                bool has1 = false, has2 = false;
-                int qb1 = 0, qb2 = 0;
-                float xa1 = 0.0f, ya1 = 0.0f, xb1 = 0.0f, yb1 = 0.0f, az1 = 0.0f;
-                float xa2 = 0.0f, ya2 = 0.0f, xb2 = 0.0f, yb2 = 0.0f, az2 = 0.0f;
-                if (i >= lo && i < hi) {
-                    int lx = (cell & 0xffff) - gx0, ly = (cell >> 16) - gy0;
-                    if constexpr (H > 1) {
-                        // since the last sort the particle may have left the
-                        // tile by up to H - 1 cells, also across the periodic
-                        // seam (one image lies in that band: 2H - 2 < T)
-                        if (cell < 0 || (cell & 0xffff) >= a.nx || (cell >> 16) >= a.ny) {
-                            lx = T + H;   // not a cell of the grid: flagged below
-                        } else {
-                            if (tx_wrap) lx += lx >= T + H - 1 ? -a.nx : (lx < 1 - H ? a.nx : 0);
-                            if (ty_wrap) ly += ly >= T + H - 1 ? -a.ny : (ly < 1 - H ? a.ny : 0);
-                        }
+                // Every lane computes; only the lanes of the run (valid) have
+                // side effects.  The others (the previous tile's particles
+                // before the run's start in the section's first chunk, zeros
+                // past its end) take their values through the same arithmetic
+                // with their cell clamped into the halo, so their LDS reads
+                // stay in bounds.  No divergent region means no values to
+                // merge at its end for the lanes that skipped it.
+                const bool valid = i >= lo && i < hi;
+                int lx = (cell & 0xffff) - gx0, ly = (cell >> 16) - gy0;
+                if constexpr (H > 1) {
+                    // since the last sort the particle may have left the
+                    // tile by up to H - 1 cells, also across the periodic
+                    // seam (one image lies in that band: 2H - 2 < T)
+                    if (cell < 0 || (cell & 0xffff) >= a.nx || (cell >> 16) >= a.ny) {
+                        lx = T + H;   // not a cell of the grid: flagged below
+                    } else {
+                        if (tx_wrap) lx += lx >= T + H - 1 ? -a.nx : (lx < 1 - H ? a.nx : 0);
+                        if (ty_wrap) ly += ly >= T + H - 1 ? -a.ny : (ly < 1 - H ? a.ny : 0);
                     }
-                    if ((unsigned)(lx + H - 1) >= (unsigned)(T + 2 * H - 2) ||
-                        (unsigned)(ly + H - 1) >= (unsigned)(T + 2 * H - 2)) {
-                        atomicOr(a.err, kErrOrder);
-                        lx = min(max(lx, 1 - H), T + H - 2);
-                        ly = min(max(ly, 1 - H), T + H - 2);
-                    }
+                }
+                if (valid && ((unsigned)(lx + H - 1) >= (unsigned)(T + 2 * H - 2) ||
+                              (unsigned)(ly + H - 1) >= (unsigned)(T + 2 * H - 2)))
+                    atomicOr(a.err, kErrOrder);
+                lx = min(max(lx, 1 - H), T + H - 2);
+                ly = min(max(ly, 1 - H), T + H - 2);
 
-                    // ---- interpolation (bilinear at each component's staggered point)
-                    const bool xh = x >= 0.5f, yh = y >= 0.5f;
-                    const float wxh = xh ? x - 0.5f : x + 0.5f;   // weight for (i+1/2) points
-                    const float wyh = yh ? y - 0.5f : y + 0.5f;
-                    const int ch = lx + (H - 1) + (xh ? 1 : 0);   // packed column of the half stencil
-                    const int rh = ly + (H - 1) + (yh ? 1 : 0);
-                    const int c0 = lx + H, r0 = ly + H;
-                    const int e0 = __mul24(r0, NE), eh = __mul24(rh, NE);
-                    const float4 p0 = s_exby[e0 + ch], p1 = s_exby[e0 + NE + ch];
-                    const float4 q0 = s_eybx[eh + c0], q1 = s_eybx[eh + NE + c0];
-                    const float2 z0 = s_ez[e0 + c0], z1 = s_ez[e0 + NE + c0];
-                    const float2 b0 = s_bz[eh + ch], b1 = s_bz[eh + NE + ch];
-                    const float Ex = lerpf(lerpf(p0.x, p0.z, wxh), lerpf(p1.x, p1.z, wxh), y);
-                    const float By = lerpf(lerpf(p0.y, p0.w, wxh), lerpf(p1.y, p1.w, wxh), y);
-                    const float Ey = lerpf(lerpf(q0.x, q0.z, x), lerpf(q1.x, q1.z, x), wyh);
-                    const float Bx = lerpf(lerpf(q0.y, q0.w, x), lerpf(q1.y, q1.w, x), wyh);
-                    const float Ez = lerpf(lerpf(z0.x, z0.y, x), lerpf(z1.x, z1.y, x), y);
-                    const float Bz = lerpf(lerpf(b0.x, b0.y, wxh), lerpf(b1.x, b1.y, wxh), wyh);
+                // ---- interpolation (bilinear at each component's staggered point)
+                const bool xh = x >= 0.5f, yh = y >= 0.5f;
+                const float wxh = xh ? x - 0.5f : x + 0.5f;   // weight for (i+1/2) points
+                const float wyh = yh ? y - 0.5f : y + 0.5f;
+                const int ch = lx + (H - 1) + (xh ? 1 : 0);   // packed column of the half stencil
+                const int rh = ly + (H - 1) + (yh ? 1 : 0);
+                const int c0 = lx + H, r0 = ly + H;
+                const int e0 = __mul24(r0, NE), eh = __mul24(rh, NE);
+                const float4 p0 = s_exby[e0 + ch], p1 = s_exby[e0 + NE + ch];
+                const float4 q0 = s_eybx[eh + c0], q1 = s_eybx[eh + NE + c0];
+                const float2 z0 = s_ez[e0 + c0], z1 = s_ez[e0 + NE + c0];
+                const float2 b0 = s_bz[eh + ch], b1 = s_bz[eh + NE + ch];
+                const float Ex = lerpf(lerpf(p0.x, p0.z, wxh), lerpf(p1.x, p1.z, wxh), y);
+                const float By = lerpf(lerpf(p0.y, p0.w, wxh), lerpf(p1.y, p1.w, wxh), y);
+                const float Ey = lerpf(lerpf(q0.x, q0.z, x), lerpf(q1.x, q1.z, x), wyh);
+                const float Bx = lerpf(lerpf(q0.y, q0.w, x), lerpf(q1.y, q1.w, x), wyh);
+                const float Ez = lerpf(lerpf(z0.x, z0.y, x), lerpf(z1.x, z1.y, x), y);
+                const float Bz = lerpf(lerpf(b0.x, b0.y, wxh), lerpf(b1.x, b1.y, wxh), wyh);
 
-                    // ---- Boris push (Eqs. 6-10); 1 + |u|^2 >= 1, so the hardware
-                    // reciprocal square root needs no denormal care
-                    const float mx = fmaf(h, Ex, ux), my = fmaf(h, Ey, uy), mz = fmaf(h, Ez, uz);
-                    const float gi = __builtin_amdgcn_rsqf(fmaf(mx, mx, fmaf(my, my, fmaf(mz, mz, 1.0f))));
-                    const float hg = h * gi;
-                    const float tx_ = hg * Bx, ty_ = hg * By, tz_ = hg * Bz;
-                    const float px = fmaf(my, tz_, fmaf(-mz, ty_, mx));
-                    const float py = fmaf(mz, tx_, fmaf(-mx, tz_, my));
-                    const float pz = fmaf(mx, ty_, fmaf(-my, tx_, mz));
-                    const float f2 =
-                        2.0f * __builtin_amdgcn_rcpf(fmaf(tx_, tx_, fmaf(ty_, ty_, fmaf(tz_, tz_, 1.0f))));
-                    const float sx_ = f2 * tx_, sy_ = f2 * ty_, sz_ = f2 * tz_;
-                    ux = fmaf(h, Ex, fmaf(py, sz_, fmaf(-pz, sy_, mx)));
-                    uy = fmaf(h, Ey, fmaf(pz, sx_, fmaf(-px, sz_, my)));
-                    uz = fmaf(h, Ez, fmaf(px, sy_, fmaf(-py, sx_, mz)));
+                // ---- Boris push (Eqs. 6-10); 1 + |u|^2 >= 1, so the hardware
+                // reciprocal square root needs no denormal care
+                const float mx = fmaf(h, Ex, ux), my = fmaf(h, Ey, uy), mz = fmaf(h, Ez, uz);
+                const float gi = __builtin_amdgcn_rsqf(fmaf(mx, mx, fmaf(my, my, fmaf(mz, mz, 1.0f))));
+                const float hg = h * gi;
+                const float tx_ = hg * Bx, ty_ = hg * By, tz_ = hg * Bz;
+                const float px = fmaf(my, tz_, fmaf(-mz, ty_, mx));
+                const float py = fmaf(mz, tx_, fmaf(-mx, tz_, my));
+                const float pz = fmaf(mx, ty_, fmaf(-my, tx_, mz));
+                const float f2 =
+                    2.0f * __builtin_amdgcn_rcpf(fmaf(tx_, tx_, fmaf(ty_, ty_, fmaf(tz_, tz_, 1.0f))));
+                const float sx_ = f2 * tx_, sy_ = f2 * ty_, sz_ = f2 * tz_;
+                ux = fmaf(h, Ex, fmaf(py, sz_, fmaf(-pz, sy_, mx)));
+                uy = fmaf(h, Ey, fmaf(pz, sx_, fmaf(-px, sz_, my)));
+                uz = fmaf(h, Ez, fmaf(px, sy_, fmaf(-py, sx_, mz)));
 
-                    // ---- move (Eq. 11), in cells
-                    const float ig = __builtin_amdgcn_rsqf(fmaf(ux, ux, fmaf(uy, uy, fmaf(uz, uz, 1.0f))));
-                    float dX = ux * ig * a.cx, dY = uy * ig * a.cy;
-                    if (!(fabsf(dX) < 1.0f && fabsf(dY) < 1.0f)) {
-                        atomicOr(a.err, kErrRange);
-                        dX = 0.0f;
-                        dY = 0.0f;
-                    }
-                    const float x1 = x + dX, y1 = y + dY;
-                    const int sxn = x1 >= 1.0f ? 1 : (x1 < 0.0f ? -1 : 0);
-                    const int syn = y1 >= 1.0f ? 1 : (y1 < 0.0f ? -1 : 0);
+                // ---- move (Eq. 11), in cells
+                const float ig = __builtin_amdgcn_rsqf(fmaf(ux, ux, fmaf(uy, uy, fmaf(uz, uz, 1.0f))));
+                float dX = ux * ig * a.cx, dY = uy * ig * a.cy;
+                if (!(fabsf(dX) < 1.0f && fabsf(dY) < 1.0f)) {
+                    if (valid) atomicOr(a.err, kErrRange);
+                    dX = 0.0f;
+                    dY = 0.0f;
+                }
+                const float x1 = x + dX, y1 = y + dY;
+                const int sxn = x1 >= 1.0f ? 1 : (x1 < 0.0f ? -1 : 0);
+                const int syn = y1 >= 1.0f ? 1 : (y1 < 0.0f ? -1 : 0);
 
-                    // ---- Villasenor-Buneman deposit of the 1, 2 or 3 pieces: the
-                    // motion is cut at the face crossings in time order; piece k
-                    // lies in the cell reached after k crossings, in whose frame
-                    // its endpoints are taken
-                    {
-                        const float ex = sxn > 0 ? 1.0f : 0.0f;   // x face crossed (start-cell frame)
-                        const float ey = syn > 0 ? 1.0f : 0.0f;
-                        const float tcx = sxn ? clamp01((ex - x) * __builtin_amdgcn_rcpf(dX)) : 1.0f;
-                        const float tcy = syn ? clamp01((ey - y) * __builtin_amdgcn_rcpf(dY)) : 1.0f;
-                        const bool xfirst = sxn != 0 && (syn == 0 || tcx <= tcy);
-                        const float t1 = xfirst ? tcx : tcy;
-                        const float t2 = xfirst ? tcy : tcx;
-                        const int nseg = 1 + (sxn != 0) + (syn != 0);
-                        const float fqvz = fq * uz * ig;
-                        // crossing points (start-cell frame)
-                        const float p1x = xfirst ? ex : fmaf(t1, dX, x);
-                        const float p1y = xfirst ? fmaf(t1, dY, y) : ey;
-                        const float p2x = xfirst ? fmaf(t2, dX, x) : ex;
-                        const float p2y = xfirst ? ey : fmaf(t2, dY, y);
-                        if constexpr (DM == kDepEsirkepov) {
-                            // inside the cell both schemes coincide; a crossing
-                            // motion is queued whole for the 4 x 4 stencil
-                            if (nseg == 1) {
-                                deposit_piece<NJ, JM>(sj, jcell<NJ, H>(lx, ly), clamp01(x), clamp01(y), clamp01(x1),
-                                                      clamp01(y1), fqvz * (1.0f - 0.0f), fq);
-                            } else {
-                                has1 = true;
-                                qb1 = jcell<NJ, H>(lx, ly);
-                                xa1 = x;
-                                ya1 = y;
-                                xb1 = x1;
-                                yb1 = y1;
-                                az1 = fqvz;
-                            }
-                        }
-                        // piece 0, in the start cell
-                        const float e0x = nseg == 1 ? x1 : p1x, e0y = nseg == 1 ? y1 : p1y;
-                        const float f0 = nseg == 1 ? 1.0f : t1;
-                        if constexpr (DM == kDepVB)
-                            deposit_piece<NJ, JM>(sj, jcell<NJ, H>(lx, ly), clamp01(x), clamp01(y), clamp01(e0x),
-                                                  clamp01(e0y), fqvz * (f0 - 0.0f), fq);
-                        // piece 1, after the first crossing
-                        if (DM == kDepVB && nseg >= 2) {
-                            const int ox = xfirst ? sxn : 0, oy = xfirst ? 0 : syn;
-                            const float e1x = nseg == 2 ? x1 : p2x, e1y = nseg == 2 ? y1 : p2y;
-                            const float f1 = nseg == 2 ? 1.0f : t2;
-                            has1 = true;
-                            qb1 = jcell<NJ, H>(lx + ox, ly + oy);
-                            xa1 = clamp01(p1x - ox);
-                            ya1 = clamp01(p1y - oy);
-                            xb1 = clamp01(e1x - ox);
-                            yb1 = clamp01(e1y - oy);
-                            az1 = fqvz * (f1 - t1);
-                        }
-                        // piece 2, after both crossings
-                        if (DM == kDepVB && nseg == 3) {
-                            has2 = true;
-                            qb2 = jcell<NJ, H>(lx + sxn, ly + syn);
-                            xa2 = clamp01(p2x - sxn);
-                            ya2 = clamp01(p2y - syn);
-                            xb2 = clamp01(x1 - sxn);
-                            yb2 = clamp01(y1 - syn);
-                            az2 = fqvz * (1.0f - t2);
-                        }
-                    }
+                // ---- current: a motion inside its cell is one piece, and
+                // there both deposits agree (x, x1 in [0, 1)); one that
+                // crosses a face is queued whole and cut (or, for
+                // Esirkepov, spread over its 4 x 4 stencil) when the queue
+                // is drained
+                const float fqvz = fq * uz * ig;
+                const int b = jcell<NJ, H>(lx, ly);
+                const bool cross = valid && (sxn | syn) != 0;
+                if (valid && !cross) deposit_piece<NJ, JM>(sj, b, x, y, x1, y1, fqvz, fq);
 
-                    // ---- new position: offset back into [0,1), cell index, periodic wrap
-                    int nlx = lx, nly = ly;
-                    xn = x1;
-                    yn = y1;
-                    if (sxn > 0) {
-                        xn = x1 - 1.0f;
+                // ---- new position: offset back into [0,1), cell index, periodic wrap
+                int nlx = lx, nly = ly;
+                float xn = x1, yn = y1;
+                if (sxn > 0) {
+                    xn = x1 - 1.0f;
+                    nlx += 1;
+                } else if (sxn < 0) {
+                    xn = x1 + 1.0f;
+                    nlx -= 1;
+                    if (xn >= 1.0f) {   // rounded onto the face: it is x = 0 of the old cell
+                        xn = 0.0f;
                         nlx += 1;
-                    } else if (sxn < 0) {
-                        xn = x1 + 1.0f;
-                        nlx -= 1;
-                        if (xn >= 1.0f) {   // rounded onto the face: it is x = 0 of the old cell
-                            xn = 0.0f;
-                            nlx += 1;
-                        }
                     }
-                    if (syn > 0) {
-                        yn = y1 - 1.0f;
+                }
+                if (syn > 0) {
+                    yn = y1 - 1.0f;
+                    nly += 1;
+                } else if (syn < 0) {
+                    yn = y1 + 1.0f;
+                    nly -= 1;
+                    if (yn >= 1.0f) {
+                        yn = 0.0f;
                         nly += 1;
-                    } else if (syn < 0) {
-                        yn = y1 + 1.0f;
-                        nly -= 1;
-                        if (yn >= 1.0f) {
-                            yn = 0.0f;
-                            nly += 1;
-                        }
                     }
-                    const int gx = wrapi(gx0 + nlx, a.nx), gy = wrapi(gy0 + nly, a.ny);
-                    ncell = gx | (gy << 16);
+                }
+                const int gx = wrapi(gx0 + nlx, a.nx), gy = wrapi(gy0 + nly, a.ny);
+                const int ncell = gx | (gy << 16);
+                if (valid) {
                     __builtin_amdgcn_raw_buffer_store_b32((unsigned)ncell, st.cell, off, 0, kStoreCpol);
                     stf(st.x, off, xn);
                     stf(st.y, off, yn);
                     stf(st.ux, off, ux);
                     stf(st.uy, off, uy);
                     stf(st.uz, off, uz);
-
-                    const int dtx = tx_wrap ? (nlx < 0 ? -1 : (nlx >= T ? 1 : 0)) : 0;
-                    const int dty = ty_wrap ? (nly < 0 ? -1 : (nly >= T ? 1 : 0)) : 0;
-                    dir = (dty + 1) * 3 + (dtx + 1);
-                    leaver = dir != 4;
                 }
-                queue_piece<NJ, JM, DM>(sj, s_pq[wave], npq, has1, qb1, xa1, ya1, xb1, yb1, az1, fq, lane);
-                if constexpr (DM == kDepVB)
-                    queue_piece<NJ, JM, DM>(sj, s_pq[wave], npq, has2, qb2, xa2, ya2, xb2, yb2, az2, fq, lane);
+
+                const int dtx = tx_wrap ? (nlx < 0 ? -1 : (nlx >= T ? 1 : 0)) : 0;
+                const int dty = ty_wrap ? (nly < 0 ? -1 : (nly >= T ? 1 : 0)) : 0;
+                const int dir = (dty + 1) * 3 + (dtx + 1);
+                const bool leaver = valid && dir != 4;
+                queue_motion<NJ, JM, DM>(sj, s_pq[wave], npq, cross, b, x, y, dX, dY, fqvz, fq, lane);
                 // leavers go to the wavefront's LDS buffer in slot order; a full
                 // buffer is written out as whole cache lines
                 const unsigned long long m = __ballot(leaver);
@@ -591,7 +570,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                     nbuf += c;
                 }
             }
-            drain_pieces<NJ, JM, DM>(sj, s_pq[wave], npq, fq, lane);
+            drain_motions<NJ, JM, DM>(sj, s_pq[wave], npq, fq, lane);
             flush_leavers(sp, s_lb[wave], nbuf, (int64_t)lo + nleav, lane);
             nleav += nbuf;
         }
