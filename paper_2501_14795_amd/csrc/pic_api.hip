@@ -140,6 +140,11 @@ struct pic_sim {
     int halo;           // sort cadence: pushes between sorts (the push kernel's halo pad)
     int since_sort;     // pushes since the last sort
     int32_t *wrem;      // moving window: particles that left, per species
+    // pic_step's second stream: the field half of a step (J fold, filter,
+    // field advance) runs there beside the sort, forked from and joined back
+    // into the caller's stream with these two events
+    hipStream_t side;
+    hipEvent_t ev_fork, ev_join;
     int64_t cap[kMaxSpecies];
     bool have_snapshot;
     struct Sp {
@@ -164,6 +169,18 @@ struct pic_sim {
 };
 
 namespace {
+
+void release_side(pic_sim *s)
+{
+    if (s->side) {
+        (void)hipStreamSynchronize(s->side);
+        (void)hipStreamDestroy(s->side);
+    }
+    if (s->ev_fork) (void)hipEventDestroy(s->ev_fork);
+    if (s->ev_join) (void)hipEventDestroy(s->ev_join);
+    s->side = nullptr;
+    s->ev_fork = s->ev_join = nullptr;
+}
 
 hipEvent_t take_event(pic_sim *s)
 {
@@ -507,7 +524,22 @@ int build_tiles(pic_sim *S, hipStream_t stream)
 
 }  // namespace
 
+namespace {
+// with_side: create pic_step's second stream (the members of a batch have
+// none: the batch forks its own step)
+int init_sim(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream, pic_sim **out, bool with_side);
+}  // namespace
+
 int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream, pic_sim **out)
+{
+    return init_sim(cfg, bufs, stream, out, true);
+}
+
+}  // extern "C"
+
+namespace {
+
+int init_sim(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream, pic_sim **out, bool with_side)
 {
     if (!out || !bufs) return PIC_EINVAL;
     *out = nullptr;
@@ -572,7 +604,14 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
 
     rc = hip_ok(hipMemsetAsync(S->err, 0, 64, stream));
     if (rc == PIC_OK) rc = build_tiles(S, stream);
+    if (with_side) {
+        // default priority, like every stream of the library's callers
+        if (rc == PIC_OK) rc = hip_ok(hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking));
+        if (rc == PIC_OK) rc = hip_ok(hipEventCreateWithFlags(&S->ev_fork, hipEventDisableTiming));
+        if (rc == PIC_OK) rc = hip_ok(hipEventCreateWithFlags(&S->ev_join, hipEventDisableTiming));
+    }
     if (rc != PIC_OK) {
+        release_side(S);
         delete S;
         return rc;
     }
@@ -580,9 +619,16 @@ int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
     return PIC_OK;
 }
 
-int pic_push_deposit(pic_sim *S, hipStream_t stream)
+}  // namespace
+
+extern "C" {
+
+
+namespace {
+
+// The push kernel alone (steps a1-a7 up to the per-tile current halos).
+int push_only(pic_sim *S, hipStream_t stream)
 {
-    if (!S) return PIC_EINVAL;
     // a particle may stray at most sort_every - 1 cells from its tile before a push
     if (S->since_sort >= S->halo) return PIC_EORDER;
     const PushArgs a = push_args(S);
@@ -592,6 +638,12 @@ int pic_push_deposit(pic_sim *S, hipStream_t stream)
                             stream);
     }
     S->since_sort += 1;
+    return hip_ok(hipGetLastError());
+}
+
+// The fold of the tile current halos into J, then the optional filter passes.
+int fold_current(pic_sim *S, hipStream_t stream)
+{
     {
         Timed t(S, PIC_KERNEL_JREDUCE, stream);
         launch_j_reduce(S->tile, S->halo, jreduce_args(S), stream);
@@ -601,6 +653,16 @@ int pic_push_deposit(pic_sim *S, hipStream_t stream)
         launch_filter(filter_args(S, p), false, stream);
     }
     return hip_ok(hipGetLastError());
+}
+
+}  // namespace
+
+int pic_push_deposit(pic_sim *S, hipStream_t stream)
+{
+    if (!S) return PIC_EINVAL;
+    int rc = push_only(S, stream);
+    if (rc == PIC_OK) rc = fold_current(S, stream);
+    return rc;
 }
 
 // The alternative sort (PIC_FLAG_FULL_SORT): every species regrouped by the
@@ -797,10 +859,32 @@ int pic_get_counts(pic_sim *S, int64_t *counts)
 
 int pic_step(pic_sim *S, hipStream_t stream)
 {
-    int rc = pic_push_deposit(S, stream);
-    if (rc == PIC_OK && S->since_sort >= S->halo) rc = pic_sort(S, stream);
-    if (rc == PIC_OK) rc = pic_field_advance(S, stream);
-    return rc;
+    if (!S) return PIC_EINVAL;
+    int rc = push_only(S, stream);
+    if (rc) return rc;
+    if (S->since_sort < S->halo || !S->side) {   // no sort this step, or no second stream
+        rc = fold_current(S, stream);
+        if (rc == PIC_OK && S->since_sort >= S->halo) rc = pic_sort(S, stream);
+        if (rc == PIC_OK) rc = pic_field_advance(S, stream);
+        return rc;
+    }
+    // Once the push is done, the sort (particles, count records, leaver
+    // lists) and the field half (tile current halos, J, E, B) touch disjoint
+    // data: the field half runs on the second stream, beside the sort, and
+    // the caller's stream waits for it before anything later.  Both halves
+    // are small, latency-bound kernels, so they overlap well.
+    rc = hip_ok(hipEventRecord(S->ev_fork, stream));
+    if (rc) return rc;
+    rc = hip_ok(hipStreamWaitEvent(S->side, S->ev_fork, 0));
+    if (rc) return rc;
+    int rf = fold_current(S, S->side);
+    if (rf == PIC_OK) rf = pic_field_advance(S, S->side);
+    const int rj = hip_ok(hipEventRecord(S->ev_join, S->side));
+    rc = pic_sort(S, stream);
+    // the join is enqueued whatever happened above, so the caller's stream
+    // never runs ahead of work already on the second stream
+    const int rw = rj == PIC_OK ? hip_ok(hipStreamWaitEvent(stream, S->ev_join, 0)) : rj;
+    return rc ? rc : (rf ? rf : rw);
 }
 
 int pic_check(pic_sim *S, hipStream_t stream)
@@ -999,6 +1083,7 @@ void pic_destroy(pic_sim *S)
             S->pool.push_back(pr.second);
         }
     for (hipEvent_t e : S->pool) (void)hipEventDestroy(e);
+    release_side(S);
     delete S;
 }
 
@@ -1028,6 +1113,9 @@ struct pic_batch {
     int push_grid;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    // the field half of a sorting step runs here beside the sort (as in pic_step)
+    hipStream_t side;
+    hipEvent_t ev_fork, ev_join;
 };
 
 namespace {
@@ -1094,9 +1182,19 @@ void batch_enqueue_step(pic_batch *b, bool sort, hipStream_t stream)
     launch_set_int(b->counter, 0, stream);
     launch_push_batch(b->tile, b->replicas, b->jm, b->dm, b->halo, b->d_push, b->push_items, b->n_push, b->counter,
                       b->push_grid, stream);
-    launch_j_reduce_batch(b->tile, b->halo, b->d_jr, b->node_items, b->n_node, stream);
+    // with a sort, the field half goes to the second stream (disjoint data)
+    const bool fork = sort && b->side;
+    hipStream_t fs = stream;
+    if (fork) {
+        (void)hipEventRecord(b->ev_fork, stream);
+        (void)hipStreamWaitEvent(b->side, b->ev_fork, 0);
+        fs = b->side;
+    }
+    launch_j_reduce_batch(b->tile, b->halo, b->d_jr, b->node_items, b->n_node, fs);
     for (int p = 0; p < b->j_filter; ++p)
-        launch_filter_batch(b->d_filter + (p & 1) * b->sims.size(), b->node_items, b->n_node, stream);
+        launch_filter_batch(b->d_filter + (p & 1) * b->sims.size(), b->node_items, b->n_node, fs);
+    launch_field_advance_batch(b->d_field, b->node_items, b->n_node, fs);
+    if (fork) (void)hipEventRecord(b->ev_join, b->side);
     SortBatch sb;
     sb.descs = b->d_sort;
     sb.count_items = b->count_items;
@@ -1106,7 +1204,7 @@ void batch_enqueue_step(pic_batch *b, bool sort, hipStream_t stream)
     sb.plan_items = b->plan_items;
     sb.n_plan = b->n_plan;
     if (sort) launch_sort_batch(sb, stream);
-    launch_field_advance_batch(b->d_field, b->node_items, b->n_node, stream);
+    if (fork) (void)hipStreamWaitEvent(stream, b->ev_join, 0);
 }
 
 }  // namespace
@@ -1134,9 +1232,16 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
 
     pic_batch *B = new (std::nothrow) pic_batch();
     if (!B) return PIC_EINVAL;
+    rc = hip_ok(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
+    if (rc == PIC_OK) rc = hip_ok(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
+    if (rc == PIC_OK) rc = hip_ok(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
+    if (rc) {
+        pic_batch_destroy(B);
+        return rc;
+    }
     for (int i = 0; i < n; ++i) {
         pic_sim *S = nullptr;
-        rc = pic_init(&cfgs[i], &bufs[i], stream, &S);
+        rc = init_sim(&cfgs[i], &bufs[i], stream, &S, false);
         if (rc) {
             pic_batch_destroy(B);
             return rc;
@@ -1298,6 +1403,12 @@ void pic_batch_destroy(pic_batch *B)
     if (B->exec) (void)hipGraphExecDestroy(B->exec);
     if (B->graph) (void)hipGraphDestroy(B->graph);
     for (pic_sim *S : B->sims) pic_destroy(S);
+    if (B->side) {
+        (void)hipStreamSynchronize(B->side);
+        (void)hipStreamDestroy(B->side);
+    }
+    if (B->ev_fork) (void)hipEventDestroy(B->ev_fork);
+    if (B->ev_join) (void)hipEventDestroy(B->ev_join);
     delete B;
 }
 
