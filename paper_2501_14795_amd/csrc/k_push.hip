@@ -263,11 +263,11 @@ __device__ __forceinline__ void deposit_esirkepov(typename JAcc<JM>::T *sj, int 
         }
 }
 
-// The wavefront's queue of face-crossing motions: kPieceBuf entries of
+// The wavefront's queue of face-crossing motions: kMotionBuf entries of
 // (halo index of the start cell, x, y, dX, dY, fq vz).
 
 template <int NJ, int JM, int DM>
-__device__ __forceinline__ void drain_motions(typename JAcc<JM>::T *sj, uint32_t (*pq)[kPieceBuf], int n,
+__device__ __forceinline__ void drain_motions(typename JAcc<JM>::T *sj, uint32_t (*pq)[kMotionBuf], int n,
                                               float fq, int lane)
 {
     __builtin_amdgcn_wave_barrier();
@@ -287,14 +287,14 @@ __device__ __forceinline__ void drain_motions(typename JAcc<JM>::T *sj, uint32_t
 // Append the motions of the lanes with `has` set to the queue (slot order by
 // lane), draining it first if they do not fit.  n: queue fill, uniform.
 template <int NJ, int JM, int DM>
-__device__ __forceinline__ void queue_motion(typename JAcc<JM>::T *sj, uint32_t (*pq)[kPieceBuf], int &n, bool has,
+__device__ __forceinline__ void queue_motion(typename JAcc<JM>::T *sj, uint32_t (*pq)[kMotionBuf], int &n, bool has,
                                              int b, float x, float y, float dX, float dY, float az, float fq,
                                              int lane)
 {
     const unsigned long long m = __ballot(has);
     const int c = __popcll(m);
     if (c == 0) return;
-    if (n + c > kPieceBuf) {
+    if (n + c > kMotionBuf) {
         drain_motions<NJ, JM, DM>(sj, pq, n, fq, lane);
         n = 0;
     }
@@ -351,7 +351,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
     __shared__ int s_dir[kMaxSpecies][9];
     __shared__ int s_wl[kMaxSpecies][W];
     __shared__ uint32_t s_lb[W][7][kLeaverBuf];   // leaver entry + new particle data
-    __shared__ uint32_t s_pq[W][6][kPieceBuf];    // queued deposit jobs
+    __shared__ uint32_t s_pq[W][6][kMotionBuf];   // queued face-crossing motions
 
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int gx0 = tx * T, gy0 = ty * T;
@@ -401,7 +401,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             st.uz = rsrc(sp.uz + base, bytes);
             const float h = sp.h, fq = sp.fq;
             int nbuf = 0;   // leavers waiting in the wavefront's LDS buffer (uniform)
-            int npq = 0;    // pieces waiting in the wavefront's queue (uniform)
+            int npq = 0;    // motions waiting in the wavefront's queue (uniform)
             // Loads past the run's end return 0; lanes before its start (first
             // chunk of the section only) read the previous tile's particles
             // and discard them.  The next chunk is always prefetched before

@@ -63,9 +63,9 @@ constexpr int kDepEsirkepov = 1;   // Esirkepov's density decomposition (variant
 
 constexpr int kLdsBytes = 160 * 1024;   // LDS of one gfx950 compute unit
 constexpr int kLeaverBuf = 64;           // leavers buffered per wavefront before a write-out
-constexpr int kPieceBuf = 64;            // queued second / third motion pieces per wavefront
+constexpr int kMotionBuf = 64;           // queued face-crossing motions per wavefront
 // one ballot can add a whole wavefront to either buffer
-static_assert(kLeaverBuf >= 64 && kPieceBuf >= 64, "per-wavefront LDS buffers must hold 64 entries");
+static_assert(kLeaverBuf >= 64 && kMotionBuf >= 64, "per-wavefront LDS buffers must hold 64 entries");
 
 // Static LDS of the push kernel for tile T, R current replicas, mode JM and
 // halo pad H (the sort cadence: between two sorts a particle may stray up to
@@ -75,7 +75,7 @@ constexpr int push_lds_bytes(int T, int R, int JM, int H = 1)
 {
     return (T + 2 * H) * (T + 2 * H) * 48 + R * 3 * (T + 2 * H + 1) * (T + 2 * H + 1) * (JM == kJFixed ? 8 : 4) +
            kMaxSpecies * (9 + push_waves(T)) * 4 + push_waves(T) * 7 * kLeaverBuf * 4 +
-           push_waves(T) * 6 * kPieceBuf * 4;
+           push_waves(T) * 6 * kMotionBuf * 4;
 }
 
 // Sort cadences the push kernel is built for: every 1, 2 or 4 steps, with
