@@ -329,6 +329,145 @@ __device__ __forceinline__ void flush_leavers(const SpeciesDev &sp, uint32_t (*l
     __builtin_amdgcn_wave_barrier();
 }
 
+// One lane's particle of one chunk, as loaded.
+struct Chunk {
+    int cell;
+    float x, y, ux, uy, uz;
+};
+
+__device__ __forceinline__ Chunk load_chunk(const Stream6 &st, int off)
+{
+    Chunk c;
+    c.cell = (int)__builtin_amdgcn_raw_buffer_load_b32(st.cell, off, 0, kLoadCpol);
+    c.x = ldf(st.x, off);
+    c.y = ldf(st.y, off);
+    c.ux = ldf(st.ux, off);
+    c.uy = ldf(st.uy, off);
+    c.uz = ldf(st.uz, off);
+    return c;
+}
+
+// What a particle's step produces: its new state, its motion for the
+// current, and where it goes.
+struct Moved {
+    bool valid, cross;   // in the wavefront's run; motion crosses a cell face
+    int b;               // current-halo index of the start cell
+    int ncell, dir;      // new packed cell; direction of the new tile (4: same tile)
+    int err;             // error bits (kErrOrder, kErrRange), valid lanes only
+    float x, y, dX, dY, x1, y1, fqvz;
+    float xn, yn, ux, uy, uz;
+};
+
+// Interpolation, Boris push and move of one particle (no side effects, no
+// branches).  Lanes outside the run compute on a cell clamped into the halo,
+// so their LDS reads stay in bounds; their results are discarded.
+template <int T, int NJ, int NE, int H>
+__device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool valid, int gx0, int gy0,
+                                         bool tx_wrap, bool ty_wrap, float h, float fq, const float4 *s_exby,
+                                         const float4 *s_eybx, const float2 *s_ez, const float2 *s_bz)
+{
+    Moved m;
+    m.valid = valid;
+    m.err = 0;
+    const int cell = p.cell;
+    const float x = p.x, y = p.y;
+    int lx = (cell & 0xffff) - gx0, ly = (cell >> 16) - gy0;
+    if constexpr (H > 1) {
+        // since the last sort the particle may have left the tile by up to
+        // H - 1 cells, also across the periodic seam (one image lies in that
+        // band: 2H - 2 < T); a cell outside the grid is flagged below
+        const bool off_grid = cell < 0 || (cell & 0xffff) >= a.nx || (cell >> 16) >= a.ny;
+        const int wx = tx_wrap ? (lx >= T + H - 1 ? -a.nx : (lx < 1 - H ? a.nx : 0)) : 0;
+        const int wy = ty_wrap ? (ly >= T + H - 1 ? -a.ny : (ly < 1 - H ? a.ny : 0)) : 0;
+        lx = off_grid ? T + H : lx + wx;
+        ly = off_grid ? ly : ly + wy;
+    }
+    if (valid && ((unsigned)(lx + H - 1) >= (unsigned)(T + 2 * H - 2) ||
+                  (unsigned)(ly + H - 1) >= (unsigned)(T + 2 * H - 2)))
+        m.err |= kErrOrder;
+    lx = min(max(lx, 1 - H), T + H - 2);
+    ly = min(max(ly, 1 - H), T + H - 2);
+
+    // ---- interpolation (bilinear at each component's staggered point)
+    const bool xh = x >= 0.5f, yh = y >= 0.5f;
+    const float wxh = xh ? x - 0.5f : x + 0.5f;   // weight for (i+1/2) points
+    const float wyh = yh ? y - 0.5f : y + 0.5f;
+    const int ch = lx + (H - 1) + (xh ? 1 : 0);   // packed column of the half stencil
+    const int rh = ly + (H - 1) + (yh ? 1 : 0);
+    const int c0 = lx + H, r0 = ly + H;
+    const int e0 = __mul24(r0, NE), eh = __mul24(rh, NE);
+    const float4 p0 = s_exby[e0 + ch], p1 = s_exby[e0 + NE + ch];
+    const float4 q0 = s_eybx[eh + c0], q1 = s_eybx[eh + NE + c0];
+    const float2 z0 = s_ez[e0 + c0], z1 = s_ez[e0 + NE + c0];
+    const float2 b0 = s_bz[eh + ch], b1 = s_bz[eh + NE + ch];
+    const float Ex = lerpf(lerpf(p0.x, p0.z, wxh), lerpf(p1.x, p1.z, wxh), y);
+    const float By = lerpf(lerpf(p0.y, p0.w, wxh), lerpf(p1.y, p1.w, wxh), y);
+    const float Ey = lerpf(lerpf(q0.x, q0.z, x), lerpf(q1.x, q1.z, x), wyh);
+    const float Bx = lerpf(lerpf(q0.y, q0.w, x), lerpf(q1.y, q1.w, x), wyh);
+    const float Ez = lerpf(lerpf(z0.x, z0.y, x), lerpf(z1.x, z1.y, x), y);
+    const float Bz = lerpf(lerpf(b0.x, b0.y, wxh), lerpf(b1.x, b1.y, wxh), wyh);
+
+    // ---- Boris push (Eqs. 6-10); 1 + |u|^2 >= 1, so the hardware
+    // reciprocal square root needs no denormal care
+    const float ux0 = p.ux, uy0 = p.uy, uz0 = p.uz;
+    const float mx = fmaf(h, Ex, ux0), my = fmaf(h, Ey, uy0), mz = fmaf(h, Ez, uz0);
+    const float gi = __builtin_amdgcn_rsqf(fmaf(mx, mx, fmaf(my, my, fmaf(mz, mz, 1.0f))));
+    const float hg = h * gi;
+    const float tx_ = hg * Bx, ty_ = hg * By, tz_ = hg * Bz;
+    const float px = fmaf(my, tz_, fmaf(-mz, ty_, mx));
+    const float py = fmaf(mz, tx_, fmaf(-mx, tz_, my));
+    const float pz = fmaf(mx, ty_, fmaf(-my, tx_, mz));
+    const float f2 = 2.0f * __builtin_amdgcn_rcpf(fmaf(tx_, tx_, fmaf(ty_, ty_, fmaf(tz_, tz_, 1.0f))));
+    const float sx_ = f2 * tx_, sy_ = f2 * ty_, sz_ = f2 * tz_;
+    const float ux = fmaf(h, Ex, fmaf(py, sz_, fmaf(-pz, sy_, mx)));
+    const float uy = fmaf(h, Ey, fmaf(pz, sx_, fmaf(-px, sz_, my)));
+    const float uz = fmaf(h, Ez, fmaf(px, sy_, fmaf(-py, sx_, mz)));
+
+    // ---- move (Eq. 11), in cells
+    const float ig = __builtin_amdgcn_rsqf(fmaf(ux, ux, fmaf(uy, uy, fmaf(uz, uz, 1.0f))));
+    float dX = ux * ig * a.cx, dY = uy * ig * a.cy;
+    const bool ok = fabsf(dX) < 1.0f && fabsf(dY) < 1.0f;
+    if (valid && !ok) m.err |= kErrRange;
+    dX = ok ? dX : 0.0f;
+    dY = ok ? dY : 0.0f;
+    const float x1 = x + dX, y1 = y + dY;
+    const int sxn = x1 >= 1.0f ? 1 : (x1 < 0.0f ? -1 : 0);
+    const int syn = y1 >= 1.0f ? 1 : (y1 < 0.0f ? -1 : 0);
+
+    // ---- current: a motion inside its cell is one piece, and there both
+    // deposits agree (x, x1 in [0, 1)); one that crosses a face is queued
+    // whole and cut (or, for Esirkepov, spread over its 4 x 4 stencil) when
+    // the queue is drained
+    m.fqvz = fq * uz * ig;
+    m.b = jcell<NJ, H>(lx, ly);
+    m.cross = valid && (sxn | syn) != 0;
+    m.x = x;
+    m.y = y;
+    m.dX = dX;
+    m.dY = dY;
+    m.x1 = x1;
+    m.y1 = y1;
+
+    // ---- new position: offset back into [0,1), cell index, periodic wrap.
+    // A backward step whose offset rounds up to 1 lies on the face: it is
+    // x = 0 of the old cell (likewise y).
+    const float xs = sxn > 0 ? x1 - 1.0f : (sxn < 0 ? x1 + 1.0f : x1);
+    const float ys = syn > 0 ? y1 - 1.0f : (syn < 0 ? y1 + 1.0f : y1);
+    const bool xr = sxn < 0 && xs >= 1.0f, yr = syn < 0 && ys >= 1.0f;
+    m.xn = xr ? 0.0f : xs;
+    m.yn = yr ? 0.0f : ys;
+    const int nlx = lx + sxn + (xr ? 1 : 0), nly = ly + syn + (yr ? 1 : 0);
+    const int gx = wrapi(gx0 + nlx, a.nx), gy = wrapi(gy0 + nly, a.ny);
+    m.ncell = gx | (gy << 16);
+    m.ux = ux;
+    m.uy = uy;
+    m.uz = uz;
+    const int dtx = tx_wrap ? (nlx < 0 ? -1 : (nlx >= T ? 1 : 0)) : 0;
+    const int dty = ty_wrap ? (nly < 0 ? -1 : (nly >= T ? 1 : 0)) : 0;
+    m.dir = (dty + 1) * 3 + (dtx + 1);
+    return m;
+}
+
 // One tile of one simulation, by the whole workgroup (push_waves(T) wavefronts).
 template <int T, int R, int JM, int DM, int H>
 __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
@@ -402,154 +541,31 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             const float h = sp.h, fq = sp.fq;
             int nbuf = 0;   // leavers waiting in the wavefront's LDS buffer (uniform)
             int npq = 0;    // motions waiting in the wavefront's queue (uniform)
+            // Two chunks per iteration: lane L holds the particles of slots
+            // cb + L and cb + 64 + L.  Their arithmetic (advance) has no side
+            // effects and no branches, so the two instruction streams
+            // interleave; the side effects (finish) follow in slot order.
             // Loads past the run's end return 0; lanes before its start (first
             // chunk of the section only) read the previous tile's particles
-            // and discard them.  The next chunk is always prefetched before
-            // the current one is processed.
-            int cb = (lo >> 6) << 6;
-            int off = (cb + lane - base) * 4;
-            int n_cell = (int)__builtin_amdgcn_raw_buffer_load_b32(st.cell, off, 0, kLoadCpol);
-            float n_x = ldf(st.x, off), n_y = ldf(st.y, off);
-            float n_ux = ldf(st.ux, off), n_uy = ldf(st.uy, off), n_uz = ldf(st.uz, off);
-            for (; cb < hi; cb += 64, off += 256) {
-                const int i = cb + lane;
-                const int cell = n_cell;
-                const float x = n_x, y = n_y;
-                float ux = n_ux, uy = n_uy, uz = n_uz;
-                n_cell = (int)__builtin_amdgcn_raw_buffer_load_b32(st.cell, off + 256, 0, kLoadCpol);
-                n_x = ldf(st.x, off + 256);
-                n_y = ldf(st.y, off + 256);
-                n_ux = ldf(st.ux, off + 256);
-                n_uy = ldf(st.uy, off + 256);
-                n_uz = ldf(st.uz, off + 256);
-                // Every lane computes; only the lanes of the run (valid) have
-                // side effects.  The others (the previous tile's particles
-                // before the run's start in the section's first chunk, zeros
-                // past its end) take their values through the same arithmetic
-                // with their cell clamped into the halo, so their LDS reads
-                // stay in bounds.  No divergent region means no values to
-                // merge at its end for the lanes that skipped it.
-                const bool valid = i >= lo && i < hi;
-                int lx = (cell & 0xffff) - gx0, ly = (cell >> 16) - gy0;
-                if constexpr (H > 1) {
-                    // since the last sort the particle may have left the
-                    // tile by up to H - 1 cells, also across the periodic
-                    // seam (one image lies in that band: 2H - 2 < T)
-                    if (cell < 0 || (cell & 0xffff) >= a.nx || (cell >> 16) >= a.ny) {
-                        lx = T + H;   // not a cell of the grid: flagged below
-                    } else {
-                        if (tx_wrap) lx += lx >= T + H - 1 ? -a.nx : (lx < 1 - H ? a.nx : 0);
-                        if (ty_wrap) ly += ly >= T + H - 1 ? -a.ny : (ly < 1 - H ? a.ny : 0);
-                    }
+            // and discard them.  The next two chunks are always prefetched
+            // before the current ones are processed.
+            auto finish = [&](const Moved &m, int i, int at) {
+                if (m.valid && !m.cross) deposit_piece<NJ, JM>(sj, m.b, m.x, m.y, m.x1, m.y1, m.fqvz, fq);
+                if (m.valid) {
+                    __builtin_amdgcn_raw_buffer_store_b32((unsigned)m.ncell, st.cell, at, 0, kStoreCpol);
+                    stf(st.x, at, m.xn);
+                    stf(st.y, at, m.yn);
+                    stf(st.ux, at, m.ux);
+                    stf(st.uy, at, m.uy);
+                    stf(st.uz, at, m.uz);
                 }
-                if (valid && ((unsigned)(lx + H - 1) >= (unsigned)(T + 2 * H - 2) ||
-                              (unsigned)(ly + H - 1) >= (unsigned)(T + 2 * H - 2)))
-                    atomicOr(a.err, kErrOrder);
-                lx = min(max(lx, 1 - H), T + H - 2);
-                ly = min(max(ly, 1 - H), T + H - 2);
-
-                // ---- interpolation (bilinear at each component's staggered point)
-                const bool xh = x >= 0.5f, yh = y >= 0.5f;
-                const float wxh = xh ? x - 0.5f : x + 0.5f;   // weight for (i+1/2) points
-                const float wyh = yh ? y - 0.5f : y + 0.5f;
-                const int ch = lx + (H - 1) + (xh ? 1 : 0);   // packed column of the half stencil
-                const int rh = ly + (H - 1) + (yh ? 1 : 0);
-                const int c0 = lx + H, r0 = ly + H;
-                const int e0 = __mul24(r0, NE), eh = __mul24(rh, NE);
-                const float4 p0 = s_exby[e0 + ch], p1 = s_exby[e0 + NE + ch];
-                const float4 q0 = s_eybx[eh + c0], q1 = s_eybx[eh + NE + c0];
-                const float2 z0 = s_ez[e0 + c0], z1 = s_ez[e0 + NE + c0];
-                const float2 b0 = s_bz[eh + ch], b1 = s_bz[eh + NE + ch];
-                const float Ex = lerpf(lerpf(p0.x, p0.z, wxh), lerpf(p1.x, p1.z, wxh), y);
-                const float By = lerpf(lerpf(p0.y, p0.w, wxh), lerpf(p1.y, p1.w, wxh), y);
-                const float Ey = lerpf(lerpf(q0.x, q0.z, x), lerpf(q1.x, q1.z, x), wyh);
-                const float Bx = lerpf(lerpf(q0.y, q0.w, x), lerpf(q1.y, q1.w, x), wyh);
-                const float Ez = lerpf(lerpf(z0.x, z0.y, x), lerpf(z1.x, z1.y, x), y);
-                const float Bz = lerpf(lerpf(b0.x, b0.y, wxh), lerpf(b1.x, b1.y, wxh), wyh);
-
-                // ---- Boris push (Eqs. 6-10); 1 + |u|^2 >= 1, so the hardware
-                // reciprocal square root needs no denormal care
-                const float mx = fmaf(h, Ex, ux), my = fmaf(h, Ey, uy), mz = fmaf(h, Ez, uz);
-                const float gi = __builtin_amdgcn_rsqf(fmaf(mx, mx, fmaf(my, my, fmaf(mz, mz, 1.0f))));
-                const float hg = h * gi;
-                const float tx_ = hg * Bx, ty_ = hg * By, tz_ = hg * Bz;
-                const float px = fmaf(my, tz_, fmaf(-mz, ty_, mx));
-                const float py = fmaf(mz, tx_, fmaf(-mx, tz_, my));
-                const float pz = fmaf(mx, ty_, fmaf(-my, tx_, mz));
-                const float f2 =
-                    2.0f * __builtin_amdgcn_rcpf(fmaf(tx_, tx_, fmaf(ty_, ty_, fmaf(tz_, tz_, 1.0f))));
-                const float sx_ = f2 * tx_, sy_ = f2 * ty_, sz_ = f2 * tz_;
-                ux = fmaf(h, Ex, fmaf(py, sz_, fmaf(-pz, sy_, mx)));
-                uy = fmaf(h, Ey, fmaf(pz, sx_, fmaf(-px, sz_, my)));
-                uz = fmaf(h, Ez, fmaf(px, sy_, fmaf(-py, sx_, mz)));
-
-                // ---- move (Eq. 11), in cells
-                const float ig = __builtin_amdgcn_rsqf(fmaf(ux, ux, fmaf(uy, uy, fmaf(uz, uz, 1.0f))));
-                float dX = ux * ig * a.cx, dY = uy * ig * a.cy;
-                if (!(fabsf(dX) < 1.0f && fabsf(dY) < 1.0f)) {
-                    if (valid) atomicOr(a.err, kErrRange);
-                    dX = 0.0f;
-                    dY = 0.0f;
-                }
-                const float x1 = x + dX, y1 = y + dY;
-                const int sxn = x1 >= 1.0f ? 1 : (x1 < 0.0f ? -1 : 0);
-                const int syn = y1 >= 1.0f ? 1 : (y1 < 0.0f ? -1 : 0);
-
-                // ---- current: a motion inside its cell is one piece, and
-                // there both deposits agree (x, x1 in [0, 1)); one that
-                // crosses a face is queued whole and cut (or, for
-                // Esirkepov, spread over its 4 x 4 stencil) when the queue
-                // is drained
-                const float fqvz = fq * uz * ig;
-                const int b = jcell<NJ, H>(lx, ly);
-                const bool cross = valid && (sxn | syn) != 0;
-                if (valid && !cross) deposit_piece<NJ, JM>(sj, b, x, y, x1, y1, fqvz, fq);
-
-                // ---- new position: offset back into [0,1), cell index, periodic wrap
-                int nlx = lx, nly = ly;
-                float xn = x1, yn = y1;
-                if (sxn > 0) {
-                    xn = x1 - 1.0f;
-                    nlx += 1;
-                } else if (sxn < 0) {
-                    xn = x1 + 1.0f;
-                    nlx -= 1;
-                    if (xn >= 1.0f) {   // rounded onto the face: it is x = 0 of the old cell
-                        xn = 0.0f;
-                        nlx += 1;
-                    }
-                }
-                if (syn > 0) {
-                    yn = y1 - 1.0f;
-                    nly += 1;
-                } else if (syn < 0) {
-                    yn = y1 + 1.0f;
-                    nly -= 1;
-                    if (yn >= 1.0f) {
-                        yn = 0.0f;
-                        nly += 1;
-                    }
-                }
-                const int gx = wrapi(gx0 + nlx, a.nx), gy = wrapi(gy0 + nly, a.ny);
-                const int ncell = gx | (gy << 16);
-                if (valid) {
-                    __builtin_amdgcn_raw_buffer_store_b32((unsigned)ncell, st.cell, off, 0, kStoreCpol);
-                    stf(st.x, off, xn);
-                    stf(st.y, off, yn);
-                    stf(st.ux, off, ux);
-                    stf(st.uy, off, uy);
-                    stf(st.uz, off, uz);
-                }
-
-                const int dtx = tx_wrap ? (nlx < 0 ? -1 : (nlx >= T ? 1 : 0)) : 0;
-                const int dty = ty_wrap ? (nly < 0 ? -1 : (nly >= T ? 1 : 0)) : 0;
-                const int dir = (dty + 1) * 3 + (dtx + 1);
-                const bool leaver = valid && dir != 4;
-                queue_motion<NJ, JM, DM>(sj, s_pq[wave], npq, cross, b, x, y, dX, dY, fqvz, fq, lane);
+                queue_motion<NJ, JM, DM>(sj, s_pq[wave], npq, m.cross, m.b, m.x, m.y, m.dX, m.dY, m.fqvz, fq,
+                                         lane);
                 // leavers go to the wavefront's LDS buffer in slot order; a full
                 // buffer is written out as whole cache lines
-                const unsigned long long m = __ballot(leaver);
-                const int c = __popcll(m);
+                const bool leaver = m.valid && m.dir != 4;
+                const unsigned long long mk = __ballot(leaver);
+                const int c = __popcll(mk);
                 if (c != 0) {
                     if (nbuf + c > kLeaverBuf) {
                         flush_leavers(sp, s_lb[wave], nbuf, (int64_t)lo + nleav, lane);
@@ -557,19 +573,37 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                         nbuf = 0;
                     }
                     if (leaver) {
-                        const int r = nbuf + lane_rank(m);
-                        s_lb[wave][0][r] = ((uint32_t)(i - begin) << 4) | (uint32_t)dir;
-                        s_lb[wave][1][r] = (uint32_t)ncell;
-                        s_lb[wave][2][r] = __float_as_uint(xn);
-                        s_lb[wave][3][r] = __float_as_uint(yn);
-                        s_lb[wave][4][r] = __float_as_uint(ux);
-                        s_lb[wave][5][r] = __float_as_uint(uy);
-                        s_lb[wave][6][r] = __float_as_uint(uz);
-                        atomicAdd(&s_dir[s][dir], 1);
+                        const int r = nbuf + lane_rank(mk);
+                        s_lb[wave][0][r] = ((uint32_t)(i - begin) << 4) | (uint32_t)m.dir;
+                        s_lb[wave][1][r] = (uint32_t)m.ncell;
+                        s_lb[wave][2][r] = __float_as_uint(m.xn);
+                        s_lb[wave][3][r] = __float_as_uint(m.yn);
+                        s_lb[wave][4][r] = __float_as_uint(m.ux);
+                        s_lb[wave][5][r] = __float_as_uint(m.uy);
+                        s_lb[wave][6][r] = __float_as_uint(m.uz);
+                        atomicAdd(&s_dir[s][m.dir], 1);
                     }
                     nbuf += c;
                 }
+            };
+            int cb = (lo >> 6) << 6;
+            int off = (cb + lane - base) * 4;
+            Chunk nA = load_chunk(st, off), nB = load_chunk(st, off + 256);
+            int errs = 0;   // error bits of this lane's particles
+            for (; cb < hi; cb += 128, off += 512) {
+                const Chunk A = nA, B = nB;
+                nA = load_chunk(st, off + 512);
+                nB = load_chunk(st, off + 768);
+                const int i = cb + lane;
+                const Moved mA = advance<T, NJ, NE, H>(a, A, i >= lo && i < hi, gx0, gy0, tx_wrap, ty_wrap, h, fq,
+                                                       s_exby, s_eybx, s_ez, s_bz);
+                const Moved mB = advance<T, NJ, NE, H>(a, B, i + 64 >= lo && i + 64 < hi, gx0, gy0, tx_wrap,
+                                                       ty_wrap, h, fq, s_exby, s_eybx, s_ez, s_bz);
+                errs |= mA.err | mB.err;
+                finish(mA, i, off);
+                finish(mB, i + 64, off + 256);
             }
+            if (errs) atomicOr(a.err, errs);
             drain_motions<NJ, JM, DM>(sj, s_pq[wave], npq, fq, lane);
             flush_leavers(sp, s_lb[wave], nbuf, (int64_t)lo + nleav, lane);
             nleav += nbuf;
