@@ -471,7 +471,8 @@ namespace {
 // the in-place sort and the leaver copies (free at initialisation, and after a
 // push when the full re-sort replaces the in-place one) and, for the
 // histogram, the leaver copies' cell array (n >= its size) or the tile
-// current halos (consumed by then).
+// current halos (consumed by then: pic_step folds them before a full
+// re-sort, on the same stream).
 TileSortArgs tile_sort_args(pic_sim *S, int s)
 {
     auto &P = S->sp[s];
@@ -862,7 +863,10 @@ int pic_step(pic_sim *S, hipStream_t stream)
     if (!S) return PIC_EINVAL;
     int rc = push_only(S, stream);
     if (rc) return rc;
-    if (S->since_sort < S->halo || !S->side) {   // no sort this step, or no second stream
+    // Unforked: no sort this step, no second stream, or the full re-sort,
+    // whose histogram may borrow the tile current halos (tiny species) that
+    // the field half still has to fold
+    if (S->since_sort < S->halo || !S->side || (S->cfg.flags & PIC_FLAG_FULL_SORT)) {
         rc = fold_current(S, stream);
         if (rc == PIC_OK && S->since_sort >= S->halo) rc = pic_sort(S, stream);
         if (rc == PIC_OK) rc = pic_field_advance(S, stream);

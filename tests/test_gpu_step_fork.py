@@ -5,7 +5,10 @@ that of the same kernels one after the other: a twin stepped through the
 separate entry points (pic_push_deposit, pic_sort, pic_field_advance, all on
 one stream) must hold bit-identical fields, particles and tile offsets after
 every step -- on the default stream and on a caller stream, with the filter,
-and with a sort cadence of 2 (whose unsorted steps take the unforked path)."""
+and with a sort cadence of 2 (whose unsorted steps take the unforked path).
+The full re-sort stays unforked: with fewer particles than its histogram has
+entries, the histogram borrows the tile current halos that the field half
+folds, so a species of 144 particles checks that case."""
 import numpy as np
 import pytest
 
@@ -33,13 +36,20 @@ def _same(a, b):
     ({}, True),
     ({"j_filter": 2}, True),
     ({"sort_every": 2}, False),
+    ({"full_sort": True, "tiny": True}, True),
 ])
 def test_forked_step_equals_the_sequential_calls(options, caller_stream):
     import torch
     from paper_2501_14795_amd import Sim
+    options = dict(options)
+    tiny = options.pop("tiny", False)
     nx = ny = 64
     spec = pw.SpeciesSpec(-1.0, (3, 3), (0.2, 0.2, 0.2), (0.3, -0.2, 0.1))
-    state = species_states(nx, ny, 16, [spec], 21)[0]
+    if tiny:   # 16 cells x 9 particles: fewer than the radix histogram's 257 entries
+        state = pw.species_state(nx, ny, 16, spec, 21, cell_box=(0, 4, 0, 4))
+        assert state["ix"].size == 144
+    else:
+        state = species_states(nx, ny, 16, [spec], 21)[0]
     E, B = pw.random_fields(nx, ny, 0.05, 21)
     stream = torch.cuda.Stream() if caller_stream else None
     forked = Sim(nx, ny, DX, DY, DT, 16, [(spec.qm, spec.q, state)], E=E, B=B, stream=stream, **options)
@@ -53,7 +63,8 @@ def test_forked_step_equals_the_sequential_calls(options, caller_stream):
         serial.field_advance()
         torch.cuda.synchronize()
         _same(forked, serial)
-    flush(f"{options or 'default'}, caller stream {caller_stream}: six forked steps equal the sequential calls")
+    flush(f"{options or 'default'}{' (144 particles)' if tiny else ''}, caller stream {caller_stream}: "
+          "six steps equal the sequential calls")
     assert forked.check() == 0 and serial.check() == 0
     forked.close()
     serial.close()
