@@ -187,7 +187,8 @@ int pic_query(const pic_config *cfg, pic_sizes *out);
  * yet (a stable sort on the tile id: inside a tile the given order is kept,
  * so grouped input is left as it is), builds tile_offset and synchronises
  * `stream`.  Returns PIC_EORDER if a cell is out of range.  On success *out
- * owns a host record that pic_destroy() frees.
+ * owns a host record, one HIP stream of default priority and two events
+ * (pic_step's fork and join), all released by pic_destroy().
  */
 int pic_init(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
              pic_sim **out);
@@ -257,10 +258,16 @@ int pic_get_window_origin(pic_sim *sim, int32_t *origin);
  * device access). */
 int pic_get_counts(pic_sim *sim, int64_t *counts);
 
-/* pic_push_deposit + pic_sort (every sort_every-th step) + pic_field_advance.
- * Issues kernels only (no memset, no synchronisation), so a caller may
- * capture it into a HIP graph; with sort_every > 1 the captured step keeps the
- * sort decision taken at capture time. */
+/* pic_push_deposit + pic_sort (every sort_every-th step) + pic_field_advance,
+ * with the same results.  In a step that sorts, the field half (J fold,
+ * filter, field advance) runs on the library's own stream beside the sort:
+ * forked from `stream` after the push with an event and joined back into
+ * `stream` before the call returns, so everything the caller enqueues on
+ * `stream` afterwards sees the whole step (the full re-sort stays on
+ * `stream`).  Issues kernels and event records/waits only (no memset, no
+ * synchronisation), so a caller may capture it into a HIP graph; with
+ * sort_every > 1 the captured step keeps the sort decision taken at capture
+ * time. */
 int pic_step(pic_sim *sim, hipStream_t stream);
 
 /* Synchronise `stream` and report (and clear) the device error flags. */
@@ -412,7 +419,9 @@ int pic_batch_query(int n, const pic_config *cfgs, size_t *bytes);
  * own caller-owned fields, workspace and particles).  batch_work: device
  * memory of pic_batch_query() bytes, 256-byte aligned, caller-owned.
  * Synchronises `stream`.  Errors as pic_init, or PIC_EINVAL if the members do
- * not share tile / j_replicas / flags / j_filter / sort_every.
+ * not share tile / j_replicas / flags / j_filter / sort_every.  The batch
+ * owns one HIP stream of default priority and two events (the fork and join
+ * of pic_batch_step), released by pic_batch_destroy(); its members own none.
  */
 int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void *batch_work,
                    size_t batch_bytes, hipStream_t stream, pic_batch **out);
@@ -420,7 +429,8 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
 /* nsteps full steps of every member (push + deposit, sort every sort_every-th
  * step, field advance): replays of the captured cycle of sort_every steps if
  * pic_batch_capture() was called and a whole cycle remains, else direct
- * launches. */
+ * launches.  As in pic_step, the field half of a sorting step runs on the
+ * batch's own stream beside the sort and is joined back into `stream`. */
 int pic_batch_step(pic_batch *b, int nsteps, hipStream_t stream);
 
 /* Capture one batched cadence cycle (sort_every steps, the last with the
@@ -442,7 +452,8 @@ void pic_batch_destroy(pic_batch *b);
 /* Static string naming a return code. */
 const char *pic_strerror(int code);
 
-/* Free the host record.  Caller buffers are untouched. */
+/* Free the host record, the library's stream (after its work has finished)
+ * and events.  Caller buffers are untouched. */
 void pic_destroy(pic_sim *sim);
 
 #ifdef __cplusplus
