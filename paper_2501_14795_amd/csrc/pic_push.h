@@ -19,9 +19,14 @@ constexpr int kCntStride = 32;       // ints per tile in the count record
 constexpr int kScanBlock = 256;      // tiles per block of the tile-count scan
 
 // Wavefronts that push one tile (one workgroup of 64 * W threads): 4 up to
-// 16 x 16 tiles; 16 for 32 x 32 tiles, whose LDS (E/B halo and current) fills
-// most of a compute unit, so a single workgroup must bring the occupancy.
-__host__ __device__ constexpr int push_waves(int T) { return T >= 32 ? 16 : 4; }
+// 16 x 16 tiles; 8 for 32 x 32 tiles, whose 70 KB of LDS (E/B halo, current,
+// motion queues) let two workgroups share a compute unit, so one tile's
+// staging and write-out overlap the other's particle stream.
+__host__ __device__ constexpr int push_waves(int T) { return T >= 32 ? 8 : 4; }
+// Waves per SIMD the 32 x 32 kernels are compiled for (two 8-wavefront
+// workgroups per CU: at most 128 VGPRs); smaller tiles fit several
+// workgroups per CU by LDS and need no register cap.
+__host__ __device__ constexpr int push_min_waves(int T) { return T >= 32 ? 4 : 1; }
 constexpr int kMaxWaves = 16;
 
 // Count record of one tile, written by the push kernel:
@@ -62,10 +67,9 @@ constexpr int kDepVB = 0;          // Villasenor-Buneman with the 1/2/3-piece sp
 constexpr int kDepEsirkepov = 1;   // Esirkepov's density decomposition (variant)
 
 constexpr int kLdsBytes = 160 * 1024;   // LDS of one gfx950 compute unit
-constexpr int kLeaverBuf = 64;           // leavers buffered per wavefront before a write-out
 constexpr int kMotionBuf = 64;           // queued face-crossing motions per wavefront
-// one ballot can add a whole wavefront to either buffer
-static_assert(kLeaverBuf >= 64 && kMotionBuf >= 64, "per-wavefront LDS buffers must hold 64 entries");
+// one ballot can add a whole wavefront to the queue
+static_assert(kMotionBuf >= 64, "the per-wavefront motion queue must hold 64 entries");
 
 // Static LDS of the push kernel for tile T, R current replicas, mode JM and
 // halo pad H (the sort cadence: between two sorts a particle may stray up to
@@ -73,9 +77,8 @@ static_assert(kLeaverBuf >= 64 && kMotionBuf >= 64, "per-wavefront LDS buffers m
 // the current halo nodes -H..T+H).
 constexpr int push_lds_bytes(int T, int R, int JM, int H = 1)
 {
-    return (T + 2 * H) * (T + 2 * H) * 48 + R * 3 * (T + 2 * H + 1) * (T + 2 * H + 1) * (JM == kJFixed ? 8 : 4) +
-           kMaxSpecies * (9 + push_waves(T)) * 4 + push_waves(T) * 7 * kLeaverBuf * 4 +
-           push_waves(T) * 6 * kMotionBuf * 4;
+    return (T + 2 * H) * (T + 2 * H) * 24 + R * 3 * (T + 2 * H + 1) * (T + 2 * H + 1) * (JM == kJFixed ? 8 : 4) +
+           kMaxSpecies * (9 + push_waves(T)) * 4 + push_waves(T) * 6 * kMotionBuf * 4;
 }
 
 // Sort cadences the push kernel is built for: every 1, 2 or 4 steps, with

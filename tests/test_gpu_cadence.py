@@ -61,6 +61,7 @@ def _outside(sim, species, tile):
     (64, 64, 8, 2, 1, False),
     (96, 64, 32, 2, 1, False),
     (32, 48, 16, 4, 1, True),
+    (64, 64, 32, 4, 1, False),    # 32 x 32 tiles with a 4-cell pad (one workgroup per CU)
 ])
 def test_cadence_replay(nx, ny, tile, k, nspecies, esirkepov):
     specs = _fast(nspecies)

@@ -177,6 +177,15 @@ def test_float_current_mode_other_tiles(tile):
     _replay_steps(64, 64, tile, specs, states, E, B, steps=2, j_float=True, label=f"float T={tile}")
 
 
+@pytest.mark.parametrize("j_float", [False, True])
+def test_four_replicas_at_32x32_tiles(j_float):
+    """The largest LDS configuration: 32 x 32 tiles with four current copies
+    (158 KB with the int64 current: one workgroup per CU)."""
+    specs, states, E, B = _uniform(nx=64, ny=64, tile=32, ppc=(2, 2), u_th=0.3, seed=14, fields=0.05)
+    _replay_steps(64, 64, 32, specs, states, E, B, steps=2, reps=4, j_float=j_float,
+                  label=f"{'float' if j_float else 'fixed'} T=32 R=4")
+
+
 def test_repeatability_fixed_point_is_bitwise():
     """Two identical runs with the default exact fixed-point current: particle
     updates, the sort and the integer current sums are all order-independent,
