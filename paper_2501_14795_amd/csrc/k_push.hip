@@ -311,6 +311,25 @@ __device__ __forceinline__ void queue_motion(typename JAcc<JM>::T *sj, uint32_t 
     n += c;
 }
 
+// Write the n leavers buffered in LDS by one wavefront to the leaver list
+// and the leaver copies, from position pos on (contiguous: whole lines).
+__device__ __forceinline__ void flush_leavers(const SpeciesDev &sp, uint32_t (*lb)[kLeaverBuf], int n,
+                                              int64_t pos, int lane)
+{
+    __builtin_amdgcn_wave_barrier();
+    if (lane < n) {
+        const int64_t q = pos + lane;
+        sp.leav[q] = lb[0][lane];
+        sp.lp.cell[q] = (int32_t)lb[1][lane];
+        sp.lp.x[q] = __uint_as_float(lb[2][lane]);
+        sp.lp.y[q] = __uint_as_float(lb[3][lane]);
+        sp.lp.ux[q] = __uint_as_float(lb[4][lane]);
+        sp.lp.uy[q] = __uint_as_float(lb[5][lane]);
+        sp.lp.uz[q] = __uint_as_float(lb[6][lane]);
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
 // One lane's particle of one chunk, as loaded.
 struct Chunk {
     int cell;
@@ -343,10 +362,10 @@ struct Moved {
 // Interpolation, Boris push and move of one particle (no side effects, no
 // branches).  Lanes outside the run compute on a cell clamped into the halo,
 // so their LDS reads stay in bounds; their results are discarded.
-template <int T, int NJ, int NE, int H>
+template <int T, int NJ, int NE, int H, class V2, class V1>
 __device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool valid, int gx0, int gy0,
-                                         bool tx_wrap, bool ty_wrap, float h, float fq, const float2 *s_exby,
-                                         const float2 *s_eybx, const float *s_ez, const float *s_bz)
+                                         bool tx_wrap, bool ty_wrap, float h, float fq, const V2 *s_exby,
+                                         const V2 *s_eybx, const V1 *s_ez, const V1 *s_bz)
 {
     Moved m;
     m.valid = valid;
@@ -378,19 +397,35 @@ __device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool
     const int rh = ly + (H - 1) + (yh ? 1 : 0);
     const int c0 = lx + H, r0 = ly + H;
     const int e0 = __mul24(r0, NE), eh = __mul24(rh, NE);
-    // each stencil: two x-neighbours (adjacent entries: one ds_read2) on two rows
-    const float2 p0 = s_exby[e0 + ch], p0r = s_exby[e0 + ch + 1];
-    const float2 p1 = s_exby[e0 + NE + ch], p1r = s_exby[e0 + NE + ch + 1];
-    const float2 q0 = s_eybx[eh + c0], q0r = s_eybx[eh + c0 + 1];
-    const float2 q1 = s_eybx[eh + NE + c0], q1r = s_eybx[eh + NE + c0 + 1];
-    const float z0 = s_ez[e0 + c0], z0r = s_ez[e0 + c0 + 1], z1 = s_ez[e0 + NE + c0], z1r = s_ez[e0 + NE + c0 + 1];
-    const float b0 = s_bz[eh + ch], b0r = s_bz[eh + ch + 1], b1 = s_bz[eh + NE + ch], b1r = s_bz[eh + NE + ch + 1];
-    const float Ex = lerpf(lerpf(p0.x, p0r.x, wxh), lerpf(p1.x, p1r.x, wxh), y);
-    const float By = lerpf(lerpf(p0.y, p0r.y, wxh), lerpf(p1.y, p1r.y, wxh), y);
-    const float Ey = lerpf(lerpf(q0.x, q0r.x, x), lerpf(q1.x, q1r.x, x), wyh);
-    const float Bx = lerpf(lerpf(q0.y, q0r.y, x), lerpf(q1.y, q1r.y, x), wyh);
-    const float Ez = lerpf(lerpf(z0, z0r, x), lerpf(z1, z1r, x), y);
-    const float Bz = lerpf(lerpf(b0, b0r, wxh), lerpf(b1, b1r, wxh), wyh);
+    // each stencil: the two x-neighbours on two rows (the values at cells
+    // (c, c+1) of a row: one entry in the packed layout, two adjacent ones
+    // -- one ds_read2 -- otherwise)
+    float Ex, By, Ey, Bx, Ez, Bz;
+    if constexpr (std::is_same<V2, float4>::value) {
+        const float4 p0 = s_exby[e0 + ch], p1 = s_exby[e0 + NE + ch];
+        const float4 q0 = s_eybx[eh + c0], q1 = s_eybx[eh + NE + c0];
+        const float2 z0 = s_ez[e0 + c0], z1 = s_ez[e0 + NE + c0];
+        const float2 b0 = s_bz[eh + ch], b1 = s_bz[eh + NE + ch];
+        Ex = lerpf(lerpf(p0.x, p0.z, wxh), lerpf(p1.x, p1.z, wxh), y);
+        By = lerpf(lerpf(p0.y, p0.w, wxh), lerpf(p1.y, p1.w, wxh), y);
+        Ey = lerpf(lerpf(q0.x, q0.z, x), lerpf(q1.x, q1.z, x), wyh);
+        Bx = lerpf(lerpf(q0.y, q0.w, x), lerpf(q1.y, q1.w, x), wyh);
+        Ez = lerpf(lerpf(z0.x, z0.y, x), lerpf(z1.x, z1.y, x), y);
+        Bz = lerpf(lerpf(b0.x, b0.y, wxh), lerpf(b1.x, b1.y, wxh), wyh);
+    } else {
+        const float2 p0 = s_exby[e0 + ch], p0r = s_exby[e0 + ch + 1];
+        const float2 p1 = s_exby[e0 + NE + ch], p1r = s_exby[e0 + NE + ch + 1];
+        const float2 q0 = s_eybx[eh + c0], q0r = s_eybx[eh + c0 + 1];
+        const float2 q1 = s_eybx[eh + NE + c0], q1r = s_eybx[eh + NE + c0 + 1];
+        const float z0 = s_ez[e0 + c0], z0r = s_ez[e0 + c0 + 1], z1 = s_ez[e0 + NE + c0], z1r = s_ez[e0 + NE + c0 + 1];
+        const float b0 = s_bz[eh + ch], b0r = s_bz[eh + ch + 1], b1 = s_bz[eh + NE + ch], b1r = s_bz[eh + NE + ch + 1];
+        Ex = lerpf(lerpf(p0.x, p0r.x, wxh), lerpf(p1.x, p1r.x, wxh), y);
+        By = lerpf(lerpf(p0.y, p0r.y, wxh), lerpf(p1.y, p1r.y, wxh), y);
+        Ey = lerpf(lerpf(q0.x, q0r.x, x), lerpf(q1.x, q1r.x, x), wyh);
+        Bx = lerpf(lerpf(q0.y, q0r.y, x), lerpf(q1.y, q1r.y, x), wyh);
+        Ez = lerpf(lerpf(z0, z0r, x), lerpf(z1, z1r, x), y);
+        Bz = lerpf(lerpf(b0, b0r, wxh), lerpf(b1, b1r, wxh), wyh);
+    }
 
     // ---- Boris push (Eqs. 6-10); 1 + |u|^2 >= 1, so the hardware
     // reciprocal square root needs no denormal care
@@ -465,12 +500,17 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
     constexpr int NT = 64 * W;         // its threads
     using Acc = typename JAcc<JM>::T;
 
-    // E/B halo: entry [r][c] holds relative cell (c-H, r-H); the two
-    // components interpolated at the same points share an entry
-    __shared__ float2 s_exby[NE * NE];   // Ex, By
-    __shared__ float2 s_eybx[NE * NE];   // Ey, Bx
-    __shared__ float s_ez[NE * NE];
-    __shared__ float s_bz[NE * NE];
+    // E/B halo: entry [r][c] holds relative cell (c-H, r-H) -- and, in the
+    // packed layout, cell (c-H+1, r-H) after it; the two components
+    // interpolated at the same points share an entry
+    constexpr bool P = push_packed(T);
+    using V2 = typename std::conditional<P, float4, float2>::type;
+    using V1 = typename std::conditional<P, float2, float>::type;
+    __shared__ V2 s_exby[NE * NE];   // Ex, By (packed: Ex, By, Ex', By')
+    __shared__ V2 s_eybx[NE * NE];   // Ey, Bx
+    __shared__ V1 s_ez[NE * NE];
+    __shared__ V1 s_bz[NE * NE];
+    __shared__ uint32_t s_lb[P ? W : 1][7][P ? kLeaverBuf : 1];   // packed layout: leaver entry + new data
     __shared__ Acc s_j[R][3 * JP];
     __shared__ int s_dir[kMaxSpecies][9];
     __shared__ int s_wl[kMaxSpecies][W];
@@ -489,10 +529,18 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
         const int64_t row = (int64_t)wrapi(gy0 - H + r, a.ny) * a.nx;
         const int64_t i0 = row + wrapi(gx0 - H + c, a.nx);
         const float *f = a.fld;
-        s_exby[e] = make_float2(f[i0], f[4 * plane + i0]);
-        s_eybx[e] = make_float2(f[plane + i0], f[3 * plane + i0]);
-        s_ez[e] = f[2 * plane + i0];
-        s_bz[e] = f[5 * plane + i0];
+        if constexpr (P) {
+            const int64_t i1 = row + wrapi(gx0 - H + 1 + c, a.nx);
+            s_exby[e] = make_float4(f[i0], f[4 * plane + i0], f[i1], f[4 * plane + i1]);
+            s_eybx[e] = make_float4(f[plane + i0], f[3 * plane + i0], f[plane + i1], f[3 * plane + i1]);
+            s_ez[e] = make_float2(f[2 * plane + i0], f[2 * plane + i1]);
+            s_bz[e] = make_float2(f[5 * plane + i0], f[5 * plane + i1]);
+        } else {
+            s_exby[e] = make_float2(f[i0], f[4 * plane + i0]);
+            s_eybx[e] = make_float2(f[plane + i0], f[3 * plane + i0]);
+            s_ez[e] = f[2 * plane + i0];
+            s_bz[e] = f[5 * plane + i0];
+        }
     }
     for (int e = tid; e < R * 3 * JP; e += NT) (&s_j[0][0])[e] = Acc(0);
     if (tid < kMaxSpecies * 9) (&s_dir[0][0])[tid] = 0;
@@ -523,6 +571,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             st.uz = rsrc(sp.uz + base, bytes);
             const float h = sp.h, fq = sp.fq;
             int npq = 0;    // motions waiting in the wavefront's queue (uniform)
+            int nbuf = 0;   // leavers waiting in the wavefront's LDS buffer (packed layout; uniform)
             // Two chunks per iteration: lane L holds the particles of slots
             // cb + L and cb + 64 + L.  Their arithmetic (advance) has no side
             // effects and no branches, so the two instruction streams
@@ -544,21 +593,46 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                 queue_motion<NJ, JM, DM>(sj, s_pq[wave], npq, m.cross, m.b, m.x, m.y, m.dX, m.dY, m.fqvz, fq,
                                          lane);
                 // leavers are appended to the wavefront's leaver sub-list in
-                // slot order, with a copy of their new data
+                // slot order, with a copy of their new data: through the
+                // wavefront's LDS buffer, written out as whole lines (packed
+                // layout), or straight from the registers
                 const bool leaver = m.valid && m.dir != 4;
                 const unsigned long long mk = __ballot(leaver);
-                if (leaver) {
-                    const int64_t q = (int64_t)lo + nleav + lane_rank(mk);
-                    sp.leav[q] = ((uint32_t)(i - begin) << 4) | (uint32_t)m.dir;
-                    sp.lp.cell[q] = m.ncell;
-                    sp.lp.x[q] = m.xn;
-                    sp.lp.y[q] = m.yn;
-                    sp.lp.ux[q] = m.ux;
-                    sp.lp.uy[q] = m.uy;
-                    sp.lp.uz[q] = m.uz;
-                    atomicAdd(&s_dir[s][m.dir], 1);
+                if constexpr (P) {
+                    const int c = __popcll(mk);
+                    if (c != 0) {
+                        if (nbuf + c > kLeaverBuf) {
+                            flush_leavers(sp, s_lb[wave], nbuf, (int64_t)lo + nleav, lane);
+                            nleav += nbuf;
+                            nbuf = 0;
+                        }
+                        if (leaver) {
+                            const int r = nbuf + lane_rank(mk);
+                            s_lb[wave][0][r] = ((uint32_t)(i - begin) << 4) | (uint32_t)m.dir;
+                            s_lb[wave][1][r] = (uint32_t)m.ncell;
+                            s_lb[wave][2][r] = __float_as_uint(m.xn);
+                            s_lb[wave][3][r] = __float_as_uint(m.yn);
+                            s_lb[wave][4][r] = __float_as_uint(m.ux);
+                            s_lb[wave][5][r] = __float_as_uint(m.uy);
+                            s_lb[wave][6][r] = __float_as_uint(m.uz);
+                            atomicAdd(&s_dir[s][m.dir], 1);
+                        }
+                        nbuf += c;
+                    }
+                } else {
+                    if (leaver) {
+                        const int64_t q = (int64_t)lo + nleav + lane_rank(mk);
+                        sp.leav[q] = ((uint32_t)(i - begin) << 4) | (uint32_t)m.dir;
+                        sp.lp.cell[q] = m.ncell;
+                        sp.lp.x[q] = m.xn;
+                        sp.lp.y[q] = m.yn;
+                        sp.lp.ux[q] = m.ux;
+                        sp.lp.uy[q] = m.uy;
+                        sp.lp.uz[q] = m.uz;
+                        atomicAdd(&s_dir[s][m.dir], 1);
+                    }
+                    nleav += __popcll(mk);
                 }
-                nleav += __popcll(mk);
             };
             int cb = (lo >> 6) << 6;
             int off = (cb + lane - base) * 4;
@@ -569,16 +643,20 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                 nA = load_chunk(st, off + 512);
                 nB = load_chunk(st, off + 768);
                 const int i = cb + lane;
-                const Moved mA = advance<T, NJ, NE, H>(a, A, i >= lo && i < hi, gx0, gy0, tx_wrap, ty_wrap, h, fq,
-                                                       s_exby, s_eybx, s_ez, s_bz);
-                const Moved mB = advance<T, NJ, NE, H>(a, B, i + 64 >= lo && i + 64 < hi, gx0, gy0, tx_wrap,
-                                                       ty_wrap, h, fq, s_exby, s_eybx, s_ez, s_bz);
+                const Moved mA = advance<T, NJ, NE, H, V2, V1>(a, A, i >= lo && i < hi, gx0, gy0, tx_wrap,
+                                                               ty_wrap, h, fq, s_exby, s_eybx, s_ez, s_bz);
+                const Moved mB = advance<T, NJ, NE, H, V2, V1>(a, B, i + 64 >= lo && i + 64 < hi, gx0, gy0,
+                                                               tx_wrap, ty_wrap, h, fq, s_exby, s_eybx, s_ez, s_bz);
                 errs |= mA.err | mB.err;
                 finish(mA, i, off);
                 finish(mB, i + 64, off + 256);
             }
             if (errs) atomicOr(a.err, errs);
             drain_motions<NJ, JM, DM>(sj, s_pq[wave], npq, fq, lane);
+            if constexpr (P) {
+                flush_leavers(sp, s_lb[wave], nbuf, (int64_t)lo + nleav, lane);
+                nleav += nbuf;
+            }
         }
         if (lane == 0) s_wl[s][wave] = nleav;
     }

@@ -27,6 +27,12 @@ __host__ __device__ constexpr int push_waves(int T) { return T >= 32 ? 8 : 4; }
 // workgroups per CU: at most 128 VGPRs); smaller tiles fit several
 // workgroups per CU by LDS and need no register cap.
 __host__ __device__ constexpr int push_min_waves(int T) { return T >= 32 ? 4 : 1; }
+// LDS layout of the push kernel.  Up to 16 x 16 tiles, where LDS is plentiful:
+// each E/B entry holds its cell and the next one in x (one 16-byte read per
+// stencil row of two components), and leavers are buffered per wavefront and
+// written out as whole lines.  32 x 32 tiles: one cell per entry and leaver
+// copies straight from registers, which is what lets two workgroups share a CU.
+__host__ __device__ constexpr bool push_packed(int T) { return T < 32; }
 constexpr int kMaxWaves = 16;
 
 // Count record of one tile, written by the push kernel:
@@ -68,8 +74,9 @@ constexpr int kDepEsirkepov = 1;   // Esirkepov's density decomposition (variant
 
 constexpr int kLdsBytes = 160 * 1024;   // LDS of one gfx950 compute unit
 constexpr int kMotionBuf = 64;           // queued face-crossing motions per wavefront
-// one ballot can add a whole wavefront to the queue
-static_assert(kMotionBuf >= 64, "the per-wavefront motion queue must hold 64 entries");
+constexpr int kLeaverBuf = 64;           // leavers buffered per wavefront (packed layout)
+// one ballot can add a whole wavefront to either buffer
+static_assert(kMotionBuf >= 64 && kLeaverBuf >= 64, "per-wavefront LDS buffers must hold 64 entries");
 
 // Static LDS of the push kernel for tile T, R current replicas, mode JM and
 // halo pad H (the sort cadence: between two sorts a particle may stray up to
@@ -77,8 +84,10 @@ static_assert(kMotionBuf >= 64, "the per-wavefront motion queue must hold 64 ent
 // the current halo nodes -H..T+H).
 constexpr int push_lds_bytes(int T, int R, int JM, int H = 1)
 {
-    return (T + 2 * H) * (T + 2 * H) * 24 + R * 3 * (T + 2 * H + 1) * (T + 2 * H + 1) * (JM == kJFixed ? 8 : 4) +
-           kMaxSpecies * (9 + push_waves(T)) * 4 + push_waves(T) * 6 * kMotionBuf * 4;
+    return (T + 2 * H) * (T + 2 * H) * (push_packed(T) ? 48 : 24) +
+           R * 3 * (T + 2 * H + 1) * (T + 2 * H + 1) * (JM == kJFixed ? 8 : 4) +
+           kMaxSpecies * (9 + push_waves(T)) * 4 + push_waves(T) * 6 * kMotionBuf * 4 +
+           (push_packed(T) ? push_waves(T) * 7 * kLeaverBuf * 4 : 0);
 }
 
 // Sort cadences the push kernel is built for: every 1, 2 or 4 steps, with
