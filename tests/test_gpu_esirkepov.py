@@ -28,7 +28,7 @@ def _specs(nspecies=1, u_th=0.1, drift=(0.0, 0.0, 0.0), ppc=(4, 4)):
             for k in range(nspecies)]
 
 
-@pytest.mark.parametrize("tile,nspecies", [(16, 1), (8, 2)])
+@pytest.mark.parametrize("tile,nspecies", [(16, 1), (8, 2), (32, 1)])
 def test_esirkepov_replay(tile, nspecies):
     nx = ny = 64
     specs = _specs(nspecies, u_th=0.2, drift=(0.3, -0.2, 0.1))
