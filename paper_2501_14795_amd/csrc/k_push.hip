@@ -684,7 +684,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
 }
 
 template <int T, int R, int JM, int DM, int H>
-__global__ void __launch_bounds__(64 * push_waves(T), push_min_waves(T)) k_push_deposit(PushArgs a)
+__global__ void __launch_bounds__(64 * push_waves(T), push_min_waves(T, R, JM, H)) k_push_deposit(PushArgs a)
 {
     push_tile<T, R, JM, DM, H>(a, blockIdx.x);
 }
@@ -693,7 +693,7 @@ __global__ void __launch_bounds__(64 * push_waves(T), push_min_waves(T)) k_push_
 // items from a shared counter (the items come largest simulations first, so
 // the expensive tiles start early and the cheap ones fill the tail).
 template <int T, int R, int JM, int DM, int H>
-__global__ void __launch_bounds__(64 * push_waves(T), push_min_waves(T)) k_push_batch(const PushArgs *__restrict__ descs,
+__global__ void __launch_bounds__(64 * push_waves(T), push_min_waves(T, R, JM, H)) k_push_batch(const PushArgs *__restrict__ descs,
                                                        const int4 *__restrict__ items, int n_items, int *counter)
 {
     __shared__ int s_item;

@@ -23,10 +23,6 @@ constexpr int kScanBlock = 256;      // tiles per block of the tile-count scan
 // motion queues) let two workgroups share a compute unit, so one tile's
 // staging and write-out overlap the other's particle stream.
 __host__ __device__ constexpr int push_waves(int T) { return T >= 32 ? 8 : 4; }
-// Waves per SIMD the 32 x 32 kernels are compiled for (two 8-wavefront
-// workgroups per CU: at most 128 VGPRs); smaller tiles fit several
-// workgroups per CU by LDS and need no register cap.
-__host__ __device__ constexpr int push_min_waves(int T) { return T >= 32 ? 4 : 1; }
 // LDS layout of the push kernel.  Up to 16 x 16 tiles, where LDS is plentiful:
 // each E/B entry holds its cell and the next one in x (one 16-byte read per
 // stencil row of two components), and leavers are buffered per wavefront and
@@ -95,6 +91,14 @@ constexpr int push_lds_bytes(int T, int R, int JM, int H = 1)
 // current halo then still overlaps at most one neighbour per axis (2H + 1 <=
 // T), a position outside the tile has one periodic image within the pad
 // (2H - 2 < T), and the LDS fits.
+// Waves per SIMD a 32 x 32 kernel is compiled for: 4 (at most 128 VGPRs)
+// where two of its 8-wavefront workgroups fit a CU's LDS, else 2; smaller
+// tiles fit several workgroups per CU by LDS and need no register cap.
+constexpr int push_min_waves(int T, int R, int JM, int H)
+{
+    return T < 32 ? 1 : (2 * push_lds_bytes(T, R, JM, H) <= kLdsBytes ? 4 : 2);
+}
+
 constexpr bool cadence_ok(int T, int H)
 {
     return (H == 1 || H == 2 || H == 4) && 2 * H + 1 <= T && push_lds_bytes(T, 1, kJFixed, H) <= kLdsBytes;
