@@ -139,6 +139,115 @@ def test_boris_pure_magnetic_rotation(ora):
         assert np.sign(ang) == np.sign(np.cross(up0, force) @ bh)
 
 
+def _rotate(v, axis, ang):
+    """v rotated about the unit vector axis by ang (right-handed; Rodrigues)."""
+    return v * math.cos(ang) + np.cross(axis, v) * math.sin(ang) + axis * (axis @ v) * (1 - math.cos(ang))
+
+
+def test_boris_parallel_electric_and_magnetic_fields(ora):
+    """E parallel to B, both non-zero: the parallel momentum gains exactly
+    (q/m) E dt, the perpendicular momentum keeps its length and turns by
+    2 atan(|q/m| |B| dt / (2 gamma-)), gamma- being the Lorentz factor after
+    the first half kick u- = u + (q/m) E dt / 2 (the reading of Eq. 10).
+
+    What fails if the oracle is wrong:
+      * gamma taken from u instead of u-: the angle check (the kick here
+        changes gamma by 5-60 %);
+      * one full E kick after the rotation (or before it) instead of the
+        two half kicks of Eqs. (6) and (9): the angle check (the rotation
+        then sees gamma(u) or gamma(u + (q/m) E dt));
+      * a wrong sign or a dropped factor in either kick: the parallel check."""
+    rng = np.random.default_rng(21)
+    for _ in range(200):
+        qm = rng.choice([-1.0, 1.0, -2.0])
+        dt = 0.07
+        bh = rng.normal(size=3)
+        bh /= np.linalg.norm(bh)
+        Bm = rng.uniform(0.5, 20.0)
+        Em = rng.choice([-1.0, 1.0]) * rng.uniform(2.0, 20.0)
+        u = rng.normal(size=3) * rng.uniform(0.05, 1.0)
+        out = ora.boris(qm, dt, np.r_[Em * bh, Bm * bh], u)
+        # parallel component: the two half kicks, nothing from the rotation
+        assert abs(out @ bh - (u @ bh + qm * Em * dt)) < 1e-13 * (1 + abs(u @ bh))
+        up0, up1 = u - (u @ bh) * bh, out - (out @ bh) * bh
+        assert abs(np.linalg.norm(up1) - np.linalg.norm(up0)) < 1e-14 * (1 + np.linalg.norm(up0))
+        um = u + 0.5 * qm * Em * dt * bh
+        gm = math.sqrt(1 + um @ um)
+        theta = 2 * math.atan(abs(qm) * Bm * dt / (2 * gm))
+        # the sense of du/dt = (q/m) u/gamma x B is a rotation about -sign(q/m) B
+        want = _rotate(up0, -np.sign(qm) * bh, theta)
+        np.testing.assert_allclose(up1, want, rtol=0, atol=1e-13 * (1 + np.linalg.norm(up0)))
+
+
+def test_boris_solves_the_time_centred_equation(ora):
+    """General E and B, both non-zero: the Boris update (Eqs. 6-10) is the
+    exact solution of the implicit, time-centred form of Eq. (4) with the
+    Lorentz factor held at gamma- (the reading of Eq. 10),
+
+        u' - u = (q/m) dt [E + (u' + u) / (2 gamma-) x B],
+        gamma- = sqrt(1 + |u + (q/m) E dt / 2|^2),
+
+    a 3 x 3 linear system for u' solved here with numpy.  Every arithmetic
+    slip in the explicit sequence (a dropped half kick, gamma of u instead of
+    u-, a sign in either cross product, s = t instead of 2t / (1 + t^2))
+    breaks the equality."""
+    rng = np.random.default_rng(22)
+    for _ in range(300):
+        qm = rng.choice([-1.0, 1.0, -0.01, 3.0])
+        dt = 0.07
+        E = rng.normal(size=3) * rng.uniform(0.1, 20.0)
+        B = rng.normal(size=3) * rng.uniform(0.1, 20.0)
+        u = rng.normal(size=3) * rng.uniform(0.01, 3.0)
+        out = ora.boris(qm, dt, np.r_[E, B], u)
+        a = qm * dt
+        um = u + 0.5 * a * E
+        k = a / (2 * math.sqrt(1 + um @ um))
+        # u' - k u' x B = u + aE + k u x B, with u' x B = -[B]x u'
+        Bx = np.array([[0, -B[2], B[1]], [B[2], 0, -B[0]], [-B[1], B[0], 0]])
+        want = np.linalg.solve(np.eye(3) + k * Bx, u + a * E + k * np.cross(u, B))
+        np.testing.assert_allclose(out, want, rtol=0, atol=1e-12 * (1 + np.linalg.norm(want)))
+
+
+def test_boris_keeps_the_exb_drift(ora):
+    """Crossed E and B (|E| < |B|): a particle whose momentum is gamma- v_E,
+    v_E = E x B / |B|^2 the drift velocity, feels no net force
+    (E + v_E x B = 0) and keeps its momentum; any other perpendicular momentum
+    w = u - gamma- v_E turns rigidly about B (the drift frame).  gamma- is
+    that of u- = u + (q/m) E dt / 2; for u = gamma- v_E it has the closed
+    form |u|^2 = (1 + (q/m)^2 E^2 dt^2 / 4) |v_E|^2 / (1 - |v_E|^2).
+    gamma of u instead of u-, or a single full E kick, leaves a residual
+    force and fails the first check."""
+    rng = np.random.default_rng(23)
+    for _ in range(200):
+        qm = rng.choice([-1.0, 1.0])
+        dt = 0.07
+        bh = rng.normal(size=3)
+        bh /= np.linalg.norm(bh)
+        eh = np.cross(bh, rng.normal(size=3))
+        eh /= np.linalg.norm(eh)
+        Bm = rng.uniform(1.0, 10.0)
+        Em = Bm * rng.uniform(0.05, 0.9)
+        E, B = Em * eh, Bm * bh
+        vE = np.cross(E, B) / (Bm * Bm)
+        h2 = (0.5 * qm * Em * dt) ** 2
+        umag = math.sqrt((1 + h2) * (vE @ vE) / (1 - vE @ vE))
+        u = umag * vE / np.linalg.norm(vE)
+        out = ora.boris(qm, dt, np.r_[E, B], u)
+        np.testing.assert_allclose(out, u, rtol=0, atol=1e-13 * (1 + umag))
+        # add a perpendicular offset w and a parallel momentum p: in the drift
+        # frame w turns by 2 atan(|q/m| B dt / (2 gamma-)), p is untouched
+        w = np.cross(bh, eh) * rng.uniform(-1, 1) + eh * rng.uniform(-1, 1)
+        p = rng.uniform(-1, 1)
+        u2 = u + w + p * bh
+        um = u2 + 0.5 * qm * dt * E
+        gm = math.sqrt(1 + um @ um)
+        out2 = ora.boris(qm, dt, np.r_[E, B], u2)
+        theta = 2 * math.atan(abs(qm) * Bm * dt / (2 * gm))
+        drift = gm * vE
+        want = drift + _rotate(u2 - drift - p * bh, -np.sign(qm) * bh, theta) + p * bh
+        np.testing.assert_allclose(out2, want, rtol=0, atol=1e-12 * (1 + np.linalg.norm(want)))
+
+
 def test_cyclotron_orbit_radius(ora):
     """Uniform B_z, full particle advance (interp + Boris + Eq. 11): the
     positions are the vertices of a regular polygon whose circumradius is
