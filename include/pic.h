@@ -70,17 +70,18 @@ extern "C" {
 #define PIC_ERANGE (-6)   /* a particle tried to move one cell or more in a step */
 #define PIC_ESORT (-7)    /* internal sort consistency check failed */
 #define PIC_ECOUNT (-8)   /* tile counts do not add up to the particle count */
-#define PIC_EOVERFLOW (-9) /* fixed-point current: 2^16+ contributions to one node of one tile */
+#define PIC_EOVERFLOW (-9) /* fixed-point current: a tile holds 2^31+ particles over all species */
 #define PIC_ENOCONV (-10)  /* pic_solve_gauss: the iteration did not reach its tolerance */
 
 /*
  * Current accumulation inside a tile (pic_config.flags).
- * Default (0): exact 64-bit fixed point -- each deposit contribution is
- *   rounded once, to within 2^-23 of the largest possible contribution (max
- *   |q| moving one cell), sums are exact, J is bit-reproducible from run to
- *   run.
- *   Limit: fewer than 2^16 contributions to one node within one tile per step
- *   (else PIC_EOVERFLOW), i.e. a few thousand particles per cell.
+ * Default (0): exact 64-bit fixed point -- each deposit contribution is the
+ *   FP32 product of charge, motion and weight truncated to a unit of 2^-30 of
+ *   the largest possible contribution (max |q| moving one cell, or at c for
+ *   Jz), the sums are exact signed 64-bit integers, J is bit-reproducible
+ *   from run to run and does not depend on the order of the additions.
+ *   Limit: fewer than 2^31 particles in one tile over all species (else
+ *   PIC_EOVERFLOW), which keeps every sum inside 64 bits.
  * PIC_FLAG_J_FLOAT: FP32 atomic adds into j_replicas LDS copies, summed with
  *   compensation; J reproducible only to round-off (and slower on gfx950).
  */

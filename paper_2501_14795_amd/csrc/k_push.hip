@@ -23,9 +23,9 @@
 //      so the cutting and the extra deposits run on full wavefronts instead of
 //      on the few lanes of each wavefront that cross:
 //        kJFixed  exact int64 fixed point (ds_add_u64): every contribution is
-//                 rounded once, to within 2^-23 of the largest possible
-//                 contribution, the sums are exact, so J does not depend on
-//                 the order of the additions -- bit-reproducible;
+//                 the FP32 product truncated to 2^-30 of the largest
+//                 possible contribution, the sums are exact, so J does not
+//                 depend on the order of the additions -- bit-reproducible;
 //        kJFloat  FP32 ds_add_f32 into one of R replicas (lane mod R), the
 //                 replicas summed with compensation at the end.  Kept as the
 //                 reference mode: on gfx950 FP32 LDS atomics are several times
@@ -89,33 +89,31 @@ __device__ __forceinline__ void stf(__amdgpu_buffer_rsrc_t r, int off, float v)
 template <int JM>
 struct JAcc;
 
-// Exact fixed point.  A contribution a*w (|a*w| <= 2^22 units) is stored as
-// u = a*w + 3*2^22, an integer in [2^23, 2^24): a single fma rounds it to the
-// nearest integer, because floats in [2^23, 2^24) are spaced by exactly one.
-// Each 64-bit add also carries 2^40, so the high bits count the
-// contributions and the bias is removed exactly at the end; the low 40 bits
-// cannot carry into the count while a node takes fewer than 2^16
-// contributions per tile (checked).
+// Exact fixed point.  A contribution a*w (|a*w| <= 2^30 units: the largest
+// particle charge moving one cell, or at c for Jz) is rounded once, in the
+// FP32 product, then truncated to a whole unit (2^-30 of the largest
+// contribution) and added as a signed 64-bit integer.  The sums are exact,
+// so J does not depend on the order of the additions; they cannot overflow
+// while a tile holds fewer than 2^31 particles (checked), since a particle
+// adds to one node at most three times per component.
 template <>
 struct JAcc<kJFixed> {
-    using T = unsigned long long;
-    static constexpr unsigned long long kCount = 1ull << 40;
-    static constexpr float kBias = 12582912.0f;   // 3 * 2^22
+    using T = unsigned long long;   // two's complement int64 (ds_add_u64)
     __device__ static __forceinline__ void add(T *p, float a, float w)
     {
-        const unsigned u = (unsigned)fmaf(a, w, kBias);
-        atomicAdd(p, kCount | (T)u);
+        const int v = (int)(a * w);
+        atomicAdd(p, (T)(long long)v);
     }
-    __device__ static __forceinline__ float value(const T *p, int replicas, int stride, float unit, int *err)
+    // int64 -> float without FP64: s = hi 2^32 + lo with lo a signed 32-bit
+    // remainder, so a small negative sum is not the difference of two large
+    // numbers; hi is exact in FP32 while |s| < 2^55
+    __device__ static __forceinline__ float value(const T *p, int replicas, int stride, float unit, int *)
     {
         long long s = 0;
-        for (int r = 0; r < replicas; ++r) {
-            const T t = p[r * stride];
-            const long long count = (long long)(t >> 40);
-            if (count >= 65536) atomicOr(err, kErrOverflow);
-            s += (long long)(t & (kCount - 1)) - count * 12582912ll;
-        }
-        return (float)((double)s * (double)unit);
+        for (int r = 0; r < replicas; ++r) s += (long long)p[r * stride];
+        const int hi = (int)((s + 0x80000000ll) >> 32);
+        const int lo = (int)(s - ((long long)hi << 32));
+        return fmaf((float)hi, 4294967296.0f, (float)lo) * unit;
     }
 };
 
@@ -147,18 +145,21 @@ __device__ __forceinline__ int jcell(int cx, int cy)
 }
 
 // Current of one piece of the motion inside the cell at halo index b, from
-// (xa, ya) to (xb, yb) in that cell's frame, in accumulator units (fq =
+// (xa, ya) in that cell's frame by (dxk, dyk), in accumulator units (fq =
 // particle charge in those units; az = fq vz times the piece's share of the
 // step).  Jx/Jy: the Villasenor-Buneman face fluxes; Jz: az times the exact
 // time average of each corner's bilinear weight, w_mid +- dxk dyk / 12.
+// The piece is given by its displacement, not its end point: for a small
+// motion the difference of two offsets near 1/2 would carry an absolute
+// rounding error of half an ulp of the offset (3e-8), a large relative
+// error of the flux when the motion is a thousandth of a cell.
 template <int NJ, int JM>
-__device__ __forceinline__ void deposit_piece(typename JAcc<JM>::T *sj, int b, float xa, float ya, float xb,
-                                              float yb, float az, float fq)
+__device__ __forceinline__ void deposit_piece(typename JAcc<JM>::T *sj, int b, float xa, float ya, float dxk,
+                                              float dyk, float az, float fq)
 {
     constexpr int P = NJ * NJ;
     using A = JAcc<JM>;
-    const float dxk = xb - xa, dyk = yb - ya;
-    const float xm = 0.5f * (xa + xb), ym = 0.5f * (ya + yb);
+    const float xm = fmaf(0.5f, dxk, xa), ym = fmaf(0.5f, dyk, ya);
     const float ax = fq * dxk, ay = fq * dyk;
     const float c = dxk * dyk * (1.0f / 12.0f);
     const float xm1 = 1.0f - xm, ym1 = 1.0f - ym;
@@ -175,8 +176,12 @@ __device__ __forceinline__ void deposit_piece(typename JAcc<JM>::T *sj, int b, f
 // Villasenor-Buneman current of a motion that crosses one or two cell faces,
 // from (x, y) in the cell at halo index b by (dX, dY) cells (|dX|, |dY| < 1):
 // the motion is cut at the face crossings in time order, and piece k lies in
-// the cell reached after k crossings, in whose frame its endpoints are taken
-// (az: fq vz for the whole step, shared among the pieces by duration).
+// the cell reached after k crossings, in whose frame it starts (az: fq vz
+// for the whole step, shared among the pieces by duration).  The pieces'
+// displacements are differences of the motion's cumulative displacement at
+// the crossings -- the distance to the face on the crossing axis (exact),
+// the crossing time times the motion on the other -- so they add up to
+// (dX, dY) to within an ulp of the motion.
 template <int NJ, int JM>
 __device__ __forceinline__ void deposit_split(typename JAcc<JM>::T *sj, int b, float x, float y, float dX,
                                               float dY, float az, float fq)
@@ -192,23 +197,20 @@ __device__ __forceinline__ void deposit_split(typename JAcc<JM>::T *sj, int b, f
     const bool three = sxn != 0 && syn != 0;
     const float t1 = xfirst ? tcx : tcy;
     const float t2 = xfirst ? tcy : tcx;
-    // crossing points (start-cell frame)
-    const float p1x = xfirst ? ex : fmaf(t1, dX, x);
-    const float p1y = xfirst ? fmaf(t1, dY, y) : ey;
-    const float p2x = xfirst ? fmaf(t2, dX, x) : ex;
-    const float p2y = xfirst ? ey : fmaf(t2, dY, y);
+    // cumulative displacement at the first and second crossing
+    const float X1 = xfirst ? ex - x : t1 * dX, Y1 = xfirst ? t1 * dY : ey - y;
+    const float X2 = three ? (xfirst ? t2 * dX : ex - x) : dX;
+    const float Y2 = three ? (xfirst ? ey - y : t2 * dY) : dY;
     // piece 0, in the start cell
-    deposit_piece<NJ, JM>(sj, b, clamp01(x), clamp01(y), clamp01(p1x), clamp01(p1y), az * t1, fq);
+    deposit_piece<NJ, JM>(sj, b, x, y, X1, Y1, az * t1, fq);
     // piece 1, after the first crossing
     const int ox = xfirst ? sxn : 0, oy = xfirst ? 0 : syn;
-    const float e1x = three ? p2x : x1, e1y = three ? p2y : y1;
-    const float f1 = three ? t2 : 1.0f;
-    deposit_piece<NJ, JM>(sj, b + oy * NJ + ox, clamp01(p1x - ox), clamp01(p1y - oy), clamp01(e1x - ox),
-                          clamp01(e1y - oy), az * (f1 - t1), fq);
+    deposit_piece<NJ, JM>(sj, b + oy * NJ + ox, clamp01(x + X1 - (float)ox), clamp01(y + Y1 - (float)oy), X2 - X1,
+                          Y2 - Y1, az * ((three ? t2 : 1.0f) - t1), fq);
     // piece 2, after both crossings
     if (three)
-        deposit_piece<NJ, JM>(sj, b + syn * NJ + sxn, clamp01(p2x - sxn), clamp01(p2y - syn), clamp01(x1 - sxn),
-                              clamp01(y1 - syn), az * (1.0f - t2), fq);
+        deposit_piece<NJ, JM>(sj, b + syn * NJ + sxn, clamp01(x + X2 - (float)sxn), clamp01(y + Y2 - (float)syn),
+                              dX - X2, dY - Y2, az * (1.0f - t2), fq);
 }
 
 // Esirkepov's current of a whole straight motion (the variant deposit) from
@@ -319,13 +321,13 @@ __device__ __forceinline__ void flush_leavers(const SpeciesDev &sp, uint32_t (*l
     __builtin_amdgcn_wave_barrier();
     if (lane < n) {
         const int64_t q = pos + lane;
-        sp.leav[q] = lb[0][lane];
-        sp.lp.cell[q] = (int32_t)lb[1][lane];
-        sp.lp.x[q] = __uint_as_float(lb[2][lane]);
-        sp.lp.y[q] = __uint_as_float(lb[3][lane]);
-        sp.lp.ux[q] = __uint_as_float(lb[4][lane]);
-        sp.lp.uy[q] = __uint_as_float(lb[5][lane]);
-        sp.lp.uz[q] = __uint_as_float(lb[6][lane]);
+        gp(sp.leav)[q] = lb[0][lane];
+        gp(sp.lp.cell)[q] = (int32_t)lb[1][lane];
+        gp(sp.lp.x)[q] = __uint_as_float(lb[2][lane]);
+        gp(sp.lp.y)[q] = __uint_as_float(lb[3][lane]);
+        gp(sp.lp.ux)[q] = __uint_as_float(lb[4][lane]);
+        gp(sp.lp.uy)[q] = __uint_as_float(lb[5][lane]);
+        gp(sp.lp.uz)[q] = __uint_as_float(lb[6][lane]);
     }
     __builtin_amdgcn_wave_barrier();
 }
@@ -355,7 +357,7 @@ struct Moved {
     int b;               // current-halo index of the start cell
     int ncell, dir;      // new packed cell; direction of the new tile (4: same tile)
     int err;             // error bits (kErrOrder, kErrRange), valid lanes only
-    float x, y, dX, dY, x1, y1, fqvz;
+    float x, y, dX, dY, fqvz;
     float xn, yn, ux, uy, uz;
 };
 
@@ -465,8 +467,6 @@ __device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool
     m.y = y;
     m.dX = dX;
     m.dY = dY;
-    m.x1 = x1;
-    m.y1 = y1;
 
     // ---- new position: offset back into [0,1), cell index, periodic wrap.
     // A backward step whose offset rounds up to 1 lies on the face: it is
@@ -528,7 +528,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
         const int r = e / NE, c = e - r * NE;
         const int64_t row = (int64_t)wrapi(gy0 - H + r, a.ny) * a.nx;
         const int64_t i0 = row + wrapi(gx0 - H + c, a.nx);
-        const float *f = a.fld;
+        const PIC_GLOBAL float *f = gp(a.fld);
         if constexpr (P) {
             const int64_t i1 = row + wrapi(gx0 - H + 1 + c, a.nx);
             s_exby[e] = make_float4(f[i0], f[4 * plane + i0], f[i1], f[4 * plane + i1]);
@@ -551,7 +551,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
 
     for (int s = 0; s < a.n_species; ++s) {
         const SpeciesDev sp = a.sp[s];
-        const int begin = sp.off[tile], end = sp.off[tile + 1];
+        const int begin = gp(sp.off)[tile], end = gp(sp.off)[tile + 1];
         int lo, hi;
         wave_range(begin, end, wave, W, lo, hi);
         int nleav = 0;   // wavefront-uniform
@@ -581,7 +581,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             // and discard them.  The next two chunks are always prefetched
             // before the current ones are processed.
             auto finish = [&](const Moved &m, int i, int at) {
-                if (m.valid && !m.cross) deposit_piece<NJ, JM>(sj, m.b, m.x, m.y, m.x1, m.y1, m.fqvz, fq);
+                if (m.valid && !m.cross) deposit_piece<NJ, JM>(sj, m.b, m.x, m.y, m.dX, m.dY, m.fqvz, fq);
                 if (m.valid) {
                     __builtin_amdgcn_raw_buffer_store_b32((unsigned)m.ncell, st.cell, at, 0, kStoreCpol);
                     stf(st.x, at, m.xn);
@@ -622,13 +622,13 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                 } else {
                     if (leaver) {
                         const int64_t q = (int64_t)lo + nleav + lane_rank(mk);
-                        sp.leav[q] = ((uint32_t)(i - begin) << 4) | (uint32_t)m.dir;
-                        sp.lp.cell[q] = m.ncell;
-                        sp.lp.x[q] = m.xn;
-                        sp.lp.y[q] = m.yn;
-                        sp.lp.ux[q] = m.ux;
-                        sp.lp.uy[q] = m.uy;
-                        sp.lp.uz[q] = m.uz;
+                        gp(sp.leav)[q] = ((uint32_t)(i - begin) << 4) | (uint32_t)m.dir;
+                        gp(sp.lp.cell)[q] = m.ncell;
+                        gp(sp.lp.x)[q] = m.xn;
+                        gp(sp.lp.y)[q] = m.yn;
+                        gp(sp.lp.ux)[q] = m.ux;
+                        gp(sp.lp.uy)[q] = m.uy;
+                        gp(sp.lp.uz)[q] = m.uz;
                         atomicAdd(&s_dir[s][m.dir], 1);
                     }
                     nleav += __popcll(mk);
@@ -651,7 +651,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                 finish(mA, i, off);
                 finish(mB, i + 64, off + 256);
             }
-            if (errs) atomicOr(a.err, errs);
+            if (errs) set_err(a.err, errs);
             drain_motions<NJ, JM, DM>(sj, s_pq[wave], npq, fq, lane);
             if constexpr (P) {
                 flush_leavers(sp, s_lb[wave], nbuf, (int64_t)lo + nleav, lane);
@@ -662,21 +662,28 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
     }
     __syncthreads();
 
+    // the int64 current sums are exact while the tile holds fewer than 2^31
+    // particles over all species
+    if (JM == kJFixed && tid == 0) {
+        int64_t total = 0;
+        for (int s = 0; s < a.n_species; ++s) total += gp(a.sp[s].off)[tile + 1] - gp(a.sp[s].off)[tile];
+        if (total >= (int64_t(1) << 31)) set_err(a.err, kErrOverflow);
+    }
     // per-tile count records
     if (tid < a.n_species * kCntStride) {
         const int s = tid / kCntStride, k = tid % kCntStride;
-        const int n = a.sp[s].off[tile + 1] - a.sp[s].off[tile];
+        const int n = gp(a.sp[s].off)[tile + 1] - gp(a.sp[s].off)[tile];
         int leavers = 0;
         for (int w = 0; w < W; ++w) leavers += s_wl[s][w];
         int v = 0;
         if (k < 9) v = (k == 4) ? n - leavers : s_dir[s][k];
         else if (k == kCntLeavers) v = leavers;
         else if (k < kCntSub + W) v = s_wl[s][k - kCntSub];
-        a.sp[s].cnt[(int64_t)tile * kCntStride + k] = v;
+        gp(a.sp[s].cnt)[(int64_t)tile * kCntStride + k] = v;
     }
 
     // the tile's current halo in physical units
-    float *out = a.jtile + (int64_t)tile * 3 * JP;
+    PIC_GLOBAL float *out = gp(a.jtile) + (int64_t)tile * 3 * JP;
     for (int e = tid; e < 3 * JP; e += NT) {
         const int comp = e / JP;
         out[e] = JAcc<JM>::value(&s_j[0][e], R, 3 * JP, a.ju[comp], a.err);

@@ -315,7 +315,7 @@ PushArgs push_args(const pic_sim *S)
     a.cx = (float)(c.dt / c.dx);
     a.cy = (float)(c.dt / c.dy);
     // accumulator units: the largest particle charge moving one cell (Jx, Jy)
-    // or at the speed of light (Jz) is 1 (x 2^24 in fixed point)
+    // or at the speed of light (Jz) is 1 (x 2^30 in fixed point)
     double qmax = 0.0;
     for (int s = 0; s < c.n_species; ++s) qmax = std::max(qmax, fabs(c.species[s].q));
     if (qmax == 0.0) qmax = 1.0;
@@ -445,7 +445,7 @@ const char *pic_strerror(int code)
     case PIC_ERANGE: return "a particle moved one cell or more in one step";
     case PIC_ESORT: return "sort consistency check failed";
     case PIC_ECOUNT: return "tile counts do not add up to the particle count";
-    case PIC_EOVERFLOW: return "a tile current accumulator took 2^16 or more contributions to one node";
+    case PIC_EOVERFLOW: return "a tile holds 2^31 or more particles (its fixed-point current could overflow)";
     case PIC_ENOCONV: return "the Poisson iteration did not reach its tolerance";
     default: return "unknown error";
     }

@@ -12,6 +12,21 @@
 
 namespace pic {
 
+// A pointer into device global memory, marked as such: loads and stores
+// through it are global_* instructions (scalar base + 32-bit lane offset)
+// rather than flat ones, which a kernel would otherwise issue for pointers it
+// reads from memory (the batched kernels' per-simulation descriptors).
+#define PIC_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ PIC_GLOBAL T *gp(T *p)
+{
+    return (PIC_GLOBAL T *)p;
+}
+__device__ __forceinline__ void set_err(int *err, int bits)
+{
+    __hip_atomic_fetch_or(gp(err), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int kMaxSpecies = PIC_MAX_SPECIES;
 constexpr int kBlock = 256;          // threads per sort / stencil block (4 wavefronts)
 constexpr int kSortWaves = kBlock / 64;   // tiles per sort plan / scatter block (one per wavefront)
@@ -48,7 +63,7 @@ enum : int {
     kErrRange = 2,   // displacement of one cell or more
     kErrSort = 4,    // hole / mover count mismatch
     kErrCount = 8,   // tile counts do not sum to n
-    kErrOverflow = 16, // a fixed-point current accumulator took 2^16 contributions or more
+    kErrOverflow = 16, // a tile holds 2^31 particles or more (its fixed-point current could overflow)
     kErrGroup = 32,  // caller particles not grouped by tile (cells in range)
 };
 
@@ -60,9 +75,9 @@ enum : int {
 
 // Fixed-point resolution: one current contribution of the largest possible
 // magnitude (the particle charge of the largest species times a full cell of
-// motion) is 2^22 units; each contribution is rounded once to a unit
-// (error at most 2^-23 of the largest one) and the sums are exact.
-constexpr float kFixedScale = 4194304.0f;
+// motion, or at the speed of light for Jz) is 2^30 units; each contribution
+// is the FP32 product truncated to a unit, and the sums are exact.
+constexpr float kFixedScale = 1073741824.0f;
 
 // deposit scheme of the push kernel
 constexpr int kDepVB = 0;          // Villasenor-Buneman with the 1/2/3-piece split (Eqs. 13-16)
@@ -91,12 +106,14 @@ constexpr int push_lds_bytes(int T, int R, int JM, int H = 1)
 // current halo then still overlaps at most one neighbour per axis (2H + 1 <=
 // T), a position outside the tile has one periodic image within the pad
 // (2H - 2 < T), and the LDS fits.
-// Waves per SIMD a 32 x 32 kernel is compiled for: 4 (at most 128 VGPRs)
-// where two of its 8-wavefront workgroups fit a CU's LDS, else 2; smaller
-// tiles fit several workgroups per CU by LDS and need no register cap.
+// Waves per SIMD a push kernel is compiled for (its register budget): the
+// workgroups of its size that fit a CU's LDS, at most 4 waves per SIMD (128
+// VGPRs).  A 4-wavefront workgroup (tiles up to 16 x 16) puts one wave on
+// each SIMD, an 8-wavefront one (32 x 32) two.
 constexpr int push_min_waves(int T, int R, int JM, int H)
 {
-    return T < 32 ? 1 : (2 * push_lds_bytes(T, R, JM, H) <= kLdsBytes ? 4 : 2);
+    return T < 32 ? (kLdsBytes / push_lds_bytes(T, R, JM, H) < 4 ? kLdsBytes / push_lds_bytes(T, R, JM, H) : 4)
+                  : (2 * push_lds_bytes(T, R, JM, H) <= kLdsBytes ? 4 : 2);
 }
 
 constexpr bool cadence_ok(int T, int H)

@@ -131,3 +131,88 @@ def test_autotuner_picks_the_fastest_valid_candidate():
     assert set(timings) == {(8, 1, 1), (16, 1, 1), (16, 1, 2), (16, 1, 4)}
     assert best == min(timings, key=timings.get)
     assert all(v > 0 for v in timings.values())
+
+
+class _Sp:
+    def __init__(self, qm, q):
+        self.qm, self.q = qm, q
+
+
+@pytest.mark.parametrize("tile,every", [(8, 1), (16, 1), (32, 1), (16, 2), (8, 2)])
+def test_batch_members_against_the_oracle(tile, every):
+    """Every member of a batch against the FP64 oracle.
+
+    Four batched steps (two direct, two graph replays) beside a free-running
+    OracleSim per member, sorted every step (particle order does not change
+    the physics): E, B and J within 1e-5 of their max, particles within 1e-5
+    after nearest-neighbour pairing (with a cadence of 2 they are unsorted
+    half of the time).  Then one cadence cycle of batched steps, each
+    replayed by the oracle from the member's own state: J, E and B within
+    1e-5, particles slot by slot within 1e-5, and the sort bit-exact against
+    the oracle's canonical sort of the post-push cells.  A standalone twin of
+    every member, stepped alongside, exposes the post-push state the batched
+    step does not return; the batch equals the twins bit for bit after every
+    step, so what is checked on the twin holds for the batch."""
+    import oracle
+    from _parity import PARTICLE_ARRAYS, matched_particle_errors, oracle_from_gpu, particle_errors, rel_err
+    from paper_2501_14795_amd import Batch, Sim
+    members = _members(6, 31 + tile + every, tile, sizes=(32, 64, 96) if tile == 32 else (32, 48, 64, 96))
+    batch = Batch(members, tile=tile, sort_every=every)
+    twins = [Sim(m["nx"], m["ny"], m["dx"], m["dy"], m["dt"], tile, m["species"], sort_every=every)
+             for m in members]
+    oras, sps = [], []
+    for m in members:
+        (qm, q, st), = m["species"]
+        sps.append(_Sp(qm, q))
+        osp = oracle.OracleSpecies(qm, q, st["ix"], st["iy"], st["x"], st["y"], st["ux"], st["uy"], st["uz"])
+        oras.append(oracle.OracleSim(m["nx"], m["ny"], m["dx"], m["dy"], m["dt"], [osp]))
+    for step in range(4):
+        if step == 2:
+            batch.capture()
+        batch.step()
+        for t in twins:
+            t.step()
+        for o in oras:
+            o.step(T=tile)
+    assert batch.check() == 0
+    for i, (m, o) in enumerate(zip(members, oras)):
+        f = batch[i].field_arrays()
+        errs = {k: rel_err(f[k], getattr(o, k)) for k in ("E", "B", "J")}
+        pos, du, matched = matched_particle_errors(batch[i].state(0), o.species[0], m["nx"], m["ny"])
+        flush(f"T={tile} k={every} member {i} ({m['nx']}x{m['ny']}): 4 steps vs free-running oracle: "
+              + " ".join(f"{k} {v:.2e}" for k, v in errs.items()) + f"; particles pos {pos:.2e} u {du:.2e}")
+        assert max(errs.values()) < 1e-5 and pos < 1e-5 and du < 1e-5
+        _assert_same(batch[i], twins[i])
+    for j in range(every):
+        sorts = j == every - 1
+        for i, m in enumerate(members):
+            ref = oracle_from_gpu(batch[i], [sps[i]], m["dx"], m["dy"], m["dt"])
+            ref.push_deposit()
+            tw = twins[i]
+            tw.push_deposit()
+            post = tw.state(0)
+            pos, du = particle_errors(post, ref.species[0], m["nx"], m["ny"])
+            ej = rel_err(tw.field_arrays()["J"], ref.J)
+            assert pos < 1e-5 and du < 1e-5 and ej < 1e-5, (i, pos, du, ej)
+            if sorts:
+                off, src = oracle.sort_canonical(m["nx"], m["ny"], tile, post["ix"], post["iy"])
+                tw.sort()
+                srt = tw.state(0)
+                assert np.array_equal(tw.tile_offsets(0), off)
+                for k in PARTICLE_ARRAYS:
+                    assert np.array_equal(srt[k], post[k][src]), k
+            tw.field_advance()
+            ref.field_advance()
+            g = tw.field_arrays()
+            eb = max(rel_err(g["E"], ref.E), rel_err(g["B"], ref.B))
+            assert eb < 1e-5, (i, eb)
+            flush(f"T={tile} k={every} member {i}: replayed step {j}: pos {pos:.2e} u {du:.2e} J {ej:.2e} "
+                  f"E/B {eb:.2e}" + (", sort bit-exact" if sorts else ""))
+        batch.step()
+        assert batch.check() == 0
+        for i in range(len(members)):
+            _assert_same(batch[i], twins[i])
+    for t in twins:
+        assert t.check() == 0
+        t.close()
+    batch.close()

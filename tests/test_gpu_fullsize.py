@@ -1,15 +1,16 @@
 """Parity at the full benchmark sizes, in the launch configuration bench.py
 times (the workload's tile, default current mode), and with a sort cadence of 2.
 
-The oracle cannot run every particle of a 67M-particle step in a test, so:
-  * push + move: a seeded random sample of particles is advanced one by one by
-    the oracle from the GPU's own pre-step state and full E/B fields and
-    compared element by element (same tolerances as the small cases);
-  * sort: the oracle's canonical sort of ALL the GPU's post-push cells is
-    compared bit for bit with the GPU's sorted arrays and tile_offset;
-  * current: properties that hold at any size -- the discrete continuity
-    residual (device FP64 diagnostic) and the total current, sum(Jx) dt/dx =
-    sum_p q dX_p over all particles (dX from the GPU's own positions).
+Every step is replayed by the oracle over ALL particles from the GPU's own
+pre-step state and E/B fields (about 8 s of FP64 per 67M-particle step):
+  * push + move: every particle, slot by slot -- position within 1e-5 cells
+    (X = ix + x modulo the box), momentum within 1e-5 of max|u|, and every
+    offset in [0, 1);
+  * current: every J node, per component within 1e-5 of that component's
+    max|J|; also the discrete continuity residual (device FP64 diagnostic)
+    and the total current, sum(Jx) dt/dx = sum_p q dX_p;
+  * sort: the oracle's canonical sort of ALL the GPU's post-push cells,
+    compared bit for bit with the GPU's sorted arrays and tile_offset.
 """
 import time
 
@@ -18,11 +19,11 @@ import pytest
 
 import oracle
 import pic_workloads as pw
-from _parity import PARTICLE_ARRAYS, flush
+from _parity import PARTICLE_ARRAYS, flush, particle_errors
 
 pytestmark = pytest.mark.gpu
 
-SAMPLE = 20000
+TOL = 1e-5
 
 
 def _lib():
@@ -30,19 +31,19 @@ def _lib():
     return _lib
 
 
-def _sampled_push_errors(pre, post, idx, spec, E, B, w):
-    st = {k: pre[k][idx] for k in ("ix", "iy", "x", "y", "ux", "uy", "uz")}
-    osp = oracle.OracleSpecies(spec.qm, spec.q, st["ix"], st["iy"], st["x"], st["y"], st["ux"], st["uy"], st["uz"])
-    ora = oracle.OracleSim(w.nx, w.ny, w.dx, w.dy, w.dt, [osp], E, B)
+def _full_push_errors(pre_list, post_list, specs, E, B, w):
+    """The oracle's push + deposit of every particle from the GPU's pre-step
+    state; returns (worst position error, worst relative momentum error,
+    per-component J errors relative to each component's max|J|, oracle J)."""
+    osp = [oracle.OracleSpecies(s.qm, s.q, pre["ix"], pre["iy"], pre["x"], pre["y"], pre["ux"], pre["uy"],
+                                pre["uz"]) for s, pre in zip(specs, pre_list)]
+    ora = oracle.OracleSim(w.nx, w.ny, w.dx, w.dy, w.dt, osp, E, B)
     ora.push_deposit()
-    X = post["ix"][idx] + post["x"][idx].astype(np.float64)
-    Y = post["iy"][idx] + post["y"][idx].astype(np.float64)
-    dX = (X - (osp.ix + osp.x) + w.nx / 2) % w.nx - w.nx / 2
-    dY = (Y - (osp.iy + osp.y) + w.ny / 2) % w.ny - w.ny / 2
-    umax = max(np.abs(osp.ux).max(), np.abs(osp.uy).max(), np.abs(osp.uz).max())
-    du = max(np.abs(post["ux"][idx] - osp.ux).max(), np.abs(post["uy"][idx] - osp.uy).max(),
-             np.abs(post["uz"][idx] - osp.uz).max())
-    return max(np.abs(dX).max(), np.abs(dY).max()), du / umax
+    pos = du = 0.0
+    for o, post in zip(osp, post_list):
+        p, u = particle_errors(post, o, w.nx, w.ny)
+        pos, du = max(pos, p), max(du, u)
+    return pos, du, ora.J
 
 
 def _total_current_check(pre_list, post_list, specs, J, w):
@@ -60,6 +61,7 @@ def _total_current_check(pre_list, post_list, specs, J, w):
         assert abs(got - want) <= 1e-6 * scale, (comp, got, want)
 
 
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("name,steps,every", [("warm2048", 2, 1), ("weibel512", 2, 1), ("warm2048", 4, 2)])
 def test_full_size_step(name, steps, every):
     """every > 1: the sort cadence -- the sort (checked bit-exact over all
@@ -73,25 +75,29 @@ def test_full_size_step(name, steps, every):
               sort_every=every)
     del states
     flush(f"[{name}] initialised {sim.n_tiles} tiles in {time.time() - t0:.1f}s")
-    rng = np.random.default_rng(123)
     for step in range(steps):
         pre = [sim.state(k) for k in range(len(w.species))]
         f = sim.field_arrays()
         E, B = f["E"].astype(np.float64), f["B"].astype(np.float64)
+        del f
         sim.diag(L.PIC_DIAG_RHO_SNAPSHOT)
         sim.push_deposit()
         d = sim.diag(L.PIC_DIAG_CONTINUITY | L.PIC_DIAG_COUNTS)
         assert d.continuity_max <= 1e-6 * d.rho_max, (d.continuity_max, d.rho_max)
         post = [sim.state(k) for k in range(len(w.species))]
+        for g in post:
+            assert (g["x"] >= 0).all() and (g["x"] < 1).all() and (g["y"] >= 0).all() and (g["y"] < 1).all()
         J = sim.field_arrays()["J"]
         _total_current_check(pre, post, w.species, J, w)
-        for k, spec in enumerate(w.species):
-            idx = rng.choice(pre[k]["ix"].size, SAMPLE, replace=False)
-            pos, du = _sampled_push_errors(pre[k], post[k], idx, spec, E, B, w)
-            flush(f"[{name}] step {step} species {k}: sampled pos {pos:.2e} u {du:.2e}; "
-                  f"continuity {d.continuity_max:.2e}; leavers {d.leavers[k]}")
-            assert pos < 1e-5 and du < 1e-5
-        del pre
+        t1 = time.time()
+        pos, du, Jo = _full_push_errors(pre, post, w.species, E, B, w)
+        ej = [float(np.abs(J[c] - Jo[c]).max() / max(np.abs(Jo[c]).max(), 1e-30)) for c in range(3)]
+        n = sum(p["ix"].size for p in pre)
+        flush(f"[{name}] step {step}: oracle over all {n} particles in {time.time() - t1:.1f}s: "
+              f"pos {pos:.2e} u {du:.2e} J {ej[0]:.2e} {ej[1]:.2e} {ej[2]:.2e}; "
+              f"continuity {d.continuity_max:.2e}; leavers {list(d.leavers)[:len(w.species)]}")
+        assert pos < TOL and du < TOL and max(ej) < TOL
+        del pre, Jo, E, B
         if step % every != every - 1:
             del post
             sim.field_advance()

@@ -11,9 +11,11 @@ reference history: tests/golden/langmuir_fixture.py).
     round-off every 1,000 steps;
   - the run stays exactly one-dimensional (B, u_y and the y-variation of E are
     exactly zero) -- the fixed-point current sums make every row identical;
-  - the total energy follows the oracle's (scaled by the area) to 2e-5 up to
-    step 1,250; later the cold plasma heats (the FP64 oracle heats the same
-    way, from round-off) and the two histories agree statistically.
+  - the total energy follows the oracle's (scaled by the area) to 1e-5 up to
+    step 1,500 and to 1e-3 at step 1,750; from about step 2,000 the cold
+    plasma heats (the FP64 oracle's own history heats from there, from
+    round-off: +7 % by step 2,250) and the two histories agree only
+    statistically (25 %).
 * The same x-structure on 1024 x 16 cells for 200 steps, GPU FP32 against the
   FP64 oracle from the same initial state: the error table for E, B, J and the
   total energy.
@@ -100,7 +102,7 @@ def test_langmuir_long_run_full_size():
         if n % 250:
             continue
         ratio = energy[n] / (r[0] * area)
-        assert abs(ratio - 1) < (2e-5 if n <= 1250 else 0.25), (n, ratio)
+        assert abs(ratio - 1) < (1e-5 if n <= 1500 else (1e-3 if n <= 1750 else 0.25)), (n, ratio)
     sim.close()
 
 
@@ -129,4 +131,30 @@ def test_langmuir_error_table_against_oracle():
     assert sim.check() == 0
     assert all(r[1] < 1e-4 and r[3] < 1e-4 and r[4] < 1e-5 for r in rows)
     assert np.abs(ora.B).max() < 1e-12 and rows[-1][2] == 0.0
+    sim.close()
+
+
+def test_cold_langmuir_current_ten_steps():
+    """The cold plasma is where a fixed-point current is weakest: every
+    particle moves a few thousandths of a cell per step, so each current
+    contribution is small against the accumulator's unit (the largest charge
+    moving a whole cell).  Ten steps from the same state on both sides: J,
+    E and the particles within 1e-5 of the FP64 oracle."""
+    from _parity import matched_particle_errors
+    from paper_2501_14795_amd import Sim
+    nx, ny = 1024, 16
+    spec, st, E = langmuir_state(nx, ny, 16)
+    sim = Sim(nx, ny, DX, DX, DT, 16, [(spec.qm, spec.q, st)], E=E.astype(np.float32))
+    osp = oracle.OracleSpecies(spec.qm, spec.q, st["ix"], st["iy"], st["x"], st["y"], st["ux"], st["uy"], st["uz"])
+    ora = oracle.OracleSim(nx, ny, DX, DX, DT, [osp], E.astype(np.float32).astype(np.float64))
+    for n in range(1, 11):
+        sim.step()
+        ora.step(T=16)
+        f = sim.field_arrays()
+        ej, ee = rel_err(f["J"], ora.J), rel_err(f["E"], ora.E)
+        pos, du, _ = matched_particle_errors(sim.state(0), osp, nx, ny)
+        flush(f"cold Langmuir step {n}: J {ej:.2e} E {ee:.2e} pos {pos:.2e} u {du:.2e} "
+              f"(max |dX| {np.abs(osp.ux).max() * DT / DX:.1e} cells)")
+        assert ej < 1e-5 and ee < 1e-5 and pos < 1e-5 and du < 1e-5
+    assert sim.check() == 0
     sim.close()

@@ -55,7 +55,9 @@ def _replay_steps(nx, ny, tile, specs, states, E, B, steps, reps=0, label="", j_
         assert sim.check() == 0
         f = sim.field_arrays()
         for k in range(len(specs)):
-            pos, du = particle_errors(sim.state(k), ref.species[k], nx, ny)
+            g = sim.state(k)
+            assert (g["x"] >= 0).all() and (g["x"] < 1).all() and (g["y"] >= 0).all() and (g["y"] < 1).all()
+            pos, du = particle_errors(g, ref.species[k], nx, ny)
             worst[0] = max(worst[0], pos)
             worst[1] = max(worst[1], du)
         worst[2] = max(worst[2], rel_err(f["J"], ref.J))
