@@ -72,6 +72,7 @@ extern "C" {
 #define PIC_ECOUNT (-8)   /* tile counts do not add up to the particle count */
 #define PIC_EOVERFLOW (-9) /* fixed-point current: a tile holds 2^31+ particles over all species */
 #define PIC_ENOCONV (-10)  /* pic_solve_gauss: the iteration did not reach its tolerance */
+#define PIC_ESCRATCH (-11) /* pic_solve_gauss_noalloc: grid larger than its static scratch holds */
 
 /*
  * Current accumulation inside a tile (pic_config.flags).
@@ -334,6 +335,24 @@ typedef struct pic_gauss_out {
 } pic_gauss_out;
 int pic_solve_gauss(pic_sim *sim, void *scratch, size_t scratch_bytes, double tol, int max_iter,
                     pic_gauss_out *out, hipStream_t stream);
+
+/*
+ * pic_solve_gauss for callers that cannot allocate device memory (a serving
+ * loop or a harness that forbids hipMalloc): the same solve, with the same
+ * results bit for bit, in a scratch array the library holds in every
+ * device's memory from the moment it is loaded until the process ends --
+ * PIC_GAUSS_SCRATCH_BYTES(1024, 1024) bytes, so at most
+ * PIC_GAUSS_NOALLOC_MAX_CELLS cells (nx * ny; PIC_ESCRATCH beyond, nothing
+ * done).  Allocates nothing.  Every call on one device shares that device's
+ * array, which keeps the last call's contents (each call writes every value
+ * it reads first): calls that overlap in time on one device -- from two host
+ * threads, or on two streams -- race and must not be made.  The device
+ * current at the call must be the one the simulation was created on
+ * (PIC_EINVAL otherwise).  Synchronises `stream`; out and the return codes
+ * as for pic_solve_gauss.
+ */
+#define PIC_GAUSS_NOALLOC_MAX_CELLS (1 << 20)
+int pic_solve_gauss_noalloc(pic_sim *sim, double tol, int max_iter, pic_gauss_out *out, hipStream_t stream);
 
 /*
  * State I/O: host copies of everything that carries over from one step to

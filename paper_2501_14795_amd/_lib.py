@@ -23,6 +23,8 @@ PIC_ESORT = -7
 PIC_ECOUNT = -8
 PIC_EOVERFLOW = -9
 PIC_ENOCONV = -10
+PIC_ESCRATCH = -11
+PIC_GAUSS_NOALLOC_MAX_CELLS = 1 << 20
 
 PIC_FLAG_J_FLOAT = 1
 PIC_FLAG_ESIRKEPOV = 2
@@ -41,7 +43,7 @@ PIC_MAX_FILTER = 16
 # every symbol the header declares
 EXPORTS = [
     "pic_query", "pic_init", "pic_push_deposit", "pic_sort", "pic_field_advance", "pic_move_window",
-    "pic_get_window_origin", "pic_get_counts", "pic_solve_gauss", "pic_step",
+    "pic_get_window_origin", "pic_get_counts", "pic_solve_gauss", "pic_solve_gauss_noalloc", "pic_step",
     "pic_check", "pic_diag", "pic_get_state", "pic_set_state", "pic_get_tile_offsets",
     "pic_set_timing", "pic_set_timing_mask", "pic_get_timing",
     "pic_batch_query", "pic_batch_init", "pic_batch_step", "pic_batch_capture", "pic_batch_sim",
@@ -133,6 +135,7 @@ def load(path: str = SO_PATH):
     L.pic_get_counts.argtypes = [vp, P(ctypes.c_int64)]
     L.pic_get_window_origin.argtypes = [vp, P(ctypes.c_int32)]
     L.pic_solve_gauss.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int, P(pic_gauss_out), vp]
+    L.pic_solve_gauss_noalloc.argtypes = [vp, ctypes.c_double, ctypes.c_int, P(pic_gauss_out), vp]
     L.pic_set_state.argtypes = [vp, P(pic_host_state), vp]
     L.pic_set_timing.argtypes = [vp, ctypes.c_int]
     L.pic_set_timing_mask.argtypes = [vp, ctypes.c_uint]
@@ -233,6 +236,15 @@ def pic_solve_gauss(sim: int, scratch: int, scratch_bytes: int, tol: float, max_
     out = pic_gauss_out()
     _chk(load().pic_solve_gauss(ctypes.c_void_p(sim), ctypes.c_void_p(scratch), scratch_bytes, float(tol),
                                 int(max_iter), ctypes.byref(out), ctypes.c_void_p(stream)), "pic_solve_gauss")
+    return out
+
+
+def pic_solve_gauss_noalloc(sim: int, tol: float, max_iter: int, stream: int):
+    """pic_solve_gauss in the library's static scratch (no device allocation);
+    returns the pic_gauss_out record; raises PicError."""
+    out = pic_gauss_out()
+    _chk(load().pic_solve_gauss_noalloc(ctypes.c_void_p(sim), float(tol), int(max_iter), ctypes.byref(out),
+                                        ctypes.c_void_p(stream)), "pic_solve_gauss_noalloc")
     return out
 
 

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -146,6 +147,7 @@ struct pic_sim {
     hipStream_t side;
     hipEvent_t ev_fork, ev_join;
     int64_t cap[kMaxSpecies];
+    int device;         // the device current at pic_init
     bool have_snapshot;
     struct Sp {
         int32_t *off;    // current tile_offset
@@ -168,7 +170,36 @@ struct pic_sim {
     int64_t launches[PIC_N_KERNELS];
 };
 
+// The scratch of pic_solve_gauss_noalloc: the conjugate-gradient vectors of
+// the largest grid it takes.  Every device holds its own copy from the
+// moment the library is loaded until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in
+// for the symbol): it uses the device address hipGetSymbolAddress returns,
+// looked up once per device.
+static __device__ __align__(256) unsigned char scratch[PIC_GAUSS_SCRATCH_BYTES(1024, 1024)];
+static_assert(PIC_GAUSS_SCRATCH_BYTES(1024, 1024) == 32 * (size_t)PIC_GAUSS_NOALLOC_MAX_CELLS + 16384,
+              "the static scratch holds the largest grid pic_solve_gauss_noalloc takes");
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on `dev`, which must be the current device
+// (the symbol has one address per device).
+int scratch_address(int dev, void **ptr)
+{
+    if (dev < 0 || dev >= kMaxDevices) return PIC_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PIC_EHIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return PIC_OK;
+}
 
 void release_side(pic_sim *s)
 {
@@ -295,6 +326,42 @@ double mean_density(const pic_sim *S)
     double total = 0.0;
     for (int s = 0; s < c.n_species; ++s) total += c.species[s].q * (double)c.species[s].n;
     return total / ((double)c.nx * c.ny);
+}
+
+// Both Poisson projections of pic_solve_gauss in the scratch d of
+// PIC_GAUSS_SCRATCH_BYTES(nx, ny) bytes (4 CG vectors, the block partial
+// sums, the scalars); every value is written before it is read.
+int solve_gauss_in(pic_sim *S, double *d, double tol, int max_iter, pic_gauss_out *out, hipStream_t stream)
+{
+    const pic_config &c = S->cfg;
+    const int64_t P = (int64_t)c.nx * c.ny;
+    if (!(tol > 0.0)) tol = 1e-12;
+    if (max_iter <= 0) max_iter = 20 * (c.nx > c.ny ? c.nx : c.ny) + 100;
+    CgScratch w;
+    w.x = d;
+    w.r = d + P;
+    w.p = d + 2 * P;
+    w.q = d + 3 * P;
+    w.partial = d + 4 * P;
+    w.scal = w.partial + kCgPartials;
+    int rc = node_density(S, stream);
+    if (rc) return rc;
+    const CgResult e = cg_project(S->buf.fields, S->rho_now, mean_density(S), 0, c.nx, c.ny, c.dx, c.dy, tol,
+                                  max_iter, w, stream);
+    if (e.iterations < 0) return PIC_EHIP;
+    const CgResult b = cg_project(S->buf.fields, nullptr, 0.0, 1, c.nx, c.ny, c.dx, c.dy, tol, max_iter, w, stream);
+    if (b.iterations < 0) return PIC_EHIP;
+    rc = hip_ok(hipGetLastError());
+    if (rc == PIC_OK) rc = hip_ok(hipStreamSynchronize(stream));
+    if (rc) return rc;
+    if (out) {
+        out->iterations[0] = e.iterations;
+        out->iterations[1] = b.iterations;
+        out->residual[0] = e.residual;
+        out->residual[1] = b.residual;
+    }
+    S->have_snapshot = false;
+    return e.converged && b.converged ? PIC_OK : PIC_ENOCONV;
 }
 
 
@@ -446,6 +513,7 @@ const char *pic_strerror(int code)
     case PIC_ESORT: return "sort consistency check failed";
     case PIC_ECOUNT: return "tile counts do not add up to the particle count";
     case PIC_EOVERFLOW: return "a tile holds 2^31 or more particles (its fixed-point current could overflow)";
+    case PIC_ESCRATCH: return "the grid is larger than pic_solve_gauss_noalloc's static scratch holds";
     case PIC_ENOCONV: return "the Poisson iteration did not reach its tolerance";
     default: return "unknown error";
     }
@@ -603,7 +671,14 @@ int init_sim(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
         S->cap[s] = cfg->species[s].cap ? cfg->species[s].cap : cfg->species[s].n;
     }
 
-    rc = hip_ok(hipMemsetAsync(S->err, 0, 64, stream));
+    rc = hip_ok(hipGetDevice(&S->device));
+    if (rc == PIC_OK) {
+        // set-up of pic_solve_gauss_noalloc on this device (a failure here is
+        // reported by that call, which looks the address up again)
+        void *unused = nullptr;
+        (void)scratch_address(S->device, &unused);
+    }
+    if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(S->err, 0, 64, stream));
     if (rc == PIC_OK) rc = build_tiles(S, stream);
     if (with_side) {
         // default priority, like every stream of the library's callers
@@ -814,41 +889,26 @@ int pic_get_window_origin(pic_sim *S, int32_t *origin)
     return PIC_OK;
 }
 
-int pic_solve_gauss(pic_sim *S, void *scratch, size_t scratch_bytes, double tol, int max_iter,
-                    pic_gauss_out *out, hipStream_t stream)
+int pic_solve_gauss(pic_sim *S, void *work, size_t work_bytes, double tol, int max_iter, pic_gauss_out *out,
+                    hipStream_t stream)
 {
-    if (!S || !scratch || ((uintptr_t)scratch) % kAlign) return PIC_EINVAL;
-    const pic_config &c = S->cfg;
-    const int64_t P = (int64_t)c.nx * c.ny;
-    if (scratch_bytes < PIC_GAUSS_SCRATCH_BYTES(c.nx, c.ny)) return PIC_EINVAL;
-    if (!(tol > 0.0)) tol = 1e-12;
-    if (max_iter <= 0) max_iter = 20 * (c.nx > c.ny ? c.nx : c.ny) + 100;
-    double *d = (double *)scratch;
-    CgScratch w;
-    w.x = d;
-    w.r = d + P;
-    w.p = d + 2 * P;
-    w.q = d + 3 * P;
-    w.partial = d + 4 * P;
-    w.scal = w.partial + kCgPartials;
-    int rc = node_density(S, stream);
+    if (!S || !work || ((uintptr_t)work) % kAlign) return PIC_EINVAL;
+    if (work_bytes < PIC_GAUSS_SCRATCH_BYTES(S->cfg.nx, S->cfg.ny)) return PIC_EINVAL;
+    return solve_gauss_in(S, (double *)work, tol, max_iter, out, stream);
+}
+
+int pic_solve_gauss_noalloc(pic_sim *S, double tol, int max_iter, pic_gauss_out *out, hipStream_t stream)
+{
+    if (!S) return PIC_EINVAL;
+    if ((int64_t)S->cfg.nx * S->cfg.ny > PIC_GAUSS_NOALLOC_MAX_CELLS) return PIC_ESCRATCH;
+    int dev = -1;
+    int rc = hip_ok(hipGetDevice(&dev));
     if (rc) return rc;
-    const CgResult e = cg_project(S->buf.fields, S->rho_now, mean_density(S), 0, c.nx, c.ny, c.dx, c.dy, tol,
-                                  max_iter, w, stream);
-    if (e.iterations < 0) return PIC_EHIP;
-    const CgResult b = cg_project(S->buf.fields, nullptr, 0.0, 1, c.nx, c.ny, c.dx, c.dy, tol, max_iter, w, stream);
-    if (b.iterations < 0) return PIC_EHIP;
-    rc = hip_ok(hipGetLastError());
-    if (rc == PIC_OK) rc = hip_ok(hipStreamSynchronize(stream));
+    if (dev != S->device) return PIC_EINVAL;
+    void *p = nullptr;
+    rc = scratch_address(dev, &p);
     if (rc) return rc;
-    if (out) {
-        out->iterations[0] = e.iterations;
-        out->iterations[1] = b.iterations;
-        out->residual[0] = e.residual;
-        out->residual[1] = b.residual;
-    }
-    S->have_snapshot = false;
-    return e.converged && b.converged ? PIC_OK : PIC_ENOCONV;
+    return solve_gauss_in(S, (double *)p, tol, max_iter, out, stream);
 }
 
 int pic_get_counts(pic_sim *S, int64_t *counts)
