@@ -151,6 +151,10 @@ typedef struct pic_config {
                             moving window, and 2k + 1 <= tile within the LDS budget
                             (tile 8: k <= 2; 16: k <= 4; 32: k <= 2), else PIC_EINVAL /
                             PIC_ETILE */
+    int32_t ppl;         /* particles per lane per pass of the push loop: 1, 2 or 4 (0: 2),
+                            the 64-particle chunks a wavefront carries side by side; other
+                            than 2 needs the fixed-point current, the default deposit and
+                            j_replicas <= 1 (else PIC_EINVAL).  Results do not depend on it */
     pic_species species[PIC_MAX_SPECIES];
 } pic_config;
 

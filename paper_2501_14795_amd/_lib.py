@@ -61,7 +61,8 @@ class pic_config(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dt", ctypes.c_double),
                 ("tile", ctypes.c_int32), ("j_replicas", ctypes.c_int32),
                 ("n_species", ctypes.c_int32), ("flags", ctypes.c_uint32), ("j_filter", ctypes.c_int32),
-                ("sort_every", ctypes.c_int32), ("species", pic_species * MAX_SPECIES)]
+                ("sort_every", ctypes.c_int32), ("ppl", ctypes.c_int32),
+                ("species", pic_species * MAX_SPECIES)]
 
 
 class pic_particles(ctypes.Structure):

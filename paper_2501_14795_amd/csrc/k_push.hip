@@ -489,7 +489,9 @@ __device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool
 }
 
 // One tile of one simulation, by the whole workgroup (push_waves(T) wavefronts).
-template <int T, int R, int JM, int DM, int H>
+// C: particles per lane per pass of the particle loop (64-particle chunks
+// carried side by side).
+template <int T, int R, int JM, int DM, int H, int C>
 __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
 {
     static_assert(cadence_ok(T, H), "halo pad not supported for this tile");
@@ -572,13 +574,13 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             const float h = sp.h, fq = sp.fq;
             int npq = 0;    // motions waiting in the wavefront's queue (uniform)
             int nbuf = 0;   // leavers waiting in the wavefront's LDS buffer (packed layout; uniform)
-            // Two chunks per iteration: lane L holds the particles of slots
-            // cb + L and cb + 64 + L.  Their arithmetic (advance) has no side
-            // effects and no branches, so the two instruction streams
+            // C chunks per iteration: lane L holds the particles of slots
+            // cb + L, cb + 64 + L, ...  Their arithmetic (advance) has no side
+            // effects and no branches, so the C instruction streams
             // interleave; the side effects (finish) follow in slot order.
             // Loads past the run's end return 0; lanes before its start (first
             // chunk of the section only) read the previous tile's particles
-            // and discard them.  The next two chunks are always prefetched
+            // and discard them.  The next C chunks are always prefetched
             // before the current ones are processed.
             auto finish = [&](const Moved &m, int i, int at) {
                 if (m.valid && !m.cross) deposit_piece<NJ, JM>(sj, m.b, m.x, m.y, m.dX, m.dY, m.fqvz, fq);
@@ -636,20 +638,27 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             };
             int cb = (lo >> 6) << 6;
             int off = (cb + lane - base) * 4;
-            Chunk nA = load_chunk(st, off), nB = load_chunk(st, off + 256);
+            Chunk nxt[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) nxt[c] = load_chunk(st, off + 256 * c);
             int errs = 0;   // error bits of this lane's particles
-            for (; cb < hi; cb += 128, off += 512) {
-                const Chunk A = nA, B = nB;
-                nA = load_chunk(st, off + 512);
-                nB = load_chunk(st, off + 768);
+            for (; cb < hi; cb += 64 * C, off += 256 * C) {
+                Chunk cur[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    cur[c] = nxt[c];
+                    nxt[c] = load_chunk(st, off + 256 * (C + c));
+                }
                 const int i = cb + lane;
-                const Moved mA = advance<T, NJ, NE, H, V2, V1>(a, A, i >= lo && i < hi, gx0, gy0, tx_wrap,
-                                                               ty_wrap, h, fq, s_exby, s_eybx, s_ez, s_bz);
-                const Moved mB = advance<T, NJ, NE, H, V2, V1>(a, B, i + 64 >= lo && i + 64 < hi, gx0, gy0,
-                                                               tx_wrap, ty_wrap, h, fq, s_exby, s_eybx, s_ez, s_bz);
-                errs |= mA.err | mB.err;
-                finish(mA, i, off);
-                finish(mB, i + 64, off + 256);
+                Moved m[C];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    m[c] = advance<T, NJ, NE, H, V2, V1>(a, cur[c], i + 64 * c >= lo && i + 64 * c < hi, gx0, gy0,
+                                                         tx_wrap, ty_wrap, h, fq, s_exby, s_eybx, s_ez, s_bz);
+                    errs |= m[c].err;
+                }
+#pragma unroll
+                for (int c = 0; c < C; ++c) finish(m[c], i + 64 * c, off + 256 * c);
             }
             if (errs) set_err(a.err, errs);
             drain_motions<NJ, JM, DM>(sj, s_pq[wave], npq, fq, lane);
@@ -690,17 +699,26 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
     }
 }
 
-template <int T, int R, int JM, int DM, int H>
-__global__ void __launch_bounds__(64 * push_waves(T), push_min_waves(T, R, JM, H)) k_push_deposit(PushArgs a)
+// Register budget: the LDS fit (push_min_waves), and at most two waves per
+// SIMD (256 VGPRs) for four chunks per lane, whose particle state does not
+// fit 128 registers.
+template <int T, int R, int JM, int DM, int H, int C>
+constexpr int push_waves_per_simd()
 {
-    push_tile<T, R, JM, DM, H>(a, blockIdx.x);
+    return C > 2 && push_min_waves(T, R, JM, H) > 2 ? 2 : push_min_waves(T, R, JM, H);
+}
+
+template <int T, int R, int JM, int DM, int H, int C>
+__global__ void __launch_bounds__(64 * push_waves(T), (push_waves_per_simd<T, R, JM, DM, H, C>())) k_push_deposit(PushArgs a)
+{
+    push_tile<T, R, JM, DM, H, C>(a, blockIdx.x);
 }
 
 // Many simulations in one launch: a persistent grid takes (simulation, tile)
 // items from a shared counter (the items come largest simulations first, so
 // the expensive tiles start early and the cheap ones fill the tail).
-template <int T, int R, int JM, int DM, int H>
-__global__ void __launch_bounds__(64 * push_waves(T), push_min_waves(T, R, JM, H)) k_push_batch(const PushArgs *__restrict__ descs,
+template <int T, int R, int JM, int DM, int H, int C>
+__global__ void __launch_bounds__(64 * push_waves(T), (push_waves_per_simd<T, R, JM, DM, H, C>())) k_push_batch(const PushArgs *__restrict__ descs,
                                                        const int4 *__restrict__ items, int n_items, int *counter)
 {
     __shared__ int s_item;
@@ -711,7 +729,7 @@ __global__ void __launch_bounds__(64 * push_waves(T), push_min_waves(T, R, JM, H
         __syncthreads();
         if (it >= n_items) break;
         const int4 w = items[it];
-        push_tile<T, R, JM, DM, H>(descs[w.x], w.y);
+        push_tile<T, R, JM, DM, H, C>(descs[w.x], w.y);
         __syncthreads();
     }
 }
@@ -786,16 +804,16 @@ __global__ void __launch_bounds__(256) k_j_reduce_batch(const JReduceArgs *__res
     j_reduce_block<T, H>(descs[w.x], w.y, w.z);
 }
 
-template <int T, int R, int JM, int DM, int H>
+template <int T, int R, int JM, int DM, int H, int C>
 static void launch_pd(const PushArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_push_deposit<T, R, JM, DM, H>), dim3(n_tiles), dim3(64 * push_waves(T)), 0, s, a);
+    hipLaunchKernelGGL((k_push_deposit<T, R, JM, DM, H, C>), dim3(n_tiles), dim3(64 * push_waves(T)), 0, s, a);
 }
 
-template <int T, int R, int JM, int DM, int H>
+template <int T, int R, int JM, int DM, int H, int C>
 static void launch_pb(const PushArgs *descs, const int4 *items, int n_items, int *counter, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_push_batch<T, R, JM, DM, H>), dim3(grid), dim3(64 * push_waves(T)), 0, s, descs, items,
+    hipLaunchKernelGGL((k_push_batch<T, R, JM, DM, H, C>), dim3(grid), dim3(64 * push_waves(T)), 0, s, descs, items,
                        n_items, counter);
 }
 
@@ -811,64 +829,83 @@ struct PushLaunch {
     int *counter;
     int grid;
     hipStream_t s;
-    template <int T, int R, int JM, int DM, int H>
+    template <int T, int R, int JM, int DM, int H, int C>
     void go() const
     {
         if constexpr (push_lds_bytes(T, R, JM, H) <= kLdsBytes && cadence_ok(T, H)) {
-            if (single) launch_pd<T, R, JM, DM, H>(*single, n_tiles, s);
-            else launch_pb<T, R, JM, DM, H>(descs, items, n_items, counter, grid, s);
+            if (single) launch_pd<T, R, JM, DM, H, C>(*single, n_tiles, s);
+            else launch_pb<T, R, JM, DM, H, C>(descs, items, n_items, counter, grid, s);
         }
     }
 };
 
+// particles per lane per pass: 1, 2 or 4 for the default current and
+// deposit with one LDS copy (the configurations the autotuner searches), 2
+// otherwise (pic_query / pic_init refuse the rest)
+template <int T, int R, int JM, int DM, int H>
+static void push_c(const PushLaunch &L, int ppl)
+{
+    if constexpr (R == 1 && JM == kJFixed && DM == kDepVB) {
+        if (ppl == 1) {
+            L.go<T, R, JM, DM, H, 1>();
+            return;
+        }
+        if (ppl == 4) {
+            L.go<T, R, JM, DM, H, 4>();
+            return;
+        }
+    }
+    L.go<T, R, JM, DM, H, 2>();
+}
+
 template <int T, int JM, int DM>
-static void push_r(const PushLaunch &L, int replicas, int halo)
+static void push_r(const PushLaunch &L, int replicas, int halo, int ppl)
 {
     if (halo > 1) {
         // sort cadences above 1: fixed-point current, one LDS copy
         if constexpr (JM == kJFixed) {
-            if (halo == 2) L.go<T, 1, JM, DM, 2>();
-            else L.go<T, 1, JM, DM, 4>();
+            if (halo == 2) push_c<T, 1, JM, DM, 2>(L, ppl);
+            else push_c<T, 1, JM, DM, 4>(L, ppl);
         }
         return;
     }
     switch (replicas) {
-    case 1: L.go<T, 1, JM, DM, 1>(); break;
-    case 2: L.go<T, 2, JM, DM, 1>(); break;
-    default: L.go<T, 4, JM, DM, 1>(); break;
+    case 1: push_c<T, 1, JM, DM, 1>(L, ppl); break;
+    case 2: push_c<T, 2, JM, DM, 1>(L, ppl); break;
+    default: push_c<T, 4, JM, DM, 1>(L, ppl); break;
     }
 }
 
 // the Esirkepov deposit is built for the fixed-point current only
 template <int T>
-static void push_j(const PushLaunch &L, int replicas, int jmode, int dmode, int halo)
+static void push_j(const PushLaunch &L, int replicas, int jmode, int dmode, int halo, int ppl)
 {
-    if (jmode == kJFloat) push_r<T, kJFloat, kDepVB>(L, replicas, halo);
-    else if (dmode == kDepEsirkepov) push_r<T, kJFixed, kDepEsirkepov>(L, replicas, halo);
-    else push_r<T, kJFixed, kDepVB>(L, replicas, halo);
+    if (jmode == kJFloat) push_r<T, kJFloat, kDepVB>(L, replicas, halo, ppl);
+    else if (dmode == kDepEsirkepov) push_r<T, kJFixed, kDepEsirkepov>(L, replicas, halo, ppl);
+    else push_r<T, kJFixed, kDepVB>(L, replicas, halo, ppl);
 }
 
-static void push_t(const PushLaunch &L, int tile, int replicas, int jmode, int dmode, int halo)
+static void push_t(const PushLaunch &L, int tile, int replicas, int jmode, int dmode, int halo, int ppl)
 {
     switch (tile) {
-    case 8: push_j<8>(L, replicas, jmode, dmode, halo); break;
-    case 16: push_j<16>(L, replicas, jmode, dmode, halo); break;
-    default: push_j<32>(L, replicas, jmode, dmode, halo); break;
+    case 8: push_j<8>(L, replicas, jmode, dmode, halo, ppl); break;
+    case 16: push_j<16>(L, replicas, jmode, dmode, halo, ppl); break;
+    default: push_j<32>(L, replicas, jmode, dmode, halo, ppl); break;
     }
 }
 
-void launch_push_deposit(int tile, int replicas, int jmode, int dmode, int halo, const PushArgs &a, int n_tiles,
-                         hipStream_t s)
+void launch_push_deposit(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs &a,
+                         int n_tiles, hipStream_t s)
 {
     PushLaunch L{&a, n_tiles, nullptr, nullptr, 0, nullptr, 0, s};
-    push_t(L, tile, replicas, jmode, dmode, halo);
+    push_t(L, tile, replicas, jmode, dmode, halo, ppl);
 }
 
-void launch_push_batch(int tile, int replicas, int jmode, int dmode, int halo, const PushArgs *descs,
+void launch_push_batch(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs *descs,
                        const int4 *items, int n_items, int *counter, int grid, hipStream_t s)
 {
     PushLaunch L{nullptr, 0, descs, items, n_items, counter, grid, s};
-    push_t(L, tile, replicas, jmode, dmode, halo);
+    push_t(L, tile, replicas, jmode, dmode, halo, ppl);
 }
 
 template <int T>

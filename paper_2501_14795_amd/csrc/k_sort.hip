@@ -15,9 +15,14 @@
 //                             the leavers of the up-to-eight neighbour tiles
 //                             heading to t (their leaver lists) and t's own
 //                             stayers pushed out of [A, B) by section shifts;
-//                  the movers are gathered into a staging area at once, so
-//                  only O(movers) particle bytes are touched.
-//   k_sort_scatter step (5): the k-th hole receives the k-th mover.
+//                  a mover whose hole is one of t's own leaver slots (no
+//                  other tile reads or writes such a slot) is written there
+//                  at once; the others -- the head and tail of the holes,
+//                  which lie in neighbouring tiles' old sections and may
+//                  still hold their movers -- go to a staging area, so only
+//                  O(movers) particle bytes are touched.
+//   k_sort_scatter step (5): the staged movers into their holes (contiguous
+//                  runs of slots at the ends of the section).
 #include "pic_internal.h"
 
 namespace pic {
@@ -199,8 +204,9 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
     auto tile_of = [&](int cell) { return cell < 0 ? -1 : ((cell >> 16) >> tsh) * ntx + ((cell & 0xffff) >> tsh); };
     bool bad = false;
 
-    // ---------------- holes, ascending
-    int nh = 0;
+    // ---------------- holes, ascending: nhead in [A, min(B, oA)), then t's
+    // leaver slots, then ntail in [max(A, oB), B)
+    int nh = 0, nhead = 0, ntail = 0;
     {
         const int lA = max(A, oA), lB = min(B, oB);
         int kind = 0, base = 0, len = 0;   // kind 0: slot range, 1: leaver sub-list of t
@@ -239,8 +245,12 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
             const int r = nh + lane_rank_s(m);
             if (p && r < B - A) sp.hole[(int64_t)A + r] = slot;
             nh += __popcll(m);
+            nhead += __popcll(__ballot(p && L == 0));
+            ntail += __popcll(__ballot(p && L == W + 1));
         }
     }
+    // the holes' slots, written by this wavefront, are read back below
+    __threadfence_block();
 
     // ---------------- movers, ascending old slot, gathered into staging
     int nm = 0;
@@ -320,7 +330,11 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
                 }
                 const unsigned long long m = __ballot(p);
                 const int r = nm + lane_rank_s(m);
-                if (p && r < B - A) copy_particle(from_leavers ? sp.lp : sp.p, at, sp.stg, (int64_t)A + r);
+                if (p && r < B - A) {
+                    const Parts &src = from_leavers ? sp.lp : sp.p;
+                    if (r < nhead || r >= nh - ntail) copy_particle(src, at, sp.stg, (int64_t)A + r);
+                    else copy_particle(src, at, sp.p, sp.hole[(int64_t)A + r]);   // one of t's leaver slots
+                }
                 nm += __popcll(m);
             }
         };
@@ -365,12 +379,16 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
     const bool anybad = __ballot(bad) != 0ull;
     if (lane == 0) {
         if (nh != nm || anybad) atomicOr(a.err, kErrSort);
-        sp.mcount[t] = min(nh, nm);
+        const int m = min(nh, nm);
+        sp.mcount[t] = m;
+        sp.mcount[a.n_tiles + t] = min(nhead, m);
+        sp.mcount[2 * a.n_tiles + t] = min(ntail, m - min(nhead, m));
     }
 }
 
-// Step (5): the k-th hole of each tile receives the k-th mover; the new
-// tile_offset replaces the old one (all plans have read the old one).
+// Step (5): the staged movers of each tile (the head and the tail of its
+// holes: contiguous runs of slots) into their holes; the new tile_offset
+// replaces the old one (all plans have read the old one).
 __device__ __forceinline__ void sort_scatter_unit(const SortArgs &a, int spi, int grp)
 {
     const int lane = threadIdx.x & 63;
@@ -378,8 +396,9 @@ __device__ __forceinline__ void sort_scatter_unit(const SortArgs &a, int spi, in
     if (t >= a.n_tiles) return;
     const SortSpecies &sp = a.sp[spi];
     const int A = sp.offn[t], m = sp.mcount[t];
-    for (int k = lane; k < m; k += 64) {
-        const int64_t r = (int64_t)A + k;
+    const int head = sp.mcount[a.n_tiles + t], tail = sp.mcount[2 * a.n_tiles + t];
+    for (int k = lane; k < head + tail; k += 64) {
+        const int64_t r = (int64_t)A + (k < head ? k : m - tail + (k - head));
         copy_particle(sp.stg, r, sp.p, sp.hole[r]);
     }
     if (lane == 0) {

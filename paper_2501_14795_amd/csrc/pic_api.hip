@@ -32,6 +32,7 @@ int j_mode(const pic_config *c) { return (c->flags & PIC_FLAG_J_FLOAT) ? kJFloat
 int d_mode(const pic_config *c) { return (c->flags & PIC_FLAG_ESIRKEPOV) ? kDepEsirkepov : kDepVB; }
 
 int halo_of(const pic_config *c) { return c->sort_every ? c->sort_every : 1; }
+int ppl_of(const pic_config *c) { return c->ppl ? c->ppl : 2; }
 
 int default_replicas(const pic_config *c)
 {
@@ -66,6 +67,12 @@ int validate(const pic_config *c)
             if (c->flags & PIC_FLAG_MOVING_WINDOW) return PIC_EINVAL;
             if (!cadence_ok(c->tile, k)) return PIC_ETILE;
         }
+    }
+    {
+        // particles per lane: 1 and 4 are built for the autotuner's configurations
+        const int ppl = ppl_of(c);
+        if (ppl != 1 && ppl != 2 && ppl != 4) return PIC_EINVAL;
+        if (ppl != 2 && (j_mode(c) != kJFixed || d_mode(c) != kDepVB || c->j_replicas > 1)) return PIC_EINVAL;
     }
     if (!(c->dx > 0) || !(c->dy > 0) || !(c->dt > 0)) return PIC_EINVAL;
     // Courant-Levy condition, Eq. (1), with c = 1
@@ -116,7 +123,7 @@ Layout make_layout(const pic_config *c)
         for (int k = 0; k < 6; ++k) L.lpart[s][k] = take(n * 4);
         L.hole[s] = take(n * sizeof(int32_t));
         for (int k = 0; k < 6; ++k) L.stg[s][k] = take(n * 4);
-        L.mcount[s] = take((size_t)n_tiles * sizeof(int32_t));
+        L.mcount[s] = take((size_t)3 * n_tiles * sizeof(int32_t));   // movers, staged head and tail
         L.bsum[s] = take((size_t)(n_tiles / kScanBlock + 1) * sizeof(int32_t));
     }
     L.total = p;
@@ -710,8 +717,8 @@ int push_only(pic_sim *S, hipStream_t stream)
     const PushArgs a = push_args(S);
     {
         Timed t(S, PIC_KERNEL_PUSH, stream);
-        launch_push_deposit(S->tile, S->replicas, j_mode(&S->cfg), d_mode(&S->cfg), S->halo, a, S->n_tiles,
-                            stream);
+        launch_push_deposit(S->tile, S->replicas, j_mode(&S->cfg), d_mode(&S->cfg), S->halo, ppl_of(&S->cfg), a,
+                            S->n_tiles, stream);
     }
     S->since_sort += 1;
     return hip_ok(hipGetLastError());
@@ -1161,6 +1168,7 @@ struct pic_batch {
     std::vector<pic_sim *> sims;
     int tile, replicas, jm, dm;
     int halo;    // sort cadence shared by the members
+    int ppl;     // particles per lane of the push loop, shared by the members
     int phase;   // steps since the members were last sorted
     int cus;
     char *dev;
@@ -1197,7 +1205,7 @@ int batch_validate(int n, const pic_config *cfgs)
         if (rc) return rc;
         if (cfgs[i].tile != cfgs[0].tile || cfgs[i].flags != cfgs[0].flags ||
             cfgs[i].j_replicas != cfgs[0].j_replicas || cfgs[i].j_filter != cfgs[0].j_filter ||
-            halo_of(&cfgs[i]) != halo_of(&cfgs[0]))
+            halo_of(&cfgs[i]) != halo_of(&cfgs[0]) || ppl_of(&cfgs[i]) != ppl_of(&cfgs[0]))
             return PIC_EINVAL;
         if (cfgs[i].flags & PIC_FLAG_MOVING_WINDOW) return PIC_EINVAL;   // member counts are fixed
         if (cfgs[i].flags & PIC_FLAG_FULL_SORT) return PIC_EINVAL;       // the graph holds the in-place sort
@@ -1244,8 +1252,8 @@ BatchLayout batch_layout(int n, const pic_config *cfgs)
 void batch_enqueue_step(pic_batch *b, bool sort, hipStream_t stream)
 {
     launch_set_int(b->counter, 0, stream);
-    launch_push_batch(b->tile, b->replicas, b->jm, b->dm, b->halo, b->d_push, b->push_items, b->n_push, b->counter,
-                      b->push_grid, stream);
+    launch_push_batch(b->tile, b->replicas, b->jm, b->dm, b->halo, b->ppl, b->d_push, b->push_items, b->n_push,
+                      b->counter, b->push_grid, stream);
     // with a sort, the field half goes to the second stream (disjoint data)
     const bool fork = sort && b->side;
     hipStream_t fs = stream;
@@ -1318,6 +1326,7 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
     B->dm = d_mode(&cfgs[0]);
     B->replicas = cfgs[0].j_replicas ? cfgs[0].j_replicas : default_replicas(&cfgs[0]);
     B->halo = halo_of(&cfgs[0]);
+    B->ppl = ppl_of(&cfgs[0]);
     B->phase = 0;
     char *d = (char *)batch_work;
     B->dev = d;

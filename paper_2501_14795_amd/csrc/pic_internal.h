@@ -19,7 +19,7 @@ struct SortSpecies {
     const int32_t *cnt;
     const uint32_t *leav;
     int32_t *hole;        // [n]: tile t's holes, ascending, at offn[t] + k
-    int32_t *mcount;      // [n_tiles]
+    int32_t *mcount;      // [3][n_tiles]: movers; staged movers at the head and at the tail of the holes
     int32_t *bsum;        // [n_tiles / kScanBlock + 1] block totals of the tile scan
     int32_t n;            // particles before the sort
     // moving window (else null / 0): new particles appended at slots
@@ -55,10 +55,11 @@ struct FieldArgs {
 
 // ---- launchers (each defined next to its kernels) ----
 // halo: the pad H of cadence_ok (1 unless particles are sorted less often than every step)
-void launch_push_deposit(int tile, int replicas, int jmode, int dmode, int halo, const PushArgs &a, int n_tiles,
-                         hipStream_t s);
+// ppl: particles per lane per pass of the push loop (1, 2 or 4; ppl_ok)
+void launch_push_deposit(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs &a,
+                         int n_tiles, hipStream_t s);
 void launch_j_reduce(int tile, int halo, const JReduceArgs &r, hipStream_t s);
-void launch_push_batch(int tile, int replicas, int jmode, int dmode, int halo, const PushArgs *descs,
+void launch_push_batch(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs *descs,
                        const int4 *items, int n_items, int *counter, int grid, hipStream_t s);
 void launch_j_reduce_batch(int tile, int halo, const JReduceArgs *descs, const int4 *items, int n_items,
                            hipStream_t s);

@@ -1,22 +1,25 @@
-"""Autotuner for the batched mode: times candidate launch configurations
-(tile size x LDS current replicas x sort cadence) on graph replays of the
-actual batch and keeps the fastest.  The particle arrays must be grouped by
-tile for each candidate tile size, so the caller supplies a function that
-builds the members' initial states for a given tile size.
-
-The push processes one particle per lane per pass with the next 64-particle
-chunk already loading, so particles per lane is not a tuning dimension
-here: the sort cadence and the tile size set how much work a workgroup
-streams between sorts."""
+"""Autotuner for the batched mode: times candidate launch configurations on
+graph replays of the actual batch and keeps the fastest.  A candidate is
+(tile size, LDS current replicas, sort cadence, particles per lane): the tile
+size sets the work per workgroup and the halo overhead, the sort cadence how
+many pushes run between two sorts, and the particles per lane how many
+64-particle chunks a wavefront of the push carries side by side (more chunks:
+more independent work to cover latencies; fewer: fewer registers, more
+resident wavefronts).  The particle arrays must be grouped by tile for each
+candidate tile size, so the caller supplies a function that builds the
+members' initial states for a given tile size."""
 from __future__ import annotations
 
 import time
 from typing import Callable, Dict, Sequence, Tuple
 
-Candidate = Tuple[int, int, int]   # (tile, replicas, sort_every)
+Candidate = Tuple[int, int, int, int]   # (tile, replicas, sort_every, particles per lane)
 
 DEFAULT_CANDIDATES: Tuple[Candidate, ...] = (
-    (8, 1, 1), (8, 1, 2), (16, 1, 1), (16, 2, 1), (16, 1, 2), (16, 1, 4), (32, 1, 1), (32, 1, 2))
+    (8, 1, 1, 2), (8, 1, 2, 2), (8, 1, 1, 1),
+    (16, 1, 1, 2), (16, 2, 1, 2), (16, 1, 2, 2), (16, 1, 4, 2),
+    (16, 1, 1, 1), (16, 1, 1, 4), (16, 1, 2, 1), (16, 1, 2, 4),
+    (32, 1, 1, 2), (32, 1, 2, 2), (32, 1, 1, 1), (32, 1, 1, 4))
 
 
 def time_batch(batch, steps: int) -> float:
@@ -35,23 +38,27 @@ def time_batch(batch, steps: int) -> float:
 def autotune_batch(build_members: Callable[[int], Sequence[dict]],
                    candidates: Sequence[Candidate] = DEFAULT_CANDIDATES,
                    steps: int = 4, j_float: bool = False) -> Tuple[Candidate, Dict[Candidate, float]]:
-    """Returns ((tile, replicas, sort_every), {candidate: seconds per step})."""
+    """Returns (best candidate, {candidate: seconds per step}); candidates the
+    library refuses (LDS budget, a cadence the tile cannot take, particles per
+    lane outside the default current) or whose grids are not whole tiles are
+    skipped."""
     from .sim import Batch
     from . import _lib
     timings: Dict[Candidate, float] = {}
-    for tile, reps, every in candidates:
+    for cand in candidates:
+        tile, reps, every, ppl = cand
         try:
             members = build_members(tile)
         except ValueError:
             continue   # a grid is not a whole number of such tiles
         try:
-            b = Batch(members, tile=tile, j_replicas=reps, j_float=j_float, sort_every=every)
+            b = Batch(members, tile=tile, j_replicas=reps, j_float=j_float, sort_every=every, ppl=ppl)
         except _lib.PicError:
-            continue   # e.g. over the LDS budget, or a cadence the tile cannot take
+            continue
         b.capture()
-        timings[(tile, reps, every)] = time_batch(b, steps)
+        timings[cand] = time_batch(b, steps)
         if b.check() != 0:
-            raise RuntimeError(f"device error while tuning tile={tile} replicas={reps} sort_every={every}")
+            raise RuntimeError(f"device error while tuning {cand}")
         b.close()
     best = min(timings, key=timings.get)
     return best, timings

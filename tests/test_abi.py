@@ -61,11 +61,13 @@ int main(void) {
     assert [int(v) for v in got] == want
 
 
-def _cfg(L, nx=64, ny=64, dx=0.1, dy=0.1, dt=0.07, tile=16, n=1000, ns=1, reps=0, flags=0, filt=0, every=0):
+def _cfg(L, nx=64, ny=64, dx=0.1, dy=0.1, dt=0.07, tile=16, n=1000, ns=1, reps=0, flags=0, filt=0, every=0,
+         ppl=0):
     c = L.pic_config()
     c.nx, c.ny, c.dx, c.dy, c.dt, c.tile, c.j_replicas, c.n_species, c.flags = nx, ny, dx, dy, dt, tile, reps, ns, flags
     c.j_filter = filt
     c.sort_every = every
+    c.ppl = ppl
     for k in range(ns):
         c.species[k].qm = -1.0
         c.species[k].q = -1.0 / 16
@@ -106,6 +108,13 @@ def test_query_sizes_and_validation():
         (dict(every=2, reps=2), L.PIC_EINVAL),
         (dict(every=2, flags=4), L.PIC_EINVAL),             # PIC_FLAG_MOVING_WINDOW
         (dict(tile=8, every=4), L.PIC_ETILE),               # 2k + 1 > tile
+        # particles per lane: 1, 2 or 4; other than 2 with the fixed-point
+        # current, the default deposit and one LDS copy
+        (dict(ppl=3), L.PIC_EINVAL),
+        (dict(ppl=-1), L.PIC_EINVAL),
+        (dict(ppl=4, flags=1), L.PIC_EINVAL),
+        (dict(ppl=1, flags=2), L.PIC_EINVAL),
+        (dict(ppl=4, reps=2), L.PIC_EINVAL),
     ]
     for kw, code in cases:
         ns = kw.pop("ns", 1)
@@ -116,6 +125,8 @@ def test_query_sizes_and_validation():
             L.pic_query(c)
         assert e.value.code == code, (kw, e.value.code)
     assert L.pic_query(_cfg(L, dt=0.0707)).n_tiles == 16
+    for ppl in (1, 2, 4):
+        assert L.pic_query(_cfg(L, ppl=ppl, every=2)).work_bytes == L.pic_query(_cfg(L, every=2)).work_bytes
     # 32 x 32 tiles take 70 KB of LDS with one current copy (two workgroups per
     # CU); the largest allowed configurations still fit the CU's 160 KB
     assert L.pic_query(_cfg(L, nx=64, tile=32, reps=2, flags=L.PIC_FLAG_J_FLOAT)).n_tiles == 4
@@ -146,7 +157,7 @@ def test_query_sizes_and_validation():
     # the filter's ping-pong planes: three FP32 current planes + one FP64 density plane
     sf = L.pic_query(_cfg(L, filt=L.PIC_MAX_FILTER))
     assert 20 * 64 * 64 <= sf.work_bytes - s.work_bytes <= 20 * 64 * 64 + 2 * 256
-    for code in range(0, -11, -1):
+    for code in range(0, -12, -1):
         assert L.strerror(code) != "unknown error"
     assert L.strerror(-99) == "unknown error"
 
@@ -169,7 +180,7 @@ def test_batch_query_validation():
                 [_cfg(L), _cfg(L, reps=2)], [_cfg(L), _cfg(L, filt=1)],
                 [_cfg(L), _cfg(L, flags=L.PIC_FLAG_ESIRKEPOV)],
                 [_cfg(L, flags=L.PIC_FLAG_MOVING_WINDOW)], [_cfg(L, flags=L.PIC_FLAG_FULL_SORT)],
-                [_cfg(L), _cfg(L, every=2)]):
+                [_cfg(L), _cfg(L, every=2)], [_cfg(L), _cfg(L, ppl=4)]):
         with pytest.raises(L.PicError) as e:
             L.pic_batch_query(bad)
         assert e.value.code == L.PIC_EINVAL

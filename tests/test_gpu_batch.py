@@ -108,8 +108,9 @@ def test_graph_replays_equal_direct_launches():
 
 def test_autotuner_picks_the_fastest_valid_candidate():
     """The autotuner times every candidate the library accepts for the
-    members (tile x replicas x sort cadence), skips the ones it rejects (tile
-    8 with cadence 4; tile 32 on grids that are not multiples of 32), and
+    members (tile x replicas x sort cadence x particles per lane), skips the
+    ones it rejects (tile 8 with cadence 4; four particles per lane with two
+    current copies; tile 32 on grids that are not multiples of 32), and
     returns the fastest."""
     from paper_2501_14795_amd.tune import autotune_batch
     members = pw.batched_members(n_sims=4, seed=23)
@@ -124,11 +125,13 @@ def test_autotuner_picks_the_fastest_valid_candidate():
                             species=[(m["spec"].qm, m["spec"].q, st)]))
         return out
 
-    cands = ((8, 1, 1), (8, 1, 4), (16, 1, 1), (16, 1, 2), (16, 1, 4))
+    cands = ((8, 1, 1, 2), (8, 1, 4, 2), (16, 1, 1, 2), (16, 1, 2, 2), (16, 1, 4, 2), (16, 1, 1, 1),
+             (16, 1, 1, 4), (16, 2, 1, 4))
     best, timings = autotune_batch(build, candidates=cands, steps=4)
     flush(f"autotuner: best {best}; " + ", ".join(f"{k}: {v * 1e3:.3f} ms" for k, v in timings.items()))
-    assert (8, 1, 4) not in timings            # 2k + 1 > tile: rejected by the library
-    assert set(timings) == {(8, 1, 1), (16, 1, 1), (16, 1, 2), (16, 1, 4)}
+    assert (8, 1, 4, 2) not in timings            # 2k + 1 > tile: rejected by the library
+    assert (16, 2, 1, 4) not in timings           # four particles per lane need one LDS current copy
+    assert set(timings) == {(8, 1, 1, 2), (16, 1, 1, 2), (16, 1, 2, 2), (16, 1, 4, 2), (16, 1, 1, 1), (16, 1, 1, 4)}
     assert best == min(timings, key=timings.get)
     assert all(v > 0 for v in timings.values())
 
@@ -216,3 +219,48 @@ def test_batch_members_against_the_oracle(tile, every):
         assert t.check() == 0
         t.close()
     batch.close()
+
+
+@pytest.mark.parametrize("tile,every", [(16, 1), (32, 1), (8, 2)])
+def test_particles_per_lane_do_not_change_results(tile, every):
+    """The push loop carrying 1, 2 or 4 chunks per lane gives bit-identical
+    particles, fields and tile offsets (each particle's arithmetic is the same,
+    the fixed-point current sums do not depend on their order), standalone
+    and batched; one step of ppl = 1 and 4 replayed against the oracle."""
+    from _parity import oracle_from_gpu, particle_errors, rel_err
+    from paper_2501_14795_amd import Batch, Sim
+    members = _members(3, 50 + tile, tile, sizes=(32, 64, 96) if tile == 32 else (32, 48, 64, 96))
+    runs = {ppl: [Sim(m["nx"], m["ny"], m["dx"], m["dy"], m["dt"], tile, m["species"], sort_every=every, ppl=ppl)
+                  for m in members] for ppl in (1, 2, 4)}
+    batches = {ppl: Batch(members, tile=tile, sort_every=every, ppl=ppl) for ppl in (1, 4)}
+    for step in range(5):
+        for ppl, sims in runs.items():
+            for i, s in enumerate(sims):
+                if step == 2 and ppl != 2:
+                    m = members[i]
+                    sp = type("S", (), {"qm": m["species"][0][0], "q": m["species"][0][1]})()
+                    ref = oracle_from_gpu(s, [sp], m["dx"], m["dy"], m["dt"])
+                    ref.push_deposit()
+                    s.push_deposit()
+                    pos, du = particle_errors(s.state(0), ref.species[0], m["nx"], m["ny"])
+                    ej = rel_err(s.field_arrays()["J"], ref.J)
+                    flush(f"T={tile} k={every} ppl={ppl} member {i}: replay pos {pos:.2e} u {du:.2e} J {ej:.2e}")
+                    assert pos < 1e-5 and du < 1e-5 and ej < 1e-5
+                    if (step + 1) % every == 0:
+                        s.sort()
+                    s.field_advance()
+                else:
+                    s.step()
+        for b in batches.values():
+            b.step()
+    for ppl in (1, 4):
+        for i in range(len(members)):
+            assert runs[ppl][i].check() == 0
+            _assert_same(runs[ppl][i], runs[2][i])
+            _assert_same(batches[ppl][i], runs[2][i])
+    flush(f"T={tile} k={every}: ppl 1, 2, 4 bit-identical, standalone and batched")
+    for sims in runs.values():
+        for s in sims:
+            s.close()
+    for b in batches.values():
+        b.close()
