@@ -20,6 +20,9 @@ Particle-Mesh Algorithms with FPGAs and OmpSs@OpenCL"):
                            three-step Yee update of Listing 3.1
 * ``sort_canonical``    -- strict tile re-sort (Sec. 4.3, Fig. 4.5), with the
                            removed / appended particles of the moving window
+* ``sort_motion_classes`` -- the alternative sort of Sec. 4.3 (after
+                           Germaschewski et al.): regrouping by new tile in
+                           one counting pass keyed on the motion class
 * ``sort_stable_by_tile`` -- particles in any order grouped into the tile
                            sections of Sec. 4.1 (Fig. 4.3), keeping their order
                            within a tile (numpy's stable sort, Python)
@@ -78,6 +81,8 @@ def lib():
         L.ora_field_advance.argtypes = [_i, _i, _d, _d, _d, _p, _p, _p]
         L.ora_sort_canonical.argtypes = [_i, _i, _i, _i64, _p, _p, _p, _p, _p, _p]
         L.ora_sort_canonical.restype = _i
+        L.ora_sort_motion_classes.argtypes = [_i, _i, _i, _i64, _p, _p, _p, _p, _p]
+        L.ora_sort_motion_classes.restype = _i
         L.ora_deposit_rho.argtypes = [_i, _i, _d, _i64, _p, _p, _p, _p, _p]
         L.ora_field_energy.argtypes = [_i, _i, _d, _d, _p]
         L.ora_field_energy.restype = _d
@@ -166,6 +171,26 @@ def sort_canonical(nx, ny, T, ix, iy, removed=None):
     if rc != 0:
         raise ValueError("cell index out of range")
     return off, src[:int(n_out[0])]
+
+
+def sort_motion_classes(nx, ny, T, ix, iy, off_old):
+    """The motion-class sort: particles in their tile sections (off_old, the
+    tile_offset before the sort) with cells (ix, iy) after the push, ordered
+    by (new tile, motion class, old slot); the class of a particle moving from
+    tile s to tile t is (dty + 1) * 3 + (dtx + 1), (dtx, dty) the step on the
+    periodic tile grid (+1 when an axis has two tiles).  Returns (new
+    tile_offset, src) with src[j] the old slot of the particle at slot j."""
+    ix, iy = _i32(ix), _i32(iy)
+    n = ix.size
+    ntiles = (nx // T) * (ny // T)
+    oo = np.ascontiguousarray(off_old, dtype=np.int64)
+    assert oo.size == ntiles + 1 and oo[-1] == n
+    off = np.zeros(ntiles + 1, dtype=np.int64)
+    src = np.zeros(max(n, 1), dtype=np.int64)
+    rc = lib().ora_sort_motion_classes(nx, ny, T, n, _ptr(ix), _ptr(iy), _ptr(oo), _ptr(off), _ptr(src))
+    if rc != 0:
+        raise ValueError("a cell is outside the grid or more than one tile from its section")
+    return off, src[:n]
 
 
 def sort_stable_by_tile(nx, ny, T, ix, iy):

@@ -463,6 +463,76 @@ done:
 }
 
 /* ------------------------------------------------------------------------ */
+/* The motion-class sort, the alternative Sec. 4.3 cites (after Germaschewski */
+/* et al.): by the Courant condition of Eq. (1) a particle ends each step in  */
+/* its own tile or one of the eight around it, so its motion falls into one   */
+/* of nine classes, and the array is regrouped by new tile in one counting    */
+/* pass keyed on the class.                                                   */
+/* ------------------------------------------------------------------------ */
+
+/* Step of a tile index from a to b on a periodic axis of m tiles: 0, +1 or
+ * -1; +1 when m == 2 (both neighbours are the same tile); 2 if b is further
+ * than one tile from a. */
+static int tile_step(int a, int b, int m)
+{
+    int d = wrap(b - a, m);
+    if (d == 0) return 0;
+    if (d == 1) return 1;
+    if (d == m - 1) return -1;
+    return 2;
+}
+
+/*
+ * Input: n particles in their tile sections before the sort -- slots
+ * off_old[s] .. off_old[s+1]-1 hold the particles of tile s (tile_offset,
+ * Sec. 4.1) -- and their cells (ix, iy) after the push.  The class of the
+ * particle at a slot of section s that now lies in tile t is
+ * (dty + 1) * 3 + (dtx + 1), with (dtx, dty) the step from s to t on the
+ * periodic tile grid (tile_step).
+ * Output: the particles ordered by (new tile, class, old slot): off[0 ..
+ * ntiles] the new tile_offset, src[j] the old slot of the particle that ends
+ * at slot j.  Returns 0, or -1 if a cell is out of range or further than one
+ * tile from its section's tile.
+ */
+int ora_sort_motion_classes(int nx, int ny, int T, int64_t n, const int32_t *ix,
+                            const int32_t *iy, const int64_t *off_old,
+                            int64_t *off, int64_t *src)
+{
+    const int ntx = nx / T, nty = ny / T;
+    const int64_t ntiles = (int64_t)ntx * nty;
+    int64_t *key = malloc(sizeof(int64_t) * (n ? n : 1));
+    int64_t *start = calloc(ntiles * 9 + 1, sizeof(int64_t));
+    int rc = 0;
+
+    for (int64_t s = 0; s < ntiles && rc == 0; s++) {
+        const int sx = (int)(s % ntx), sy = (int)(s / ntx);
+        for (int64_t i = off_old[s]; i < off_old[s + 1]; i++) {
+            if (ix[i] < 0 || ix[i] >= nx || iy[i] < 0 || iy[i] >= ny) {
+                rc = -1;
+                break;
+            }
+            const int tx = ix[i] / T, ty = iy[i] / T;
+            const int dtx = tile_step(sx, tx, ntx), dty = tile_step(sy, ty, nty);
+            if (dtx == 2 || dty == 2) {
+                rc = -1;
+                break;
+            }
+            key[i] = ((int64_t)ty * ntx + tx) * 9 + (dty + 1) * 3 + (dtx + 1);
+            start[key[i] + 1]++;
+        }
+    }
+    if (rc == 0) {
+        /* counting sort on the key, stable in the old slot order */
+        for (int64_t k = 0; k < ntiles * 9; k++) start[k + 1] += start[k];
+        for (int64_t t = 0; t <= ntiles; t++) off[t] = start[t * 9];
+        for (int64_t i = 0; i < n; i++) src[start[key[i]]++] = i;
+    }
+    free(key);
+    free(start);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Diagnostics.                                                               */
 /* ------------------------------------------------------------------------ */
 

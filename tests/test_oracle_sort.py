@@ -28,7 +28,8 @@ def _read_golden(name):
                 continue
             k, v = line.split(":")
             vals = [int(t) for t in v.split()]
-            d[k.strip()] = vals if len(vals) > 1 or k.strip() in ("ix", "iy", "off", "src", "removed") else vals[0]
+            d[k.strip()] = vals if len(vals) > 1 or k.strip() in ("ix", "iy", "off", "src", "removed",
+                                                                  "off_old") else vals[0]
     return d
 
 
@@ -172,3 +173,80 @@ def test_stable_grouping_by_tile(ora):
     assert ora.sort_stable_by_tile(16, 8, 8, ix, iy)[1].tolist() == list(ok[0])
     with pytest.raises(ValueError):
         ora.sort_stable_by_tile(16, 8, 8, np.array([16], np.int32), np.array([0], np.int32))
+
+
+# ---------------------------------------------------------------- motion-class sort
+# The alternative sort of Sec. 4.3 (after Germaschewski et al.): the particles
+# are regrouped by their new tile in one counting pass keyed on their motion
+# class.  Its result is characterised by: (a) the new sections hold only their
+# tile's particles, counted from the final positions; (b) inside a section the
+# particles come in ascending motion class, the class of a particle being the
+# step (dtx, dty) from its old section's tile to its new tile on the periodic
+# tile grid, numbered (dty + 1) * 3 + (dtx + 1), with the step counted +1 on
+# an axis of two tiles (both neighbours coincide); (c) within one class, in
+# ascending old slot; (d) a permutation.  Brute force over all permutations of
+# tiny arrays finds exactly one such order, which the oracle must return.
+
+@pytest.mark.parametrize("name", ["sort_motion_1d.txt", "sort_motion_2d.txt", "sort_motion_two_tiles.txt"])
+def test_sort_motion_golden(ora, name):
+    g = _read_golden(name)
+    off, src = ora.sort_motion_classes(g["nx"], g["ny"], g["T"], g["ix"], g["iy"], g["off_old"])
+    assert off.tolist() == g["off"]
+    assert src.tolist() == g["src"]
+
+
+def _step(a, b, m):
+    d = (b - a) % m
+    return 0 if d == 0 else (1 if d == 1 else (-1 if d == m - 1 else None))
+
+
+def _motion_valid(perm, new_tile, cls, off):
+    for j, i in enumerate(perm):
+        if not (off[new_tile[i]] <= j < off[new_tile[i] + 1]):
+            return False
+    for t in range(len(off) - 1):
+        sec = [perm[j] for j in range(off[t], off[t + 1])]
+        keys = [(cls[i], i) for i in sec]
+        if keys != sorted(keys):
+            return False
+    return True
+
+
+def test_sort_motion_brute_force_tiny(ora):
+    rng = np.random.default_rng(1)
+    for trial in range(120):
+        nx, ny, T = [(3, 3, 1), (4, 2, 2), (2, 2, 1), (6, 2, 2), (3, 1, 1)][trial % 5]
+        ntx, nty = nx // T, ny // T
+        ntiles = ntx * nty
+        n = int(rng.integers(0, 7))
+        # old sections: a random split of the n slots over the tiles
+        sizes = np.bincount(rng.integers(0, ntiles, n), minlength=ntiles) if n else np.zeros(ntiles, int)
+        off_old = np.r_[0, np.cumsum(sizes)]
+        old_tile = np.repeat(np.arange(ntiles), sizes)
+        # every particle ends in its section's tile or a neighbour (cells anywhere inside it)
+        ix = np.zeros(n, int)
+        iy = np.zeros(n, int)
+        new_tile = np.zeros(n, int)
+        cls = np.zeros(n, int)
+        for i in range(n):
+            sx, sy = old_tile[i] % ntx, old_tile[i] // ntx
+            tx = (sx + int(rng.integers(-1, 2))) % ntx
+            ty = (sy + int(rng.integers(-1, 2))) % nty
+            ix[i] = tx * T + int(rng.integers(0, T))
+            iy[i] = ty * T + int(rng.integers(0, T))
+            new_tile[i] = ty * ntx + tx
+            cls[i] = (_step(sy, ty, nty) + 1) * 3 + (_step(sx, tx, ntx) + 1)
+        off = np.r_[0, np.cumsum(np.bincount(new_tile, minlength=ntiles))] if n else np.zeros(ntiles + 1, int)
+        sols = [p for p in itertools.permutations(range(n)) if _motion_valid(p, new_tile, cls, off)]
+        assert len(sols) == 1
+        o_off, o_src = ora.sort_motion_classes(nx, ny, T, ix, iy, off_old)
+        assert o_off.tolist() == off.tolist()
+        assert tuple(o_src.tolist()) == sols[0]
+
+
+def test_sort_motion_rejects_moves_beyond_a_neighbour(ora):
+    # 4 tiles along x: from tile 0 to tile 2 is two tiles
+    with pytest.raises(ValueError):
+        ora.sort_motion_classes(8, 2, 2, [4], [0], [0, 1, 1, 1, 1])
+    with pytest.raises(ValueError):
+        ora.sort_motion_classes(8, 2, 2, [8], [0], [0, 1, 1, 1, 1])   # outside the grid
