@@ -115,12 +115,12 @@ def batched_comparison(n_sims=256, steps=5, tune_sims=32):
         return out
 
     t0 = time.perf_counter()
-    (tile, reps, every, ppl), tuning = autotune_batch(lambda T: build(T, tune_sims))
-    log(f"autotuned tile {tile} replicas {reps} sort_every {every} particles/lane {ppl} in "
+    (tile, reps, every, ppl, motion), tuning = autotune_batch(lambda T: build(T, tune_sims))
+    log(f"autotuned tile {tile} replicas {reps} sort_every {every} particles/lane {ppl} motion sort {motion} in "
         f"{time.perf_counter() - t0:.1f}s: {tuning}")
     members = build(tile)
     n = sum(m["species"][0][2]["ix"].size for m in members)
-    b = Batch(members, tile=tile, j_replicas=reps, sort_every=every, ppl=ppl)
+    b = Batch(members, tile=tile, j_replicas=reps, sort_every=every, ppl=ppl, motion_sort=motion)
     del members
     direct = time_batch(b, steps)
     # one simulation per launch sequence, on the same members
@@ -145,8 +145,9 @@ def batched_comparison(n_sims=256, steps=5, tune_sims=32):
     return {
         "workload": f"{n_sims} simulations, grids 32..256 cells, 8..64 ppc (seed 4)",
         "particles": n, "steps": steps, "tile": tile, "j_replicas": reps, "sort_every": every,
-        "particles_per_lane": ppl,
-        "autotune_ms_per_step": {f"T{k[0]}_R{k[1]}_S{k[2]}_P{k[3]}": v * 1e3 for k, v in tuning.items()},
+        "particles_per_lane": ppl, "sort": "motion-class" if motion else "in-place",
+        "autotune_ms_per_step": {f"T{k[0]}_R{k[1]}_S{k[2]}_P{k[3]}{'_M' if k[4] else ''}": v * 1e3
+                                 for k, v in tuning.items()},
         "graph_pushes_per_s": n / graph, "direct_pushes_per_s": n / direct,
         "per_sim_launch_pushes_per_s": n / per_sim,
         "graph_ms_per_step": graph * 1e3, "direct_ms_per_step": direct * 1e3,
@@ -416,8 +417,8 @@ def main():
         if not args.esirkepov:
             out["esirkepov"] = variant_measurement(w, T, esirkepov=True)
             log(f"esirkepov: {out['esirkepov']}")
-        out["full_sort"] = variant_measurement(w, T, full_sort=True)
-        log(f"full re-sort: {out['full_sort']}")
+        out["motion_sort"] = variant_measurement(w, T, motion_sort=True)
+        log(f"motion-class sort: {out['motion_sort']}")
         for ppl in (1, 4):
             out[f"particles_per_lane_{ppl}"] = variant_measurement(w, T, ppl=ppl)
             log(f"{ppl} particle(s) per lane: {out[f'particles_per_lane_{ppl}']}")

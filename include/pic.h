@@ -107,15 +107,20 @@ extern "C" {
 #define PIC_FLAG_MOVING_WINDOW 4u
 
 /*
- * Alternative sort (pic_config.flags; the full re-sort the paper cites as the
- * other way to keep particles grouped, Sec. 4.3): pic_sort() regroups every
- * species out of place by a stable radix sort on the tile id (the order
- * inside a tile kept) instead of moving only the particles that left their
- * section.  It reads and writes every particle, so it pays only when most
- * particles move; the autotuner and the bench compare the two.  Not in
- * batched mode.  pic_diag's mover count is 0 with it.
+ * Alternative sort (pic_config.flags): the motion-class sort Sec. 4.3 cites
+ * (after Germaschewski et al.).  By the Courant condition a particle ends a
+ * step in its own tile or one of the eight around it, so its motion falls
+ * into one of nine classes, (dty + 1) * 3 + (dtx + 1) for the step (dtx, dty)
+ * from the tile whose section held it to its new tile (counted +1 on an axis
+ * of two tiles, where both neighbours coincide); the push counts every tile's
+ * particles per class.  pic_sort() then moves every particle, in one counting
+ * pass, to its slot in the order (new tile, class, old slot) in the
+ * workspace, and copies the result back: out of place, reading and writing
+ * every particle twice, so it pays only when most particles change tile.
+ * Also in batched mode.  pic_diag's mover count is 0 with it.  The moving
+ * window keeps its own (in-place) re-sort.
  */
-#define PIC_FLAG_FULL_SORT 8u
+#define PIC_FLAG_MOTION_SORT 8u
 
 /*
  * Binomial current filter (pic_config.j_filter; Listing 3.1's optional
@@ -143,7 +148,7 @@ typedef struct pic_config {
     int32_t j_replicas;  /* LDS current replicas per tile: 1, 2 or 4 (0 = default) */
     int32_t n_species;   /* 1 .. PIC_MAX_SPECIES */
     uint32_t flags;      /* OR of PIC_FLAG_J_FLOAT, PIC_FLAG_ESIRKEPOV, PIC_FLAG_MOVING_WINDOW,
-                            PIC_FLAG_FULL_SORT, or 0 */
+                            PIC_FLAG_MOTION_SORT, or 0 */
     int32_t j_filter;    /* binomial current filter passes, 0 (off) .. PIC_MAX_FILTER */
     int32_t sort_every;  /* sort cadence k = 1, 2 or 4 (0: 1): pic_step sorts every
                             k-th step and the push stages a halo k cells wide.  k > 1

@@ -29,7 +29,7 @@ PIC_GAUSS_NOALLOC_MAX_CELLS = 1 << 20
 PIC_FLAG_J_FLOAT = 1
 PIC_FLAG_ESIRKEPOV = 2
 PIC_FLAG_MOVING_WINDOW = 4
-PIC_FLAG_FULL_SORT = 8
+PIC_FLAG_MOTION_SORT = 8
 
 PIC_DIAG_ENERGY = 1
 PIC_DIAG_RHO_SNAPSHOT = 2

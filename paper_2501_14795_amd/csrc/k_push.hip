@@ -482,8 +482,10 @@ __device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool
     m.ux = ux;
     m.uy = uy;
     m.uz = uz;
-    const int dtx = tx_wrap ? (nlx < 0 ? -1 : (nlx >= T ? 1 : 0)) : 0;
-    const int dty = ty_wrap ? (nly < 0 ? -1 : (nly >= T ? 1 : 0)) : 0;
+    // the step to the new tile; on an axis of two tiles both neighbours are
+    // the same tile, and the step is counted +1 either way
+    const int dtx = tx_wrap ? (nlx < 0 ? (a.ntx == 2 ? 1 : -1) : (nlx >= T ? 1 : 0)) : 0;
+    const int dty = ty_wrap ? (nly < 0 ? (a.nty == 2 ? 1 : -1) : (nly >= T ? 1 : 0)) : 0;
     m.dir = (dty + 1) * 3 + (dtx + 1);
     return m;
 }

@@ -407,12 +407,185 @@ __device__ __forceinline__ void sort_scatter_unit(const SortArgs &a, int spi, in
     }
 }
 
+// ---- The motion-class sort (the alternative of Sec. 4.3, after
+// Germaschewski et al.): by the Courant condition a particle ends a step in
+// its own tile or one of the eight around it, so its motion falls into one of
+// nine classes d = (dty + 1) * 3 + (dtx + 1) -- the step from the tile whose
+// section holds it to its new tile, counted +1 on an axis of two tiles, the
+// push kernel's direction code -- and the push has already counted the
+// particles of every (tile, class).  One pass then moves every particle of
+// source tile s and class d to its place in the new order (new tile, class,
+// old slot) in the staging arrays: base(s, d) = the new section start of the
+// destination tile t = s + step(d), plus the counts of the classes before d
+// arriving at t from their own source tiles.  A second pass copies the
+// staging arrays back.  Out of place: reads and writes every particle twice,
+// so it pays only when most particles change tile.
+
+// the step from tile coordinate a to b on an axis of m tiles: 0, +1, -1
+// (+1 when m == 2), 2 if further
+__device__ __forceinline__ int tile_step_s(int a, int b, int m)
+{
+    const int d = b - a;
+    if (d == 0) return 0;
+    if (d == 1 || d == 1 - m) return 1;
+    if (d == -1 || d == m - 1) return -1;
+    return 2;
+}
+
+// The motion class of a particle of the tile at (sx, sy) now in cell `cell`,
+// or 9 if the cell is outside the grid or more than one tile away.
+__device__ __forceinline__ int motion_class(int cell, int sx, int sy, int ntx, int nty, int tsh)
+{
+    const int stx = tile_step_s(sx, (cell & 0xffff) >> tsh, ntx);
+    const int sty = tile_step_s(sy, (cell >> 16) >> tsh, nty);
+    return (cell < 0 || stx == 2 || sty == 2) ? 9 : (sty + 1) * 3 + (stx + 1);
+}
+
+struct Part6 {
+    int cell;
+    float x, y, ux, uy, uz;
+};
+
+__device__ __forceinline__ Part6 load_part(const Parts &p, int i)
+{
+    return Part6{p.cell[i], p.x[i], p.y[i], p.ux[i], p.uy[i], p.uz[i]};
+}
+
+__device__ __forceinline__ void store_part(const Parts &p, int i, const Part6 &v)
+{
+    p.cell[i] = v.cell;
+    p.x[i] = v.x;
+    p.y[i] = v.y;
+    p.ux[i] = v.ux;
+    p.uy[i] = v.uy;
+    p.uz[i] = v.uz;
+}
+
+// The kSortWaves source tiles of group grp, one after the other, each by the
+// whole block: the section's 64-aligned chunks are split into one run per
+// wavefront; a first pass counts every run's particles per class, a second
+// streams the runs again and moves each particle to its slot (its class's
+// first slot in the destination, the class's particles in the earlier runs,
+// its rank in its chunk).
+__device__ __forceinline__ void motion_scatter_unit(const SortArgs &a, int spi, int grp)
+{
+    constexpr int W = kSortWaves;
+    __shared__ int s_cls[W][9];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const SortSpecies &sp = a.sp[spi];
+    const int ntx = a.ntx, nty = a.nty;
+    const int tsh = __builtin_ctz(a.tile);
+    for (int q = 0; q < kSortWaves; ++q) {
+        const int s = grp * kSortWaves + q;
+        if (s >= a.n_tiles) break;   // uniform over the block
+        const int sx = s % ntx, sy = s / ntx;
+        const int oA = sp.off[s], oB = sp.off[s + 1];
+        int lo, hi;
+        wave_range(oA, oB, w, W, lo, hi);
+        // pass 1: lane d counts the run's particles of class d
+        int mine = 0;
+        for (int c0 = (lo >> 6) << 6; c0 < hi; c0 += 64) {
+            const int i = c0 + lane;
+            const int d = (i >= lo && i < hi) ? motion_class(sp.p.cell[i], sx, sy, ntx, nty, tsh) : 10;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const int c = __popcll(__ballot(d == k));
+                if (lane == k) mine += c;
+            }
+        }
+        if (lane < 9) s_cls[w][lane] = mine;
+        __syncthreads();
+        // lane d < 9: the run's first slot for class d and the class's end
+        int pos = 0, end = 0;
+        bool bad = false;
+        if (lane < 9) {
+            const int dx = lane % 3 - 1, dy = lane / 3 - 1;
+            const int t = wrap_s(sy + dy, nty) * ntx + wrap_s(sx + dx, ntx);
+            const int tx = t % ntx, ty = t / ntx;
+            pos = sp.offn[t];
+            for (int d2 = 0; d2 < lane; ++d2) {
+                const int src = wrap_s(ty - (d2 / 3 - 1), nty) * ntx + wrap_s(tx - (d2 % 3 - 1), ntx);
+                pos += sp.cnt[(int64_t)src * kCntStride + d2];
+            }
+            const int total = sp.cnt[(int64_t)s * kCntStride + lane];
+            end = pos + total;
+            int all = 0;
+            for (int w2 = 0; w2 < W; ++w2) {
+                if (w2 < w) pos += s_cls[w2][lane];
+                all += s_cls[w2][lane];
+            }
+            bad = all != total;   // the push's counts and the cells disagree
+        }
+        // pass 2: the particles to their slots, the next chunk in flight
+        int c0 = (lo >> 6) << 6;
+        Part6 nxt{};
+        if (c0 < hi && c0 + lane >= lo && c0 + lane < hi) nxt = load_part(sp.p, c0 + lane);
+        for (; c0 < hi; c0 += 64) {
+            const Part6 cur = nxt;
+            const int i = c0 + lane;
+            const bool in = i >= lo && i < hi;
+            const int i2 = i + 64;
+            if (i2 >= lo && i2 < hi) nxt = load_part(sp.p, i2);
+            const int d = in ? motion_class(cur.cell, sx, sy, ntx, nty, tsh) : 10;
+            unsigned long long m_d = 0ull;
+            int taken = 0;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const unsigned long long m = __ballot(d == k);
+                if (d == k) m_d = m;
+                if (lane == k) taken = __popcll(m);
+            }
+            const int at = __shfl(pos, d < 9 ? d : 0, 64) + lane_rank_s(m_d);
+            const int lim = __shfl(end, d < 9 ? d : 0, 64);
+            if (in) {
+                if (d < 9 && at < lim && (unsigned)at < (unsigned)sp.n) store_part(sp.stg, at, cur);
+                else bad = true;
+            }
+            pos += taken;
+        }
+        const bool anybad = __ballot(bad) != 0ull;
+        if (lane == 0 && anybad) atomicOr(a.err, kErrSort);
+        if (threadIdx.x == 0) sp.mcount[s] = 0;   // pic_diag's mover count: not tracked by this sort
+        __syncthreads();   // s_cls is reused by the next tile
+    }
+}
+
+// The new sections of the group's tiles (contiguous) from the staging arrays
+// into the particle arrays, by the whole block, four particles per thread in
+// flight; the new tile_offset replaces the old one.
+__device__ __forceinline__ void motion_copy_unit(const SortArgs &a, int spi, int grp)
+{
+    const SortSpecies &sp = a.sp[spi];
+    const int t0 = grp * kSortWaves;
+    if (t0 >= a.n_tiles) return;
+    const int t1 = min(t0 + kSortWaves, a.n_tiles);
+    const int A = sp.offn[t0], B = sp.offn[t1];
+    constexpr int U = 4;
+    for (int i0 = A + (int)threadIdx.x; i0 < B; i0 += U * kBlock) {
+        Part6 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + u * kBlock < B) v[u] = load_part(sp.stg, i0 + u * kBlock);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + u * kBlock < B) store_part(sp.p, i0 + u * kBlock, v[u]);
+    }
+    if ((int)threadIdx.x < t1 - t0) {
+        const int t = t0 + threadIdx.x;
+        sp.off[t] = sp.offn[t];
+        if (t == a.n_tiles - 1) sp.off[t + 1] = sp.offn[t + 1];
+    }
+}
+
 // ---- single-simulation kernels: blockIdx.y = species
 __global__ void __launch_bounds__(kScanBlock) k_sort_count(SortArgs a) { sort_count_unit(a, blockIdx.y, blockIdx.x); }
 __global__ void __launch_bounds__(1024) k_sort_scan_blocks(SortArgs a) { sort_scan_unit(a, blockIdx.x); }
 __global__ void __launch_bounds__(kScanBlock) k_sort_add_base(SortArgs a) { sort_add_unit(a, blockIdx.y, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_sort_plan(SortArgs a) { sort_plan_unit(a, blockIdx.y, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_sort_scatter(SortArgs a) { sort_scatter_unit(a, blockIdx.y, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_motion_scatter(SortArgs a) { motion_scatter_unit(a, blockIdx.y, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_motion_copy(SortArgs a) { motion_copy_unit(a, blockIdx.y, blockIdx.x); }
 
 // ---- many simulations: one block per work item (sim, species, unit)
 __global__ void __launch_bounds__(kScanBlock) k_sort_count_b(const SortArgs *d, const int4 *it)
@@ -439,6 +612,17 @@ __global__ void __launch_bounds__(kBlock) k_sort_scatter_b(const SortArgs *d, co
 {
     const int4 w = it[blockIdx.x];
     sort_scatter_unit(d[w.x], w.y, w.z);
+}
+
+__global__ void __launch_bounds__(kBlock) k_motion_scatter_b(const SortArgs *d, const int4 *it)
+{
+    const int4 w = it[blockIdx.x];
+    motion_scatter_unit(d[w.x], w.y, w.z);
+}
+__global__ void __launch_bounds__(kBlock) k_motion_copy_b(const SortArgs *d, const int4 *it)
+{
+    const int4 w = it[blockIdx.x];
+    motion_copy_unit(d[w.x], w.y, w.z);
 }
 
 // ---- tile_offset from caller particles: whether every cell is in the grid
@@ -500,14 +684,31 @@ void launch_sort_scatter(const SortArgs &a, int n_tiles, hipStream_t s)
                        s, a);
 }
 
-void launch_sort_batch(const SortBatch &b, hipStream_t s)
+void launch_sort_batch(const SortBatch &b, bool motion, hipStream_t s)
 {
     if (b.n_count == 0) return;
     hipLaunchKernelGGL(k_sort_count_b, dim3(b.n_count), dim3(kScanBlock), 0, s, b.descs, b.count_items);
     hipLaunchKernelGGL(k_sort_scan_blocks_b, dim3(b.n_scan), dim3(1024), 0, s, b.descs, b.scan_items);
     hipLaunchKernelGGL(k_sort_add_base_b, dim3(b.n_count), dim3(kScanBlock), 0, s, b.descs, b.count_items);
-    hipLaunchKernelGGL(k_sort_plan_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
-    hipLaunchKernelGGL(k_sort_scatter_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
+    if (motion) {
+        hipLaunchKernelGGL(k_motion_scatter_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
+        hipLaunchKernelGGL(k_motion_copy_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
+    } else {
+        hipLaunchKernelGGL(k_sort_plan_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
+        hipLaunchKernelGGL(k_sort_scatter_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
+    }
+}
+
+void launch_motion_scatter(const SortArgs &a, int n_tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_motion_scatter, dim3((n_tiles + kSortWaves - 1) / kSortWaves, a.n_species), dim3(kBlock),
+                       0, s, a);
+}
+
+void launch_motion_copy(const SortArgs &a, int n_tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_motion_copy, dim3((n_tiles + kSortWaves - 1) / kSortWaves, a.n_species), dim3(kBlock), 0, s,
+                       a);
 }
 
 void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile, int ntx, int n_tiles, int32_t *off,

@@ -3,9 +3,7 @@
 // arrive in any order: a stable least-significant-digit radix sort on the
 // tile id, 8 bits per pass, then a gather of the six particle arrays.
 // Stability keeps the given order inside a tile, so already grouped input is
-// left as it is.  Runs at initialisation and state loads, and after every
-// push as the full re-sort of PIC_FLAG_FULL_SORT (the alternative to the
-// in-place sort, which moves only the particles that left their section).
+// left as it is.  Runs at initialisation and state loads.
 //
 // One pass over n keys, in chunks of kTsChunk consecutive keys per
 // workgroup:

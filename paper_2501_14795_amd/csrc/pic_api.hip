@@ -43,7 +43,7 @@ int default_replicas(const pic_config *c)
 int validate(const pic_config *c)
 {
     if (!c) return PIC_EINVAL;
-    if (c->flags & ~(uint32_t)(PIC_FLAG_J_FLOAT | PIC_FLAG_ESIRKEPOV | PIC_FLAG_MOVING_WINDOW | PIC_FLAG_FULL_SORT))
+    if (c->flags & ~(uint32_t)(PIC_FLAG_J_FLOAT | PIC_FLAG_ESIRKEPOV | PIC_FLAG_MOVING_WINDOW | PIC_FLAG_MOTION_SORT))
         return PIC_EINVAL;
     // the Esirkepov deposit is built for the fixed-point current only
     if ((c->flags & PIC_FLAG_ESIRKEPOV) && (c->flags & PIC_FLAG_J_FLOAT)) return PIC_EINVAL;
@@ -748,36 +748,26 @@ int pic_push_deposit(pic_sim *S, hipStream_t stream)
     return rc;
 }
 
-// The alternative sort (PIC_FLAG_FULL_SORT): every species regrouped by the
-// stable radix sort on the tile id, then tile_offset rebuilt from the
-// grouped cells (which also re-checks the grouping: PIC_EORDER through
-// pic_check if it failed).  Timed as plan (radix passes), scatter (gather)
-// and scan (offsets).
-static int full_sort(pic_sim *S, hipStream_t stream)
+// The alternative sort (PIC_FLAG_MOTION_SORT): the motion-class sort --
+// recount and scan as for the in-place sort, then every particle into the
+// staging arrays at its slot in the (new tile, motion class, old slot) order
+// (timed as plan), and the staging arrays copied back (timed as scatter).
+static int motion_sort(pic_sim *S, hipStream_t stream)
 {
-    const pic_config &c = S->cfg;
-    int rc = PIC_OK;
-    for (int s = 0; s < c.n_species && rc == PIC_OK; ++s) {
-        auto &P = S->sp[s];
-        const TileSortArgs t = tile_sort_args(S, s);
-        const uint32_t *perm;
-        {
-            Timed tm(S, PIC_KERNEL_SORT_PLAN, stream);
-            perm = launch_tile_sort_perm(t, stream);
-        }
-        {
-            Timed tm(S, PIC_KERNEL_SORT_SCATTER, stream);
-            launch_tile_sort_gather(t, perm, stream);
-        }
-        {
-            Timed tm(S, PIC_KERNEL_SORT_SCAN, stream);
-            launch_init_tiles(t.p.cell, t.n, c.nx, c.ny, c.tile, S->ntx, S->n_tiles, P.off, S->err, stream);
-        }
-        // a fill kernel, not a memset: pic_step may be captured into a graph
-        launch_zero_i32(P.mcount, S->n_tiles, stream);
+    const SortArgs a = sort_args(S);
+    {
+        Timed t(S, PIC_KERNEL_SORT_SCAN, stream);
+        launch_sort_scan(a, S->n_tiles, stream);
     }
-    if (rc == PIC_OK) rc = hip_ok(hipGetLastError());
-    return rc;
+    {
+        Timed t(S, PIC_KERNEL_SORT_PLAN, stream);
+        launch_motion_scatter(a, S->n_tiles, stream);
+    }
+    {
+        Timed t(S, PIC_KERNEL_SORT_SCATTER, stream);
+        launch_motion_copy(a, S->n_tiles, stream);
+    }
+    return hip_ok(hipGetLastError());
 }
 
 int pic_sort(pic_sim *S, hipStream_t stream)
@@ -785,7 +775,7 @@ int pic_sort(pic_sim *S, hipStream_t stream)
     if (!S) return PIC_EINVAL;
     if (S->since_sort == 0) return PIC_OK;   // already sorted: the count records are spent
     S->since_sort = 0;
-    if (S->cfg.flags & PIC_FLAG_FULL_SORT) return full_sort(S, stream);
+    if (S->cfg.flags & PIC_FLAG_MOTION_SORT) return motion_sort(S, stream);
     const SortArgs a = sort_args(S);
     {
         Timed t(S, PIC_KERNEL_SORT_SCAN, stream);
@@ -930,10 +920,8 @@ int pic_step(pic_sim *S, hipStream_t stream)
     if (!S) return PIC_EINVAL;
     int rc = push_only(S, stream);
     if (rc) return rc;
-    // Unforked: no sort this step, no second stream, or the full re-sort,
-    // whose histogram may borrow the tile current halos (tiny species) that
-    // the field half still has to fold
-    if (S->since_sort < S->halo || !S->side || (S->cfg.flags & PIC_FLAG_FULL_SORT)) {
+    // Unforked: no sort this step, or no second stream
+    if (S->since_sort < S->halo || !S->side) {
         rc = fold_current(S, stream);
         if (rc == PIC_OK && S->since_sort >= S->halo) rc = pic_sort(S, stream);
         if (rc == PIC_OK) rc = pic_field_advance(S, stream);
@@ -1208,7 +1196,6 @@ int batch_validate(int n, const pic_config *cfgs)
             halo_of(&cfgs[i]) != halo_of(&cfgs[0]) || ppl_of(&cfgs[i]) != ppl_of(&cfgs[0]))
             return PIC_EINVAL;
         if (cfgs[i].flags & PIC_FLAG_MOVING_WINDOW) return PIC_EINVAL;   // member counts are fixed
-        if (cfgs[i].flags & PIC_FLAG_FULL_SORT) return PIC_EINVAL;       // the graph holds the in-place sort
     }
     return PIC_OK;
 }
@@ -1275,7 +1262,7 @@ void batch_enqueue_step(pic_batch *b, bool sort, hipStream_t stream)
     sb.n_scan = b->n_scan;
     sb.plan_items = b->plan_items;
     sb.n_plan = b->n_plan;
-    if (sort) launch_sort_batch(sb, stream);
+    if (sort) launch_sort_batch(sb, (b->sims[0]->cfg.flags & PIC_FLAG_MOTION_SORT) != 0, stream);
     if (fork) (void)hipStreamWaitEvent(stream, b->ev_join, 0);
 }
 

@@ -77,7 +77,12 @@ struct SortBatch {
     const int4 *scan_items; int n_scan;
     const int4 *plan_items; int n_plan;
 };
-void launch_sort_batch(const SortBatch &b, hipStream_t s);
+// motion: the motion-class sort (PIC_FLAG_MOTION_SORT) instead of the in-place one
+void launch_sort_batch(const SortBatch &b, bool motion, hipStream_t s);
+// the motion-class sort after the recount and scan: every particle into the
+// staging arrays at its new slot, then the staging arrays copied back
+void launch_motion_scatter(const SortArgs &a, int n_tiles, hipStream_t s);
+void launch_motion_copy(const SortArgs &a, int n_tiles, hipStream_t s);
 // tile_offset (off, n_tiles + 1) of n cells grouped by tile; sets kErrOrder
 // for a cell outside the grid and kErrGroup if they are not grouped (off is
 // then meaningless but every write stays inside it)

@@ -134,8 +134,8 @@ def test_query_sizes_and_validation():
     assert L.pic_query(_cfg(L, nx=64, tile=32, reps=4)).n_tiles == 4     # int64 current x 4: 158 KB
     assert L.pic_query(_cfg(L, nx=64, tile=32, every=4)).n_tiles == 4    # halo pad 4: 91 KB
     assert L.pic_query(_cfg(L, flags=L.PIC_FLAG_ESIRKEPOV)).work_bytes == s.work_bytes
-    # the full re-sort works in the in-place sort's scratch: no extra workspace
-    assert L.pic_query(_cfg(L, flags=L.PIC_FLAG_FULL_SORT)).work_bytes == s.work_bytes
+    # the motion-class sort works in the in-place sort's staging arrays: no extra workspace
+    assert L.pic_query(_cfg(L, flags=L.PIC_FLAG_MOTION_SORT)).work_bytes == s.work_bytes
     # capacity: per-particle scratch sized for it; below n is invalid
     c = _cfg(L)
     c.species[0].cap = 2000
@@ -179,11 +179,13 @@ def test_batch_query_validation():
     for bad in ([_cfg(L), _cfg(L, tile=8)], [_cfg(L), _cfg(L, flags=L.PIC_FLAG_J_FLOAT)],
                 [_cfg(L), _cfg(L, reps=2)], [_cfg(L), _cfg(L, filt=1)],
                 [_cfg(L), _cfg(L, flags=L.PIC_FLAG_ESIRKEPOV)],
-                [_cfg(L, flags=L.PIC_FLAG_MOVING_WINDOW)], [_cfg(L, flags=L.PIC_FLAG_FULL_SORT)],
+                [_cfg(L, flags=L.PIC_FLAG_MOVING_WINDOW)], [_cfg(L), _cfg(L, flags=L.PIC_FLAG_MOTION_SORT)],
                 [_cfg(L), _cfg(L, every=2)], [_cfg(L), _cfg(L, ppl=4)]):
         with pytest.raises(L.PicError) as e:
             L.pic_batch_query(bad)
         assert e.value.code == L.PIC_EINVAL
+    # the motion-class sort is offered in batched mode
+    assert L.pic_batch_query([_cfg(L, flags=L.PIC_FLAG_MOTION_SORT), _cfg(L, nx=32, flags=L.PIC_FLAG_MOTION_SORT)]) > 0
     with pytest.raises(L.PicError):
         L.pic_batch_query([])
     with pytest.raises(L.PicError) as e:

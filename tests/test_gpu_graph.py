@@ -27,7 +27,7 @@ def _same(a, b):
     assert np.array_equal(a.tile_offsets(0), b.tile_offsets(0))
 
 
-@pytest.mark.parametrize("options", [{}, {"j_filter": 2}, {"esirkepov": True}, {"full_sort": True}])
+@pytest.mark.parametrize("options", [{}, {"j_filter": 2}, {"esirkepov": True}, {"motion_sort": True}])
 def test_captured_step_replays_like_eager_steps(options):
     import torch
     from paper_2501_14795_amd import Sim, _lib

@@ -5,10 +5,8 @@ that of the same kernels one after the other: a twin stepped through the
 separate entry points (pic_push_deposit, pic_sort, pic_field_advance, all on
 one stream) must hold bit-identical fields, particles and tile offsets after
 every step -- on the default stream and on a caller stream, with the filter,
-and with a sort cadence of 2 (whose unsorted steps take the unforked path).
-The full re-sort stays unforked: with fewer particles than its histogram has
-entries, the histogram borrows the tile current halos that the field half
-folds, so a species of 144 particles checks that case."""
+with a sort cadence of 2 (whose unsorted steps take the unforked path), and
+with the motion-class sort, also for a species of only 144 particles."""
 import numpy as np
 import pytest
 
@@ -36,7 +34,8 @@ def _same(a, b):
     ({}, True),
     ({"j_filter": 2}, True),
     ({"sort_every": 2}, False),
-    ({"full_sort": True, "tiny": True}, True),
+    ({"motion_sort": True}, True),
+    ({"motion_sort": True, "tiny": True}, False),
 ])
 def test_forked_step_equals_the_sequential_calls(options, caller_stream):
     import torch
@@ -45,7 +44,7 @@ def test_forked_step_equals_the_sequential_calls(options, caller_stream):
     tiny = options.pop("tiny", False)
     nx = ny = 64
     spec = pw.SpeciesSpec(-1.0, (3, 3), (0.2, 0.2, 0.2), (0.3, -0.2, 0.1))
-    if tiny:   # 16 cells x 9 particles: fewer than the radix histogram's 257 entries
+    if tiny:   # 16 cells x 9 particles
         state = pw.species_state(nx, ny, 16, spec, 21, cell_box=(0, 4, 0, 4))
         assert state["ix"].size == 144
     else:

@@ -89,7 +89,7 @@ def _expected_layout(pre, inject, origin, nx, ny, tile):
 @pytest.mark.parametrize("nx,ny,tile,nspecies,options", [
     (64, 32, 16, 1, {}), (48, 40, 8, 2, {}), (96, 64, 32, 1, {}),
     # with the current filter, the Esirkepov deposit and the full re-sort between moves
-    (64, 48, 16, 2, {"j_filter": 1, "esirkepov": True, "full_sort": True}),
+    (64, 48, 16, 2, {"j_filter": 1, "esirkepov": True, "motion_sort": True}),
 ])
 def test_window_step_matches_oracle(nx, ny, tile, nspecies, options):
     L = _lib()
