@@ -91,6 +91,70 @@ def cpu_baseline(w, st, T, budget_s=10.0, max_steps=8):
             "seconds": t_hot}
 
 
+def cpu_baseline_openmp(w, st, T, steps=3):
+    """The oracle's OpenMP driver (Sec. 4.2.1's CPU scheme: an OpenMP loop over
+    tiles, a private current per thread; the canonical sort split over
+    threads) on the WHOLE workload, on every host core it is given
+    (OMP_NUM_THREADS); push + deposit + sort timed per step, the median of
+    `steps` steps (the field advance untimed)."""
+    import oracle
+    s = w.species[0]
+    sp = oracle.OracleSpecies(s.qm, s.q, *(st[k] for k in ("ix", "iy", "x", "y", "ux", "uy", "uz")))
+    sim = oracle.OracleOmpSim(w.nx, w.ny, w.dx, w.dy, w.dt, [sp], T)
+    times = []
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        sim.push_deposit()
+        sim.sort()
+        times.append(time.perf_counter() - t0)
+        sim.field_advance()
+    n = sp.n
+    med = float(np.median(times))
+    return {"value": n / med, "unit": "particle-pushes/s", "cores": oracle.omp_threads(), "kind": "oracle-openmp",
+            "sample": f"all {n} particles of the {w.nx}x{w.ny} workload, median of {steps} steps of "
+                      f"push+deposit+sort (FP64, OpenMP over {T}x{T} tiles, private current per thread)",
+            "step_s": times}
+
+
+def stream_probe(n=1 << 26, launches=20):
+    """The push's particle stream without its arithmetic (pic_probe_stream):
+    six float arrays of n values read and written back in place, with and
+    without the non-temporal hint, event-timed; and a plain device copy of
+    the same bytes.  Returns achieved GB/s (48 n bytes per launch)."""
+    import torch
+
+    from paper_2501_14795_amd import _lib
+    arrays = [torch.zeros(n, dtype=torch.float32, device="cuda") for _ in range(6)]
+    ptrs = [a.data_ptr() for a in arrays]
+    s = torch.cuda.current_stream().cuda_stream
+    out = {"elements": n, "bytes_per_launch": 48 * n}
+    for name, nt in (("soa_rw_nontemporal", True), ("soa_rw", False)):
+        for _ in range(3):
+            _lib.pic_probe_stream(ptrs, n, nt, s)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(launches):
+            _lib.pic_probe_stream(ptrs, n, nt, s)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / launches
+        out[name + "_gbs"] = 48 * n / (ms * 1e-3) / 1e9
+    src = torch.ones(6 * n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(launches):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    out["copy_gbs"] = 2 * 24 * n / (e0.elapsed_time(e1) / launches * 1e-3) / 1e9
+    del arrays, src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def batched_comparison(n_sims=256, steps=5, tune_sims=32):
     """The batched workload (256 independent simulations, grids 32..256
     cells, 8..64 ppc): the autotuner picks tile size x replicas x sort
@@ -316,6 +380,11 @@ def main():
     if not args.no_cpu_baseline and len(states) == 1:
         cpu = cpu_baseline(w, states[0], T)
         log(f"cpu baseline {cpu['value'] / 1e6:.2f} M push/s over {cpu['seconds']:.1f}s")
+        cpu["openmp"] = cpu_baseline_openmp(w, states[0], T)
+        log(f"cpu baseline (OpenMP, {cpu['openmp']['cores']} threads) {cpu['openmp']['value'] / 1e6:.1f} M push/s, "
+            f"steps {cpu['openmp']['step_s']}")
+    probe = stream_probe()
+    log(f"stream probe: {probe}")
 
     sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, T, [(s.qm, s.q, st) for s, st in zip(w.species, states)],
               j_replicas=args.replicas, j_float=args.j_float, j_filter=args.j_filter, esirkepov=args.esirkepov)
@@ -393,8 +462,13 @@ def main():
                    "step": "push+deposit+sort+field_advance"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_source": None if traffic is None else
+                     "rocprofv3 FETCH_SIZE/WRITE_SIZE passes of this kernel source (profiles/push_traffic.json)",
                      "kernel": "k_push_deposit", "algorithmic_bytes_per_launch": pb,
-                     "avg_launch_ms": push_ms},
+                     "avg_launch_ms": push_ms,
+                     "probe_gbs": probe["soa_rw_nontemporal_gbs"],
+                     "frac_of_probe": achieved / probe["soa_rw_nontemporal_gbs"],
+                     "probe": probe},
         "hot_path": {
             "ms_per_step": hot_ms,
             "pushes_per_s": n / (hot_ms * 1e-3),
@@ -405,7 +479,7 @@ def main():
         "energy": {"u_e": d.u_e, "u_b": d.u_b, "u_k": d.u_k[0]},
         "paper_context": PAPER_CONTEXT,
         "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample",
-                                                                     "host_cores", "cpu_model")},
+                                                                     "host_cores", "cpu_model", "openmp")},
     }
     sim.close()
     del sim

@@ -478,6 +478,19 @@ int pic_batch_check(pic_batch *b, hipStream_t stream);
 /* Free the batch's host record, its graph and its members' host records. */
 void pic_batch_destroy(pic_batch *b);
 
+/*
+ * Measurement aid, not a step of the method: the push kernel's particle
+ * stream without its arithmetic.  Six device arrays of n 32-bit values
+ * (arrays[0..5], e.g. one species' cell, x, y, ux, uy, uz) are each read and
+ * written back unchanged, in 64-value chunks through buffer descriptors,
+ * 16,384 values of every array per workgroup; nontemporal != 0 gives the
+ * loads and stores the push's non-temporal hint.  Timing it gives the
+ * bandwidth this access pattern reaches (24 n bytes read, 24 n written), the
+ * practical ceiling of the push's streaming.  Enqueues one kernel on
+ * `stream`; PIC_EINVAL for a null array or n < 0.
+ */
+int pic_probe_stream(float *const *arrays, int64_t n, int nontemporal, hipStream_t stream);
+
 /* Static string naming a return code. */
 const char *pic_strerror(int code);
 

@@ -44,8 +44,11 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pic_oracle.c")
 _SO = os.path.join(_HERE, "liboracle.so")
+_SRC_OMP = os.path.join(_HERE, "pic_oracle_omp.c")
+_SO_OMP = os.path.join(_HERE, "liboracle_omp.so")
 
 _lib = None
+_lib_omp = None
 
 _d = ctypes.c_double
 _i = ctypes.c_int
@@ -62,6 +65,36 @@ def build(force: bool = True) -> str:
              "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _SO)
     return _SO
+
+
+def build_omp(force: bool = True) -> str:
+    """Compile the OpenMP driver with the oracle into ``liboracle_omp.so``
+    (the timed CPU baseline; the checker is ``liboracle.so``)."""
+    if force or not os.path.exists(_SO_OMP):
+        tmp = _SO_OMP + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+             "-o", tmp, _SRC, _SRC_OMP, "-lm"])
+        os.replace(tmp, _SO_OMP)
+    return _SO_OMP
+
+
+def lib_omp():
+    global _lib_omp
+    if _lib_omp is None:
+        if (not os.path.exists(_SO_OMP) or os.path.getmtime(_SO_OMP) < os.path.getmtime(_SRC_OMP)
+                or os.path.getmtime(_SO_OMP) < os.path.getmtime(_SRC)):
+            build_omp()
+        L = ctypes.CDLL(_SO_OMP)
+        L.ora_omp_threads.restype = _i
+        L.ora_advance_omp.argtypes = [_i, _i, _d, _d, _d, _d, _d, _i64, _p] + [_p] * 7 + [_p] * 3
+        L.ora_advance_omp.restype = _i
+        L.ora_sort_canonical_omp.argtypes = [_i, _i, _i, _i64, _p, _p, _p, _p]
+        L.ora_sort_canonical_omp.restype = _i
+        L.ora_permute_omp.argtypes = [_i64, _p] + [_p] * 7
+        L.ora_permute_omp.restype = _i
+        _lib_omp = L
+    return _lib_omp
 
 
 def lib():
@@ -410,3 +443,68 @@ class OracleSim:
         ub = field_energy(self.nx, self.ny, self.dx, self.dy, self.B)
         uk = [kinetic_energy(self.dx, self.dy, s.qm, s.q, s.ux, s.uy, s.uz) for s in self.species]
         return ue, ub, uk
+
+
+# --------------------------------------------------------------------------
+# the OpenMP driver (timed CPU baseline, not a checker)
+# --------------------------------------------------------------------------
+
+def omp_threads() -> int:
+    """Threads the OpenMP driver uses (OMP_NUM_THREADS, else every core)."""
+    return int(lib_omp().ora_omp_threads())
+
+
+def sort_canonical_omp(nx, ny, T, ix, iy):
+    """sort_canonical (no removed particles) computed by the OpenMP driver."""
+    ix, iy = _i32(ix), _i32(iy)
+    n = ix.size
+    ntiles = (nx // T) * (ny // T)
+    off = np.zeros(ntiles + 1, dtype=np.int64)
+    src = np.zeros(max(n, 1), dtype=np.int64)
+    if lib_omp().ora_sort_canonical_omp(nx, ny, T, n, _ptr(ix), _ptr(iy), _ptr(off), _ptr(src)) != 0:
+        raise ValueError("cell index out of range")
+    return off, src[:n]
+
+
+class OracleOmpSim(OracleSim):
+    """OracleSim whose particle half runs tile-parallel with OpenMP (Sec.
+    4.2.1: an OpenMP loop over the tiles, a private current per thread) and
+    whose strict sort is computed with the work split over threads.  The
+    particles must be grouped by tiles of T x T cells (they are after every
+    sort).  Same results as OracleSim to FP64 round-off (the sort bit for
+    bit); Villasenor-Buneman deposit, no filter."""
+
+    def __init__(self, nx, ny, dx, dy, dt, species, T, E=None, B=None):
+        super().__init__(nx, ny, dx, dy, dt, species, E, B)
+        self.T = int(T)
+        self.offs = [self._offsets(s) for s in self.species]
+
+    def _offsets(self, s):
+        ntx = self.nx // self.T
+        tile = (s.iy // self.T).astype(np.int64) * ntx + s.ix // self.T
+        if tile.size and (np.diff(tile) < 0).any():
+            raise ValueError("particles are not grouped by tile")
+        return np.searchsorted(tile, np.arange((self.ny // self.T) * ntx + 1)).astype(np.int64)
+
+    def push_deposit(self):
+        self.J[...] = 0.0
+        ntiles = (self.nx // self.T) * (self.ny // self.T)
+        for s, off in zip(self.species, self.offs):
+            rc = lib_omp().ora_advance_omp(self.nx, self.ny, self.dx, self.dy, self.dt, s.qm, s.q, ntiles,
+                                           _ptr(off), _ptr(s.ix), _ptr(s.iy), _ptr(s.x), _ptr(s.y),
+                                           _ptr(s.ux), _ptr(s.uy), _ptr(s.uz),
+                                           _ptr(self.E), _ptr(self.B), _ptr(self.J))
+            if rc != 0:
+                raise FloatingPointError("a particle moved one cell or more (Courant condition)")
+
+    def sort(self, T=None):
+        offs = []
+        for k, s in enumerate(self.species):
+            off, src = sort_canonical_omp(self.nx, self.ny, self.T, s.ix, s.iy)
+            src = np.ascontiguousarray(src, dtype=np.int64)
+            if lib_omp().ora_permute_omp(s.n, _ptr(src), _ptr(s.ix), _ptr(s.iy), _ptr(s.x), _ptr(s.y),
+                                         _ptr(s.ux), _ptr(s.uy), _ptr(s.uz)) != 0:
+                raise MemoryError("ora_permute_omp")
+            self.offs[k] = off
+            offs.append(off)
+        return offs

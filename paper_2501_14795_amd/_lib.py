@@ -48,7 +48,7 @@ EXPORTS = [
     "pic_set_timing", "pic_set_timing_mask", "pic_get_timing",
     "pic_batch_query", "pic_batch_init", "pic_batch_step", "pic_batch_capture", "pic_batch_sim",
     "pic_batch_check", "pic_batch_destroy",
-    "pic_strerror", "pic_destroy",
+    "pic_probe_stream", "pic_strerror", "pic_destroy",
 ]
 
 
@@ -137,6 +137,7 @@ def load(path: str = SO_PATH):
     L.pic_get_window_origin.argtypes = [vp, P(ctypes.c_int32)]
     L.pic_solve_gauss.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_int, P(pic_gauss_out), vp]
     L.pic_solve_gauss_noalloc.argtypes = [vp, ctypes.c_double, ctypes.c_int, P(pic_gauss_out), vp]
+    L.pic_probe_stream.argtypes = [vp, ctypes.c_int64, ctypes.c_int, vp]
     L.pic_set_state.argtypes = [vp, P(pic_host_state), vp]
     L.pic_set_timing.argtypes = [vp, ctypes.c_int]
     L.pic_set_timing_mask.argtypes = [vp, ctypes.c_uint]
@@ -247,6 +248,12 @@ def pic_solve_gauss_noalloc(sim: int, tol: float, max_iter: int, stream: int):
     _chk(load().pic_solve_gauss_noalloc(ctypes.c_void_p(sim), float(tol), int(max_iter), ctypes.byref(out),
                                         ctypes.c_void_p(stream)), "pic_solve_gauss_noalloc")
     return out
+
+
+def pic_probe_stream(arrays, n: int, nontemporal: bool, stream: int):
+    """arrays: six device pointers of n float32 each, read and written back."""
+    ptrs = (ctypes.c_void_p * 6)(*arrays)
+    _chk(load().pic_probe_stream(ptrs, int(n), int(bool(nontemporal)), ctypes.c_void_p(stream)), "pic_probe_stream")
 
 
 def pic_get_counts(sim: int, n_species: int):

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 SO = os.path.join(HERE, "libpic.so")
 OBJ = os.path.join(ROOT, "_build")
 SOURCES = ["pic_api.hip", "k_push.hip", "k_sort.hip", "k_field.hip", "k_filter.hip", "k_window.hip", "k_diag.hip",
-           "k_poisson.hip", "k_tilesort.hip"]
+           "k_poisson.hip", "k_tilesort.hip", "k_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
