@@ -403,11 +403,13 @@ int pic_get_tile_offsets(pic_sim *sim, int species, int32_t *host_out, hipStream
 
 /* Per-kernel timing with HIP events on the launching stream. */
 #define PIC_KERNEL_PUSH 0         /* push + deposit kernel */
-#define PIC_KERNEL_JREDUCE 1      /* tile current fold into the J planes */
+#define PIC_KERNEL_JREDUCE 1      /* tile current fold into the J planes (pic_push_deposit; in
+                                     pic_step only with the filter, else fused into the field advance) */
 #define PIC_KERNEL_SORT_SCAN 2    /* tile recount + tile_offset scan */
 #define PIC_KERNEL_SORT_PLAN 3    /* hole/mover pairing + mover gather */
 #define PIC_KERNEL_SORT_SCATTER 4 /* mover scatter into holes */
-#define PIC_KERNEL_FIELD 5        /* the three Yee sub-steps */
+#define PIC_KERNEL_FIELD 5        /* the three Yee sub-steps (in pic_step without the filter, the
+                                     E step also folds J) */
 #define PIC_KERNEL_FILTER 6       /* binomial current filter passes */
 #define PIC_N_KERNELS 7
 

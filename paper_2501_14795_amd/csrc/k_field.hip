@@ -1,8 +1,12 @@
 // Yee field update on the periodic staggered grid (Eqs. 19-20; the three
 // sub-steps of Listing 3.1 are three launches).  One thread per cell, the
 // periodic neighbours read directly (this replaces the guard-cell copy).
-// Outside the particle hot path: a plain coalesced stencil.
+// Outside the particle hot path: a plain coalesced stencil.  In a step
+// without the current filter the E step also folds the tile current halos
+// into J (update_gc_add, the same per-node sum as the fold kernel), so J is
+// written once and not read back.
 #include "pic_internal.h"
+#include "pic_fold.h"
 
 namespace pic {
 
@@ -26,7 +30,10 @@ __device__ __forceinline__ void yee_b_block(const FieldArgs &a, int bx, int by)
     Bz[k] -= a.hdx * (Ey[kx] - Ey[k]) - a.hdy * (Ex[ky] - Ex[k]);
 }
 
-// Ampere: E += dt (curl B - J) for one 64 x 4 block of cells.
+// Ampere: E += dt (curl B - J) for one 64 x 4 block of cells.  FOLD: J is
+// first folded from the tile current halos (tile edge T, halo pad H) and
+// written to the J planes; else read from them.
+template <bool FOLD, int T, int H>
 __device__ __forceinline__ void yee_e_block(const FieldArgs &a, int bx, int by)
 {
     const int i = bx * 64 + (threadIdx.x & 63);
@@ -40,15 +47,35 @@ __device__ __forceinline__ void yee_e_block(const FieldArgs &a, int bx, int by)
     const int64_t ky = (int64_t)(j == 0 ? ny - 1 : j - 1) * nx + i;
     float *Ex = f, *Ey = f + P, *Ez = f + 2 * P;
     const float *Bx = f + 3 * P, *By = f + 4 * P, *Bz = f + 5 * P;
-    const float *Jx = f + 6 * P, *Jy = f + 7 * P, *Jz = f + 8 * P;
+    float *Jx = f + 6 * P, *Jy = f + 7 * P, *Jz = f + 8 * P;
+    float jx, jy, jz;
+    if constexpr (FOLD) {
+        float jv[3];
+        fold_node<T, H>(a.jtile, nx, ny, a.ntx, a.nty, i, j, jv);
+        jx = jv[0];
+        jy = jv[1];
+        jz = jv[2];
+        Jx[k] = jx;
+        Jy[k] = jy;
+        Jz[k] = jz;
+    } else {
+        jx = Jx[k];
+        jy = Jy[k];
+        jz = Jz[k];
+    }
     const float bz = Bz[k];
-    Ex[k] += a.dtdy * (bz - Bz[ky]) - a.dt * Jx[k];
-    Ey[k] += -a.dtdx * (bz - Bz[kx]) - a.dt * Jy[k];
-    Ez[k] += a.dtdx * (By[k] - By[kx]) - a.dtdy * (Bx[k] - Bx[ky]) - a.dt * Jz[k];
+    Ex[k] += a.dtdy * (bz - Bz[ky]) - a.dt * jx;
+    Ey[k] += -a.dtdx * (bz - Bz[kx]) - a.dt * jy;
+    Ez[k] += a.dtdx * (By[k] - By[kx]) - a.dtdy * (Bx[k] - Bx[ky]) - a.dt * jz;
 }
 
 __global__ void __launch_bounds__(256) k_yee_b(FieldArgs a) { yee_b_block(a, blockIdx.x, blockIdx.y); }
-__global__ void __launch_bounds__(256) k_yee_e(FieldArgs a) { yee_e_block(a, blockIdx.x, blockIdx.y); }
+
+template <bool FOLD, int T, int H>
+__global__ void __launch_bounds__(256) k_yee_e(FieldArgs a)
+{
+    yee_e_block<FOLD, T, H>(a, blockIdx.x, blockIdx.y);
+}
 
 // many simulations: items = (simulation, bx, by)
 __global__ void __launch_bounds__(256) k_yee_b_b(const FieldArgs *d, const int4 *it)
@@ -56,26 +83,76 @@ __global__ void __launch_bounds__(256) k_yee_b_b(const FieldArgs *d, const int4 
     const int4 w = it[blockIdx.x];
     yee_b_block(d[w.x], w.y, w.z);
 }
+
+template <bool FOLD, int T, int H>
 __global__ void __launch_bounds__(256) k_yee_e_b(const FieldArgs *d, const int4 *it)
 {
     const int4 w = it[blockIdx.x];
-    yee_e_block(d[w.x], w.y, w.z);
+    yee_e_block<FOLD, T, H>(d[w.x], w.y, w.z);
 }
 
-void launch_field_advance(const FieldArgs &f, hipStream_t s)
+namespace {
+
+// The three sub-steps, single (one 64 x 4 block per cell block) or batched
+// (items), with the E step of fold / tile T / halo pad H.
+struct FieldLaunch {
+    const FieldArgs *single;
+    const FieldArgs *descs;
+    const int4 *items;
+    int n_items;
+    hipStream_t s;
+    template <bool FOLD, int T, int H>
+    void go() const
+    {
+        if constexpr (cadence_ok(T, H)) {
+            if (single) {
+                const dim3 grid((single->nx + 63) / 64, (single->ny + 3) / 4);
+                hipLaunchKernelGGL(k_yee_b, grid, dim3(256), 0, s, *single);
+                hipLaunchKernelGGL((k_yee_e<FOLD, T, H>), grid, dim3(256), 0, s, *single);
+                hipLaunchKernelGGL(k_yee_b, grid, dim3(256), 0, s, *single);
+            } else if (n_items > 0) {
+                hipLaunchKernelGGL(k_yee_b_b, dim3(n_items), dim3(256), 0, s, descs, items);
+                hipLaunchKernelGGL((k_yee_e_b<FOLD, T, H>), dim3(n_items), dim3(256), 0, s, descs, items);
+                hipLaunchKernelGGL(k_yee_b_b, dim3(n_items), dim3(256), 0, s, descs, items);
+            }
+        }
+    }
+};
+
+template <int T>
+void field_h(const FieldLaunch &L, int halo)
 {
-    const dim3 grid((f.nx + 63) / 64, (f.ny + 3) / 4);
-    hipLaunchKernelGGL(k_yee_b, grid, dim3(256), 0, s, f);
-    hipLaunchKernelGGL(k_yee_e, grid, dim3(256), 0, s, f);
-    hipLaunchKernelGGL(k_yee_b, grid, dim3(256), 0, s, f);
+    if (halo == 2) L.go<true, T, 2>();
+    else if (halo == 4) L.go<true, T, 4>();
+    else L.go<true, T, 1>();
 }
 
-void launch_field_advance_batch(const FieldArgs *descs, const int4 *items, int n_items, hipStream_t s)
+void field_dispatch(const FieldLaunch &L, bool fold, int tile, int halo)
 {
-    if (n_items == 0) return;
-    hipLaunchKernelGGL(k_yee_b_b, dim3(n_items), dim3(256), 0, s, descs, items);
-    hipLaunchKernelGGL(k_yee_e_b, dim3(n_items), dim3(256), 0, s, descs, items);
-    hipLaunchKernelGGL(k_yee_b_b, dim3(n_items), dim3(256), 0, s, descs, items);
+    if (!fold) {
+        L.go<false, 8, 1>();
+        return;
+    }
+    switch (tile) {
+    case 8: field_h<8>(L, halo); break;
+    case 16: field_h<16>(L, halo); break;
+    default: field_h<32>(L, halo); break;
+    }
+}
+
+}  // namespace
+
+void launch_field_advance(const FieldArgs &f, int tile, int halo, hipStream_t s)
+{
+    FieldLaunch L{&f, nullptr, nullptr, 0, s};
+    field_dispatch(L, f.jtile != nullptr, tile, halo);
+}
+
+void launch_field_advance_batch(const FieldArgs *descs, const int4 *items, int n_items, bool fold, int tile,
+                                int halo, hipStream_t s)
+{
+    FieldLaunch L{nullptr, descs, items, n_items, s};
+    field_dispatch(L, fold, tile, halo);
 }
 
 }  // namespace pic

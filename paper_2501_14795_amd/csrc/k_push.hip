@@ -40,6 +40,7 @@
 #include <type_traits>
 
 #include "pic_internal.h"
+#include "pic_fold.h"
 
 namespace pic {
 
@@ -736,59 +737,24 @@ __global__ void __launch_bounds__(64 * push_waves(T), (push_waves_per_simd<T, R,
     }
 }
 
-// J[c][gy][gx] = sum over the tiles whose halo (relative nodes -H..T+H)
-// covers the node, in fixed (ty, tx) order with compensation -- the periodic
-// fold of update_gc_add.  One 64 x 4 block of nodes.  A node at
-// tile-relative (rx, ry) is covered by its own tile and, along x, by the left
-// neighbour when rx <= H or the right one when rx >= T-H (never both: 2H + 1
-// <= T), likewise along y: at most 2 x 2 halos, whose values are all loaded
-// before the sums (absent ones as zero, which leaves a compensated sum
-// unchanged).
+// The periodic fold of the tile current halos into the J planes
+// (update_gc_add), one 64 x 4 block of nodes; the per-node sum is fold_node
+// (pic_fold.h), which the fused field advance shares.
 template <int T, int H>
 __device__ __forceinline__ void j_reduce_block(const JReduceArgs &r, int bxb, int byb)
 {
-    constexpr int NJ = T + 2 * H + 1;
-    constexpr int JP = NJ * NJ;
-    const float *__restrict__ jtile = r.jtile;
-    float *__restrict__ J = r.J;
-    const int nx = r.nx, ny = r.ny, ntx = r.ntx, nty = r.nty;
+    const int nx = r.nx, ny = r.ny;
     const int gx = bxb * 64 + (threadIdx.x & 63);
     const int gy = byb * 4 + (threadIdx.x >> 6);
     if (gx >= nx || gy >= ny) return;
-    const int bx = gx / T, by = gy / T;
-    const int rx = gx - bx * T, ry = gy - by * T;
-    // the two candidate offsets per axis, ascending: (-1, 0), (0, +1) or (0, none)
-    const int kx0 = rx <= H ? -1 : 0, kx1 = rx <= H ? 0 : (rx >= T - H ? 1 : 0);
-    const bool hx = rx <= H || rx >= T - H;
-    const int ky0 = ry <= H ? -1 : 0, ky1 = ry <= H ? 0 : (ry >= T - H ? 1 : 0);
-    const bool hy = ry <= H || ry >= T - H;
-    float v[4][3];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int ky = (q >> 1) ? ky1 : ky0, kx = (q & 1) ? kx1 : kx0;
-        const bool valid = ((q >> 1) == 0 || hy) && ((q & 1) == 0 || hx);
-        const int ty = wrapi(by + ky, nty), tx = wrapi(bx + kx, ntx);
-        const int ly = ry - ky * T, lx = rx - kx * T;   // in -H..T+H
-        const float *src = jtile + (int64_t)(ty * ntx + tx) * 3 * JP + (ly + H) * NJ + (lx + H);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) v[q][c] = valid ? src[c * JP] : 0.0f;
-    }
-    float sum[3] = {0.0f, 0.0f, 0.0f}, cmp[3] = {0.0f, 0.0f, 0.0f};
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float x = v[q][c];
-            const float t = sum[c] + x;
-            const float bp = t - sum[c];
-            cmp[c] += (sum[c] - (t - bp)) + (x - bp);
-            sum[c] = t;
-        }
+    float j[3];
+    fold_node<T, H>(r.jtile, nx, ny, r.ntx, r.nty, gx, gy, j);
     const int64_t plane = (int64_t)nx * ny;
     const int64_t k = (int64_t)gy * nx + gx;
-    J[k] = sum[0] + cmp[0];
-    J[plane + k] = sum[1] + cmp[1];
-    J[2 * plane + k] = sum[2] + cmp[2];
+    float *__restrict__ J = r.J;
+    J[k] = j[0];
+    J[plane + k] = j[1];
+    J[2 * plane + k] = j[2];
 }
 
 template <int T, int H>

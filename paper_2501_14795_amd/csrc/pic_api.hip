@@ -488,13 +488,18 @@ SortArgs sort_args(const pic_sim *S)
     return a;
 }
 
-FieldArgs field_args(const pic_sim *S)
+// fold: J folded from the tile current halos by the E step of the field
+// advance (and written to the J planes), else read from the J planes
+FieldArgs field_args(const pic_sim *S, bool fold)
 {
     const pic_config &c = S->cfg;
     FieldArgs f;
     f.fld = S->buf.fields;
+    f.jtile = fold ? S->jtile : nullptr;
     f.nx = c.nx;
     f.ny = c.ny;
+    f.ntx = S->ntx;
+    f.nty = S->nty;
     f.hdx = (float)(0.5 * c.dt / c.dx);
     f.hdy = (float)(0.5 * c.dt / c.dy);
     f.dt = (float)c.dt;
@@ -725,6 +730,22 @@ int push_only(pic_sim *S, hipStream_t stream)
 }
 
 // The fold of the tile current halos into J, then the optional filter passes.
+int fold_current(pic_sim *S, hipStream_t stream);
+
+// The field half of a step after the push: the J fold (and the filter), then
+// the field advance -- the fold done by the field advance's E step when there
+// is no filter (the same J, bit for bit: both use fold_node).
+int field_half(pic_sim *S, hipStream_t stream)
+{
+    if (S->cfg.j_filter > 0) {
+        const int rc = fold_current(S, stream);
+        return rc ? rc : pic_field_advance(S, stream);
+    }
+    Timed t(S, PIC_KERNEL_FIELD, stream);
+    launch_field_advance(field_args(S, true), S->tile, S->halo, stream);
+    return hip_ok(hipGetLastError());
+}
+
 int fold_current(pic_sim *S, hipStream_t stream)
 {
     {
@@ -796,7 +817,7 @@ int pic_field_advance(pic_sim *S, hipStream_t stream)
 {
     if (!S) return PIC_EINVAL;
     Timed t(S, PIC_KERNEL_FIELD, stream);
-    launch_field_advance(field_args(S), stream);
+    launch_field_advance(field_args(S, false), S->tile, S->halo, stream);
     return hip_ok(hipGetLastError());
 }
 
@@ -922,9 +943,8 @@ int pic_step(pic_sim *S, hipStream_t stream)
     if (rc) return rc;
     // Unforked: no sort this step, or no second stream
     if (S->since_sort < S->halo || !S->side) {
-        rc = fold_current(S, stream);
-        if (rc == PIC_OK && S->since_sort >= S->halo) rc = pic_sort(S, stream);
-        if (rc == PIC_OK) rc = pic_field_advance(S, stream);
+        if (S->since_sort >= S->halo) rc = pic_sort(S, stream);
+        if (rc == PIC_OK) rc = field_half(S, stream);
         return rc;
     }
     // Once the push is done, the sort (particles, count records, leaver
@@ -936,8 +956,7 @@ int pic_step(pic_sim *S, hipStream_t stream)
     if (rc) return rc;
     rc = hip_ok(hipStreamWaitEvent(S->side, S->ev_fork, 0));
     if (rc) return rc;
-    int rf = fold_current(S, S->side);
-    if (rf == PIC_OK) rf = pic_field_advance(S, S->side);
+    int rf = field_half(S, S->side);
     const int rj = hip_ok(hipEventRecord(S->ev_join, S->side));
     rc = pic_sort(S, stream);
     // the join is enqueued whatever happened above, so the caller's stream
@@ -1181,7 +1200,8 @@ struct pic_batch {
 namespace {
 
 struct BatchLayout {
-    size_t d_push, d_jr, d_sort, d_field, d_filter, push_items, node_items, count_items, scan_items, plan_items, counter, total;
+    size_t d_push, d_jr, d_sort, d_field, d_filter, push_items, node_items, count_items, scan_items, plan_items,
+        counter, total;
     int n_push, n_node, n_count, n_scan, n_plan;
 };
 
@@ -1249,10 +1269,13 @@ void batch_enqueue_step(pic_batch *b, bool sort, hipStream_t stream)
         (void)hipStreamWaitEvent(b->side, b->ev_fork, 0);
         fs = b->side;
     }
-    launch_j_reduce_batch(b->tile, b->halo, b->d_jr, b->node_items, b->n_node, fs);
-    for (int p = 0; p < b->j_filter; ++p)
-        launch_filter_batch(b->d_filter + (p & 1) * b->sims.size(), b->node_items, b->n_node, fs);
-    launch_field_advance_batch(b->d_field, b->node_items, b->n_node, fs);
+    // the J fold, fused into the field advance when there is no filter
+    if (b->j_filter > 0) {
+        launch_j_reduce_batch(b->tile, b->halo, b->d_jr, b->node_items, b->n_node, fs);
+        for (int p = 0; p < b->j_filter; ++p)
+            launch_filter_batch(b->d_filter + (p & 1) * b->sims.size(), b->node_items, b->n_node, fs);
+    }
+    launch_field_advance_batch(b->d_field, b->node_items, b->n_node, b->j_filter == 0, b->tile, b->halo, fs);
     if (fork) (void)hipEventRecord(b->ev_join, b->side);
     SortBatch sb;
     sb.descs = b->d_sort;
@@ -1347,7 +1370,7 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
         hp[i] = push_args(S);
         hj[i] = jreduce_args(S);
         hs[i] = sort_args(S);
-        hf[i] = field_args(S);
+        hf[i] = field_args(S, S->cfg.j_filter == 0);
         hfl[i] = filter_args(S, 0);
         hfl[n + i] = filter_args(S, 1);
         int64_t np = 0;

@@ -47,8 +47,9 @@ struct FilterArgs {
 };
 
 struct FieldArgs {
-    float *fld;
-    int nx, ny;
+    float *fld;           // the nine field planes
+    const float *jtile;   // tile current halos folded into J by the E step, or null: J is input
+    int nx, ny, ntx, nty;
     float hdx, hdy;       // (dt/2)/dx, (dt/2)/dy  (B half steps)
     float dt, dtdx, dtdy; // E full step
 };
@@ -123,8 +124,13 @@ void launch_window_remove(int tile, const WindowSpecies &w, int ntx, int nty, in
 void launch_place_new(const int32_t *src, int32_t *dst, int n, int nx, int ny, int col, int *err, hipStream_t s);
 void launch_filter(const FilterArgs &a, bool fp64, hipStream_t s);
 void launch_filter_batch(const FilterArgs *descs, const int4 *items, int n_items, hipStream_t s);
-void launch_field_advance(const FieldArgs &f, hipStream_t s);
-void launch_field_advance_batch(const FieldArgs *descs, const int4 *items, int n_items, hipStream_t s);
+// the three Yee sub-steps (k_field.hip); with f.jtile set, the E step folds
+// the tile current halos (tiles of edge `tile`, halo pad `halo`) into J
+void launch_field_advance(const FieldArgs &f, int tile, int halo, hipStream_t s);
+// batched: items (simulation, 64 x 4 cell block); fold: every member's
+// FieldArgs has jtile set
+void launch_field_advance_batch(const FieldArgs *descs, const int4 *items, int n_items, bool fold, int tile,
+                                int halo, hipStream_t s);
 
 // Conjugate-gradient projection of E (Eq. 17) or B (Eq. 18), k_poisson.hip.
 constexpr int kCgPartials = 1024;   // per-block partial sums of one dot product, at most
