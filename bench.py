@@ -47,15 +47,15 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def push_bytes(n_particles, n_tiles, tile, leavers, n_species=1):
+def push_bytes(n_particles, n_tiles, tile, leavers, n_species=1, halo=1):
     """Algorithmic HBM bytes of one push + deposit launch: every particle read
-    and written once, each tile's E/B halo ((T+2)^2 cells x 6 fields) read once,
-    each tile's current halo ((T+3)^2 nodes x 3) written once, the tile_offset
-    pair and the count record (32 ints) per tile and species, and one 4-byte
-    entry per leaver."""
+    and written once, each tile's E/B halo ((T+2H)^2 cells x 6 fields, H the
+    halo pad: 1, or the sort cadence) read once, each tile's current halo
+    ((T+2H+1)^2 nodes x 3) written once, the tile_offset pair and the count
+    record (32 ints) per tile and species, and one 4-byte entry per leaver."""
     return (2 * BYTES_PARTICLE * n_particles
-            + n_tiles * (tile + 2) ** 2 * 6 * 4
-            + n_tiles * (tile + 3) ** 2 * 3 * 4
+            + n_tiles * (tile + 2 * halo) ** 2 * 6 * 4
+            + n_tiles * (tile + 2 * halo + 1) ** 2 * 3 * 4
             + n_species * n_tiles * (8 + 32 * 4)
             + 4 * leavers)
 
@@ -200,6 +200,20 @@ def batched_comparison(n_sims=256, steps=5, tune_sims=32):
             _lib.pic_step(m.handle, s)
     b.stream.synchronize()
     per_sim = (time.perf_counter() - t0) / steps
+    # the persistent push alone, event-timed in direct batched steps: its
+    # algorithmic bytes (every member's push bytes, as for one simulation)
+    # over its average duration
+    m0 = b[0]
+    m0.set_timing(["push"])
+    b.step(steps)
+    b.stream.synchronize()
+    kt = m0.timing()["push"]
+    m0.set_timing(False)
+    push_ms = kt[0] / max(kt[1], 1)
+    bytes_push = 0
+    for m in b.members:
+        d = m.diag(_lib.PIC_DIAG_COUNTS)
+        bytes_push += push_bytes(m.buf.cfg.species[0].n, m.n_tiles, tile, d.leavers[0], halo=every)
     b.capture()
     graph = time_batch(b, steps)
     rc = b.check()
@@ -217,6 +231,10 @@ def batched_comparison(n_sims=256, steps=5, tune_sims=32):
         "graph_ms_per_step": graph * 1e3, "direct_ms_per_step": direct * 1e3,
         "per_sim_launch_ms_per_step": per_sim * 1e3,
         "speedup_vs_per_sim_launch": per_sim / graph,
+        "roofline": {"bound": "hbm", "kernel": "k_push_batch (persistent)", "avg_launch_ms": push_ms,
+                     "algorithmic_bytes_per_launch": bytes_push,
+                     "achieved": bytes_push / (push_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": bytes_push / (push_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
 
 

@@ -471,7 +471,10 @@ int pic_batch_capture(pic_batch *b, hipStream_t stream);
 
 /* Member i as a pic_sim for pic_diag / pic_get_tile_offsets / pic_check and
  * the single-member calls; owned by the batch (do not pic_destroy it).
- * NULL if i is out of range. */
+ * NULL if i is out of range.  Event timing switched on for member 0
+ * (pic_set_timing_mask with PIC_KERNEL_PUSH) also times the batch's
+ * persistent push launch in direct (not graph-replayed) batched steps; do
+ * not capture with it on. */
 pic_sim *pic_batch_sim(pic_batch *b, int i);
 
 /* pic_check of every member; the first error found. */

@@ -1259,8 +1259,12 @@ BatchLayout batch_layout(int n, const pic_config *cfgs)
 void batch_enqueue_step(pic_batch *b, bool sort, hipStream_t stream)
 {
     launch_set_int(b->counter, 0, stream);
-    launch_push_batch(b->tile, b->replicas, b->jm, b->dm, b->halo, b->ppl, b->d_push, b->push_items, b->n_push,
-                      b->counter, b->push_grid, stream);
+    {
+        // member 0's event timing, if on, times the batch's push launch
+        Timed t(b->sims[0], PIC_KERNEL_PUSH, stream);
+        launch_push_batch(b->tile, b->replicas, b->jm, b->dm, b->halo, b->ppl, b->d_push, b->push_items,
+                          b->n_push, b->counter, b->push_grid, stream);
+    }
     // with a sort, the field half goes to the second stream (disjoint data)
     const bool fork = sort && b->side;
     hipStream_t fs = stream;
