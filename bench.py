@@ -2,15 +2,18 @@
 
 Workload: the warm uniform plasma, 2048 x 2048 cells, dx = dy = 0.1,
 dt = 0.07, periodic, 16 electrons per cell (67,108,864 particles), u_th = 0.05
-with drift u_x = 0.2, tile 16 x 16, strict sort every step, FP32 particles
-with an int32 packed cell index + FP32 in-cell offsets.  Synthetic, seeded.
+with drift u_x = 0.2, tiles of 32 x 32 cells, strict sort every step, FP32
+particles with an int32 packed cell index + FP32 in-cell offsets.  Synthetic,
+seeded, resident in HBM before the timed region.
 
-A timed step is one full PIC step through the C ABI: push + deposit
-(pic_push_deposit), strict re-sort (pic_sort) and the Yee field advance
-(pic_field_advance).  `value` counts particle pushes over the whole step.
+A timed step is one full PIC step through the C ABI (pic_step): push +
+deposit, then the strict in-place re-sort and the Yee field advance (with the
+fold of the tile currents into J) side by side on two streams, joined before
+the call returns.  `value` counts particle pushes over the whole step.
 
-Prints ONE JSON line.  Per-kernel durations come from HIP events that libpic
-records on the launching stream during the timed region.
+Prints ONE JSON line.  The push kernel's duration comes from HIP events that
+libpic records around it on its launching stream during the timed region;
+the other kernels' split from a few extra steps timed the same way.
 """
 from __future__ import annotations
 
@@ -523,13 +526,14 @@ def main():
 
 
 def _kernel_sha():
-    """Hash of what the push kernel is compiled from: k_push.hip and the
-    definitions it shares, pic_push.h (pic_internal.h adds only launcher
-    declarations and other kernels' structures to them)."""
+    """Hash of what the push kernel's translation unit is compiled from:
+    k_push.hip, the definitions it shares (pic_push.h) and the fold it
+    includes (pic_fold.h); pic_internal.h adds only launcher declarations and
+    other kernels' structures to them."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2501_14795_amd", "csrc")
-    for name in ("k_push.hip", "pic_push.h"):
+    for name in ("k_push.hip", "pic_push.h", "pic_fold.h"):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
