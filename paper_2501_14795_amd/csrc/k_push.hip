@@ -323,12 +323,8 @@ __device__ __forceinline__ void flush_leavers(const SpeciesDev &sp, uint32_t (*l
     if (lane < n) {
         const int64_t q = pos + lane;
         gp(sp.leav)[q] = lb[0][lane];
-        gp(sp.lp.cell)[q] = (int32_t)lb[1][lane];
-        gp(sp.lp.x)[q] = __uint_as_float(lb[2][lane]);
-        gp(sp.lp.y)[q] = __uint_as_float(lb[3][lane]);
-        gp(sp.lp.ux)[q] = __uint_as_float(lb[4][lane]);
-        gp(sp.lp.uy)[q] = __uint_as_float(lb[5][lane]);
-        gp(sp.lp.uz)[q] = __uint_as_float(lb[6][lane]);
+        put_leaver(sp.lrec, q, (int)lb[1][lane], __uint_as_float(lb[2][lane]), __uint_as_float(lb[3][lane]),
+                   __uint_as_float(lb[4][lane]), __uint_as_float(lb[5][lane]), __uint_as_float(lb[6][lane]));
     }
     __builtin_amdgcn_wave_barrier();
 }
@@ -628,12 +624,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                     if (leaver) {
                         const int64_t q = (int64_t)lo + nleav + lane_rank(mk);
                         gp(sp.leav)[q] = ((uint32_t)(i - begin) << 4) | (uint32_t)m.dir;
-                        gp(sp.lp.cell)[q] = m.ncell;
-                        gp(sp.lp.x)[q] = m.xn;
-                        gp(sp.lp.y)[q] = m.yn;
-                        gp(sp.lp.ux)[q] = m.ux;
-                        gp(sp.lp.uy)[q] = m.uy;
-                        gp(sp.lp.uz)[q] = m.uz;
+                        put_leaver(sp.lrec, q, m.ncell, m.xn, m.yn, m.ux, m.uy, m.uz);
                         atomicAdd(&s_dir[s][m.dir], 1);
                     }
                     nleav += __popcll(mk);

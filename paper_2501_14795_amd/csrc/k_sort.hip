@@ -162,6 +162,20 @@ __device__ __forceinline__ int wave_exclusive(int v, int &total)
     return x - v;
 }
 
+// one leaver record (two vector loads) into slot j of dst
+__device__ __forceinline__ void copy_leaver(const LeaverRec *src, int64_t i, const Parts &dst, int64_t j)
+{
+    const PIC_GLOBAL vf4 *s = (const PIC_GLOBAL vf4 *)(src + i);
+    const vf4 a = s[0];
+    const vf2 b = *(const PIC_GLOBAL vf2 *)(s + 1);
+    dst.cell[j] = __float_as_int(a.x);
+    dst.x[j] = a.y;
+    dst.y[j] = a.z;
+    dst.ux[j] = a.w;
+    dst.uy[j] = b.x;
+    dst.uz[j] = b.y;
+}
+
 __device__ __forceinline__ void copy_particle(const Parts &src, int64_t i, const Parts &dst, int64_t j)
 {
     dst.cell[j] = src.cell[i];
@@ -331,9 +345,12 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
                 const unsigned long long m = __ballot(p);
                 const int r = nm + lane_rank_s(m);
                 if (p && r < B - A) {
-                    const Parts &src = from_leavers ? sp.lp : sp.p;
-                    if (r < nhead || r >= nh - ntail) copy_particle(src, at, sp.stg, (int64_t)A + r);
-                    else copy_particle(src, at, sp.p, sp.hole[(int64_t)A + r]);   // one of t's leaver slots
+                    // staged (head and tail of the holes), or straight into one of t's leaver slots
+                    const bool staged = r < nhead || r >= nh - ntail;
+                    const Parts &dst = staged ? sp.stg : sp.p;
+                    const int64_t to = staged ? (int64_t)A + r : (int64_t)sp.hole[(int64_t)A + r];
+                    if (from_leavers) copy_leaver(sp.lrec, at, dst, to);
+                    else copy_particle(sp.p, at, dst, to);
                 }
                 nm += __popcll(m);
             }

@@ -24,7 +24,7 @@ struct Layout {
     size_t wrem = 0, inj_off[kMaxSpecies] = {};
     size_t off[kMaxSpecies][2] = {}, cnt[kMaxSpecies] = {}, leav[kMaxSpecies] = {};
     size_t hole[kMaxSpecies] = {}, stg[kMaxSpecies][6] = {}, mcount[kMaxSpecies] = {}, bsum[kMaxSpecies] = {};
-    size_t lpart[kMaxSpecies][6] = {};
+    size_t lrec[kMaxSpecies] = {};
     size_t total = 0;
 };
 
@@ -120,7 +120,9 @@ Layout make_layout(const pic_config *c)
         L.off[s][1] = take((n_tiles + 1) * sizeof(int32_t));
         L.cnt[s] = take((size_t)n_tiles * kCntStride * sizeof(int32_t));
         L.leav[s] = take(n * sizeof(uint32_t));
-        for (int k = 0; k < 6; ++k) L.lpart[s][k] = take(n * 4);
+        // leaver records; the full re-sort also borrows the region as six
+        // arrays of n values (lp_view)
+        L.lrec[s] = take(n * sizeof(LeaverRec) + 6 * kAlign);
         L.hole[s] = take(n * sizeof(int32_t));
         for (int k = 0; k < 6; ++k) L.stg[s][k] = take(n * 4);
         L.mcount[s] = take((size_t)3 * n_tiles * sizeof(int32_t));   // movers, staged head and tail
@@ -163,7 +165,8 @@ struct pic_sim {
         uint32_t *leav;
         int32_t *hole;
         Parts stg;
-        Parts lp;
+        LeaverRec *lrec;   // the push's leaver records
+        Parts lp;          // the same memory as six arrays of n values (full re-sort scratch)
         int32_t *mcount;
         int32_t *bsum;
         int32_t *inj_off;   // moving window: tile offsets of the new particles
@@ -410,7 +413,7 @@ PushArgs push_args(const pic_sim *S)
         d.off = S->sp[s].off;
         d.cnt = S->sp[s].cnt;
         d.leav = S->sp[s].leav;
-        d.lp = S->sp[s].lp;
+        d.lrec = S->sp[s].lrec;
         d.n = (int32_t)c.species[s].n;
         d.h = (float)(0.5 * c.species[s].qm * c.dt);
         d.fq = (float)(scale * c.species[s].q / qmax);
@@ -471,7 +474,7 @@ SortArgs sort_args(const pic_sim *S)
         d.p.ux = p.ux;
         d.p.uy = p.uy;
         d.p.uz = p.uz;
-        d.lp = P.lp;
+        d.lrec = P.lrec;
         d.stg = P.stg;
         d.off = P.off;
         d.offn = P.offn;
@@ -676,7 +679,13 @@ int init_sim(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
             return q;
         };
         P.stg = parts_at(L.stg[s]);
-        P.lp = parts_at(L.lpart[s]);
+        P.lrec = (LeaverRec *)(w + L.lrec[s]);
+        {
+            size_t o[6];
+            const size_t n = (size_t)(cfg->species[s].cap ? cfg->species[s].cap : cfg->species[s].n);
+            for (int k = 0; k < 6; ++k) o[k] = L.lrec[s] + align_up((size_t)k * n * 4);
+            P.lp = parts_at(o);
+        }
         P.mcount = (int32_t *)(w + L.mcount[s]);
         P.bsum = (int32_t *)(w + L.bsum[s]);
         P.inj_off = window ? (int32_t *)(w + L.inj_off[s]) : nullptr;

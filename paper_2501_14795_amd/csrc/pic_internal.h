@@ -12,7 +12,7 @@ namespace pic {
 
 struct SortSpecies {
     Parts p;              // the particle arrays
-    Parts lp;             // leaver particle data written by the push kernel
+    const LeaverRec *lrec;   // leaver particle data written by the push kernel
     Parts stg;            // mover staging, [n]: tile t's movers at offn[t] + k
     int32_t *off;         // tile_offset: read by the plan, replaced by the new one in the scatter
     int32_t *offn;        // new tile_offset (scratch)

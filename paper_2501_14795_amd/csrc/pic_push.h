@@ -127,13 +127,36 @@ struct Parts {
     float *x, *y, *ux, *uy, *uz;
 };
 
+// One leaver's new particle data, written by the push and read by the sort:
+// one aligned 32-byte record, so each copy is one memory sector on both sides
+// (six separate arrays would cost six scattered sectors per leaver).
+struct __attribute__((aligned(32))) LeaverRec {
+    int32_t cell;
+    float x, y, ux, uy, uz;
+    int32_t pad[2];
+};
+
+// plain clang vectors (HIP's vector classes have no address-space-qualified
+// assignment)
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef float vf2 __attribute__((ext_vector_type(2)));
+
+// Write one leaver record as two vector stores (16 + 8 bytes).
+__device__ __forceinline__ void put_leaver(LeaverRec *r, int64_t q, int cell, float x, float y, float ux, float uy,
+                                           float uz)
+{
+    PIC_GLOBAL vf4 *d = (PIC_GLOBAL vf4 *)(r + q);
+    d[0] = vf4{__int_as_float(cell), x, y, ux};
+    *(PIC_GLOBAL vf2 *)(d + 1) = vf2{uy, uz};
+}
+
 struct SpeciesDev {
     int32_t *cell;
     float *x, *y, *ux, *uy, *uz;
     const int32_t *off;   // tile_offset at the start of the step (n_tiles + 1)
     int32_t *cnt;         // [n_tiles][kCntStride]
     uint32_t *leav;       // [n]: leaver sub-lists, (slot - off[t]) << 4 | direction
-    Parts lp;             // [n]: the leavers' new particle data, same positions as leav
+    LeaverRec *lrec;      // [n]: the leavers' new particle data, same positions as leav
     int32_t n;
     float h;              // (q/m) dt / 2
     float fq;             // charge in accumulator units: q / max|q| (x kFixedScale in fixed mode)

@@ -81,9 +81,10 @@ def test_query_sizes_and_validation():
     assert s.n_tiles == 16 and s.field_bytes == 9 * 64 * 64 * 4 and s.work_bytes > 0
     big = L.pic_query(_cfg(L, nx=2048, ny=2048, n=2048 * 2048 * 16))
     assert big.n_tiles == 128 * 128
-    # workspace grows linearly with particles (leaver entries + copies, holes, staging: 56 B/particle)
+    # workspace grows linearly with particles (leaver entries 4 B + 32-B leaver records, holes 4 B,
+    # staging 24 B: 64 B/particle)
     s2 = L.pic_query(_cfg(L, n=2000))
-    assert 56 * 1000 <= s2.work_bytes - s.work_bytes <= 56 * 1000 + 16 * 256
+    assert 64 * 1000 <= s2.work_bytes - s.work_bytes <= 64 * 1000 + 16 * 256
     cases = [
         (dict(dt=0.0708), L.PIC_ECFL),          # Eq. (1): limit 0.070711 at dx = dy = 0.1
         (dict(dt=0.08), L.PIC_ECFL),
