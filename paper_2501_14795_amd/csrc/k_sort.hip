@@ -27,6 +27,9 @@
 
 namespace pic {
 
+// Iterations of 64 candidates whose loads the sort plan keeps in flight together.
+constexpr int kPlanBatch = 4;
+
 __device__ __forceinline__ int wrap_s(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 __device__ __forceinline__ int lane_rank_s(unsigned long long m)
@@ -162,18 +165,34 @@ __device__ __forceinline__ int wave_exclusive(int v, int &total)
     return x - v;
 }
 
-// one leaver record (two vector loads) into slot j of dst
-__device__ __forceinline__ void copy_leaver(const LeaverRec *src, int64_t i, const Parts &dst, int64_t j)
+// One particle's six values in registers.
+struct Chunk6 {
+    int cell;
+    float x, y, ux, uy, uz;
+};
+
+// one leaver record (two vector loads)
+__device__ __forceinline__ Chunk6 load_leaver(const LeaverRec *src, int64_t i)
 {
     const PIC_GLOBAL vf4 *s = (const PIC_GLOBAL vf4 *)(src + i);
     const vf4 a = s[0];
     const vf2 b = *(const PIC_GLOBAL vf2 *)(s + 1);
-    dst.cell[j] = __float_as_int(a.x);
-    dst.x[j] = a.y;
-    dst.y[j] = a.z;
-    dst.ux[j] = a.w;
-    dst.uy[j] = b.x;
-    dst.uz[j] = b.y;
+    return Chunk6{__float_as_int(a.x), a.y, a.z, a.w, b.x, b.y};
+}
+
+__device__ __forceinline__ Chunk6 load_parts(const Parts &src, int64_t i)
+{
+    return Chunk6{src.cell[i], src.x[i], src.y[i], src.ux[i], src.uy[i], src.uz[i]};
+}
+
+__device__ __forceinline__ void store_parts(const Parts &dst, int64_t j, const Chunk6 &c)
+{
+    dst.cell[j] = c.cell;
+    dst.x[j] = c.x;
+    dst.y[j] = c.y;
+    dst.ux[j] = c.ux;
+    dst.uy[j] = c.uy;
+    dst.uz[j] = c.uz;
 }
 
 __device__ __forceinline__ void copy_particle(const Parts &src, int64_t i, const Parts &dst, int64_t j)
@@ -240,27 +259,39 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
         int total;
         int ex = wave_exclusive(len, total);
         if (lane > W + 1) ex = INT_MAX;
-        for (int k0 = 0; k0 < total; k0 += 64) {
-            const int k = k0 + lane;
-            const int L = find_list(k, ex);
-            const int kL = __shfl(kind, L, 64), bL = __shfl(base, L, 64), eL = __shfl(ex, L, 64);
-            bool p = false;
-            int slot = 0;
-            if (k < total) {
-                if (kL == 0) {
-                    slot = bL + (k - eL);
-                    p = tile_of(sp.p.cell[slot]) != t;
-                } else {
-                    slot = oA + (int)(sp.leav[(int64_t)bL + (k - eL)] >> 4);
+        // kPlanBatch iterations of 64 candidates: all their loads first, then
+        // the ballots in candidate order
+        for (int k0 = 0; k0 < total; k0 += 64 * kPlanBatch) {
+            int at[kPlanBatch], lv[kPlanBatch];
+            uint32_t v[kPlanBatch];
+#pragma unroll
+            for (int u = 0; u < kPlanBatch; ++u) {
+                const int k = k0 + 64 * u + lane;
+                const int L = find_list(k, ex);
+                const int kL = __shfl(kind, L, 64), bL = __shfl(base, L, 64), eL = __shfl(ex, L, 64);
+                lv[u] = k < total ? L : -1;
+                at[u] = bL + (k - eL);   // a slot (kind 0) or a position in t's leaver list (kind 1)
+                v[u] = 0;
+                if (k < total) v[u] = kL == 0 ? (uint32_t)sp.p.cell[at[u]] : sp.leav[at[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < kPlanBatch; ++u) {
+                const int L = lv[u];
+                bool p = false;
+                int slot = at[u];
+                if (L == 0 || L == W + 1) {
+                    p = tile_of((int)v[u]) != t;
+                } else if (L > 0) {
+                    slot = oA + (int)(v[u] >> 4);
                     p = slot >= lA && slot < lB;
                 }
+                const unsigned long long m = __ballot(p);
+                const int r = nh + lane_rank_s(m);
+                if (p && r < B - A) sp.hole[(int64_t)A + r] = slot;
+                nh += __popcll(m);
+                nhead += __popcll(__ballot(p && L == 0));
+                ntail += __popcll(__ballot(p && L == W + 1));
             }
-            const unsigned long long m = __ballot(p);
-            const int r = nh + lane_rank_s(m);
-            if (p && r < B - A) sp.hole[(int64_t)A + r] = slot;
-            nh += __popcll(m);
-            nhead += __popcll(__ballot(p && L == 0));
-            ntail += __popcll(__ballot(p && L == W + 1));
         }
     }
     // the holes' slots, written by this wavefront, are read back below
@@ -285,11 +316,14 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
             if (o < lane && v == so) first = 0;
         }
         // The lists of one source tile: kind 0 -- t's own slot ranges outside
-        // [A, B) (lists 0 and 1), kind 1 -- the source's W leaver sub-lists.
-        auto source_list = [&](int src, int w, int &kind, int &base, int &len) {
+        // [A, B) (lists 0 and 1), kind 1 -- the source's W leaver sub-lists
+        // (with the source's first slot s0 and particle count ns).
+        auto source_list = [&](int src, int w, int &kind, int &base, int &len, int &s0, int &ns) {
             kind = 0;
             base = 0;
             len = 0;
+            s0 = 0;
+            ns = 0;
             if (src < 0) return;   // no source of that rank
             if (src == t) {
                 if (w == 0) {
@@ -300,7 +334,9 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
                     len = max(0, oB - base);
                 }
             } else if (w < W) {
-                const int s0 = sp.off[src], s1 = sp.off[src + 1];
+                s0 = sp.off[src];
+                const int s1 = sp.off[src + 1];
+                ns = s1 - s0;
                 int wlo, whi;
                 wave_range(s0, s1, w, W, wlo, whi);
                 kind = 1;
@@ -309,50 +345,82 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
             }
         };
         // Stream the lists held by the lanes (one each; `valid` false: none) as
-        // one index space, 64 candidates per iteration, appending t's movers.
-        auto stream_lists = [&](int kind, int base, int len, int src, bool valid) {
+        // one index space, appending t's movers: kPlanBatch iterations of 64
+        // candidates at a time -- their loads, then the ballots in candidate
+        // order, then the movers' hole slots and data, then the stores, so
+        // each stage's memory accesses are in flight together.
+        auto stream_lists = [&](int kind, int base, int len, int src, int s0, int ns, bool valid) {
             int total;
             int ex = wave_exclusive(len, total);
             if (!valid) ex = INT_MAX;
-            for (int k0 = 0; k0 < total; k0 += 64) {
-                const int k = k0 + lane;
-                const int Lk = find_list(k, ex);
-                const int kL = __shfl(kind, Lk, 64), bL = __shfl(base, Lk, 64), eL = __shfl(ex, Lk, 64);
-                const int sL = __shfl(src, Lk, 64);
-                bool p = false;
-                bool from_leavers = false;
-                int64_t at = 0;
-                if (k < total) {
-                    if (kL == 0) {
-                        at = bL + (k - eL);
-                        p = tile_of(sp.p.cell[at]) == t;
-                    } else {
-                        at = (int64_t)bL + (k - eL);
-                        const uint32_t e = sp.leav[at];
-                        const int d = (int)(e & 15u), loc = (int)(e >> 4);
-                        const int s0 = sp.off[sL], ns = sp.off[sL + 1] - s0;
-                        if (loc >= ns || d > kDirRemoved) {
-                            bad = true;
-                        } else if (d != kDirRemoved) {   // a removed particle is nobody's mover
-                            const int sx = sL % ntx, sy = sL / ntx;
-                            const int dest = wrap_s(sy + d / 3 - 1, nty) * ntx + wrap_s(sx + d % 3 - 1, ntx);
-                            const int slot = s0 + loc;
-                            p = dest == t && !(slot >= A && slot < B);
-                            from_leavers = true;
+            for (int k0 = 0; k0 < total; k0 += 64 * kPlanBatch) {
+                int64_t at[kPlanBatch];
+                uint32_t v[kPlanBatch];
+                int kv[kPlanBatch], sv[kPlanBatch], s0v[kPlanBatch], nsv[kPlanBatch];
+                bool in[kPlanBatch];
+#pragma unroll
+                for (int u = 0; u < kPlanBatch; ++u) {
+                    const int k = k0 + 64 * u + lane;
+                    const int Lk = find_list(k, ex);
+                    kv[u] = __shfl(kind, Lk, 64);
+                    const int bL = __shfl(base, Lk, 64), eL = __shfl(ex, Lk, 64);
+                    sv[u] = __shfl(src, Lk, 64);
+                    s0v[u] = __shfl(s0, Lk, 64);
+                    nsv[u] = __shfl(ns, Lk, 64);
+                    at[u] = (int64_t)bL + (k - eL);
+                    in[u] = k < total;
+                    v[u] = 0;
+                    if (in[u]) v[u] = kv[u] == 0 ? (uint32_t)sp.p.cell[at[u]] : sp.leav[at[u]];
+                }
+                bool mv[kPlanBatch], fl[kPlanBatch];
+                int rr[kPlanBatch];
+#pragma unroll
+                for (int u = 0; u < kPlanBatch; ++u) {
+                    bool p = false, from_leavers = false;
+                    if (in[u]) {
+                        if (kv[u] == 0) {
+                            p = tile_of((int)v[u]) == t;
+                        } else {
+                            const int d = (int)(v[u] & 15u), loc = (int)(v[u] >> 4);
+                            if (loc >= nsv[u] || d > kDirRemoved) {
+                                bad = true;
+                            } else if (d != kDirRemoved) {   // a removed particle is nobody's mover
+                                const int sx = sv[u] % ntx, sy = sv[u] / ntx;
+                                const int dest = wrap_s(sy + d / 3 - 1, nty) * ntx + wrap_s(sx + d % 3 - 1, ntx);
+                                const int slot = s0v[u] + loc;
+                                p = dest == t && !(slot >= A && slot < B);
+                                from_leavers = true;
+                            }
                         }
                     }
+                    const unsigned long long m = __ballot(p);
+                    rr[u] = nm + lane_rank_s(m);
+                    mv[u] = p && rr[u] < B - A;
+                    fl[u] = from_leavers;
+                    nm += __popcll(m);
                 }
-                const unsigned long long m = __ballot(p);
-                const int r = nm + lane_rank_s(m);
-                if (p && r < B - A) {
-                    // staged (head and tail of the holes), or straight into one of t's leaver slots
-                    const bool staged = r < nhead || r >= nh - ntail;
-                    const Parts &dst = staged ? sp.stg : sp.p;
-                    const int64_t to = staged ? (int64_t)A + r : (int64_t)sp.hole[(int64_t)A + r];
-                    if (from_leavers) copy_leaver(sp.lrec, at, dst, to);
-                    else copy_particle(sp.p, at, dst, to);
+                // staged (the head and tail of the holes), or straight into
+                // one of t's leaver slots
+                int64_t to[kPlanBatch];
+                Chunk6 d[kPlanBatch];
+#pragma unroll
+                for (int u = 0; u < kPlanBatch; ++u) {
+                    to[u] = 0;
+                    if (mv[u]) {
+                        const int r = rr[u];
+                        const bool staged = r < nhead || r >= nh - ntail;
+                        to[u] = staged ? (int64_t)A + r : (int64_t)sp.hole[(int64_t)A + r];
+                        d[u] = fl[u] ? load_leaver(sp.lrec, at[u]) : load_parts(sp.p, at[u]);
+                    }
                 }
-                nm += __popcll(m);
+#pragma unroll
+                for (int u = 0; u < kPlanBatch; ++u) {
+                    if (mv[u]) {
+                        const int r = rr[u];
+                        const bool staged = r < nhead || r >= nh - ntail;
+                        store_parts(staged ? sp.stg : sp.p, to[u], d[u]);
+                    }
+                }
             }
         };
         // the source tile of rank q (ascending tile id = ascending old slot),
@@ -373,9 +441,9 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
         for (int q0 = 0; q0 < nuniq; q0 += G) {
             const int pr = q0 + lane / W, w = lane % W;
             const int src = source_of_rank(pr);
-            int kind, base, len;
-            source_list(src, w, kind, base, len);
-            stream_lists(kind, base, len, src, pr < nuniq);
+            int kind, base, len, s0, ns;
+            source_list(src, w, kind, base, len, s0, ns);
+            stream_lists(kind, base, len, src, s0, ns, pr < nuniq);
         }
         if (sp.inj_off) {
             // the window's new particles for t, appended after every old
@@ -389,7 +457,7 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
                 base = max(i0, B);
                 len = max(0, i1 - base);
             }
-            stream_lists(0, base, len, t, lane < 2);
+            stream_lists(0, base, len, t, 0, 0, lane < 2);
         }
     }
 
