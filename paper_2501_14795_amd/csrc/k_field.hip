@@ -7,10 +7,13 @@
 // written once and not read back.
 #include "pic_internal.h"
 #include "pic_fold.h"
+#include "pic_yee.h"
 
 namespace pic {
 
-// Faraday: B -= h curl E for one 64 x 4 block of cells (hdx = h/dx, hdy = h/dy).
+// Faraday: B -= h curl E for one 64 x 4 block of cells (hdx = h/dx, hdy = h/dy),
+// from the B planes in place, or from the push's half-step planes (a.bh) into
+// the B planes.
 __device__ __forceinline__ void yee_b_block(const FieldArgs &a, int bx, int by)
 {
     const int i = bx * 64 + (threadIdx.x & 63);
@@ -23,11 +26,13 @@ __device__ __forceinline__ void yee_b_block(const FieldArgs &a, int bx, int by)
     const int64_t kx = (int64_t)j * nx + (i + 1 == nx ? 0 : i + 1);
     const int64_t ky = (int64_t)(j + 1 == ny ? 0 : j + 1) * nx + i;
     const float *Ex = f, *Ey = f + P, *Ez = f + 2 * P;
+    const float *Bin = a.bh ? a.bh : f + 3 * P;
     float *Bx = f + 3 * P, *By = f + 4 * P, *Bz = f + 5 * P;
-    const float ez = Ez[k];
-    Bx[k] -= a.hdy * (Ez[ky] - ez);
-    By[k] += a.hdx * (Ez[kx] - ez);
-    Bz[k] -= a.hdx * (Ey[kx] - Ey[k]) - a.hdy * (Ex[ky] - Ex[k]);
+    const BCell b = faraday_half(Bin[k], Bin[P + k], Bin[2 * P + k], Ex[k], Ex[ky], Ey[k], Ey[kx], Ez[k], Ez[kx],
+                                 Ez[ky], a.hdx, a.hdy);
+    Bx[k] = b.x;
+    By[k] = b.y;
+    Bz[k] = b.z;
 }
 
 // Ampere: E += dt (curl B - J) for one 64 x 4 block of cells.  FOLD: J is
@@ -46,7 +51,8 @@ __device__ __forceinline__ void yee_e_block(const FieldArgs &a, int bx, int by)
     const int64_t kx = (int64_t)j * nx + (i == 0 ? nx - 1 : i - 1);
     const int64_t ky = (int64_t)(j == 0 ? ny - 1 : j - 1) * nx + i;
     float *Ex = f, *Ey = f + P, *Ez = f + 2 * P;
-    const float *Bx = f + 3 * P, *By = f + 4 * P, *Bz = f + 5 * P;
+    const float *Bh = a.bh ? a.bh : f + 3 * P;   // B at the half step
+    const float *Bx = Bh, *By = Bh + P, *Bz = Bh + 2 * P;
     float *Jx = f + 6 * P, *Jy = f + 7 * P, *Jz = f + 8 * P;
     float jx, jy, jz;
     if constexpr (FOLD) {
@@ -93,13 +99,16 @@ __global__ void __launch_bounds__(256) k_yee_e_b(const FieldArgs *d, const int4 
 
 namespace {
 
-// The three sub-steps, single (one 64 x 4 block per cell block) or batched
-// (items), with the E step of fold / tile T / halo pad H.
+// The sub-steps, single (one 64 x 4 block per cell block) or batched
+// (items), with the E step of fold / tile T / halo pad H: the first B half
+// step, the E step and the second B half step, or, when the push has formed
+// the first half step (bh), the E step and the second half step only.
 struct FieldLaunch {
     const FieldArgs *single;
     const FieldArgs *descs;
     const int4 *items;
     int n_items;
+    bool bh;
     hipStream_t s;
     template <bool FOLD, int T, int H>
     void go() const
@@ -107,11 +116,11 @@ struct FieldLaunch {
         if constexpr (cadence_ok(T, H)) {
             if (single) {
                 const dim3 grid((single->nx + 63) / 64, (single->ny + 3) / 4);
-                hipLaunchKernelGGL(k_yee_b, grid, dim3(256), 0, s, *single);
+                if (!bh) hipLaunchKernelGGL(k_yee_b, grid, dim3(256), 0, s, *single);
                 hipLaunchKernelGGL((k_yee_e<FOLD, T, H>), grid, dim3(256), 0, s, *single);
                 hipLaunchKernelGGL(k_yee_b, grid, dim3(256), 0, s, *single);
             } else if (n_items > 0) {
-                hipLaunchKernelGGL(k_yee_b_b, dim3(n_items), dim3(256), 0, s, descs, items);
+                if (!bh) hipLaunchKernelGGL(k_yee_b_b, dim3(n_items), dim3(256), 0, s, descs, items);
                 hipLaunchKernelGGL((k_yee_e_b<FOLD, T, H>), dim3(n_items), dim3(256), 0, s, descs, items);
                 hipLaunchKernelGGL(k_yee_b_b, dim3(n_items), dim3(256), 0, s, descs, items);
             }
@@ -144,14 +153,14 @@ void field_dispatch(const FieldLaunch &L, bool fold, int tile, int halo)
 
 void launch_field_advance(const FieldArgs &f, int tile, int halo, hipStream_t s)
 {
-    FieldLaunch L{&f, nullptr, nullptr, 0, s};
+    FieldLaunch L{&f, nullptr, nullptr, 0, f.bh != nullptr, s};
     field_dispatch(L, f.jtile != nullptr, tile, halo);
 }
 
-void launch_field_advance_batch(const FieldArgs *descs, const int4 *items, int n_items, bool fold, int tile,
-                                int halo, hipStream_t s)
+void launch_field_advance_batch(const FieldArgs *descs, const int4 *items, int n_items, bool fold, bool bh,
+                                int tile, int halo, hipStream_t s)
 {
-    FieldLaunch L{nullptr, descs, items, n_items, s};
+    FieldLaunch L{nullptr, descs, items, n_items, bh, s};
     field_dispatch(L, fold, tile, halo);
 }
 

@@ -41,6 +41,7 @@
 
 #include "pic_internal.h"
 #include "pic_fold.h"
+#include "pic_yee.h"
 
 namespace pic {
 
@@ -691,6 +692,49 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
         const int comp = e / JP;
         out[e] = JAcc<JM>::value(&s_j[0][e], R, 3 * JP, a.ju[comp], a.err);
     }
+    // The first half step of the field advance for the tile's own cells, from
+    // the staged halo (cell (i, j) is entry (j + H) NE + i + H; its +x and +y
+    // neighbours are in the halo since H >= 1), into the half-step planes.
+    if (a.bh) {
+        PIC_GLOBAL float *bh = gp(a.bh);
+        for (int c = tid; c < T * T; c += NT) {
+            const int i = c % T, j = c / T;
+            const int e = (j + H) * NE + (i + H);
+            float ex, ex_y, ey, ey_x, ez, ez_x, ez_y, bx, by, bz;
+            if constexpr (P) {   // entries hold cells i and i + 1
+                const float4 q = s_exby[e], w = s_eybx[e];
+                const float2 z = s_ez[e];
+                ex = q.x;
+                by = q.y;
+                ex_y = s_exby[e + NE].x;
+                ey = w.x;
+                bx = w.y;
+                ey_x = w.z;
+                ez = z.x;
+                ez_x = z.y;
+                ez_y = s_ez[e + NE].x;
+                bz = s_bz[e].x;
+            } else {
+                const float2 q = s_exby[e], w = s_eybx[e];
+                ex = q.x;
+                by = q.y;
+                ex_y = s_exby[e + NE].x;
+                ey = w.x;
+                bx = w.y;
+                ey_x = s_eybx[e + 1].x;
+                ez = s_ez[e];
+                ez_x = s_ez[e + 1];
+                ez_y = s_ez[e + NE];
+                bz = s_bz[e];
+            }
+            const BCell b = faraday_half(bx, by, bz, ex, ex_y, ey, ey_x, ez, ez_x, ez_y, a.hdx, a.hdy);
+            const int64_t g = (int64_t)(gy0 + j) * a.nx + (gx0 + i);
+            bh[g] = b.x;
+            bh[plane + g] = b.y;
+            bh[2 * plane + g] = b.z;
+        }
+    }
+
 }
 
 // Register budget: the LDS fit (push_min_waves), and at most two waves per

@@ -20,7 +20,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t err = 0, dacc = 0, cacc = 0, jtile = 0, rho_prev = 0, rho_now = 0, jf = 0, rho_tmp = 0;
+    size_t err = 0, dacc = 0, cacc = 0, jtile = 0, bh = 0, rho_prev = 0, rho_now = 0, jf = 0, rho_tmp = 0;
     size_t wrem = 0, inj_off[kMaxSpecies] = {};
     size_t off[kMaxSpecies][2] = {}, cnt[kMaxSpecies] = {}, leav[kMaxSpecies] = {};
     size_t hole[kMaxSpecies] = {}, stg[kMaxSpecies][6] = {}, mcount[kMaxSpecies] = {}, bsum[kMaxSpecies] = {};
@@ -103,6 +103,7 @@ Layout make_layout(const pic_config *c)
     L.cacc = take(8 * sizeof(unsigned long long));
     const int NJ = T + 2 * halo_of(c) + 1;   // current halo nodes per axis
     L.jtile = take((size_t)n_tiles * 3 * NJ * NJ * sizeof(float));
+    L.bh = take(nodes * 3 * sizeof(float));   // B after the first half step (pic_step)
     L.rho_prev = take(nodes * sizeof(double));
     L.rho_now = take(nodes * sizeof(double));
     if (c->j_filter > 0) {
@@ -143,6 +144,7 @@ struct pic_sim {
     double *dacc;
     unsigned long long *cacc;
     float *jtile;
+    float *bh;          // B after the step's first half step, written by pic_step's push
     double *rho_prev, *rho_now;
     float *jf;          // filter partner of the J planes (j_filter > 0)
     double *rho_tmp;    // filter partner of rho_now (j_filter > 0)
@@ -377,12 +379,15 @@ int solve_gauss_in(pic_sim *S, double *d, double tol, int max_iter, pic_gauss_ou
 
 // Kernel arguments of one simulation (identical every step: the sort writes
 // the new tile_offset in place).
-PushArgs push_args(const pic_sim *S)
+PushArgs push_args(const pic_sim *S, bool bh)
 {
     const pic_config &c = S->cfg;
     PushArgs a;
     memset(&a, 0, sizeof(a));
     a.fld = S->buf.fields;
+    a.bh = bh ? S->bh : nullptr;
+    a.hdx = (float)(0.5 * c.dt / c.dx);
+    a.hdy = (float)(0.5 * c.dt / c.dy);
     a.jtile = S->jtile;
     a.err = S->err;
     a.nx = c.nx;
@@ -493,12 +498,13 @@ SortArgs sort_args(const pic_sim *S)
 
 // fold: J folded from the tile current halos by the E step of the field
 // advance (and written to the J planes), else read from the J planes
-FieldArgs field_args(const pic_sim *S, bool fold)
+FieldArgs field_args(const pic_sim *S, bool fold, bool bh)
 {
     const pic_config &c = S->cfg;
     FieldArgs f;
     f.fld = S->buf.fields;
     f.jtile = fold ? S->jtile : nullptr;
+    f.bh = bh ? S->bh : nullptr;
     f.nx = c.nx;
     f.ny = c.ny;
     f.ntx = S->ntx;
@@ -652,6 +658,7 @@ int init_sim(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
     S->dacc = (double *)(w + L.dacc);
     S->cacc = (unsigned long long *)(w + L.cacc);
     S->jtile = (float *)(w + L.jtile);
+    S->bh = (float *)(w + L.bh);
     S->rho_prev = (double *)(w + L.rho_prev);
     S->rho_now = (double *)(w + L.rho_now);
     S->jf = cfg->j_filter > 0 ? (float *)(w + L.jf) : nullptr;
@@ -723,12 +730,13 @@ extern "C" {
 
 namespace {
 
-// The push kernel alone (steps a1-a7 up to the per-tile current halos).
-int push_only(pic_sim *S, hipStream_t stream)
+// The push kernel alone (steps a1-a7 up to the per-tile current halos); with
+// bh, it also forms the field advance's first half step (pic_step).
+int push_only(pic_sim *S, hipStream_t stream, bool bh)
 {
     // a particle may stray at most sort_every - 1 cells from its tile before a push
     if (S->since_sort >= S->halo) return PIC_EORDER;
-    const PushArgs a = push_args(S);
+    const PushArgs a = push_args(S, bh);
     {
         Timed t(S, PIC_KERNEL_PUSH, stream);
         launch_push_deposit(S->tile, S->replicas, j_mode(&S->cfg), d_mode(&S->cfg), S->halo, ppl_of(&S->cfg), a,
@@ -741,17 +749,20 @@ int push_only(pic_sim *S, hipStream_t stream)
 // The fold of the tile current halos into J, then the optional filter passes.
 int fold_current(pic_sim *S, hipStream_t stream);
 
-// The field half of a step after the push: the J fold (and the filter), then
-// the field advance -- the fold done by the field advance's E step when there
-// is no filter (the same J, bit for bit: both use fold_node).
+// The field half of a step after a push that formed the first B half step:
+// the J fold (and the filter), then the E step and the second B half step --
+// the fold done by the E step when there is no filter (the same J, bit for
+// bit: both use fold_node).  The same fields as pic_field_advance, bit for
+// bit: the push's half step uses the same per-cell function.
 int field_half(pic_sim *S, hipStream_t stream)
 {
-    if (S->cfg.j_filter > 0) {
+    const bool fold = S->cfg.j_filter == 0;
+    if (!fold) {
         const int rc = fold_current(S, stream);
-        return rc ? rc : pic_field_advance(S, stream);
+        if (rc) return rc;
     }
     Timed t(S, PIC_KERNEL_FIELD, stream);
-    launch_field_advance(field_args(S, true), S->tile, S->halo, stream);
+    launch_field_advance(field_args(S, fold, true), S->tile, S->halo, stream);
     return hip_ok(hipGetLastError());
 }
 
@@ -773,7 +784,7 @@ int fold_current(pic_sim *S, hipStream_t stream)
 int pic_push_deposit(pic_sim *S, hipStream_t stream)
 {
     if (!S) return PIC_EINVAL;
-    int rc = push_only(S, stream);
+    int rc = push_only(S, stream, false);
     if (rc == PIC_OK) rc = fold_current(S, stream);
     return rc;
 }
@@ -826,7 +837,7 @@ int pic_field_advance(pic_sim *S, hipStream_t stream)
 {
     if (!S) return PIC_EINVAL;
     Timed t(S, PIC_KERNEL_FIELD, stream);
-    launch_field_advance(field_args(S, false), S->tile, S->halo, stream);
+    launch_field_advance(field_args(S, false, false), S->tile, S->halo, stream);
     return hip_ok(hipGetLastError());
 }
 
@@ -948,7 +959,7 @@ int pic_get_counts(pic_sim *S, int64_t *counts)
 int pic_step(pic_sim *S, hipStream_t stream)
 {
     if (!S) return PIC_EINVAL;
-    int rc = push_only(S, stream);
+    int rc = push_only(S, stream, true);
     if (rc) return rc;
     // Unforked: no sort this step, or no second stream
     if (S->since_sort < S->halo || !S->side) {
@@ -1288,7 +1299,8 @@ void batch_enqueue_step(pic_batch *b, bool sort, hipStream_t stream)
         for (int p = 0; p < b->j_filter; ++p)
             launch_filter_batch(b->d_filter + (p & 1) * b->sims.size(), b->node_items, b->n_node, fs);
     }
-    launch_field_advance_batch(b->d_field, b->node_items, b->n_node, b->j_filter == 0, b->tile, b->halo, fs);
+    launch_field_advance_batch(b->d_field, b->node_items, b->n_node, b->j_filter == 0, true, b->tile, b->halo,
+                               fs);
     if (fork) (void)hipEventRecord(b->ev_join, b->side);
     SortBatch sb;
     sb.descs = b->d_sort;
@@ -1380,10 +1392,10 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
     std::vector<std::pair<double, int>> cost(n);
     for (int i = 0; i < n; ++i) {
         const pic_sim *S = B->sims[i];
-        hp[i] = push_args(S);
+        hp[i] = push_args(S, true);
         hj[i] = jreduce_args(S);
         hs[i] = sort_args(S);
-        hf[i] = field_args(S, S->cfg.j_filter == 0);
+        hf[i] = field_args(S, S->cfg.j_filter == 0, true);
         hfl[i] = filter_args(S, 0);
         hfl[n + i] = filter_args(S, 1);
         int64_t np = 0;

@@ -49,6 +49,8 @@ struct FilterArgs {
 struct FieldArgs {
     float *fld;           // the nine field planes
     const float *jtile;   // tile current halos folded into J by the E step, or null: J is input
+    const float *bh;      // B after the step's first half step, formed by the push (three planes),
+                          // or null: the field advance forms it in place
     int nx, ny, ntx, nty;
     float hdx, hdy;       // (dt/2)/dx, (dt/2)/dy  (B half steps)
     float dt, dtdx, dtdy; // E full step
@@ -129,7 +131,7 @@ void launch_filter_batch(const FilterArgs *descs, const int4 *items, int n_items
 void launch_field_advance(const FieldArgs &f, int tile, int halo, hipStream_t s);
 // batched: items (simulation, 64 x 4 cell block); fold: every member's
 // FieldArgs has jtile set
-void launch_field_advance_batch(const FieldArgs *descs, const int4 *items, int n_items, bool fold, int tile,
+void launch_field_advance_batch(const FieldArgs *descs, const int4 *items, int n_items, bool fold, bool bh, int tile,
                                 int halo, hipStream_t s);
 
 // Conjugate-gradient projection of E (Eq. 17) or B (Eq. 18), k_poisson.hip.

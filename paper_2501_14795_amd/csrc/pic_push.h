@@ -164,6 +164,9 @@ struct SpeciesDev {
 
 struct PushArgs {
     const float *fld;     // Ex Ey Ez Bx By Bz planes
+    float *bh;            // or null: B after the first half step of the field advance (three planes,
+                          // each tile writes its cells from its staged halo)
+    float hdx, hdy;       // (dt/2)/dx, (dt/2)/dy
     float *jtile;         // [n_tiles][3][(T+2H+1)^2], physical current of each tile halo
     int *err;
     int nx, ny, ntx, nty;
