@@ -27,8 +27,6 @@
 
 namespace pic {
 
-// Iterations of 64 candidates whose loads the sort plan keeps in flight together.
-constexpr int kPlanBatch = 4;
 
 __device__ __forceinline__ int wrap_s(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
@@ -207,124 +205,122 @@ __device__ __forceinline__ void copy_particle(const Parts &src, int64_t i, const
 
 // Steps (2)-(4) of the sort for one destination tile t per wavefront, new
 // section [A, B), old section [oA, oB).  Every candidate list of holes and
-// of movers is described by one lane; the lists are then streamed as one
-// flat index space, 64 candidates per iteration, and compacted with ballots,
-// which keeps both outputs in ascending slot order.  W = leaver sub-lists per
-// tile (the push kernel's wavefronts per tile).
-//   hole lists  : [A, min(B, oA))  slots of lower old sections (hole unless
-//                                  the particle there moved into t)
-//                 t's W leaver sub-lists, restricted to [max(A,oA), min(B,oB))
-//                 [max(A, oB), B)  slots of higher old sections
-//   mover lists : for each source tile s of t (the nine tiles a particle of t
-//                 can come from, ascending, duplicates dropped):
-//                 s != t: s's W leaver sub-lists, entries heading to t whose
-//                         slot is outside [A, B); data from the leaver copy
-//                 s == t: t's slots outside [A, B) whose particle kept tile t
-//                 streamed 64 / W sources at a time, in ascending order
+// of movers is described by one list slot (two per lane: slots lane and
+// lane + 64); the lists are streamed as one flat index space, holes first,
+// and compacted with ballots, which keeps both outputs in ascending slot
+// order.  W = leaver sub-lists per tile (the push kernel's wavefronts per
+// tile).  List slots:
+//   0             : holes in [A, min(B, oA)), slots of lower old sections
+//                   (hole unless the particle there moved into t)
+//   1 .. W        : holes among t's W leaver sub-lists, restricted to
+//                   [max(A, oA), min(B, oB))
+//   W + 1         : holes in [max(A, oB), B), slots of higher old sections
+//   W + 2 + q W + w : movers from the source tile of rank q (the nine tiles a
+//                   particle of t can come from, ascending, duplicates
+//                   dropped): s != t -- s's leaver sub-list w, entries heading
+//                   to t whose slot is outside [A, B), data from the leaver
+//                   records; s == t -- (w = 0, 1) t's slots outside [A, B)
+//                   whose particle kept tile t
+//   W + 2 + 9 W, +1 : the moving window's new particles for t outside [A, B)
+// The loads are staged so that each round trip to memory serves all lists at
+// once: the list bounds, then the candidates (kPlanBatch iterations of 64),
+// then the movers' data, then the stores.
+constexpr int kPlanBatch = 6;
+constexpr int kPlanLdsHoles = 512;   // hole slots per wavefront kept in LDS
+enum : int { kListHoleRange = 0, kListHoleLeav = 1, kListMoverRange = 2, kListMoverLeav = 3 };
+static_assert(10 * push_waves(32) + 4 <= 128 && 10 * push_waves(8) + 4 <= 128, "sort plan list slots");
+
 __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int grp)
 {
+    __shared__ int s_hole[kSortWaves][kPlanLdsHoles];
     const int lane = threadIdx.x & 63;
     // one tile per wavefront: the index is wavefront-uniform (scalar registers)
-    const int t = grp * kSortWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = grp * kSortWaves + wv;
     if (t >= a.n_tiles) return;   // whole wavefront
     const SortSpecies &sp = a.sp[spi];
     const int ntx = a.ntx, nty = a.nty;
     const int tsh = __builtin_ctz(a.tile);
     const int W = push_waves(a.tile);   // leaver sub-lists per tile
-    const int A = sp.offn[t], B = sp.offn[t + 1];
-    const int oA = sp.off[t], oB = sp.off[t + 1];
     // a negative cell marks a particle that left the moving window: no tile
     auto tile_of = [&](int cell) { return cell < 0 ? -1 : ((cell >> 16) >> tsh) * ntx + ((cell & 0xffff) >> tsh); };
-    bool bad = false;
 
-    // ---------------- holes, ascending: nhead in [A, min(B, oA)), then t's
-    // leaver slots, then ntail in [max(A, oB), B)
-    int nh = 0, nhead = 0, ntail = 0;
-    {
-        const int lA = max(A, oA), lB = min(B, oB);
-        int kind = 0, base = 0, len = 0;   // kind 0: slot range, 1: leaver sub-list of t
-        if (lane == 0) {
-            base = A;
-            len = max(0, min(B, oA) - A);
-        } else if (lane <= W) {
-            int wlo, whi;
-            wave_range(oA, oB, lane - 1, W, wlo, whi);
-            kind = 1;
-            base = wlo;
-            len = lA < lB ? min(sp.cnt[(int64_t)t * kCntStride + kCntSub + lane - 1], whi - wlo) : 0;
-        } else if (lane == W + 1) {
-            base = max(A, oB);
-            len = max(0, B - base);
-        }
-        int total;
-        int ex = wave_exclusive(len, total);
-        if (lane > W + 1) ex = INT_MAX;
-        // kPlanBatch iterations of 64 candidates: all their loads first, then
-        // the ballots in candidate order
-        for (int k0 = 0; k0 < total; k0 += 64 * kPlanBatch) {
-            int at[kPlanBatch], lv[kPlanBatch];
-            uint32_t v[kPlanBatch];
+    // ---------------- the sources of t and their ranks (lanes 0..8)
+    const int tx = t % ntx, ty = t / ntx;
+    int so = -1;
+    if (lane < 9) so = wrap_s(ty - (lane / 3 - 1), nty) * ntx + wrap_s(tx - (lane % 3 - 1), ntx);
+    int rank = 0, first = 1;
 #pragma unroll
-            for (int u = 0; u < kPlanBatch; ++u) {
-                const int k = k0 + 64 * u + lane;
-                const int L = find_list(k, ex);
-                const int kL = __shfl(kind, L, 64), bL = __shfl(base, L, 64), eL = __shfl(ex, L, 64);
-                lv[u] = k < total ? L : -1;
-                at[u] = bL + (k - eL);   // a slot (kind 0) or a position in t's leaver list (kind 1)
-                v[u] = 0;
-                if (k < total) v[u] = kL == 0 ? (uint32_t)sp.p.cell[at[u]] : sp.leav[at[u]];
-            }
-#pragma unroll
-            for (int u = 0; u < kPlanBatch; ++u) {
-                const int L = lv[u];
-                bool p = false;
-                int slot = at[u];
-                if (L == 0 || L == W + 1) {
-                    p = tile_of((int)v[u]) != t;
-                } else if (L > 0) {
-                    slot = oA + (int)(v[u] >> 4);
-                    p = slot >= lA && slot < lB;
-                }
-                const unsigned long long m = __ballot(p);
-                const int r = nh + lane_rank_s(m);
-                if (p && r < B - A) sp.hole[(int64_t)A + r] = slot;
-                nh += __popcll(m);
-                nhead += __popcll(__ballot(p && L == 0));
-                ntail += __popcll(__ballot(p && L == W + 1));
-            }
-        }
+    for (int o = 0; o < 9; ++o) {
+        const int v = __shfl(so, o, 64);
+        bool vfirst = true;
+        for (int o2 = 0; o2 < o; ++o2)
+            if (__shfl(so, o2, 64) == v) vfirst = false;
+        if (vfirst && v < so) ++rank;
+        if (o < lane && v == so) first = 0;
     }
-    // the holes' slots, written by this wavefront, are read back below
-    __threadfence_block();
-
-    // ---------------- movers, ascending old slot, gathered into staging
-    int nm = 0;
-    {
-        // source tiles: lane o < 9 holds one, then its rank among the distinct ones
-        const int tx = t % ntx, ty = t / ntx;
-        int so = -1;
-        if (lane < 9) so = wrap_s(ty - (lane / 3 - 1), nty) * ntx + wrap_s(tx - (lane % 3 - 1), ntx);
-        int rank = 0, first = 1, nuniq = 0;
+    // the source of rank q, -1 if there is none (all lanes take part)
+    auto source_of_rank = [&](int q) {
+        int v = -1;
 #pragma unroll
         for (int o = 0; o < 9; ++o) {
-            const int v = __shfl(so, o, 64);
-            bool vfirst = true;
-            for (int o2 = 0; o2 < o; ++o2)
-                if (__shfl(so, o2, 64) == v) vfirst = false;
-            if (vfirst) ++nuniq;
-            if (vfirst && v < so) ++rank;
-            if (o < lane && v == so) first = 0;
+            const int so_o = __shfl(so, o, 64), rank_o = __shfl(rank, o, 64), first_o = __shfl(first, o, 64);
+            if (first_o && rank_o == q) v = so_o;
         }
-        // The lists of one source tile: kind 0 -- t's own slot ranges outside
-        // [A, B) (lists 0 and 1), kind 1 -- the source's W leaver sub-lists
-        // (with the source's first slot s0 and particle count ns).
-        auto source_list = [&](int src, int w, int &kind, int &base, int &len, int &s0, int &ns) {
-            kind = 0;
-            base = 0;
-            len = 0;
-            s0 = 0;
-            ns = 0;
-            if (src < 0) return;   // no source of that rank
+        return v;
+    };
+
+    // ---------------- list bounds: every load of this stage in flight at once
+    const int nl_mov = 9 * W;
+    int srcv[2], wv_[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int v = lane + 64 * h;
+        const int q = v >= W + 2 && v < W + 2 + nl_mov ? (v - W - 2) / W : -1;
+        wv_[h] = v >= W + 2 ? (v - W - 2) % W : v - 1;   // sub-list index (movers; holes: v - 1)
+        srcv[h] = source_of_rank(q);
+    }
+    const int A = sp.offn[t], B = sp.offn[t + 1];
+    const int oA = sp.off[t], oB = sp.off[t + 1];
+    int f0[2], f1[2], fc[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int v = lane + 64 * h;
+        // hole sub-lists read t's record, mover sub-lists their source's (index 0 when unused)
+        const int s = v >= 1 && v <= W ? t : (srcv[h] >= 0 ? srcv[h] : 0);
+        const int w = v >= 1 && v <= W ? v - 1 : (srcv[h] >= 0 ? wv_[h] : 0);
+        f0[h] = sp.off[s];
+        f1[h] = sp.off[s + 1];
+        fc[h] = sp.cnt[(int64_t)s * kCntStride + kCntSub + w];
+    }
+    int i0 = 0, i1 = 0;
+    if (sp.inj_off) {
+        i0 = sp.n + sp.inj_off[t];
+        i1 = sp.n + sp.inj_off[t + 1];
+    }
+    const int lA = max(A, oA), lB = min(B, oB);
+    // descriptors: kind | src << 2, (base - first index), length, s0, ns
+    int dks[2], dbm[2], dlen[2], ds0[2], dns[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int v = lane + 64 * h;
+        int kind = kListHoleRange, base = 0, len = 0, src = 0, s0 = 0, ns = 0;
+        if (v == 0) {
+            base = A;
+            len = max(0, min(B, oA) - A);
+        } else if (v <= W) {
+            int wlo, whi;
+            wave_range(oA, oB, v - 1, W, wlo, whi);
+            kind = kListHoleLeav;
+            base = wlo;
+            len = lA < lB ? min(fc[h], whi - wlo) : 0;
+        } else if (v == W + 1) {
+            base = max(A, oB);
+            len = max(0, B - base);
+        } else if (v < W + 2 + nl_mov) {
+            src = srcv[h];
+            const int w = wv_[h];
+            kind = kListMoverRange;
             if (src == t) {
                 if (w == 0) {
                     base = oA;
@@ -333,131 +329,139 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
                     base = max(oA, B);
                     len = max(0, oB - base);
                 }
-            } else if (w < W) {
-                s0 = sp.off[src];
-                const int s1 = sp.off[src + 1];
-                ns = s1 - s0;
+            } else if (src >= 0) {
                 int wlo, whi;
-                wave_range(s0, s1, w, W, wlo, whi);
-                kind = 1;
+                wave_range(f0[h], f1[h], w, W, wlo, whi);
+                kind = kListMoverLeav;
                 base = wlo;
-                len = min(sp.cnt[(int64_t)src * kCntStride + kCntSub + w], whi - wlo);
+                len = min(fc[h], whi - wlo);
+                s0 = f0[h];
+                ns = f1[h] - f0[h];
             }
-        };
-        // Stream the lists held by the lanes (one each; `valid` false: none) as
-        // one index space, appending t's movers: kPlanBatch iterations of 64
-        // candidates at a time -- their loads, then the ballots in candidate
-        // order, then the movers' hole slots and data, then the stores, so
-        // each stage's memory accesses are in flight together.
-        auto stream_lists = [&](int kind, int base, int len, int src, int s0, int ns, bool valid) {
-            int total;
-            int ex = wave_exclusive(len, total);
-            if (!valid) ex = INT_MAX;
-            for (int k0 = 0; k0 < total; k0 += 64 * kPlanBatch) {
-                int64_t at[kPlanBatch];
-                uint32_t v[kPlanBatch];
-                int kv[kPlanBatch], sv[kPlanBatch], s0v[kPlanBatch], nsv[kPlanBatch];
-                bool in[kPlanBatch];
-#pragma unroll
-                for (int u = 0; u < kPlanBatch; ++u) {
-                    const int k = k0 + 64 * u + lane;
-                    const int Lk = find_list(k, ex);
-                    kv[u] = __shfl(kind, Lk, 64);
-                    const int bL = __shfl(base, Lk, 64), eL = __shfl(ex, Lk, 64);
-                    sv[u] = __shfl(src, Lk, 64);
-                    s0v[u] = __shfl(s0, Lk, 64);
-                    nsv[u] = __shfl(ns, Lk, 64);
-                    at[u] = (int64_t)bL + (k - eL);
-                    in[u] = k < total;
-                    v[u] = 0;
-                    if (in[u]) v[u] = kv[u] == 0 ? (uint32_t)sp.p.cell[at[u]] : sp.leav[at[u]];
-                }
-                bool mv[kPlanBatch], fl[kPlanBatch];
-                int rr[kPlanBatch];
-#pragma unroll
-                for (int u = 0; u < kPlanBatch; ++u) {
-                    bool p = false, from_leavers = false;
-                    if (in[u]) {
-                        if (kv[u] == 0) {
-                            p = tile_of((int)v[u]) == t;
-                        } else {
-                            const int d = (int)(v[u] & 15u), loc = (int)(v[u] >> 4);
-                            if (loc >= nsv[u] || d > kDirRemoved) {
-                                bad = true;
-                            } else if (d != kDirRemoved) {   // a removed particle is nobody's mover
-                                const int sx = sv[u] % ntx, sy = sv[u] / ntx;
-                                const int dest = wrap_s(sy + d / 3 - 1, nty) * ntx + wrap_s(sx + d % 3 - 1, ntx);
-                                const int slot = s0v[u] + loc;
-                                p = dest == t && !(slot >= A && slot < B);
-                                from_leavers = true;
-                            }
-                        }
-                    }
-                    const unsigned long long m = __ballot(p);
-                    rr[u] = nm + lane_rank_s(m);
-                    mv[u] = p && rr[u] < B - A;
-                    fl[u] = from_leavers;
-                    nm += __popcll(m);
-                }
-                // staged (the head and tail of the holes), or straight into
-                // one of t's leaver slots
-                int64_t to[kPlanBatch];
-                Chunk6 d[kPlanBatch];
-#pragma unroll
-                for (int u = 0; u < kPlanBatch; ++u) {
-                    to[u] = 0;
-                    if (mv[u]) {
-                        const int r = rr[u];
-                        const bool staged = r < nhead || r >= nh - ntail;
-                        to[u] = staged ? (int64_t)A + r : (int64_t)sp.hole[(int64_t)A + r];
-                        d[u] = fl[u] ? load_leaver(sp.lrec, at[u]) : load_parts(sp.p, at[u]);
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kPlanBatch; ++u) {
-                    if (mv[u]) {
-                        const int r = rr[u];
-                        const bool staged = r < nhead || r >= nh - ntail;
-                        store_parts(staged ? sp.stg : sp.p, to[u], d[u]);
-                    }
-                }
-            }
-        };
-        // the source tile of rank q (ascending tile id = ascending old slot),
-        // -1 if there is none; executed by all lanes (it reads lanes 0..8)
-        auto source_of_rank = [&](int q) {
-            int v = -1;
-#pragma unroll
-            for (int o = 0; o < 9; ++o) {
-                // every lane takes part in every shuffle; the selection follows
-                const int so_o = __shfl(so, o, 64), rank_o = __shfl(rank, o, 64), first_o = __shfl(first, o, 64);
-                if (first_o && rank_o == q) v = so_o;
-            }
-            return v;
-        };
-        // 64 / W sources per round, in ascending order: lane L holds list
-        // L % W of the source of rank q0 + L / W (one round when W = 4)
-        const int G = 64 / W;
-        for (int q0 = 0; q0 < nuniq; q0 += G) {
-            const int pr = q0 + lane / W, w = lane % W;
-            const int src = source_of_rank(pr);
-            int kind, base, len, s0, ns;
-            source_list(src, w, kind, base, len, s0, ns);
-            stream_lists(kind, base, len, src, s0, ns, pr < nuniq);
+            src = max(src, 0);
+        } else if (v == W + 2 + nl_mov && sp.inj_off) {
+            kind = kListMoverRange;
+            base = i0;
+            len = max(0, min(i1, A) - i0);
+        } else if (v == W + 3 + nl_mov && sp.inj_off) {
+            kind = kListMoverRange;
+            base = max(i0, B);
+            len = max(0, i1 - base);
         }
-        if (sp.inj_off) {
-            // the window's new particles for t, appended after every old
-            // section: the parts of their slot range outside [A, B)
-            const int i0 = sp.n + sp.inj_off[t], i1 = sp.n + sp.inj_off[t + 1];
-            int base = 0, len = 0;
-            if (lane == 0) {
-                base = i0;
-                len = max(0, min(i1, A) - i0);
-            } else if (lane == 1) {
-                base = max(i0, B);
-                len = max(0, i1 - base);
+        dks[h] = kind | (src << 2);
+        dbm[h] = base;
+        dlen[h] = len;
+        ds0[h] = s0;
+        dns[h] = ns;
+    }
+    // the flat index space: slots 0..63 (first register), then 64..127
+    int tot0, tot1;
+    const int ex0 = wave_exclusive(dlen[0], tot0);
+    const int ex1 = tot0 + wave_exclusive(dlen[1], tot1);
+    const int total = tot0 + tot1;
+    dbm[0] -= ex0;   // candidate k of the list: base + (k - ex) = dbm + k
+    dbm[1] -= ex1;
+
+    bool bad = false;
+    int nh = 0, nhead = 0, ntail = 0, nm = 0;
+    for (int k0 = 0; k0 < total; k0 += 64 * kPlanBatch) {
+        // ---- the candidates: their lists, then every load in flight at once
+        int at[kPlanBatch], ks[kPlanBatch], s0v[kPlanBatch], nsv[kPlanBatch], lv[kPlanBatch];
+        uint32_t v[kPlanBatch];
+#pragma unroll
+        for (int u = 0; u < kPlanBatch; ++u) {
+            const int k = k0 + 64 * u + lane;
+            const int L0 = find_list(k, ex0), L1 = find_list(k, ex1);
+            const bool hi = k >= tot0;
+            const int L = hi ? L1 : L0;
+            auto pick = [&](const int *f) {
+                const int x0 = __shfl(f[0], L, 64), x1 = __shfl(f[1], L, 64);
+                return hi ? x1 : x0;
+            };
+            lv[u] = k < total ? L + (hi ? 64 : 0) : -1;
+            ks[u] = pick(dks);
+            at[u] = pick(dbm) + k;
+            s0v[u] = pick(ds0);
+            nsv[u] = pick(dns);
+            const int kind = ks[u] & 3;
+            v[u] = 0;
+            if (k < total)
+                v[u] = kind == kListHoleRange || kind == kListMoverRange ? (uint32_t)sp.p.cell[at[u]] : sp.leav[at[u]];
+        }
+        // ---- the ballots, in candidate order: holes first, then movers
+        int rr[kPlanBatch];
+        unsigned mvf = 0, flf = 0;   // per iteration: a mover of this lane, from the leaver records
+#pragma unroll
+        for (int u = 0; u < kPlanBatch; ++u) {
+            const int kind = ks[u] & 3, L = lv[u];
+            bool ph = false, pm = false, fl = false;
+            int slot = at[u];
+            if (L >= 0) {
+                if (kind == kListHoleRange) {
+                    ph = tile_of((int)v[u]) != t;
+                } else if (kind == kListHoleLeav) {
+                    slot = oA + (int)(v[u] >> 4);
+                    ph = slot >= lA && slot < lB;
+                } else if (kind == kListMoverRange) {
+                    pm = tile_of((int)v[u]) == t;
+                } else {
+                    const int d = (int)(v[u] & 15u), loc = (int)(v[u] >> 4);
+                    if (loc >= nsv[u] || d > kDirRemoved) {
+                        bad = true;
+                    } else if (d != kDirRemoved) {   // a removed particle is nobody's mover
+                        const int src = ks[u] >> 2;
+                        const int sx = src % ntx, sy = src / ntx;
+                        const int dest = wrap_s(sy + d / 3 - 1, nty) * ntx + wrap_s(sx + d % 3 - 1, ntx);
+                        const int ms = s0v[u] + loc;
+                        pm = dest == t && !(ms >= A && ms < B);
+                        fl = true;
+                    }
+                }
             }
-            stream_lists(0, base, len, t, 0, 0, lane < 2);
+            const unsigned long long mh = __ballot(ph);
+            const int r = nh + lane_rank_s(mh);
+            if (ph && r < B - A) {
+                sp.hole[(int64_t)A + r] = slot;
+                if (r < kPlanLdsHoles) s_hole[wv][r] = slot;
+            }
+            nh += __popcll(mh);
+            nhead += __popcll(__ballot(ph && L == 0));
+            ntail += __popcll(__ballot(ph && L == W + 1));
+            const unsigned long long mm = __ballot(pm);
+            rr[u] = nm + lane_rank_s(mm);
+            if (pm && rr[u] < B - A) mvf |= 1u << u;
+            if (fl) flf |= 1u << u;
+            nm += __popcll(mm);
+        }
+        // the hole slots written above are read back below (LDS; global
+        // memory past the LDS share)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (nh > kPlanLdsHoles) __threadfence_block();
+        if (__ballot(mvf != 0) == 0ull) continue;
+        // ---- the movers' holes and data, every load in flight at once;
+        // staged (the head and tail of the holes), or straight into one of
+        // t's leaver slots
+        int to[kPlanBatch];
+        Chunk6 dv[kPlanBatch];
+#pragma unroll
+        for (int u = 0; u < kPlanBatch; ++u) {
+            to[u] = 0;
+            if (mvf >> u & 1u) {
+                const int r = rr[u];
+                const bool staged = r < nhead || r >= nh - ntail;
+                to[u] = staged ? A + r : (r < kPlanLdsHoles ? s_hole[wv][r] : sp.hole[(int64_t)A + r]);
+                dv[u] = flf >> u & 1u ? load_leaver(sp.lrec, at[u]) : load_parts(sp.p, at[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPlanBatch; ++u) {
+            if (mvf >> u & 1u) {
+                const int r = rr[u];
+                const bool staged = r < nhead || r >= nh - ntail;
+                store_parts(staged ? sp.stg : sp.p, to[u], dv[u]);
+            }
         }
     }
 
