@@ -51,14 +51,17 @@ def log(msg):
 
 
 def push_bytes(n_particles, n_tiles, tile, leavers, n_species=1, halo=1):
-    """Algorithmic HBM bytes of one push + deposit launch: every particle read
-    and written once, each tile's E/B halo ((T+2H)^2 cells x 6 fields, H the
-    halo pad: 1, or the sort cadence) read once, each tile's current halo
-    ((T+2H+1)^2 nodes x 3) written once, the tile_offset pair and the count
-    record (32 ints) per tile and species, and one 4-byte entry per leaver."""
+    """Algorithmic HBM bytes of one push + deposit launch of pic_step: every
+    particle read and written once, each tile's E/B halo ((T+2H)^2 cells x 6
+    fields, H the halo pad: 1, or the sort cadence) read once, each tile's
+    current halo ((T+2H+1)^2 nodes x 3) written once, the B half step of the
+    tile's T^2 cells (3 floats each) written once, the tile_offset pair and
+    the count record (32 ints) per tile and species, and one 4-byte entry per
+    leaver (the leavers' 32-byte records are not counted)."""
     return (2 * BYTES_PARTICLE * n_particles
             + n_tiles * (tile + 2 * halo) ** 2 * 6 * 4
             + n_tiles * (tile + 2 * halo + 1) ** 2 * 3 * 4
+            + n_tiles * tile * tile * 3 * 4
             + n_species * n_tiles * (8 + 32 * 4)
             + 4 * leavers)
 
