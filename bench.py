@@ -204,6 +204,7 @@ def batched_comparison(n_sims=256, steps=5, tune_sims=32):
     for _ in range(steps):
         for m in b.members:
             _lib.pic_step(m.handle, s)
+    b.sync()
     b.stream.synchronize()
     per_sim = (time.perf_counter() - t0) / steps
     # the persistent push alone, event-timed in direct batched steps: its
@@ -288,6 +289,7 @@ def variant_measurement(w, T, steps=20, warmup=3, **options):
     t0 = time.perf_counter()
     for _ in range(steps):
         sim.step()
+    sim.sync()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     # per-kernel split from as many extra, event-timed steps
@@ -428,6 +430,7 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         sim.step()
+    sim.sync()   # the last sort's hole fill (the next push would do it) inside the timed region
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     kt_push = sim.timing()["push"]

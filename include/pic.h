@@ -23,6 +23,14 @@
  *     and pic_get_timing(), which synchronise the stream they are given.
  *   - Calls on one pic_sim must not run concurrently from several host
  *     threads.
+ *   - pic_step() and pic_batch_step() leave the last part of their sort, the
+ *     copy of the staged movers into their holes, to the next push, which
+ *     streams those slots anyway: until then the particle arrays hold stale
+ *     values in those slots.  Every entry point that reads the particles
+ *     (pic_get_state, pic_diag, pic_move_window, the Gauss solves, and of
+ *     course the next push) completes it first; a caller that reads the
+ *     particle arrays itself calls pic_sync() before.  tile_offset, the
+ *     counts and the fields are final when pic_step() returns.
  *
  * Data layout
  *   - Grid: nx x ny cells, node (i, j) at (i dx, j dy), periodic in x and y.
@@ -231,6 +239,14 @@ int pic_push_deposit(pic_sim *sim, hipStream_t stream);
 int pic_sort(pic_sim *sim, hipStream_t stream);
 
 /*
+ * Complete the hole fill that pic_step()'s or pic_batch_step()'s sort left to
+ * the next push (see the memory model): copies the staged movers into their
+ * holes, so the caller's particle arrays hold the sorted state.  Does nothing
+ * if no fill is pending.  Enqueues on `stream` without synchronising.
+ */
+int pic_sync(pic_sim *sim, hipStream_t stream);
+
+/*
  * Field half of the step (Listing 3.1): B half step, E full step with the
  * current J, B half step (Eqs. 19-20 on the Yee grid, periodic images read
  * directly: update_gc_copy).
@@ -270,7 +286,8 @@ int pic_get_window_origin(pic_sim *sim, int32_t *origin);
 int pic_get_counts(pic_sim *sim, int64_t *counts);
 
 /* pic_push_deposit + pic_sort (every sort_every-th step) + pic_field_advance,
- * with the same results.  In a step that sorts, the field half (J fold,
+ * with the same results once the sort's hole fill is done: the next push
+ * does it, or pic_sync() (see the memory model).  In a step that sorts, the field half (J fold,
  * filter, field advance) runs on the library's own stream beside the sort:
  * forked from `stream` after the push with an event and joined back into
  * `stream` before the call returns, so everything the caller enqueues on
@@ -476,6 +493,10 @@ int pic_batch_capture(pic_batch *b, hipStream_t stream);
  * persistent push launch in direct (not graph-replayed) batched steps; do
  * not capture with it on. */
 pic_sim *pic_batch_sim(pic_batch *b, int i);
+
+/* pic_sync() for every member at once (one launch): the hole fill that the
+ * last batched sort left to the next push.  Enqueues on `stream`. */
+int pic_batch_sync(pic_batch *b, hipStream_t stream);
 
 /* pic_check of every member; the first error found. */
 int pic_batch_check(pic_batch *b, hipStream_t stream);

@@ -42,12 +42,12 @@ PIC_MAX_FILTER = 16
 
 # every symbol the header declares
 EXPORTS = [
-    "pic_query", "pic_init", "pic_push_deposit", "pic_sort", "pic_field_advance", "pic_move_window",
+    "pic_query", "pic_init", "pic_push_deposit", "pic_sort", "pic_sync", "pic_field_advance", "pic_move_window",
     "pic_get_window_origin", "pic_get_counts", "pic_solve_gauss", "pic_solve_gauss_noalloc", "pic_step",
     "pic_check", "pic_diag", "pic_get_state", "pic_set_state", "pic_get_tile_offsets",
     "pic_set_timing", "pic_set_timing_mask", "pic_get_timing",
     "pic_batch_query", "pic_batch_init", "pic_batch_step", "pic_batch_capture", "pic_batch_sim",
-    "pic_batch_check", "pic_batch_destroy",
+    "pic_batch_check", "pic_batch_sync", "pic_batch_destroy",
     "pic_probe_stream", "pic_strerror", "pic_destroy",
 ]
 
@@ -127,7 +127,7 @@ def load(path: str = SO_PATH):
     vp = ctypes.c_void_p
     L.pic_query.argtypes = [P(pic_config), P(pic_sizes)]
     L.pic_init.argtypes = [P(pic_config), P(pic_buffers), vp, P(vp)]
-    for name in ("pic_push_deposit", "pic_sort", "pic_field_advance", "pic_step", "pic_check"):
+    for name in ("pic_push_deposit", "pic_sort", "pic_sync", "pic_field_advance", "pic_step", "pic_check"):
         getattr(L, name).argtypes = [vp, vp]
     L.pic_diag.argtypes = [vp, ctypes.c_uint, P(pic_diag_out), vp]
     L.pic_get_tile_offsets.argtypes = [vp, ctypes.c_int, vp, vp]
@@ -153,6 +153,7 @@ def load(path: str = SO_PATH):
     L.pic_batch_sim.argtypes = [vp, ctypes.c_int]
     L.pic_batch_sim.restype = vp
     L.pic_batch_check.argtypes = [vp, vp]
+    L.pic_batch_sync.argtypes = [vp, vp]
     L.pic_batch_destroy.argtypes = [vp]
     L.pic_batch_destroy.restype = None
     for name in EXPORTS:
@@ -193,6 +194,10 @@ def pic_push_deposit(sim: int, stream: int):
 
 def pic_sort(sim: int, stream: int):
     _chk(load().pic_sort(ctypes.c_void_p(sim), ctypes.c_void_p(stream)), "pic_sort")
+
+
+def pic_sync(sim: int, stream: int):
+    _chk(load().pic_sync(ctypes.c_void_p(sim), ctypes.c_void_p(stream)), "pic_sync")
 
 
 def pic_field_advance(sim: int, stream: int):
@@ -334,6 +339,10 @@ def pic_batch_sim(batch: int, i: int) -> int:
 
 def pic_batch_check(batch: int, stream: int) -> int:
     return load().pic_batch_check(ctypes.c_void_p(batch), ctypes.c_void_p(stream))
+
+
+def pic_batch_sync(batch: int, stream: int):
+    _chk(load().pic_batch_sync(ctypes.c_void_p(batch), ctypes.c_void_p(stream)), "pic_batch_sync")
 
 
 def pic_batch_destroy(batch: int):

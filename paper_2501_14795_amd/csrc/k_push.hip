@@ -517,6 +517,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
     __shared__ int s_dir[kMaxSpecies][9];
     __shared__ int s_wl[kMaxSpecies][W];
     __shared__ uint32_t s_pq[W][6][kMotionBuf];   // queued face-crossing motions
+    __shared__ int s_fill[W][64];                  // pending holes of the chunk being loaded
 
     const int tx = tile % a.ntx, ty = tile / a.ntx;
     const int gx0 = tx * T, gy0 = ty * T;
@@ -572,6 +573,57 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             st.uy = rsrc(sp.uy + base, bytes);
             st.uz = rsrc(sp.uz + base, bytes);
             const float h = sp.h, fq = sp.fq;
+            // The fill the last sort left (holes of the section, ascending,
+            // whose particles wait in the staging arrays): a window of 64 of
+            // this run's hole slots, one per lane (fhw: the slot of rank
+            // fhb + lane), and the next rank not yet placed (fhp).  All uniform
+            // but fhw.
+            const int nfill = gp(sp.fcount)[tile];
+            const PIC_GLOBAL int32_t *fhole = gp(sp.fhole) + begin;
+            int fhb = 0, fhp = 0, fhw = INT_MAX;
+            if (nfill > 0) {
+                fhb = fhp = gp(sp.fbase)[(int64_t)tile * W + wave];
+                fhw = fhb + lane < nfill ? fhole[fhb + lane] : INT_MAX;
+            }
+            // the rank of the hole at slot c0 + lane (chunks in ascending
+            // order), or -1; a chunk without holes costs one compare
+            auto fill_ref = [&](int c0) -> int {
+                if (fhp >= nfill) return -1;
+                const int lim = min(c0 + 64, hi);
+                if (__builtin_amdgcn_readlane(fhw, fhp - fhb) >= lim) return -1;
+                int *map = s_fill[wave];
+                map[lane] = -1;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                for (;;) {
+                    const bool in = lane >= fhp - fhb && fhw >= c0 && fhw < lim;
+                    const unsigned long long mk = __ballot(in);
+                    if (in) map[fhw - c0] = fhb + lane;
+                    fhp += __popcll(mk);
+                    if (fhp - fhb < 64 || fhp >= nfill) break;
+                    fhb = fhp;   // the window is used up: the next one
+                    fhw = fhb + lane < nfill ? fhole[fhb + lane] : INT_MAX;
+                    if (__builtin_amdgcn_readlane(fhw, 0) >= lim) break;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                return map[lane];
+            };
+            // a hole lane's particle from its staged 32-byte record
+            auto fill_load = [&](Chunk &d, int ref) {
+                if (ref >= 0) {
+                    const PIC_GLOBAL vf4 *r = (const PIC_GLOBAL vf4 *)(sp.fsrc + begin + ref);
+                    const vf4 u = r[0];
+                    const vf2 v = *(const PIC_GLOBAL vf2 *)(r + 1);
+                    d.cell = __float_as_int(u.x);
+                    d.x = u.y;
+                    d.y = u.z;
+                    d.ux = u.w;
+                    d.uy = v.x;
+                    d.uz = v.y;
+                }
+            };
             int npq = 0;    // motions waiting in the wavefront's queue (uniform)
             int nbuf = 0;   // leavers waiting in the wavefront's LDS buffer (packed layout; uniform)
             // C chunks per iteration: lane L holds the particles of slots
@@ -633,16 +685,24 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             };
             int cb = (lo >> 6) << 6;
             int off = (cb + lane - base) * 4;
-            Chunk nxt[C];
+            Chunk nxt[C], nstg[C];
+            int nref[C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) nxt[c] = load_chunk(st, off + 256 * c);
+            for (int c = 0; c < C; ++c) {
+                nxt[c] = load_chunk(st, off + 256 * c);
+                nref[c] = fill_ref(cb + 64 * c);
+                nstg[c] = Chunk{};
+                fill_load(nstg[c], nref[c]);
+            }
             int errs = 0;   // error bits of this lane's particles
             for (; cb < hi; cb += 64 * C, off += 256 * C) {
                 Chunk cur[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    cur[c] = nxt[c];
+                    cur[c] = nref[c] >= 0 ? nstg[c] : nxt[c];   // a hole: its particle from the fill
                     nxt[c] = load_chunk(st, off + 256 * (C + c));
+                    nref[c] = fill_ref(cb + 64 * (C + c));
+                    fill_load(nstg[c], nref[c]);
                 }
                 const int i = cb + lane;
                 Moved m[C];
@@ -665,6 +725,8 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
         if (lane == 0) s_wl[s][wave] = nleav;
     }
     __syncthreads();
+    // the fill the last sort left is done (every wavefront has read its count)
+    if (tid < a.n_species && gp(a.sp[tid].fcount)[tile] != 0) gp(a.sp[tid].fcount)[tile] = 0;
 
     // the int64 current sums are exact while the tile holds fewer than 2^31
     // particles over all species

@@ -15,14 +15,15 @@
 //                             the leavers of the up-to-eight neighbour tiles
 //                             heading to t (their leaver lists) and t's own
 //                             stayers pushed out of [A, B) by section shifts;
-//                  a mover whose hole is one of t's own leaver slots (no
-//                  other tile reads or writes such a slot) is written there
-//                  at once; the others -- the head and tail of the holes,
-//                  which lie in neighbouring tiles' old sections and may
-//                  still hold their movers -- go to a staging area, so only
-//                  O(movers) particle bytes are touched.
-//   k_sort_scatter step (5): the staged movers into their holes (contiguous
-//                  runs of slots at the ends of the section).
+//                  every mover is copied, in hole order, to a staging area
+//                  (contiguous stores), so only O(movers) particle bytes
+//                  are touched and no particle slot is written while other
+//                  plans may still read it.
+//   k_sort_scatter step (5): the staged movers into their holes -- or, in
+//                  pic_step, nothing: the next push fills each hole from
+//                  the staging area as it streams its section (a deferred
+//                  fill; k_fill completes one on its own when anything else
+//                  is to read the particles first).
 #include "pic_internal.h"
 
 namespace pic {
@@ -226,13 +227,11 @@ __device__ __forceinline__ void copy_particle(const Parts &src, int64_t i, const
 // once: the list bounds, then the candidates (kPlanBatch iterations of 64),
 // then the movers' data, then the stores.
 constexpr int kPlanBatch = 6;
-constexpr int kPlanLdsHoles = 512;   // hole slots per wavefront kept in LDS
 enum : int { kListHoleRange = 0, kListHoleLeav = 1, kListMoverRange = 2, kListMoverLeav = 3 };
 static_assert(10 * push_waves(32) + 4 <= 128 && 10 * push_waves(8) + 4 <= 128, "sort plan list slots");
 
 __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int grp)
 {
-    __shared__ int s_hole[kSortWaves][kPlanLdsHoles];
     const int lane = threadIdx.x & 63;
     // one tile per wavefront: the index is wavefront-uniform (scalar registers)
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -362,8 +361,16 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
     dbm[0] -= ex0;   // candidate k of the list: base + (k - ex) = dbm + k
     dbm[1] -= ex1;
 
+    // the first slot of each pushing wavefront's run of the new section
+    // (lane w < W): the holes below it give that run's first hole rank
+    int wlo_mine = INT_MAX, fb = 0;
+    if (lane < W) {
+        int whi;
+        wave_range(A, B, lane, W, wlo_mine, whi);
+    }
+
     bool bad = false;
-    int nh = 0, nhead = 0, ntail = 0, nm = 0;
+    int nh = 0, nm = 0;
     for (int k0 = 0; k0 < total; k0 += 64 * kPlanBatch) {
         // ---- the candidates: their lists, then every load in flight at once
         int at[kPlanBatch], ks[kPlanBatch], s0v[kPlanBatch], nsv[kPlanBatch], lv[kPlanBatch];
@@ -420,75 +427,61 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
             }
             const unsigned long long mh = __ballot(ph);
             const int r = nh + lane_rank_s(mh);
-            if (ph && r < B - A) {
-                sp.hole[(int64_t)A + r] = slot;
-                if (r < kPlanLdsHoles) s_hole[wv][r] = slot;
-            }
+            if (ph && r < B - A) sp.hole[(int64_t)A + r] = slot;
             nh += __popcll(mh);
-            nhead += __popcll(__ballot(ph && L == 0));
-            ntail += __popcll(__ballot(ph && L == W + 1));
+            if (mh != 0ull)
+                for (int w = 0; w < W; ++w) {
+                    const int lo_w = __builtin_amdgcn_readlane(wlo_mine, w);
+                    const int c = __popcll(__ballot(ph && slot < lo_w));
+                    if (lane == w) fb += c;
+                }
             const unsigned long long mm = __ballot(pm);
             rr[u] = nm + lane_rank_s(mm);
             if (pm && rr[u] < B - A) mvf |= 1u << u;
             if (fl) flf |= 1u << u;
             nm += __popcll(mm);
         }
-        // the hole slots written above are read back below (LDS; global
-        // memory past the LDS share)
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (nh > kPlanLdsHoles) __threadfence_block();
         if (__ballot(mvf != 0) == 0ull) continue;
-        // ---- the movers' holes and data, every load in flight at once;
-        // staged (the head and tail of the holes), or straight into one of
-        // t's leaver slots
-        int to[kPlanBatch];
+        // ---- the movers' data, every load in flight at once, then staged in
+        // hole order (contiguous stores)
         Chunk6 dv[kPlanBatch];
 #pragma unroll
-        for (int u = 0; u < kPlanBatch; ++u) {
-            to[u] = 0;
-            if (mvf >> u & 1u) {
-                const int r = rr[u];
-                const bool staged = r < nhead || r >= nh - ntail;
-                to[u] = staged ? A + r : (r < kPlanLdsHoles ? s_hole[wv][r] : sp.hole[(int64_t)A + r]);
-                dv[u] = flf >> u & 1u ? load_leaver(sp.lrec, at[u]) : load_parts(sp.p, at[u]);
-            }
-        }
+        for (int u = 0; u < kPlanBatch; ++u)
+            if (mvf >> u & 1u) dv[u] = flf >> u & 1u ? load_leaver(sp.lrec, at[u]) : load_parts(sp.p, at[u]);
 #pragma unroll
-        for (int u = 0; u < kPlanBatch; ++u) {
+        for (int u = 0; u < kPlanBatch; ++u)
             if (mvf >> u & 1u) {
-                const int r = rr[u];
-                const bool staged = r < nhead || r >= nh - ntail;
-                store_parts(staged ? sp.stg : sp.p, to[u], dv[u]);
+                const Chunk6 &c = dv[u];
+                put_leaver(sp.srec, (int64_t)A + rr[u], c.cell, c.x, c.y, c.ux, c.uy, c.uz);
             }
-        }
     }
 
     const bool anybad = __ballot(bad) != 0ull;
+    const int m = min(min(nh, nm), B - A);   // holes and movers agree unless the records were corrupt
     if (lane == 0) {
         if (nh != nm || anybad) atomicOr(a.err, kErrSort);
-        const int m = min(nh, nm);
         sp.mcount[t] = m;
-        sp.mcount[a.n_tiles + t] = min(nhead, m);
-        sp.mcount[2 * a.n_tiles + t] = min(ntail, m - min(nhead, m));
+        sp.fcount[t] = a.defer ? m : 0;
     }
+    if (a.defer && lane < W) sp.fbase[(int64_t)t * W + lane] = min(fb, m);
 }
 
-// Step (5): the staged movers of each tile (the head and the tail of its
-// holes: contiguous runs of slots) into their holes; the new tile_offset
-// replaces the old one (all plans have read the old one).
+// Step (5): the staged movers of each tile into its holes (unless the sort
+// is deferred: then the next push fills them as it streams the section);
+// the new tile_offset replaces the old one (all plans have read the old one).
 __device__ __forceinline__ void sort_scatter_unit(const SortArgs &a, int spi, int grp)
 {
     const int lane = threadIdx.x & 63;
     const int t = grp * kSortWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (t >= a.n_tiles) return;
     const SortSpecies &sp = a.sp[spi];
-    const int A = sp.offn[t], m = sp.mcount[t];
-    const int head = sp.mcount[a.n_tiles + t], tail = sp.mcount[2 * a.n_tiles + t];
-    for (int k = lane; k < head + tail; k += 64) {
-        const int64_t r = (int64_t)A + (k < head ? k : m - tail + (k - head));
-        copy_particle(sp.stg, r, sp.p, sp.hole[r]);
+    const int A = sp.offn[t];
+    if (!a.defer) {
+        const int m = sp.mcount[t];
+        for (int k = lane; k < m; k += 64) {
+            const int64_t r = (int64_t)A + k;
+            store_parts(sp.p, sp.hole[r], load_leaver(sp.srec, r));
+        }
     }
     if (lane == 0) {
         sp.off[t] = A;
@@ -671,6 +664,24 @@ __device__ __forceinline__ void motion_copy_unit(const SortArgs &a, int spi, int
 __global__ void __launch_bounds__(kScanBlock) k_sort_count(SortArgs a) { sort_count_unit(a, blockIdx.y, blockIdx.x); }
 __global__ void __launch_bounds__(1024) k_sort_scan_blocks(SortArgs a) { sort_scan_unit(a, blockIdx.x); }
 __global__ void __launch_bounds__(kScanBlock) k_sort_add_base(SortArgs a) { sort_add_unit(a, blockIdx.y, blockIdx.x); }
+// A fill left pending by a deferred sort, done on its own (before anything
+// reads the particle arrays other than a push): tile t's fcount[t] staged
+// movers into its holes, as the next push would, and fcount[t] back to 0.
+__device__ __forceinline__ void fill_unit(const SortArgs &a, int spi, int grp)
+{
+    const int lane = threadIdx.x & 63;
+    const int t = grp * kSortWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (t >= a.n_tiles) return;
+    const SortSpecies &sp = a.sp[spi];
+    const int A = sp.off[t], m = sp.fcount[t];
+    for (int k = lane; k < m; k += 64) {
+        const int64_t r = (int64_t)A + k;
+        store_parts(sp.p, sp.hole[r], load_leaver(sp.srec, r));
+    }
+    if (lane == 0 && m != 0) sp.fcount[t] = 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill(SortArgs a) { fill_unit(a, blockIdx.y, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_sort_plan(SortArgs a) { sort_plan_unit(a, blockIdx.y, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_sort_scatter(SortArgs a) { sort_scatter_unit(a, blockIdx.y, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_motion_scatter(SortArgs a) { motion_scatter_unit(a, blockIdx.y, blockIdx.x); }
@@ -701,6 +712,11 @@ __global__ void __launch_bounds__(kBlock) k_sort_scatter_b(const SortArgs *d, co
 {
     const int4 w = it[blockIdx.x];
     sort_scatter_unit(d[w.x], w.y, w.z);
+}
+__global__ void __launch_bounds__(kBlock) k_fill_b(const SortArgs *d, const int4 *it)
+{
+    const int4 w = it[blockIdx.x];
+    fill_unit(d[w.x], w.y, w.z);
 }
 
 __global__ void __launch_bounds__(kBlock) k_motion_scatter_b(const SortArgs *d, const int4 *it)
@@ -771,6 +787,16 @@ void launch_sort_scatter(const SortArgs &a, int n_tiles, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sort_scatter, dim3((n_tiles + kSortWaves - 1) / kSortWaves, a.n_species), dim3(kBlock), 0,
                        s, a);
+}
+
+void launch_fill(const SortArgs &a, int n_tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill, dim3((n_tiles + kSortWaves - 1) / kSortWaves, a.n_species), dim3(kBlock), 0, s, a);
+}
+
+void launch_fill_batch(const SortBatch &b, hipStream_t s)
+{
+    if (b.n_plan > 0) hipLaunchKernelGGL(k_fill_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
 }
 
 void launch_sort_batch(const SortBatch &b, bool motion, hipStream_t s)

@@ -24,7 +24,7 @@ struct Layout {
     size_t wrem = 0, inj_off[kMaxSpecies] = {};
     size_t off[kMaxSpecies][2] = {}, cnt[kMaxSpecies] = {}, leav[kMaxSpecies] = {};
     size_t hole[kMaxSpecies] = {}, stg[kMaxSpecies][6] = {}, mcount[kMaxSpecies] = {}, bsum[kMaxSpecies] = {};
-    size_t lrec[kMaxSpecies] = {};
+    size_t lrec[kMaxSpecies] = {}, srec[kMaxSpecies] = {}, fcount[kMaxSpecies] = {}, fbase[kMaxSpecies] = {};
     size_t total = 0;
 };
 
@@ -125,8 +125,15 @@ Layout make_layout(const pic_config *c)
         // arrays of n values (lp_view)
         L.lrec[s] = take(n * sizeof(LeaverRec) + 6 * kAlign);
         L.hole[s] = take(n * sizeof(int32_t));
-        for (int k = 0; k < 6; ++k) L.stg[s][k] = take(n * 4);
-        L.mcount[s] = take((size_t)3 * n_tiles * sizeof(int32_t));   // movers, staged head and tail
+        // mover staging: the in-place sort's 32-byte records (every
+        // simulation: the moving window's sort is the in-place one; also the
+        // initial grouping's scratch), and the motion-class sort's six arrays
+        L.srec[s] = take(n * sizeof(LeaverRec));
+        if (c->flags & PIC_FLAG_MOTION_SORT)
+            for (int k = 0; k < 6; ++k) L.stg[s][k] = take(n * 4);
+        L.mcount[s] = take((size_t)3 * n_tiles * sizeof(int32_t));   // movers (motion sort: class bases)
+        L.fcount[s] = take((size_t)n_tiles * sizeof(int32_t));       // pending fill per tile
+        L.fbase[s] = take((size_t)n_tiles * push_waves(T) * sizeof(int32_t));
         L.bsum[s] = take((size_t)(n_tiles / kScanBlock + 1) * sizeof(int32_t));
     }
     L.total = p;
@@ -166,10 +173,13 @@ struct pic_sim {
         int32_t *cnt;
         uint32_t *leav;
         int32_t *hole;
-        Parts stg;
+        Parts stg;         // the motion-class sort's staging (null without PIC_FLAG_MOTION_SORT)
+        LeaverRec *srec;   // the in-place sort's mover staging (every simulation)
         LeaverRec *lrec;   // the push's leaver records
         Parts lp;          // the same memory as six arrays of n values (full re-sort scratch)
         int32_t *mcount;
+        int32_t *fcount;   // holes whose fill a deferred sort left to the next push
+        int32_t *fbase;
         int32_t *bsum;
         int32_t *inj_off;   // moving window: tile offsets of the new particles
     } sp[kMaxSpecies];
@@ -419,6 +429,10 @@ PushArgs push_args(const pic_sim *S, bool bh)
         d.cnt = S->sp[s].cnt;
         d.leav = S->sp[s].leav;
         d.lrec = S->sp[s].lrec;
+        d.fcount = S->sp[s].fcount;
+        d.fbase = S->sp[s].fbase;
+        d.fhole = S->sp[s].hole;
+        d.fsrc = S->sp[s].srec;
         d.n = (int32_t)c.species[s].n;
         d.h = (float)(0.5 * c.species[s].qm * c.dt);
         d.fq = (float)(scale * c.species[s].q / qmax);
@@ -456,12 +470,13 @@ JReduceArgs jreduce_args(const pic_sim *S)
     return r;
 }
 
-SortArgs sort_args(const pic_sim *S)
+SortArgs sort_args(const pic_sim *S, bool defer = false)
 {
     const pic_config &c = S->cfg;
     SortArgs a;
     memset(&a, 0, sizeof(a));
     a.err = S->err;
+    a.defer = defer ? 1 : 0;
     a.nx = c.nx;
     a.ny = c.ny;
     a.ntx = S->ntx;
@@ -481,12 +496,15 @@ SortArgs sort_args(const pic_sim *S)
         d.p.uz = p.uz;
         d.lrec = P.lrec;
         d.stg = P.stg;
+        d.srec = P.srec;
         d.off = P.off;
         d.offn = P.offn;
         d.cnt = P.cnt;
         d.leav = P.leav;
         d.hole = P.hole;
         d.mcount = P.mcount;
+        d.fcount = P.fcount;
+        d.fbase = P.fbase;
         d.bsum = P.bsum;
         d.n = (int32_t)c.species[s].n;
         d.inj_off = nullptr;
@@ -572,8 +590,9 @@ TileSortArgs tile_sort_args(pic_sim *S, int s)
     t.tmp = P.lp;
     t.key[0] = (uint32_t *)P.hole;
     t.key[1] = P.leav;
-    t.val[0] = (uint32_t *)P.stg.cell;
-    t.val[1] = (uint32_t *)P.stg.x;
+    // scratch: the in-place sort's staging records (8 n words)
+    t.val[0] = (uint32_t *)P.srec;
+    t.val[1] = (uint32_t *)P.srec + n;
     t.hist = tile_sort_hist_entries(n) <= n ? P.lp.cell : (int32_t *)S->jtile;
     t.n = n;
     t.tile = S->cfg.tile;
@@ -607,6 +626,7 @@ int build_tiles(pic_sim *S, hipStream_t stream)
             rc = hip_ok(hipGetLastError());
         }
         if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(P.mcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
+        if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(P.fcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
     }
     if (rc == PIC_OK) rc = read_errors(S, stream);
     return rc;
@@ -685,7 +705,9 @@ int init_sim(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
             q.uz = (float *)(w + o[5]);
             return q;
         };
-        P.stg = parts_at(L.stg[s]);
+        const bool motion = (cfg->flags & PIC_FLAG_MOTION_SORT) != 0;
+        P.stg = motion ? parts_at(L.stg[s]) : Parts{};
+        P.srec = (LeaverRec *)(w + L.srec[s]);
         P.lrec = (LeaverRec *)(w + L.lrec[s]);
         {
             size_t o[6];
@@ -694,6 +716,8 @@ int init_sim(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
             P.lp = parts_at(o);
         }
         P.mcount = (int32_t *)(w + L.mcount[s]);
+        P.fcount = (int32_t *)(w + L.fcount[s]);
+        P.fbase = (int32_t *)(w + L.fbase[s]);
         P.bsum = (int32_t *)(w + L.bsum[s]);
         P.inj_off = window ? (int32_t *)(w + L.inj_off[s]) : nullptr;
         S->cap[s] = cfg->species[s].cap ? cfg->species[s].cap : cfg->species[s].n;
@@ -811,13 +835,14 @@ static int motion_sort(pic_sim *S, hipStream_t stream)
     return hip_ok(hipGetLastError());
 }
 
-int pic_sort(pic_sim *S, hipStream_t stream)
+// The sort after a push; defer: the in-place sort leaves its hole fill to
+// the next push (pic_step), which streams those slots anyway.
+static int sort_after_push(pic_sim *S, hipStream_t stream, bool defer)
 {
-    if (!S) return PIC_EINVAL;
     if (S->since_sort == 0) return PIC_OK;   // already sorted: the count records are spent
     S->since_sort = 0;
     if (S->cfg.flags & PIC_FLAG_MOTION_SORT) return motion_sort(S, stream);
-    const SortArgs a = sort_args(S);
+    const SortArgs a = sort_args(S, defer);
     {
         Timed t(S, PIC_KERNEL_SORT_SCAN, stream);
         launch_sort_scan(a, S->n_tiles, stream);
@@ -833,6 +858,28 @@ int pic_sort(pic_sim *S, hipStream_t stream)
     return hip_ok(hipGetLastError());
 }
 
+// A fill left pending by pic_step's sort, done before anything but a push
+// reads the particle arrays.  Always launched: the device fill counts, not
+// the host, know whether a fill is pending (replays of a captured step run
+// no host code); a tile with none costs one read.
+static int settle(pic_sim *S, hipStream_t stream)
+{
+    launch_fill(sort_args(S), S->n_tiles, stream);
+    return hip_ok(hipGetLastError());
+}
+
+int pic_sort(pic_sim *S, hipStream_t stream)
+{
+    if (!S) return PIC_EINVAL;
+    return sort_after_push(S, stream, false);
+}
+
+int pic_sync(pic_sim *S, hipStream_t stream)
+{
+    if (!S) return PIC_EINVAL;
+    return settle(S, stream);
+}
+
 int pic_field_advance(pic_sim *S, hipStream_t stream)
 {
     if (!S) return PIC_EINVAL;
@@ -845,6 +892,7 @@ int pic_move_window(pic_sim *S, const pic_particles *inject, const int64_t *n_in
 {
     if (!S || !(S->cfg.flags & PIC_FLAG_MOVING_WINDOW)) return PIC_EINVAL;
     if (S->since_sort != 0) return PIC_EORDER;   // the last push is not sorted yet
+    if (const int rs = settle(S, stream)) return rs;
     pic_config &c = S->cfg;
     int64_t k[kMaxSpecies] = {};
     for (int s = 0; s < c.n_species; ++s) {
@@ -932,6 +980,7 @@ int pic_solve_gauss(pic_sim *S, void *work, size_t work_bytes, double tol, int m
 {
     if (!S || !work || ((uintptr_t)work) % kAlign) return PIC_EINVAL;
     if (work_bytes < PIC_GAUSS_SCRATCH_BYTES(S->cfg.nx, S->cfg.ny)) return PIC_EINVAL;
+    if (const int rs = settle(S, stream)) return rs;   // the density reads the particles
     return solve_gauss_in(S, (double *)work, tol, max_iter, out, stream);
 }
 
@@ -945,6 +994,7 @@ int pic_solve_gauss_noalloc(pic_sim *S, double tol, int max_iter, pic_gauss_out 
     if (dev != S->device) return PIC_EINVAL;
     void *p = nullptr;
     rc = scratch_address(dev, &p);
+    if (rc == PIC_OK) rc = settle(S, stream);   // the density reads the particles
     if (rc) return rc;
     return solve_gauss_in(S, (double *)p, tol, max_iter, out, stream);
 }
@@ -963,7 +1013,7 @@ int pic_step(pic_sim *S, hipStream_t stream)
     if (rc) return rc;
     // Unforked: no sort this step, or no second stream
     if (S->since_sort < S->halo || !S->side) {
-        if (S->since_sort >= S->halo) rc = pic_sort(S, stream);
+        if (S->since_sort >= S->halo) rc = sort_after_push(S, stream, true);
         if (rc == PIC_OK) rc = field_half(S, stream);
         return rc;
     }
@@ -978,7 +1028,7 @@ int pic_step(pic_sim *S, hipStream_t stream)
     if (rc) return rc;
     int rf = field_half(S, S->side);
     const int rj = hip_ok(hipEventRecord(S->ev_join, S->side));
-    rc = pic_sort(S, stream);
+    rc = sort_after_push(S, stream, true);
     // the join is enqueued whatever happened above, so the caller's stream
     // never runs ahead of work already on the second stream
     const int rw = rj == PIC_OK ? hip_ok(hipStreamWaitEvent(stream, S->ev_join, 0)) : rj;
@@ -998,7 +1048,8 @@ int pic_diag(pic_sim *S, unsigned what, pic_diag_out *out, hipStream_t stream)
     const pic_config &c = S->cfg;
     const int64_t plane = (int64_t)c.nx * c.ny;
     if ((what & PIC_DIAG_CONTINUITY) && !S->have_snapshot) return PIC_EINVAL;
-    int rc = hip_ok(hipMemsetAsync(S->dacc, 0, 32 * sizeof(double), stream));
+    int rc = settle(S, stream);
+    if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(S->dacc, 0, 32 * sizeof(double), stream));
     if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(S->cacc, 0, 8 * sizeof(unsigned long long), stream));
     if (rc) return rc;
     if (what & PIC_DIAG_ENERGY) {
@@ -1083,7 +1134,7 @@ int pic_get_state(pic_sim *S, pic_host_state *out, hipStream_t stream)
 {
     if (!S || !out) return PIC_EINVAL;
     const size_t fbytes = 9 * sizeof(float) * (size_t)S->cfg.nx * S->cfg.ny;
-    int rc = PIC_OK;
+    int rc = settle(S, stream);
     if (out->fields) rc = hip_ok(hipMemcpyAsync(out->fields, S->buf.fields, fbytes, hipMemcpyDeviceToHost, stream));
     for (int s = 0; s < S->cfg.n_species && rc == PIC_OK; ++s) rc = copy_particles(S, s, out->sp[s], true, stream);
     if (rc == PIC_OK) rc = hip_ok(hipStreamSynchronize(stream));
@@ -1394,7 +1445,7 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
         const pic_sim *S = B->sims[i];
         hp[i] = push_args(S, true);
         hj[i] = jreduce_args(S);
-        hs[i] = sort_args(S);
+        hs[i] = sort_args(S, !(S->cfg.flags & PIC_FLAG_MOTION_SORT));
         hf[i] = field_args(S, S->cfg.j_filter == 0, true);
         hfl[i] = filter_args(S, 0);
         hfl[n + i] = filter_args(S, 1);
@@ -1492,6 +1543,21 @@ pic_sim *pic_batch_sim(pic_batch *B, int i)
 {
     if (!B || i < 0 || i >= (int)B->sims.size()) return nullptr;
     return B->sims[i];
+}
+
+int pic_batch_sync(pic_batch *B, hipStream_t stream)
+{
+    if (!B) return PIC_EINVAL;
+    SortBatch sb;
+    sb.descs = B->d_sort;
+    sb.count_items = B->count_items;
+    sb.n_count = B->n_count;
+    sb.scan_items = B->scan_items;
+    sb.n_scan = B->n_scan;
+    sb.plan_items = B->plan_items;
+    sb.n_plan = B->n_plan;
+    launch_fill_batch(sb, stream);   // members without a pending fill have zero fill counts
+    return hip_ok(hipGetLastError());
 }
 
 int pic_batch_check(pic_batch *B, hipStream_t stream)

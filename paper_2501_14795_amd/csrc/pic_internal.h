@@ -13,13 +13,16 @@ namespace pic {
 struct SortSpecies {
     Parts p;              // the particle arrays
     const LeaverRec *lrec;   // leaver particle data written by the push kernel
-    Parts stg;            // mover staging, [n]: tile t's movers at offn[t] + k
+    Parts stg;            // the motion-class sort's staging, [n]: every particle at its new slot
+    LeaverRec *srec;      // the in-place sort's mover staging, [n]: tile t's movers at offn[t] + k, in hole order
     int32_t *off;         // tile_offset: read by the plan, replaced by the new one in the scatter
     int32_t *offn;        // new tile_offset (scratch)
     const int32_t *cnt;
     const uint32_t *leav;
     int32_t *hole;        // [n]: tile t's holes, ascending, at offn[t] + k
-    int32_t *mcount;      // [3][n_tiles]: movers; staged movers at the head and at the tail of the holes
+    int32_t *mcount;      // [n_tiles]: movers (the motion-class sort: [3][n_tiles] class bases)
+    int32_t *fcount;      // [n_tiles]: holes whose fill is pending (the next push fills them), else 0
+    int32_t *fbase;       // [n_tiles][W]: first pending hole of each push wavefront's run
     int32_t *bsum;        // [n_tiles / kScanBlock + 1] block totals of the tile scan
     int32_t n;            // particles before the sort
     // moving window (else null / 0): new particles appended at slots
@@ -35,6 +38,7 @@ struct SortArgs {
     int nx, ny, ntx, nty, tile;
     int n_tiles;
     int n_species;
+    int defer;            // 1: the scatter leaves the holes to the next push (pic_step)
     SortSpecies sp[kMaxSpecies];
 };
 
@@ -70,6 +74,7 @@ void launch_set_int(int *p, int v, hipStream_t s);
 void launch_sort_scan(const SortArgs &a, int n_tiles, hipStream_t s);
 void launch_sort_plan(const SortArgs &a, int n_tiles, hipStream_t s);
 void launch_sort_scatter(const SortArgs &a, int n_tiles, hipStream_t s);
+void launch_fill(const SortArgs &a, int n_tiles, hipStream_t s);
 
 // Batched sort phases.  Work tables (int4 per block):
 //   count/add: (sim, species, block of kScanBlock tiles)   scan: (sim, species)
@@ -80,6 +85,8 @@ struct SortBatch {
     const int4 *scan_items; int n_scan;
     const int4 *plan_items; int n_plan;
 };
+// a pending hole fill of every member (fill_unit)
+void launch_fill_batch(const SortBatch &b, hipStream_t s);
 // motion: the motion-class sort (PIC_FLAG_MOTION_SORT) instead of the in-place one
 void launch_sort_batch(const SortBatch &b, bool motion, hipStream_t s);
 // the motion-class sort after the recount and scan: every particle into the

@@ -98,7 +98,7 @@ constexpr int push_lds_bytes(int T, int R, int JM, int H = 1)
     return (T + 2 * H) * (T + 2 * H) * (push_packed(T) ? 48 : 24) +
            R * 3 * (T + 2 * H + 1) * (T + 2 * H + 1) * (JM == kJFixed ? 8 : 4) +
            kMaxSpecies * (9 + push_waves(T)) * 4 + push_waves(T) * 6 * kMotionBuf * 4 +
-           (push_packed(T) ? push_waves(T) * 7 * kLeaverBuf * 4 : 0);
+           (push_packed(T) ? push_waves(T) * 7 * kLeaverBuf * 4 : 0) + push_waves(T) * 64 * 4;
 }
 
 // Sort cadences the push kernel is built for: every 1, 2 or 4 steps, with
@@ -157,6 +157,13 @@ struct SpeciesDev {
     int32_t *cnt;         // [n_tiles][kCntStride]
     uint32_t *leav;       // [n]: leaver sub-lists, (slot - off[t]) << 4 | direction
     LeaverRec *lrec;      // [n]: the leavers' new particle data, same positions as leav
+    // a fill left by the last sort: tile t's fcount[t] holes, slots fhole[off[t] + r]
+    // ascending, take the staged particles fsrc[off[t] + r]; wavefront w's first
+    // is rank fbase[t W + w].  The push zeroes fcount[t].
+    int32_t *fcount;
+    const int32_t *fbase;
+    const int32_t *fhole;
+    const LeaverRec *fsrc;
     int32_t n;
     float h;              // (q/m) dt / 2
     float fq;             // charge in accumulator units: q / max|q| (x kFixedScale in fixed mode)

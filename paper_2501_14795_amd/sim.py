@@ -128,6 +128,11 @@ class _SimView:
     def field_advance(self):
         _lib.pic_field_advance(self.handle, self.s)
 
+    def sync(self):
+        """Complete a hole fill that step()'s sort left to the next push
+        (pic_sync), so the particle tensors hold the sorted state."""
+        _lib.pic_sync(self.handle, self.s)
+
     def step(self):
         _lib.pic_step(self.handle, self.s)
 
@@ -196,6 +201,7 @@ class _SimView:
         _lib.pic_move_window(self.handle, arr, cnt, self.s)
 
     def state(self, species: int = 0) -> Dict[str, np.ndarray]:
+        self.sync()
         self.stream.synchronize()
         p = self.particles[species]
         n = self.counts()[species]
@@ -364,6 +370,10 @@ class Batch:
 
     def check(self) -> int:
         return _lib.pic_batch_check(self.handle, self.stream.cuda_stream)
+
+    def sync(self):
+        """pic_sync for every member in one launch (pic_batch_sync)."""
+        _lib.pic_batch_sync(self.handle, self.stream.cuda_stream)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -37,6 +37,7 @@ def time_batch(batch, steps: int) -> float:
     batch.stream.synchronize()
     t0 = time.perf_counter()
     batch.step(steps)
+    batch.sync()   # the last sort's hole fill, which the next push would do
     batch.stream.synchronize()
     return (time.perf_counter() - t0) / steps
 

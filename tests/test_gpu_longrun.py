@@ -68,6 +68,7 @@ def test_langmuir_long_run_full_size():
                 flush(f"step {n}: U = {energy[n]:.6e}, oracle (x{area:.0f}) {ref[n][0] * area:.6e}, "
                       f"ratio {energy[n] / (ref[n][0] * area):.6f}")
     assert sim.check() == 0
+    sim.sync()   # the particle tensors are read directly below
     assert sim.fields[3:6].abs().max().item() == 0.0
     assert sim.particles[0]["uy"].abs().max().item() == 0.0
     assert sim.fields[0].std(dim=0).max().item() == 0.0
