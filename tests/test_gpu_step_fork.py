@@ -6,7 +6,9 @@ separate entry points (pic_push_deposit, pic_sort, pic_field_advance, all on
 one stream) must hold bit-identical fields, particles and tile offsets after
 every step -- on the default stream and on a caller stream, with the filter,
 with a sort cadence of 2 (whose unsorted steps take the unforked path), and
-with the motion-class sort, also for a species of only 144 particles."""
+with the motion-class sort, also for a species of only 144 particles.  The
+forked simulation's particles are read through state(), which completes the
+hole fill its sort left to the next push (pic_sync)."""
 import numpy as np
 import pytest
 
