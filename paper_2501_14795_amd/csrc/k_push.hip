@@ -586,11 +586,14 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                 fhw = fhb + lane < nfill ? fhole[fhb + lane] : INT_MAX;
             }
             // the rank of the hole at slot c0 + lane (chunks in ascending
-            // order), or -1; a chunk without holes costs one compare
-            auto fill_ref = [&](int c0) -> int {
+            // order), or -1; `any` (uniform): the chunk has a hole.  A chunk
+            // without holes costs one compare
+            auto fill_ref = [&](int c0, bool &any) -> int {
+                any = false;
                 if (fhp >= nfill) return -1;
                 const int lim = min(c0 + 64, hi);
                 if (__builtin_amdgcn_readlane(fhw, fhp - fhb) >= lim) return -1;
+                any = true;
                 int *map = s_fill[wave];
                 map[lane] = -1;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -687,10 +690,11 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             int off = (cb + lane - base) * 4;
             Chunk nxt[C], nstg[C];
             int nref[C];
+            bool nany[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
                 nxt[c] = load_chunk(st, off + 256 * c);
-                nref[c] = fill_ref(cb + 64 * c);
+                nref[c] = fill_ref(cb + 64 * c, nany[c]);
                 nstg[c] = Chunk{};
                 fill_load(nstg[c], nref[c]);
             }
@@ -699,9 +703,10 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                 Chunk cur[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    cur[c] = nref[c] >= 0 ? nstg[c] : nxt[c];   // a hole: its particle from the fill
+                    cur[c] = nxt[c];
+                    if (nany[c] && nref[c] >= 0) cur[c] = nstg[c];   // a hole: its particle from the fill
                     nxt[c] = load_chunk(st, off + 256 * (C + c));
-                    nref[c] = fill_ref(cb + 64 * (C + c));
+                    nref[c] = fill_ref(cb + 64 * (C + c), nany[c]);
                     fill_load(nstg[c], nref[c]);
                 }
                 const int i = cb + lane;
