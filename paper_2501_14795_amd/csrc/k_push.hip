@@ -574,26 +574,25 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             st.uz = rsrc(sp.uz + base, bytes);
             const float h = sp.h, fq = sp.fq;
             // The fill the last sort left (holes of the section, ascending,
-            // whose particles wait in the staging arrays): a window of 64 of
+            // whose particles wait in the staging records): a window of 64 of
             // this run's hole slots, one per lane (fhw: the slot of rank
-            // fhb + lane), and the next rank not yet placed (fhp).  All uniform
-            // but fhw.
+            // fhb + lane), the next rank not yet placed (fhp) and its slot
+            // (fnext, INT_MAX once none is left).  All uniform but fhw.
             const int nfill = gp(sp.fcount)[tile];
             const PIC_GLOBAL int32_t *fhole = gp(sp.fhole) + begin;
-            int fhb = 0, fhp = 0, fhw = INT_MAX;
+            int fhb = 0, fhp = 0, fhw = INT_MAX, fnext = INT_MAX;
             if (nfill > 0) {
                 fhb = fhp = gp(sp.fbase)[(int64_t)tile * W + wave];
                 fhw = fhb + lane < nfill ? fhole[fhb + lane] : INT_MAX;
+                fnext = fhp < nfill ? __builtin_amdgcn_readfirstlane(fhw) : INT_MAX;
             }
             // the rank of the hole at slot c0 + lane (chunks in ascending
             // order), or -1; `any` (uniform): the chunk has a hole.  A chunk
             // without holes costs one compare
             auto fill_ref = [&](int c0, bool &any) -> int {
-                any = false;
-                if (fhp >= nfill) return -1;
                 const int lim = min(c0 + 64, hi);
-                if (__builtin_amdgcn_readlane(fhw, fhp - fhb) >= lim) return -1;
-                any = true;
+                any = fnext < lim;
+                if (!any) return -1;
                 int *map = s_fill[wave];
                 map[lane] = -1;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -606,8 +605,9 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                     if (fhp - fhb < 64 || fhp >= nfill) break;
                     fhb = fhp;   // the window is used up: the next one
                     fhw = fhb + lane < nfill ? fhole[fhb + lane] : INT_MAX;
-                    if (__builtin_amdgcn_readlane(fhw, 0) >= lim) break;
+                    if (__builtin_amdgcn_readfirstlane(fhw) >= lim) break;
                 }
+                fnext = fhp < nfill ? __builtin_amdgcn_readlane(fhw, fhp - fhb) : INT_MAX;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
