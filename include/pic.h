@@ -287,12 +287,14 @@ int pic_get_counts(pic_sim *sim, int64_t *counts);
 
 /* pic_push_deposit + pic_sort (every sort_every-th step) + pic_field_advance,
  * with the same results once the sort's hole fill is done: the next push
- * does it, or pic_sync() (see the memory model).  In a step that sorts, the field half (J fold,
- * filter, field advance) runs on the library's own stream beside the sort:
- * forked from `stream` after the push with an event and joined back into
- * `stream` before the call returns, so everything the caller enqueues on
- * `stream` afterwards sees the whole step (the full re-sort stays on
- * `stream`).  Issues kernels and event records/waits only (no memset, no
+ * does it, or pic_sync() (see the memory model).  The push also forms the
+ * field advance's first B half step for its tile (into workspace planes), so
+ * the field half is the E step and the second half step.  In a step that
+ * sorts, the field half (J fold, filter, field advance) runs on the
+ * library's own stream beside the sort: forked from `stream` after the push
+ * with an event and joined back into `stream` before the call returns, so
+ * everything the caller enqueues on `stream` afterwards sees the whole step.
+ * Issues kernels and event records/waits only (no memset, no
  * synchronisation), so a caller may capture it into a HIP graph; with
  * sort_every > 1 the captured step keeps the sort decision taken at capture
  * time. */
