@@ -161,7 +161,7 @@ def stream_probe(n=1 << 26, launches=20):
     return out
 
 
-def batched_comparison(n_sims=256, steps=5, tune_sims=32):
+def batched_comparison(n_sims=256, steps=20, tune_sims=32):
     """The batched workload (256 independent simulations, grids 32..256
     cells, 8..64 ppc): the autotuner picks tile size x replicas x sort
     cadence on the first tune_sims members, then the full batch runs as
