@@ -271,12 +271,12 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
 
     // ---------------- list bounds: every load of this stage in flight at once
     const int nl_mov = 9 * W;
-    int srcv[2], wv_[2];
+    int srcv[2], subl[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int v = lane + 64 * h;
         const int q = v >= W + 2 && v < W + 2 + nl_mov ? (v - W - 2) / W : -1;
-        wv_[h] = v >= W + 2 ? (v - W - 2) % W : v - 1;   // sub-list index (movers; holes: v - 1)
+        subl[h] = v >= W + 2 ? (v - W - 2) % W : v - 1;   // sub-list index (movers; holes: v - 1)
         srcv[h] = source_of_rank(q);
     }
     const int A = sp.offn[t], B = sp.offn[t + 1];
@@ -287,7 +287,7 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
         const int v = lane + 64 * h;
         // hole sub-lists read t's record, mover sub-lists their source's (index 0 when unused)
         const int s = v >= 1 && v <= W ? t : (srcv[h] >= 0 ? srcv[h] : 0);
-        const int w = v >= 1 && v <= W ? v - 1 : (srcv[h] >= 0 ? wv_[h] : 0);
+        const int w = v >= 1 && v <= W ? v - 1 : (srcv[h] >= 0 ? subl[h] : 0);
         f0[h] = sp.off[s];
         f1[h] = sp.off[s + 1];
         fc[h] = sp.cnt[(int64_t)s * kCntStride + kCntSub + w];
@@ -318,7 +318,7 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
             len = max(0, B - base);
         } else if (v < W + 2 + nl_mov) {
             src = srcv[h];
-            const int w = wv_[h];
+            const int w = subl[h];
             kind = kListMoverRange;
             if (src == t) {
                 if (w == 0) {
