@@ -79,7 +79,8 @@ __device__ __forceinline__ int tile_count_in(const int32_t *cnt, int t, int ntx,
 }
 
 // Step (1), first pass: new count of every tile and its exclusive prefix
-// within its block of kScanBlock tiles; block totals to bsum.
+// within its block of kScanBlock tiles, in place of tile_offset (which goes
+// to offp, the plan's old sections); block totals to bsum.
 __device__ __forceinline__ void sort_count_unit(const SortArgs &a, int spi, int blk)
 {
     const SortSpecies &sp = a.sp[spi];
@@ -100,7 +101,11 @@ __device__ __forceinline__ void sort_count_unit(const SortArgs &a, int spi, int 
     __syncthreads();
     int base = 0;
     for (int k = 0; k < w; ++k) base += s_w[k];
-    if (t < n_tiles) sp.offn[t] = base + x - c;
+    if (t < n_tiles) {
+        sp.offp[t] = sp.off[t];
+        sp.off[t] = base + x - c;
+    }
+    if (t == n_tiles - 1) sp.offp[n_tiles] = sp.off[n_tiles];
     if (threadIdx.x == kScanBlock - 1) sp.bsum[blk] = base + x;
 }
 
@@ -122,7 +127,7 @@ __device__ __forceinline__ void sort_scan_unit(const SortArgs &a, int spi)
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        sp.offn[n_tiles] = carry;
+        sp.off[n_tiles] = carry;
         const int expect = sp.removed ? sp.n - *sp.removed + sp.inj_n : sp.n;
         if (carry != expect) atomicOr(a.err, kErrCount);
     }
@@ -133,7 +138,37 @@ __device__ __forceinline__ void sort_add_unit(const SortArgs &a, int spi, int bl
 {
     const SortSpecies &sp = a.sp[spi];
     const int t = blk * kScanBlock + threadIdx.x;
-    if (t < a.n_tiles) sp.offn[t] += sp.bsum[blk];
+    if (t < a.n_tiles) sp.off[t] += sp.bsum[blk];
+}
+
+// Step (1), second and third pass in one, while there are at most
+// kScanDirect blocks: each block sums its predecessors' totals itself and
+// adds them; the last one also writes tile_offset'[n_tiles] and checks it.
+constexpr int kScanDirect = 64;
+static_assert(kScanDirect <= kScanBlock, "one predecessor total per thread");
+__device__ __forceinline__ void sort_add_direct_unit(const SortArgs &a, int spi, int blk)
+{
+    const SortSpecies &sp = a.sp[spi];
+    const int n_tiles = a.n_tiles;
+    const int nb = (n_tiles + kScanBlock - 1) / kScanBlock;
+    __shared__ int s_w[kScanBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int v = (int)threadIdx.x < blk ? sp.bsum[threadIdx.x] : 0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (lane == 0) s_w[w] = v;
+    __syncthreads();
+    int base = 0;
+#pragma unroll
+    for (int k = 0; k < kScanBlock / 64; ++k) base += s_w[k];
+    const int t = blk * kScanBlock + threadIdx.x;
+    if (t < n_tiles) sp.off[t] += base;
+    if (blk == nb - 1 && threadIdx.x == 0) {
+        const int total = base + sp.bsum[blk];
+        sp.off[n_tiles] = total;
+        const int expect = sp.removed ? sp.n - *sp.removed + sp.inj_n : sp.n;
+        if (total != expect) atomicOr(a.err, kErrCount);
+    }
 }
 
 // Slot of the list holding flat index k, over the lists described by lanes
@@ -279,8 +314,8 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
         subl[h] = v >= W + 2 ? (v - W - 2) % W : v - 1;   // sub-list index (movers; holes: v - 1)
         srcv[h] = source_of_rank(q);
     }
-    const int A = sp.offn[t], B = sp.offn[t + 1];
-    const int oA = sp.off[t], oB = sp.off[t + 1];
+    const int A = sp.off[t], B = sp.off[t + 1];     // new section
+    const int oA = sp.offp[t], oB = sp.offp[t + 1];  // old section
     int f0[2], f1[2], fc[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -288,8 +323,8 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
         // hole sub-lists read t's record, mover sub-lists their source's (index 0 when unused)
         const int s = v >= 1 && v <= W ? t : (srcv[h] >= 0 ? srcv[h] : 0);
         const int w = v >= 1 && v <= W ? v - 1 : (srcv[h] >= 0 ? subl[h] : 0);
-        f0[h] = sp.off[s];
-        f1[h] = sp.off[s + 1];
+        f0[h] = sp.offp[s];
+        f1[h] = sp.offp[s + 1];
         fc[h] = sp.cnt[(int64_t)s * kCntStride + kCntSub + w];
     }
     int i0 = 0, i1 = 0;
@@ -466,26 +501,19 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
     if (a.defer && lane < W) sp.fbase[(int64_t)t * W + lane] = min(fb, m);
 }
 
-// Step (5): the staged movers of each tile into its holes (unless the sort
-// is deferred: then the next push fills them as it streams the section);
-// the new tile_offset replaces the old one (all plans have read the old one).
+// Step (5): the staged movers of each tile into its holes.  Not launched
+// when the sort is deferred (pic_step): the next push fills them as it
+// streams the section.
 __device__ __forceinline__ void sort_scatter_unit(const SortArgs &a, int spi, int grp)
 {
     const int lane = threadIdx.x & 63;
     const int t = grp * kSortWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (t >= a.n_tiles) return;
     const SortSpecies &sp = a.sp[spi];
-    const int A = sp.offn[t];
-    if (!a.defer) {
-        const int m = sp.mcount[t];
-        for (int k = lane; k < m; k += 64) {
-            const int64_t r = (int64_t)A + k;
-            store_parts(sp.p, sp.hole[r], load_leaver(sp.srec, r));
-        }
-    }
-    if (lane == 0) {
-        sp.off[t] = A;
-        if (t == a.n_tiles - 1) sp.off[t + 1] = sp.offn[t + 1];
+    const int A = sp.off[t], m = sp.mcount[t];
+    for (int k = lane; k < m; k += 64) {
+        const int64_t r = (int64_t)A + k;
+        store_parts(sp.p, sp.hole[r], load_leaver(sp.srec, r));
     }
 }
 
@@ -562,7 +590,7 @@ __device__ __forceinline__ void motion_scatter_unit(const SortArgs &a, int spi, 
         const int s = grp * kSortWaves + q;
         if (s >= a.n_tiles) break;   // uniform over the block
         const int sx = s % ntx, sy = s / ntx;
-        const int oA = sp.off[s], oB = sp.off[s + 1];
+        const int oA = sp.offp[s], oB = sp.offp[s + 1];
         int lo, hi;
         wave_range(oA, oB, w, W, lo, hi);
         // pass 1: lane d counts the run's particles of class d
@@ -585,7 +613,7 @@ __device__ __forceinline__ void motion_scatter_unit(const SortArgs &a, int spi, 
             const int dx = lane % 3 - 1, dy = lane / 3 - 1;
             const int t = wrap_s(sy + dy, nty) * ntx + wrap_s(sx + dx, ntx);
             const int tx = t % ntx, ty = t / ntx;
-            pos = sp.offn[t];
+            pos = sp.off[t];
             for (int d2 = 0; d2 < lane; ++d2) {
                 const int src = wrap_s(ty - (d2 / 3 - 1), nty) * ntx + wrap_s(tx - (d2 % 3 - 1), ntx);
                 pos += sp.cnt[(int64_t)src * kCntStride + d2];
@@ -642,7 +670,7 @@ __device__ __forceinline__ void motion_copy_unit(const SortArgs &a, int spi, int
     const int t0 = grp * kSortWaves;
     if (t0 >= a.n_tiles) return;
     const int t1 = min(t0 + kSortWaves, a.n_tiles);
-    const int A = sp.offn[t0], B = sp.offn[t1];
+    const int A = sp.off[t0], B = sp.off[t1];
     constexpr int U = 4;
     for (int i0 = A + (int)threadIdx.x; i0 < B; i0 += U * kBlock) {
         Part6 v[U];
@@ -653,17 +681,16 @@ __device__ __forceinline__ void motion_copy_unit(const SortArgs &a, int spi, int
         for (int u = 0; u < U; ++u)
             if (i0 + u * kBlock < B) store_part(sp.p, i0 + u * kBlock, v[u]);
     }
-    if ((int)threadIdx.x < t1 - t0) {
-        const int t = t0 + threadIdx.x;
-        sp.off[t] = sp.offn[t];
-        if (t == a.n_tiles - 1) sp.off[t + 1] = sp.offn[t + 1];
-    }
 }
 
 // ---- single-simulation kernels: blockIdx.y = species
 __global__ void __launch_bounds__(kScanBlock) k_sort_count(SortArgs a) { sort_count_unit(a, blockIdx.y, blockIdx.x); }
 __global__ void __launch_bounds__(1024) k_sort_scan_blocks(SortArgs a) { sort_scan_unit(a, blockIdx.x); }
 __global__ void __launch_bounds__(kScanBlock) k_sort_add_base(SortArgs a) { sort_add_unit(a, blockIdx.y, blockIdx.x); }
+__global__ void __launch_bounds__(kScanBlock) k_sort_add_direct(SortArgs a)
+{
+    sort_add_direct_unit(a, blockIdx.y, blockIdx.x);
+}
 // A fill left pending by a deferred sort, done on its own (before anything
 // reads the particle arrays other than a push): tile t's fcount[t] staged
 // movers into its holes, as the next push would, and fcount[t] back to 0.
@@ -698,6 +725,11 @@ __global__ void __launch_bounds__(1024) k_sort_scan_blocks_b(const SortArgs *d, 
     const int4 w = it[blockIdx.x];
     sort_scan_unit(d[w.x], w.y);
 }
+__global__ void __launch_bounds__(kScanBlock) k_sort_add_direct_b(const SortArgs *d, const int4 *it)
+{
+    const int4 w = it[blockIdx.x];
+    sort_add_direct_unit(d[w.x], w.y, w.z);
+}
 __global__ void __launch_bounds__(kScanBlock) k_sort_add_base_b(const SortArgs *d, const int4 *it)
 {
     const int4 w = it[blockIdx.x];
@@ -707,11 +739,6 @@ __global__ void __launch_bounds__(kBlock) k_sort_plan_b(const SortArgs *d, const
 {
     const int4 w = it[blockIdx.x];
     sort_plan_unit(d[w.x], w.y, w.z);
-}
-__global__ void __launch_bounds__(kBlock) k_sort_scatter_b(const SortArgs *d, const int4 *it)
-{
-    const int4 w = it[blockIdx.x];
-    sort_scatter_unit(d[w.x], w.y, w.z);
 }
 __global__ void __launch_bounds__(kBlock) k_fill_b(const SortArgs *d, const int4 *it)
 {
@@ -773,6 +800,10 @@ void launch_sort_scan(const SortArgs &a, int n_tiles, hipStream_t s)
 {
     const int nb = (n_tiles + kScanBlock - 1) / kScanBlock;
     hipLaunchKernelGGL(k_sort_count, dim3(nb, a.n_species), dim3(kScanBlock), 0, s, a);
+    if (nb <= kScanDirect) {
+        hipLaunchKernelGGL(k_sort_add_direct, dim3(nb, a.n_species), dim3(kScanBlock), 0, s, a);
+        return;
+    }
     hipLaunchKernelGGL(k_sort_scan_blocks, dim3(a.n_species), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_sort_add_base, dim3(nb, a.n_species), dim3(kScanBlock), 0, s, a);
 }
@@ -803,14 +834,18 @@ void launch_sort_batch(const SortBatch &b, bool motion, hipStream_t s)
 {
     if (b.n_count == 0) return;
     hipLaunchKernelGGL(k_sort_count_b, dim3(b.n_count), dim3(kScanBlock), 0, s, b.descs, b.count_items);
-    hipLaunchKernelGGL(k_sort_scan_blocks_b, dim3(b.n_scan), dim3(1024), 0, s, b.descs, b.scan_items);
-    hipLaunchKernelGGL(k_sort_add_base_b, dim3(b.n_count), dim3(kScanBlock), 0, s, b.descs, b.count_items);
+    if (b.max_blocks <= kScanDirect) {
+        hipLaunchKernelGGL(k_sort_add_direct_b, dim3(b.n_count), dim3(kScanBlock), 0, s, b.descs, b.count_items);
+    } else {
+        hipLaunchKernelGGL(k_sort_scan_blocks_b, dim3(b.n_scan), dim3(1024), 0, s, b.descs, b.scan_items);
+        hipLaunchKernelGGL(k_sort_add_base_b, dim3(b.n_count), dim3(kScanBlock), 0, s, b.descs, b.count_items);
+    }
     if (motion) {
         hipLaunchKernelGGL(k_motion_scatter_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
         hipLaunchKernelGGL(k_motion_copy_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
     } else {
+        // the batched in-place sort is deferred: the next batched push fills the holes
         hipLaunchKernelGGL(k_sort_plan_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
-        hipLaunchKernelGGL(k_sort_scatter_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
     }
 }
 

@@ -169,7 +169,7 @@ struct pic_sim {
     bool have_snapshot;
     struct Sp {
         int32_t *off;    // current tile_offset
-        int32_t *offn;   // the sort's new tile_offset (scratch, copied into off)
+        int32_t *offp;   // the tile_offset before the sort (scratch)
         int32_t *cnt;
         uint32_t *leav;
         int32_t *hole;
@@ -498,7 +498,7 @@ SortArgs sort_args(const pic_sim *S, bool defer = false)
         d.stg = P.stg;
         d.srec = P.srec;
         d.off = P.off;
-        d.offn = P.offn;
+        d.offp = P.offp;
         d.cnt = P.cnt;
         d.leav = P.leav;
         d.hole = P.hole;
@@ -691,7 +691,7 @@ int init_sim(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
     for (int s = 0; s < cfg->n_species; ++s) {
         auto &P = S->sp[s];
         P.off = (int32_t *)(w + L.off[s][0]);
-        P.offn = (int32_t *)(w + L.off[s][1]);
+        P.offp = (int32_t *)(w + L.off[s][1]);
         P.cnt = (int32_t *)(w + L.cnt[s]);
         P.leav = (uint32_t *)(w + L.leav[s]);
         P.hole = (int32_t *)(w + L.hole[s]);
@@ -851,7 +851,7 @@ static int sort_after_push(pic_sim *S, hipStream_t stream, bool defer)
         Timed t(S, PIC_KERNEL_SORT_PLAN, stream);
         launch_sort_plan(a, S->n_tiles, stream);
     }
-    {
+    if (!defer) {   // deferred: the next push places the movers
         Timed t(S, PIC_KERNEL_SORT_SCATTER, stream);
         launch_sort_scatter(a, S->n_tiles, stream);
     }
@@ -1259,6 +1259,7 @@ struct pic_batch {
     int j_filter;
     int4 *push_items, *node_items, *count_items, *scan_items, *plan_items;
     int n_push, n_node, n_count, n_scan, n_plan;
+    int max_blocks;   // the most scan blocks of one member
     int *counter;
     int push_grid;
     hipGraph_t graph;
@@ -1361,6 +1362,7 @@ void batch_enqueue_step(pic_batch *b, bool sort, hipStream_t stream)
     sb.n_scan = b->n_scan;
     sb.plan_items = b->plan_items;
     sb.n_plan = b->n_plan;
+    sb.max_blocks = b->max_blocks;
     if (sort) launch_sort_batch(sb, (b->sims[0]->cfg.flags & PIC_FLAG_MOTION_SORT) != 0, stream);
     if (fork) (void)hipStreamWaitEvent(stream, b->ev_join, 0);
 }
@@ -1432,6 +1434,11 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
     B->n_count = L.n_count;
     B->n_scan = L.n_scan;
     B->n_plan = L.n_plan;
+    B->max_blocks = 0;
+    for (int i = 0; i < n; ++i) {
+        const int nt = (cfgs[i].nx / cfgs[i].tile) * (cfgs[i].ny / cfgs[i].tile);
+        B->max_blocks = std::max(B->max_blocks, (nt + kScanBlock - 1) / kScanBlock);
+    }
 
     // host images of the descriptors and work tables
     std::vector<PushArgs> hp(n);
@@ -1556,6 +1563,7 @@ int pic_batch_sync(pic_batch *B, hipStream_t stream)
     sb.n_scan = B->n_scan;
     sb.plan_items = B->plan_items;
     sb.n_plan = B->n_plan;
+    sb.max_blocks = B->max_blocks;
     launch_fill_batch(sb, stream);   // members without a pending fill have zero fill counts
     return hip_ok(hipGetLastError());
 }

@@ -14,12 +14,13 @@ struct SortSpecies {
     Parts p;              // the particle arrays
     const LeaverRec *lrec;   // leaver particle data written by the push kernel
     Parts stg;            // the motion-class sort's staging, [n]: every particle at its new slot
-    LeaverRec *srec;      // the in-place sort's mover staging, [n]: tile t's movers at offn[t] + k, in hole order
-    int32_t *off;         // tile_offset: read by the plan, replaced by the new one in the scatter
-    int32_t *offn;        // new tile_offset (scratch)
+    LeaverRec *srec;      // the in-place sort's mover staging, [n]: tile t's movers at off[t] + k, in hole order
+    int32_t *off;         // tile_offset: the recount's first pass keeps it in offp and the scan
+                          // writes the new one in its place
+    int32_t *offp;        // the tile_offset before the sort (scratch)
     const int32_t *cnt;
     const uint32_t *leav;
-    int32_t *hole;        // [n]: tile t's holes, ascending, at offn[t] + k
+    int32_t *hole;        // [n]: tile t's holes, ascending, at off[t] + k
     int32_t *mcount;      // [n_tiles]: movers (the motion-class sort: [3][n_tiles] class bases)
     int32_t *fcount;      // [n_tiles]: holes whose fill is pending (the next push fills them), else 0
     int32_t *fbase;       // [n_tiles][W]: first pending hole of each push wavefront's run
@@ -84,6 +85,7 @@ struct SortBatch {
     const int4 *count_items; int n_count;
     const int4 *scan_items; int n_scan;
     const int4 *plan_items; int n_plan;
+    int max_blocks;   // the most scan blocks of one member
 };
 // a pending hole fill of every member (fill_unit)
 void launch_fill_batch(const SortBatch &b, hipStream_t s);
