@@ -31,7 +31,7 @@ if ROOT not in sys.path:
 
 METRIC = "particle-pushes/sec (push+deposit+sort), 1 MI355X; % of HBM roofline"
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
-BYTES_PARTICLE = 24          # cell (4) + x, y (8) + ux, uy, uz (12)
+BYTES_PARTICLE = 22          # tile-relative cell (2) + x, y (8) + ux, uy, uz (12)
 
 
 # The thesis's whole-run figures (500 steps, field solve and overheads
@@ -140,16 +140,19 @@ def cpu_baseline_openmp(w, st, T, steps=3):
 
 def stream_probe(n=1 << 26, launches=20):
     """The push's particle stream without its arithmetic (pic_probe_stream):
-    six float arrays of n values read and written back in place, with and
-    without the non-temporal hint, event-timed; and a plain device copy of
-    the same bytes.  Returns achieved GB/s (48 n bytes per launch)."""
+    one 16-bit and five float arrays of n values read and written back in
+    place, with and without the non-temporal hint, event-timed; and a plain
+    device copy of the same bytes.  Returns achieved GB/s (44 n bytes per
+    launch)."""
     import torch
 
     from paper_2501_14795_amd import _lib
-    arrays = [torch.zeros(n, dtype=torch.float32, device="cuda") for _ in range(6)]
+    nb = 2 * BYTES_PARTICLE * n
+    arrays = [torch.zeros(n, dtype=torch.int16, device="cuda")]
+    arrays += [torch.zeros(n, dtype=torch.float32, device="cuda") for _ in range(5)]
     ptrs = [a.data_ptr() for a in arrays]
     s = torch.cuda.current_stream().cuda_stream
-    out = {"elements": n, "bytes_per_launch": 48 * n}
+    out = {"elements": n, "bytes_per_launch": nb}
     for name, nt in (("soa_rw_nontemporal", True), ("soa_rw", False)):
         for _ in range(3):
             _lib.pic_probe_stream(ptrs, n, nt, s)
@@ -160,8 +163,8 @@ def stream_probe(n=1 << 26, launches=20):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / launches
-        out[name + "_gbs"] = 48 * n / (ms * 1e-3) / 1e9
-    src = torch.ones(6 * n, dtype=torch.float32, device="cuda")
+        out[name + "_gbs"] = nb / (ms * 1e-3) / 1e9
+    src = torch.ones(BYTES_PARTICLE * n // 2, dtype=torch.int16, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
@@ -171,7 +174,7 @@ def stream_probe(n=1 << 26, launches=20):
         dst.copy_(src)
     e1.record()
     torch.cuda.synchronize()
-    out["copy_gbs"] = 2 * 24 * n / (e0.elapsed_time(e1) / launches * 1e-3) / 1e9
+    out["copy_gbs"] = nb / (e0.elapsed_time(e1) / launches * 1e-3) / 1e9
     del arrays, src, dst
     torch.cuda.empty_cache()
     return out

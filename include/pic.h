@@ -23,13 +23,18 @@
  *     and pic_get_timing(), which synchronise the stream they are given.
  *   - Calls on one pic_sim must not run concurrently from several host
  *     threads.
+ *   - The push and the sort keep each particle's cell in the workspace, as
+ *     16 bits relative to its tile (the caller's cell array is read by
+ *     pic_init and pic_set_state, and written back by pic_sync); x, y, ux, uy
+ *     and uz they read and write in the caller's arrays.
  *   - pic_step() and pic_batch_step() leave the last part of their sort, the
  *     copy of the staged movers into their holes, to the next push, which
  *     streams those slots anyway: until then the particle arrays hold stale
  *     values in those slots.  Every entry point that reads the particles
  *     (pic_get_state, pic_diag, pic_move_window, the Gauss solves, and of
- *     course the next push) completes it first; a caller that reads the
- *     particle arrays itself calls pic_sync() before.  tile_offset, the
+ *     course the next push) completes it first.  A caller that reads the
+ *     particle arrays itself calls pic_sync() before: it completes the fill
+ *     and writes every particle's cell into the cell array.  tile_offset, the
  *     counts and the fields are final when pic_step() returns.
  *
  * Data layout
@@ -239,10 +244,11 @@ int pic_push_deposit(pic_sim *sim, hipStream_t stream);
 int pic_sort(pic_sim *sim, hipStream_t stream);
 
 /*
- * Complete the hole fill that pic_step()'s or pic_batch_step()'s sort left to
- * the next push (see the memory model): copies the staged movers into their
- * holes, so the caller's particle arrays hold the sorted state.  Does nothing
- * if no fill is pending.  Enqueues on `stream` without synchronising.
+ * Bring the caller's particle arrays up to date (see the memory model):
+ * completes the hole fill that pic_step()'s or pic_batch_step()'s sort left
+ * to the next push (the staged movers into their holes; nothing if none is
+ * pending) and writes every particle's cell, ix | iy << 16, into the cell
+ * array.  Enqueues two kernels on `stream` without synchronising.
  */
 int pic_sync(pic_sim *sim, hipStream_t stream);
 
@@ -496,8 +502,9 @@ int pic_batch_capture(pic_batch *b, hipStream_t stream);
  * not capture with it on. */
 pic_sim *pic_batch_sim(pic_batch *b, int i);
 
-/* pic_sync() for every member at once (one launch): the hole fill that the
- * last batched sort left to the next push.  Enqueues on `stream`. */
+/* pic_sync() for every member at once (one launch for the hole fills that
+ * the last batched sort left to the next push, one for the cells).  Enqueues
+ * on `stream`. */
 int pic_batch_sync(pic_batch *b, hipStream_t stream);
 
 /* pic_check of every member; the first error found. */
@@ -508,16 +515,17 @@ void pic_batch_destroy(pic_batch *b);
 
 /*
  * Measurement aid, not a step of the method: the push kernel's particle
- * stream without its arithmetic.  Six device arrays of n 32-bit values
- * (arrays[0..5], e.g. one species' cell, x, y, ux, uy, uz) are each read and
- * written back unchanged, in 64-value chunks through buffer descriptors,
- * 16,384 values of every array per workgroup; nontemporal != 0 gives the
- * loads and stores the push's non-temporal hint.  Timing it gives the
- * bandwidth this access pattern reaches (24 n bytes read, 24 n written), the
- * practical ceiling of the push's streaming.  Enqueues one kernel on
- * `stream`; PIC_EINVAL for a null array or n < 0.
+ * stream without its arithmetic.  Six device arrays -- arrays[0] of n 16-bit
+ * values (the tile-relative cells), arrays[1..5] of n 32-bit values (x, y,
+ * ux, uy, uz) -- are each read and written back unchanged, in 64-value
+ * chunks through buffer descriptors, 16,384 values of every array per
+ * workgroup; nontemporal != 0 gives the loads and stores the push's
+ * non-temporal hint.  Timing it gives the bandwidth this access pattern
+ * reaches (22 n bytes read, 22 n written), the practical ceiling of the
+ * push's streaming.  Enqueues one kernel on `stream`; PIC_EINVAL for a null
+ * array or n < 0.
  */
-int pic_probe_stream(float *const *arrays, int64_t n, int nontemporal, hipStream_t stream);
+int pic_probe_stream(void *const *arrays, int64_t n, int nontemporal, hipStream_t stream);
 
 /* Static string naming a return code. */
 const char *pic_strerror(int code);

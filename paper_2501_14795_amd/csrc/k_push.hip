@@ -330,16 +330,18 @@ __device__ __forceinline__ void flush_leavers(const SpeciesDev &sp, uint32_t (*l
     __builtin_amdgcn_wave_barrier();
 }
 
-// One lane's particle of one chunk, as loaded.
+// One lane's particle of one chunk, as loaded (cell: tile-relative, tcell_pack).
 struct Chunk {
     int cell;
     float x, y, ux, uy, uz;
 };
 
+// off: the byte offset of the slot in the 32-bit arrays (half of it in the
+// 16-bit cell array)
 __device__ __forceinline__ Chunk load_chunk(const Stream6 &st, int off)
 {
     Chunk c;
-    c.cell = (int)__builtin_amdgcn_raw_buffer_load_b32(st.cell, off, 0, kLoadCpol);
+    c.cell = (int)__builtin_amdgcn_raw_buffer_load_b16(st.cell, off >> 1, 0, kLoadCpol);
     c.x = ldf(st.x, off);
     c.y = ldf(st.y, off);
     c.ux = ldf(st.ux, off);
@@ -353,7 +355,8 @@ __device__ __forceinline__ Chunk load_chunk(const Stream6 &st, int off)
 struct Moved {
     bool valid, cross;   // in the wavefront's run; motion crosses a cell face
     int b;               // current-halo index of the start cell
-    int ncell, dir;      // new packed cell; direction of the new tile (4: same tile)
+    int ncell, dir;      // new whole-grid cell; direction of the new tile (4: same tile)
+    int nlc;             // new tile-relative cell (the same tile's frame)
     int err;             // error bits (kErrOrder, kErrRange), valid lanes only
     float x, y, dX, dY, fqvz;
     float xn, yn, ux, uy, uz;
@@ -363,29 +366,27 @@ struct Moved {
 // branches).  Lanes outside the run compute on a cell clamped into the halo,
 // so their LDS reads stay in bounds; their results are discarded.
 template <int T, int NJ, int NE, int H, class V2, class V1>
-__device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool valid, int gx0, int gy0,
-                                         bool tx_wrap, bool ty_wrap, float h, float fq, const V2 *s_exby,
+__device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool valid, bool rebase, int gx0,
+                                         int gy0, bool tx_wrap, bool ty_wrap, float h, float fq, const V2 *s_exby,
                                          const V2 *s_eybx, const V1 *s_ez, const V1 *s_bz)
 {
     Moved m;
     m.valid = valid;
     m.err = 0;
-    const int cell = p.cell;
     const float x = p.x, y = p.y;
-    int lx = (cell & 0xffff) - gx0, ly = (cell >> 16) - gy0;
-    if constexpr (H > 1) {
-        // since the last sort the particle may have left the tile by up to
-        // H - 1 cells, also across the periodic seam (one image lies in that
-        // band: 2H - 2 < T); a cell outside the grid is flagged below
-        const bool off_grid = cell < 0 || (cell & 0xffff) >= a.nx || (cell >> 16) >= a.ny;
-        const int wx = tx_wrap ? (lx >= T + H - 1 ? -a.nx : (lx < 1 - H ? a.nx : 0)) : 0;
-        const int wy = ty_wrap ? (ly >= T + H - 1 ? -a.ny : (ly < 1 - H ? a.ny : 0)) : 0;
-        lx = off_grid ? T + H : lx + wx;
-        ly = off_grid ? ly : ly + wy;
-    }
-    if (valid && ((unsigned)(lx + H - 1) >= (unsigned)(T + 2 * H - 2) ||
-                  (unsigned)(ly + H - 1) >= (unsigned)(T + 2 * H - 2)))
+    // The cell relative to the tile.  Since the last sort the particle may
+    // have left the tile by up to H - 1 cells.  Right after a sort (rebase)
+    // it is inside the tile, and its cell is relative to the tile it was in
+    // before the sort, up to H cells off: modulo T it is its cell here.
+    // Anything further is flagged.
+    int lx = tcell_x(p.cell), ly = tcell_y(p.cell);
+    const int bl = rebase ? H : H - 1;   // the band of cells allowed: -bl .. T - 1 + bl
+    if (valid && ((unsigned)(lx + bl) >= (unsigned)(T + 2 * bl) || (unsigned)(ly + bl) >= (unsigned)(T + 2 * bl)))
         m.err |= kErrOrder;
+    if (rebase) {
+        lx &= T - 1;
+        ly &= T - 1;
+    }
     lx = min(max(lx, 1 - H), T + H - 2);
     ly = min(max(ly, 1 - H), T + H - 2);
 
@@ -477,6 +478,8 @@ __device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool
     const int nlx = lx + sxn + (xr ? 1 : 0), nly = ly + syn + (yr ? 1 : 0);
     const int gx = wrapi(gx0 + nlx, a.nx), gy = wrapi(gy0 + nly, a.ny);
     m.ncell = gx | (gy << 16);
+    // on an axis of one tile the periodic image is in the tile itself
+    m.nlc = tcell_pack(tx_wrap ? nlx : gx, ty_wrap ? nly : gy);
     m.ux = ux;
     m.uy = uy;
     m.uz = uz;
@@ -492,7 +495,7 @@ __device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool
 // C: particles per lane per pass of the particle loop (64-particle chunks
 // carried side by side).
 template <int T, int R, int JM, int DM, int H, int C>
-__device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
+__device__ __forceinline__ void push_tile(const PushArgs &a, const int tile, const bool rebase)
 {
     static_assert(cadence_ok(T, H), "halo pad not supported for this tile");
     constexpr int NE = T + 2 * H;       // staged E/B cells per axis: relative -H..T+H-1
@@ -566,7 +569,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             const int base = (begin >> 6) << 6;
             const int bytes = (hi - base) * 4;
             Stream6 st;
-            st.cell = rsrc(sp.cell + base, bytes);
+            st.cell = rsrc(sp.cell + base, bytes / 2);
             st.x = rsrc(sp.x + base, bytes);
             st.y = rsrc(sp.y + base, bytes);
             st.ux = rsrc(sp.ux + base, bytes);
@@ -619,7 +622,8 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                     const PIC_GLOBAL vf4 *r = (const PIC_GLOBAL vf4 *)(sp.fsrc + begin + ref);
                     const vf4 u = r[0];
                     const vf2 v = *(const PIC_GLOBAL vf2 *)(r + 1);
-                    d.cell = __float_as_int(u.x);
+                    const int g = __float_as_int(u.x);   // a particle of this tile, whole-grid cell
+                    d.cell = tcell_pack((g & 0xffff) - gx0, (g >> 16) - gy0);
                     d.x = u.y;
                     d.y = u.z;
                     d.ux = u.w;
@@ -640,7 +644,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
             auto finish = [&](const Moved &m, int i, int at) {
                 if (m.valid && !m.cross) deposit_piece<NJ, JM>(sj, m.b, m.x, m.y, m.dX, m.dY, m.fqvz, fq);
                 if (m.valid) {
-                    __builtin_amdgcn_raw_buffer_store_b32((unsigned)m.ncell, st.cell, at, 0, kStoreCpol);
+                    __builtin_amdgcn_raw_buffer_store_b16((unsigned short)m.nlc, st.cell, at >> 1, 0, kStoreCpol);
                     stf(st.x, at, m.xn);
                     stf(st.y, at, m.yn);
                     stf(st.ux, at, m.ux);
@@ -713,8 +717,9 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile)
                 Moved m[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    m[c] = advance<T, NJ, NE, H, V2, V1>(a, cur[c], i + 64 * c >= lo && i + 64 * c < hi, gx0, gy0,
-                                                         tx_wrap, ty_wrap, h, fq, s_exby, s_eybx, s_ez, s_bz);
+                    m[c] = advance<T, NJ, NE, H, V2, V1>(a, cur[c], i + 64 * c >= lo && i + 64 * c < hi, rebase,
+                                                         gx0, gy0, tx_wrap, ty_wrap, h, fq, s_exby, s_eybx, s_ez,
+                                                         s_bz);
                     errs |= m[c].err;
                 }
 #pragma unroll
@@ -816,7 +821,7 @@ constexpr int push_waves_per_simd()
 template <int T, int R, int JM, int DM, int H, int C>
 __global__ void __launch_bounds__(64 * push_waves(T), (push_waves_per_simd<T, R, JM, DM, H, C>())) k_push_deposit(PushArgs a)
 {
-    push_tile<T, R, JM, DM, H, C>(a, blockIdx.x);
+    push_tile<T, R, JM, DM, H, C>(a, blockIdx.x, a.rebase != 0);
 }
 
 // Many simulations in one launch: a persistent grid takes (simulation, tile)
@@ -824,7 +829,8 @@ __global__ void __launch_bounds__(64 * push_waves(T), (push_waves_per_simd<T, R,
 // the expensive tiles start early and the cheap ones fill the tail).
 template <int T, int R, int JM, int DM, int H, int C>
 __global__ void __launch_bounds__(64 * push_waves(T), (push_waves_per_simd<T, R, JM, DM, H, C>())) k_push_batch(const PushArgs *__restrict__ descs,
-                                                       const int4 *__restrict__ items, int n_items, int *counter)
+                                                       const int4 *__restrict__ items, int n_items, int *counter,
+                                                       int rebase)
 {
     __shared__ int s_item;
     for (;;) {
@@ -834,7 +840,7 @@ __global__ void __launch_bounds__(64 * push_waves(T), (push_waves_per_simd<T, R,
         __syncthreads();
         if (it >= n_items) break;
         const int4 w = items[it];
-        push_tile<T, R, JM, DM, H, C>(descs[w.x], w.y);
+        push_tile<T, R, JM, DM, H, C>(descs[w.x], w.y, rebase != 0);
         __syncthreads();
     }
 }
@@ -881,10 +887,11 @@ static void launch_pd(const PushArgs &a, int n_tiles, hipStream_t s)
 }
 
 template <int T, int R, int JM, int DM, int H, int C>
-static void launch_pb(const PushArgs *descs, const int4 *items, int n_items, int *counter, int grid, hipStream_t s)
+static void launch_pb(const PushArgs *descs, const int4 *items, int n_items, int *counter, int grid, int rebase,
+                      hipStream_t s)
 {
     hipLaunchKernelGGL((k_push_batch<T, R, JM, DM, H, C>), dim3(grid), dim3(64 * push_waves(T)), 0, s, descs, items,
-                       n_items, counter);
+                       n_items, counter, rebase);
 }
 
 // One push launch, single or batched, with every template parameter chosen.
@@ -898,13 +905,14 @@ struct PushLaunch {
     int n_items;
     int *counter;
     int grid;
+    int rebase;               // batched: the pushes follow a sort
     hipStream_t s;
     template <int T, int R, int JM, int DM, int H, int C>
     void go() const
     {
         if constexpr (push_lds_bytes(T, R, JM, H) <= kLdsBytes && cadence_ok(T, H)) {
             if (single) launch_pd<T, R, JM, DM, H, C>(*single, n_tiles, s);
-            else launch_pb<T, R, JM, DM, H, C>(descs, items, n_items, counter, grid, s);
+            else launch_pb<T, R, JM, DM, H, C>(descs, items, n_items, counter, grid, rebase, s);
         }
     }
 };
@@ -967,14 +975,14 @@ static void push_t(const PushLaunch &L, int tile, int replicas, int jmode, int d
 void launch_push_deposit(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs &a,
                          int n_tiles, hipStream_t s)
 {
-    PushLaunch L{&a, n_tiles, nullptr, nullptr, 0, nullptr, 0, s};
+    PushLaunch L{&a, n_tiles, nullptr, nullptr, 0, nullptr, 0, 0, s};
     push_t(L, tile, replicas, jmode, dmode, halo, ppl);
 }
 
 void launch_push_batch(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs *descs,
-                       const int4 *items, int n_items, int *counter, int grid, hipStream_t s)
+                       const int4 *items, int n_items, int *counter, int grid, bool rebase, hipStream_t s)
 {
-    PushLaunch L{nullptr, 0, descs, items, n_items, counter, grid, s};
+    PushLaunch L{nullptr, 0, descs, items, n_items, counter, grid, rebase ? 1 : 0, s};
     push_t(L, tile, replicas, jmode, dmode, halo, ppl);
 }
 

@@ -214,14 +214,21 @@ __device__ __forceinline__ Chunk6 load_leaver(const LeaverRec *src, int64_t i)
     return Chunk6{__float_as_int(a.x), a.y, a.z, a.w, b.x, b.y};
 }
 
-__device__ __forceinline__ Chunk6 load_parts(const Parts &src, int64_t i)
+// The particle at slot i, inside the tile whose first cell is (gx0, gy0),
+// with its whole-grid cell (the staging records' form); mask: T - 1 in a
+// sorted state (the cell is relative to the tile modulo T), else -1.
+__device__ __forceinline__ Chunk6 load_parts(const Parts &src, int64_t i, int gx0, int gy0, int mask)
 {
-    return Chunk6{src.cell[i], src.x[i], src.y[i], src.ux[i], src.uy[i], src.uz[i]};
+    const int lc = src.cell[i];
+    return Chunk6{(gx0 + (tcell_x(lc) & mask)) | ((gy0 + (tcell_y(lc) & mask)) << 16), src.x[i], src.y[i],
+                  src.ux[i], src.uy[i], src.uz[i]};
 }
 
-__device__ __forceinline__ void store_parts(const Parts &dst, int64_t j, const Chunk6 &c)
+// A particle of the tile whose first cell is (gx0, gy0), given with its
+// whole-grid cell, into slot j (its cell relative to that tile).
+__device__ __forceinline__ void store_parts(const Parts &dst, int64_t j, const Chunk6 &c, int gx0, int gy0)
 {
-    dst.cell[j] = c.cell;
+    dst.cell[j] = (int16_t)tcell_pack((c.cell & 0xffff) - gx0, (c.cell >> 16) - gy0);
     dst.x[j] = c.x;
     dst.y[j] = c.y;
     dst.ux[j] = c.ux;
@@ -229,14 +236,10 @@ __device__ __forceinline__ void store_parts(const Parts &dst, int64_t j, const C
     dst.uz[j] = c.uz;
 }
 
-__device__ __forceinline__ void copy_particle(const Parts &src, int64_t i, const Parts &dst, int64_t j)
+// Whether tile-relative cell lc lies inside its tile (of edge T).
+__device__ __forceinline__ bool tcell_inside(int lc, int T)
 {
-    dst.cell[j] = src.cell[i];
-    dst.x[j] = src.x[i];
-    dst.y[j] = src.y[i];
-    dst.ux[j] = src.ux[i];
-    dst.uy[j] = src.uy[i];
-    dst.uz[j] = src.uz[i];
+    return (unsigned)tcell_x(lc) < (unsigned)T && (unsigned)tcell_y(lc) < (unsigned)T;
 }
 
 // Steps (2)-(4) of the sort for one destination tile t per wavefront, new
@@ -274,13 +277,12 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
     if (t >= a.n_tiles) return;   // whole wavefront
     const SortSpecies &sp = a.sp[spi];
     const int ntx = a.ntx, nty = a.nty;
-    const int tsh = __builtin_ctz(a.tile);
-    const int W = push_waves(a.tile);   // leaver sub-lists per tile
-    // a negative cell marks a particle that left the moving window: no tile
-    auto tile_of = [&](int cell) { return cell < 0 ? -1 : ((cell >> 16) >> tsh) * ntx + ((cell & 0xffff) >> tsh); };
+    const int T = a.tile;
+    const int W = push_waves(T);   // leaver sub-lists per tile
+    const int tx = t % ntx, ty = t / ntx;
+    const int gx0 = tx * T, gy0 = ty * T;
 
     // ---------------- the sources of t and their ranks (lanes 0..8)
-    const int tx = t % ntx, ty = t / ntx;
     int so = -1;
     if (lane < 9) so = wrap_s(ty - (lane / 3 - 1), nty) * ntx + wrap_s(tx - (lane % 3 - 1), ntx);
     int rank = 0, first = 1;
@@ -293,6 +295,19 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
         if (vfirst && v < so) ++rank;
         if (o < lane && v == so) first = 0;
     }
+    // lane o < 9: the old section of the source in offset o
+    const int so_a = lane < 9 ? sp.offp[so] : 0, so_b = lane < 9 ? sp.offp[so + 1] : 0;
+    // Whether the particle at `slot` of another tile's old section, with
+    // tile-relative cell lc, has moved into t: its cell lies one tile off
+    // its own in some offset o, and the source of t in offset o is the tile
+    // whose old section holds the slot.  A particle that left the moving
+    // window is in no tile.  All lanes take part.
+    auto arrived = [&](int lc, int slot) {
+        const int lx = tcell_x(lc), ly = tcell_y(lc);
+        const int o = (ly < 0 ? 0 : (ly >= T ? 6 : 3)) + (lx < 0 ? 0 : (lx >= T ? 2 : 1));
+        const int sa = __shfl(so_a, o, 64), sb = __shfl(so_b, o, 64);
+        return o != 4 && (lc & 0xffff) != kTCellRemoved && slot >= sa && slot < sb;
+    };
     // the source of rank q, -1 if there is none (all lanes take part)
     auto source_of_rank = [&](int q) {
         int v = -1;
@@ -428,7 +443,13 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
             const int kind = ks[u] & 3;
             v[u] = 0;
             if (k < total)
-                v[u] = kind == kListHoleRange || kind == kListMoverRange ? (uint32_t)sp.p.cell[at[u]] : sp.leav[at[u]];
+                v[u] = kind == kListHoleRange || kind == kListMoverRange ? (uint32_t)(int)sp.p.cell[at[u]]
+                                                                         : sp.leav[at[u]];
+            // a sorted state (the window's sort): every particle is in the
+            // tile of its section, its cell relative to it modulo T
+            if (a.rebase && (kind == kListHoleRange || kind == kListMoverRange) &&
+                (v[u] & 0xffffu) != (uint32_t)kTCellRemoved)
+                v[u] = (uint32_t)tcell_pack(tcell_x((int)v[u]) & (T - 1), tcell_y((int)v[u]) & (T - 1));
         }
         // ---- the ballots, in candidate order: holes first, then movers
         int rr[kPlanBatch];
@@ -438,14 +459,15 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
             const int kind = ks[u] & 3, L = lv[u];
             bool ph = false, pm = false, fl = false;
             int slot = at[u];
+            const bool in_t = arrived((int)v[u], slot);
             if (L >= 0) {
                 if (kind == kListHoleRange) {
-                    ph = tile_of((int)v[u]) != t;
+                    ph = !in_t;
                 } else if (kind == kListHoleLeav) {
                     slot = oA + (int)(v[u] >> 4);
                     ph = slot >= lA && slot < lB;
                 } else if (kind == kListMoverRange) {
-                    pm = tile_of((int)v[u]) == t;
+                    pm = tcell_inside((int)v[u], T);   // t's own slots, or its new particles
                 } else {
                     const int d = (int)(v[u] & 15u), loc = (int)(v[u] >> 4);
                     if (loc >= nsv[u] || d > kDirRemoved) {
@@ -482,7 +504,7 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
         Chunk6 dv[kPlanBatch];
 #pragma unroll
         for (int u = 0; u < kPlanBatch; ++u)
-            if (mvf >> u & 1u) dv[u] = flf >> u & 1u ? load_leaver(sp.lrec, at[u]) : load_parts(sp.p, at[u]);
+            if (mvf >> u & 1u) dv[u] = flf >> u & 1u ? load_leaver(sp.lrec, at[u]) : load_parts(sp.p, at[u], gx0, gy0, a.rebase ? T - 1 : -1);
 #pragma unroll
         for (int u = 0; u < kPlanBatch; ++u)
             if (mvf >> u & 1u) {
@@ -511,9 +533,10 @@ __device__ __forceinline__ void sort_scatter_unit(const SortArgs &a, int spi, in
     if (t >= a.n_tiles) return;
     const SortSpecies &sp = a.sp[spi];
     const int A = sp.off[t], m = sp.mcount[t];
+    const int gx0 = (t % a.ntx) * a.tile, gy0 = (t / a.ntx) * a.tile;
     for (int k = lane; k < m; k += 64) {
         const int64_t r = (int64_t)A + k;
-        store_parts(sp.p, sp.hole[r], load_leaver(sp.srec, r));
+        store_parts(sp.p, sp.hole[r], load_leaver(sp.srec, r), gx0, gy0);
     }
 }
 
@@ -531,24 +554,17 @@ __device__ __forceinline__ void sort_scatter_unit(const SortArgs &a, int spi, in
 // staging arrays back.  Out of place: reads and writes every particle twice,
 // so it pays only when most particles change tile.
 
-// the step from tile coordinate a to b on an axis of m tiles: 0, +1, -1
-// (+1 when m == 2), 2 if further
-__device__ __forceinline__ int tile_step_s(int a, int b, int m)
+// The motion class of a particle with tile-relative cell lc (tiles of edge
+// T, ntx x nty of them): the push kernel's direction code of the step to the
+// tile it is in now (+1 on an axis of two tiles, either way), or 9 if that
+// is more than one tile away or the particle left the moving window.
+__device__ __forceinline__ int motion_class(int lc, int T, int ntx, int nty)
 {
-    const int d = b - a;
-    if (d == 0) return 0;
-    if (d == 1 || d == 1 - m) return 1;
-    if (d == -1 || d == m - 1) return -1;
-    return 2;
-}
-
-// The motion class of a particle of the tile at (sx, sy) now in cell `cell`,
-// or 9 if the cell is outside the grid or more than one tile away.
-__device__ __forceinline__ int motion_class(int cell, int sx, int sy, int ntx, int nty, int tsh)
-{
-    const int stx = tile_step_s(sx, (cell & 0xffff) >> tsh, ntx);
-    const int sty = tile_step_s(sy, (cell >> 16) >> tsh, nty);
-    return (cell < 0 || stx == 2 || sty == 2) ? 9 : (sty + 1) * 3 + (stx + 1);
+    const int lx = tcell_x(lc), ly = tcell_y(lc);
+    const int stx = lx < 0 ? (ntx == 2 ? 1 : -1) : (lx >= T ? 1 : 0);
+    const int sty = ly < 0 ? (nty == 2 ? 1 : -1) : (ly >= T ? 1 : 0);
+    const bool far = lx < -T || lx >= 2 * T || ly < -T || ly >= 2 * T;   // the removed mark too
+    return far ? 9 : (sty + 1) * 3 + (stx + 1);
 }
 
 struct Part6 {
@@ -585,7 +601,7 @@ __device__ __forceinline__ void motion_scatter_unit(const SortArgs &a, int spi, 
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const SortSpecies &sp = a.sp[spi];
     const int ntx = a.ntx, nty = a.nty;
-    const int tsh = __builtin_ctz(a.tile);
+    const int T = a.tile;
     for (int q = 0; q < kSortWaves; ++q) {
         const int s = grp * kSortWaves + q;
         if (s >= a.n_tiles) break;   // uniform over the block
@@ -597,7 +613,7 @@ __device__ __forceinline__ void motion_scatter_unit(const SortArgs &a, int spi, 
         int mine = 0;
         for (int c0 = (lo >> 6) << 6; c0 < hi; c0 += 64) {
             const int i = c0 + lane;
-            const int d = (i >= lo && i < hi) ? motion_class(sp.p.cell[i], sx, sy, ntx, nty, tsh) : 10;
+            const int d = (i >= lo && i < hi) ? motion_class(sp.p.cell[i], T, ntx, nty) : 10;
 #pragma unroll
             for (int k = 0; k < 9; ++k) {
                 const int c = __popcll(__ballot(d == k));
@@ -637,7 +653,7 @@ __device__ __forceinline__ void motion_scatter_unit(const SortArgs &a, int spi, 
             const bool in = i >= lo && i < hi;
             const int i2 = i + 64;
             if (i2 >= lo && i2 < hi) nxt = load_part(sp.p, i2);
-            const int d = in ? motion_class(cur.cell, sx, sy, ntx, nty, tsh) : 10;
+            const int d = in ? motion_class(cur.cell, T, ntx, nty) : 10;
             unsigned long long m_d = 0ull;
             int taken = 0;
 #pragma unroll
@@ -649,7 +665,11 @@ __device__ __forceinline__ void motion_scatter_unit(const SortArgs &a, int spi, 
             const int at = __shfl(pos, d < 9 ? d : 0, 64) + lane_rank_s(m_d);
             const int lim = __shfl(end, d < 9 ? d : 0, 64);
             if (in) {
-                if (d < 9 && at < lim && (unsigned)at < (unsigned)sp.n) store_part(sp.stg, at, cur);
+                if (d < 9 && at < lim && (unsigned)at < (unsigned)sp.n) {
+                    Part6 v = cur;   // its cell relative to the tile it is in now
+                    v.cell = tcell_pack(tcell_x(cur.cell) & (T - 1), tcell_y(cur.cell) & (T - 1));
+                    store_part(sp.stg, at, v);
+                }
                 else bad = true;
             }
             pos += taken;
@@ -701,14 +721,38 @@ __device__ __forceinline__ void fill_unit(const SortArgs &a, int spi, int grp)
     if (t >= a.n_tiles) return;
     const SortSpecies &sp = a.sp[spi];
     const int A = sp.off[t], m = sp.fcount[t];
+    const int gx0 = (t % a.ntx) * a.tile, gy0 = (t / a.ntx) * a.tile;
     for (int k = lane; k < m; k += 64) {
         const int64_t r = (int64_t)A + k;
-        store_parts(sp.p, sp.hole[r], load_leaver(sp.srec, r));
+        store_parts(sp.p, sp.hole[r], load_leaver(sp.srec, r), gx0, gy0);
     }
     if (lane == 0 && m != 0) sp.fcount[t] = 0;
 }
 
+// The whole-grid cells of tile t's section into the caller's cell array
+// (one wavefront per tile), from the tile-relative ones: the cell of a
+// particle that has left its tile wraps across the periodic seam.  rebase:
+// a sorted state, each cell relative to the tile modulo its edge.
+__device__ __forceinline__ void publish_unit(const SortArgs &a, int spi, int grp, bool rebase)
+{
+    const int lane = threadIdx.x & 63;
+    const int t = grp * kSortWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (t >= a.n_tiles) return;
+    const SortSpecies &sp = a.sp[spi];
+    const int gx0 = (t % a.ntx) * a.tile, gy0 = (t / a.ntx) * a.tile;
+    const int A = sp.off[t], B = sp.off[t + 1];
+    const int mask = rebase ? a.tile - 1 : -1;
+    for (int i = A + lane; i < B; i += 64) {
+        const int lc = sp.p.cell[i];
+        sp.gcell[i] = wrap_s(gx0 + (tcell_x(lc) & mask), a.nx) | (wrap_s(gy0 + (tcell_y(lc) & mask), a.ny) << 16);
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_fill(SortArgs a) { fill_unit(a, blockIdx.y, blockIdx.x); }
+__global__ void __launch_bounds__(kBlock) k_publish(SortArgs a, int rebase)
+{
+    publish_unit(a, blockIdx.y, blockIdx.x, rebase != 0);
+}
 __global__ void __launch_bounds__(kBlock) k_sort_plan(SortArgs a) { sort_plan_unit(a, blockIdx.y, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_sort_scatter(SortArgs a) { sort_scatter_unit(a, blockIdx.y, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_motion_scatter(SortArgs a) { motion_scatter_unit(a, blockIdx.y, blockIdx.x); }
@@ -744,6 +788,11 @@ __global__ void __launch_bounds__(kBlock) k_fill_b(const SortArgs *d, const int4
 {
     const int4 w = it[blockIdx.x];
     fill_unit(d[w.x], w.y, w.z);
+}
+__global__ void __launch_bounds__(kBlock) k_publish_b(const SortArgs *d, const int4 *it, int rebase)
+{
+    const int4 w = it[blockIdx.x];
+    publish_unit(d[w.x], w.y, w.z, rebase != 0);
 }
 
 __global__ void __launch_bounds__(kBlock) k_motion_scatter_b(const SortArgs *d, const int4 *it)
@@ -830,6 +879,18 @@ void launch_fill_batch(const SortBatch &b, hipStream_t s)
     if (b.n_plan > 0) hipLaunchKernelGGL(k_fill_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items);
 }
 
+void launch_publish(const SortArgs &a, int n_tiles, bool rebase, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_publish, dim3((n_tiles + kSortWaves - 1) / kSortWaves, a.n_species), dim3(kBlock), 0, s, a,
+                       rebase ? 1 : 0);
+}
+
+void launch_publish_batch(const SortBatch &b, bool rebase, hipStream_t s)
+{
+    if (b.n_plan > 0)
+        hipLaunchKernelGGL(k_publish_b, dim3(b.n_plan), dim3(kBlock), 0, s, b.descs, b.plan_items, rebase ? 1 : 0);
+}
+
 void launch_sort_batch(const SortBatch &b, bool motion, hipStream_t s)
 {
     if (b.n_count == 0) return;
@@ -859,6 +920,22 @@ void launch_motion_copy(const SortArgs &a, int n_tiles, hipStream_t s)
 {
     hipLaunchKernelGGL(k_motion_copy, dim3((n_tiles + kSortWaves - 1) / kSortWaves, a.n_species), dim3(kBlock), 0, s,
                        a);
+}
+
+// Tile-relative cells of n particles grouped by tile, each inside its tile
+// (checked before), from their whole-grid cells.
+__global__ void __launch_bounds__(256) k_localize(const int32_t *__restrict__ cell, int16_t *__restrict__ lcell,
+                                                  int32_t n, int tile)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int c = cell[i];
+    lcell[i] = (int16_t)tcell_pack((c & 0xffff) & (tile - 1), (c >> 16) & (tile - 1));
+}
+
+void launch_localize(const int32_t *cell, int16_t *lcell, int32_t n, int tile, hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL(k_localize, dim3((n + 255) / 256), dim3(256), 0, s, cell, lcell, n, tile);
 }
 
 void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile, int ntx, int n_tiles, int32_t *off,

@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(kTsThreads) k_ts_scatter(const uint32_t *__res
     }
 }
 
-__global__ void __launch_bounds__(256) k_ts_gather(Parts dst, Parts src, const uint32_t *__restrict__ perm, int n)
+__global__ void __launch_bounds__(256) k_ts_gather(GParts dst, GParts src, const uint32_t *__restrict__ perm, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;

@@ -36,7 +36,8 @@ __global__ void __launch_bounds__(256) k_window_records(const int32_t *__restric
 // The tiles of the tile column that holds array column `col`, one per
 // workgroup of push_waves(T) wavefronts, each streaming the run of the
 // section the push kernel would give it.  A particle in column `col` leaves
-// (cell = -1, direction kDirRemoved); every other particle stays.
+// (its cell marked kTCellRemoved, direction kDirRemoved); every other
+// particle stays.  The particles are sorted: each lies in its own tile.
 template <int T>
 __global__ void __launch_bounds__(64 * push_waves(T)) k_window_remove(WindowSpecies w, int ntx, int col)
 {
@@ -52,8 +53,9 @@ __global__ void __launch_bounds__(64 * push_waves(T)) k_window_remove(WindowSpec
         const int i = cb + lane;
         bool leaves = false;
         if (i >= lo && i < hi) {
-            leaves = (w.p.cell[i] & 0xffff) == col;
-            if (leaves) w.p.cell[i] = -1;
+            // sorted: the cell is relative to the tile modulo T
+            leaves = (tcell_x(w.p.cell[i]) & (T - 1)) == (col & (T - 1));
+            if (leaves) w.p.cell[i] = (int16_t)kTCellRemoved;
         }
         const unsigned long long m = __ballot(leaves);
         if (leaves) {
@@ -79,10 +81,12 @@ __global__ void __launch_bounds__(64 * push_waves(T)) k_window_remove(WindowSpec
 }
 
 // The new particles, given in window column nx - 1, into array column `col`:
-// dst[i] = col | iy << 16.  Anything else sets kErrOrder (and is written
-// clamped into the grid, so later kernels of the same call stay in bounds).
-__global__ void __launch_bounds__(256) k_place_new(const int32_t *__restrict__ src, int32_t *__restrict__ dst, int n,
-                                                   int nx, int ny, int col, int *err)
+// dst[i] = col | iy << 16 and, relative to their tile, ldst[i].  Anything
+// else sets kErrOrder (and is written clamped into the grid, so later kernels
+// of the same call stay in bounds).
+__global__ void __launch_bounds__(256) k_place_new(const int32_t *__restrict__ src, int32_t *__restrict__ dst,
+                                                   int16_t *__restrict__ ldst, int n, int nx, int ny, int col,
+                                                   int tile, int *err)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -90,7 +94,9 @@ __global__ void __launch_bounds__(256) k_place_new(const int32_t *__restrict__ s
     const int ix = c & 0xffff, iy = c >> 16;
     const bool ok = c >= 0 && ix == nx - 1 && iy < ny;
     if (!ok) atomicOr(err, kErrOrder);
-    dst[i] = col | ((ok ? iy : 0) << 16);
+    const int jy = ok ? iy : 0;
+    dst[i] = col | (jy << 16);
+    ldst[i] = (int16_t)tcell_pack(col & (tile - 1), jy & (tile - 1));
 }
 
 __global__ void __launch_bounds__(256) k_zero_i32(int32_t *__restrict__ p, int n)
@@ -126,9 +132,12 @@ void launch_window_remove(int tile, const WindowSpecies &w, int ntx, int nty, in
     }
 }
 
-void launch_place_new(const int32_t *src, int32_t *dst, int n, int nx, int ny, int col, int *err, hipStream_t s)
+void launch_place_new(const int32_t *src, int32_t *dst, int16_t *ldst, int n, int nx, int ny, int col, int tile,
+                      int *err, hipStream_t s)
 {
-    if (n > 0) hipLaunchKernelGGL(k_place_new, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, n, nx, ny, col, err);
+    if (n > 0)
+        hipLaunchKernelGGL(k_place_new, dim3((n + 255) / 256), dim3(256), 0, s, src, dst, ldst, n, nx, ny, col, tile,
+                           err);
 }
 
 }  // namespace pic

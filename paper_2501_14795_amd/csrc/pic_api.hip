@@ -25,6 +25,7 @@ struct Layout {
     size_t off[kMaxSpecies][2] = {}, cnt[kMaxSpecies] = {}, leav[kMaxSpecies] = {};
     size_t hole[kMaxSpecies] = {}, stg[kMaxSpecies][6] = {}, mcount[kMaxSpecies] = {}, bsum[kMaxSpecies] = {};
     size_t lrec[kMaxSpecies] = {}, srec[kMaxSpecies] = {}, fcount[kMaxSpecies] = {}, fbase[kMaxSpecies] = {};
+    size_t lcell[kMaxSpecies] = {};
     size_t total = 0;
 };
 
@@ -117,6 +118,8 @@ Layout make_layout(const pic_config *c)
     for (int s = 0; s < c->n_species; ++s) {
         // per-particle scratch sized for the capacity (the window changes n)
         const size_t n = (size_t)(c->species[s].cap ? c->species[s].cap : c->species[s].n);
+        // the tile-relative cells the kernels stream (16 bits each)
+        L.lcell[s] = take(n * sizeof(int16_t));
         L.off[s][0] = take((n_tiles + 1) * sizeof(int32_t));
         L.off[s][1] = take((n_tiles + 1) * sizeof(int32_t));
         L.cnt[s] = take((size_t)n_tiles * kCntStride * sizeof(int32_t));
@@ -130,7 +133,7 @@ Layout make_layout(const pic_config *c)
         // initial grouping's scratch), and the motion-class sort's six arrays
         L.srec[s] = take(n * sizeof(LeaverRec));
         if (c->flags & PIC_FLAG_MOTION_SORT)
-            for (int k = 0; k < 6; ++k) L.stg[s][k] = take(n * 4);
+            for (int k = 0; k < 6; ++k) L.stg[s][k] = take(n * (k == 0 ? sizeof(int16_t) : sizeof(float)));
         L.mcount[s] = take((size_t)3 * n_tiles * sizeof(int32_t));   // movers (motion sort: class bases)
         L.fcount[s] = take((size_t)n_tiles * sizeof(int32_t));       // pending fill per tile
         L.fbase[s] = take((size_t)n_tiles * push_waves(T) * sizeof(int32_t));
@@ -168,6 +171,7 @@ struct pic_sim {
     int device;         // the device current at pic_init
     bool have_snapshot;
     struct Sp {
+        int16_t *lcell;  // the tile-relative cells the push and the sort stream
         int32_t *off;    // current tile_offset
         int32_t *offp;   // the tile_offset before the sort (scratch)
         int32_t *cnt;
@@ -176,7 +180,7 @@ struct pic_sim {
         Parts stg;         // the motion-class sort's staging (null without PIC_FLAG_MOTION_SORT)
         LeaverRec *srec;   // the in-place sort's mover staging (every simulation)
         LeaverRec *lrec;   // the push's leaver records
-        Parts lp;          // the same memory as six arrays of n values (full re-sort scratch)
+        GParts lp;         // the same memory as six arrays of n values (the initial grouping's scratch)
         int32_t *mcount;
         int32_t *fcount;   // holes whose fill a deferred sort left to the next push
         int32_t *fbase;
@@ -416,10 +420,11 @@ PushArgs push_args(const pic_sim *S, bool bh)
     a.ju[1] = (float)(qmax * c.dy / c.dt / scale);
     a.ju[2] = (float)(qmax / scale);
     a.n_species = c.n_species;
+    a.rebase = S->since_sort == 0 ? 1 : 0;   // batched pushes take theirs from the launch
     for (int s = 0; s < c.n_species; ++s) {
         const pic_particles &p = S->buf.sp[s];
         SpeciesDev &d = a.sp[s];
-        d.cell = p.cell;
+        d.cell = S->sp[s].lcell;
         d.x = p.x;
         d.y = p.y;
         d.ux = p.ux;
@@ -488,7 +493,8 @@ SortArgs sort_args(const pic_sim *S, bool defer = false)
         const pic_particles &p = S->buf.sp[s];
         const auto &P = S->sp[s];
         SortSpecies &d = a.sp[s];
-        d.p.cell = p.cell;
+        d.p.cell = P.lcell;
+        d.gcell = p.cell;
         d.p.x = p.x;
         d.p.y = p.y;
         d.p.ux = p.ux;
@@ -586,7 +592,7 @@ TileSortArgs tile_sort_args(pic_sim *S, int s)
     const pic_particles &b = S->buf.sp[s];
     const int n = (int)S->cfg.species[s].n;
     TileSortArgs t;
-    t.p = Parts{b.cell, b.x, b.y, b.ux, b.uy, b.uz};
+    t.p = GParts{b.cell, b.x, b.y, b.ux, b.uy, b.uz};
     t.tmp = P.lp;
     t.key[0] = (uint32_t *)P.hole;
     t.key[1] = P.leav;
@@ -625,6 +631,7 @@ int build_tiles(pic_sim *S, hipStream_t stream)
             launch_tile_sort(tile_sort_args(S, s), stream);
             rc = hip_ok(hipGetLastError());
         }
+        if (rc == PIC_OK) launch_localize(S->buf.sp[s].cell, P.lcell, n, c.tile, stream);
         if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(P.mcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
         if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(P.fcount, 0, (size_t)S->n_tiles * sizeof(int32_t), stream));
     }
@@ -695,9 +702,10 @@ int init_sim(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
         P.cnt = (int32_t *)(w + L.cnt[s]);
         P.leav = (uint32_t *)(w + L.leav[s]);
         P.hole = (int32_t *)(w + L.hole[s]);
+        P.lcell = (int16_t *)(w + L.lcell[s]);
         auto parts_at = [&](const size_t *o) {
             Parts q;
-            q.cell = (int32_t *)(w + o[0]);
+            q.cell = (int16_t *)(w + o[0]);
             q.x = (float *)(w + o[1]);
             q.y = (float *)(w + o[2]);
             q.ux = (float *)(w + o[3]);
@@ -713,7 +721,8 @@ int init_sim(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
             size_t o[6];
             const size_t n = (size_t)(cfg->species[s].cap ? cfg->species[s].cap : cfg->species[s].n);
             for (int k = 0; k < 6; ++k) o[k] = L.lrec[s] + align_up((size_t)k * n * 4);
-            P.lp = parts_at(o);
+            P.lp = GParts{(int32_t *)(w + o[0]), (float *)(w + o[1]), (float *)(w + o[2]), (float *)(w + o[3]),
+                          (float *)(w + o[4]), (float *)(w + o[5])};
         }
         P.mcount = (int32_t *)(w + L.mcount[s]);
         P.fcount = (int32_t *)(w + L.fcount[s]);
@@ -859,12 +868,16 @@ static int sort_after_push(pic_sim *S, hipStream_t stream, bool defer)
 }
 
 // A fill left pending by pic_step's sort, done before anything but a push
-// reads the particle arrays.  Always launched: the device fill counts, not
-// the host, know whether a fill is pending (replays of a captured step run
-// no host code); a tile with none costs one read.
-static int settle(pic_sim *S, hipStream_t stream)
+// reads the particle arrays, and (publish) the whole-grid cells written into
+// the caller's cell arrays from the tile-relative ones the kernels keep.
+// Always launched: the device fill counts, not the host, know whether a fill
+// is pending (replays of a captured step run no host code); a tile with none
+// costs one read.
+static int settle(pic_sim *S, hipStream_t stream, bool publish = true)
 {
-    launch_fill(sort_args(S), S->n_tiles, stream);
+    const SortArgs a = sort_args(S);
+    launch_fill(a, S->n_tiles, stream);
+    if (publish) launch_publish(a, S->n_tiles, S->since_sort == 0, stream);
     return hip_ok(hipGetLastError());
 }
 
@@ -892,7 +905,7 @@ int pic_move_window(pic_sim *S, const pic_particles *inject, const int64_t *n_in
 {
     if (!S || !(S->cfg.flags & PIC_FLAG_MOVING_WINDOW)) return PIC_EINVAL;
     if (S->since_sort != 0) return PIC_EORDER;   // the last push is not sorted yet
-    if (const int rs = settle(S, stream)) return rs;
+    if (const int rs = settle(S, stream, false)) return rs;   // the window reads the tile-relative cells
     pic_config &c = S->cfg;
     int64_t k[kMaxSpecies] = {};
     for (int s = 0; s < c.n_species; ++s) {
@@ -907,6 +920,7 @@ int pic_move_window(pic_sim *S, const pic_particles *inject, const int64_t *n_in
     // array column of window column 0 now, and of window column nx - 1 after the move
     const int col = S->origin;
     SortArgs a = sort_args(S);
+    a.rebase = 1;   // sorted: no push since the last sort
     int rc = PIC_OK;
     // 1. the new particles into the unused slots after the existing ones, their
     //    cells moved to array column col, and checked (window column nx - 1,
@@ -922,7 +936,7 @@ int pic_move_window(pic_sim *S, const pic_particles *inject, const int64_t *n_in
         for (int f = 0; f < 5 && rc == PIC_OK; ++f)
             rc = hip_ok(hipMemcpyAsync(dst[f], src[f], bytes, hipMemcpyDeviceToDevice, stream));
         if (rc) break;
-        launch_place_new(q.cell, p.cell + n0, (int)k[s], c.nx, c.ny, col, S->err, stream);
+        launch_place_new(q.cell, p.cell + n0, P.lcell + n0, (int)k[s], c.nx, c.ny, col, c.tile, S->err, stream);
         launch_init_tiles(p.cell + n0, (int32_t)k[s], c.nx, c.ny, c.tile, S->ntx, S->n_tiles, P.inj_off, S->err,
                           stream);
         a.sp[s].inj_off = P.inj_off;
@@ -1327,15 +1341,15 @@ BatchLayout batch_layout(int n, const pic_config *cfgs)
 }
 
 // One step of every member; the sort only when `sort` is set (the last step
-// of a cadence cycle).
-void batch_enqueue_step(pic_batch *b, bool sort, hipStream_t stream)
+// of a cadence cycle); rebase: the first step after a sort.
+void batch_enqueue_step(pic_batch *b, bool sort, bool rebase, hipStream_t stream)
 {
     launch_set_int(b->counter, 0, stream);
     {
         // member 0's event timing, if on, times the batch's push launch
         Timed t(b->sims[0], PIC_KERNEL_PUSH, stream);
         launch_push_batch(b->tile, b->replicas, b->jm, b->dm, b->halo, b->ppl, b->d_push, b->push_items,
-                          b->n_push, b->counter, b->push_grid, stream);
+                          b->n_push, b->counter, b->push_grid, rebase, stream);
     }
     // with a sort, the field half goes to the second stream (disjoint data)
     const bool fork = sort && b->side;
@@ -1513,7 +1527,7 @@ int pic_batch_step(pic_batch *B, int nsteps, hipStream_t stream)
             k += B->halo;
         } else {
             const bool sort = B->phase + 1 == B->halo;
-            batch_enqueue_step(B, sort, stream);
+            batch_enqueue_step(B, sort, B->phase == 0, stream);
             B->phase = sort ? 0 : B->phase + 1;
             k += 1;
         }
@@ -1535,7 +1549,7 @@ int pic_batch_capture(pic_batch *B, hipStream_t stream)
         B->graph = nullptr;
     }
     if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PIC_EHIP;
-    for (int k = 0; k < B->halo; ++k) batch_enqueue_step(B, k + 1 == B->halo, stream);
+    for (int k = 0; k < B->halo; ++k) batch_enqueue_step(B, k + 1 == B->halo, k == 0, stream);
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(stream, &g) != hipSuccess || !g) return PIC_EHIP;
     B->graph = g;
@@ -1565,6 +1579,7 @@ int pic_batch_sync(pic_batch *B, hipStream_t stream)
     sb.n_plan = B->n_plan;
     sb.max_blocks = B->max_blocks;
     launch_fill_batch(sb, stream);   // members without a pending fill have zero fill counts
+    launch_publish_batch(sb, B->phase == 0, stream);
     return hip_ok(hipGetLastError());
 }
 

@@ -11,7 +11,8 @@
 namespace pic {
 
 struct SortSpecies {
-    Parts p;              // the particle arrays
+    Parts p;              // the particle arrays (tile-relative cells)
+    int32_t *gcell;       // the caller's cell array: whole-grid cells, written by the publish
     const LeaverRec *lrec;   // leaver particle data written by the push kernel
     Parts stg;            // the motion-class sort's staging, [n]: every particle at its new slot
     LeaverRec *srec;      // the in-place sort's mover staging, [n]: tile t's movers at off[t] + k, in hole order
@@ -40,6 +41,8 @@ struct SortArgs {
     int n_tiles;
     int n_species;
     int defer;            // 1: the scatter leaves the holes to the next push (pic_step)
+    int rebase;           // 1: no push since the last sort (the moving window's sort): cells are
+                          // relative to their tile modulo its edge
     SortSpecies sp[kMaxSpecies];
 };
 
@@ -67,8 +70,9 @@ struct FieldArgs {
 void launch_push_deposit(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs &a,
                          int n_tiles, hipStream_t s);
 void launch_j_reduce(int tile, int halo, const JReduceArgs &r, hipStream_t s);
+// rebase: the pushes follow a sort (PushArgs::rebase of every member)
 void launch_push_batch(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs *descs,
-                       const int4 *items, int n_items, int *counter, int grid, hipStream_t s);
+                       const int4 *items, int n_items, int *counter, int grid, bool rebase, hipStream_t s);
 void launch_j_reduce_batch(int tile, int halo, const JReduceArgs *descs, const int4 *items, int n_items,
                            hipStream_t s);
 void launch_set_int(int *p, int v, hipStream_t s);
@@ -76,6 +80,11 @@ void launch_sort_scan(const SortArgs &a, int n_tiles, hipStream_t s);
 void launch_sort_plan(const SortArgs &a, int n_tiles, hipStream_t s);
 void launch_sort_scatter(const SortArgs &a, int n_tiles, hipStream_t s);
 void launch_fill(const SortArgs &a, int n_tiles, hipStream_t s);
+// the whole-grid cells of every particle into the caller's cell arrays
+// (gcell); rebase: no push since the last sort
+void launch_publish(const SortArgs &a, int n_tiles, bool rebase, hipStream_t s);
+// tile-relative cells of n particles grouped by tile, inside their tiles
+void launch_localize(const int32_t *cell, int16_t *lcell, int32_t n, int tile, hipStream_t s);
 
 // Batched sort phases.  Work tables (int4 per block):
 //   count/add: (sim, species, block of kScanBlock tiles)   scan: (sim, species)
@@ -87,8 +96,9 @@ struct SortBatch {
     const int4 *plan_items; int n_plan;
     int max_blocks;   // the most scan blocks of one member
 };
-// a pending hole fill of every member (fill_unit)
+// a pending hole fill of every member (fill_unit), and the publish of their cells
 void launch_fill_batch(const SortBatch &b, hipStream_t s);
+void launch_publish_batch(const SortBatch &b, bool rebase, hipStream_t s);
 // motion: the motion-class sort (PIC_FLAG_MOTION_SORT) instead of the in-place one
 void launch_sort_batch(const SortBatch &b, bool motion, hipStream_t s);
 // the motion-class sort after the recount and scan: every particle into the
@@ -103,8 +113,8 @@ void launch_init_tiles(const int32_t *cell, int32_t n, int nx, int ny, int tile,
 // grouping caller particles by tile: stable radix sort on the tile id
 // (k_tilesort.hip), in place on p
 struct TileSortArgs {
-    Parts p;                     // n each: the particle arrays
-    Parts tmp;                   // n each: a copy of them is made here
+    GParts p;                    // n each: the particle arrays (the caller's, whole-grid cells)
+    GParts tmp;                  // n each: a copy of them is made here
     uint32_t *key[2], *val[2];   // n each: double buffers
     int32_t *hist;               // tile_sort_hist_entries(n)
     int n, tile, ntx, n_tiles;
@@ -124,15 +134,17 @@ void launch_zero_i32(int32_t *p, int n, hipStream_t s);
 // of every tile in the push kernel's format (no leaver copies: a removed
 // particle is nobody's mover)
 struct WindowSpecies {
-    Parts p;
+    Parts p;                     // tile-relative cells
     const int32_t *off;
     int32_t *cnt;
     uint32_t *leav;
     int32_t *removed;   // device count of the particles that left
 };
 void launch_window_remove(int tile, const WindowSpecies &w, int ntx, int nty, int n_tiles, int col, hipStream_t s);
-// new particles given in window column nx - 1 into array column col (checked)
-void launch_place_new(const int32_t *src, int32_t *dst, int n, int nx, int ny, int col, int *err, hipStream_t s);
+// new particles given in window column nx - 1 into array column col (checked):
+// whole-grid cells to dst, and cells relative to their tiles (of edge tile) to ldst
+void launch_place_new(const int32_t *src, int32_t *dst, int16_t *ldst, int n, int nx, int ny, int col, int tile,
+                      int *err, hipStream_t s);
 void launch_filter(const FilterArgs &a, bool fp64, hipStream_t s);
 void launch_filter_batch(const FilterArgs *descs, const int4 *items, int n_items, hipStream_t s);
 // the three Yee sub-steps (k_field.hip); with f.jtile set, the E step folds

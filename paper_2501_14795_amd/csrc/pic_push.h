@@ -121,8 +121,33 @@ constexpr bool cadence_ok(int T, int H)
     return (H == 1 || H == 2 || H == 4) && 2 * H + 1 <= T && push_lds_bytes(T, 1, kJFixed, H) <= kLdsBytes;
 }
 
-// One species' particles as a structure of arrays (n entries each).
+// The cell of a particle as the push and the sort stream it: 16 bits, the
+// cell's offset (lx, ly) from the first cell of the tile whose section holds
+// the particle, each a signed byte, lx | ly << 8.  Inside the tile both lie
+// in [0, tile); a particle that has left it is up to a few cells outside,
+// across the periodic seam too (no wrap: the offset says which neighbour it
+// went to).  The sort copies the particles it moves with their cells
+// relative to their new tile, but one that entered a tile and already sits
+// in that tile's new section stays where it is, its cell still relative to
+// the tile it came from: so in a sorted state (no push since the last sort)
+// a cell is relative to its tile modulo the tile edge, and every reader
+// then takes it modulo the edge.  The caller's arrays keep the whole-grid
+// cell ix | iy << 16, written from these when the caller is to read them.
+__host__ __device__ __forceinline__ int tcell_pack(int lx, int ly) { return (lx & 0xff) | ((ly & 0xff) << 8); }
+__device__ __forceinline__ int tcell_x(int c) { return __builtin_amdgcn_sbfe(c, 0, 8); }
+__device__ __forceinline__ int tcell_y(int c) { return __builtin_amdgcn_sbfe(c, 8, 8); }
+// a particle that left the moving window: (-128, -128), no tile
+constexpr int kTCellRemoved = 0x8080;
+
+// One species' particles as the kernels stream them: a structure of arrays
+// (n entries each), tile-relative cells.
 struct Parts {
+    int16_t *cell;
+    float *x, *y, *ux, *uy, *uz;
+};
+
+// The same with whole-grid cells ix | iy << 16 (the caller's arrays).
+struct GParts {
     int32_t *cell;
     float *x, *y, *ux, *uy, *uz;
 };
@@ -151,7 +176,7 @@ __device__ __forceinline__ void put_leaver(LeaverRec *r, int64_t q, int cell, fl
 }
 
 struct SpeciesDev {
-    int32_t *cell;
+    int16_t *cell;        // tile-relative cells (tcell_pack)
     float *x, *y, *ux, *uy, *uz;
     const int32_t *off;   // tile_offset at the start of the step (n_tiles + 1)
     int32_t *cnt;         // [n_tiles][kCntStride]
@@ -180,6 +205,7 @@ struct PushArgs {
     float cx, cy;         // dt/dx, dt/dy
     float ju[3];          // accumulator unit -> physical Jx, Jy, Jz
     int n_species;
+    int rebase;           // the push follows a sort: each cell is relative to the tile modulo its edge
     SpeciesDev sp[kMaxSpecies];
 };
 

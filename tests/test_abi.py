@@ -81,10 +81,10 @@ def test_query_sizes_and_validation():
     assert s.n_tiles == 16 and s.field_bytes == 9 * 64 * 64 * 4 and s.work_bytes > 0
     big = L.pic_query(_cfg(L, nx=2048, ny=2048, n=2048 * 2048 * 16))
     assert big.n_tiles == 128 * 128
-    # workspace grows linearly with particles (leaver entries 4 B + 32-B leaver records, holes 4 B,
-    # 32-B mover staging records: 72 B/particle)
+    # workspace grows linearly with particles (the 16-bit tile-relative cells 2 B, leaver
+    # entries 4 B + 32-B leaver records, holes 4 B, 32-B mover staging records: 74 B/particle)
     s2 = L.pic_query(_cfg(L, n=2000))
-    assert 72 * 1000 <= s2.work_bytes - s.work_bytes <= 72 * 1000 + 16 * 256
+    assert 74 * 1000 <= s2.work_bytes - s.work_bytes <= 74 * 1000 + 16 * 256
     cases = [
         (dict(dt=0.0708), L.PIC_ECFL),          # Eq. (1): limit 0.070711 at dx = dy = 0.1
         (dict(dt=0.08), L.PIC_ECFL),
@@ -135,10 +135,10 @@ def test_query_sizes_and_validation():
     assert L.pic_query(_cfg(L, nx=64, tile=32, reps=4)).n_tiles == 4     # int64 current x 4: 158 KB
     assert L.pic_query(_cfg(L, nx=64, tile=32, every=4)).n_tiles == 4    # halo pad 4: 91 KB
     assert L.pic_query(_cfg(L, flags=L.PIC_FLAG_ESIRKEPOV)).work_bytes == s.work_bytes
-    # the motion-class sort stages in six more arrays (24 B/particle); the in-place sort's
-    # 32-byte records stay (the moving window's sort is the in-place one)
+    # the motion-class sort stages in six more arrays (22 B/particle: 16-bit cells); the
+    # in-place sort's 32-byte records stay (the moving window's sort is the in-place one)
     m = L.pic_query(_cfg(L, flags=L.PIC_FLAG_MOTION_SORT)).work_bytes
-    assert s.work_bytes + 24 * 1000 <= m <= s.work_bytes + 24 * 1000 + 16 * 256
+    assert s.work_bytes + 22 * 1000 <= m <= s.work_bytes + 22 * 1000 + 16 * 256
     # capacity: per-particle scratch sized for it; below n is invalid
     c = _cfg(L)
     c.species[0].cap = 2000
