@@ -30,7 +30,10 @@
  *   - pic_step() and pic_batch_step() leave the last part of their sort, the
  *     copy of the staged movers into their holes, to the next push, which
  *     streams those slots anyway: until then the particle arrays hold stale
- *     values in those slots.  Every entry point that reads the particles
+ *     values in those slots.  With PIC_FLAG_MOTION_SORT, pic_step() likewise
+ *     leaves the sorted particles in the workspace's staging arrays, where
+ *     the next push reads them (the particle arrays hold the unsorted ones
+ *     until then).  Every entry point that reads the particles
  *     (pic_get_state, pic_diag, pic_move_window, the Gauss solves, and of
  *     course the next push) completes it first.  A caller that reads the
  *     particle arrays itself calls pic_sync() before: it completes the fill
@@ -130,7 +133,9 @@ extern "C" {
  * pass, to its slot in the order (new tile, class, old slot) in the
  * workspace, and copies the result back: out of place, reading and writing
  * every particle twice, so it pays only when most particles change tile.
- * Also in batched mode.  pic_diag's mover count is 0 with it.  The moving
+ * In pic_step() (with the default current and deposit) the copy back is
+ * left to the next push, which reads the particles from the workspace
+ * (see the memory model).  Also in batched mode (copied back at once).  pic_diag's mover count is 0 with it.  The moving
  * window keeps its own (in-place) re-sort.
  */
 #define PIC_FLAG_MOTION_SORT 8u
@@ -245,10 +250,11 @@ int pic_sort(pic_sim *sim, hipStream_t stream);
 
 /*
  * Bring the caller's particle arrays up to date (see the memory model):
- * completes the hole fill that pic_step()'s or pic_batch_step()'s sort left
- * to the next push (the staged movers into their holes; nothing if none is
- * pending) and writes every particle's cell, ix | iy << 16, into the cell
- * array.  Enqueues two kernels on `stream` without synchronising.
+ * completes what pic_step()'s or pic_batch_step()'s sort left to the next
+ * push (the staged movers into their holes, or the motion-class sort's
+ * staging arrays copied back; nothing if none is pending) and writes every
+ * particle's cell, ix | iy << 16, into the cell array.  Enqueues its kernels
+ * on `stream` without synchronising.
  */
 int pic_sync(pic_sim *sim, hipStream_t stream);
 

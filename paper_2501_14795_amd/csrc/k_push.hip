@@ -62,9 +62,24 @@ struct Stream6 {
     __amdgpu_buffer_rsrc_t cell, x, y, ux, uy, uz;
 };
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(void *base, int bytes)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base, int bytes)
 {
-    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, bytes, kRsrcWord3);
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, kRsrcWord3);
+}
+
+// Views of six particle arrays from slot `base`, `bytes` bytes of the 32-bit ones.
+__device__ __forceinline__ Stream6 stream6(const int16_t *cell, const float *x, const float *y, const float *ux,
+                                           const float *uy, const float *uz, int base, int bytes)
+{
+    Stream6 s;
+    s.cell = rsrc(cell + base, bytes / 2);
+    s.x = rsrc(x + base, bytes);
+    s.y = rsrc(y + base, bytes);
+    s.ux = rsrc(ux + base, bytes);
+    s.uy = rsrc(uy + base, bytes);
+    s.uz = rsrc(uz + base, bytes);
+    return s;
 }
 
 // Cache policy of the particle stream's buffer loads and stores: the
@@ -494,7 +509,7 @@ __device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool
 // One tile of one simulation, by the whole workgroup (push_waves(T) wavefronts).
 // C: particles per lane per pass of the particle loop (64-particle chunks
 // carried side by side).
-template <int T, int R, int JM, int DM, int H, int C>
+template <int T, int R, int JM, int DM, int H, int C, bool MS = false>
 __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile, const bool rebase)
 {
     static_assert(cadence_ok(T, H), "halo pad not supported for this tile");
@@ -554,6 +569,12 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile, con
 
     Acc *sj = s_j[R > 1 ? lane % R : 0];
     const bool tx_wrap = a.ntx > 1, ty_wrap = a.nty > 1;
+    // MS: the simulation's sort is the motion-class one, whose last pass --
+    // the staging arrays copied back -- may have been left to this push: the
+    // particles are then read from the staging arrays (the flag is cleared
+    // by the next launch after this kernel)
+    bool from_stg = false;
+    if constexpr (MS) from_stg = *gp(a.stg_live) != 0;
 
     for (int s = 0; s < a.n_species; ++s) {
         const SpeciesDev sp = a.sp[s];
@@ -568,13 +589,10 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile, con
             // touching memory
             const int base = (begin >> 6) << 6;
             const int bytes = (hi - base) * 4;
-            Stream6 st;
-            st.cell = rsrc(sp.cell + base, bytes / 2);
-            st.x = rsrc(sp.x + base, bytes);
-            st.y = rsrc(sp.y + base, bytes);
-            st.ux = rsrc(sp.ux + base, bytes);
-            st.uy = rsrc(sp.uy + base, bytes);
-            st.uz = rsrc(sp.uz + base, bytes);
+            const Stream6 st = stream6(sp.cell, sp.x, sp.y, sp.ux, sp.uy, sp.uz, base, bytes);   // the particle arrays
+            // MS: the loads' view, the staging arrays or the same
+            const Stream6 ld = MS && from_stg ? stream6(sp.scell, sp.sx, sp.sy, sp.sux, sp.suy, sp.suz, base, bytes)
+                                              : st;
             const float h = sp.h, fq = sp.fq;
             // The fill the last sort left (holes of the section, ascending,
             // whose particles wait in the staging records): a window of 64 of
@@ -697,7 +715,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile, con
             bool nany[C];
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                nxt[c] = load_chunk(st, off + 256 * c);
+                nxt[c] = load_chunk(ld, off + 256 * c);
                 nref[c] = fill_ref(cb + 64 * c, nany[c]);
                 nstg[c] = Chunk{};
                 fill_load(nstg[c], nref[c]);
@@ -709,7 +727,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile, con
                 for (int c = 0; c < C; ++c) {
                     cur[c] = nxt[c];
                     if (nany[c] && nref[c] >= 0) cur[c] = nstg[c];   // a hole: its particle from the fill
-                    nxt[c] = load_chunk(st, off + 256 * (C + c));
+                    nxt[c] = load_chunk(ld, off + 256 * (C + c));
                     nref[c] = fill_ref(cb + 64 * (C + c), nany[c]);
                     fill_load(nstg[c], nref[c]);
                 }
@@ -818,10 +836,10 @@ constexpr int push_waves_per_simd()
     return C > 2 && push_min_waves(T, R, JM, H) > 2 ? 2 : push_min_waves(T, R, JM, H);
 }
 
-template <int T, int R, int JM, int DM, int H, int C>
+template <int T, int R, int JM, int DM, int H, int C, bool MS>
 __global__ void __launch_bounds__(64 * push_waves(T), (push_waves_per_simd<T, R, JM, DM, H, C>())) k_push_deposit(PushArgs a)
 {
-    push_tile<T, R, JM, DM, H, C>(a, blockIdx.x, a.rebase != 0);
+    push_tile<T, R, JM, DM, H, C, MS>(a, blockIdx.x, a.rebase != 0);
 }
 
 // Many simulations in one launch: a persistent grid takes (simulation, tile)
@@ -880,10 +898,10 @@ __global__ void __launch_bounds__(256) k_j_reduce_batch(const JReduceArgs *__res
     j_reduce_block<T, H>(descs[w.x], w.y, w.z);
 }
 
-template <int T, int R, int JM, int DM, int H, int C>
+template <int T, int R, int JM, int DM, int H, int C, bool MS>
 static void launch_pd(const PushArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_push_deposit<T, R, JM, DM, H, C>), dim3(n_tiles), dim3(64 * push_waves(T)), 0, s, a);
+    hipLaunchKernelGGL((k_push_deposit<T, R, JM, DM, H, C, MS>), dim3(n_tiles), dim3(64 * push_waves(T)), 0, s, a);
 }
 
 template <int T, int R, int JM, int DM, int H, int C>
@@ -906,13 +924,24 @@ struct PushLaunch {
     int *counter;
     int grid;
     int rebase;               // batched: the pushes follow a sort
+    int ms;                   // single: the particles may wait in the motion-class sort's staging arrays
     hipStream_t s;
     template <int T, int R, int JM, int DM, int H, int C>
     void go() const
     {
         if constexpr (push_lds_bytes(T, R, JM, H) <= kLdsBytes && cadence_ok(T, H)) {
-            if (single) launch_pd<T, R, JM, DM, H, C>(*single, n_tiles, s);
-            else launch_pb<T, R, JM, DM, H, C>(descs, items, n_items, counter, grid, rebase, s);
+            if (single) {
+                // the reading of the staging arrays is built for the default current and deposit
+                if constexpr (R == 1 && JM == kJFixed && DM == kDepVB) {
+                    if (ms) {
+                        launch_pd<T, R, JM, DM, H, C, true>(*single, n_tiles, s);
+                        return;
+                    }
+                }
+                launch_pd<T, R, JM, DM, H, C, false>(*single, n_tiles, s);
+            } else {
+                launch_pb<T, R, JM, DM, H, C>(descs, items, n_items, counter, grid, rebase, s);
+            }
         }
     }
 };
@@ -973,16 +1002,16 @@ static void push_t(const PushLaunch &L, int tile, int replicas, int jmode, int d
 }
 
 void launch_push_deposit(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs &a,
-                         int n_tiles, hipStream_t s)
+                         int n_tiles, bool ms, hipStream_t s)
 {
-    PushLaunch L{&a, n_tiles, nullptr, nullptr, 0, nullptr, 0, 0, s};
+    PushLaunch L{&a, n_tiles, nullptr, nullptr, 0, nullptr, 0, 0, ms ? 1 : 0, s};
     push_t(L, tile, replicas, jmode, dmode, halo, ppl);
 }
 
 void launch_push_batch(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs *descs,
                        const int4 *items, int n_items, int *counter, int grid, bool rebase, hipStream_t s)
 {
-    PushLaunch L{nullptr, 0, descs, items, n_items, counter, grid, rebase ? 1 : 0, s};
+    PushLaunch L{nullptr, 0, descs, items, n_items, counter, grid, rebase ? 1 : 0, 0, s};
     push_t(L, tile, replicas, jmode, dmode, halo, ppl);
 }
 

@@ -572,9 +572,14 @@ struct Part6 {
     float x, y, ux, uy, uz;
 };
 
+// A whole-array pass of the motion-class sort reads every particle once, so
+// its loads carry the non-temporal hint (as the push's particle stream
+// does); its stores start mid-line (class runs), where the hint costs.
 __device__ __forceinline__ Part6 load_part(const Parts &p, int i)
 {
-    return Part6{p.cell[i], p.x[i], p.y[i], p.ux[i], p.uy[i], p.uz[i]};
+    return Part6{__builtin_nontemporal_load(p.cell + i), __builtin_nontemporal_load(p.x + i),
+                 __builtin_nontemporal_load(p.y + i),    __builtin_nontemporal_load(p.ux + i),
+                 __builtin_nontemporal_load(p.uy + i),   __builtin_nontemporal_load(p.uz + i)};
 }
 
 __device__ __forceinline__ void store_part(const Parts &p, int i, const Part6 &v)
@@ -587,13 +592,14 @@ __device__ __forceinline__ void store_part(const Parts &p, int i, const Part6 &v
     p.uz[i] = v.uz;
 }
 
-// The kSortWaves source tiles of group grp, one after the other, each by the
-// whole block: the section's 64-aligned chunks are split into one run per
+// The nt source tiles from tile t0 on, one after the other, each by the whole
+// block: the section's 64-aligned chunks are split into one run per
 // wavefront; a first pass counts every run's particles per class, a second
 // streams the runs again and moves each particle to its slot (its class's
 // first slot in the destination, the class's particles in the earlier runs,
-// its rank in its chunk).
-__device__ __forceinline__ void motion_scatter_unit(const SortArgs &a, int spi, int grp)
+// its rank in its chunk).  One tile per block for a single simulation (many
+// wavefronts in flight), kSortWaves per work item in a batch.
+__device__ __forceinline__ void motion_scatter_unit(const SortArgs &a, int spi, int t0, int nt)
 {
     constexpr int W = kSortWaves;
     __shared__ int s_cls[W][9];
@@ -602,8 +608,8 @@ __device__ __forceinline__ void motion_scatter_unit(const SortArgs &a, int spi, 
     const SortSpecies &sp = a.sp[spi];
     const int ntx = a.ntx, nty = a.nty;
     const int T = a.tile;
-    for (int q = 0; q < kSortWaves; ++q) {
-        const int s = grp * kSortWaves + q;
+    for (int q = 0; q < nt; ++q) {
+        const int s = t0 + q;
         if (s >= a.n_tiles) break;   // uniform over the block
         const int sx = s % ntx, sy = s / ntx;
         const int oA = sp.offp[s], oB = sp.offp[s + 1];
@@ -643,16 +649,18 @@ __device__ __forceinline__ void motion_scatter_unit(const SortArgs &a, int spi, 
             }
             bad = all != total;   // the push's counts and the cells disagree
         }
-        // pass 2: the particles to their slots, the next chunk in flight
+        // pass 2: the particles to their slots, the next two chunks in flight
         int c0 = (lo >> 6) << 6;
-        Part6 nxt{};
-        if (c0 < hi && c0 + lane >= lo && c0 + lane < hi) nxt = load_part(sp.p, c0 + lane);
+        Part6 nxt{}, nxt2{};
+        if (c0 + lane >= lo && c0 + lane < hi) nxt = load_part(sp.p, c0 + lane);
+        if (c0 + 64 + lane >= lo && c0 + 64 + lane < hi) nxt2 = load_part(sp.p, c0 + 64 + lane);
         for (; c0 < hi; c0 += 64) {
             const Part6 cur = nxt;
+            nxt = nxt2;
             const int i = c0 + lane;
             const bool in = i >= lo && i < hi;
-            const int i2 = i + 64;
-            if (i2 >= lo && i2 < hi) nxt = load_part(sp.p, i2);
+            const int i3 = i + 128;
+            if (i3 >= lo && i3 < hi) nxt2 = load_part(sp.p, i3);
             const int d = in ? motion_class(cur.cell, T, ntx, nty) : 10;
             unsigned long long m_d = 0ull;
             int taken = 0;
@@ -679,17 +687,19 @@ __device__ __forceinline__ void motion_scatter_unit(const SortArgs &a, int spi, 
         if (threadIdx.x == 0) sp.mcount[s] = 0;   // pic_diag's mover count: not tracked by this sort
         __syncthreads();   // s_cls is reused by the next tile
     }
+    // the copy back is left to the next push (read by launches after this one)
+    if (a.defer && threadIdx.x == 0) *a.stg_live = 1;
 }
 
-// The new sections of the group's tiles (contiguous) from the staging arrays
-// into the particle arrays, by the whole block, four particles per thread in
-// flight; the new tile_offset replaces the old one.
-__device__ __forceinline__ void motion_copy_unit(const SortArgs &a, int spi, int grp)
+// The new sections of the nt tiles from t0 on (contiguous) from the staging
+// arrays into the particle arrays, by the whole block, four particles per
+// thread in flight; live: only if the copy was left pending (*stg_live).
+__device__ __forceinline__ void motion_copy_unit(const SortArgs &a, int spi, int t0, int nt, bool live = false)
 {
+    if (live && *a.stg_live == 0) return;
     const SortSpecies &sp = a.sp[spi];
-    const int t0 = grp * kSortWaves;
     if (t0 >= a.n_tiles) return;
-    const int t1 = min(t0 + kSortWaves, a.n_tiles);
+    const int t1 = min(t0 + nt, a.n_tiles);
     const int A = sp.off[t0], B = sp.off[t1];
     constexpr int U = 4;
     for (int i0 = A + (int)threadIdx.x; i0 < B; i0 += U * kBlock) {
@@ -755,8 +765,13 @@ __global__ void __launch_bounds__(kBlock) k_publish(SortArgs a, int rebase)
 }
 __global__ void __launch_bounds__(kBlock) k_sort_plan(SortArgs a) { sort_plan_unit(a, blockIdx.y, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_sort_scatter(SortArgs a) { sort_scatter_unit(a, blockIdx.y, blockIdx.x); }
-__global__ void __launch_bounds__(kBlock) k_motion_scatter(SortArgs a) { motion_scatter_unit(a, blockIdx.y, blockIdx.x); }
-__global__ void __launch_bounds__(kBlock) k_motion_copy(SortArgs a) { motion_copy_unit(a, blockIdx.y, blockIdx.x); }
+// single simulation: one tile per block
+__global__ void __launch_bounds__(kBlock) k_motion_scatter(SortArgs a) { motion_scatter_unit(a, blockIdx.y, blockIdx.x, 1); }
+__global__ void __launch_bounds__(kBlock) k_motion_copy(SortArgs a) { motion_copy_unit(a, blockIdx.y, blockIdx.x, 1); }
+__global__ void __launch_bounds__(kBlock) k_motion_copy_live(SortArgs a)
+{
+    motion_copy_unit(a, blockIdx.y, blockIdx.x, 1, true);
+}
 
 // ---- many simulations: one block per work item (sim, species, unit)
 __global__ void __launch_bounds__(kScanBlock) k_sort_count_b(const SortArgs *d, const int4 *it)
@@ -798,12 +813,12 @@ __global__ void __launch_bounds__(kBlock) k_publish_b(const SortArgs *d, const i
 __global__ void __launch_bounds__(kBlock) k_motion_scatter_b(const SortArgs *d, const int4 *it)
 {
     const int4 w = it[blockIdx.x];
-    motion_scatter_unit(d[w.x], w.y, w.z);
+    motion_scatter_unit(d[w.x], w.y, w.z * kSortWaves, kSortWaves);
 }
 __global__ void __launch_bounds__(kBlock) k_motion_copy_b(const SortArgs *d, const int4 *it)
 {
     const int4 w = it[blockIdx.x];
-    motion_copy_unit(d[w.x], w.y, w.z);
+    motion_copy_unit(d[w.x], w.y, w.z * kSortWaves, kSortWaves);
 }
 
 // ---- tile_offset from caller particles: whether every cell is in the grid
@@ -912,14 +927,18 @@ void launch_sort_batch(const SortBatch &b, bool motion, hipStream_t s)
 
 void launch_motion_scatter(const SortArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_motion_scatter, dim3((n_tiles + kSortWaves - 1) / kSortWaves, a.n_species), dim3(kBlock),
-                       0, s, a);
+    hipLaunchKernelGGL(k_motion_scatter, dim3(n_tiles, a.n_species), dim3(kBlock), 0, s, a);
 }
 
 void launch_motion_copy(const SortArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_motion_copy, dim3((n_tiles + kSortWaves - 1) / kSortWaves, a.n_species), dim3(kBlock), 0, s,
-                       a);
+    hipLaunchKernelGGL(k_motion_copy, dim3(n_tiles, a.n_species), dim3(kBlock), 0, s, a);
+}
+
+void launch_motion_copy_live(const SortArgs &a, int n_tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_motion_copy_live, dim3(n_tiles, a.n_species), dim3(kBlock), 0, s, a);
+    launch_set_int(a.stg_live, 0, s);
 }
 
 // Tile-relative cells of n particles grouped by tile, each inside its tile

@@ -20,7 +20,7 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-    size_t err = 0, dacc = 0, cacc = 0, jtile = 0, bh = 0, rho_prev = 0, rho_now = 0, jf = 0, rho_tmp = 0;
+    size_t err = 0, stg_live = 0, dacc = 0, cacc = 0, jtile = 0, bh = 0, rho_prev = 0, rho_now = 0, jf = 0, rho_tmp = 0;
     size_t wrem = 0, inj_off[kMaxSpecies] = {};
     size_t off[kMaxSpecies][2] = {}, cnt[kMaxSpecies] = {}, leav[kMaxSpecies] = {};
     size_t hole[kMaxSpecies] = {}, stg[kMaxSpecies][6] = {}, mcount[kMaxSpecies] = {}, bsum[kMaxSpecies] = {};
@@ -100,6 +100,7 @@ Layout make_layout(const pic_config *c)
         return at;
     };
     L.err = take(64);
+    L.stg_live = take(64);
     L.dacc = take(32 * sizeof(double));
     L.cacc = take(8 * sizeof(unsigned long long));
     const int NJ = T + 2 * halo_of(c) + 1;   // current halo nodes per axis
@@ -151,6 +152,7 @@ struct pic_sim {
     int ntx, nty, n_tiles, tile, replicas;
     char *work;
     int *err;
+    int *stg_live;      // nonzero: the particles wait in the motion-class sort's staging arrays
     double *dacc;
     unsigned long long *cacc;
     float *jtile;
@@ -421,6 +423,7 @@ PushArgs push_args(const pic_sim *S, bool bh)
     a.ju[2] = (float)(qmax / scale);
     a.n_species = c.n_species;
     a.rebase = S->since_sort == 0 ? 1 : 0;   // batched pushes take theirs from the launch
+    a.stg_live = S->stg_live;
     for (int s = 0; s < c.n_species; ++s) {
         const pic_particles &p = S->buf.sp[s];
         SpeciesDev &d = a.sp[s];
@@ -438,6 +441,13 @@ PushArgs push_args(const pic_sim *S, bool bh)
         d.fbase = S->sp[s].fbase;
         d.fhole = S->sp[s].hole;
         d.fsrc = S->sp[s].srec;
+        const Parts &g = S->sp[s].stg;
+        d.scell = g.cell;
+        d.sx = g.x;
+        d.sy = g.y;
+        d.sux = g.ux;
+        d.suy = g.uy;
+        d.suz = g.uz;
         d.n = (int32_t)c.species[s].n;
         d.h = (float)(0.5 * c.species[s].qm * c.dt);
         d.fq = (float)(scale * c.species[s].q / qmax);
@@ -481,6 +491,7 @@ SortArgs sort_args(const pic_sim *S, bool defer = false)
     SortArgs a;
     memset(&a, 0, sizeof(a));
     a.err = S->err;
+    a.stg_live = S->stg_live;
     a.defer = defer ? 1 : 0;
     a.nx = c.nx;
     a.ny = c.ny;
@@ -682,6 +693,7 @@ int init_sim(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
     char *w = (char *)bufs->work;
     S->work = w;
     S->err = (int *)(w + L.err);
+    S->stg_live = (int *)(w + L.stg_live);
     S->dacc = (double *)(w + L.dacc);
     S->cacc = (unsigned long long *)(w + L.cacc);
     S->jtile = (float *)(w + L.jtile);
@@ -740,6 +752,7 @@ int init_sim(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
         (void)scratch_address(S->device, &unused);
     }
     if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(S->err, 0, 64, stream));
+    if (rc == PIC_OK) rc = hip_ok(hipMemsetAsync(S->stg_live, 0, sizeof(int), stream));
     if (rc == PIC_OK) rc = build_tiles(S, stream);
     if (with_side) {
         // default priority, like every stream of the library's callers
@@ -763,6 +776,15 @@ extern "C" {
 
 namespace {
 
+// Whether pic_step's motion-class sort leaves its copy back to the next push
+// (which then reads the staging arrays): the push is built for that with
+// the default current and deposit.
+bool motion_deferrable(const pic_sim *S)
+{
+    return (S->cfg.flags & PIC_FLAG_MOTION_SORT) && j_mode(&S->cfg) == kJFixed && S->replicas == 1 &&
+           d_mode(&S->cfg) == kDepVB;
+}
+
 // The push kernel alone (steps a1-a7 up to the per-tile current halos); with
 // bh, it also forms the field advance's first half step (pic_step).
 int push_only(pic_sim *S, hipStream_t stream, bool bh)
@@ -770,11 +792,15 @@ int push_only(pic_sim *S, hipStream_t stream, bool bh)
     // a particle may stray at most sort_every - 1 cells from its tile before a push
     if (S->since_sort >= S->halo) return PIC_EORDER;
     const PushArgs a = push_args(S, bh);
+    const bool ms = motion_deferrable(S);
     {
         Timed t(S, PIC_KERNEL_PUSH, stream);
         launch_push_deposit(S->tile, S->replicas, j_mode(&S->cfg), d_mode(&S->cfg), S->halo, ppl_of(&S->cfg), a,
-                            S->n_tiles, stream);
+                            S->n_tiles, ms, stream);
     }
+    // the push has taken the particles from wherever they were: from now on
+    // the particle arrays hold them
+    if (ms) launch_set_int(S->stg_live, 0, stream);
     S->since_sort += 1;
     return hip_ok(hipGetLastError());
 }
@@ -825,10 +851,11 @@ int pic_push_deposit(pic_sim *S, hipStream_t stream)
 // The alternative sort (PIC_FLAG_MOTION_SORT): the motion-class sort --
 // recount and scan as for the in-place sort, then every particle into the
 // staging arrays at its slot in the (new tile, motion class, old slot) order
-// (timed as plan), and the staging arrays copied back (timed as scatter).
-static int motion_sort(pic_sim *S, hipStream_t stream)
+// (timed as plan), and the staging arrays copied back (timed as scatter) --
+// or, deferred (pic_step), read from there by the next push.
+static int motion_sort(pic_sim *S, hipStream_t stream, bool defer)
 {
-    const SortArgs a = sort_args(S);
+    const SortArgs a = sort_args(S, defer);
     {
         Timed t(S, PIC_KERNEL_SORT_SCAN, stream);
         launch_sort_scan(a, S->n_tiles, stream);
@@ -837,7 +864,7 @@ static int motion_sort(pic_sim *S, hipStream_t stream)
         Timed t(S, PIC_KERNEL_SORT_PLAN, stream);
         launch_motion_scatter(a, S->n_tiles, stream);
     }
-    {
+    if (!defer) {
         Timed t(S, PIC_KERNEL_SORT_SCATTER, stream);
         launch_motion_copy(a, S->n_tiles, stream);
     }
@@ -850,7 +877,7 @@ static int sort_after_push(pic_sim *S, hipStream_t stream, bool defer)
 {
     if (S->since_sort == 0) return PIC_OK;   // already sorted: the count records are spent
     S->since_sort = 0;
-    if (S->cfg.flags & PIC_FLAG_MOTION_SORT) return motion_sort(S, stream);
+    if (S->cfg.flags & PIC_FLAG_MOTION_SORT) return motion_sort(S, stream, defer && motion_deferrable(S));
     const SortArgs a = sort_args(S, defer);
     {
         Timed t(S, PIC_KERNEL_SORT_SCAN, stream);
@@ -867,15 +894,16 @@ static int sort_after_push(pic_sim *S, hipStream_t stream, bool defer)
     return hip_ok(hipGetLastError());
 }
 
-// A fill left pending by pic_step's sort, done before anything but a push
-// reads the particle arrays, and (publish) the whole-grid cells written into
-// the caller's cell arrays from the tile-relative ones the kernels keep.
-// Always launched: the device fill counts, not the host, know whether a fill
-// is pending (replays of a captured step run no host code); a tile with none
-// costs one read.
+// A fill (or the motion-class sort's copy back) left pending by pic_step's
+// sort, done before anything but a push reads the particle arrays, and
+// (publish) the whole-grid cells written into the caller's cell arrays from
+// the tile-relative ones the kernels keep.  Always launched: the device fill
+// counts and flag, not the host, know whether anything is pending (replays
+// of a captured step run no host code); a tile with no fill costs one read.
 static int settle(pic_sim *S, hipStream_t stream, bool publish = true)
 {
     const SortArgs a = sort_args(S);
+    if (motion_deferrable(S)) launch_motion_copy_live(a, S->n_tiles, stream);   // a copy back left pending
     launch_fill(a, S->n_tiles, stream);
     if (publish) launch_publish(a, S->n_tiles, S->since_sort == 0, stream);
     return hip_ok(hipGetLastError());
@@ -1177,6 +1205,7 @@ int pic_set_state(pic_sim *S, const pic_host_state *in, hipStream_t stream)
     for (int s = 0; s < S->cfg.n_species && rc == PIC_OK; ++s) rc = copy_particles(S, s, in->sp[s], false, stream);
     S->have_snapshot = false;
     S->since_sort = 0;
+    if (rc == PIC_OK) launch_set_int(S->stg_live, 0, stream);   // the new particles are in the arrays
     if (rc == PIC_OK) rc = build_tiles(S, stream);
     if (rc == PIC_OK) S->origin = in->window_origin;
     return rc;

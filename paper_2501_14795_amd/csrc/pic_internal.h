@@ -40,7 +40,9 @@ struct SortArgs {
     int nx, ny, ntx, nty, tile;
     int n_tiles;
     int n_species;
-    int defer;            // 1: the scatter leaves the holes to the next push (pic_step)
+    int defer;            // 1: the scatter leaves the holes to the next push (pic_step); the
+                          // motion-class sort leaves its copy back to it, and sets *stg_live
+    int *stg_live;        // nonzero: the particles wait in the motion-class sort's staging arrays
     int rebase;           // 1: no push since the last sort (the moving window's sort): cells are
                           // relative to their tile modulo its edge
     SortSpecies sp[kMaxSpecies];
@@ -67,8 +69,10 @@ struct FieldArgs {
 // ---- launchers (each defined next to its kernels) ----
 // halo: the pad H of cadence_ok (1 unless particles are sorted less often than every step)
 // ppl: particles per lane per pass of the push loop (1, 2 or 4; ppl_ok)
+// ms: the particles may wait in the motion-class sort's staging arrays
+// (PushArgs::stg_live decides on the device; the default current and deposit only)
 void launch_push_deposit(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs &a,
-                         int n_tiles, hipStream_t s);
+                         int n_tiles, bool ms, hipStream_t s);
 void launch_j_reduce(int tile, int halo, const JReduceArgs &r, hipStream_t s);
 // rebase: the pushes follow a sort (PushArgs::rebase of every member)
 void launch_push_batch(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs *descs,
@@ -105,6 +109,8 @@ void launch_sort_batch(const SortBatch &b, bool motion, hipStream_t s);
 // staging arrays at its new slot, then the staging arrays copied back
 void launch_motion_scatter(const SortArgs &a, int n_tiles, hipStream_t s);
 void launch_motion_copy(const SortArgs &a, int n_tiles, hipStream_t s);
+// the copy back only if *stg_live is set (a deferred one), then *stg_live = 0
+void launch_motion_copy_live(const SortArgs &a, int n_tiles, hipStream_t s);
 // tile_offset (off, n_tiles + 1) of n cells grouped by tile; sets kErrOrder
 // for a cell outside the grid and kErrGroup if they are not grouped (off is
 // then meaningless but every write stays inside it)

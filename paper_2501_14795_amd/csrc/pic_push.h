@@ -189,6 +189,10 @@ struct SpeciesDev {
     const int32_t *fbase;
     const int32_t *fhole;
     const LeaverRec *fsrc;
+    // the motion-class sort's staging arrays (read instead of the above when
+    // PushArgs::stg_live is set), or null
+    const int16_t *scell;
+    const float *sx, *sy, *sux, *suy, *suz;
     int32_t n;
     float h;              // (q/m) dt / 2
     float fq;             // charge in accumulator units: q / max|q| (x kFixedScale in fixed mode)
@@ -206,6 +210,7 @@ struct PushArgs {
     float ju[3];          // accumulator unit -> physical Jx, Jy, Jz
     int n_species;
     int rebase;           // the push follows a sort: each cell is relative to the tile modulo its edge
+    const int *stg_live;  // nonzero: the particles wait in the motion-class sort's staging arrays
     SpeciesDev sp[kMaxSpecies];
 };
 

@@ -1,7 +1,8 @@
 """The alternative sort (PIC_FLAG_MOTION_SORT; the motion-class sort Sec. 4.3
 cites, after Germaschewski et al.): after the push every particle is moved,
 in one counting pass over the push's per-class counts, to its slot in the
-order (new tile, motion class, old slot), out of place, and copied back.
+order (new tile, motion class, old slot), out of place, and copied back (in
+pic_step, read back by the next push).
 
 Bit-exact against the oracle's motion-class sort of the GPU's post-push state
 and tile_offset (every array and the new tile_offset), with one and two
@@ -123,3 +124,43 @@ def test_batched_motion_sort_equals_members_run_alone(tile, every):
         s.close()
     flush(f"batched motion sort T={tile} k={every}: {len(members)} members equal their standalone runs")
     batch.close()
+
+
+@pytest.mark.parametrize("tile,every", [(16, 1), (32, 1), (8, 2)])
+def test_step_leaves_the_copy_back_to_the_next_push(tile, every):
+    """pic_step's motion-class sort leaves its last pass (the staging arrays
+    copied back) to the next push, which reads the particles from the staging
+    arrays; a state read in between completes the copy instead.  Six steps,
+    one state read after the third, against a twin that sorts eagerly
+    (pic_push_deposit, pic_sort, pic_field_advance): every array, the fields
+    and tile_offset equal bit for bit."""
+    from paper_2501_14795_amd import Sim
+    nx, ny = 64, 64
+    spec = _specs(1)[0]
+    state = species_states(nx, ny, tile, [spec], 17)[0]
+    E, B = pw.random_fields(nx, ny, 0.05, 17)
+    lazy = Sim(nx, ny, DX, DY, DT, tile, [(spec.qm, spec.q, state)], E=E, B=B, sort_every=every, motion_sort=True)
+    eager = Sim(nx, ny, DX, DY, DT, tile, [(spec.qm, spec.q, state)], E=E, B=B, sort_every=every, motion_sort=True)
+
+    def same():
+        a, b = lazy.state(0), eager.state(0)
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+        fa, fb = lazy.field_arrays(), eager.field_arrays()
+        for c in fa:
+            assert np.array_equal(fa[c], fb[c]), c
+        assert np.array_equal(lazy.tile_offsets(0), eager.tile_offsets(0))
+
+    for k in range(6):
+        lazy.step()
+        eager.push_deposit()
+        if (k + 1) % every == 0:
+            eager.sort()
+        eager.field_advance()
+        if k == 2:
+            same()   # completes the pending copy; the next push reads the particle arrays
+    same()
+    assert lazy.check() == 0 and eager.check() == 0
+    flush(f"T{tile} every {every}: deferred copy back equal to the eager sort bit for bit")
+    lazy.close()
+    eager.close()
