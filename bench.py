@@ -226,7 +226,7 @@ def batched_comparison(n_sims=256, steps=20, tune_sims=32):
     b.sync()
     b.stream.synchronize()
     per_sim = (time.perf_counter() - t0) / steps
-    # the persistent push alone, event-timed in direct batched steps: its
+    # the batched push alone, event-timed in direct batched steps: its
     # algorithmic bytes (every member's push bytes, as for one simulation)
     # over its average duration
     m0 = b[0]
@@ -257,7 +257,7 @@ def batched_comparison(n_sims=256, steps=20, tune_sims=32):
         "graph_ms_per_step": graph * 1e3, "direct_ms_per_step": direct * 1e3,
         "per_sim_launch_ms_per_step": per_sim * 1e3,
         "speedup_vs_per_sim_launch": per_sim / graph,
-        "roofline": {"bound": "hbm", "kernel": "k_push_batch (persistent)", "avg_launch_ms": push_ms,
+        "roofline": {"bound": "hbm", "kernel": "k_push_batch", "avg_launch_ms": push_ms,
                      "algorithmic_bytes_per_launch": bytes_push,
                      "achieved": bytes_push / (push_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": bytes_push / (push_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},

@@ -465,9 +465,9 @@ int pic_get_timing(pic_sim *sim, pic_timing_out *out);
  *
  * Hundreds of small simulations (each its own grid, species and particle
  * count) share every kernel launch: one launch per phase of the step for the
- * whole batch, the push as a persistent grid that takes (simulation, tile)
- * work items largest-simulation-first, and optionally one captured HIP graph
- * per step.  All members must share tile, j_replicas, flags, j_filter and
+ * whole batch, the push as one workgroup per (simulation, tile) work item,
+ * largest simulations first, and optionally one captured HIP graph per
+ * step.  All members must share tile, j_replicas, flags, j_filter and
  * sort_every.
  * Results are bit-identical to advancing each member alone with pic_step.
  */
@@ -504,7 +504,7 @@ int pic_batch_capture(pic_batch *b, hipStream_t stream);
  * the single-member calls; owned by the batch (do not pic_destroy it).
  * NULL if i is out of range.  Event timing switched on for member 0
  * (pic_set_timing_mask with PIC_KERNEL_PUSH) also times the batch's
- * persistent push launch in direct (not graph-replayed) batched steps; do
+ * push launch in direct (not graph-replayed) batched steps; do
  * not capture with it on. */
 pic_sim *pic_batch_sim(pic_batch *b, int i);
 

@@ -842,25 +842,19 @@ __global__ void __launch_bounds__(64 * push_waves(T), (push_waves_per_simd<T, R,
     push_tile<T, R, JM, DM, H, C, MS>(a, blockIdx.x, a.rebase != 0);
 }
 
-// Many simulations in one launch: a persistent grid takes (simulation, tile)
-// items from a shared counter (the items come largest simulations first, so
-// the expensive tiles start early and the cheap ones fill the tail).
+// Many simulations in one launch: one workgroup per (simulation, tile) item.
+// The items come largest simulations first and the hardware dispatches
+// workgroups in order, so the expensive tiles start early and the cheap ones
+// fill the tail.  (A persistent grid taking items from a shared counter keeps
+// the counter, the item table and the descriptor pointer live across the
+// whole tile loop: more scalar registers than the push has, spilled.)
 template <int T, int R, int JM, int DM, int H, int C>
 __global__ void __launch_bounds__(64 * push_waves(T), (push_waves_per_simd<T, R, JM, DM, H, C>())) k_push_batch(const PushArgs *__restrict__ descs,
-                                                       const int4 *__restrict__ items, int n_items, int *counter,
-                                                       int rebase)
+                                                       const int4 *__restrict__ items, int n_items, int rebase)
 {
-    __shared__ int s_item;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-        __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (it >= n_items) break;
-        const int4 w = items[it];
-        push_tile<T, R, JM, DM, H, C>(descs[w.x], w.y, rebase != 0);
-        __syncthreads();
-    }
+    if ((int)blockIdx.x >= n_items) return;
+    const int4 w = items[blockIdx.x];
+    push_tile<T, R, JM, DM, H, C>(descs[w.x], w.y, rebase != 0);
 }
 
 // The periodic fold of the tile current halos into the J planes
@@ -905,11 +899,10 @@ static void launch_pd(const PushArgs &a, int n_tiles, hipStream_t s)
 }
 
 template <int T, int R, int JM, int DM, int H, int C>
-static void launch_pb(const PushArgs *descs, const int4 *items, int n_items, int *counter, int grid, int rebase,
-                      hipStream_t s)
+static void launch_pb(const PushArgs *descs, const int4 *items, int n_items, int rebase, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_push_batch<T, R, JM, DM, H, C>), dim3(grid), dim3(64 * push_waves(T)), 0, s, descs, items,
-                       n_items, counter, rebase);
+    hipLaunchKernelGGL((k_push_batch<T, R, JM, DM, H, C>), dim3(n_items), dim3(64 * push_waves(T)), 0, s, descs,
+                       items, n_items, rebase);
 }
 
 // One push launch, single or batched, with every template parameter chosen.
@@ -918,11 +911,9 @@ static void launch_pb(const PushArgs *descs, const int4 *items, int n_items, int
 struct PushLaunch {
     const PushArgs *single;   // single simulation (n_tiles workgroups), or null
     int n_tiles;
-    const PushArgs *descs;    // batched: persistent grid over the items
+    const PushArgs *descs;    // batched: one workgroup per item
     const int4 *items;
     int n_items;
-    int *counter;
-    int grid;
     int rebase;               // batched: the pushes follow a sort
     int ms;                   // single: the particles may wait in the motion-class sort's staging arrays
     hipStream_t s;
@@ -940,7 +931,7 @@ struct PushLaunch {
                 }
                 launch_pd<T, R, JM, DM, H, C, false>(*single, n_tiles, s);
             } else {
-                launch_pb<T, R, JM, DM, H, C>(descs, items, n_items, counter, grid, rebase, s);
+                launch_pb<T, R, JM, DM, H, C>(descs, items, n_items, rebase, s);
             }
         }
     }
@@ -1004,14 +995,14 @@ static void push_t(const PushLaunch &L, int tile, int replicas, int jmode, int d
 void launch_push_deposit(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs &a,
                          int n_tiles, bool ms, hipStream_t s)
 {
-    PushLaunch L{&a, n_tiles, nullptr, nullptr, 0, nullptr, 0, 0, ms ? 1 : 0, s};
+    PushLaunch L{&a, n_tiles, nullptr, nullptr, 0, 0, ms ? 1 : 0, s};
     push_t(L, tile, replicas, jmode, dmode, halo, ppl);
 }
 
 void launch_push_batch(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs *descs,
-                       const int4 *items, int n_items, int *counter, int grid, bool rebase, hipStream_t s)
+                       const int4 *items, int n_items, bool rebase, hipStream_t s)
 {
-    PushLaunch L{nullptr, 0, descs, items, n_items, counter, grid, rebase ? 1 : 0, 0, s};
+    PushLaunch L{nullptr, 0, descs, items, n_items, rebase ? 1 : 0, 0, s};
     push_t(L, tile, replicas, jmode, dmode, halo, ppl);
 }
 

@@ -1291,7 +1291,6 @@ struct pic_batch {
     int halo;    // sort cadence shared by the members
     int ppl;     // particles per lane of the push loop, shared by the members
     int phase;   // steps since the members were last sorted
-    int cus;
     char *dev;
     // device tables
     PushArgs *d_push;
@@ -1303,8 +1302,6 @@ struct pic_batch {
     int4 *push_items, *node_items, *count_items, *scan_items, *plan_items;
     int n_push, n_node, n_count, n_scan, n_plan;
     int max_blocks;   // the most scan blocks of one member
-    int *counter;
-    int push_grid;
     hipGraph_t graph;
     hipGraphExec_t exec;
     // the field half of a sorting step runs here beside the sort (as in pic_step)
@@ -1316,7 +1313,7 @@ namespace {
 
 struct BatchLayout {
     size_t d_push, d_jr, d_sort, d_field, d_filter, push_items, node_items, count_items, scan_items, plan_items,
-        counter, total;
+        total;
     int n_push, n_node, n_count, n_scan, n_plan;
 };
 
@@ -1364,7 +1361,6 @@ BatchLayout batch_layout(int n, const pic_config *cfgs)
     L.count_items = take(L.n_count * sizeof(int4));
     L.scan_items = take(L.n_scan * sizeof(int4));
     L.plan_items = take(L.n_plan * sizeof(int4));
-    L.counter = take(64);
     L.total = p;
     return L;
 }
@@ -1373,12 +1369,11 @@ BatchLayout batch_layout(int n, const pic_config *cfgs)
 // of a cadence cycle); rebase: the first step after a sort.
 void batch_enqueue_step(pic_batch *b, bool sort, bool rebase, hipStream_t stream)
 {
-    launch_set_int(b->counter, 0, stream);
     {
         // member 0's event timing, if on, times the batch's push launch
         Timed t(b->sims[0], PIC_KERNEL_PUSH, stream);
         launch_push_batch(b->tile, b->replicas, b->jm, b->dm, b->halo, b->ppl, b->d_push, b->push_items,
-                          b->n_push, b->counter, b->push_grid, rebase, stream);
+                          b->n_push, rebase, stream);
     }
     // with a sort, the field half goes to the second stream (disjoint data)
     const bool fork = sort && b->side;
@@ -1471,7 +1466,6 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
     B->count_items = (int4 *)(d + L.count_items);
     B->scan_items = (int4 *)(d + L.scan_items);
     B->plan_items = (int4 *)(d + L.plan_items);
-    B->counter = (int *)(d + L.counter);
     B->n_push = L.n_push;
     B->n_node = L.n_node;
     B->n_count = L.n_count;
@@ -1531,12 +1525,6 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
     up(B->plan_items, plan_items.data(), plan_items.size() * sizeof(int4));
     if (rc == PIC_OK) rc = hip_ok(hipStreamSynchronize(stream));
 
-    // persistent push grid: as many workgroups as fit on the device at once
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const int per_cu = std::max(1, std::min(8, kLdsBytes / push_lds_bytes(B->tile, B->replicas, B->jm, B->halo)));
-    B->cus = cus;
-    B->push_grid = std::max(1, std::min(B->n_push, cus * per_cu));
     if (rc) {
         pic_batch_destroy(B);
         return rc;

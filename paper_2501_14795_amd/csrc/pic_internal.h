@@ -76,7 +76,7 @@ void launch_push_deposit(int tile, int replicas, int jmode, int dmode, int halo,
 void launch_j_reduce(int tile, int halo, const JReduceArgs &r, hipStream_t s);
 // rebase: the pushes follow a sort (PushArgs::rebase of every member)
 void launch_push_batch(int tile, int replicas, int jmode, int dmode, int halo, int ppl, const PushArgs *descs,
-                       const int4 *items, int n_items, int *counter, int grid, bool rebase, hipStream_t s);
+                       const int4 *items, int n_items, bool rebase, hipStream_t s);
 void launch_j_reduce_batch(int tile, int halo, const JReduceArgs *descs, const int4 *items, int n_items,
                            hipStream_t s);
 void launch_set_int(int *p, int v, hipStream_t s);
