@@ -264,10 +264,17 @@ __device__ __forceinline__ bool tcell_inside(int lc, int T)
 // The loads are staged so that each round trip to memory serves all lists at
 // once: the list bounds, then the candidates (kPlanBatch iterations of 64),
 // then the movers' data, then the stores.
+// candidate iterations per round trip: 6 for one simulation (one tile per
+// wavefront, all tiles resident at once at 2048^2, so each wavefront's chain
+// of round trips is what counts); fewer in a batch, whose tens of thousands of
+// small tiles take several rounds of resident wavefronts, so fewer registers
+// (more wavefronts per SIMD) count more
 constexpr int kPlanBatch = 6;
+constexpr int kPlanBatchB = 2;
 enum : int { kListHoleRange = 0, kListHoleLeav = 1, kListMoverRange = 2, kListMoverLeav = 3 };
 static_assert(10 * push_waves(32) + 4 <= 128 && 10 * push_waves(8) + 4 <= 128, "sort plan list slots");
 
+template <int NB = kPlanBatch>
 __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int grp)
 {
     const int lane = threadIdx.x & 63;
@@ -421,12 +428,12 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
 
     bool bad = false;
     int nh = 0, nm = 0;
-    for (int k0 = 0; k0 < total; k0 += 64 * kPlanBatch) {
+    for (int k0 = 0; k0 < total; k0 += 64 * NB) {
         // ---- the candidates: their lists, then every load in flight at once
-        int at[kPlanBatch], ks[kPlanBatch], s0v[kPlanBatch], nsv[kPlanBatch], lv[kPlanBatch];
-        uint32_t v[kPlanBatch];
+        int at[NB], ks[NB], s0v[NB], nsv[NB], lv[NB];
+        uint32_t v[NB];
 #pragma unroll
-        for (int u = 0; u < kPlanBatch; ++u) {
+        for (int u = 0; u < NB; ++u) {
             const int k = k0 + 64 * u + lane;
             const int L0 = find_list(k, ex0), L1 = find_list(k, ex1);
             const bool hi = k >= tot0;
@@ -452,10 +459,10 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
                 v[u] = (uint32_t)tcell_pack(tcell_x((int)v[u]) & (T - 1), tcell_y((int)v[u]) & (T - 1));
         }
         // ---- the ballots, in candidate order: holes first, then movers
-        int rr[kPlanBatch];
+        int rr[NB];
         unsigned mvf = 0, flf = 0;   // per iteration: a mover of this lane, from the leaver records
 #pragma unroll
-        for (int u = 0; u < kPlanBatch; ++u) {
+        for (int u = 0; u < NB; ++u) {
             const int kind = ks[u] & 3, L = lv[u];
             bool ph = false, pm = false, fl = false;
             int slot = at[u];
@@ -501,12 +508,12 @@ __device__ __forceinline__ void sort_plan_unit(const SortArgs &a, int spi, int g
         if (__ballot(mvf != 0) == 0ull) continue;
         // ---- the movers' data, every load in flight at once, then staged in
         // hole order (contiguous stores)
-        Chunk6 dv[kPlanBatch];
+        Chunk6 dv[NB];
 #pragma unroll
-        for (int u = 0; u < kPlanBatch; ++u)
+        for (int u = 0; u < NB; ++u)
             if (mvf >> u & 1u) dv[u] = flf >> u & 1u ? load_leaver(sp.lrec, at[u]) : load_parts(sp.p, at[u], gx0, gy0, a.rebase ? T - 1 : -1);
 #pragma unroll
-        for (int u = 0; u < kPlanBatch; ++u)
+        for (int u = 0; u < NB; ++u)
             if (mvf >> u & 1u) {
                 const Chunk6 &c = dv[u];
                 put_leaver(sp.srec, (int64_t)A + rr[u], c.cell, c.x, c.y, c.ux, c.uy, c.uz);
@@ -797,7 +804,7 @@ __global__ void __launch_bounds__(kScanBlock) k_sort_add_base_b(const SortArgs *
 __global__ void __launch_bounds__(kBlock) k_sort_plan_b(const SortArgs *d, const int4 *it)
 {
     const int4 w = it[blockIdx.x];
-    sort_plan_unit(d[w.x], w.y, w.z);
+    sort_plan_unit<kPlanBatchB>(d[w.x], w.y, w.z);
 }
 __global__ void __launch_bounds__(kBlock) k_fill_b(const SortArgs *d, const int4 *it)
 {
