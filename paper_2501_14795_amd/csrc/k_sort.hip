@@ -264,11 +264,11 @@ __device__ __forceinline__ bool tcell_inside(int lc, int T)
 // The loads are staged so that each round trip to memory serves all lists at
 // once: the list bounds, then the candidates (kPlanBatch iterations of 64),
 // then the movers' data, then the stores.
-// candidate iterations per round trip: 6 for one simulation (one tile per
-// wavefront, all tiles resident at once at 2048^2, so each wavefront's chain
-// of round trips is what counts); fewer in a batch, whose tens of thousands of
-// small tiles take several rounds of resident wavefronts, so fewer registers
-// (more wavefronts per SIMD) count more
+// candidate iterations per round trip: 6 while every tile's wavefront is
+// resident at once (2048^2 in 32 x 32 tiles: each wavefront's chain of round
+// trips is what counts); 2 for more tiles (a batch's tens of thousands, or
+// small tiles of one large grid), which take several rounds of resident
+// wavefronts, so fewer registers (more wavefronts per SIMD) count more
 constexpr int kPlanBatch = 6;
 constexpr int kPlanBatchB = 2;
 enum : int { kListHoleRange = 0, kListHoleLeav = 1, kListMoverRange = 2, kListMoverLeav = 3 };
@@ -770,7 +770,8 @@ __global__ void __launch_bounds__(kBlock) k_publish(SortArgs a, int rebase)
 {
     publish_unit(a, blockIdx.y, blockIdx.x, rebase != 0);
 }
-__global__ void __launch_bounds__(kBlock) k_sort_plan(SortArgs a) { sort_plan_unit(a, blockIdx.y, blockIdx.x); }
+template <int NB>
+__global__ void __launch_bounds__(kBlock) k_sort_plan(SortArgs a) { sort_plan_unit<NB>(a, blockIdx.y, blockIdx.x); }
 __global__ void __launch_bounds__(kBlock) k_sort_scatter(SortArgs a) { sort_scatter_unit(a, blockIdx.y, blockIdx.x); }
 // single simulation: one tile per block
 __global__ void __launch_bounds__(kBlock) k_motion_scatter(SortArgs a) { motion_scatter_unit(a, blockIdx.y, blockIdx.x, 1); }
@@ -879,10 +880,18 @@ void launch_sort_scan(const SortArgs &a, int n_tiles, hipStream_t s)
     hipLaunchKernelGGL(k_sort_add_base, dim3(nb, a.n_species), dim3(kScanBlock), 0, s, a);
 }
 
+// Plan wavefronts (one per tile and species) that fit the device at once with
+// the six-iteration plan (four wavefronts per SIMD, 256 CUs); beyond, the
+// two-iteration plan runs twice as many at once.
+constexpr int64_t kPlanResident = 4096;
+
 void launch_sort_plan(const SortArgs &a, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sort_plan, dim3((n_tiles + kSortWaves - 1) / kSortWaves, a.n_species), dim3(kBlock), 0, s,
-                       a);
+    const dim3 grid((n_tiles + kSortWaves - 1) / kSortWaves, a.n_species);
+    if ((int64_t)n_tiles * a.n_species <= kPlanResident)
+        hipLaunchKernelGGL(k_sort_plan<kPlanBatch>, grid, dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_sort_plan<kPlanBatchB>, grid, dim3(kBlock), 0, s, a);
 }
 
 void launch_sort_scatter(const SortArgs &a, int n_tiles, hipStream_t s)
