@@ -182,8 +182,9 @@ def stream_probe(n=1 << 26, launches=20):
 
 def batched_comparison(n_sims=256, steps=20, tune_sims=32):
     """The batched workload (256 independent simulations, grids 32..256
-    cells, 8..64 ppc): the autotuner picks tile size x replicas x sort
-    cadence on the first tune_sims members, then the full batch runs as
+    cells, 8..64 ppc): the autotuner times its candidates on the first
+    tune_sims members and the three fastest again on the whole batch, then the
+    full batch runs as
     captured-graph replays, as direct batched launches, and one simulation per
     launch sequence (pic_step on each member in turn, the same cadence), all
     on the same members and data."""
@@ -204,7 +205,8 @@ def batched_comparison(n_sims=256, steps=20, tune_sims=32):
         return out
 
     t0 = time.perf_counter()
-    (tile, reps, every, ppl, motion), tuning = autotune_batch(lambda T: build(T, tune_sims))
+    (tile, reps, every, ppl, motion), tuning, refined = autotune_batch(lambda T: build(T, tune_sims),
+                                                                       refine_members=lambda T: build(T))
     log(f"autotuned tile {tile} replicas {reps} sort_every {every} particles/lane {ppl} motion sort {motion} in "
         f"{time.perf_counter() - t0:.1f}s: {tuning}")
     members = build(tile)
@@ -252,6 +254,8 @@ def batched_comparison(n_sims=256, steps=20, tune_sims=32):
         "particles_per_lane": ppl, "sort": "motion-class" if motion else "in-place",
         "autotune_ms_per_step": {f"T{k[0]}_R{k[1]}_S{k[2]}_P{k[3]}{'_M' if k[4] else ''}": v * 1e3
                                  for k, v in tuning.items()},
+        "autotune_refined_ms_per_step": {f"T{k[0]}_R{k[1]}_S{k[2]}_P{k[3]}{'_M' if k[4] else ''}": v * 1e3
+                                         for k, v in refined.items()},
         "graph_pushes_per_s": n / graph, "direct_pushes_per_s": n / direct,
         "per_sim_launch_pushes_per_s": n / per_sim,
         "graph_ms_per_step": graph * 1e3, "direct_ms_per_step": direct * 1e3,

@@ -111,11 +111,14 @@ def test_autotuner_picks_the_fastest_valid_candidate():
     members (tile x replicas x sort cadence x particles per lane), skips the
     ones it rejects (tile 8 with cadence 4; four particles per lane with two
     current copies; tile 32 on grids that are not multiples of 32), and
-    returns the fastest."""
+    returns the fastest; with a second, larger set of members to refine on,
+    it times its three fastest again there and returns the fastest of
+    those."""
     from paper_2501_14795_amd.tune import autotune_batch
     members = pw.batched_members(n_sims=4, seed=23)
+    more = pw.batched_members(n_sims=8, seed=23)
 
-    def build(tile):
+    def build(tile, members=members):
         out = []
         for m in members:
             if m["nx"] % tile or m["ny"] % tile:
@@ -127,13 +130,20 @@ def test_autotuner_picks_the_fastest_valid_candidate():
 
     cands = ((8, 1, 1, 2), (8, 1, 4, 2), (16, 1, 1, 2), (16, 1, 2, 2), (16, 1, 4, 2), (16, 1, 1, 1),
              (16, 1, 1, 4), (16, 2, 1, 4))
-    best, timings = autotune_batch(build, candidates=cands, steps=4)
+    best, timings, refined = autotune_batch(build, candidates=cands, steps=4)
     flush(f"autotuner: best {best}; " + ", ".join(f"{k}: {v * 1e3:.3f} ms" for k, v in timings.items()))
     assert (8, 1, 4, 2) not in timings            # 2k + 1 > tile: rejected by the library
     assert (16, 2, 1, 4) not in timings           # four particles per lane need one LDS current copy
     assert set(timings) == {(8, 1, 1, 2), (16, 1, 1, 2), (16, 1, 2, 2), (16, 1, 4, 2), (16, 1, 1, 1), (16, 1, 1, 4)}
+    assert refined == {}
     assert best == min(timings, key=timings.get)
     assert all(v > 0 for v in timings.values())
+    best, timings, refined = autotune_batch(build, candidates=cands, steps=4,
+                                            refine_members=lambda t: build(t, more))
+    flush(f"autotuner with refinement: best {best}; " + ", ".join(f"{k}: {v * 1e3:.3f} ms" for k, v in refined.items()))
+    assert set(refined) == set(sorted(timings, key=timings.get)[:3])
+    assert best == min(refined, key=refined.get)
+    assert all(v > 0 for v in refined.values())
 
 
 class _Sp:
