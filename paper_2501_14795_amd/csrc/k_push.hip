@@ -11,8 +11,12 @@
 //   2. the 64-aligned particle chunks covering the tile's section are split
 //      into contiguous runs, one per wavefront (4 wavefronts per tile up to
 //      16 x 16 tiles, 8 for 32 x 32 tiles, two such workgroups per CU); every chunk is one
-//      coalesced buffer load per SoA array (per-tile buffer base in SGPRs), and
-//      there is no block barrier in the loop;
+//      coalesced buffer load per SoA array (per-tile buffer base in SGPRs):
+//      the cell as 16 bits relative to the tile, x, y, ux, uy, uz as FP32
+//      (22 bytes a particle), and there is no block barrier in the loop; the
+//      holes the last sort left get their particles from its staging records
+//      as the chunk is loaded, and after a motion-class sort the chunks come
+//      from its staging arrays;
 //   3. per particle: bilinear interpolation at the staggered points
 //      (Sec. 3.1), Boris push (Eqs. 6-10), move (Eq. 11), and the
 //      Villasenor-Buneman current (Eqs. 13-16) of each of the 1, 2 or 3 pieces
@@ -35,8 +39,10 @@
 //      data, and counted per direction -- the input of the strict sort
 //      (Sec. 4.3, step 1);
 //   5. the tile's (T+2H+1)^2 current halo is converted to physical units and
-//      written out; k_j_reduce then adds the up-to-four overlapping tile halos
-//      of every node in a fixed order with compensation (no global atomics).
+//      written out; k_j_reduce (or the E step of the field advance) then adds
+//      the up-to-four overlapping tile halos of every node in a fixed order
+//      with compensation (no global atomics); in pic_step the tile also writes
+//      the first B half step of its own cells from its staged E/B halo.
 #include <type_traits>
 
 #include "pic_internal.h"

@@ -2,7 +2,9 @@
 // redesigned for gfx950: no atomics decide any position, so the permutation
 // is the canonical one and is reproducible bit for bit.
 //
-//   k_sort_scan    step (1): the new count of tile t is the sum, over the nine
+//   k_sort_count, k_sort_add_direct (k_sort_scan_blocks, k_sort_add_base
+//                  above 64 scan blocks)
+//                  step (1): the new count of tile t is the sum, over the nine
 //                  tiles a particle can come from, of the direction counts the
 //                  push kernel recorded; an exclusive scan gives tile_offset'.
 //   k_sort_plan    steps (2)-(4), one wavefront per destination tile t with
@@ -24,6 +26,13 @@
 //                  the staging area as it streams its section (a deferred
 //                  fill; k_fill completes one on its own when anything else
 //                  is to read the particles first).
+//
+// The cells the kernels keep are 16-bit offsets from the tile whose section
+// holds the particle (tcell_pack); the staging records carry whole-grid
+// cells, converted on the way in and out.  Also here: the motion-class sort
+// (the alternative of Sec. 4.3), the conversions between the caller's
+// whole-grid cells and the 16-bit ones, and the tile offsets of caller
+// particles at initialisation.
 #include "pic_internal.h"
 
 namespace pic {
