@@ -129,8 +129,11 @@ class _SimView:
         _lib.pic_field_advance(self.handle, self.s)
 
     def sync(self):
-        """Complete a hole fill that step()'s sort left to the next push
-        (pic_sync), so the particle tensors hold the sorted state."""
+        """Bring the particle tensors up to date (pic_sync): complete what
+        step()'s sort left to the next push (the hole fill, or the
+        motion-class sort's copy back) and write every particle's cell into
+        the cell tensor (the kernels keep 16-bit tile-relative cells in the
+        workspace)."""
         _lib.pic_sync(self.handle, self.s)
 
     def step(self):
@@ -372,7 +375,7 @@ class Batch:
         return _lib.pic_batch_check(self.handle, self.stream.cuda_stream)
 
     def sync(self):
-        """pic_sync for every member in one launch (pic_batch_sync)."""
+        """pic_sync for every member at once (pic_batch_sync)."""
         _lib.pic_batch_sync(self.handle, self.stream.cuda_stream)
 
     def close(self):
