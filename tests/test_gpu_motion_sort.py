@@ -164,3 +164,41 @@ def test_step_leaves_the_copy_back_to_the_next_push(tile, every):
     flush(f"T{tile} every {every}: deferred copy back equal to the eager sort bit for bit")
     lazy.close()
     eager.close()
+
+
+@pytest.mark.parametrize("motion", [True, False])
+def test_set_state_while_the_copy_back_is_pending(motion):
+    """A state loaded (pic_set_state) while pic_step's copy back (motion-class
+    sort) or hole fill (in-place sort) is still pending replaces the
+    particles: the next push reads the loaded ones, not the staging arrays or
+    records.  The run from there equals a fresh simulation loaded from the
+    same state, bit for bit."""
+    from paper_2501_14795_amd import Sim
+    nx = ny = 64
+    tile = 16
+    spec = _specs(1)[0]
+    a = species_states(nx, ny, tile, [spec], 23)[0]
+    b = species_states(nx, ny, tile, [spec], 24)[0]
+    E, B = pw.random_fields(nx, ny, 0.05, 23)
+    donor = Sim(nx, ny, DX, DY, DT, tile, [(spec.qm, spec.q, b)], E=E, B=B, motion_sort=motion)
+    for _ in range(2):
+        donor.step()
+    ck = donor.get_state()
+    busy = Sim(nx, ny, DX, DY, DT, tile, [(spec.qm, spec.q, a)], E=E, B=B, motion_sort=motion)
+    busy.step()               # its copy back (or hole fill) is now pending
+    busy.set_state(ck)
+    fresh = Sim(nx, ny, DX, DY, DT, tile, [(spec.qm, spec.q, a)], E=E, B=B, motion_sort=motion)
+    fresh.set_state(ck)
+    for _ in range(3):
+        busy.step()
+        fresh.step()
+    sa, sb = busy.state(0), fresh.state(0)
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    fa, fb = busy.field_arrays(), fresh.field_arrays()
+    for c in fa:
+        assert np.array_equal(fa[c], fb[c]), c
+    assert busy.check() == 0 and fresh.check() == 0
+    flush(f"motion sort {motion}: set_state during a pending copy back / fill: the loaded state is the one pushed")
+    for s in (donor, busy, fresh):
+        s.close()
