@@ -66,7 +66,7 @@ def push_bytes(n_particles, n_tiles, tile, leavers, n_species=1, halo=1):
             + 4 * leavers)
 
 
-def step_bytes(n_particles, n_tiles, tile, nx, ny, leavers, movers, n_species=1):
+def step_bytes(n_particles, n_tiles, tile, nx, ny, leavers, movers, n_species=1, motion=False):
     """Algorithmic HBM bytes of one whole pic_step: the push (push_bytes),
     the hole fill it does for the last sort (per mover: its hole slot and its
     32-byte staged record), the field half (the E step: E read and written,
@@ -74,11 +74,18 @@ def step_bytes(n_particles, n_tiles, tile, nx, ny, leavers, movers, n_species=1)
     B half step: the half-step B and E read, B written: 21 plane passes) and
     the sort (per tile: nine count-record entries and the offsets; per leaver
     entry 4 B; per mover its 32-byte record read, its staging record written
-    and its hole slot)."""
+    and its hole slot).  With motion=True the sort is the motion-class
+    counting pass instead (per tile its class counts and offsets; per
+    particle its 2-byte cell read to count, then its 22 bytes read and
+    written into the staging arrays) and there is no hole fill: the push
+    reads the staging arrays, the same bytes as the particle arrays."""
     plane = 4 * nx * ny
     field = 21 * plane + n_tiles * (tile + 3) ** 2 * 3 * 4
     sort = n_species * n_tiles * (9 * 4 + 8) + 4 * leavers + movers * (32 + 32 + 4)
     fill = movers * (4 + 32)
+    if motion:
+        sort = n_species * n_tiles * (9 * 4 + 8) + (2 * BYTES_PARTICLE + 2) * n_particles
+        fill = 0
     return push_bytes(n_particles, n_tiles, tile, leavers, n_species) + fill + field + sort
 
 
@@ -387,6 +394,8 @@ def main():
     ap.add_argument("--j-float", action="store_true", help="FP32-atomic LDS current instead of fixed point")
     ap.add_argument("--j-filter", type=int, default=0, help="binomial current filter passes in the timed step")
     ap.add_argument("--esirkepov", action="store_true", help="Esirkepov deposit instead of split Villasenor-Buneman")
+    ap.add_argument("--motion-sort", action="store_true",
+                    help="the motion-class sort instead of the in-place one in the timed step")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the short measurements of the filter pass and of the Esirkepov deposit")
 
@@ -436,7 +445,8 @@ def main():
     log(f"stream probe: {probe}")
 
     sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, T, [(s.qm, s.q, st) for s, st in zip(w.species, states)],
-              j_replicas=args.replicas, j_float=args.j_float, j_filter=args.j_filter, esirkepov=args.esirkepov)
+              j_replicas=args.replicas, j_float=args.j_float, j_filter=args.j_filter, esirkepov=args.esirkepov,
+              motion_sort=args.motion_sort)
     del states
     log("initialised")
     for _ in range(args.warmup):
@@ -478,12 +488,15 @@ def main():
     push_ms = kt_push[0] / max(kt_push[1], 1)
     pb = push_bytes(n, sim.n_tiles, T, leavers, len(w.species))
     achieved = pb / (push_ms * 1e-3) / 1e9
-    sb = step_bytes(n, sim.n_tiles, T, w.nx, w.ny, leavers, movers, len(w.species))
+    sb = step_bytes(n, sim.n_tiles, T, w.nx, w.ny, leavers, movers, len(w.species), motion=args.motion_sort)
     step_gbs = sb / (ms_step * 1e-3) / 1e9
     hot_ms = sum(kt[k][0] for k in ("push", "j_reduce", "sort_scan", "sort_plan", "sort_scatter")) / split_steps
 
     traffic = None
-    if os.path.exists(args.traffic_json):
+    # the counters were taken on the default push (split Villasenor-Buneman
+    # deposit, fixed-point current, in-place sort, no filter)
+    default_push = not (args.esirkepov or args.j_float or args.motion_sort or args.j_filter or args.replicas > 1)
+    if default_push and os.path.exists(args.traffic_json):
         try:
             tj = json.load(open(args.traffic_json))
             if tj.get("workload") == w.name and tj.get("tile") == T and tj.get("kernel_source_sha") == \
@@ -511,6 +524,7 @@ def main():
                    "j_replicas": args.replicas or ((4 if T < 32 else 2) if args.j_float else 1),
                    "sort_every": 1, "j_filter": args.j_filter,
                    "deposit": "esirkepov" if args.esirkepov else "villasenor-buneman-split",
+                   "sort": "motion-class" if args.motion_sort else "in-place",
                    "step": "push+deposit+sort+field_advance"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
