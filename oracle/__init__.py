@@ -15,6 +15,10 @@ Particle-Mesh Algorithms with FPGAs and OmpSs@OpenCL"):
                            1/2/3-piece split of Figs. 3.4-3.5
 * ``deposit_esirkepov`` -- Esirkepov's charge-conserving current, the variant
                            deposit (density decomposition, linear shape)
+* ``interp_quad`` / ``deposit_esirkepov_quad`` / ``rho(quadratic=True)`` -- the
+                           quadratic B-spline shape for the gather, Esirkepov's
+                           deposit and the node charge (an extension of the
+                           linear weighting of Sec. 3.1; the paper has none)
 * ``OracleSim.push_deposit`` -- the particle loop of Listing 3.1 + Eq. (11)
 * ``yee_b`` / ``yee_e`` / ``OracleSim.field_advance`` -- Eqs. (19)-(20), the
                            three-step Yee update of Listing 3.1
@@ -108,6 +112,9 @@ def lib():
         L.ora_deposit_move.argtypes = [_i, _i, _d, _d, _d, _d, _d, _i, _i, _d, _d, _d, _d, _p]
         L.ora_advance.argtypes = [_i, _i, _d, _d, _d, _d, _d, _i64] + [_p] * 10 + [_i]
         L.ora_deposit_esirkepov.argtypes = [_i, _i, _d, _d, _d, _d, _d, _i, _i, _d, _d, _d, _d, _p]
+        L.ora_deposit_esirkepov_quad.argtypes = [_i, _i, _d, _d, _d, _d, _d, _i, _i, _d, _d, _d, _d, _p]
+        L.ora_interp_quad.argtypes = [_i, _i, _p, _p, _i, _i, _d, _d, _p]
+        L.ora_deposit_rho_quad.argtypes = [_i, _i, _d, _i64, _p, _p, _p, _p, _p]
         L.ora_advance.restype = _i
         L.ora_yee_b.argtypes = [_i, _i, _d, _d, _d, _p, _p]
         L.ora_yee_e.argtypes = [_i, _i, _d, _d, _d, _p, _p, _p]
@@ -154,6 +161,15 @@ def interp(nx, ny, E, B, ix, iy, x, y) -> np.ndarray:
     return out
 
 
+def interp_quad(nx, ny, E, B, ix, iy, x, y) -> np.ndarray:
+    """{Ex,Ey,Ez,Bx,By,Bz} at one particle with the quadratic shape."""
+    E = _f64(E)
+    B = _f64(B)
+    out = np.zeros(6)
+    lib().ora_interp_quad(nx, ny, _ptr(E), _ptr(B), int(ix), int(iy), float(x), float(y), _ptr(out))
+    return out
+
+
 def boris(qm, dt, EB, u) -> np.ndarray:
     """One Boris update of u(t-dt/2) -> u(t+dt/2) in the fields EB = (E, B)."""
     EB = _f64(EB)
@@ -177,6 +193,15 @@ def deposit_esirkepov(nx, ny, dx, dy, dt, q, vz, ix, iy, x, y, ddx, ddy, J=None)
         J = np.zeros((3, ny, nx))
     lib().ora_deposit_esirkepov(nx, ny, dx, dy, dt, q, vz, int(ix), int(iy), float(x), float(y),
                                 float(ddx), float(ddy), _ptr(J))
+    return J
+
+
+def deposit_esirkepov_quad(nx, ny, dx, dy, dt, q, vz, ix, iy, x, y, ddx, ddy, J=None) -> np.ndarray:
+    """Esirkepov current (3, ny, nx) of one straight move with the quadratic shape."""
+    if J is None:
+        J = np.zeros((3, ny, nx))
+    lib().ora_deposit_esirkepov_quad(nx, ny, dx, dy, dt, q, vz, int(ix), int(iy), float(x), float(y),
+                                     float(ddx), float(ddy), _ptr(J))
     return J
 
 
@@ -242,15 +267,17 @@ def sort_stable_by_tile(nx, ny, T, ix, iy):
     return off, src
 
 
-def rho(nx, ny, q, ix, iy, x, y, out=None) -> np.ndarray:
-    """Node charge density (ny, nx) of one species (accumulates into out)."""
+def rho(nx, ny, q, ix, iy, x, y, out=None, quadratic=False) -> np.ndarray:
+    """Node charge density (ny, nx) of one species (accumulates into out),
+    with the linear or the quadratic shape."""
     if out is None:
         out = np.zeros((ny, nx))
     ix = _i32(ix)
     iy = _i32(iy)
     x = _f64(x)
     y = _f64(y)
-    lib().ora_deposit_rho(nx, ny, q, ix.size, _ptr(ix), _ptr(iy), _ptr(x), _ptr(y), _ptr(out))
+    f = lib().ora_deposit_rho_quad if quadratic else lib().ora_deposit_rho
+    f(nx, ny, q, ix.size, _ptr(ix), _ptr(iy), _ptr(x), _ptr(y), _ptr(out))
     return out
 
 
@@ -357,10 +384,12 @@ class OracleSpecies:
 class OracleSim:
     """Serial FP64 PIC on a periodic nx x ny grid (Listing 3.1 order)."""
 
-    def __init__(self, nx, ny, dx, dy, dt, species, E=None, B=None, j_filter=0, esirkepov=False):
+    def __init__(self, nx, ny, dx, dy, dt, species, E=None, B=None, j_filter=0, esirkepov=False,
+                 quadratic=False):
         self.nx, self.ny = int(nx), int(ny)
         self.j_filter = int(j_filter)
         self.esirkepov = bool(esirkepov)
+        self.quadratic = bool(quadratic)   # quadratic shape: gather and Esirkepov deposit
         self.dx, self.dy, self.dt = float(dx), float(dy), float(dt)
         self.species = list(species)
         shape = (3, self.ny, self.nx)
@@ -375,7 +404,8 @@ class OracleSim:
             rc = lib().ora_advance(self.nx, self.ny, self.dx, self.dy, self.dt, s.qm, s.q, s.n,
                                    _ptr(s.ix), _ptr(s.iy), _ptr(s.x), _ptr(s.y),
                                    _ptr(s.ux), _ptr(s.uy), _ptr(s.uz),
-                                   _ptr(self.E), _ptr(self.B), _ptr(self.J), int(self.esirkepov))
+                                   _ptr(self.E), _ptr(self.B), _ptr(self.J),
+                                   2 if self.quadratic else int(self.esirkepov))
             if rc != 0:
                 raise FloatingPointError("a particle moved one cell or more (Courant condition)")
         if self.j_filter:
@@ -433,7 +463,7 @@ class OracleSim:
         (the density whose continuity the filtered current satisfies)."""
         r = np.zeros((self.ny, self.nx))
         for s in self.species:
-            rho(self.nx, self.ny, s.q, s.ix, s.iy, s.x, s.y, out=r)
+            rho(self.nx, self.ny, s.q, s.ix, s.iy, s.x, s.y, out=r, quadratic=self.quadratic)
         if filtered and self.j_filter:
             binomial_filter(self.nx, self.ny, self.j_filter, r)
         return r

@@ -200,7 +200,10 @@ void ora_deposit_move(int nx, int ny, double dx, double dy, double dt,
 /* 135 (2001) 144), the alternative deposit to Eqs. (13)-(16) with splits:    */
 /* the change of the particle's shape-function product over the step is      */
 /* decomposed into an x part W^x and a y part W^y, and the current is their  */
-/* running sum across the stencil.  Linear (cloud-in-cell) shape.            */
+/* running sum across the stencil.  Linear (cloud-in-cell) shape, and the    */
+/* quadratic B-spline, with which the field gather weights the three nearest */
+/* sample points of each component too (a higher-order extension of the      */
+/* linear weighting of Sec. 3.1, not in the paper).                          */
 /* ------------------------------------------------------------------------ */
 
 /* Cloud-in-cell weight of a node at distance d (cells). */
@@ -210,54 +213,115 @@ static double shape_cic(double d)
     return a < 1.0 ? 1.0 - a : 0.0;
 }
 
+/* Quadratic B-spline weight of a node at distance d (cells): the linear shape
+ * convolved once more with the unit cell, three nodes wide. */
+static double shape_quad(double d)
+{
+    double a = fabs(d);
+    if (a <= 0.5) return 0.75 - a * a;
+    if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
+    return 0.0;
+}
+
 /*
  * Current of a straight motion from offset (x, y) in cell (ix, iy) by
- * (ddx, ddy) cells, |ddx|, |ddy| < 1, on the 4 x 4 nodes ix-1 .. ix+2 (and
- * likewise in y).  With S0, S1 the node weights before and after and
- * DS = S1 - S0:
+ * (ddx, ddy) cells, |ddx|, |ddy| < 1, on the n x n nodes ix+lo .. ix+lo+n-1
+ * (likewise in y), wide enough to hold the shape before and after.  With S0,
+ * S1 the node weights before and after and DS = S1 - S0:
  *   W^x_kl = DSx_k (S0y_l + DSy_l / 2),   W^y_kl = DSy_l (S0x_k + DSx_k / 2),
  *   W^z_kl = S0x_k S0y_l + (DSx_k S0y_l + S0x_k DSy_l) / 2 + DSx_k DSy_l / 3,
  * and Jx at (k + 1/2, l) = -q dx/dt sum_{k' <= k} W^x_k'l (likewise Jy),
  * Jz at (k, l) = q vz W^z_kl.
  */
+static void esirkepov(int nx, int ny, double dx, double dy, double dt, double q,
+                      double vz, int ix, int iy, double x, double y, double ddx,
+                      double ddy, double *J, double (*shape)(double), int lo,
+                      int n)
+{
+    const int64_t plane = (int64_t)nx * ny;
+    double *Jx = J, *Jy = J + plane, *Jz = J + 2 * plane;
+    double s0x[6], s1x[6], dsx[6], s0y[6], s1y[6], dsy[6];
+    for (int k = 0; k < n; k++) {
+        double p = lo + k; /* node position relative to the starting cell */
+        s0x[k] = shape(x - p);
+        s1x[k] = shape(x + ddx - p);
+        dsx[k] = s1x[k] - s0x[k];
+        s0y[k] = shape(y - p);
+        s1y[k] = shape(y + ddy - p);
+        dsy[k] = s1y[k] - s0y[k];
+    }
+    for (int l = 0; l < n; l++) {
+        int j = wrap(iy + lo + l, ny);
+        double run = 0.0;
+        for (int k = 0; k + 1 < n; k++) {
+            run -= dsx[k] * (s0y[l] + 0.5 * dsy[l]);
+            Jx[IDX(wrap(ix + lo + k, nx), j, nx)] += q * run * dx / dt;
+        }
+    }
+    for (int k = 0; k < n; k++) {
+        int i = wrap(ix + lo + k, nx);
+        double run = 0.0;
+        for (int l = 0; l + 1 < n; l++) {
+            run -= dsy[l] * (s0x[k] + 0.5 * dsx[k]);
+            Jy[IDX(i, wrap(iy + lo + l, ny), nx)] += q * run * dy / dt;
+        }
+    }
+    for (int l = 0; l < n; l++)
+        for (int k = 0; k < n; k++) {
+            double w = s0x[k] * s0y[l] + 0.5 * (dsx[k] * s0y[l] + s0x[k] * dsy[l]) +
+                       dsx[k] * dsy[l] / 3.0;
+            Jz[IDX(wrap(ix + lo + k, nx), wrap(iy + lo + l, ny), nx)] += q * vz * w;
+        }
+}
+
+/* Linear shape: the 4 x 4 nodes ix-1 .. ix+2 hold it before and after. */
 void ora_deposit_esirkepov(int nx, int ny, double dx, double dy, double dt,
                            double q, double vz, int ix, int iy, double x,
                            double y, double ddx, double ddy, double *J)
 {
+    esirkepov(nx, ny, dx, dy, dt, q, vz, ix, iy, x, y, ddx, ddy, J, shape_cic, -1, 4);
+}
+
+/* Quadratic shape: a position in (-1, 2) relative to the cell has its three
+ * nodes within ix-2 .. ix+3, so the 6 x 6 nodes there hold it before and
+ * after. */
+void ora_deposit_esirkepov_quad(int nx, int ny, double dx, double dy,
+                                double dt, double q, double vz, int ix, int iy,
+                                double x, double y, double ddx, double ddy,
+                                double *J)
+{
+    esirkepov(nx, ny, dx, dy, dt, q, vz, ix, iy, x, y, ddx, ddy, J, shape_quad, -2, 6);
+}
+
+/* Quadratic-shape gather of one staggered component sampled at (i+sx, j+sy):
+ * the three sample points nearest the particle on each axis, weighted by the
+ * shape at their distance. */
+static double interp_component_quad(const double *F, int nx, int ny, double X,
+                                    double Y, double sx, double sy)
+{
+    double xs = X - sx, ys = Y - sy;
+    int i0 = (int)floor(xs + 0.5), j0 = (int)floor(ys + 0.5);
+    double v = 0.0;
+    for (int b = -1; b <= 1; b++)
+        for (int a = -1; a <= 1; a++) {
+            double w = shape_quad(xs - (i0 + a)) * shape_quad(ys - (j0 + b));
+            v += w * F[IDX(wrap(i0 + a, nx), wrap(j0 + b, ny), nx)];
+        }
+    return v;
+}
+
+/* E and B at a particle with the quadratic shape: out = {Ex, .., Bz}. */
+void ora_interp_quad(int nx, int ny, const double *E, const double *B, int ix,
+                     int iy, double x, double y, double *out)
+{
     const int64_t plane = (int64_t)nx * ny;
-    double *Jx = J, *Jy = J + plane, *Jz = J + 2 * plane;
-    double s0x[4], s1x[4], dsx[4], s0y[4], s1y[4], dsy[4];
-    for (int k = 0; k < 4; k++) {
-        double p = k - 1; /* node position relative to the starting cell */
-        s0x[k] = shape_cic(x - p);
-        s1x[k] = shape_cic(x + ddx - p);
-        dsx[k] = s1x[k] - s0x[k];
-        s0y[k] = shape_cic(y - p);
-        s1y[k] = shape_cic(y + ddy - p);
-        dsy[k] = s1y[k] - s0y[k];
+    double X = ix + x, Y = iy + y;
+    for (int c = 0; c < 3; c++) {
+        out[c] = interp_component_quad(E + c * plane, nx, ny, X, Y, STAG_X[c],
+                                       STAG_Y[c]);
+        out[3 + c] = interp_component_quad(B + c * plane, nx, ny, X, Y,
+                                           STAG_X[3 + c], STAG_Y[3 + c]);
     }
-    for (int l = 0; l < 4; l++) {
-        int j = wrap(iy - 1 + l, ny);
-        double run = 0.0;
-        for (int k = 0; k < 3; k++) {
-            run -= dsx[k] * (s0y[l] + 0.5 * dsy[l]);
-            Jx[IDX(wrap(ix - 1 + k, nx), j, nx)] += q * run * dx / dt;
-        }
-    }
-    for (int k = 0; k < 4; k++) {
-        int i = wrap(ix - 1 + k, nx);
-        double run = 0.0;
-        for (int l = 0; l < 3; l++) {
-            run -= dsy[l] * (s0x[k] + 0.5 * dsx[k]);
-            Jy[IDX(i, wrap(iy - 1 + l, ny), nx)] += q * run * dy / dt;
-        }
-    }
-    for (int l = 0; l < 4; l++)
-        for (int k = 0; k < 4; k++) {
-            double w = s0x[k] * s0y[l] + 0.5 * (dsx[k] * s0y[l] + s0x[k] * dsy[l]) +
-                       dsx[k] * dsy[l] / 3.0;
-            Jz[IDX(wrap(ix - 1 + k, nx), wrap(iy - 1 + l, ny), nx)] += q * vz * w;
-        }
 }
 
 /* Move one offset coordinate by d cells and renormalise it into [0, 1). */
@@ -284,23 +348,30 @@ static void advance_coord(int *i, double *x, double d, int n)
  * for every particle in array order, interpolate E and B, Boris-push the
  * momentum, move the particle by Eq. (11) and deposit its current into J
  * (which the caller zeroes; contributions of all species add up) --
- * esirkepov = 0: Villasenor-Buneman with splits, 1: Esirkepov.
+ * deposit = 0: Villasenor-Buneman with splits, 1: Esirkepov, 2: the quadratic
+ * shape, for the gather and Esirkepov's deposit both.
  * Returns 0, or -1 if a particle would move one cell or more (Eq. 1 violated).
  */
 int ora_advance(int nx, int ny, double dx, double dy, double dt, double qm,
                 double q, int64_t n, int32_t *ix, int32_t *iy, double *x,
                 double *y, double *ux, double *uy, double *uz, const double *E,
-                const double *B, double *J, int esirkepov)
+                const double *B, double *J, int deposit)
 {
     for (int64_t p = 0; p < n; p++) {
         double EB[6], u[3] = {ux[p], uy[p], uz[p]};
-        ora_interp(nx, ny, E, B, ix[p], iy[p], x[p], y[p], EB);
+        if (deposit == 2)
+            ora_interp_quad(nx, ny, E, B, ix[p], iy[p], x[p], y[p], EB);
+        else
+            ora_interp(nx, ny, E, B, ix[p], iy[p], x[p], y[p], EB);
         ora_boris(qm, dt, EB, u);
         double g = sqrt(1.0 + u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
         double ddx = u[0] / g * dt / dx; /* Eq. (11), in cells */
         double ddy = u[1] / g * dt / dy;
         if (fabs(ddx) >= 1.0 || fabs(ddy) >= 1.0) return -1;
-        if (esirkepov)
+        if (deposit == 2)
+            ora_deposit_esirkepov_quad(nx, ny, dx, dy, dt, q, u[2] / g, ix[p],
+                                       iy[p], x[p], y[p], ddx, ddy, J);
+        else if (deposit == 1)
             ora_deposit_esirkepov(nx, ny, dx, dy, dt, q, u[2] / g, ix[p], iy[p],
                                   x[p], y[p], ddx, ddy, J);
         else
@@ -548,6 +619,22 @@ void ora_deposit_rho(int nx, int ny, double q, int64_t n, const int32_t *ix,
         rho[IDX(i1, j0, nx)] += q * x[p] * (1.0 - y[p]);
         rho[IDX(i0, j1, nx)] += q * (1.0 - x[p]) * y[p];
         rho[IDX(i1, j1, nx)] += q * x[p] * y[p];
+    }
+}
+
+/* Node charge density with the quadratic shape (the three nodes nearest the
+ * particle on each axis). */
+void ora_deposit_rho_quad(int nx, int ny, double q, int64_t n, const int32_t *ix,
+                          const int32_t *iy, const double *x, const double *y,
+                          double *rho)
+{
+    for (int64_t p = 0; p < n; p++) {
+        double X = ix[p] + x[p], Y = iy[p] + y[p];
+        int i0 = (int)floor(X + 0.5), j0 = (int)floor(Y + 0.5);
+        for (int b = -1; b <= 1; b++)
+            for (int a = -1; a <= 1; a++)
+                rho[IDX(wrap(i0 + a, nx), wrap(j0 + b, ny), nx)] +=
+                    q * shape_quad(X - (i0 + a)) * shape_quad(Y - (j0 + b));
     }
 }
 
