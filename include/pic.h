@@ -116,6 +116,20 @@ extern "C" {
 #define PIC_FLAG_ESIRKEPOV 2u
 
 /*
+ * Particle shape (pic_config.flags; not in the paper, which weights linearly,
+ * Sec. 3.1): PIC_FLAG_QUADRATIC gives every particle the quadratic B-spline
+ * shape, three nodes per axis.  The field gather weights the three nearest
+ * sample points of each staggered component on each axis; the current is
+ * Esirkepov's decomposition (as PIC_FLAG_ESIRKEPOV, which may be set too and
+ * then changes nothing) with this shape, on the 4 x 4 nodes that hold the
+ * shape before and after the motion; the charge density of pic_diag and
+ * pic_solve_gauss uses it too.  The push stages a halo two cells wide.  Needs
+ * the fixed-point current, j_replicas <= 1, sort_every 1, ppl 2 and no moving
+ * window (else PIC_EINVAL).
+ */
+#define PIC_FLAG_QUADRATIC 16u
+
+/*
  * Moving window (pic_config.flags; the last step of Listing 3.1): enables
  * pic_move_window() and sizes the workspace for it.  Not available in
  * batched mode.
@@ -166,7 +180,7 @@ typedef struct pic_config {
     int32_t j_replicas;  /* LDS current replicas per tile: 1, 2 or 4 (0 = default) */
     int32_t n_species;   /* 1 .. PIC_MAX_SPECIES */
     uint32_t flags;      /* OR of PIC_FLAG_J_FLOAT, PIC_FLAG_ESIRKEPOV, PIC_FLAG_MOVING_WINDOW,
-                            PIC_FLAG_MOTION_SORT, or 0 */
+                            PIC_FLAG_MOTION_SORT, PIC_FLAG_QUADRATIC, or 0 */
     int32_t j_filter;    /* binomial current filter passes, 0 (off) .. PIC_MAX_FILTER */
     int32_t sort_every;  /* sort cadence k = 1, 2 or 4 (0: 1): pic_step sorts every
                             k-th step and the push stages a halo k cells wide.  k > 1

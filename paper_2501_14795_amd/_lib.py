@@ -30,6 +30,7 @@ PIC_FLAG_J_FLOAT = 1
 PIC_FLAG_ESIRKEPOV = 2
 PIC_FLAG_MOVING_WINDOW = 4
 PIC_FLAG_MOTION_SORT = 8
+PIC_FLAG_QUADRATIC = 16
 
 PIC_DIAG_ENERGY = 1
 PIC_DIAG_RHO_SNAPSHOT = 2

@@ -63,8 +63,26 @@ __global__ void __launch_bounds__(256) k_rho(DiagSpecies sp, int nx, int ny, dou
     const int c = sp.cell[p];
     const int i0 = c & 0xffff, j0 = c >> 16;
     if ((unsigned)i0 >= (unsigned)nx || (unsigned)j0 >= (unsigned)ny) return;
-    const int i1 = i0 + 1 == nx ? 0 : i0 + 1, j1 = j0 + 1 == ny ? 0 : j0 + 1;
     const double x = sp.x[p], y = sp.y[p], q = sp.q;
+    if (sp.quadratic) {
+        // the three nodes nearest the particle on each axis, weighted by the
+        // quadratic B-spline at their distance
+        const int hx = x >= 0.5 ? 1 : 0, hy = y >= 0.5 ? 1 : 0;
+        const double ex = x - hx, ey = y - hy;   // offset from the nearest node, [-1/2, 1/2)
+        const double wx[3] = {0.5 * (0.5 - ex) * (0.5 - ex), 0.75 - ex * ex, 0.5 * (0.5 + ex) * (0.5 + ex)};
+        const double wy[3] = {0.5 * (0.5 - ey) * (0.5 - ey), 0.75 - ey * ey, 0.5 * (0.5 + ey) * (0.5 + ey)};
+        for (int b = 0; b < 3; ++b) {
+            int j = j0 + hy + b - 1;
+            j = j < 0 ? j + ny : (j >= ny ? j - ny : j);
+            for (int a = 0; a < 3; ++a) {
+                int i = i0 + hx + a - 1;
+                i = i < 0 ? i + nx : (i >= nx ? i - nx : i);
+                atomicAdd(&rho[(int64_t)j * nx + i], q * wx[a] * wy[b]);
+            }
+        }
+        return;
+    }
+    const int i1 = i0 + 1 == nx ? 0 : i0 + 1, j1 = j0 + 1 == ny ? 0 : j0 + 1;
     atomicAdd(&rho[(int64_t)j0 * nx + i0], q * (1.0 - x) * (1.0 - y));
     atomicAdd(&rho[(int64_t)j0 * nx + i1], q * x * (1.0 - y));
     atomicAdd(&rho[(int64_t)j1 * nx + i0], q * (1.0 - x) * y);

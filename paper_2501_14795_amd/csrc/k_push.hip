@@ -289,6 +289,87 @@ __device__ __forceinline__ void deposit_esirkepov(typename JAcc<JM>::T *sj, int 
         }
 }
 
+// Quadratic B-spline weights of the three nodes around a position e in
+// [-1/2, 1/2) from the middle one: at distances 1 + e, e, 1 - e.
+__device__ __forceinline__ void quad_w3(float e, float &wm, float &w0, float &wp)
+{
+    const float a = 0.5f - e, b = 0.5f + e;
+    wm = 0.5f * a * a;
+    w0 = fmaf(-e, e, 0.75f);
+    wp = 0.5f * b * b;
+}
+
+// Quadratic B-spline weight of a node at distance d (cells).
+__device__ __forceinline__ float quad_w(float d)
+{
+    const float a = fabsf(d), b = 1.5f - a;
+    return a <= 0.5f ? fmaf(-a, a, 0.75f) : (a < 1.5f ? 0.5f * b * b : 0.0f);
+}
+
+// Esirkepov's current with the quadratic shape (kDepQuad) of a whole straight
+// motion from (x, y) in the cell at halo index b by (dX, dY) cells.  The
+// shape covers the three nodes nearest the particle; the nearest node moves
+// by at most one, so the four nodes from one below the lower of the two
+// nearest nodes hold the shape before and after (per axis the window starts
+// 0, 1 or 2 nodes below the cell).  With the window's node weights S0, S1
+// and DS = S1 - S0, the same decomposition as deposit_esirkepov:
+//   W^x_kl = DSx_k (S0y_l + DSy_l / 2) -> Jx at (k+1/2, l) = -sum_{k'<=k} W^x
+//   W^y likewise, W^z_kl = S0x S0y + (DSx S0y + S0x DSy) / 2 + DSx DSy / 3,
+// each in accumulator units (|run| <= 3/4, W^z <= 9/16: within the
+// fixed-point range of one contribution).
+template <int NJ, int JM>
+__device__ __forceinline__ void deposit_quad(typename JAcc<JM>::T *sj, int b, float x, float y, float dX, float dY,
+                                             float az, float fq)
+{
+    constexpr int P = NJ * NJ;
+    using A = JAcc<JM>;
+    const float x1 = x + dX, y1 = y + dY;
+    // window start relative to the cell: min(nearest before, nearest after) - 1
+    const int nx0 = x >= 0.5f ? 1 : 0, ny0 = y >= 0.5f ? 1 : 0;
+    // x1, y1 lie in (-1, 2) (|dX|, |dY| < 1): their nearest node -1 .. 2 (the
+    // clamp keeps the window inside the halo whatever the input)
+    const int nx1 = min(max((int)floorf(x1 + 0.5f), -1), 2), ny1 = min(max((int)floorf(y1 + 0.5f), -1), 2);
+    const int wx = min(nx0, nx1) - 1, wy = min(ny0, ny1) - 1;
+    float s0x[4], s0y[4], dsx[4], dsy[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float px = (float)(wx + k), py = (float)(wy + k);
+        s0x[k] = quad_w(x - px);
+        dsx[k] = quad_w(x1 - px) - s0x[k];
+        s0y[k] = quad_w(y - py);
+        dsy[k] = quad_w(y1 - py) - s0y[k];
+    }
+    const int o = b + wy * NJ + wx;   // window node (0, 0)
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const float gy = fmaf(0.5f, dsy[l], s0y[l]);
+        float run = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            run = fmaf(-dsx[k], gy, run);
+            A::add(&sj[o + l * NJ + k], fq, run);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float gx = fmaf(0.5f, dsx[k], s0x[k]);
+        float run = 0.0f;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            run = fmaf(-dsy[l], gx, run);
+            A::add(&sj[P + o + l * NJ + k], fq, run);
+        }
+    }
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float w = s0x[k] * s0y[l] + 0.5f * (dsx[k] * s0y[l] + s0x[k] * dsy[l]) +
+                            dsx[k] * dsy[l] * (1.0f / 3.0f);
+            A::add(&sj[2 * P + o + l * NJ + k], az, w);
+        }
+}
+
 // The wavefront's queue of face-crossing motions: kMotionBuf entries of
 // (halo index of the start cell, x, y, dX, dY, fq vz).
 
@@ -386,7 +467,7 @@ struct Moved {
 // Interpolation, Boris push and move of one particle (no side effects, no
 // branches).  Lanes outside the run compute on a cell clamped into the halo,
 // so their LDS reads stay in bounds; their results are discarded.
-template <int T, int NJ, int NE, int H, class V2, class V1>
+template <int T, int NJ, int NE, int H, int DM, class V2, class V1>
 __device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool valid, bool rebase, int gx0,
                                          int gy0, bool tx_wrap, bool ty_wrap, float h, float fq, const V2 *s_exby,
                                          const V2 *s_eybx, const V1 *s_ez, const V1 *s_bz)
@@ -400,53 +481,118 @@ __device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool
     // it is inside the tile, and its cell is relative to the tile it was in
     // before the sort, up to H cells off: modulo T it is its cell here.
     // Anything further is flagged.
+    // (The halo pad H is the sort cadence plus the shape's pad Q.)
+    constexpr int Q = shape_pad(DM);
     int lx = tcell_x(p.cell), ly = tcell_y(p.cell);
-    const int bl = rebase ? H : H - 1;   // the band of cells allowed: -bl .. T - 1 + bl
+    const int bl = rebase ? H - Q : H - 1 - Q;   // the band of cells allowed: -bl .. T - 1 + bl
     if (valid && ((unsigned)(lx + bl) >= (unsigned)(T + 2 * bl) || (unsigned)(ly + bl) >= (unsigned)(T + 2 * bl)))
         m.err |= kErrOrder;
     if (rebase) {
         lx &= T - 1;
         ly &= T - 1;
     }
-    lx = min(max(lx, 1 - H), T + H - 2);
-    ly = min(max(ly, 1 - H), T + H - 2);
+    lx = min(max(lx, 1 - H + Q), T + H - 2 - Q);
+    ly = min(max(ly, 1 - H + Q), T + H - 2 - Q);
 
-    // ---- interpolation (bilinear at each component's staggered point)
-    const bool xh = x >= 0.5f, yh = y >= 0.5f;
-    const float wxh = xh ? x - 0.5f : x + 0.5f;   // weight for (i+1/2) points
-    const float wyh = yh ? y - 0.5f : y + 0.5f;
-    const int ch = lx + (H - 1) + (xh ? 1 : 0);   // packed column of the half stencil
-    const int rh = ly + (H - 1) + (yh ? 1 : 0);
-    const int c0 = lx + H, r0 = ly + H;
-    const int e0 = __mul24(r0, NE), eh = __mul24(rh, NE);
-    // each stencil: the two x-neighbours on two rows (the values at cells
-    // (c, c+1) of a row: one entry in the packed layout, two adjacent ones
-    // -- one ds_read2 -- otherwise)
     float Ex, By, Ey, Bx, Ez, Bz;
-    if constexpr (std::is_same<V2, float4>::value) {
-        const float4 p0 = s_exby[e0 + ch], p1 = s_exby[e0 + NE + ch];
-        const float4 q0 = s_eybx[eh + c0], q1 = s_eybx[eh + NE + c0];
-        const float2 z0 = s_ez[e0 + c0], z1 = s_ez[e0 + NE + c0];
-        const float2 b0 = s_bz[eh + ch], b1 = s_bz[eh + NE + ch];
-        Ex = lerpf(lerpf(p0.x, p0.z, wxh), lerpf(p1.x, p1.z, wxh), y);
-        By = lerpf(lerpf(p0.y, p0.w, wxh), lerpf(p1.y, p1.w, wxh), y);
-        Ey = lerpf(lerpf(q0.x, q0.z, x), lerpf(q1.x, q1.z, x), wyh);
-        Bx = lerpf(lerpf(q0.y, q0.w, x), lerpf(q1.y, q1.w, x), wyh);
-        Ez = lerpf(lerpf(z0.x, z0.y, x), lerpf(z1.x, z1.y, x), y);
-        Bz = lerpf(lerpf(b0.x, b0.y, wxh), lerpf(b1.x, b1.y, wxh), wyh);
+    if constexpr (DM == kDepQuad) {
+        // ---- interpolation with the quadratic shape: per axis the three
+        // sample points nearest the particle.  Points at whole cells: the
+        // nearest is the cell's own or the next one (x >= 1/2), at offset
+        // ex = x or x - 1; points at half cells: the nearest is the cell's,
+        // at offset x - 1/2.  Stencil columns from ci / ch, rows from ri / rh
+        // (LDS indices; within 1 .. NE - 1 by the clamp above).
+        const int hx = x >= 0.5f ? 1 : 0, hy = y >= 0.5f ? 1 : 0;
+        float ix3[3], hx3[3], iy3[3], hy3[3];
+        quad_w3(x - (float)hx, ix3[0], ix3[1], ix3[2]);
+        quad_w3(x - 0.5f, hx3[0], hx3[1], hx3[2]);
+        quad_w3(y - (float)hy, iy3[0], iy3[1], iy3[2]);
+        quad_w3(y - 0.5f, hy3[0], hy3[1], hy3[2]);
+        const int ci = lx + hx - 1 + H, ch = lx - 1 + H;
+        const int ri = ly + hy - 1 + H, rh = ly - 1 + H;
+        Ex = By = Ey = Bx = Ez = Bz = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const int ei = __mul24(ri + r, NE), eh = __mul24(rh + r, NE);
+            // the three values of a row: packed entries hold a cell and the next
+            float2 p3[3], q3[3];
+            float z3[3], b3[3];
+            if constexpr (std::is_same<V2, float4>::value) {
+                const float4 pa = s_exby[ei + ch], pb = s_exby[ei + ch + 2];
+                const float4 qa = s_eybx[eh + ci], qb = s_eybx[eh + ci + 2];
+                const float2 za = s_ez[ei + ci], zb = s_ez[ei + ci + 2];
+                const float2 ba = s_bz[eh + ch], bb = s_bz[eh + ch + 2];
+                p3[0] = make_float2(pa.x, pa.y);
+                p3[1] = make_float2(pa.z, pa.w);
+                p3[2] = make_float2(pb.x, pb.y);
+                q3[0] = make_float2(qa.x, qa.y);
+                q3[1] = make_float2(qa.z, qa.w);
+                q3[2] = make_float2(qb.x, qb.y);
+                z3[0] = za.x;
+                z3[1] = za.y;
+                z3[2] = zb.x;
+                b3[0] = ba.x;
+                b3[1] = ba.y;
+                b3[2] = bb.x;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    p3[k] = s_exby[ei + ch + k];
+                    q3[k] = s_eybx[eh + ci + k];
+                    z3[k] = s_ez[ei + ci + k];
+                    b3[k] = s_bz[eh + ch + k];
+                }
+            }
+            const float pex = fmaf(hx3[0], p3[0].x, fmaf(hx3[1], p3[1].x, hx3[2] * p3[2].x));
+            const float pby = fmaf(hx3[0], p3[0].y, fmaf(hx3[1], p3[1].y, hx3[2] * p3[2].y));
+            const float qey = fmaf(ix3[0], q3[0].x, fmaf(ix3[1], q3[1].x, ix3[2] * q3[2].x));
+            const float qbx = fmaf(ix3[0], q3[0].y, fmaf(ix3[1], q3[1].y, ix3[2] * q3[2].y));
+            const float zz = fmaf(ix3[0], z3[0], fmaf(ix3[1], z3[1], ix3[2] * z3[2]));
+            const float bz = fmaf(hx3[0], b3[0], fmaf(hx3[1], b3[1], hx3[2] * b3[2]));
+            Ex = fmaf(iy3[r], pex, Ex);
+            By = fmaf(iy3[r], pby, By);
+            Ey = fmaf(hy3[r], qey, Ey);
+            Bx = fmaf(hy3[r], qbx, Bx);
+            Ez = fmaf(iy3[r], zz, Ez);
+            Bz = fmaf(hy3[r], bz, Bz);
+        }
     } else {
-        const float2 p0 = s_exby[e0 + ch], p0r = s_exby[e0 + ch + 1];
-        const float2 p1 = s_exby[e0 + NE + ch], p1r = s_exby[e0 + NE + ch + 1];
-        const float2 q0 = s_eybx[eh + c0], q0r = s_eybx[eh + c0 + 1];
-        const float2 q1 = s_eybx[eh + NE + c0], q1r = s_eybx[eh + NE + c0 + 1];
-        const float z0 = s_ez[e0 + c0], z0r = s_ez[e0 + c0 + 1], z1 = s_ez[e0 + NE + c0], z1r = s_ez[e0 + NE + c0 + 1];
-        const float b0 = s_bz[eh + ch], b0r = s_bz[eh + ch + 1], b1 = s_bz[eh + NE + ch], b1r = s_bz[eh + NE + ch + 1];
-        Ex = lerpf(lerpf(p0.x, p0r.x, wxh), lerpf(p1.x, p1r.x, wxh), y);
-        By = lerpf(lerpf(p0.y, p0r.y, wxh), lerpf(p1.y, p1r.y, wxh), y);
-        Ey = lerpf(lerpf(q0.x, q0r.x, x), lerpf(q1.x, q1r.x, x), wyh);
-        Bx = lerpf(lerpf(q0.y, q0r.y, x), lerpf(q1.y, q1r.y, x), wyh);
-        Ez = lerpf(lerpf(z0, z0r, x), lerpf(z1, z1r, x), y);
-        Bz = lerpf(lerpf(b0, b0r, wxh), lerpf(b1, b1r, wxh), wyh);
+        // ---- interpolation (bilinear at each component's staggered point)
+        const bool xh = x >= 0.5f, yh = y >= 0.5f;
+        const float wxh = xh ? x - 0.5f : x + 0.5f;   // weight for (i+1/2) points
+        const float wyh = yh ? y - 0.5f : y + 0.5f;
+        const int ch = lx + (H - 1) + (xh ? 1 : 0);   // packed column of the half stencil
+        const int rh = ly + (H - 1) + (yh ? 1 : 0);
+        const int c0 = lx + H, r0 = ly + H;
+        const int e0 = __mul24(r0, NE), eh = __mul24(rh, NE);
+        // each stencil: the two x-neighbours on two rows (the values at cells
+        // (c, c+1) of a row: one entry in the packed layout, two adjacent ones
+        // -- one ds_read2 -- otherwise)
+        if constexpr (std::is_same<V2, float4>::value) {
+            const float4 p0 = s_exby[e0 + ch], p1 = s_exby[e0 + NE + ch];
+            const float4 q0 = s_eybx[eh + c0], q1 = s_eybx[eh + NE + c0];
+            const float2 z0 = s_ez[e0 + c0], z1 = s_ez[e0 + NE + c0];
+            const float2 b0 = s_bz[eh + ch], b1 = s_bz[eh + NE + ch];
+            Ex = lerpf(lerpf(p0.x, p0.z, wxh), lerpf(p1.x, p1.z, wxh), y);
+            By = lerpf(lerpf(p0.y, p0.w, wxh), lerpf(p1.y, p1.w, wxh), y);
+            Ey = lerpf(lerpf(q0.x, q0.z, x), lerpf(q1.x, q1.z, x), wyh);
+            Bx = lerpf(lerpf(q0.y, q0.w, x), lerpf(q1.y, q1.w, x), wyh);
+            Ez = lerpf(lerpf(z0.x, z0.y, x), lerpf(z1.x, z1.y, x), y);
+            Bz = lerpf(lerpf(b0.x, b0.y, wxh), lerpf(b1.x, b1.y, wxh), wyh);
+        } else {
+            const float2 p0 = s_exby[e0 + ch], p0r = s_exby[e0 + ch + 1];
+            const float2 p1 = s_exby[e0 + NE + ch], p1r = s_exby[e0 + NE + ch + 1];
+            const float2 q0 = s_eybx[eh + c0], q0r = s_eybx[eh + c0 + 1];
+            const float2 q1 = s_eybx[eh + NE + c0], q1r = s_eybx[eh + NE + c0 + 1];
+            const float z0 = s_ez[e0 + c0], z0r = s_ez[e0 + c0 + 1], z1 = s_ez[e0 + NE + c0], z1r = s_ez[e0 + NE + c0 + 1];
+            const float b0 = s_bz[eh + ch], b0r = s_bz[eh + ch + 1], b1 = s_bz[eh + NE + ch], b1r = s_bz[eh + NE + ch + 1];
+            Ex = lerpf(lerpf(p0.x, p0r.x, wxh), lerpf(p1.x, p1r.x, wxh), y);
+            By = lerpf(lerpf(p0.y, p0r.y, wxh), lerpf(p1.y, p1r.y, wxh), y);
+            Ey = lerpf(lerpf(q0.x, q0r.x, x), lerpf(q1.x, q1r.x, x), wyh);
+            Bx = lerpf(lerpf(q0.y, q0r.y, x), lerpf(q1.y, q1r.y, x), wyh);
+            Ez = lerpf(lerpf(z0, z0r, x), lerpf(z1, z1r, x), y);
+            Bz = lerpf(lerpf(b0, b0r, wxh), lerpf(b1, b1r, wxh), wyh);
+        }
     }
 
     // ---- Boris push (Eqs. 6-10); 1 + |u|^2 >= 1, so the hardware
@@ -482,7 +628,7 @@ __device__ __forceinline__ Moved advance(const PushArgs &a, const Chunk &p, bool
     // the queue is drained
     m.fqvz = fq * uz * ig;
     m.b = jcell<NJ, H>(lx, ly);
-    m.cross = valid && (sxn | syn) != 0;
+    m.cross = DM != kDepQuad && valid && (sxn | syn) != 0;   // the quadratic deposit is one call for every motion
     m.x = x;
     m.y = y;
     m.dX = dX;
@@ -666,7 +812,11 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile, con
             // and discard them.  The next C chunks are always prefetched
             // before the current ones are processed.
             auto finish = [&](const Moved &m, int i, int at) {
-                if (m.valid && !m.cross) deposit_piece<NJ, JM>(sj, m.b, m.x, m.y, m.dX, m.dY, m.fqvz, fq);
+                if constexpr (DM == kDepQuad) {
+                    if (m.valid) deposit_quad<NJ, JM>(sj, m.b, m.x, m.y, m.dX, m.dY, m.fqvz, fq);
+                } else {
+                    if (m.valid && !m.cross) deposit_piece<NJ, JM>(sj, m.b, m.x, m.y, m.dX, m.dY, m.fqvz, fq);
+                }
                 if (m.valid) {
                     __builtin_amdgcn_raw_buffer_store_b16((unsigned short)m.nlc, st.cell, at >> 1, 0, kStoreCpol);
                     stf(st.x, at, m.xn);
@@ -741,7 +891,7 @@ __device__ __forceinline__ void push_tile(const PushArgs &a, const int tile, con
                 Moved m[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
-                    m[c] = advance<T, NJ, NE, H, V2, V1>(a, cur[c], i + 64 * c >= lo && i + 64 * c < hi, rebase,
+                    m[c] = advance<T, NJ, NE, H, DM, V2, V1>(a, cur[c], i + 64 * c >= lo && i + 64 * c < hi, rebase,
                                                          gx0, gy0, tx_wrap, ty_wrap, h, fq, s_exby, s_eybx, s_ez,
                                                          s_bz);
                     errs |= m[c].err;
@@ -944,11 +1094,17 @@ struct PushLaunch {
 };
 
 // particles per lane per pass: 1, 2 or 4 for the default current and
-// deposit with one LDS copy (the configurations the autotuner searches), 2
-// otherwise (pic_query / pic_init refuse the rest)
+// deposit with one LDS copy (the configurations the autotuner searches), 1
+// for the quadratic shape, 2 otherwise (pic_query / pic_init refuse the rest)
 template <int T, int R, int JM, int DM, int H>
 static void push_c(const PushLaunch &L, int ppl)
 {
+    if constexpr (DM == kDepQuad) {
+        // one chunk per lane: the nine-point stencils of two particles in
+        // flight would not fit the register budget
+        L.go<T, R, JM, DM, H, 1>();
+        return;
+    }
     if constexpr (R == 1 && JM == kJFixed && DM == kDepVB) {
         if (ppl == 1) {
             L.go<T, R, JM, DM, H, 1>();
@@ -965,6 +1121,11 @@ static void push_c(const PushLaunch &L, int ppl)
 template <int T, int JM, int DM>
 static void push_r(const PushLaunch &L, int replicas, int halo, int ppl)
 {
+    if constexpr (DM == kDepQuad) {
+        // the quadratic shape: one sort per step, halo pad 2, one LDS copy
+        if (halo == 2) push_c<T, 1, JM, DM, 2>(L, ppl);
+        return;
+    }
     if (halo > 1) {
         // sort cadences above 1: fixed-point current, one LDS copy
         if constexpr (JM == kJFixed) {
@@ -980,11 +1141,13 @@ static void push_r(const PushLaunch &L, int replicas, int halo, int ppl)
     }
 }
 
-// the Esirkepov deposit is built for the fixed-point current only
+// the Esirkepov deposit (linear or quadratic shape) is built for the
+// fixed-point current only
 template <int T>
 static void push_j(const PushLaunch &L, int replicas, int jmode, int dmode, int halo, int ppl)
 {
     if (jmode == kJFloat) push_r<T, kJFloat, kDepVB>(L, replicas, halo, ppl);
+    else if (dmode == kDepQuad) push_r<T, kJFixed, kDepQuad>(L, replicas, halo, ppl);
     else if (dmode == kDepEsirkepov) push_r<T, kJFixed, kDepEsirkepov>(L, replicas, halo, ppl);
     else push_r<T, kJFixed, kDepVB>(L, replicas, halo, ppl);
 }

@@ -30,9 +30,16 @@ struct Layout {
 };
 
 int j_mode(const pic_config *c) { return (c->flags & PIC_FLAG_J_FLOAT) ? kJFloat : kJFixed; }
-int d_mode(const pic_config *c) { return (c->flags & PIC_FLAG_ESIRKEPOV) ? kDepEsirkepov : kDepVB; }
+int d_mode(const pic_config *c)
+{
+    if (c->flags & PIC_FLAG_QUADRATIC) return kDepQuad;
+    return (c->flags & PIC_FLAG_ESIRKEPOV) ? kDepEsirkepov : kDepVB;
+}
 
-int halo_of(const pic_config *c) { return c->sort_every ? c->sort_every : 1; }
+// sort cadence: pushes between sorts
+int cadence_of(const pic_config *c) { return c->sort_every ? c->sort_every : 1; }
+// the push kernel's halo pad: the cadence, plus what the particle shape needs
+int halo_of(const pic_config *c) { return cadence_of(c) + shape_pad(d_mode(c)); }
 int ppl_of(const pic_config *c) { return c->ppl ? c->ppl : 2; }
 
 int default_replicas(const pic_config *c)
@@ -44,8 +51,11 @@ int default_replicas(const pic_config *c)
 int validate(const pic_config *c)
 {
     if (!c) return PIC_EINVAL;
-    if (c->flags & ~(uint32_t)(PIC_FLAG_J_FLOAT | PIC_FLAG_ESIRKEPOV | PIC_FLAG_MOVING_WINDOW | PIC_FLAG_MOTION_SORT))
+    if (c->flags & ~(uint32_t)(PIC_FLAG_J_FLOAT | PIC_FLAG_ESIRKEPOV | PIC_FLAG_MOVING_WINDOW | PIC_FLAG_MOTION_SORT |
+                               PIC_FLAG_QUADRATIC))
         return PIC_EINVAL;
+    // the quadratic shape is built for one sort per step (its halo pad is 2)
+    if ((c->flags & PIC_FLAG_QUADRATIC) && c->sort_every > 1) return PIC_EINVAL;
     // the Esirkepov deposit is built for the fixed-point current only
     if ((c->flags & PIC_FLAG_ESIRKEPOV) && (c->flags & PIC_FLAG_J_FLOAT)) return PIC_EINVAL;
     if (c->tile != 8 && c->tile != 16 && c->tile != 32) return PIC_ETILE;
@@ -60,7 +70,8 @@ int validate(const pic_config *c)
         if (push_lds_bytes(c->tile, r, j_mode(c)) > kLdsBytes) return PIC_EINVAL;
     }
     {
-        // sort cadence: the push kernel's halo pad is the number of steps between sorts
+        // the push kernel's halo pad: the number of steps between sorts (plus
+        // one cell for the quadratic shape)
         const int k = halo_of(c);
         if (k != 1 && k != 2 && k != 4) return PIC_EINVAL;
         if (k > 1) {
@@ -161,7 +172,8 @@ struct pic_sim {
     float *jf;          // filter partner of the J planes (j_filter > 0)
     double *rho_tmp;    // filter partner of rho_now (j_filter > 0)
     int32_t origin;     // moving window: array column of window column 0
-    int halo;           // sort cadence: pushes between sorts (the push kernel's halo pad)
+    int cadence;        // sort cadence: pushes between sorts
+    int halo;           // the push kernel's halo pad (the cadence, + 1 for the quadratic shape)
     int since_sort;     // pushes since the last sort
     int32_t *wrem;      // moving window: particles that left, per species
     // pic_step's second stream: the field half of a step (J fold, filter,
@@ -320,6 +332,7 @@ DiagSpecies diag_species(const pic_sim *s, int k)
     d.uz = p.uz;
     d.n = (int32_t)s->cfg.species[k].n;
     d.q = s->cfg.species[k].q;
+    d.quadratic = d_mode(&s->cfg) == kDepQuad ? 1 : 0;
     return d;
 }
 
@@ -705,6 +718,7 @@ int init_sim(const pic_config *cfg, const pic_buffers *bufs, hipStream_t stream,
     const bool window = (cfg->flags & PIC_FLAG_MOVING_WINDOW) != 0;
     S->wrem = window ? (int32_t *)(w + L.wrem) : nullptr;
     S->origin = 0;
+    S->cadence = cadence_of(cfg);
     S->halo = halo_of(cfg);
     S->since_sort = 0;
     for (int s = 0; s < cfg->n_species; ++s) {
@@ -790,7 +804,7 @@ bool motion_deferrable(const pic_sim *S)
 int push_only(pic_sim *S, hipStream_t stream, bool bh)
 {
     // a particle may stray at most sort_every - 1 cells from its tile before a push
-    if (S->since_sort >= S->halo) return PIC_EORDER;
+    if (S->since_sort >= S->cadence) return PIC_EORDER;
     const PushArgs a = push_args(S, bh);
     const bool ms = motion_deferrable(S);
     {
@@ -1054,8 +1068,8 @@ int pic_step(pic_sim *S, hipStream_t stream)
     int rc = push_only(S, stream, true);
     if (rc) return rc;
     // Unforked: no sort this step, or no second stream
-    if (S->since_sort < S->halo || !S->side) {
-        if (S->since_sort >= S->halo) rc = sort_after_push(S, stream, true);
+    if (S->since_sort < S->cadence || !S->side) {
+        if (S->since_sort >= S->cadence) rc = sort_after_push(S, stream, true);
         if (rc == PIC_OK) rc = field_half(S, stream);
         return rc;
     }
@@ -1288,7 +1302,8 @@ void pic_destroy(pic_sim *S)
 struct pic_batch {
     std::vector<pic_sim *> sims;
     int tile, replicas, jm, dm;
-    int halo;    // sort cadence shared by the members
+    int cadence; // sort cadence shared by the members
+    int halo;    // the push kernel's halo pad
     int ppl;     // particles per lane of the push loop, shared by the members
     int phase;   // steps since the members were last sorted
     char *dev;
@@ -1451,6 +1466,7 @@ int pic_batch_init(int n, const pic_config *cfgs, const pic_buffers *bufs, void 
     B->jm = j_mode(&cfgs[0]);
     B->dm = d_mode(&cfgs[0]);
     B->replicas = cfgs[0].j_replicas ? cfgs[0].j_replicas : default_replicas(&cfgs[0]);
+    B->cadence = cadence_of(&cfgs[0]);
     B->halo = halo_of(&cfgs[0]);
     B->ppl = ppl_of(&cfgs[0]);
     B->phase = 0;
@@ -1538,12 +1554,12 @@ int pic_batch_step(pic_batch *B, int nsteps, hipStream_t stream)
     if (!B || nsteps < 0) return PIC_EINVAL;
     int k = 0;
     while (k < nsteps) {
-        if (B->exec && B->phase == 0 && nsteps - k >= B->halo) {
-            // one captured cadence cycle: halo steps, the last with the sort
+        if (B->exec && B->phase == 0 && nsteps - k >= B->cadence) {
+            // one captured cadence cycle: cadence steps, the last with the sort
             if (hipGraphLaunch(B->exec, stream) != hipSuccess) return PIC_EHIP;
-            k += B->halo;
+            k += B->cadence;
         } else {
-            const bool sort = B->phase + 1 == B->halo;
+            const bool sort = B->phase + 1 == B->cadence;
             batch_enqueue_step(B, sort, B->phase == 0, stream);
             B->phase = sort ? 0 : B->phase + 1;
             k += 1;
@@ -1566,7 +1582,7 @@ int pic_batch_capture(pic_batch *B, hipStream_t stream)
         B->graph = nullptr;
     }
     if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return PIC_EHIP;
-    for (int k = 0; k < B->halo; ++k) batch_enqueue_step(B, k + 1 == B->halo, k == 0, stream);
+    for (int k = 0; k < B->cadence; ++k) batch_enqueue_step(B, k + 1 == B->cadence, k == 0, stream);
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(stream, &g) != hipSuccess || !g) return PIC_EHIP;
     B->graph = g;

@@ -181,6 +181,7 @@ struct DiagSpecies {
     const float *x, *y, *ux, *uy, *uz;
     int32_t n;
     double q;
+    int quadratic;   // the particle shape: 0 linear, 1 quadratic B-spline
 };
 void launch_diag_field_energy(const float *fld, int64_t plane, double *acc, hipStream_t s);
 void launch_diag_kinetic(const DiagSpecies &sp, double *acc, hipStream_t s);

@@ -82,6 +82,14 @@ constexpr float kFixedScale = 1073741824.0f;
 // deposit scheme of the push kernel
 constexpr int kDepVB = 0;          // Villasenor-Buneman with the 1/2/3-piece split (Eqs. 13-16)
 constexpr int kDepEsirkepov = 1;   // Esirkepov's density decomposition (variant)
+// The quadratic particle shape (B-spline of order two, three nodes per axis):
+// the field gather at each component's staggered point and Esirkepov's
+// current with that shape.  The shape reaches one node further than the
+// linear one, so the push stages a halo one cell wider than the sort cadence
+// alone needs.
+constexpr int kDepQuad = 2;
+// extra halo cells the deposit scheme's shape needs beyond the cadence's
+__host__ __device__ constexpr int shape_pad(int DM) { return DM == kDepQuad ? 1 : 0; }
 
 constexpr int kLdsBytes = 160 * 1024;   // LDS of one gfx950 compute unit
 constexpr int kMotionBuf = 64;           // queued face-crossing motions per wavefront

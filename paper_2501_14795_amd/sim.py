@@ -37,7 +37,7 @@ class _Buffers:
 
     def __init__(self, nx, ny, dx, dy, dt, tile, species, E=None, B=None, j_replicas=0, j_float=False,
                  device="cuda:0", j_filter=0, esirkepov=False, moving_window=False, capacity=None,
-                 sort_every=1, motion_sort=False, ppl=0):
+                 sort_every=1, motion_sort=False, ppl=0, quadratic=False):
         torch = _torch()
         if not 1 <= len(species) <= _lib.MAX_SPECIES:
             raise ValueError("1..4 species")
@@ -48,7 +48,8 @@ class _Buffers:
         cfg.j_replicas = int(j_replicas)
         cfg.n_species = len(species)
         cfg.flags = ((_lib.PIC_FLAG_J_FLOAT if j_float else 0) | (_lib.PIC_FLAG_ESIRKEPOV if esirkepov else 0) |
-                     (_lib.PIC_FLAG_MOVING_WINDOW if moving_window else 0) | (_lib.PIC_FLAG_MOTION_SORT if motion_sort else 0))
+                     (_lib.PIC_FLAG_MOVING_WINDOW if moving_window else 0) | (_lib.PIC_FLAG_MOTION_SORT if motion_sort else 0) |
+                     (_lib.PIC_FLAG_QUADRATIC if quadratic else 0))
         cfg.j_filter = int(j_filter)
         cfg.sort_every = int(sort_every)
         cfg.ppl = int(ppl)
@@ -299,12 +300,12 @@ class Sim(_SimView):
                  species: Sequence, E: Optional[np.ndarray] = None, B: Optional[np.ndarray] = None,
                  j_replicas: int = 0, j_float: bool = False, device: str = "cuda:0", stream=None,
                  j_filter: int = 0, esirkepov: bool = False, moving_window: bool = False, capacity=None,
-                 sort_every: int = 1, motion_sort: bool = False, ppl: int = 0):
+                 sort_every: int = 1, motion_sort: bool = False, ppl: int = 0, quadratic: bool = False):
         torch = _torch()
         self.handle = None
         self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
         self.buf = _Buffers(nx, ny, dx, dy, dt, tile, species, E, B, j_replicas, j_float, device, j_filter,
-                            esirkepov, moving_window, capacity, sort_every, motion_sort, ppl)
+                            esirkepov, moving_window, capacity, sort_every, motion_sort, ppl, quadratic)
         self.cfg = self.buf.cfg
         torch.cuda.synchronize(torch.device(device))
         self.handle = _lib.pic_init(self.cfg, self.buf.bufs, self.s)
@@ -341,13 +342,14 @@ class Batch:
 
     def __init__(self, members: Sequence[dict], tile: int, j_replicas: int = 0, j_float: bool = False,
                  device: str = "cuda:0", stream=None, j_filter: int = 0, esirkepov: bool = False,
-                 sort_every: int = 1, ppl: int = 0, motion_sort: bool = False):
+                 sort_every: int = 1, ppl: int = 0, motion_sort: bool = False, quadratic: bool = False):
         torch = _torch()
         self.handle = None
         self.stream = stream if stream is not None else torch.cuda.Stream(torch.device(device))
         self.bufs = [_Buffers(m["nx"], m["ny"], m["dx"], m["dy"], m["dt"], tile, m["species"], m.get("E"),
                               m.get("B"), j_replicas, j_float, device, j_filter, esirkepov,
-                              sort_every=sort_every, ppl=ppl, motion_sort=motion_sort) for m in members]
+                              sort_every=sort_every, ppl=ppl, motion_sort=motion_sort, quadratic=quadratic)
+                     for m in members]
         cfgs = [b.cfg for b in self.bufs]
         nbytes = _lib.pic_batch_query(cfgs)
         self.work = torch.empty(nbytes + 256, dtype=torch.uint8, device=torch.device(device))

@@ -18,17 +18,18 @@ def species_states(nx, ny, tile, specs, seed, cell_box=None):
 
 
 def make_pair(nx, ny, dx, dy, dt, tile, specs, states, E=None, B=None, j_replicas=0, j_float=False, j_filter=0,
-              esirkepov=False, sort_every=1, motion_sort=False):
+              esirkepov=False, sort_every=1, motion_sort=False, quadratic=False):
     """GPU Sim and OracleSim from the same FP32 initial state."""
     from paper_2501_14795_amd import Sim
     sim = Sim(nx, ny, dx, dy, dt, tile, [(s.qm, s.q, st) for s, st in zip(specs, states)], E=E, B=B,
               j_replicas=j_replicas, j_float=j_float, j_filter=j_filter, esirkepov=esirkepov, sort_every=sort_every,
-              motion_sort=motion_sort)
+              motion_sort=motion_sort, quadratic=quadratic)
     osp = [oracle.OracleSpecies(s.qm, s.q, st["ix"], st["iy"], st["x"], st["y"], st["ux"], st["uy"], st["uz"])
            for s, st in zip(specs, states)]
     ora = oracle.OracleSim(nx, ny, dx, dy, dt, osp,
                            None if E is None else E.astype(np.float64),
-                           None if B is None else B.astype(np.float64), j_filter=j_filter, esirkepov=esirkepov)
+                           None if B is None else B.astype(np.float64), j_filter=j_filter, esirkepov=esirkepov,
+                           quadratic=quadratic)
     return sim, ora
 
 

@@ -95,7 +95,14 @@ def test_query_sizes_and_validation():
         (dict(ns=0), L.PIC_EINVAL),
         (dict(ns=5), L.PIC_EINVAL),
         (dict(reps=3), L.PIC_EINVAL),
-        (dict(flags=16), L.PIC_EINVAL),
+        (dict(flags=32), L.PIC_EINVAL),
+        # the quadratic shape: one sort per step, fixed-point current, one LDS
+        # copy, two particles per lane, no moving window
+        (dict(flags=16, every=2), L.PIC_EINVAL),
+        (dict(flags=16 | 1), L.PIC_EINVAL),
+        (dict(flags=16, reps=2), L.PIC_EINVAL),
+        (dict(flags=16 | 4), L.PIC_EINVAL),
+        (dict(flags=16, ppl=1), L.PIC_EINVAL),
         (dict(flags=3), L.PIC_EINVAL),          # Esirkepov needs the fixed-point current
         (dict(n=-1), L.PIC_EINVAL),
         (dict(n=2 ** 31), L.PIC_EINVAL),
@@ -157,6 +164,11 @@ def test_query_sizes_and_validation():
         grow = base.n_tiles * 3 * 4 * ((T + 2 * every + 1) ** 2 - (T + 3) ** 2)
         assert grow <= wide.work_bytes - base.work_bytes <= grow + 256, (every, T)
     assert L.pic_query(_cfg(L, every=1)).work_bytes == s.work_bytes
+    # the quadratic shape reaches one node further: the halo pad of a cadence of 2
+    for T in (8, 16, 32):
+        q = L.pic_query(_cfg(L, tile=T, flags=L.PIC_FLAG_QUADRATIC))
+        assert q.work_bytes == L.pic_query(_cfg(L, tile=T, every=2)).work_bytes, T
+        assert q.work_bytes == L.pic_query(_cfg(L, tile=T, flags=L.PIC_FLAG_QUADRATIC | 2, every=1)).work_bytes
     # the filter's ping-pong planes: three FP32 current planes + one FP64 density plane
     sf = L.pic_query(_cfg(L, filt=L.PIC_MAX_FILTER))
     assert 20 * 64 * 64 <= sf.work_bytes - s.work_bytes <= 20 * 64 * 64 + 2 * 256
