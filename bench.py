@@ -53,11 +53,12 @@ def log(msg):
 def push_bytes(n_particles, n_tiles, tile, leavers, n_species=1, halo=1):
     """Algorithmic HBM bytes of one push + deposit launch of pic_step: every
     particle read and written once, each tile's E/B halo ((T+2H)^2 cells x 6
-    fields, H the halo pad: 1, or the sort cadence) read once, each tile's
-    current halo ((T+2H+1)^2 nodes x 3) written once, the B half step of the
-    tile's T^2 cells (3 floats each) written once, the tile_offset pair and
-    the count record (32 ints) per tile and species, and one 4-byte entry per
-    leaver (the leavers' 32-byte records are not counted)."""
+    fields, H the halo pad: 1, the sort cadence, or 2 for the quadratic
+    shape) read once, each tile's current halo ((T+2H+1)^2 nodes x 3)
+    written once, the B half step of the tile's T^2 cells (3 floats each)
+    written once, the tile_offset pair and the count record (32 ints) per
+    tile and species, and one 4-byte entry per leaver (the leavers' 32-byte
+    records are not counted)."""
     return (2 * BYTES_PARTICLE * n_particles
             + n_tiles * (tile + 2 * halo) ** 2 * 6 * 4
             + n_tiles * (tile + 2 * halo + 1) ** 2 * 3 * 4
@@ -66,7 +67,7 @@ def push_bytes(n_particles, n_tiles, tile, leavers, n_species=1, halo=1):
             + 4 * leavers)
 
 
-def step_bytes(n_particles, n_tiles, tile, nx, ny, leavers, movers, n_species=1, motion=False):
+def step_bytes(n_particles, n_tiles, tile, nx, ny, leavers, movers, n_species=1, motion=False, halo=1):
     """Algorithmic HBM bytes of one whole pic_step: the push (push_bytes),
     the hole fill it does for the last sort (per mover: its hole slot and its
     32-byte staged record), the field half (the E step: E read and written,
@@ -78,15 +79,16 @@ def step_bytes(n_particles, n_tiles, tile, nx, ny, leavers, movers, n_species=1,
     counting pass instead (per tile its class counts and offsets; per
     particle its 2-byte cell read to count, then its 22 bytes read and
     written into the staging arrays) and there is no hole fill: the push
-    reads the staging arrays, the same bytes as the particle arrays."""
+    reads the staging arrays, the same bytes as the particle arrays.  halo:
+    the push's halo pad (2 for the quadratic shape)."""
     plane = 4 * nx * ny
-    field = 21 * plane + n_tiles * (tile + 3) ** 2 * 3 * 4
+    field = 21 * plane + n_tiles * (tile + 2 * halo + 1) ** 2 * 3 * 4
     sort = n_species * n_tiles * (9 * 4 + 8) + 4 * leavers + movers * (32 + 32 + 4)
     fill = movers * (4 + 32)
     if motion:
         sort = n_species * n_tiles * (9 * 4 + 8) + (2 * BYTES_PARTICLE + 2) * n_particles
         fill = 0
-    return push_bytes(n_particles, n_tiles, tile, leavers, n_species) + fill + field + sort
+    return push_bytes(n_particles, n_tiles, tile, leavers, n_species, halo) + fill + field + sort
 
 
 def cpu_baseline(w, st, T, budget_s=10.0, max_steps=8):
@@ -394,6 +396,8 @@ def main():
     ap.add_argument("--j-float", action="store_true", help="FP32-atomic LDS current instead of fixed point")
     ap.add_argument("--j-filter", type=int, default=0, help="binomial current filter passes in the timed step")
     ap.add_argument("--esirkepov", action="store_true", help="Esirkepov deposit instead of split Villasenor-Buneman")
+    ap.add_argument("--quadratic", action="store_true",
+                    help="the quadratic particle shape (gather and Esirkepov deposit) in the timed step")
     ap.add_argument("--motion-sort", action="store_true",
                     help="the motion-class sort instead of the in-place one in the timed step")
     ap.add_argument("--no-variants", action="store_true",
@@ -446,7 +450,7 @@ def main():
 
     sim = Sim(w.nx, w.ny, w.dx, w.dy, w.dt, T, [(s.qm, s.q, st) for s, st in zip(w.species, states)],
               j_replicas=args.replicas, j_float=args.j_float, j_filter=args.j_filter, esirkepov=args.esirkepov,
-              motion_sort=args.motion_sort)
+              motion_sort=args.motion_sort, quadratic=args.quadratic)
     del states
     log("initialised")
     for _ in range(args.warmup):
@@ -486,16 +490,19 @@ def main():
     ms_step = elapsed * 1e3 / args.steps
     value = n * args.steps / elapsed
     push_ms = kt_push[0] / max(kt_push[1], 1)
-    pb = push_bytes(n, sim.n_tiles, T, leavers, len(w.species))
+    halo = 2 if args.quadratic else 1
+    pb = push_bytes(n, sim.n_tiles, T, leavers, len(w.species), halo)
     achieved = pb / (push_ms * 1e-3) / 1e9
-    sb = step_bytes(n, sim.n_tiles, T, w.nx, w.ny, leavers, movers, len(w.species), motion=args.motion_sort)
+    sb = step_bytes(n, sim.n_tiles, T, w.nx, w.ny, leavers, movers, len(w.species), motion=args.motion_sort,
+                    halo=halo)
     step_gbs = sb / (ms_step * 1e-3) / 1e9
     hot_ms = sum(kt[k][0] for k in ("push", "j_reduce", "sort_scan", "sort_plan", "sort_scatter")) / split_steps
 
     traffic = None
     # the counters were taken on the default push (split Villasenor-Buneman
     # deposit, fixed-point current, in-place sort, no filter)
-    default_push = not (args.esirkepov or args.j_float or args.motion_sort or args.j_filter or args.replicas > 1)
+    default_push = not (args.esirkepov or args.j_float or args.motion_sort or args.j_filter or args.replicas > 1 or
+                        args.quadratic)
     if default_push and os.path.exists(args.traffic_json):
         try:
             tj = json.load(open(args.traffic_json))
@@ -523,7 +530,8 @@ def main():
                    "j_accumulation": "fp32-atomic" if args.j_float else "int64-fixed-point",
                    "j_replicas": args.replicas or ((4 if T < 32 else 2) if args.j_float else 1),
                    "sort_every": 1, "j_filter": args.j_filter,
-                   "deposit": "esirkepov" if args.esirkepov else "villasenor-buneman-split",
+                   "deposit": ("esirkepov-quadratic" if args.quadratic else
+                               "esirkepov" if args.esirkepov else "villasenor-buneman-split"),
                    "sort": "motion-class" if args.motion_sort else "in-place",
                    "step": "push+deposit+sort+field_advance"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -560,6 +568,9 @@ def main():
         if not args.esirkepov:
             out["esirkepov"] = variant_measurement(w, T, esirkepov=True)
             log(f"esirkepov: {out['esirkepov']}")
+        if not args.quadratic:
+            out["quadratic"] = variant_measurement(w, T, quadratic=True)
+            log(f"quadratic shape: {out['quadratic']}")
         out["motion_sort"] = variant_measurement(w, T, motion_sort=True)
         log(f"motion-class sort: {out['motion_sort']}")
         for ppl in (1, 4):

@@ -20,7 +20,13 @@ void ora_deposit_esirkepov(int nx, int ny, double dx, double dy, double dt, doub
                            double x, double y, double ddx, double ddy, double *J);
 int ora_advance(int nx, int ny, double dx, double dy, double dt, double qm, double q, int64_t n, int32_t *ix,
                 int32_t *iy, double *x, double *y, double *ux, double *uy, double *uz, const double *E,
-                const double *B, double *J, int esirkepov);
+                const double *B, double *J, int deposit);
+void ora_interp_quad(int nx, int ny, const double *E, const double *B, int ix, int iy, double x, double y,
+                     double *out);
+void ora_deposit_esirkepov_quad(int nx, int ny, double dx, double dy, double dt, double q, double vz, int ix,
+                                int iy, double x, double y, double ddx, double ddy, double *J);
+void ora_deposit_rho_quad(int nx, int ny, double q, int64_t n, const int32_t *ix, const int32_t *iy,
+                          const double *x, const double *y, double *rho);
 void ora_field_advance(int nx, int ny, double dx, double dy, double dt, double *E, double *B, const double *J);
 int ora_sort_canonical(int nx, int ny, int T, int64_t n, const int32_t *ix, const int32_t *iy,
                        const unsigned char *removed, int64_t *off, int64_t *src, int64_t *n_out);
@@ -48,7 +54,7 @@ static int fail(const char *what)
     return 1;
 }
 
-static int run_grid(int nx, int ny, int T, int64_t n, int esirkepov)
+static int run_grid(int nx, int ny, int T, int64_t n, int deposit)
 {
     const int64_t P = (int64_t)nx * ny;
     const double dx = 0.1, dy = 0.1, dt = 0.07;
@@ -87,10 +93,16 @@ static int run_grid(int nx, int ny, int T, int64_t n, int esirkepov)
     ora_boris(-1.0, dt, EB, u);
     ora_deposit_move(nx, ny, dx, dy, dt, -0.1, 0.2, nx - 1, 0, 0.95, 0.02, 0.6, -0.5, J);
     ora_deposit_esirkepov(nx, ny, dx, dy, dt, -0.1, 0.2, 0, ny - 1, 0.01, 0.98, -0.6, 0.5, J);
-    if (ora_advance(nx, ny, dx, dy, dt, -1.0, -0.1, n, ix, iy, x, y, ux, uy, uz, E, B, J, esirkepov) != 0)
+    /* quadratic shape at both seams: the stencils reach two nodes out */
+    ora_interp_quad(nx, ny, E, B, nx - 1, 0, 0.999, 0.0, out);
+    ora_interp_quad(nx, ny, E, B, 0, ny - 1, 0.0, 0.999, out);
+    ora_deposit_esirkepov_quad(nx, ny, dx, dy, dt, -0.1, 0.2, 0, ny - 1, 0.01, 0.98, -0.99, 0.99, J);
+    ora_deposit_esirkepov_quad(nx, ny, dx, dy, dt, -0.1, 0.2, nx - 1, 0, 0.99, 0.01, 0.99, -0.99, J);
+    if (ora_advance(nx, ny, dx, dy, dt, -1.0, -0.1, n, ix, iy, x, y, ux, uy, uz, E, B, J, deposit) != 0)
         rc |= fail("advance");
     ora_field_advance(nx, ny, dx, dy, dt, E, B, J);
     ora_deposit_rho(nx, ny, -0.1, n, ix, iy, x, y, rho);
+    ora_deposit_rho_quad(nx, ny, -0.1, n, ix, iy, x, y, rho);
     ora_div_e(nx, ny, dx, dy, E, div);
     ora_div_b(nx, ny, dx, dy, B, div);
     (void)ora_field_energy(nx, ny, dx, dy, E);
@@ -111,6 +123,8 @@ int main(void)
     rc |= run_grid(16, 16, 16, 500, 0);   /* one tile: every neighbour is itself */
     rc |= run_grid(16, 8, 8, 0, 0);       /* no particles */
     rc |= run_grid(8, 8, 8, 1, 1);
+    rc |= run_grid(32, 24, 8, 2000, 2);   /* the quadratic shape */
+    rc |= run_grid(8, 8, 8, 1, 2);
     if (!rc) printf("oracle driver: ok\n");
     return rc;
 }
