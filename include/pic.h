@@ -123,9 +123,10 @@ extern "C" {
  * Esirkepov's decomposition (as PIC_FLAG_ESIRKEPOV, which may be set too and
  * then changes nothing) with this shape, on the 4 x 4 nodes that hold the
  * shape before and after the motion; the charge density of pic_diag and
- * pic_solve_gauss uses it too.  The push stages a halo two cells wide.  Needs
- * the fixed-point current, j_replicas <= 1, sort_every 1, ppl 2 and no moving
- * window (else PIC_EINVAL).
+ * pic_solve_gauss uses it too.  The push stages a halo two cells wide and
+ * carries one 64-particle chunk per lane.  Needs the fixed-point current,
+ * j_replicas <= 1, sort_every 1, ppl 0 or 2 and no moving window (else
+ * PIC_EINVAL).
  */
 #define PIC_FLAG_QUADRATIC 16u
 

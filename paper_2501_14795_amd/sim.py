@@ -294,7 +294,10 @@ class Sim(_SimView):
 
     species: list of (qm, q, state) where state is a dict of numpy arrays
     ix, iy (int32), x, y, ux, uy, uz (float32), in any order (pic_init groups
-    them by tile)."""
+    them by tile).  The options map to pic_config: j_replicas, j_float
+    (PIC_FLAG_J_FLOAT), j_filter, esirkepov (PIC_FLAG_ESIRKEPOV), quadratic
+    (PIC_FLAG_QUADRATIC, the quadratic particle shape), moving_window and
+    capacity, sort_every, motion_sort (PIC_FLAG_MOTION_SORT), ppl."""
 
     def __init__(self, nx: int, ny: int, dx: float, dy: float, dt: float, tile: int,
                  species: Sequence, E: Optional[np.ndarray] = None, B: Optional[np.ndarray] = None,
@@ -338,7 +341,7 @@ class Batch:
 
     members: list of dicts with keys nx, ny, dx, dy, dt, species (as for Sim)
     and optionally E, B.  All share tile, j_replicas, j_float, j_filter, the
-    deposit scheme and the sort cadence."""
+    deposit scheme and particle shape, and the sort cadence."""
 
     def __init__(self, members: Sequence[dict], tile: int, j_replicas: int = 0, j_float: bool = False,
                  device: str = "cuda:0", stream=None, j_filter: int = 0, esirkepov: bool = False,
