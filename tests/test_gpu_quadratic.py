@@ -6,8 +6,10 @@ state -- positions within 1e-5 cells, momenta within 1e-5 of max|u|, J within
 1e-5 of max|J|, the sort bit-exact -- at T = 8, 16, 32 (the halo pad is 2);
 10 free-running steps -- fields within 1e-5; the device continuity residual
 with the quadratic charge within 1e-6 of max|rho| and Gauss's law kept;
-batched members bit-identical to standalone runs; and at the 2048^2 workload,
-continuity at round-off and the total current equal to the charge moved."""
+batched members bit-identical to standalone runs; at the 2048^2 workload,
+continuity at round-off and the total current equal to the charge moved; grids
+of one tile on an axis; and with the motion-class sort, fields bit-identical to
+the in-place sort's."""
 import numpy as np
 import pytest
 
@@ -160,3 +162,57 @@ def test_quadratic_full_size_continuity():
     assert abs(got - want) <= 1e-8 * abs(spec.q) * pre["ix"].size
     assert sim.check() == 0
     sim.close()
+
+
+@pytest.mark.parametrize("nx,ny,tile", [(16, 16, 16), (16, 32, 16), (48, 8, 8)])
+def test_quadratic_degenerate_tile_grids(nx, ny, tile):
+    """One tile on an axis (the tile's own halo folds onto its periodic
+    images at both ends, two nodes deep) and a one-tile-high strip: replay
+    against the oracle within 1e-5, the sort bit-exact."""
+    specs = _specs(1, u_th=0.25, drift=(0.3, -0.3, 0.1))
+    states = species_states(nx, ny, tile, specs, 75)
+    E, B = pw.random_fields(nx, ny, 0.05, 75)
+    sim, _ = make_pair(nx, ny, DX, DY, DT, tile, specs, states, E, B, quadratic=True)
+    worst = [0.0, 0.0, 0.0]
+    for step in range(3):
+        ref = oracle_from_gpu(sim, specs, DX, DY, DT)
+        ref.quadratic = True
+        ref.push_deposit()
+        sim.push_deposit()
+        assert sim.check() == 0
+        pos, du = particle_errors(sim.state(0), ref.species[0], nx, ny)
+        worst[0], worst[1] = max(worst[0], pos), max(worst[1], du)
+        worst[2] = max(worst[2], rel_err(sim.field_arrays()["J"], ref.J))
+        sort_replay(sim, specs, tile)
+        sim.field_advance()
+    flush(f"quadratic {nx}x{ny} T{tile}: pos {worst[0]:.2e} u {worst[1]:.2e} J {worst[2]:.2e}")
+    assert worst[0] < 1e-5 and worst[1] < 1e-5 and worst[2] < 1e-5
+    sim.close()
+
+
+def test_quadratic_with_the_motion_class_sort():
+    """The quadratic shape with the motion-class sort (its copy back then
+    runs as its own pass): fields bit-identical to the in-place sort's after
+    six steps (the fixed-point current does not depend on particle order),
+    and within 1e-5 of the oracle."""
+    from paper_2501_14795_amd import Sim
+    nx = ny = 64
+    specs = _specs(1, u_th=0.2, drift=(0.2, 0.1, 0.0))
+    states = species_states(nx, ny, 16, specs, 76)
+    E, B = pw.random_fields(nx, ny, 0.05, 76)
+    motion, ora = make_pair(nx, ny, DX, DY, DT, 16, specs, states, E, B, quadratic=True, motion_sort=True)
+    inplace = Sim(nx, ny, DX, DY, DT, 16, [(s.qm, s.q, st) for s, st in zip(specs, states)], E=E, B=B,
+                  quadratic=True)
+    for _ in range(6):
+        motion.step()
+        inplace.step()
+        ora.step(T=16)
+    assert motion.check() == 0 and inplace.check() == 0
+    fm, fi = motion.field_arrays(), inplace.field_arrays()
+    for k in ("E", "B", "J"):
+        assert np.array_equal(fm[k], fi[k]), k
+    errs = {k: rel_err(fm[k], getattr(ora, k)) for k in ("E", "B", "J")}
+    flush(f"quadratic + motion-class sort, 6 steps: bit-identical to the in-place sort; vs oracle {errs}")
+    assert max(errs.values()) <= 1e-5
+    motion.close()
+    inplace.close()
